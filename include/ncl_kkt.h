@@ -1,0 +1,217 @@
+/*
+ * ncl_kkt.h -- C ABI of the MI355X (gfx950) library for the Newton step of
+ * the NCL augmented-Lagrangian method for security-constrained AC optimal
+ * power flow (the regularised KKT system of Section IV-B, eq. (newtonsystem)).
+ *
+ * Each interior-point iteration of NCL solves
+ *
+ *        [ A   B^T ] [dw]   [r1]        A = H + Sigma (+ nu0 off-diagonals)
+ *        [ B   -C  ] [dy] = [r2],       B = [J; 0 W2 W1],  C = diag(1/rho, 1/rho + s/nu0)
+ *
+ * whose sparsity pattern never changes (only the objective changes between
+ * outer iterations, Section IV-A).  C > 0 makes the matrix quasi-definite,
+ * so it has an LDL^T factorisation without pivoting for any symmetric
+ * ordering (Section IV-B, last paragraph).  The library computes the
+ * ordering and symbolic factorisation once (ncl_kkt_analyze), then per
+ * iteration assembles K from the state (ncl_kkt_assemble), factors it
+ * (ncl_kkt_factor) and solves (ncl_kkt_solve, ncl_kkt_solve_adjoint).
+ *
+ * Structure: K is block-arrowhead (Section II-B, eq. (scopf)): one block per
+ * scenario k = 0 (base case) .. K (contingencies), coupled only through the
+ * first-stage "border" variables u0 (pg, and with PV/PQ switching the PV
+ * voltages vm0).  Blocks are factored independently, then the Schur
+ * complement on the border.
+ *
+ * Layout (the order of every vector this library reads or writes):
+ *   per block, primal then dual:
+ *     primal: vm[nb], va[nb], qg[ng]; a single-block network adds pg[ng];
+ *             with NCL_PVPQ the contingency blocks add nu_plus[ng],
+ *             nu_minus[ng], s_up[ng], s_lo[ng], and the base block omits vm
+ *             at generator buses (those voltages are the border vm0);
+ *     dual:   P[nb], Q[nb], Ffrom[nl], Fto[nl]; with NCL_PVPQ the
+ *             contingency blocks add LIN[ng], DUP[ng], DLO[ng], CUP[ng],
+ *             CLO[ng] (eq. (pvpq): linear row, the two slack definitions and
+ *             the two complementarity products);
+ *   blocks 0..K in order, then the border pg[ng] (and vm0[ng] with NCL_PVPQ).
+ *
+ * Conventions
+ *   - Pointers named d* and the fields of ncl_kkt_point are DEVICE pointers;
+ *     everything else is host memory.  The library copies what it needs from
+ *     host arrays during the call; the caller keeps ownership of all memory
+ *     it passes in, and the library never frees caller memory.
+ *   - Device memory: the library performs no device allocation of its own.
+ *     ncl_kkt_workspace_bytes reports how much it needs and the caller binds
+ *     one buffer with ncl_kkt_bind_workspace (the Python binding uses a torch
+ *     tensor).  The buffer must stay valid until destroy or a new bind.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Compute calls are
+ *     asynchronous on it; argument and state errors return immediately;
+ *     numerical failures (zero, non-finite or wrong-sign pivot) are recorded
+ *     on the device and reported by ncl_kkt_info.
+ *   - A handle must not be used from two host threads at once, and calls on
+ *     one handle must be ordered (one stream, or caller-side events).
+ *     Distinct handles are independent.
+ *   - Results are bitwise reproducible run to run: no floating-point atomics
+ *     and fixed summation orders everywhere.
+ */
+#ifndef NCL_KKT_H
+#define NCL_KKT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ncl_kkt ncl_kkt;
+
+enum {
+    NCL_OK = 0,
+    NCL_ERR_ARG = -1,        /* bad argument (sizes, indices, null pointers, rho <= 0) */
+    NCL_ERR_ALLOC = -2,      /* host allocation failed */
+    NCL_ERR_HIP = -3,        /* a HIP runtime call failed */
+    NCL_ERR_STATE = -4,      /* call out of order (no workspace, not factored, ...) */
+    NCL_ERR_ZERO_PIVOT = -5, /* a pivot was exactly zero */
+    NCL_ERR_INERTIA = -6,    /* a pivot had the wrong sign (primal must be >0, dual <0) */
+    NCL_ERR_NONFINITE = -7   /* a pivot was NaN or infinite */
+};
+
+#define NCL_PVPQ 1u          /* PV/PQ complementarity rows and the vm0 border (eq. (pvpq)) */
+
+/* Network topology and constants (host arrays, copied during analyze).
+ * Branch l joins buses br_from[l] < br_to[l] with series impedance
+ * br_r[l] + j br_x[l] (no shunts, no taps); generator g sits at bus
+ * gen_bus[g] (distinct buses) with cost gen_c2[g] * pg^2; contingency k+1
+ * (k = 0..ncont-1) removes branch outage[k] (a non-bridge branch).
+ * Branches must be sorted by (from, to) without duplicates. */
+typedef struct {
+    int32_t nbus, nbranch, ngen, ncont;
+    const int32_t *br_from, *br_to, *gen_bus, *outage;
+    const double *br_r, *br_x, *gen_c2;
+    uint32_t flags;
+} ncl_network;
+
+/* Supernode amalgamation: a supernode absorbs its parent supernode when the
+ * merged width is <= relax_maxw and explicit zeros * relax_zden <=
+ * entries * relax_znum.  Defaults (all zero here): 16, 1, 4. */
+typedef struct {
+    int32_t relax_maxw, relax_znum, relax_zden;
+} ncl_analyze_opts;
+
+/* One primal-dual state, DEVICE arrays of length N in layout order.
+ * z: primal values at primal positions and multipliers at dual positions
+ *    (CUP/CLO rows hold the complementarity multiplier nu0).
+ * sigma: the barrier diagonal Sigma at primal positions (W0^{-1} Xi etc.,
+ *    must be > 0); at CUP/CLO rows the slack s of W1 W2 e <= t; ignored
+ *    elsewhere.
+ * rho: augmented-Lagrangian penalty (> 0). */
+typedef struct {
+    const double *z;
+    const double *sigma;
+    double rho;
+} ncl_kkt_point;
+
+/* Factorisation report (ncl_kkt_info).  npos/nneg/nzero count the signs of
+ * D; first_bad is the first pivot (factor order) that was zero, non-finite
+ * or of the wrong sign (-1 if none); status is NCL_OK or the NCL_ERR_* of
+ * that pivot. */
+typedef struct {
+    int64_t npos, nneg, nzero, first_bad;
+    double min_absd, max_absd;
+    int32_t status;
+} ncl_kkt_report;
+
+/* Symbolic analysis of the KKT of a network (once per pattern).
+ * Builds the union pattern of K (an outaged branch keeps explicit zeros,
+ * so every contingency block has the same pattern), a minimum-degree
+ * ordering per block with the border last, the elimination tree, the
+ * column counts, the supernode partition and all schedules.  Host only;
+ * no device memory is touched.  opts may be NULL (defaults).
+ * Returns NCL_ERR_ARG for out-of-range indices, unsorted or duplicate
+ * branches, too many or bridge outages. */
+int ncl_kkt_analyze(const ncl_network *net, const ncl_analyze_opts *opts, ncl_kkt **out);
+
+/* Symbolic analysis of a user-given block-arrowhead pattern (no assembly;
+ * values come through ncl_kkt_set_values).  colptr[N+1]/rowind: the lower
+ * triangle (row >= column, diagonal included, rows sorted) in the caller's
+ * order, blocks [block_off[b], block_off[b+1]) for b < nblk, border
+ * [block_off[nblk], N).  No entry may couple two different blocks.
+ * is_primal[N] gives the expected pivot sign (1 positive, 0 negative). */
+int ncl_kkt_analyze_pattern(int64_t N, int32_t nblk, const int64_t *block_off, const int64_t *colptr,
+                            const int32_t *rowind, const uint8_t *is_primal,
+                            const ncl_analyze_opts *opts, ncl_kkt **out);
+
+/* Sizes: N, primal count, nnz of K's lower triangle, nnz of L's strict
+ * lower triangle (exact pattern), number of supernodes, number of panel
+ * row indices (length of srowind below). */
+int ncl_kkt_dims(const ncl_kkt *h, int64_t *N, int64_t *nprimal, int64_t *nnzK, int64_t *nnzL,
+                 int64_t *nsuper, int64_t *npanel);
+
+/* Host copies of the symbolic result in factor order ("new" numbering).
+ * perm[N]: new -> layout index.  etree[N]: parent (-1 for roots).
+ * colcount[N]: nnz of each column of L including the diagonal.
+ * super_ptr[nsuper+1]: first column of each supernode.
+ * lcolptr[N+1], lrowind[nnzL]: strict-lower pattern of L, rows sorted.
+ * srowptr[nsuper+1], srowind[npanel]: panel rows of each supernode (its
+ * columns, then the sorted rows below it).  Any pointer may be NULL. */
+int ncl_kkt_symbolic(const ncl_kkt *h, int32_t *perm, int32_t *etree, int64_t *colcount,
+                     int64_t *super_ptr, int64_t *lcolptr, int32_t *lrowind, int64_t *srowptr,
+                     int32_t *srowind);
+
+/* Lower-triangle pattern of K in layout order (colptr[N+1], rowind[nnzK]),
+ * the order of ncl_kkt_set_values' input. */
+int ncl_kkt_pattern(const ncl_kkt *h, int64_t *colptr, int32_t *rowind);
+
+/* Device bytes needed for solves of up to nrhs_max right-hand sides. */
+int ncl_kkt_workspace_bytes(const ncl_kkt *h, int32_t nrhs_max, size_t *bytes);
+
+/* Bind caller-owned device memory (>= the reported size, 256-byte aligned)
+ * and upload the schedules on `stream`. */
+int ncl_kkt_bind_workspace(ncl_kkt *h, void *dptr, size_t bytes, int32_t nrhs_max, void *stream);
+
+/* Assemble K from a state (Section IV-B blocks A, B, C with the polar
+ * power-flow Jacobian and Lagrangian Hessian; the per-row shift
+ * delta_i = max(0, sum_{j!=i}|H_ij| - H_ii) keeps H + delta + Sigma
+ * positive definite at non-optimal states).  Writes the lower CSC values
+ * of K inside the workspace.  NCL_ERR_STATE if the handle came from
+ * ncl_kkt_analyze_pattern. */
+int ncl_kkt_assemble(ncl_kkt *h, const ncl_kkt_point *pt, void *stream);
+
+/* Seam that bypasses assembly: dvals[nnzK] are the lower CSC values (in the
+ * order of ncl_kkt_pattern), copied device-to-device into the workspace. */
+int ncl_kkt_set_values(ncl_kkt *h, const double *dvals, void *stream);
+
+/* Device copy of the current K values (lower CSC order) into dvals[nnzK]. */
+int ncl_kkt_get_values(ncl_kkt *h, double *dvals, void *stream);
+
+/* Pivot-free LDL^T of the current values: blocks in parallel, then the
+ * fixed-order sum of their border Schur contributions and the dense LDL^T
+ * of the border.  Asynchronous; see ncl_kkt_info. */
+int ncl_kkt_factor(ncl_kkt *h, void *stream);
+
+/* Synchronises `stream` and reports the last factorisation. */
+int ncl_kkt_info(ncl_kkt *h, ncl_kkt_report *rep, void *stream);
+
+/* Device copies of the factors: lx[nnzL] on the exact pattern of
+ * ncl_kkt_symbolic (strict lower part of unit-lower L) and d[N], both in
+ * factor order. */
+int ncl_kkt_get_factors(ncl_kkt *h, double *dlx, double *dd, void *stream);
+
+/* X = K^{-1} B for nrhs columns of length N in layout order, leading
+ * dimension ld >= N (device).  dx may equal db.  nrhs <= the workspace's
+ * nrhs_max.  NCL_ERR_STATE before the first factor. */
+int ncl_kkt_solve(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream);
+
+/* X = K^{-T} B on the stored factors (K is symmetric, so the same
+ * triangular solves; bitwise equal to ncl_kkt_solve).  The entry used by
+ * reverse-mode differentiation; it never refactors. */
+int ncl_kkt_solve_adjoint(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld,
+                          void *stream);
+
+void ncl_kkt_destroy(ncl_kkt *h);
+const char *ncl_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NCL_KKT_H */

@@ -1,0 +1,419 @@
+// Network model: the layout of each block template, the union sparsity
+// pattern of K (lower triangle), and the tables the assembly kernel uses to
+// find where each value goes.  Structure of K follows the Newton system of
+// Section IV-B (blocks A, B, C) for the corrective SCOPF of Section II-B
+// with the PV/PQ complementarity rows of eq. (pvpq).
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "ncl_internal.h"
+
+namespace ncl {
+
+namespace {
+
+struct Net {
+    int nb, nl, ng, K;
+    const int32_t *f, *t, *gb, *out;
+    bool pvpq;
+};
+
+// template kinds
+enum { T_SINGLE, T_PLAIN, T_PVPQ_BASE, T_PVPQ_CONT };
+
+struct Local {
+    std::vector<int32_t> vm, va, qg, pg, nup, num, sup, slo, vm0, rP, rQ, rFf, rFt, rLin, rDup, rDlo, rCup, rClo;
+};
+
+using PairList = std::vector<std::pair<int32_t, int32_t>>;   // (row, col), row >= col
+
+void add_pair(PairList &tp, PairList &bp, int n, int32_t a, int32_t b) {
+    int32_t r = std::max(a, b), c = std::min(a, b);
+    if (c >= n) bp.emplace_back(r - n, c - n);
+    else tp.emplace_back(r, c);
+}
+
+void layout(const Net &net, int kind, Local &L, int &n, int &nprim, std::vector<uint8_t> &isprim) {
+    const int nb = net.nb, nl = net.nl, ng = net.ng;
+    std::vector<int> genat(nb, -1);
+    for (int g = 0; g < ng; g++) genat[net.gb[g]] = g;
+    const bool base_pvpq = kind == T_PVPQ_BASE, cont_pvpq = kind == T_PVPQ_CONT;
+    nprim = (base_pvpq ? nb - ng : nb) + nb + ng + (kind == T_SINGLE ? ng : 0) + (cont_pvpq ? 4 * ng : 0);
+    int ndual = 2 * nb + 2 * nl + (cont_pvpq ? 5 * ng : 0);
+    n = nprim + ndual;
+    const int bpg = n, bvm0 = n + ng;   // border local indices
+    int k = 0;
+    L.vm.assign(nb, -1);
+    for (int i = 0; i < nb; i++) {
+        if (base_pvpq && genat[i] >= 0) L.vm[i] = bvm0 + genat[i];
+        else L.vm[i] = k++;
+    }
+    auto seq = [&](std::vector<int32_t> &v, int cnt) {
+        v.resize(cnt);
+        for (int i = 0; i < cnt; i++) v[i] = k++;
+    };
+    seq(L.va, nb);
+    seq(L.qg, ng);
+    if (kind == T_SINGLE) seq(L.pg, ng);
+    else {
+        L.pg.resize(ng);
+        for (int g = 0; g < ng; g++) L.pg[g] = bpg + g;
+    }
+    if (cont_pvpq) { seq(L.nup, ng); seq(L.num, ng); seq(L.sup, ng); seq(L.slo, ng); }
+    L.vm0.resize(ng);
+    for (int g = 0; g < ng; g++) L.vm0[g] = net.pvpq ? bvm0 + g : -1;
+    seq(L.rP, nb); seq(L.rQ, nb); seq(L.rFf, nl); seq(L.rFt, nl);
+    if (cont_pvpq) { seq(L.rLin, ng); seq(L.rDup, ng); seq(L.rDlo, ng); seq(L.rCup, ng); seq(L.rClo, ng); }
+    isprim.assign(n, 0);
+    for (int i = 0; i < nprim; i++) isprim[i] = 1;
+}
+
+void enumerate(const Net &net, int kind, const Local &L, int n, PairList &tp, PairList &bp) {
+    const int nb = net.nb, nl = net.nl, ng = net.ng;
+    for (int l = 0; l < nl; l++) {
+        int f = net.f[l], t = net.t[l];
+        int32_t V[4] = {L.vm[f], L.vm[t], L.va[f], L.va[t]};
+        for (int a = 0; a < 4; a++)
+            for (int b = a; b < 4; b++) add_pair(tp, bp, n, V[a], V[b]);
+        int32_t R[6] = {L.rP[f], L.rQ[f], L.rP[t], L.rQ[t], L.rFf[l], L.rFt[l]};
+        for (int r = 0; r < 6; r++)
+            for (int a = 0; a < 4; a++) add_pair(tp, bp, n, R[r], V[a]);
+        add_pair(tp, bp, n, L.rFf[l], L.rFf[l]);
+        add_pair(tp, bp, n, L.rFt[l], L.rFt[l]);
+    }
+    for (int i = 0; i < nb; i++) {
+        add_pair(tp, bp, n, L.vm[i], L.vm[i]);
+        add_pair(tp, bp, n, L.va[i], L.va[i]);
+        add_pair(tp, bp, n, L.rP[i], L.rP[i]);
+        add_pair(tp, bp, n, L.rQ[i], L.rQ[i]);
+    }
+    for (int g = 0; g < ng; g++) {
+        int i = net.gb[g];
+        add_pair(tp, bp, n, L.rP[i], L.pg[g]);
+        add_pair(tp, bp, n, L.rQ[i], L.qg[g]);
+        add_pair(tp, bp, n, L.qg[g], L.qg[g]);
+        if (kind == T_SINGLE) add_pair(tp, bp, n, L.pg[g], L.pg[g]);
+        if (kind == T_PVPQ_CONT) {
+            add_pair(tp, bp, n, L.rLin[g], L.nup[g]);
+            add_pair(tp, bp, n, L.rLin[g], L.num[g]);
+            add_pair(tp, bp, n, L.rLin[g], L.vm[i]);
+            add_pair(tp, bp, n, L.rLin[g], L.vm0[g]);
+            add_pair(tp, bp, n, L.rDup[g], L.sup[g]);
+            add_pair(tp, bp, n, L.rDup[g], L.qg[g]);
+            add_pair(tp, bp, n, L.rDlo[g], L.slo[g]);
+            add_pair(tp, bp, n, L.rDlo[g], L.qg[g]);
+            add_pair(tp, bp, n, L.rCup[g], L.num[g]);
+            add_pair(tp, bp, n, L.rCup[g], L.sup[g]);
+            add_pair(tp, bp, n, L.rClo[g], L.nup[g]);
+            add_pair(tp, bp, n, L.rClo[g], L.slo[g]);
+            add_pair(tp, bp, n, L.num[g], L.sup[g]);
+            add_pair(tp, bp, n, L.nup[g], L.slo[g]);
+            for (auto v : {L.nup[g], L.num[g], L.sup[g], L.slo[g], L.rLin[g], L.rDup[g], L.rDlo[g], L.rCup[g], L.rClo[g]})
+                add_pair(tp, bp, n, v, v);
+        }
+    }
+}
+
+void to_csc(PairList &p, int ncol, std::vector<int64_t> &colptr, std::vector<int32_t> &rowind) {
+    std::sort(p.begin(), p.end(), [](const auto &a, const auto &b) {
+        return a.second != b.second ? a.second < b.second : a.first < b.first;
+    });
+    p.erase(std::unique(p.begin(), p.end()), p.end());
+    colptr.assign(ncol + 1, 0);
+    rowind.resize(p.size());
+    for (size_t e = 0; e < p.size(); e++) {
+        colptr[p[e].second + 1]++;
+        rowind[e] = p[e].first;
+    }
+    for (int c = 0; c < ncol; c++) colptr[c + 1] += colptr[c];
+}
+
+int32_t find_pos(const std::vector<int64_t> &cp, const std::vector<int32_t> &ri, int32_t r, int32_t c) {
+    auto b = ri.begin() + cp[c], e = ri.begin() + cp[c + 1];
+    auto it = std::lower_bound(b, e, r);
+    if (it == e || *it != r) return -1;
+    return int32_t(it - ri.begin());
+}
+
+}  // namespace
+
+int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
+    if (!nw || nw->nbus < 1 || nw->nbranch < 0 || nw->ngen < 0 || nw->ncont < 0) { err = "bad sizes"; return NCL_ERR_ARG; }
+    if (!nw->br_from || !nw->br_to || !nw->br_r || !nw->br_x || (nw->ngen && (!nw->gen_bus || !nw->gen_c2)) ||
+        (nw->ncont && !nw->outage)) { err = "null array"; return NCL_ERR_ARG; }
+    Net net{nw->nbus, nw->nbranch, nw->ngen, nw->ncont, nw->br_from, nw->br_to, nw->gen_bus, nw->outage,
+            (nw->flags & NCL_PVPQ) != 0};
+    if (net.pvpq && net.K == 0) { err = "PV/PQ rows need contingencies"; return NCL_ERR_ARG; }
+    for (int l = 0; l < net.nl; l++) {
+        if (net.f[l] < 0 || net.t[l] >= net.nb || net.f[l] >= net.t[l]) { err = "branch endpoints"; return NCL_ERR_ARG; }
+        if (l && (net.f[l] < net.f[l - 1] || (net.f[l] == net.f[l - 1] && net.t[l] <= net.t[l - 1]))) {
+            err = "branches not sorted or duplicated";
+            return NCL_ERR_ARG;
+        }
+        if (!(nw->br_r[l] * nw->br_r[l] + nw->br_x[l] * nw->br_x[l] > 0)) { err = "zero impedance"; return NCL_ERR_ARG; }
+    }
+    {
+        std::vector<char> used(net.nb, 0);
+        for (int g = 0; g < net.ng; g++) {
+            if (net.gb[g] < 0 || net.gb[g] >= net.nb || used[net.gb[g]]) { err = "generator buses"; return NCL_ERR_ARG; }
+            used[net.gb[g]] = 1;
+        }
+    }
+    {
+        std::vector<char> used(net.nl, 0);
+        for (int k = 0; k < net.K; k++) {
+            if (net.out[k] < 0 || net.out[k] >= net.nl || used[net.out[k]]) { err = "outage index"; return NCL_ERR_ARG; }
+            used[net.out[k]] = 1;
+        }
+    }
+    h.from_network = true;
+    h.nb = net.nb; h.nl = net.nl; h.ng = net.ng; h.flags = nw->flags;
+    h.nblk = net.K + 1;
+    h.nbd = net.K == 0 ? 0 : net.ng * (net.pvpq ? 2 : 1);
+    h.gen_c2.assign(nw->gen_c2, nw->gen_c2 + net.ng);
+    h.br_r.assign(nw->br_r, nw->br_r + net.nl);
+    h.br_x.assign(nw->br_x, nw->br_x + net.nl);
+    std::vector<int> kinds;
+    if (net.K == 0) kinds = {T_SINGLE};
+    else if (!net.pvpq) kinds = {T_PLAIN};
+    else kinds = {T_PVPQ_BASE, T_PVPQ_CONT};
+    h.tmpl.assign(kinds.size(), Template());
+    h.block_tmpl.assign(h.nblk, 0);
+    h.block_outage.assign(h.nblk, -1);
+    for (int k = 1; k < h.nblk; k++) {
+        h.block_tmpl[k] = net.pvpq ? 1 : 0;
+        h.block_outage[k] = net.out[k - 1];
+    }
+    PairList border_pairs;
+    std::vector<Local> locs(kinds.size());
+    for (size_t ti = 0; ti < kinds.size(); ti++) {
+        Template &t = h.tmpl[ti];
+        int n, nprim;
+        layout(net, kinds[ti], locs[ti], n, nprim, t.is_primal);
+        t.n = n;
+        t.nprim = nprim;
+        t.pvpq_rows = kinds[ti] == T_PVPQ_CONT;
+        t.pg_local = kinds[ti] == T_SINGLE;
+        PairList tp;
+        enumerate(net, kinds[ti], locs[ti], n, tp, border_pairs);
+        to_csc(tp, n, t.colptr, t.rowind);
+    }
+    for (int b = 0; b < h.nbd; b++) border_pairs.emplace_back(b, b);
+    to_csc(border_pairs, h.nbd, h.bcolptr, h.browind);
+    h.border_primal.assign(h.nbd, 1);
+    h.border_pg.assign(net.ng, -1);
+    if (h.nbd)
+        for (int g = 0; g < net.ng; g++) h.border_pg[g] = g;
+    // block offsets and K value bases
+    h.block_off.assign(h.nblk + 1, 0);
+    h.kbase.assign(h.nblk + 1, 0);
+    for (int k = 0; k < h.nblk; k++) {
+        const Template &t = h.tmpl[h.block_tmpl[k]];
+        h.block_off[k + 1] = h.block_off[k] + t.n;
+        h.kbase[k + 1] = h.kbase[k] + t.colptr[t.n];
+    }
+    h.N = h.block_off[h.nblk] + h.nbd;
+    h.nnzK = h.kbase[h.nblk] + (h.nbd ? h.bcolptr[h.nbd] : 0);
+    h.nprimal = h.nbd;
+    for (int k = 0; k < h.nblk; k++) h.nprimal += h.tmpl[h.block_tmpl[k]].nprim;
+    h.kbb_pos.assign(size_t(h.nbd) * h.nbd, -1);
+    for (int c = 0; c < h.nbd; c++)
+        for (int64_t p = h.bcolptr[c]; p < h.bcolptr[c + 1]; p++) h.kbb_pos[size_t(h.browind[p]) * h.nbd + c] = int32_t(p);
+
+    // assembly tables
+    for (size_t ti = 0; ti < kinds.size(); ti++) {
+        Template &t = h.tmpl[ti];
+        const Local &L = locs[ti];
+        const int n = t.n;
+        auto slot = [&](int32_t a, int32_t b) -> int32_t {
+            if (a < 0 || b < 0) return -1;
+            int32_t r = std::max(a, b), c = std::min(a, b);
+            if (c >= n) {
+                int32_t p = find_pos(h.bcolptr, h.browind, r - n, c - n);
+                return p < 0 ? -1 : (kBorderFlag | p);
+            }
+            return find_pos(t.colptr, t.rowind, r, c);
+        };
+        const int nb = net.nb, nl = net.nl, ng = net.ng;
+        t.bus_idx.assign(size_t(nb) * BI_N, -1);
+        t.bus_slot.assign(size_t(nb) * BS_N, -1);
+        for (int i = 0; i < nb; i++) {
+            int32_t *bi = &t.bus_idx[size_t(i) * BI_N];
+            bi[BI_VM] = L.vm[i]; bi[BI_VA] = L.va[i]; bi[BI_P] = L.rP[i]; bi[BI_Q] = L.rQ[i];
+            int32_t *bs = &t.bus_slot[size_t(i) * BS_N];
+            bs[BS_VMVM] = slot(L.vm[i], L.vm[i]);
+            bs[BS_VAVA] = slot(L.va[i], L.va[i]);
+            bs[BS_VMVA] = slot(L.vm[i], L.va[i]);
+            bs[BS_PVM] = slot(L.rP[i], L.vm[i]);
+            bs[BS_PVA] = slot(L.rP[i], L.va[i]);
+            bs[BS_QVM] = slot(L.rQ[i], L.vm[i]);
+            bs[BS_QVA] = slot(L.rQ[i], L.va[i]);
+            bs[BS_PP] = slot(L.rP[i], L.rP[i]);
+            bs[BS_QQ] = slot(L.rQ[i], L.rQ[i]);
+        }
+        t.bus_adj_ptr.assign(nb + 1, 0);
+        for (int l = 0; l < nl; l++) { t.bus_adj_ptr[net.f[l] + 1]++; t.bus_adj_ptr[net.t[l] + 1]++; }
+        for (int i = 0; i < nb; i++) t.bus_adj_ptr[i + 1] += t.bus_adj_ptr[i];
+        t.bus_adj.assign(t.bus_adj_ptr[nb], 0);
+        {
+            std::vector<int32_t> fill(t.bus_adj_ptr.begin(), t.bus_adj_ptr.end() - 1);
+            for (int l = 0; l < nl; l++) {
+                t.bus_adj[fill[net.f[l]]++] = l;
+                t.bus_adj[fill[net.t[l]]++] = ~l;
+            }
+        }
+        t.br_slot.assign(size_t(nl) * LS_N, -1);
+        t.br_idx.assign(size_t(nl) * 4, -1);
+        for (int l = 0; l < nl; l++) {
+            int f = net.f[l], tt = net.t[l];
+            int32_t *s = &t.br_slot[size_t(l) * LS_N];
+            s[LS_VMVM] = slot(L.vm[f], L.vm[tt]);
+            s[LS_VMVA] = slot(L.vm[f], L.va[tt]);
+            s[LS_VAVM] = slot(L.va[f], L.vm[tt]);
+            s[LS_VAVA] = slot(L.va[f], L.va[tt]);
+            s[LS_PF_VMT] = slot(L.rP[f], L.vm[tt]);
+            s[LS_PF_VAT] = slot(L.rP[f], L.va[tt]);
+            s[LS_QF_VMT] = slot(L.rQ[f], L.vm[tt]);
+            s[LS_QF_VAT] = slot(L.rQ[f], L.va[tt]);
+            s[LS_PT_VMF] = slot(L.rP[tt], L.vm[f]);
+            s[LS_PT_VAF] = slot(L.rP[tt], L.va[f]);
+            s[LS_QT_VMF] = slot(L.rQ[tt], L.vm[f]);
+            s[LS_QT_VAF] = slot(L.rQ[tt], L.va[f]);
+            s[LS_FF_VMF] = slot(L.rFf[l], L.vm[f]);
+            s[LS_FF_VMT] = slot(L.rFf[l], L.vm[tt]);
+            s[LS_FF_VAF] = slot(L.rFf[l], L.va[f]);
+            s[LS_FF_VAT] = slot(L.rFf[l], L.va[tt]);
+            s[LS_FT_VMF] = slot(L.rFt[l], L.vm[f]);
+            s[LS_FT_VMT] = slot(L.rFt[l], L.vm[tt]);
+            s[LS_FT_VAF] = slot(L.rFt[l], L.va[f]);
+            s[LS_FT_VAT] = slot(L.rFt[l], L.va[tt]);
+            s[LS_FFFF] = slot(L.rFf[l], L.rFf[l]);
+            s[LS_FTFT] = slot(L.rFt[l], L.rFt[l]);
+            int32_t *bi = &t.br_idx[size_t(l) * 4];
+            bi[0] = L.rFf[l]; bi[1] = L.rFt[l]; bi[2] = f; bi[3] = tt;
+        }
+        t.gen_idx.assign(size_t(ng) * GI_N, -1);
+        t.gen_slot.assign(size_t(ng) * GS_N, -1);
+        for (int g = 0; g < ng; g++) {
+            int i = net.gb[g];
+            int32_t *gi = &t.gen_idx[size_t(g) * GI_N];
+            gi[GI_BUS] = i;
+            gi[GI_QG] = L.qg[g];
+            gi[GI_PG] = L.pg[g];
+            gi[GI_VM0] = L.vm0[g];
+            int32_t *gs = &t.gen_slot[size_t(g) * GS_N];
+            gs[GS_PPG] = slot(L.rP[i], L.pg[g]);
+            gs[GS_QQG] = slot(L.rQ[i], L.qg[g]);
+            gs[GS_QGQG] = slot(L.qg[g], L.qg[g]);
+            gs[GS_PGPG] = t.pg_local ? slot(L.pg[g], L.pg[g]) : -1;
+            if (t.pvpq_rows) {
+                gi[GI_NUP] = L.nup[g]; gi[GI_NUM] = L.num[g]; gi[GI_SUP] = L.sup[g]; gi[GI_SLO] = L.slo[g];
+                gi[GI_LIN] = L.rLin[g]; gi[GI_DUP] = L.rDup[g]; gi[GI_DLO] = L.rDlo[g];
+                gi[GI_CUP] = L.rCup[g]; gi[GI_CLO] = L.rClo[g];
+                gs[GS_LIN_NUP] = slot(L.rLin[g], L.nup[g]);
+                gs[GS_LIN_NUM] = slot(L.rLin[g], L.num[g]);
+                gs[GS_LIN_VM] = slot(L.rLin[g], L.vm[i]);
+                gs[GS_LIN_VM0] = slot(L.rLin[g], L.vm0[g]);
+                gs[GS_DUP_SUP] = slot(L.rDup[g], L.sup[g]);
+                gs[GS_DUP_QG] = slot(L.rDup[g], L.qg[g]);
+                gs[GS_DLO_SLO] = slot(L.rDlo[g], L.slo[g]);
+                gs[GS_DLO_QG] = slot(L.rDlo[g], L.qg[g]);
+                gs[GS_CUP_NUM] = slot(L.rCup[g], L.num[g]);
+                gs[GS_CUP_SUP] = slot(L.rCup[g], L.sup[g]);
+                gs[GS_CLO_NUP] = slot(L.rClo[g], L.nup[g]);
+                gs[GS_CLO_SLO] = slot(L.rClo[g], L.slo[g]);
+                gs[GS_H_NUM_SUP] = slot(L.num[g], L.sup[g]);
+                gs[GS_H_NUP_SLO] = slot(L.nup[g], L.slo[g]);
+                gs[GS_NUPNUP] = slot(L.nup[g], L.nup[g]);
+                gs[GS_NUMNUM] = slot(L.num[g], L.num[g]);
+                gs[GS_SUPSUP] = slot(L.sup[g], L.sup[g]);
+                gs[GS_SLOSLO] = slot(L.slo[g], L.slo[g]);
+                gs[GS_LL] = slot(L.rLin[g], L.rLin[g]);
+                gs[GS_UU] = slot(L.rDup[g], L.rDup[g]);
+                gs[GS_DD] = slot(L.rDlo[g], L.rDlo[g]);
+                gs[GS_CUCU] = slot(L.rCup[g], L.rCup[g]);
+                gs[GS_CLCL] = slot(L.rClo[g], L.rClo[g]);
+            }
+        }
+    }
+    return NCL_OK;
+}
+
+int build_pattern_model(int64_t N, int nblk, const int64_t *block_off, const int64_t *colptr, const int32_t *rowind,
+                        const uint8_t *is_primal, Handle &h, std::string &err) {
+    if (N <= 0 || nblk <= 0 || !block_off || !colptr || !rowind || !is_primal) { err = "bad arguments"; return NCL_ERR_ARG; }
+    if (block_off[0] != 0 || block_off[nblk] > N) { err = "block offsets"; return NCL_ERR_ARG; }
+    for (int b = 0; b < nblk; b++)
+        if (block_off[b + 1] <= block_off[b]) { err = "empty block"; return NCL_ERR_ARG; }
+    const int64_t bstart = block_off[nblk];
+    if (N - bstart > 4096) { err = "border too large"; return NCL_ERR_ARG; }
+    h.from_network = false;
+    h.nblk = nblk;
+    h.nbd = int(N - bstart);
+    h.block_off.assign(block_off, block_off + nblk + 1);
+    h.block_outage.assign(nblk, -1);
+    h.block_tmpl.assign(nblk, -1);
+    h.kbase.assign(nblk + 1, 0);
+    h.N = N;
+    // validate the pattern: lower, sorted, diagonal present, no block coupling
+    for (int64_t j = 0; j < N; j++) {
+        if (colptr[j + 1] < colptr[j]) { err = "colptr"; return NCL_ERR_ARG; }
+        bool diag = false;
+        int bj = -1;
+        for (int b = 0; b < nblk; b++)
+            if (j >= block_off[b] && j < block_off[b + 1]) bj = b;
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+            int64_t i = rowind[p];
+            if (i < j || i >= N || (p > colptr[j] && rowind[p - 1] >= i)) { err = "pattern not lower/sorted"; return NCL_ERR_ARG; }
+            if (i == j) diag = true;
+            if (bj >= 0 && i < bstart && (i < block_off[bj] || i >= block_off[bj + 1])) { err = "entry couples two blocks"; return NCL_ERR_ARG; }
+        }
+        if (!diag) { err = "missing diagonal"; return NCL_ERR_ARG; }
+    }
+    // templates: blocks with identical local patterns and signs share one
+    for (int b = 0; b < nblk; b++) {
+        int64_t o = block_off[b];
+        int n = int(block_off[b + 1] - o);
+        Template cand;
+        cand.n = n;
+        cand.colptr.assign(n + 1, 0);
+        for (int c = 0; c < n; c++) cand.colptr[c + 1] = cand.colptr[c] + (colptr[o + c + 1] - colptr[o + c]);
+        cand.rowind.resize(cand.colptr[n]);
+        for (int c = 0; c < n; c++)
+            for (int64_t p = colptr[o + c]; p < colptr[o + c + 1]; p++) {
+                int64_t i = rowind[p];
+                cand.rowind[cand.colptr[c] + (p - colptr[o + c])] = int32_t(i >= bstart ? n + (i - bstart) : i - o);
+            }
+        cand.is_primal.assign(is_primal + o, is_primal + o + n);
+        int found = -1;
+        for (size_t ti = 0; ti < h.tmpl.size() && found < 0; ti++) {
+            const Template &t = h.tmpl[ti];
+            if (t.n == n && t.colptr == cand.colptr && t.rowind == cand.rowind && t.is_primal == cand.is_primal) found = int(ti);
+        }
+        if (found < 0) {
+            cand.nprim = 0;
+            for (int c = 0; c < n; c++) cand.nprim += cand.is_primal[c];
+            h.tmpl.push_back(std::move(cand));
+            found = int(h.tmpl.size()) - 1;
+        }
+        h.block_tmpl[b] = found;
+        h.kbase[b + 1] = h.kbase[b] + (colptr[block_off[b + 1]] - colptr[o]);
+    }
+    h.bcolptr.assign(h.nbd + 1, 0);
+    for (int c = 0; c < h.nbd; c++) h.bcolptr[c + 1] = h.bcolptr[c] + (colptr[bstart + c + 1] - colptr[bstart + c]);
+    h.browind.resize(h.bcolptr[h.nbd]);
+    for (int c = 0; c < h.nbd; c++)
+        for (int64_t p = colptr[bstart + c]; p < colptr[bstart + c + 1]; p++)
+            h.browind[h.bcolptr[c] + (p - colptr[bstart + c])] = int32_t(rowind[p] - bstart);
+    h.border_primal.assign(is_primal + bstart, is_primal + N);
+    h.nnzK = colptr[N];
+    h.nprimal = 0;
+    for (int64_t j = 0; j < N; j++) h.nprimal += is_primal[j] ? 1 : 0;
+    h.kbb_pos.assign(size_t(h.nbd) * h.nbd, -1);
+    for (int c = 0; c < h.nbd; c++)
+        for (int64_t p = h.bcolptr[c]; p < h.bcolptr[c + 1]; p++) h.kbb_pos[size_t(h.browind[p]) * h.nbd + c] = int32_t(p);
+    return NCL_OK;
+}
+
+}  // namespace ncl

@@ -1,0 +1,250 @@
+"""ctypes binding of libnclkkt (include/ncl_kkt.h).
+
+Argument marshalling only: every step of assembly, factorisation and solve
+runs in the library's HIP kernels.  PyTorch provides device memory (the
+workspace and the vectors) and the current stream.  The library must have
+been built (``paper_2510_13333_amd._build.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libnclkkt.so")
+_lib = None
+
+NCL_PVPQ = 1
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
+          -4: "call out of order", -5: "zero pivot", -6: "pivot of the wrong sign (inertia)",
+          -7: "non-finite pivot"}
+
+
+class NclError(RuntimeError):
+    def __init__(self, where, code):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class _Network(ctypes.Structure):
+    _fields_ = [("nbus", ctypes.c_int32), ("nbranch", ctypes.c_int32), ("ngen", ctypes.c_int32),
+                ("ncont", ctypes.c_int32), ("br_from", ctypes.c_void_p), ("br_to", ctypes.c_void_p),
+                ("gen_bus", ctypes.c_void_p), ("outage", ctypes.c_void_p), ("br_r", ctypes.c_void_p),
+                ("br_x", ctypes.c_void_p), ("gen_c2", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("relax_maxw", ctypes.c_int32), ("relax_znum", ctypes.c_int32), ("relax_zden", ctypes.c_int32)]
+
+
+class _Point(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("rho", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("npos", ctypes.c_int64), ("nneg", ctypes.c_int64), ("nzero", ctypes.c_int64),
+                ("first_bad", ctypes.c_int64), ("min_absd", ctypes.c_double), ("max_absd", ctypes.c_double),
+                ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def library_path() -> str:
+    return _SO
+
+
+def load():
+    """Load libnclkkt.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        raise RuntimeError(f"{_SO} is missing: build it with paper_2510_13333_amd._build.build()")
+    L = ctypes.CDLL(_SO)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "ncl_kkt_analyze": ([P, P, pp], ctypes.c_int),
+        "ncl_kkt_analyze_pattern": ([i64, i32, P, P, P, P, P, pp], ctypes.c_int),
+        "ncl_kkt_dims": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_symbolic": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_pattern": ([P, P, P], ctypes.c_int),
+        "ncl_kkt_workspace_bytes": ([P, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ncl_kkt_bind_workspace": ([P, P, ctypes.c_size_t, i32, P], ctypes.c_int),
+        "ncl_kkt_assemble": ([P, P, P], ctypes.c_int),
+        "ncl_kkt_set_values": ([P, P, P], ctypes.c_int),
+        "ncl_kkt_get_values": ([P, P, P], ctypes.c_int),
+        "ncl_kkt_factor": ([P, P], ctypes.c_int),
+        "ncl_kkt_info": ([P, P, P], ctypes.c_int),
+        "ncl_kkt_get_factors": ([P, P, P, P], ctypes.c_int),
+        "ncl_kkt_solve": ([P, P, P, i32, i64, P], ctypes.c_int),
+        "ncl_kkt_solve_adjoint": ([P, P, P, i32, i64, P], ctypes.c_int),
+        "ncl_kkt_destroy": ([P], None),
+        "ncl_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(where, rc):
+    if rc != 0:
+        raise NclError(where, rc)
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class KKT:
+    """One analysed KKT pattern (ncl_kkt handle) and, once bound, its workspace."""
+
+    def __init__(self, net=None, *, relax=None, pattern=None):
+        L = load()
+        self._h = ctypes.c_void_p()
+        self._keep = []
+        opts = None
+        if relax is not None:
+            opts = _Opts(int(relax[0]), int(relax[1]), int(relax[2]))
+        if net is not None:
+            arrs = dict(br_from=np.ascontiguousarray(net.br_from, np.int32),
+                        br_to=np.ascontiguousarray(net.br_to, np.int32),
+                        gen_bus=np.ascontiguousarray(net.gen_bus, np.int32),
+                        outage=np.ascontiguousarray(net.outage, np.int32),
+                        br_r=np.ascontiguousarray(net.br_r, np.float64),
+                        br_x=np.ascontiguousarray(net.br_x, np.float64),
+                        gen_c2=np.ascontiguousarray(net.gen_c2, np.float64))
+            s = _Network(int(net.nb), int(net.nl), int(net.ng), int(arrs["outage"].shape[0]),
+                         *[_np_ptr(arrs[k]) for k in ("br_from", "br_to", "gen_bus", "outage", "br_r", "br_x",
+                                                     "gen_c2")],
+                         NCL_PVPQ if getattr(net, "pvpq", False) else 0)
+            rc = L.ncl_kkt_analyze(ctypes.byref(s), ctypes.byref(opts) if opts else None, ctypes.byref(self._h))
+            _check("ncl_kkt_analyze", rc)
+        elif pattern is not None:
+            N, block_off, colptr, rowind, is_primal = pattern
+            block_off = np.ascontiguousarray(block_off, np.int64)
+            colptr = np.ascontiguousarray(colptr, np.int64)
+            rowind = np.ascontiguousarray(rowind, np.int32)
+            is_primal = np.ascontiguousarray(is_primal, np.uint8)
+            rc = L.ncl_kkt_analyze_pattern(int(N), int(block_off.shape[0] - 1), _np_ptr(block_off), _np_ptr(colptr),
+                                           _np_ptr(rowind), _np_ptr(is_primal),
+                                           ctypes.byref(opts) if opts else None, ctypes.byref(self._h))
+            _check("ncl_kkt_analyze_pattern", rc)
+        else:
+            raise ValueError("need a network or a pattern")
+        d = [ctypes.c_int64() for _ in range(6)]
+        _check("ncl_kkt_dims", L.ncl_kkt_dims(self._h, *[ctypes.byref(x) for x in d]))
+        self.N, self.nprimal, self.nnzK, self.nnzL, self.nsuper, self.npanel = (int(x.value) for x in d)
+        self.ws = None
+        self.nrhs_max = 0
+
+    # ------------------------------------------------------------ symbolic (host)
+    def symbolic(self):
+        L = load()
+        out = dict(perm=np.empty(self.N, np.int32), etree=np.empty(self.N, np.int32),
+                   colcount=np.empty(self.N, np.int64), super_ptr=np.empty(self.nsuper + 1, np.int64),
+                   lcolptr=np.empty(self.N + 1, np.int64), lrowind=np.empty(max(self.nnzL, 1), np.int32),
+                   srowptr=np.empty(self.nsuper + 1, np.int64), srowind=np.empty(max(self.npanel, 1), np.int32))
+        _check("ncl_kkt_symbolic", L.ncl_kkt_symbolic(self._h, *[_np_ptr(out[k]) for k in (
+            "perm", "etree", "colcount", "super_ptr", "lcolptr", "lrowind", "srowptr", "srowind")]))
+        out["lrowind"] = out["lrowind"][:self.nnzL]
+        out["srowind"] = out["srowind"][:self.npanel]
+        return out
+
+    def pattern(self):
+        L = load()
+        cp = np.empty(self.N + 1, np.int64)
+        ri = np.empty(max(self.nnzK, 1), np.int32)
+        _check("ncl_kkt_pattern", L.ncl_kkt_pattern(self._h, _np_ptr(cp), _np_ptr(ri)))
+        return cp, ri[:self.nnzK]
+
+    def workspace_bytes(self, nrhs_max=1):
+        n = ctypes.c_size_t()
+        _check("ncl_kkt_workspace_bytes", load().ncl_kkt_workspace_bytes(self._h, int(nrhs_max), ctypes.byref(n)))
+        return int(n.value)
+
+    # ------------------------------------------------------------ device
+    def bind(self, nrhs_max=1, device="cuda"):
+        import torch
+        nbytes = self.workspace_bytes(nrhs_max)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = ws.data_ptr()
+        off = (-base) % 256
+        self.ws = ws
+        _check("ncl_kkt_bind_workspace", load().ncl_kkt_bind_workspace(
+            self._h, ctypes.c_void_p(base + off), ctypes.c_size_t(nbytes), int(nrhs_max), _stream_ptr()))
+        self.nrhs_max = int(nrhs_max)
+        return self
+
+    @staticmethod
+    def _dev(t, n=None):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("expected a contiguous float64 CUDA tensor")
+        if n is not None and t.numel() < n:
+            raise ValueError("tensor too short")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def assemble(self, z, sigma, rho):
+        pt = _Point(self._dev(z, self.N), self._dev(sigma, self.N), float(rho))
+        self._pt = (z, sigma)
+        _check("ncl_kkt_assemble", load().ncl_kkt_assemble(self._h, ctypes.byref(pt), _stream_ptr()))
+
+    def set_values(self, vals):
+        _check("ncl_kkt_set_values", load().ncl_kkt_set_values(self._h, self._dev(vals, self.nnzK), _stream_ptr()))
+
+    def get_values(self):
+        import torch
+        out = torch.empty(self.nnzK, dtype=torch.float64, device=self.ws.device)
+        _check("ncl_kkt_get_values", load().ncl_kkt_get_values(self._h, self._dev(out), _stream_ptr()))
+        return out
+
+    def factor(self):
+        _check("ncl_kkt_factor", load().ncl_kkt_factor(self._h, _stream_ptr()))
+
+    def info(self):
+        rep = Report()
+        _check("ncl_kkt_info", load().ncl_kkt_info(self._h, ctypes.byref(rep), _stream_ptr()))
+        return rep.as_dict()
+
+    def get_factors(self):
+        lx = np.empty(max(self.nnzL, 1), np.float64)
+        d = np.empty(self.N, np.float64)
+        _check("ncl_kkt_get_factors", load().ncl_kkt_get_factors(self._h, _np_ptr(lx), _np_ptr(d), _stream_ptr()))
+        return lx[:self.nnzL], d
+
+    def _solve(self, fn, b, out=None):
+        import torch
+        b2 = b if b.dim() == 2 else b.reshape(1, -1)
+        nrhs, ld = b2.shape
+        if out is None:
+            out = torch.empty_like(b2)
+        _check(fn, getattr(load(), fn)(self._h, self._dev(b2), self._dev(out), int(nrhs), int(ld), _stream_ptr()))
+        return out if b.dim() == 2 else out.reshape(-1)
+
+    def solve(self, b, out=None):
+        """x = K^{-1} b; b is (N,) or (nrhs, N) float64 on the device, layout order."""
+        return self._solve("ncl_kkt_solve", b, out)
+
+    def solve_adjoint(self, b, out=None):
+        return self._solve("ncl_kkt_solve_adjoint", b, out)
+
+    def __del__(self):
+        try:
+            if self._h:
+                load().ncl_kkt_destroy(self._h)
+                self._h = ctypes.c_void_p()
+        except Exception:
+            pass

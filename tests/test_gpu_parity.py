@@ -1,0 +1,173 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bars (FP64 throughout):
+* assembly: every K entry within 1e-12 * (|K_ij| + max_{j' != i} |K_ij'|);
+* factors: D within 1e-8 relative, L within 1e-8 of max(1, |L|) entrywise;
+* solve: relative solution error <= 1e-8 and normwise backward error
+  <= 1e-12, the residual taken with the oracle-assembled K;
+* inertia (n, m) and status NCL_OK; run-to-run results bitwise equal;
+  solve_adjoint bitwise equal to solve.
+"""
+import numpy as np
+import pytest
+
+import gridgen as G
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2510_13333_amd import KKT  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def small_pvpq():
+    return G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5)
+
+
+def check_assembly(kv, cp, ri, v):
+    N = cp.shape[0] - 1
+    col = np.repeat(np.arange(N), np.diff(cp))
+    off = ri != col
+    rowmax = np.zeros(N)
+    np.maximum.at(rowmax, ri[off], np.abs(v[off]))
+    np.maximum.at(rowmax, col[off], np.abs(v[off]))
+    tol = 1e-12 * (np.abs(v) + np.maximum(rowmax[ri], rowmax[col]))
+    err = np.abs(kv - v)
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, f"{bad.size} entries off, first at {bad[:5]}: {kv[bad[:5]]} vs {v[bad[:5]]}"
+
+
+def run_case(net, cfg, nrhs=1, iteration=0, factors=True, k=None):
+    z, s = G.draw_point(net, cfg, iteration=iteration)
+    if k is None:
+        k = KKT(net).bind(nrhs_max=nrhs)
+    k.assemble(dev(z), dev(s), net.rho)
+    cp, ri, v, pos = O.kkt(net, z, s)
+    kv = k.get_values().cpu().numpy()
+    check_assembly(kv, cp, ri, v)
+    k.factor()
+    info = k.info()
+    assert info["status"] == 0, info
+    assert info["npos"] == pos.is_primal.sum() and info["nneg"] == (~pos.is_primal).sum()
+    F = O.Factor(pos.N, cp, ri, np.array(pos.block_off))
+    assert F.factor(cp, ri, v, nthreads=8) == 0
+    if factors:
+        lx, d = k.get_factors()
+        np.testing.assert_allclose(d, F.d, rtol=1e-8)
+        assert (np.abs(lx - F.lx) <= 1e-8 * np.maximum(1.0, np.abs(F.lx))).all()
+    B = G.draw_rhs(pos.N, nrhs, cfg, iteration=iteration)
+    X = k.solve(dev(B)).cpu().numpy()
+    Xo = F.solve(B)
+    rel = np.abs(X - Xo).max() / np.abs(Xo).max()
+    eta = O.backward_error(cp, ri, v, X, B)
+    assert rel <= 1e-8, rel
+    assert eta <= 1e-12, eta
+    return k, (z, s, B, X)
+
+
+def test_c1_four_rhs():
+    run_case(G.config_network(1), 1, nrhs=4)
+
+
+def test_pvpq_border_small():
+    run_case(small_pvpq(), 99, nrhs=2)
+
+
+def test_tiny_networks():
+    run_case(G.make_network(7, 2, 1, 1, 0), 7)
+    run_case(G.make_network(8, 5, 6, 2, 1), 8)           # one contingency, border of 2
+    run_case(G.make_network(9, 6, 8, 2, 1, pvpq=True, rho=1e5), 9)
+
+
+def test_c2_refactor_same_pattern():
+    net = G.config_network(2)
+    k = None
+    for it in range(3):
+        k, _ = run_case(net, 2, iteration=it, factors=(it == 0), k=k)
+
+
+def test_c3_full_size():
+    run_case(G.config_network(3), 3, factors=False)
+
+
+def test_determinism_and_adjoint():
+    net = G.config_network(2)
+    k, (z, s, B, X) = run_case(net, 2, nrhs=2, factors=False)
+    lx1, d1 = k.get_factors()
+    Bd = dev(B)
+    X1 = k.solve(Bd).cpu().numpy()
+    k.assemble(dev(z), dev(s), net.rho)
+    k.factor()
+    lx2, d2 = k.get_factors()
+    X2 = k.solve(Bd).cpu().numpy()
+    Xa = k.solve_adjoint(Bd).cpu().numpy()
+    assert np.array_equal(lx1, lx2) and np.array_equal(d1, d2)
+    assert np.array_equal(X1, X2) and np.array_equal(X1, Xa)
+    # in-place solve (dx aliases db)
+    Bi = dev(B)
+    k.solve(Bi, out=Bi)
+    assert np.array_equal(Bi.cpu().numpy(), X1)
+
+
+def test_set_values_seam_random_quasidefinite():
+    """Arbitrary quasi-definite values on a block-arrowhead pattern through
+    ncl_kkt_analyze_pattern / ncl_kkt_set_values."""
+    net = G.make_network(2, 30, 41, 6, 3)
+    k0 = KKT(net)
+    cp, ri = k0.pattern()
+    z, s = G.draw_point(net, 2)
+    _, _, _, pos = O.kkt(net, z, s)
+    g = np.random.default_rng(3)
+    v = g.standard_normal(cp[-1])
+    col = np.repeat(np.arange(pos.N), np.diff(cp))
+    diag = ri == col
+    # make the primal block diagonally dominant and the dual diagonal negative
+    rowabs = np.zeros(pos.N)
+    np.add.at(rowabs, ri[~diag], np.abs(v[~diag]))
+    np.add.at(rowabs, col[~diag], np.abs(v[~diag]))
+    prim = pos.is_primal
+    dv = np.where(prim[col[diag]], rowabs[col[diag]] + 10.0 ** g.uniform(-3, 3, diag.sum()),
+                  -(10.0 ** g.uniform(-6, 0, diag.sum())))
+    v[diag] = dv
+    k = KKT(pattern=(pos.N, np.array(pos.block_off), cp, ri, prim.astype(np.uint8))).bind()
+    k.set_values(dev(v))
+    k.factor()
+    info = k.info()
+    assert info["status"] == 0 and info["npos"] == prim.sum()
+    F = O.Factor(pos.N, cp, ri, np.array(pos.block_off))
+    assert F.factor(cp, ri, v) == 0
+    lx, d = k.get_factors()
+    np.testing.assert_allclose(d, F.d, rtol=1e-10)
+    b = G.draw_rhs(pos.N, 1, 2)
+    x = k.solve(dev(b)).cpu().numpy()
+    assert O.backward_error(cp, ri, v, x, b) <= 1e-13
+
+
+def test_wrong_sign_pivot_reported():
+    """A primal diagonal made negative: the factorisation completes (finite
+    numbers) and reports NCL_ERR_INERTIA at the first wrong-sign pivot."""
+    net = G.config_network(1)
+    k0 = KKT(net)
+    cp, ri = k0.pattern()
+    z, s = G.draw_point(net, 1)
+    cpo, rio, v, pos = O.kkt(net, z, s)
+    col = np.repeat(np.arange(pos.N), np.diff(cp))
+    j = int(np.flatnonzero(pos.is_primal)[5])
+    q = np.flatnonzero((ri == j) & (col == j))[0]
+    v = v.copy()
+    v[q] = -1e9
+    k = KKT(pattern=(pos.N, np.array(pos.block_off), cp, ri, pos.is_primal.astype(np.uint8))).bind()
+    k.set_values(dev(v))
+    k.factor()
+    info = k.info()
+    assert info["status"] == -6
+    F = O.Factor(pos.N, cp, ri, np.array(pos.block_off))
+    F.factor(cp, ri, v)
+    prim_new = pos.is_primal[F.perm]
+    wrong = np.flatnonzero((F.d > 0) != prim_new)
+    assert info["first_bad"] == wrong[0]

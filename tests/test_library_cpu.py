@@ -1,0 +1,124 @@
+"""Host-side tests of libnclkkt (no GPU): the C ABI loads and exports every
+declared symbol, the symbolic analysis equals the oracle's bit for bit, the
+K pattern equals the oracle assembly's pattern, and bad inputs are
+rejected with NCL_ERR_ARG."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import gridgen as G
+import oracle as O
+from paper_2510_13333_amd import KKT, NclError, library_path, load
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ncl_kkt.h")).read()
+    names = set(re.findall(r"\b(ncl_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 17
+    lib = ctypes.CDLL(library_path())
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def _compare(k, F):
+    s = k.symbolic()
+    for key, ref in [("perm", F.perm), ("etree", F.parent), ("colcount", F.colcount), ("lcolptr", F.lp),
+                     ("lrowind", F.li), ("super_ptr", F.sup), ("srowptr", F.srp), ("srowind", F.sri)]:
+        assert np.array_equal(s[key], ref), key
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_symbolic_bit_exact(cfg):
+    net = G.config_network(cfg)
+    _compare(KKT(net), O.Factor.from_network(net))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_symbolic_bit_exact_random_small(seed):
+    g = np.random.default_rng(seed)
+    nb = int(g.integers(8, 40))
+    ng = int(g.integers(2, max(3, nb // 4)))
+    nl = int(nb - 1 + g.integers(2, nb // 2 + 3))
+    pvpq = bool(seed % 2)
+    net = G.make_network(50 + seed, nb, nl, ng, int(g.integers(1, 5)), pvpq=pvpq, topology="uniform" if seed >= 2 else "geo")
+    _compare(KKT(net), O.Factor.from_network(net))
+
+
+@pytest.mark.parametrize("relax", [(1, 0, 1), (4, 1, 2), (32, 1, 1)])
+def test_symbolic_relax_parameters(relax):
+    net = G.make_network(2, 60, 84, 10, 3)
+    _compare(KKT(net, relax=relax), O.Factor.from_network(net, relax=relax))
+
+
+@pytest.mark.slow
+def test_symbolic_bit_exact_c5():
+    net = G.config_network(5)
+    _compare(KKT(net), O.Factor.from_network(net))
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_pattern_matches_oracle(cfg):
+    net = G.config_network(cfg) if cfg == 1 else G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5)
+    k = KKT(net)
+    z, s = G.draw_point(net, cfg)
+    cp, ri, _, pos = O.kkt(net, z, s)
+    kcp, kri = k.pattern()
+    assert k.N == pos.N and k.nnzK == cp[-1]
+    assert np.array_equal(kcp, cp) and np.array_equal(kri, ri)
+    assert k.nprimal == int(pos.is_primal.sum())
+
+
+def test_analyze_pattern_seam_matches_network_analysis():
+    net = G.make_network(2, 30, 41, 6, 3)
+    k1 = KKT(net)
+    cp, ri = k1.pattern()
+    z, s = G.draw_point(net, 2)
+    _, _, _, pos = O.kkt(net, z, s)
+    k2 = KKT(pattern=(k1.N, np.array(pos.block_off), cp, ri, pos.is_primal.astype(np.uint8)))
+    a, b = k1.symbolic(), k2.symbolic()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_bad_inputs_rejected():
+    net = G.config_network(1)
+    bad = G.make_network(1, 30, 41, 6, 0)
+    bad.br_to = bad.br_to.copy()
+    bad.br_to[0] = 999
+    with pytest.raises(NclError) as e:
+        KKT(bad)
+    assert e.value.code == -1
+    dup = G.make_network(1, 30, 41, 6, 0)
+    dup.gen_bus = dup.gen_bus.copy()
+    dup.gen_bus[1] = dup.gen_bus[0]
+    with pytest.raises(NclError):
+        KKT(dup)
+    two = G.make_network(2, 30, 41, 6, 2)
+    two.outage = np.array([3, 3], np.int32)
+    with pytest.raises(NclError):
+        KKT(two)
+    # calls out of order: no workspace bound
+    k = KKT(net)
+    L = load()
+    assert L.ncl_kkt_factor(k._h, None) == -4
+    assert L.ncl_kkt_solve(k._h, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, k.N, None) == -4
+    assert L.ncl_kkt_workspace_bytes(k._h, 0, ctypes.byref(ctypes.c_size_t())) == -1
+    assert L.ncl_status_string(-6) == b"pivot of the wrong sign (inertia)"
+
+
+def test_pattern_seam_rejects_block_coupling():
+    N = 6
+    # blocks [0,2), [2,4), border [4,6); entry (2,1) couples two blocks
+    cols = {0: [0, 1], 1: [1, 2], 2: [2, 3], 3: [3], 4: [4, 5], 5: [5]}
+    cp = np.zeros(N + 1, np.int64)
+    ri = []
+    for c in range(N):
+        ri += cols[c]
+        cp[c + 1] = len(ri)
+    with pytest.raises(NclError):
+        KKT(pattern=(N, np.array([0, 2, 4]), cp, np.array(ri, np.int32), np.ones(N, np.uint8)))
