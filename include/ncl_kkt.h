@@ -189,6 +189,15 @@ int ncl_kkt_get_values(ncl_kkt *h, double *dvals, void *stream);
  * of the border.  Asynchronous; see ncl_kkt_info. */
 int ncl_kkt_factor(ncl_kkt *h, void *stream);
 
+/* The two phases of ncl_kkt_factor, callable separately (same result):
+ * factor_blocks factors every block and forms each block's border Schur
+ * contribution K_bk K_kk^{-1} K_kb; factor_border sums those
+ * contributions in block order, subtracts them from K_bb and factors the
+ * dense border.  factor_border returns NCL_ERR_STATE unless factor_blocks
+ * ran since the last bind. */
+int ncl_kkt_factor_blocks(ncl_kkt *h, void *stream);
+int ncl_kkt_factor_border(ncl_kkt *h, void *stream);
+
 /* Synchronises `stream` and reports the last factorisation. */
 int ncl_kkt_info(ncl_kkt *h, ncl_kkt_report *rep, void *stream);
 

@@ -418,6 +418,7 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.bprim_dev = base + p.bprim;
     h.bound = true;
     h.factored = false;
+    h.blocks_done = false;
     return NCL_OK;
 }
 
@@ -462,10 +463,7 @@ int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
                                  reinterpret_cast<hipStream_t>(stream)));
 }
 
-int ncl_kkt_factor(ncl_kkt *k, void *stream) {
-    if (!k) return NCL_ERR_ARG;
-    Handle &h = k->h;
-    if (!h.bound) return NCL_ERR_STATE;
+static ncl::FactorArgs factor_args(Handle &h) {
     ncl::FactorArgs fa{};
     fa.tmpls = h.d.tmpl;
     fa.blks = h.d.blk;
@@ -476,6 +474,10 @@ int ncl_kkt_factor(ncl_kkt *k, void *stream) {
     fa.stat = h.d.stat;
     fa.dminmax = h.d.dmm;
     fa.nbd = h.nbd;
+    return fa;
+}
+
+static ncl::BorderArgs border_args(Handle &h) {
     ncl::BorderArgs ba{};
     ba.nblk = h.nblk;
     ba.nbd = h.nbd;
@@ -489,9 +491,31 @@ int ncl_kkt_factor(ncl_kkt *k, void *stream) {
     ba.bprimal = h.bprim_dev;
     ba.stat = h.d.stat;
     ba.dminmax = h.d.dmm;
-    int rc = hip_rc(ncl::launch_factor(fa, ba, h.nblk, reinterpret_cast<hipStream_t>(stream)));
+    return ba;
+}
+
+int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
+    if (!k) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound) return NCL_ERR_STATE;
+    h.blocks_done = false;
+    int rc = hip_rc(ncl::launch_factor_blocks(factor_args(h), h.nblk, reinterpret_cast<hipStream_t>(stream)));
+    if (rc == NCL_OK) h.blocks_done = true;
+    return rc;
+}
+
+int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
+    if (!k) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound || !h.blocks_done) return NCL_ERR_STATE;
+    int rc = hip_rc(ncl::launch_factor_border(border_args(h), reinterpret_cast<hipStream_t>(stream)));
     if (rc == NCL_OK) h.factored = true;
     return rc;
+}
+
+int ncl_kkt_factor(ncl_kkt *k, void *stream) {
+    int rc = ncl_kkt_factor_blocks(k, stream);
+    return rc ? rc : ncl_kkt_factor_border(k, stream);
 }
 
 int ncl_kkt_info(ncl_kkt *k, ncl_kkt_report *rep, void *stream) {

@@ -55,7 +55,8 @@ struct SolveArgs {
 };
 
 hipError_t launch_assemble(const AsmArgs &a, hipStream_t st);
-hipError_t launch_factor(const FactorArgs &fa, const BorderArgs &ba, int nblk, hipStream_t st);
+hipError_t launch_factor_blocks(const FactorArgs &fa, int nblk, hipStream_t st);
+hipError_t launch_factor_border(const BorderArgs &ba, hipStream_t st);
 hipError_t launch_solve(const SolveArgs &a, hipStream_t st);
 
 }  // namespace ncl

@@ -648,13 +648,16 @@ hipError_t launch_assemble(const AsmArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_factor(const FactorArgs &fa, const BorderArgs &ba, int nblk, hipStream_t st) {
+hipError_t launch_factor_blocks(const FactorArgs &fa, int nblk, hipStream_t st) {
     hipLaunchKernelGGL(k_factor_blocks, dim3(nblk), dim3(kFactorThreads), 0, st, fa);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || ba.nbd == 0) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_border(const BorderArgs &ba, hipStream_t st) {
+    if (ba.nbd == 0) return hipSuccess;
     const int64_t npk = int64_t(ba.nbd) * (ba.nbd + 1) / 2;
     hipLaunchKernelGGL(k_border_sum, dim3(unsigned((npk + 255) / 256)), dim3(256), 0, st, ba);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lbytes = size_t(npk) * sizeof(double);
     const int use_lds = lbytes <= 160 * 1024 - 4096 ? 1 : 0;

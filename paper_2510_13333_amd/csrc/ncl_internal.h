@@ -169,6 +169,7 @@ struct Handle {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     bool factored = false;
+    bool blocks_done = false;
     bool bound = false;
     // device pointers (inside the workspace)
     struct Dev {

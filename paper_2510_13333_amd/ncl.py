@@ -79,6 +79,8 @@ def load():
         "ncl_kkt_set_values": ([P, P, P], ctypes.c_int),
         "ncl_kkt_get_values": ([P, P, P], ctypes.c_int),
         "ncl_kkt_factor": ([P, P], ctypes.c_int),
+        "ncl_kkt_factor_blocks": ([P, P], ctypes.c_int),
+        "ncl_kkt_factor_border": ([P, P], ctypes.c_int),
         "ncl_kkt_info": ([P, P, P], ctypes.c_int),
         "ncl_kkt_get_factors": ([P, P, P, P], ctypes.c_int),
         "ncl_kkt_solve": ([P, P, P, i32, i64, P], ctypes.c_int),
@@ -213,6 +215,12 @@ class KKT:
 
     def factor(self):
         _check("ncl_kkt_factor", load().ncl_kkt_factor(self._h, _stream_ptr()))
+
+    def factor_blocks(self):
+        _check("ncl_kkt_factor_blocks", load().ncl_kkt_factor_blocks(self._h, _stream_ptr()))
+
+    def factor_border(self):
+        _check("ncl_kkt_factor_border", load().ncl_kkt_factor_border(self._h, _stream_ptr()))
 
     def info(self):
         rep = Report()
