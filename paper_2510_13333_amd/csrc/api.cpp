@@ -24,24 +24,31 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts) {
         if (opts->relax_zden) { znum = opts->relax_znum; zden = opts->relax_zden; }
         if (maxw < 1 || zden <= 0 || znum < 0) return NCL_ERR_ARG;
     }
+    h.block_bl.assign(h.nblk, 0);
+    for (auto &t : h.tmpl) t.blocks.clear();
+    for (int b = 0; b < h.nblk; b++) {
+        Template &t = h.tmpl[h.block_tmpl[b]];
+        h.block_bl[b] = int32_t(t.blocks.size());
+        t.blocks.push_back(b);
+    }
     for (auto &t : h.tmpl) {
         int rc = ncl::analyze_template(t, h.nbd, maxw, znum, zden);
         if (rc) return rc;
-        rc = ncl::build_schedule(t, h.nbd);
+        rc = ncl::build_template_schedule(t, h.nbd);
         if (rc) return rc;
     }
     int rc = ncl::analyze_border(h, maxw, znum, zden);
     if (rc) return rc;
+    rc = ncl::build_schedule(h);
+    if (rc) return rc;
     h.nnzL = 0;
     h.nsuper = 0;
     h.npanel = 0;
-    h.lbase.assign(h.nblk + 1, 0);
     for (int b = 0; b < h.nblk; b++) {
         const Template &t = h.tmpl[h.block_tmpl[b]];
         h.nnzL += t.lp[t.n];
         h.nsuper += int64_t(t.sup.size()) - 1;
         h.npanel += int64_t(t.sri.size());
-        h.lbase[b + 1] = h.lbase[b] + t.panel_off.back();
     }
     if (h.nbd) {
         h.nnzL += h.blp[h.nbd];
@@ -58,89 +65,144 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts) {
     return NCL_OK;
 }
 
-struct Layout {
+// Workspace layout: schedule tables first, then the numeric arrays.  The
+// same walk sizes the workspace and, with a staging buffer, copies the
+// tables for upload.
+struct WsLayout {
     size_t off = 0;
-    size_t take(size_t bytes) {
-        size_t o = off;
-        off = align_up(off + bytes);
+    std::vector<uint8_t> *stage = nullptr;
+    size_t take(const void *src, size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + kAlign - 1) & ~(kAlign - 1);
+        if (stage) {
+            if (stage->size() < off) stage->resize(off, 0);
+            if (bytes && src) std::memcpy(stage->data() + o, src, bytes);
+        }
         return o;
     }
+    template <class T>
+    size_t vec(const std::vector<T> &v) { return take(v.data(), v.size() * sizeof(T)); }
 };
 
-template <class T>
-size_t vbytes(const std::vector<T> &v) { return v.size() * sizeof(T); }
-
-// All device memory the handle uses, carved from one buffer.
 struct Plan {
-    size_t tables_end = 0, total = 0;
-    size_t kval, lpan, dval, spart, sbb, ybuf, cpart, stat, dmm;
-    size_t tdev, bdev, kbb, bpg, c2, brr, brx, bprim;
-    std::vector<std::vector<size_t>> toff;   // per template, per array
+    std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
+    size_t tdev = 0, bdev = 0, work = 0, kbb = 0, bpg = 0, c2 = 0, brr = 0, brx = 0, bprim = 0, tables_end = 0;
+    size_t kval = 0, lpan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, stat = 0, total = 0;
 };
 
-template <class T>
-void stage(std::vector<uint8_t> &buf, size_t off, const std::vector<T> &v) {
-    if (!v.empty()) std::memcpy(buf.data() + off, v.data(), vbytes(v));
+std::vector<uint8_t> col_primal(const Template &t) {
+    std::vector<uint8_t> cp(t.n);
+    for (int j = 0; j < t.n; j++) cp[j] = t.is_primal[t.perm[j]];
+    return cp;
 }
 
-Plan plan_ws(const Handle &h, int64_t nrhs) {
+std::vector<ncl::Work> all_work(Handle &h) {
+    const ncl::Schedule &S = h.sched;
+    std::vector<ncl::Work> w;
+    auto app = [&](const std::vector<ncl::Work> &v, size_t &off) {
+        off = w.size();
+        w.insert(w.end(), v.begin(), v.end());
+    };
+    app(S.a, h.w_a);
+    app(S.b, h.w_b);
+    app(S.c, h.w_c);
+    app(S.f, h.w_f);
+    app(S.d, h.w_d);
+    app(S.g, h.w_g);
+    app(S.bpart, h.w_bpart);
+    app(S.schur, h.w_schur);
+    return w;
+}
+
+Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     Plan p;
-    Layout L;
+    WsLayout L;
+    L.stage = stage;
     p.toff.resize(h.tmpl.size());
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         std::vector<size_t> &o = p.toff[ti];
-        o.push_back(L.take(vbytes(t.sup)));
-        o.push_back(L.take(vbytes(t.srp)));
-        o.push_back(L.take(vbytes(t.sri)));
-        o.push_back(L.take(vbytes(t.panel_off)));
-        o.push_back(L.take(vbytes(t.lev_sup_ptr)));
-        o.push_back(L.take(vbytes(t.lev_sup)));
-        o.push_back(L.take(vbytes(t.lev_task_ptr)));
-        o.push_back(L.take(vbytes(t.task_s)));
-        o.push_back(L.take(vbytes(t.task_p)));
-        o.push_back(L.take(vbytes(t.task_gptr)));
-        o.push_back(L.take(vbytes(t.gitems)));
-        o.push_back(L.take(vbytes(t.crel)));
-        o.push_back(L.take(vbytes(t.task_aptr)));
-        o.push_back(L.take(vbytes(t.aents)));
-        o.push_back(L.take(vbytes(t.lev_dtask_ptr)));
-        o.push_back(L.take(vbytes(t.dtask)));
-        o.push_back(L.take(vbytes(t.bpath_ptr)));
-        o.push_back(L.take(vbytes(t.bpath_s)));
-        o.push_back(L.take(vbytes(t.bpath_pos)));
-        o.push_back(L.take(vbytes(t.bus_idx)));
-        o.push_back(L.take(vbytes(t.bus_slot)));
-        o.push_back(L.take(vbytes(t.bus_adj_ptr)));
-        o.push_back(L.take(vbytes(t.bus_adj)));
-        o.push_back(L.take(vbytes(t.br_slot)));
-        o.push_back(L.take(vbytes(t.br_idx)));
-        o.push_back(L.take(vbytes(t.gen_idx)));
-        o.push_back(L.take(vbytes(t.gen_slot)));
-        o.push_back(L.take(vbytes(t.perm)));
-        o.push_back(L.take(size_t(t.n)));      // col_primal
+        o.push_back(L.vec(t.blocks));
+        o.push_back(L.vec(t.sup));
+        o.push_back(L.vec(t.srp));
+        o.push_back(L.vec(t.sri));
+        o.push_back(L.vec(t.panel_off));
+        o.push_back(L.vec(t.task_s));
+        o.push_back(L.vec(t.task_p));
+        o.push_back(L.vec(t.task_cbase));
+        o.push_back(L.vec(t.ent_kpos));
+        o.push_back(L.vec(t.ent_out));
+        o.push_back(L.vec(t.ent_iptr));
+        o.push_back(L.vec(t.citems));
+        o.push_back(L.vec(t.bpath_ptr));
+        o.push_back(L.vec(t.bpath_s));
+        o.push_back(L.vec(t.bpath_pos));
+        o.push_back(L.vec(t.sitem_ptr));
+        o.push_back(L.vec(t.sitems));
+        o.push_back(L.vec(t.bus_idx));
+        o.push_back(L.vec(t.bus_slot));
+        o.push_back(L.vec(t.bus_adj_ptr));
+        o.push_back(L.vec(t.bus_adj));
+        o.push_back(L.vec(t.br_slot));
+        o.push_back(L.vec(t.br_idx));
+        o.push_back(L.vec(t.gen_idx));
+        o.push_back(L.vec(t.gen_slot));
+        o.push_back(L.vec(t.perm));
+        o.push_back(L.vec(col_primal(t)));
     }
-    p.tdev = L.take(sizeof(ncl::TemplDev) * h.tmpl.size());
-    p.bdev = L.take(sizeof(ncl::BlockDev) * size_t(h.nblk));
-    p.kbb = L.take(vbytes(h.kbb_pos));
-    p.bpg = L.take(vbytes(h.border_pg));
-    p.c2 = L.take(vbytes(h.gen_c2));
-    p.brr = L.take(vbytes(h.br_r));
-    p.brx = L.take(vbytes(h.br_x));
-    p.bprim = L.take(vbytes(h.border_primal));
+    p.tdev = L.take(nullptr, sizeof(ncl::TemplDev) * h.tmpl.size());
+    p.bdev = L.take(nullptr, sizeof(ncl::BlockDev) * size_t(h.nblk));
+    p.work = L.vec(all_work(h));
+    p.kbb = L.vec(h.kbb_pos);
+    p.bpg = L.vec(h.border_pg);
+    p.c2 = L.vec(h.gen_c2);
+    p.brr = L.vec(h.br_r);
+    p.brx = L.vec(h.br_x);
+    p.bprim = L.vec(h.border_primal);
     p.tables_end = L.off;
+    L.stage = nullptr;
     const int64_t npk = int64_t(h.nbd) * (h.nbd + 1) / 2;
-    p.kval = L.take(sizeof(double) * size_t(h.nnzK));
-    p.lpan = L.take(sizeof(double) * size_t(h.lbase[h.nblk]));
-    p.dval = L.take(sizeof(double) * size_t(h.N));
-    p.spart = L.take(sizeof(double) * size_t(h.nblk) * size_t(npk));
-    p.sbb = L.take(sizeof(double) * size_t(npk));
-    p.ybuf = L.take(sizeof(double) * size_t(h.N) * size_t(nrhs));
-    p.cpart = L.take(sizeof(double) * size_t(nrhs) * size_t(h.nblk) * size_t(h.nbd));
-    p.stat = L.take(sizeof(int64_t) * 4 * size_t(h.nblk + 1));
-    p.dmm = L.take(sizeof(double) * 2 * size_t(h.nblk + 1));
+    const int64_t nbb = h.nbd ? h.bcolptr[h.nbd] : 0;
+    p.kval = L.take(nullptr, sizeof(double) * size_t(h.kint + nbb));
+    p.lpan = L.take(nullptr, sizeof(double) * size_t(h.lint));
+    p.dval = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd));
+    p.spart = L.take(nullptr, sizeof(double) * size_t(npk) * size_t(h.nblk));
+    p.sbb = L.take(nullptr, sizeof(double) * size_t(npk));
+    p.ybuf = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd) * size_t(nrhs));
+    p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.nblk) * size_t(h.nbd));
+    p.stat = L.take(nullptr, sizeof(int64_t) * 8);
     p.total = L.off;
     return p;
+}
+
+ncl::DevArgs dev_args(const Handle &h) {
+    ncl::DevArgs a{};
+    a.tmpls = h.d.tmpl;
+    a.blks = h.d.blk;
+    a.ntmpl = int(h.tmpl.size());
+    a.nblk = h.nblk;
+    a.nbd = h.nbd;
+    a.nb = h.nb;
+    a.ng = h.ng;
+    a.N = h.N;
+    a.bstart = h.block_off[h.nblk];
+    a.kint = h.kint;
+    a.dint = h.dint;
+    a.kval = h.d.kval;
+    a.lpan = h.d.lpan;
+    a.dval = h.d.dval;
+    a.spart = h.d.spart;
+    a.sbb = h.d.sbb;
+    a.ybuf = h.d.ybuf;
+    a.cpart = h.d.cpart;
+    a.stat = h.d.stat;
+    a.kbb_pos = h.d.kbb_pos;
+    a.border_pg = h.d.border_pg;
+    a.gen_c2 = h.d.gen_c2;
+    a.br_r = h.d.br_r;
+    a.br_x = h.d.br_x;
+    a.bprim = h.d.bprim;
+    return a;
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? NCL_OK : NCL_ERR_HIP; }
@@ -313,87 +375,73 @@ int ncl_kkt_pattern(const ncl_kkt *k, int64_t *colptr, int32_t *rowind) {
 
 int ncl_kkt_workspace_bytes(const ncl_kkt *k, int32_t nrhs_max, size_t *bytes) {
     if (!k || !bytes || nrhs_max < 1) return NCL_ERR_ARG;
-    *bytes = plan_ws(k->h, nrhs_max).total;
+    *bytes = plan_ws(const_cast<Handle &>(k->h), nrhs_max, nullptr).total;
     return NCL_OK;
 }
 
 int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_max, void *stream) {
     if (!k || !dptr || nrhs_max < 1 || (reinterpret_cast<uintptr_t>(dptr) & (kAlign - 1))) return NCL_ERR_ARG;
     Handle &h = k->h;
-    Plan p = plan_ws(h, nrhs_max);
+    std::vector<uint8_t> buf;
+    Plan p = plan_ws(h, nrhs_max, &buf);
     if (bytes < p.total) return NCL_ERR_ARG;
+    buf.resize(p.tables_end, 0);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     uint8_t *base = static_cast<uint8_t *>(dptr);
-    std::vector<uint8_t> buf(p.tables_end, 0);
     std::vector<ncl::TemplDev> tdev(h.tmpl.size());
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const std::vector<size_t> &o = p.toff[ti];
-        int q = 0;
-        auto put = [&](const auto &v) {
-            stage(buf, o[q], v);
-            return base + o[q++];
-        };
         ncl::TemplDev &d = tdev[ti];
+        auto at = [&](int q) { return base + o[q]; };
         d.n = t.n;
         d.nsup = int32_t(t.sup.size()) - 1;
-        d.nlev = t.nlev;
-        d.ntask = int32_t(t.task_s.size());
+        d.nblk = int32_t(t.blocks.size());
         d.nbd = h.nbd;
-        d.nb = h.nb;
-        d.nl = h.nl;
-        d.ng = h.ng;
-        d.panel_size = t.panel_off.back();
+        d.kbase = h.t_kbase[ti];
+        d.lbase = h.t_lbase[ti];
+        d.dbase = h.t_dbase[ti];
+        d.nnz = int32_t(t.colptr[t.n]);
         d.pvpq_rows = t.pvpq_rows;
         d.has_pg_local = t.pg_local;
-        d.sup_first = reinterpret_cast<const int32_t *>(put(t.sup));
-        d.sup_rowptr = reinterpret_cast<const int32_t *>(put(t.srp));
-        d.sup_rows = reinterpret_cast<const int32_t *>(put(t.sri));
-        d.panel_off = reinterpret_cast<const int32_t *>(put(t.panel_off));
-        d.lev_sup_ptr = reinterpret_cast<const int32_t *>(put(t.lev_sup_ptr));
-        d.lev_sup = reinterpret_cast<const int32_t *>(put(t.lev_sup));
-        d.lev_task_ptr = reinterpret_cast<const int32_t *>(put(t.lev_task_ptr));
-        d.task_s = reinterpret_cast<const int32_t *>(put(t.task_s));
-        d.task_p = reinterpret_cast<const int32_t *>(put(t.task_p));
-        d.task_gptr = reinterpret_cast<const int32_t *>(put(t.task_gptr));
-        d.gitems = reinterpret_cast<const ncl::GItem *>(put(t.gitems));
-        d.crel = reinterpret_cast<const uint8_t *>(put(t.crel));
-        d.task_aptr = reinterpret_cast<const int32_t *>(put(t.task_aptr));
-        d.aents = reinterpret_cast<const ncl::AEnt *>(put(t.aents));
-        d.lev_dtask_ptr = reinterpret_cast<const int32_t *>(put(t.lev_dtask_ptr));
-        d.dtask = reinterpret_cast<const int32_t *>(put(t.dtask));
-        d.bpath_ptr = reinterpret_cast<const int32_t *>(put(t.bpath_ptr));
-        d.bpath_s = reinterpret_cast<const int32_t *>(put(t.bpath_s));
-        d.bpath_pos = reinterpret_cast<const int32_t *>(put(t.bpath_pos));
-        d.bus_idx = reinterpret_cast<const int32_t *>(put(t.bus_idx));
-        d.bus_slot = reinterpret_cast<const int32_t *>(put(t.bus_slot));
-        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(put(t.bus_adj_ptr));
-        d.bus_adj = reinterpret_cast<const int32_t *>(put(t.bus_adj));
-        d.br_slot = reinterpret_cast<const int32_t *>(put(t.br_slot));
-        d.br_idx = reinterpret_cast<const int32_t *>(put(t.br_idx));
-        d.gen_idx = reinterpret_cast<const int32_t *>(put(t.gen_idx));
-        d.gen_slot = reinterpret_cast<const int32_t *>(put(t.gen_slot));
-        d.perm = reinterpret_cast<const int32_t *>(put(t.perm));
-        std::vector<uint8_t> cp(t.n);
-        for (int j = 0; j < t.n; j++) cp[j] = t.is_primal[t.perm[j]];
-        d.col_primal = reinterpret_cast<const uint8_t *>(put(cp));
+        d.blocks = reinterpret_cast<const int32_t *>(at(0));
+        d.sup_first = reinterpret_cast<const int32_t *>(at(1));
+        d.sup_rowptr = reinterpret_cast<const int32_t *>(at(2));
+        d.sup_rows = reinterpret_cast<const int32_t *>(at(3));
+        d.panel_off = reinterpret_cast<const int32_t *>(at(4));
+        d.task_s = reinterpret_cast<const int32_t *>(at(5));
+        d.task_p = reinterpret_cast<const int32_t *>(at(6));
+        d.task_cbase = reinterpret_cast<const int32_t *>(at(7));
+        d.ent_kpos = reinterpret_cast<const int32_t *>(at(8));
+        d.ent_out = reinterpret_cast<const int32_t *>(at(9));
+        d.ent_iptr = reinterpret_cast<const int32_t *>(at(10));
+        d.citems = reinterpret_cast<const ncl::CItem *>(at(11));
+        d.bpath_ptr = reinterpret_cast<const int32_t *>(at(12));
+        d.bpath_s = reinterpret_cast<const int32_t *>(at(13));
+        d.bpath_pos = reinterpret_cast<const int32_t *>(at(14));
+        d.sitem_ptr = reinterpret_cast<const int32_t *>(at(15));
+        d.sitems = reinterpret_cast<const ncl::SItem *>(at(16));
+        d.bus_idx = reinterpret_cast<const int32_t *>(at(17));
+        d.bus_slot = reinterpret_cast<const int32_t *>(at(18));
+        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(19));
+        d.bus_adj = reinterpret_cast<const int32_t *>(at(20));
+        d.br_slot = reinterpret_cast<const int32_t *>(at(21));
+        d.br_idx = reinterpret_cast<const int32_t *>(at(22));
+        d.gen_idx = reinterpret_cast<const int32_t *>(at(23));
+        d.gen_slot = reinterpret_cast<const int32_t *>(at(24));
+        d.perm = reinterpret_cast<const int32_t *>(at(25));
+        d.col_primal = reinterpret_cast<const uint8_t *>(at(26));
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
     std::vector<ncl::BlockDev> bdev(h.nblk);
     for (int b = 0; b < h.nblk; b++) {
         bdev[b].tmpl = h.block_tmpl[b];
+        bdev[b].bl = h.block_bl[b];
         bdev[b].outage = h.block_outage[b];
         bdev[b].col0 = h.block_off[b];
-        bdev[b].kbase = h.kbase[b];
-        bdev[b].lbase = h.lbase[b];
+        bdev[b].kcsc = h.kbase[b];
     }
     std::memcpy(buf.data() + p.bdev, bdev.data(), sizeof(ncl::BlockDev) * bdev.size());
-    stage(buf, p.kbb, h.kbb_pos);
-    stage(buf, p.bpg, h.border_pg);
-    stage(buf, p.c2, h.gen_c2);
-    stage(buf, p.brr, h.br_r);
-    stage(buf, p.brx, h.br_x);
-    stage(buf, p.bprim, h.border_primal);
     if (hipMemcpyAsync(base, buf.data(), buf.size(), hipMemcpyHostToDevice, st) != hipSuccess) return NCL_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return NCL_ERR_HIP;
     h.ws = dptr;
@@ -401,11 +449,13 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.nrhs_max = nrhs_max;
     h.d.tmpl = reinterpret_cast<ncl::TemplDev *>(base + p.tdev);
     h.d.blk = reinterpret_cast<ncl::BlockDev *>(base + p.bdev);
+    h.d.work = reinterpret_cast<ncl::Work *>(base + p.work);
     h.d.kbb_pos = reinterpret_cast<int32_t *>(base + p.kbb);
     h.d.border_pg = reinterpret_cast<int32_t *>(base + p.bpg);
     h.d.gen_c2 = reinterpret_cast<double *>(base + p.c2);
-    h.d.br_g = reinterpret_cast<double *>(base + p.brr);
-    h.d.br_b = reinterpret_cast<double *>(base + p.brx);
+    h.d.br_r = reinterpret_cast<double *>(base + p.brr);
+    h.d.br_x = reinterpret_cast<double *>(base + p.brx);
+    h.d.bprim = reinterpret_cast<const uint8_t *>(base + p.bprim);
     h.d.kval = reinterpret_cast<double *>(base + p.kval);
     h.d.lpan = reinterpret_cast<double *>(base + p.lpan);
     h.d.dval = reinterpret_cast<double *>(base + p.dval);
@@ -414,8 +464,6 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.d.ybuf = reinterpret_cast<double *>(base + p.ybuf);
     h.d.cpart = reinterpret_cast<double *>(base + p.cpart);
     h.d.stat = reinterpret_cast<int64_t *>(base + p.stat);
-    h.d.dmm = reinterpret_cast<double *>(base + p.dmm);
-    h.bprim_dev = base + p.bprim;
     h.bound = true;
     h.factored = false;
     h.blocks_done = false;
@@ -426,72 +474,25 @@ int ncl_kkt_assemble(ncl_kkt *k, const ncl_kkt_point *pt, void *stream) {
     if (!k || !pt || !pt->z || !pt->sigma || !(pt->rho > 0)) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound || !h.from_network) return NCL_ERR_STATE;
-    ncl::AsmArgs a{};
-    a.tmpls = h.d.tmpl;
-    a.blks = h.d.blk;
-    a.nblk = h.nblk;
-    a.nb = h.nb;
-    a.ng = h.ng;
-    a.nbd = h.nbd;
-    a.z = pt->z;
-    a.sig = pt->sigma;
-    a.rho = pt->rho;
-    a.kval = h.d.kval;
-    a.kbase_border = h.kbase[h.nblk];
-    a.bstart = h.block_off[h.nblk];
-    a.br_r = h.d.br_g;
-    a.br_x = h.d.br_b;
-    a.gen_c2 = h.d.gen_c2;
-    a.border_pg = h.d.border_pg;
-    a.kbb_pos = h.d.kbb_pos;
-    return hip_rc(ncl::launch_assemble(a, reinterpret_cast<hipStream_t>(stream)));
+    return hip_rc(ncl::launch_assemble(dev_args(h), pt->z, pt->sigma, pt->rho, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_set_values(ncl_kkt *k, const double *dvals, void *stream) {
     if (!k || !dvals) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
-    return hip_rc(hipMemcpyAsync(h.d.kval, dvals, sizeof(double) * size_t(h.nnzK), hipMemcpyDeviceToDevice,
-                                 reinterpret_cast<hipStream_t>(stream)));
+    const int64_t nbb = h.nbd ? h.bcolptr[h.nbd] : 0;
+    return hip_rc(ncl::launch_values(dev_args(h), dvals, h.d.kval, true, nbb, h.kbase[h.nblk],
+                                     reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
     if (!k || !dvals) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
-    return hip_rc(hipMemcpyAsync(dvals, h.d.kval, sizeof(double) * size_t(h.nnzK), hipMemcpyDeviceToDevice,
-                                 reinterpret_cast<hipStream_t>(stream)));
-}
-
-static ncl::FactorArgs factor_args(Handle &h) {
-    ncl::FactorArgs fa{};
-    fa.tmpls = h.d.tmpl;
-    fa.blks = h.d.blk;
-    fa.kval = h.d.kval;
-    fa.lpan = h.d.lpan;
-    fa.dval = h.d.dval;
-    fa.spart = h.d.spart;
-    fa.stat = h.d.stat;
-    fa.dminmax = h.d.dmm;
-    fa.nbd = h.nbd;
-    return fa;
-}
-
-static ncl::BorderArgs border_args(Handle &h) {
-    ncl::BorderArgs ba{};
-    ba.nblk = h.nblk;
-    ba.nbd = h.nbd;
-    ba.kval = h.d.kval;
-    ba.kbase_border = h.kbase[h.nblk];
-    ba.kbb_pos = h.d.kbb_pos;
-    ba.spart = h.d.spart;
-    ba.sbb = h.d.sbb;
-    ba.dval = h.d.dval;
-    ba.bcol0 = h.block_off[h.nblk];
-    ba.bprimal = h.bprim_dev;
-    ba.stat = h.d.stat;
-    ba.dminmax = h.d.dmm;
-    return ba;
+    const int64_t nbb = h.nbd ? h.bcolptr[h.nbd] : 0;
+    return hip_rc(ncl::launch_values(dev_args(h), h.d.kval, dvals, false, nbb, h.kbase[h.nblk],
+                                     reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
@@ -499,16 +500,26 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
     h.blocks_done = false;
-    int rc = hip_rc(ncl::launch_factor_blocks(factor_args(h), h.nblk, reinterpret_cast<hipStream_t>(stream)));
-    if (rc == NCL_OK) h.blocks_done = true;
-    return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    const ncl::Schedule &S = h.sched;
+    const ncl::Work *W = h.d.work;
+    for (int l = 0; l < S.nlev; l++) {
+        hipError_t e = ncl::launch_factor_level(a, W + h.w_a + S.a_ptr[l], S.a_ptr[l + 1] - S.a_ptr[l],
+                                                W + h.w_b + S.b_ptr[l], S.b_ptr[l + 1] - S.b_ptr[l],
+                                                W + h.w_c + S.c_ptr[l], S.c_ptr[l + 1] - S.c_ptr[l], st);
+        if (e != hipSuccess) return NCL_ERR_HIP;
+    }
+    if (h.nbd && ncl::launch_schur(a, W + h.w_schur, int(S.schur.size()), st) != hipSuccess) return NCL_ERR_HIP;
+    h.blocks_done = true;
+    return NCL_OK;
 }
 
 int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
     if (!k) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound || !h.blocks_done) return NCL_ERR_STATE;
-    int rc = hip_rc(ncl::launch_factor_border(border_args(h), reinterpret_cast<hipStream_t>(stream)));
+    int rc = hip_rc(ncl::launch_factor_border(dev_args(h), reinterpret_cast<hipStream_t>(stream)));
     if (rc == NCL_OK) h.factored = true;
     return rc;
 }
@@ -522,31 +533,23 @@ int ncl_kkt_info(ncl_kkt *k, ncl_kkt_report *rep, void *stream) {
     if (!k || !rep) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.factored) return NCL_ERR_STATE;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const int nrow = h.nblk + (h.nbd ? 1 : 0);
-    std::vector<int64_t> s(4 * size_t(nrow));
-    std::vector<double> m(2 * size_t(nrow));
-    if (hipStreamSynchronize(st) != hipSuccess) return NCL_ERR_HIP;
-    if (hipMemcpy(s.data(), h.d.stat, sizeof(int64_t) * s.size(), hipMemcpyDeviceToHost) != hipSuccess) return NCL_ERR_HIP;
-    if (hipMemcpy(m.data(), h.d.dmm, sizeof(double) * m.size(), hipMemcpyDeviceToHost) != hipSuccess) return NCL_ERR_HIP;
-    int64_t bad = INT64_MAX;
-    rep->npos = rep->nneg = rep->nzero = 0;
-    rep->min_absd = INFINITY;
-    rep->max_absd = 0.0;
-    for (int r = 0; r < nrow; r++) {
-        rep->npos += s[4 * r];
-        rep->nneg += s[4 * r + 1];
-        rep->nzero += s[4 * r + 2];
-        bad = std::min(bad, s[4 * r + 3]);
-        rep->min_absd = std::min(rep->min_absd, m[2 * r]);
-        rep->max_absd = std::max(rep->max_absd, m[2 * r + 1]);
-    }
-    if (bad == INT64_MAX) {
+    int64_t s[6];
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return NCL_ERR_HIP;
+    if (hipMemcpy(s, h.d.stat, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return NCL_ERR_HIP;
+    rep->npos = s[0];
+    rep->nneg = s[1];
+    rep->nzero = s[2];
+    double mn, mx;
+    std::memcpy(&mn, &s[4], sizeof(double));
+    std::memcpy(&mx, &s[5], sizeof(double));
+    rep->min_absd = s[4] == INT64_MAX ? INFINITY : mn;
+    rep->max_absd = mx;
+    if (s[3] == INT64_MAX) {
         rep->first_bad = -1;
         rep->status = NCL_OK;
     } else {
-        rep->first_bad = bad / 8;
-        const int code = int(bad % 8);
+        rep->first_bad = s[3] / 8;
+        const int code = int(s[3] % 8);
         rep->status = code == 1 ? NCL_ERR_INERTIA : code == 2 ? NCL_ERR_ZERO_PIVOT : NCL_ERR_NONFINITE;
     }
     return NCL_OK;
@@ -556,22 +559,26 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
     if (!k) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.factored) return NCL_ERR_STATE;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (hipStreamSynchronize(st) != hipSuccess) return NCL_ERR_HIP;
-    if (dd && hipMemcpy(dd, h.d.dval, sizeof(double) * size_t(h.N), hipMemcpyDeviceToHost) != hipSuccess)
-        return NCL_ERR_HIP;
-    if (!lx) return NCL_OK;
-    std::vector<double> pan(size_t(h.lbase[h.nblk]));
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return NCL_ERR_HIP;
+    std::vector<double> pan(size_t(h.lint)), dv(size_t(h.dint + h.nbd));
     const int64_t npk = int64_t(h.nbd) * (h.nbd + 1) / 2;
     std::vector<double> sbb(static_cast<size_t>(npk));
     if (!pan.empty() && hipMemcpy(pan.data(), h.d.lpan, sizeof(double) * pan.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
+    if (!dv.empty() && hipMemcpy(dv.data(), h.d.dval, sizeof(double) * dv.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return NCL_ERR_HIP;
     if (npk && hipMemcpy(sbb.data(), h.d.sbb, sizeof(double) * sbb.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
+    const int64_t bstart = h.block_off[h.nblk];
     int64_t q = 0;
     for (int b = 0; b < h.nblk; b++) {
-        const Template &t = h.tmpl[h.block_tmpl[b]];
-        const double *P = pan.data() + h.lbase[b];
+        const int ti = h.block_tmpl[b];
+        const Template &t = h.tmpl[ti];
+        const int64_t nb = int64_t(t.blocks.size()), bl = h.block_bl[b];
+        const double *P = pan.data() + h.t_lbase[ti] + bl;
+        if (dd)
+            for (int j = 0; j < t.n; j++) dd[h.block_off[b] + j] = dv[size_t(h.t_dbase[ti] + int64_t(j) * nb + bl)];
+        if (!lx) continue;
         const int ns = int(t.sup.size()) - 1;
         for (int s = 0; s < ns; s++) {
             const int f = t.sup[s], w = t.sup[s + 1] - f, r = t.srp[s + 1] - t.srp[s];
@@ -579,18 +586,20 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
             for (int c = 0; c < w; c++) {
                 const int j = f + c;
                 for (int p = t.lp[j]; p < t.lp[j + 1]; p++) {
-                    const int32_t row = t.li[p];
-                    const int pos = int(std::lower_bound(R, R + r, row) - R);
-                    lx[q++] = P[t.panel_off[s] + int64_t(c) * r + pos];
+                    const int pos = int(std::lower_bound(R, R + r, t.li[p]) - R);
+                    lx[q++] = P[(int64_t(t.panel_off[s]) + int64_t(c) * r + pos) * nb];
                 }
             }
         }
     }
-    for (int j = 0; j < h.nbd; j++)
-        for (int p = h.blp[j]; p < h.blp[j + 1]; p++) {
-            const int i = h.bli[p];
-            lx[q++] = sbb[size_t(i) * (i + 1) / 2 + j];
-        }
+    if (dd)
+        for (int j = 0; j < h.nbd; j++) dd[bstart + j] = dv[size_t(h.dint + j)];
+    if (lx)
+        for (int j = 0; j < h.nbd; j++)
+            for (int p = h.blp[j]; p < h.blp[j + 1]; p++) {
+                const int i = h.bli[p];
+                lx[q++] = sbb[size_t(i) * (i + 1) / 2 + j];
+            }
     return NCL_OK;
 }
 
@@ -599,23 +608,32 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
     Handle &h = k->h;
     if (!h.bound || !h.factored) return NCL_ERR_STATE;
     if (nrhs > h.nrhs_max || ld < h.N) return NCL_ERR_ARG;
-    ncl::SolveArgs a{};
-    a.tmpls = h.d.tmpl;
-    a.blks = h.d.blk;
-    a.lpan = h.d.lpan;
-    a.dval = h.d.dval;
-    a.sbb = h.d.sbb;
-    a.ybuf = h.d.ybuf;
-    a.cpart = h.d.cpart;
-    a.b = db;
-    a.x = dx;
-    a.ld = ld;
-    a.N = h.N;
-    a.bstart = h.block_off[h.nblk];
-    a.nblk = h.nblk;
-    a.nbd = h.nbd;
-    a.nrhs = nrhs;
-    return hip_rc(ncl::launch_solve(a, reinterpret_cast<hipStream_t>(stream)));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    const ncl::Schedule &S = h.sched;
+    const ncl::Work *W = h.d.work;
+    for (int rhs = 0; rhs < nrhs; rhs++) {
+        const double *b = db + int64_t(rhs) * ld;
+        double *x = dx + int64_t(rhs) * ld;
+        double *y = h.d.ybuf + int64_t(rhs) * (h.dint + h.nbd);
+        double *cp = h.d.cpart + int64_t(rhs) * h.nblk * h.nbd;
+        if (ncl::launch_solve_load(a, b, y, st) != hipSuccess) return NCL_ERR_HIP;
+        for (int l = 0; l < S.nlev; l++)
+            if (ncl::launch_solve_fwd_level(a, y, W + h.w_f + S.f_ptr[l], S.f_ptr[l + 1] - S.f_ptr[l],
+                                            W + h.w_d + S.d_ptr[l], S.d_ptr[l + 1] - S.d_ptr[l], st) != hipSuccess)
+                return NCL_ERR_HIP;
+        if (h.nbd) {
+            if (ncl::launch_solve_bpart(a, y, cp, W + h.w_bpart, int(S.bpart.size()), st) != hipSuccess) return NCL_ERR_HIP;
+            if (ncl::launch_solve_border(a, b, x, y, cp, st) != hipSuccess) return NCL_ERR_HIP;
+        }
+        if (ncl::launch_solve_scale(a, y, st) != hipSuccess) return NCL_ERR_HIP;
+        for (int l = S.nlev - 1; l >= 0; l--)
+            if (ncl::launch_solve_bwd_level(a, y, W + h.w_g + S.g_ptr[l], S.g_ptr[l + 1] - S.g_ptr[l],
+                                            W + h.w_d + S.d_ptr[l], S.d_ptr[l + 1] - S.d_ptr[l], st) != hipSuccess)
+                return NCL_ERR_HIP;
+        if (ncl::launch_solve_store(a, y, x, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    return NCL_OK;
 }
 
 int ncl_kkt_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {

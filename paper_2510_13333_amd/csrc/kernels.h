@@ -1,4 +1,4 @@
-// Argument structs and launchers of the device kernels (kernels.hip).
+// Arguments and launchers of the device kernels (kernels.hip).
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -7,56 +7,40 @@
 
 namespace ncl {
 
-struct AsmArgs {
+// Device state shared by every kernel (pointers into the workspace).
+struct DevArgs {
     const TemplDev *tmpls;
     const BlockDev *blks;
-    int nblk, nb, ng, nbd;
-    const double *z, *sig;
-    double rho;
-    double *kval;
-    int64_t kbase_border, bstart;
-    const double *br_r, *br_x, *gen_c2;
-    const int32_t *border_pg, *kbb_pos;
+    int ntmpl, nblk, nbd;
+    int nb, ng;                 // network sizes (assembly)
+    int64_t N, bstart;          // global size and first border column (layout order)
+    int64_t kint;               // interleaved K values; the border K_bb values follow
+    int64_t dint;               // interleaved pivots; the border pivots follow
+    double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
+    int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits
+    const int32_t *kbb_pos;     // [nbd*nbd]
+    const int32_t *border_pg;
+    const double *gen_c2, *br_r, *br_x;
+    const uint8_t *bprim;
 };
 
-struct FactorArgs {
-    const TemplDev *tmpls;
-    const BlockDev *blks;
-    const double *kval;
-    double *lpan, *dval, *spart;
-    int64_t *stat;            // [nblk][4]: npos, nneg, nzero, first bad key (col*8+code)
-    double *dminmax;          // [nblk][2]
-    int nbd;
-};
-
-struct BorderArgs {
-    int nblk, nbd;
-    const double *kval;
-    int64_t kbase_border;
-    const int32_t *kbb_pos;
-    const double *spart;
-    double *sbb;               // packed lower S, then L_bb (unit lower, strict part) in place
-    double *dval;              // border pivots at dval[bcol0 ..]
-    int64_t bcol0;
-    const uint8_t *bprimal;
-    int64_t *stat;             // [nblk+1][4]; border row at nblk
-    double *dminmax;
-};
-
-struct SolveArgs {
-    const TemplDev *tmpls;
-    const BlockDev *blks;
-    const double *lpan, *dval, *sbb;
-    double *ybuf, *cpart;
-    const double *b;
-    double *x;
-    int64_t ld, N, bstart;
-    int nblk, nbd, nrhs;
-};
-
-hipError_t launch_assemble(const AsmArgs &a, hipStream_t st);
-hipError_t launch_factor_blocks(const FactorArgs &fa, int nblk, hipStream_t st);
-hipError_t launch_factor_border(const BorderArgs &ba, hipStream_t st);
-hipError_t launch_solve(const SolveArgs &a, hipStream_t st);
+hipError_t launch_assemble(const DevArgs &a, const double *z, const double *sig, double rho, hipStream_t st);
+hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, int64_t nnz_border,
+                         int64_t kcsc_border, hipStream_t st);
+hipError_t launch_factor_level(const DevArgs &a, const Work *wa, int na, const Work *wb, int nb, const Work *wc,
+                               int nc, hipStream_t st);
+hipError_t launch_schur(const DevArgs &a, const Work *ws, int nw, hipStream_t st);
+hipError_t launch_factor_border(const DevArgs &a, hipStream_t st);
+hipError_t launch_solve_load(const DevArgs &a, const double *b, double *y, hipStream_t st);
+hipError_t launch_solve_fwd_level(const DevArgs &a, double *y, const Work *wf, int nf, const Work *wd, int nd,
+                                  hipStream_t st);
+hipError_t launch_solve_bpart(const DevArgs &a, const double *y, double *cpart, const Work *wp, int np,
+                              hipStream_t st);
+hipError_t launch_solve_border(const DevArgs &a, const double *b, double *x, double *y, const double *cpart,
+                               hipStream_t st);
+hipError_t launch_solve_scale(const DevArgs &a, double *y, hipStream_t st);
+hipError_t launch_solve_bwd_level(const DevArgs &a, double *y, const Work *wg, int ng, const Work *wd, int nd,
+                                  hipStream_t st);
+hipError_t launch_solve_store(const DevArgs &a, const double *y, double *x, hipStream_t st);
 
 }  // namespace ncl

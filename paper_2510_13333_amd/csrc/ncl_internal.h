@@ -1,5 +1,12 @@
-// Internal structures of libnclkkt: host-side symbolic data and the plain
-// structs that carry device tables into the kernels.
+// Internal structures of libnclkkt: host-side symbolic data, schedules and
+// the plain structs that carry device tables into the kernels.
+//
+// Storage: blocks that share a template (all contingency blocks of a
+// network do) are processed together, one block per lane of a wavefront.
+// Every per-block numeric array of a template is therefore stored
+// interleaved: element e of the template's block number bl (its position in
+// the template's block list) lives at base + e * nb + bl, so that the 64
+// lanes of a wavefront touch 64 consecutive doubles.
 #pragma once
 
 #include <cstddef>
@@ -11,24 +18,30 @@
 
 namespace ncl {
 
-constexpr int kMaxW = 32;            // widest supernode (panel rows fit one thread's accumulator)
+constexpr int kMaxW = 32;            // widest supernode
 constexpr int32_t kBorderFlag = int32_t(1u << 30);   // slot refers to the border K_bb pattern
 
 // ---------------------------------------------------------------- device tables
 
-// One descendant supernode d's contribution to one panel row of a target
-// supernode s (factor), or to one column of s (forward solve).
-struct GItem {
-    int32_t ioff;    // offset (doubles, within the block's panel storage) of L_d[row, 0]
-    int32_t coff;    // offset of L_d[first row that is a column of s, 0]
+// One descendant supernode d's contribution to one entry (row, column c) of a
+// panel: sum_k L_d[row, k] d_k L_d[c, k], or (forward solve) to one column.
+struct CItem {
+    int32_t ioff;    // panel element of L_d[row, 0] (template-relative)
+    int32_t coff;    // panel element of L_d[c, 0]
     int32_t dcol;    // first column of d (block-local factor numbering)
-    int32_t crel;    // index of the first entry of d's target-column list in crel[]
-    int32_t meta;    // ld (16 bits) | wd << 16 | nc << 24
+    int32_t meta;    // ld (16 bits) | wd << 16
 };
 
-struct AEnt {        // one K entry of a panel row
-    int32_t kpos;    // position in the block's K values (template-relative CSC position)
-    int32_t crel;    // target column within the supernode
+// Common panels of two border rows (border Schur contribution).
+struct SItem {
+    int32_t s, pi, pj;
+};
+
+// A unit of work of one launch: template (high 16 bits) and block group
+// (low 16 bits), and the task / supernode / entry index within the template.
+struct Work {
+    int32_t tg;
+    int32_t k;
 };
 
 // Assembly slot indices (positions in the template CSC, or kBorderFlag|pos in K_bb, or -1).
@@ -52,33 +65,35 @@ enum BusIdx { BI_VM, BI_VA, BI_P, BI_Q, BI_N };
 enum GenIdx { GI_BUS, GI_QG, GI_PG, GI_NUP, GI_NUM, GI_SUP, GI_SLO, GI_LIN, GI_DUP, GI_DLO, GI_CUP, GI_CLO, GI_VM0, GI_N };
 
 struct TemplDev {
-    int32_t n, nsup, nlev, ntask;
-    int32_t nbd, nb, nl, ng;
-    int64_t panel_size;            // doubles of panel storage per block
+    int32_t n, nsup, nblk, nbd;     // columns, supernodes, blocks using the template, border size
+    int64_t kbase;                 // interleaved K values (nnz * nblk)
+    int64_t lbase;                 // interleaved panels (panel_size * nblk)
+    int64_t dbase;                 // interleaved pivots and solve vectors (n * nblk)
+    int32_t nnz;                   // K entries of one block
     int32_t pvpq_rows;             // this template has the complementarity rows
     int32_t has_pg_local;          // single-block network: pg inside the block
+    int32_t pad;
+    const int32_t *blocks;         // [nblk] global block ids
     // supernodes (block-local factor numbering; border rows are n + b)
     const int32_t *sup_first;      // [nsup+1]
     const int32_t *sup_rowptr;     // [nsup+1]
     const int32_t *sup_rows;
     const int32_t *panel_off;      // [nsup+1]
-    // level schedule
-    const int32_t *lev_sup_ptr;    // [nlev+1]
-    const int32_t *lev_sup;
-    const int32_t *lev_task_ptr;   // [nlev+1]
-    const int32_t *task_s;         // [ntask]
+    // row tasks: (supernode, panel row); entries of a task are its w columns
+    const int32_t *task_s;
     const int32_t *task_p;
-    const int32_t *task_gptr;      // [ntask+1]
-    const GItem *gitems;
-    const uint8_t *crel;
-    const int32_t *task_aptr;      // [ntask+1]
-    const AEnt *aents;
-    const int32_t *lev_dtask_ptr;  // [nlev+1] tasks whose row is a column of its supernode
-    const int32_t *dtask;
+    const int32_t *task_cbase;     // [ntask+1] first entry of each task
+    const int32_t *ent_kpos;       // [nent] K value of the entry or -1
+    const int32_t *ent_out;        // [nent] panel element of the entry
+    const int32_t *ent_iptr;       // [nent+1] gather items of each entry
+    const CItem *citems;
     // border rows: supernodes whose panel holds border row b, ascending
     const int32_t *bpath_ptr;      // [nbd+1]
     const int32_t *bpath_s;
     const int32_t *bpath_pos;
+    // border Schur items of each packed border entry
+    const int32_t *sitem_ptr;      // [nbd*(nbd+1)/2 + 1]
+    const SItem *sitems;
     // assembly
     const int32_t *bus_idx;        // [nb][BI_N]
     const int32_t *bus_slot;       // [nb][BS_N]
@@ -94,20 +109,11 @@ struct TemplDev {
 
 struct BlockDev {
     int32_t tmpl;
+    int32_t bl;                    // position in the template's block list
     int32_t outage;                // outaged branch or -1
-    int64_t col0;                  // first global column (layout and factor numbering agree per block)
-    int64_t kbase;                 // K values base
-    int64_t lbase;                 // panel storage base
-};
-
-struct BorderDev {
-    int32_t nbd;
-    int64_t kbase;                 // K values base of the border columns
-    const int32_t *kbb_pos;        // [nbd*nbd] position (relative to kbase) of (i, j), i >= j, or -1
-    const int32_t *pg_idx;         // [ng] border index of pg_g (or -1)
-    const double *gen_c2;          // [ng]
-    int32_t ng;
-    int32_t has_border;
+    int32_t pad;
+    int64_t col0;                  // first global column (layout order)
+    int64_t kcsc;                  // first K value of the block in the public CSC order
 };
 
 // ---------------------------------------------------------------- host symbolic
@@ -117,6 +123,7 @@ struct Template {
     int nprim = 0;
     bool pvpq_rows = false;
     bool pg_local = false;
+    std::vector<int32_t> blocks;   // global ids of the blocks using this template
     // model tables (layout-local; border refs n + b)
     std::vector<int32_t> bus_idx, bus_slot, bus_adj_ptr, bus_adj, br_slot, br_idx, gen_idx, gen_slot;
     // lower CSC pattern in layout-local numbering (rows may be n + b)
@@ -130,12 +137,29 @@ struct Template {
     std::vector<int32_t> lp, li;        // exact structure
     std::vector<int32_t> sup, srp, sri; // supernodes and panel rows
     // schedule
-    std::vector<int32_t> panel_off, lev_sup_ptr, lev_sup, lev_task_ptr, task_s, task_p, task_gptr,
-        task_aptr, lev_dtask_ptr, dtask, bpath_ptr, bpath_s, bpath_pos;
-    std::vector<GItem> gitems;
-    std::vector<uint8_t> crel;
-    std::vector<AEnt> aents;
     int nlev = 0;
+    std::vector<int32_t> level;         // [nsup]
+    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_iptr, bpath_ptr, bpath_s,
+        bpath_pos, sitem_ptr;
+    std::vector<std::vector<int32_t>> lev_tasks;   // row tasks of each level
+    std::vector<CItem> citems;
+    std::vector<SItem> sitems;
+};
+
+// Work lists of every launch (all templates together), per level.
+struct Schedule {
+    int nlev = 0;
+    // factor: A gathers every lower panel entry (k = entry); B factors the
+    // diagonal blocks of wide supernodes (two blocks per wavefront); C pivots
+    // and off-diagonal rows (k = row task)
+    std::vector<int32_t> a_ptr, b_ptr, c_ptr;           // [nlev+1]
+    std::vector<Work> a, b, c;
+    // solve: forward gathers of the diagonal rows, diagonal solves of wide supernodes
+    // (backward: gathers of every diagonal row, then the same diagonal solves)
+    std::vector<int32_t> f_ptr, d_ptr, g_ptr;           // [nlev+1]
+    std::vector<Work> f, d, g;
+    std::vector<Work> bpart;                            // border rows x block groups (forward partials)
+    std::vector<Work> schur;                            // border entries x block groups
 };
 
 struct Handle {
@@ -145,25 +169,27 @@ struct Handle {
     int nb = 0, nl = 0, ng = 0;
     uint32_t flags = 0;
     std::vector<int64_t> block_off;      // [nblk+1]
-    std::vector<int32_t> block_tmpl, block_outage;
+    std::vector<int32_t> block_tmpl, block_outage, block_bl;
     std::vector<Template> tmpl;
     std::vector<double> gen_c2, br_r, br_x;
     std::vector<int32_t> border_pg;      // [ng] border index of pg_g
-    // K pattern
-    std::vector<int64_t> kbase;          // [nblk] + border base at the end
+    // K pattern (public lower CSC in layout order)
+    std::vector<int64_t> kbase;          // [nblk+1]: first value of each block, then of the border
     int64_t nnzK = 0;
     std::vector<int64_t> bcolptr;        // border K_bb lower CSC (border-local)
     std::vector<int32_t> browind;
     std::vector<int32_t> kbb_pos;        // [nbd*nbd]
     std::vector<uint8_t> border_primal;
     // border symbolic (border-local numbering)
-    std::vector<int32_t> bparent;        // border parent (border-local) or -1
+    std::vector<int32_t> bparent;
     std::vector<int64_t> bcolcount;
-    std::vector<int32_t> blp, bli;       // exact structure
-    std::vector<int32_t> bsup;           // border supernodes
+    std::vector<int32_t> blp, bli;
+    std::vector<int32_t> bsup;
     // sizes
     int64_t nnzL = 0, nsuper = 0, npanel = 0;
-    std::vector<int64_t> lbase;          // [nblk+1]
+    int64_t kint = 0, lint = 0, dint = 0;   // interleaved K values, panels, pivots (all templates)
+    std::vector<int64_t> t_kbase, t_lbase, t_dbase;
+    Schedule sched;
     // numeric state
     int64_t nrhs_max = 0;
     void *ws = nullptr;
@@ -171,18 +197,20 @@ struct Handle {
     bool factored = false;
     bool blocks_done = false;
     bool bound = false;
-    // device pointers (inside the workspace)
     struct Dev {
-        double *kval = nullptr, *lpan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr,
-               *ybuf = nullptr, *cpart = nullptr, *xb = nullptr;
-        int64_t *stat = nullptr;         // per-block status words + border row
-        double *dmm = nullptr;           // per-block min/max |d|
+        double *kval = nullptr;          // interleaved K, then border K_bb (CSC)
+        double *lpan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
+               *cpart = nullptr, *dmm = nullptr;
+        int64_t *stat = nullptr;
         TemplDev *tmpl = nullptr;
         BlockDev *blk = nullptr;
+        Work *work = nullptr;            // all work lists
         int32_t *kbb_pos = nullptr, *border_pg = nullptr;
-        double *gen_c2 = nullptr, *br_g = nullptr, *br_b = nullptr;
+        double *gen_c2 = nullptr, *br_r = nullptr, *br_x = nullptr;
+        const uint8_t *bprim = nullptr;
     } d;
-    const uint8_t *bprim_dev = nullptr;  // border pivot signs (device)
+    // offsets of each work list inside d.work
+    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
 };
 
 // model.cpp
@@ -193,9 +221,8 @@ int build_pattern_model(int64_t N, int nblk, const int64_t *block_off, const int
 int analyze_template(Template &t, int nbd, int maxw, int znum, int zden);
 int analyze_border(Handle &h, int maxw, int znum, int zden);
 // schedule.cpp
-int build_schedule(Template &t, int nbd);
-// api helpers
-int64_t panel_entries(const Template &t);
+int build_template_schedule(Template &t, int nbd);
+int build_schedule(Handle &h);
 
 }  // namespace ncl
 
