@@ -76,6 +76,7 @@ enum {
     NCL_ERR_NONFINITE = -7   /* a pivot was NaN or infinite */
 };
 
+#define NCL_MAX_BORDER 600   /* largest first-stage border (dense factor in local memory) */
 #define NCL_PVPQ 1u          /* PV/PQ complementarity rows and the vm0 border (eq. (pvpq)) */
 
 /* Network topology and constants (host arrays, copied during analyze).
@@ -128,7 +129,9 @@ typedef struct {
  * column counts, the supernode partition and all schedules.  Host only;
  * no device memory is touched.  opts may be NULL (defaults).
  * Returns NCL_ERR_ARG for out-of-range indices, unsorted or duplicate
- * branches, too many or bridge outages. */
+ * branches, too many or bridge outages, and for a border of more than
+ * NCL_MAX_BORDER variables (the dense border factor works on one compute
+ * unit's local memory). */
 int ncl_kkt_analyze(const ncl_network *net, const ncl_analyze_opts *opts, ncl_kkt **out);
 
 /* Symbolic analysis of a user-given block-arrowhead pattern (no assembly;
@@ -136,7 +139,8 @@ int ncl_kkt_analyze(const ncl_network *net, const ncl_analyze_opts *opts, ncl_kk
  * triangle (row >= column, diagonal included, rows sorted) in the caller's
  * order, blocks [block_off[b], block_off[b+1]) for b < nblk, border
  * [block_off[nblk], N).  No entry may couple two different blocks.
- * is_primal[N] gives the expected pivot sign (1 positive, 0 negative). */
+ * is_primal[N] gives the expected pivot sign (1 positive, 0 negative).
+ * The border may hold at most NCL_MAX_BORDER columns. */
 int ncl_kkt_analyze_pattern(int64_t N, int32_t nblk, const int64_t *block_off, const int64_t *colptr,
                             const int32_t *rowind, const uint8_t *is_primal,
                             const ncl_analyze_opts *opts, ncl_kkt **out);

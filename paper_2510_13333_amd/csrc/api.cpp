@@ -17,13 +17,27 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-int finish_analyze(Handle &h, const ncl_analyze_opts *opts) {
-    int maxw = 16, znum = 1, zden = 4;
-    if (opts) {
-        if (opts->relax_maxw) maxw = opts->relax_maxw;
-        if (opts->relax_zden) { znum = opts->relax_znum; zden = opts->relax_zden; }
+int relax_params(const ncl_analyze_opts *o, int &maxw, int &znum, int &zden) {
+    maxw = 16;
+    znum = 1;
+    zden = 4;
+    if (o) {
+        if (o->relax_maxw) maxw = o->relax_maxw;
+        if (o->relax_zden) { znum = o->relax_znum; zden = o->relax_zden; }
         if (maxw < 1 || zden <= 0 || znum < 0) return NCL_ERR_ARG;
     }
+    return NCL_OK;
+}
+
+// opts: nullptr (defaults), one set for every instance (nopts == 1) or one per instance.
+int finish_analyze(Handle &h, const ncl_analyze_opts *opts, int nopts) {
+    const int ninst = int(h.inst.size());
+    auto opts_of = [&](int i) -> const ncl_analyze_opts * {
+        if (!opts) return nullptr;
+        return nopts == 1 ? opts : opts + i;
+    };
+    for (const auto &I : h.inst)
+        if (I.nbd > NCL_MAX_BORDER) return NCL_ERR_ARG;
     h.block_bl.assign(h.nblk, 0);
     for (auto &t : h.tmpl) t.blocks.clear();
     for (int b = 0; b < h.nblk; b++) {
@@ -32,14 +46,21 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts) {
         t.blocks.push_back(b);
     }
     for (auto &t : h.tmpl) {
-        int rc = ncl::analyze_template(t, h.nbd, maxw, znum, zden);
+        int maxw, znum, zden;
+        int rc = relax_params(opts_of(t.inst), maxw, znum, zden);
         if (rc) return rc;
-        rc = ncl::build_template_schedule(t, h.nbd);
+        rc = ncl::analyze_template(t, h.inst[t.inst].nbd, maxw, znum, zden);
+        if (rc) return rc;
+        rc = ncl::build_template_schedule(t, h.inst[t.inst].nbd);
         if (rc) return rc;
     }
-    int rc = ncl::analyze_border(h, maxw, znum, zden);
-    if (rc) return rc;
-    rc = ncl::build_schedule(h);
+    for (int i = 0; i < ninst; i++) {
+        int maxw, znum, zden;
+        int rc = relax_params(opts_of(i), maxw, znum, zden);
+        if (!rc) rc = ncl::analyze_border(h, h.inst[i], maxw, znum, zden);
+        if (rc) return rc;
+    }
+    int rc = ncl::build_schedule(h);
     if (rc) return rc;
     h.nnzL = 0;
     h.nsuper = 0;
@@ -50,16 +71,33 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts) {
         h.nsuper += int64_t(t.sup.size()) - 1;
         h.npanel += int64_t(t.sri.size());
     }
-    if (h.nbd) {
-        h.nnzL += h.blp[h.nbd];
-        h.nsuper += int64_t(h.bsup.size()) - 1;
-        std::vector<int32_t> mk(h.nbd, -1);
-        for (size_t s = 0; s + 1 < h.bsup.size(); s++) {
-            int f = h.bsup[s], l = h.bsup[s + 1] - 1;
+    h.nbd_tot = h.nbb_tot = h.npk_tot = h.sp_tot = h.cp_tot = h.gp_tot = 0;
+    h.max_nbd = 0;
+    for (auto &I : h.inst) {
+        I.kbb0 = h.nbb_tot;
+        I.sbb0 = h.npk_tot;
+        I.bd0 = h.nbd_tot;
+        I.sp0 = h.sp_tot;
+        I.cp0 = h.cp_tot;
+        I.npk0 = h.npk_tot;
+        I.gp0 = h.gp_tot;
+        h.nbb_tot += I.nbb();
+        h.npk_tot += I.npk();
+        h.nbd_tot += I.nbd;
+        h.sp_tot += I.npk() * I.nblk;
+        h.cp_tot += int64_t(I.nbd) * I.nblk;
+        if (I.nbd) h.gp_tot += I.ng;
+        h.max_nbd = std::max(h.max_nbd, I.nbd);
+        if (!I.nbd) continue;
+        h.nnzL += I.blp[I.nbd];
+        h.nsuper += int64_t(I.bsup.size()) - 1;
+        std::vector<int32_t> mk(I.nbd, -1);
+        for (size_t s = 0; s + 1 < I.bsup.size(); s++) {
+            int f = I.bsup[s], l = I.bsup[s + 1] - 1;
             h.npanel += l - f + 1;
             for (int j = f; j <= l; j++)
-                for (int p = h.blp[j]; p < h.blp[j + 1]; p++)
-                    if (h.bli[p] > l && mk[h.bli[p]] != int(s)) { mk[h.bli[p]] = int(s); h.npanel++; }
+                for (int p = I.blp[j]; p < I.blp[j + 1]; p++)
+                    if (I.bli[p] > l && mk[I.bli[p]] != int(s)) { mk[I.bli[p]] = int(s); h.npanel++; }
         }
     }
     return NCL_OK;
@@ -86,7 +124,8 @@ struct WsLayout {
 
 struct Plan {
     std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
-    size_t tdev = 0, bdev = 0, work = 0, kbb = 0, bpg = 0, c2 = 0, brr = 0, brx = 0, bprim = 0, tables_end = 0;
+    std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
+    size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, tables_end = 0;
     size_t kval = 0, lpan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, stat = 0, total = 0;
 };
 
@@ -132,13 +171,12 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(t.task_cbase));
         o.push_back(L.vec(t.ent_kpos));
         o.push_back(L.vec(t.ent_out));
-        o.push_back(L.vec(t.ent_iptr));
-        o.push_back(L.vec(t.citems));
-        o.push_back(L.vec(t.bpath_ptr));
-        o.push_back(L.vec(t.bpath_s));
-        o.push_back(L.vec(t.bpath_pos));
-        o.push_back(L.vec(t.sitem_ptr));
-        o.push_back(L.vec(t.sitems));
+        o.push_back(L.vec(t.ent_tptr));
+        o.push_back(L.vec(t.terms));
+        o.push_back(L.vec(t.bterm_ptr));
+        o.push_back(L.vec(t.bterms));
+        o.push_back(L.vec(t.sterm_ptr));
+        o.push_back(L.vec(t.sterms));
         o.push_back(L.vec(t.bus_idx));
         o.push_back(L.vec(t.bus_slot));
         o.push_back(L.vec(t.bus_adj_ptr));
@@ -152,24 +190,25 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     }
     p.tdev = L.take(nullptr, sizeof(ncl::TemplDev) * h.tmpl.size());
     p.bdev = L.take(nullptr, sizeof(ncl::BlockDev) * size_t(h.nblk));
+    p.idev = L.take(nullptr, sizeof(ncl::InstDev) * h.inst.size());
     p.work = L.vec(all_work(h));
-    p.kbb = L.vec(h.kbb_pos);
-    p.bpg = L.vec(h.border_pg);
-    p.c2 = L.vec(h.gen_c2);
-    p.brr = L.vec(h.br_r);
-    p.brx = L.vec(h.br_x);
-    p.bprim = L.vec(h.border_primal);
+    p.ioff.resize(h.inst.size());
+    std::vector<uint8_t> bprim;
+    for (size_t i = 0; i < h.inst.size(); i++) {
+        const ncl::Inst &I = h.inst[i];
+        p.ioff[i] = {L.vec(I.kbb_pos), L.vec(I.border_pg), L.vec(I.gen_c2), L.vec(I.br_r), L.vec(I.br_x)};
+        bprim.insert(bprim.end(), I.border_primal.begin(), I.border_primal.end());
+    }
+    p.bprim = L.vec(bprim);
     p.tables_end = L.off;
     L.stage = nullptr;
-    const int64_t npk = int64_t(h.nbd) * (h.nbd + 1) / 2;
-    const int64_t nbb = h.nbd ? h.bcolptr[h.nbd] : 0;
-    p.kval = L.take(nullptr, sizeof(double) * size_t(h.kint + nbb));
+    p.kval = L.take(nullptr, sizeof(double) * size_t(h.kint + h.nbb_tot));
     p.lpan = L.take(nullptr, sizeof(double) * size_t(h.lint));
-    p.dval = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd));
-    p.spart = L.take(nullptr, sizeof(double) * size_t(npk) * size_t(h.nblk));
-    p.sbb = L.take(nullptr, sizeof(double) * size_t(npk));
-    p.ybuf = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd) * size_t(nrhs));
-    p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.nblk) * size_t(h.nbd));
+    p.dval = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
+    p.spart = L.take(nullptr, sizeof(double) * size_t(h.sp_tot));
+    p.sbb = L.take(nullptr, sizeof(double) * size_t(h.npk_tot));
+    p.ybuf = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot) * size_t(nrhs));
+    p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.cp_tot));
     p.stat = L.take(nullptr, sizeof(int64_t) * 8);
     p.total = L.off;
     return p;
@@ -179,15 +218,19 @@ ncl::DevArgs dev_args(const Handle &h) {
     ncl::DevArgs a{};
     a.tmpls = h.d.tmpl;
     a.blks = h.d.blk;
+    a.insts = h.d.inst;
     a.ntmpl = int(h.tmpl.size());
     a.nblk = h.nblk;
-    a.nbd = h.nbd;
-    a.nb = h.nb;
-    a.ng = h.ng;
+    a.ninst = int(h.inst.size());
+    a.max_nbd = h.max_nbd;
     a.N = h.N;
-    a.bstart = h.block_off[h.nblk];
     a.kint = h.kint;
     a.dint = h.dint;
+    a.nbd_tot = h.nbd_tot;
+    a.nbb_tot = h.nbb_tot;
+    a.npk_tot = h.npk_tot;
+    a.asm_threads = h.asm_threads;
+    a.gp_tot = h.gp_tot;
     a.kval = h.d.kval;
     a.lpan = h.d.lpan;
     a.dval = h.d.dval;
@@ -196,11 +239,6 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.ybuf = h.d.ybuf;
     a.cpart = h.d.cpart;
     a.stat = h.d.stat;
-    a.kbb_pos = h.d.kbb_pos;
-    a.border_pg = h.d.border_pg;
-    a.gen_c2 = h.d.gen_c2;
-    a.br_r = h.d.br_r;
-    a.br_x = h.d.br_x;
     a.bprim = h.d.bprim;
     return a;
 }
@@ -233,7 +271,7 @@ int ncl_kkt_analyze(const ncl_network *net, const ncl_analyze_opts *opts, ncl_kk
     try {
         std::string err;
         int rc = ncl::build_network_model(net, k->h, err);
-        if (!rc) rc = finish_analyze(k->h, opts);
+        if (!rc) rc = finish_analyze(k->h, opts, opts ? 1 : 0);
         if (rc) { delete k; return rc; }
     } catch (const std::bad_alloc &) {
         delete k;
@@ -253,13 +291,53 @@ int ncl_kkt_analyze_pattern(int64_t N, int32_t nblk, const int64_t *block_off, c
     try {
         std::string err;
         int rc = ncl::build_pattern_model(N, nblk, block_off, colptr, rowind, is_primal, k->h, err);
-        if (!rc) rc = finish_analyze(k->h, opts);
+        if (!rc) rc = finish_analyze(k->h, opts, opts ? 1 : 0);
         if (rc) { delete k; return rc; }
     } catch (const std::bad_alloc &) {
         delete k;
         return NCL_ERR_ALLOC;
     }
     *out = k;
+    return NCL_OK;
+}
+
+int ncl_kkt_analyze_batch(const ncl_network *nets, int32_t count, const ncl_analyze_opts *opts, int32_t nopts,
+                          ncl_kkt **out) {
+    if (!out || !nets || count < 1 || (opts && nopts != 1 && nopts != count) || (!opts && nopts != 0))
+        return NCL_ERR_ARG;
+    *out = nullptr;
+    ncl_kkt *k = new (std::nothrow) ncl_kkt;
+    if (!k) return NCL_ERR_ALLOC;
+    try {
+        std::string err;
+        int rc = NCL_OK;
+        for (int i = 0; i < count && !rc; i++) rc = ncl::build_network_model(nets + i, k->h, err);
+        if (!rc && k->h.tmpl.size() > 32767) rc = NCL_ERR_ARG;
+        if (!rc) rc = finish_analyze(k->h, opts, nopts);
+        if (rc) { delete k; return rc; }
+    } catch (const std::bad_alloc &) {
+        delete k;
+        return NCL_ERR_ALLOC;
+    }
+    *out = k;
+    return NCL_OK;
+}
+
+int ncl_kkt_instances(const ncl_kkt *k, int32_t *count) {
+    if (!k || !count) return NCL_ERR_ARG;
+    *count = int32_t(k->h.inst.size());
+    return NCL_OK;
+}
+
+int ncl_kkt_instance(const ncl_kkt *k, int32_t i, int64_t *col0, int64_t *n, int64_t *nprimal, int32_t *nblk,
+                     int32_t *nbd) {
+    if (!k || i < 0 || i >= int32_t(k->h.inst.size())) return NCL_ERR_ARG;
+    const ncl::Inst &I = k->h.inst[i];
+    if (col0) *col0 = I.col0;
+    if (n) *n = I.N;
+    if (nprimal) *nprimal = I.nprimal;
+    if (nblk) *nblk = I.nblk;
+    if (nbd) *nbd = I.nbd;
     return NCL_OK;
 }
 
@@ -282,68 +360,70 @@ int ncl_kkt_symbolic(const ncl_kkt *k, int32_t *perm, int32_t *etree, int64_t *c
                      int64_t *lcolptr, int32_t *lrowind, int64_t *srowptr, int32_t *srowind) {
     if (!k) return NCL_ERR_ARG;
     const Handle &h = k->h;
-    const int64_t bstart = h.block_off[h.nblk];
     int64_t lq = 0, sq = 0, pq = 0;
     if (lcolptr) lcolptr[0] = 0;
     if (srowptr) srowptr[0] = 0;
-    for (int b = 0; b < h.nblk; b++) {
-        const Template &t = h.tmpl[h.block_tmpl[b]];
-        const int64_t o = h.block_off[b];
-        auto gmap = [&](int32_t i) -> int32_t { return int32_t(i < t.n ? o + i : bstart + (i - t.n)); };
-        for (int j = 0; j < t.n; j++) {
-            if (perm) perm[o + j] = int32_t(o + t.perm[j]);
-            if (colcount) colcount[o + j] = t.colcount[j];
-            if (etree) {
-                int32_t par = -1;
-                if (t.parent[j] >= 0) par = int32_t(o + t.parent[j]);
-                else if (t.lp[j + 1] > t.lp[j]) par = gmap(t.li[t.lp[j]]);
-                etree[o + j] = par;
+    for (const ncl::Inst &I : h.inst) {
+        const int64_t bstart = I.bstart;
+        for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
+            const Template &t = h.tmpl[h.block_tmpl[b]];
+            const int64_t o = h.block_col0[b];
+            auto gmap = [&](int32_t i) -> int32_t { return int32_t(i < t.n ? o + i : bstart + (i - t.n)); };
+            for (int j = 0; j < t.n; j++) {
+                if (perm) perm[o + j] = int32_t(o + t.perm[j]);
+                if (colcount) colcount[o + j] = t.colcount[j];
+                if (etree) {
+                    int32_t par = -1;
+                    if (t.parent[j] >= 0) par = int32_t(o + t.parent[j]);
+                    else if (t.lp[j + 1] > t.lp[j]) par = gmap(t.li[t.lp[j]]);
+                    etree[o + j] = par;
+                }
+                for (int p = t.lp[j]; p < t.lp[j + 1]; p++) {
+                    if (lrowind) lrowind[lq] = gmap(t.li[p]);
+                    lq++;
+                }
+                if (lcolptr) lcolptr[o + j + 1] = lq;
             }
-            for (int p = t.lp[j]; p < t.lp[j + 1]; p++) {
-                if (lrowind) lrowind[lq] = gmap(t.li[p]);
+            const int ns = int(t.sup.size()) - 1;
+            for (int s = 0; s < ns; s++) {
+                if (super_ptr) super_ptr[sq] = o + t.sup[s];
+                for (int p = t.srp[s]; p < t.srp[s + 1]; p++) {
+                    if (srowind) srowind[pq] = gmap(t.sri[p]);
+                    pq++;
+                }
+                sq++;
+                if (srowptr) srowptr[sq] = pq;
+            }
+        }
+        std::vector<int32_t> mk(I.nbd, -1), buf;
+        for (int j = 0; j < I.nbd; j++) {
+            const int64_t g = bstart + j;
+            if (perm) perm[g] = int32_t(g);
+            if (colcount) colcount[g] = I.bcolcount[j];
+            if (etree) etree[g] = I.bparent[j] >= 0 ? int32_t(bstart + I.bparent[j]) : -1;
+            for (int p = I.blp[j]; p < I.blp[j + 1]; p++) {
+                if (lrowind) lrowind[lq] = int32_t(bstart + I.bli[p]);
                 lq++;
             }
-            if (lcolptr) lcolptr[o + j + 1] = lq;
+            if (lcolptr) lcolptr[g + 1] = lq;
         }
-        const int ns = int(t.sup.size()) - 1;
-        for (int s = 0; s < ns; s++) {
-            if (super_ptr) super_ptr[sq] = o + t.sup[s];
-            for (int p = t.srp[s]; p < t.srp[s + 1]; p++) {
-                if (srowind) srowind[pq] = gmap(t.sri[p]);
+        for (size_t s = 0; s + 1 < I.bsup.size(); s++) {
+            const int f = I.bsup[s], l = I.bsup[s + 1] - 1;
+            if (super_ptr) super_ptr[sq] = bstart + f;
+            buf.clear();
+            for (int j = f; j <= l; j++) buf.push_back(j);
+            size_t c0 = buf.size();
+            for (int j = f; j <= l; j++)
+                for (int p = I.blp[j]; p < I.blp[j + 1]; p++)
+                    if (I.bli[p] > l && mk[I.bli[p]] != int(s)) { mk[I.bli[p]] = int(s); buf.push_back(I.bli[p]); }
+            std::sort(buf.begin() + c0, buf.end());
+            for (int32_t r : buf) {
+                if (srowind) srowind[pq] = int32_t(bstart + r);
                 pq++;
             }
             sq++;
             if (srowptr) srowptr[sq] = pq;
         }
-    }
-    std::vector<int32_t> mk(h.nbd, -1), buf;
-    for (int j = 0; j < h.nbd; j++) {
-        const int64_t g = bstart + j;
-        if (perm) perm[g] = int32_t(g);
-        if (colcount) colcount[g] = h.bcolcount[j];
-        if (etree) etree[g] = h.bparent[j] >= 0 ? int32_t(bstart + h.bparent[j]) : -1;
-        for (int p = h.blp[j]; p < h.blp[j + 1]; p++) {
-            if (lrowind) lrowind[lq] = int32_t(bstart + h.bli[p]);
-            lq++;
-        }
-        if (lcolptr) lcolptr[g + 1] = lq;
-    }
-    for (size_t s = 0; s + 1 < h.bsup.size(); s++) {
-        const int f = h.bsup[s], l = h.bsup[s + 1] - 1;
-        if (super_ptr) super_ptr[sq] = bstart + f;
-        buf.clear();
-        for (int j = f; j <= l; j++) buf.push_back(j);
-        size_t c0 = buf.size();
-        for (int j = f; j <= l; j++)
-            for (int p = h.blp[j]; p < h.blp[j + 1]; p++)
-                if (h.bli[p] > l && mk[h.bli[p]] != int(s)) { mk[h.bli[p]] = int(s); buf.push_back(h.bli[p]); }
-        std::sort(buf.begin() + c0, buf.end());
-        for (int32_t r : buf) {
-            if (srowind) srowind[pq] = int32_t(bstart + r);
-            pq++;
-        }
-        sq++;
-        if (srowptr) srowptr[sq] = pq;
     }
     if (super_ptr) super_ptr[sq] = h.N;
     return NCL_OK;
@@ -352,23 +432,25 @@ int ncl_kkt_symbolic(const ncl_kkt *k, int32_t *perm, int32_t *etree, int64_t *c
 int ncl_kkt_pattern(const ncl_kkt *k, int64_t *colptr, int32_t *rowind) {
     if (!k || !colptr || !rowind) return NCL_ERR_ARG;
     const Handle &h = k->h;
-    const int64_t bstart = h.block_off[h.nblk];
     colptr[0] = 0;
-    for (int b = 0; b < h.nblk; b++) {
-        const Template &t = h.tmpl[h.block_tmpl[b]];
-        const int64_t o = h.block_off[b];
-        for (int c = 0; c < t.n; c++) {
-            colptr[o + c + 1] = h.kbase[b] + t.colptr[c + 1];
-            for (int64_t p = t.colptr[c]; p < t.colptr[c + 1]; p++) {
-                int32_t r = t.rowind[p];
-                rowind[h.kbase[b] + p] = int32_t(r < t.n ? o + r : bstart + (r - t.n));
+    for (const ncl::Inst &I : h.inst) {
+        const int64_t bstart = I.bstart;
+        for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
+            const Template &t = h.tmpl[h.block_tmpl[b]];
+            const int64_t o = h.block_col0[b];
+            for (int c = 0; c < t.n; c++) {
+                colptr[o + c + 1] = h.kbase[b] + t.colptr[c + 1];
+                for (int64_t p = t.colptr[c]; p < t.colptr[c + 1]; p++) {
+                    int32_t r = t.rowind[p];
+                    rowind[h.kbase[b] + p] = int32_t(r < t.n ? o + r : bstart + (r - t.n));
+                }
             }
         }
-    }
-    for (int c = 0; c < h.nbd; c++) {
-        colptr[bstart + c + 1] = h.kbase[h.nblk] + h.bcolptr[c + 1];
-        for (int64_t p = h.bcolptr[c]; p < h.bcolptr[c + 1]; p++)
-            rowind[h.kbase[h.nblk] + p] = int32_t(bstart + h.browind[p]);
+        for (int c = 0; c < I.nbd; c++) {
+            colptr[bstart + c + 1] = I.kcsc_border + I.bcolptr[c + 1];
+            for (int64_t p = I.bcolptr[c]; p < I.bcolptr[c + 1]; p++)
+                rowind[I.kcsc_border + p] = int32_t(bstart + I.browind[p]);
+        }
     }
     return NCL_OK;
 }
@@ -397,7 +479,16 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.n = t.n;
         d.nsup = int32_t(t.sup.size()) - 1;
         d.nblk = int32_t(t.blocks.size());
-        d.nbd = h.nbd;
+        const ncl::Inst &I = h.inst[t.inst];
+        d.nbd = I.nbd;
+        d.inst = t.inst;
+        d.nbus = I.nb;
+        d.ngen = I.ng;
+        d.abase = h.t_abase[ti];
+        d.bd0 = I.bd0;
+        d.br_r = reinterpret_cast<const double *>(base + p.ioff[t.inst][3]);
+        d.br_x = reinterpret_cast<const double *>(base + p.ioff[t.inst][4]);
+        d.gen_c2 = reinterpret_cast<const double *>(base + p.ioff[t.inst][2]);
         d.kbase = h.t_kbase[ti];
         d.lbase = h.t_lbase[ti];
         d.dbase = h.t_dbase[ti];
@@ -414,23 +505,22 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.task_cbase = reinterpret_cast<const int32_t *>(at(7));
         d.ent_kpos = reinterpret_cast<const int32_t *>(at(8));
         d.ent_out = reinterpret_cast<const int32_t *>(at(9));
-        d.ent_iptr = reinterpret_cast<const int32_t *>(at(10));
-        d.citems = reinterpret_cast<const ncl::CItem *>(at(11));
-        d.bpath_ptr = reinterpret_cast<const int32_t *>(at(12));
-        d.bpath_s = reinterpret_cast<const int32_t *>(at(13));
-        d.bpath_pos = reinterpret_cast<const int32_t *>(at(14));
-        d.sitem_ptr = reinterpret_cast<const int32_t *>(at(15));
-        d.sitems = reinterpret_cast<const ncl::SItem *>(at(16));
-        d.bus_idx = reinterpret_cast<const int32_t *>(at(17));
-        d.bus_slot = reinterpret_cast<const int32_t *>(at(18));
-        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(19));
-        d.bus_adj = reinterpret_cast<const int32_t *>(at(20));
-        d.br_slot = reinterpret_cast<const int32_t *>(at(21));
-        d.br_idx = reinterpret_cast<const int32_t *>(at(22));
-        d.gen_idx = reinterpret_cast<const int32_t *>(at(23));
-        d.gen_slot = reinterpret_cast<const int32_t *>(at(24));
-        d.perm = reinterpret_cast<const int32_t *>(at(25));
-        d.col_primal = reinterpret_cast<const uint8_t *>(at(26));
+        d.ent_tptr = reinterpret_cast<const int32_t *>(at(10));
+        d.terms = reinterpret_cast<const ncl::Term *>(at(11));
+        d.bterm_ptr = reinterpret_cast<const int32_t *>(at(12));
+        d.bterms = reinterpret_cast<const ncl::Term *>(at(13));
+        d.sterm_ptr = reinterpret_cast<const int32_t *>(at(14));
+        d.sterms = reinterpret_cast<const ncl::Term *>(at(15));
+        d.bus_idx = reinterpret_cast<const int32_t *>(at(16));
+        d.bus_slot = reinterpret_cast<const int32_t *>(at(17));
+        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(18));
+        d.bus_adj = reinterpret_cast<const int32_t *>(at(19));
+        d.br_slot = reinterpret_cast<const int32_t *>(at(20));
+        d.br_idx = reinterpret_cast<const int32_t *>(at(21));
+        d.gen_idx = reinterpret_cast<const int32_t *>(at(22));
+        d.gen_slot = reinterpret_cast<const int32_t *>(at(23));
+        d.perm = reinterpret_cast<const int32_t *>(at(24));
+        d.col_primal = reinterpret_cast<const uint8_t *>(at(25));
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
     std::vector<ncl::BlockDev> bdev(h.nblk);
@@ -438,10 +528,33 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         bdev[b].tmpl = h.block_tmpl[b];
         bdev[b].bl = h.block_bl[b];
         bdev[b].outage = h.block_outage[b];
-        bdev[b].col0 = h.block_off[b];
+        bdev[b].col0 = h.block_col0[b];
         bdev[b].kcsc = h.kbase[b];
     }
     std::memcpy(buf.data() + p.bdev, bdev.data(), sizeof(ncl::BlockDev) * bdev.size());
+    std::vector<ncl::InstDev> idev(h.inst.size());
+    for (size_t i = 0; i < h.inst.size(); i++) {
+        const ncl::Inst &I = h.inst[i];
+        ncl::InstDev &d = idev[i];
+        d.nbd = I.nbd;
+        d.nblk = I.nblk;
+        d.blk0 = I.blk0;
+        d.ng = I.ng;
+        d.bstart = I.bstart;
+        d.kbb0 = I.kbb0;
+        d.sbb0 = I.sbb0;
+        d.bd0 = I.bd0;
+        d.sp0 = I.sp0;
+        d.cp0 = I.cp0;
+        d.npk0 = I.npk0;
+        d.gp0 = I.gp0;
+        d.kcsc_border = I.kcsc_border;
+        d.nbb = I.nbb();
+        d.kbb_pos = reinterpret_cast<const int32_t *>(base + p.ioff[i][0]);
+        d.border_pg = reinterpret_cast<const int32_t *>(base + p.ioff[i][1]);
+        d.gen_c2 = reinterpret_cast<const double *>(base + p.ioff[i][2]);
+    }
+    std::memcpy(buf.data() + p.idev, idev.data(), sizeof(ncl::InstDev) * idev.size());
     if (hipMemcpyAsync(base, buf.data(), buf.size(), hipMemcpyHostToDevice, st) != hipSuccess) return NCL_ERR_HIP;
     if (hipStreamSynchronize(st) != hipSuccess) return NCL_ERR_HIP;
     h.ws = dptr;
@@ -449,12 +562,8 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.nrhs_max = nrhs_max;
     h.d.tmpl = reinterpret_cast<ncl::TemplDev *>(base + p.tdev);
     h.d.blk = reinterpret_cast<ncl::BlockDev *>(base + p.bdev);
+    h.d.inst = reinterpret_cast<ncl::InstDev *>(base + p.idev);
     h.d.work = reinterpret_cast<ncl::Work *>(base + p.work);
-    h.d.kbb_pos = reinterpret_cast<int32_t *>(base + p.kbb);
-    h.d.border_pg = reinterpret_cast<int32_t *>(base + p.bpg);
-    h.d.gen_c2 = reinterpret_cast<double *>(base + p.c2);
-    h.d.br_r = reinterpret_cast<double *>(base + p.brr);
-    h.d.br_x = reinterpret_cast<double *>(base + p.brx);
     h.d.bprim = reinterpret_cast<const uint8_t *>(base + p.bprim);
     h.d.kval = reinterpret_cast<double *>(base + p.kval);
     h.d.lpan = reinterpret_cast<double *>(base + p.lpan);
@@ -481,18 +590,14 @@ int ncl_kkt_set_values(ncl_kkt *k, const double *dvals, void *stream) {
     if (!k || !dvals) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
-    const int64_t nbb = h.nbd ? h.bcolptr[h.nbd] : 0;
-    return hip_rc(ncl::launch_values(dev_args(h), dvals, h.d.kval, true, nbb, h.kbase[h.nblk],
-                                     reinterpret_cast<hipStream_t>(stream)));
+    return hip_rc(ncl::launch_values(dev_args(h), dvals, h.d.kval, true, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
     if (!k || !dvals) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
-    const int64_t nbb = h.nbd ? h.bcolptr[h.nbd] : 0;
-    return hip_rc(ncl::launch_values(dev_args(h), h.d.kval, dvals, false, nbb, h.kbase[h.nblk],
-                                     reinterpret_cast<hipStream_t>(stream)));
+    return hip_rc(ncl::launch_values(dev_args(h), h.d.kval, dvals, false, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
@@ -510,7 +615,7 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
                                                 W + h.w_c + S.c_ptr[l], S.c_ptr[l + 1] - S.c_ptr[l], st);
         if (e != hipSuccess) return NCL_ERR_HIP;
     }
-    if (h.nbd && ncl::launch_schur(a, W + h.w_schur, int(S.schur.size()), st) != hipSuccess) return NCL_ERR_HIP;
+    if (h.nbd_tot && ncl::launch_schur(a, W + h.w_schur, int(S.schur.size()), st) != hipSuccess) return NCL_ERR_HIP;
     h.blocks_done = true;
     return NCL_OK;
 }
@@ -560,46 +665,46 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
     Handle &h = k->h;
     if (!h.factored) return NCL_ERR_STATE;
     if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return NCL_ERR_HIP;
-    std::vector<double> pan(size_t(h.lint)), dv(size_t(h.dint + h.nbd));
-    const int64_t npk = int64_t(h.nbd) * (h.nbd + 1) / 2;
-    std::vector<double> sbb(static_cast<size_t>(npk));
+    std::vector<double> pan(size_t(h.lint)), dv(size_t(h.dint + h.nbd_tot));
+    std::vector<double> sbb(static_cast<size_t>(h.npk_tot));
     if (!pan.empty() && hipMemcpy(pan.data(), h.d.lpan, sizeof(double) * pan.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
     if (!dv.empty() && hipMemcpy(dv.data(), h.d.dval, sizeof(double) * dv.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
-    if (npk && hipMemcpy(sbb.data(), h.d.sbb, sizeof(double) * sbb.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    if (!sbb.empty() && hipMemcpy(sbb.data(), h.d.sbb, sizeof(double) * sbb.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
-    const int64_t bstart = h.block_off[h.nblk];
     int64_t q = 0;
-    for (int b = 0; b < h.nblk; b++) {
-        const int ti = h.block_tmpl[b];
-        const Template &t = h.tmpl[ti];
-        const int64_t nb = int64_t(t.blocks.size()), bl = h.block_bl[b];
-        const double *P = pan.data() + h.t_lbase[ti] + bl;
-        if (dd)
-            for (int j = 0; j < t.n; j++) dd[h.block_off[b] + j] = dv[size_t(h.t_dbase[ti] + int64_t(j) * nb + bl)];
-        if (!lx) continue;
-        const int ns = int(t.sup.size()) - 1;
-        for (int s = 0; s < ns; s++) {
-            const int f = t.sup[s], w = t.sup[s + 1] - f, r = t.srp[s + 1] - t.srp[s];
-            const int32_t *R = &t.sri[t.srp[s]];
-            for (int c = 0; c < w; c++) {
-                const int j = f + c;
-                for (int p = t.lp[j]; p < t.lp[j + 1]; p++) {
-                    const int pos = int(std::lower_bound(R, R + r, t.li[p]) - R);
-                    lx[q++] = P[(int64_t(t.panel_off[s]) + int64_t(c) * r + pos) * nb];
+    for (const ncl::Inst &I : h.inst) {
+        for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
+            const int ti = h.block_tmpl[b];
+            const Template &t = h.tmpl[ti];
+            const int64_t nb = int64_t(t.blocks.size()), bl = h.block_bl[b];
+            const double *P = pan.data() + h.t_lbase[ti] + bl;
+            if (dd)
+                for (int j = 0; j < t.n; j++) dd[h.block_col0[b] + j] = dv[size_t(h.t_dbase[ti] + int64_t(j) * nb + bl)];
+            if (!lx) continue;
+            const int ns = int(t.sup.size()) - 1;
+            for (int s = 0; s < ns; s++) {
+                const int f = t.sup[s], w = t.sup[s + 1] - f, r = t.srp[s + 1] - t.srp[s];
+                const int32_t *R = &t.sri[t.srp[s]];
+                for (int c = 0; c < w; c++) {
+                    const int j = f + c;
+                    for (int p = t.lp[j]; p < t.lp[j + 1]; p++) {
+                        const int pos = int(std::lower_bound(R, R + r, t.li[p]) - R);
+                        lx[q++] = P[(int64_t(t.panel_off[s]) + int64_t(c) * r + pos) * nb];
+                    }
                 }
             }
         }
+        if (dd)
+            for (int j = 0; j < I.nbd; j++) dd[I.bstart + j] = dv[size_t(h.dint + I.bd0 + j)];
+        if (lx)
+            for (int j = 0; j < I.nbd; j++)
+                for (int p = I.blp[j]; p < I.blp[j + 1]; p++) {
+                    const int i = I.bli[p];
+                    lx[q++] = sbb[size_t(I.sbb0) + size_t(i) * (i + 1) / 2 + j];
+                }
     }
-    if (dd)
-        for (int j = 0; j < h.nbd; j++) dd[bstart + j] = dv[size_t(h.dint + j)];
-    if (lx)
-        for (int j = 0; j < h.nbd; j++)
-            for (int p = h.blp[j]; p < h.blp[j + 1]; p++) {
-                const int i = h.bli[p];
-                lx[q++] = sbb[size_t(i) * (i + 1) / 2 + j];
-            }
     return NCL_OK;
 }
 
@@ -615,14 +720,14 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const double *b = db + int64_t(rhs) * ld;
         double *x = dx + int64_t(rhs) * ld;
-        double *y = h.d.ybuf + int64_t(rhs) * (h.dint + h.nbd);
-        double *cp = h.d.cpart + int64_t(rhs) * h.nblk * h.nbd;
+        double *y = h.d.ybuf + int64_t(rhs) * (h.dint + h.nbd_tot);
+        double *cp = h.d.cpart + int64_t(rhs) * h.cp_tot;
         if (ncl::launch_solve_load(a, b, y, st) != hipSuccess) return NCL_ERR_HIP;
         for (int l = 0; l < S.nlev; l++)
             if (ncl::launch_solve_fwd_level(a, y, W + h.w_f + S.f_ptr[l], S.f_ptr[l + 1] - S.f_ptr[l],
                                             W + h.w_d + S.d_ptr[l], S.d_ptr[l + 1] - S.d_ptr[l], st) != hipSuccess)
                 return NCL_ERR_HIP;
-        if (h.nbd) {
+        if (h.nbd_tot) {
             if (ncl::launch_solve_bpart(a, y, cp, W + h.w_bpart, int(S.bpart.size()), st) != hipSuccess) return NCL_ERR_HIP;
             if (ncl::launch_solve_border(a, b, x, y, cp, st) != hipSuccess) return NCL_ERR_HIP;
         }

@@ -11,26 +11,25 @@ namespace ncl {
 struct DevArgs {
     const TemplDev *tmpls;
     const BlockDev *blks;
-    int ntmpl, nblk, nbd;
-    int nb, ng;                 // network sizes (assembly)
-    int64_t N, bstart;          // global size and first border column (layout order)
-    int64_t kint;               // interleaved K values; the border K_bb values follow
-    int64_t dint;               // interleaved pivots; the border pivots follow
+    const InstDev *insts;
+    int ntmpl, nblk, ninst, max_nbd;
+    int64_t N;
+    int64_t kint;               // interleaved K values; the border K_bb values of every instance follow
+    int64_t dint;               // interleaved pivots; the border pivots of every instance follow
+    int64_t nbd_tot, nbb_tot, npk_tot;
+    int64_t asm_threads, gp_tot;   // assembly threads of the templates, then of the border pg values
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
     int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits
-    const int32_t *kbb_pos;     // [nbd*nbd]
-    const int32_t *border_pg;
-    const double *gen_c2, *br_r, *br_x;
-    const uint8_t *bprim;
+    const uint8_t *bprim;       // [nbd_tot] expected sign of the border pivots
 };
 
 hipError_t launch_assemble(const DevArgs &a, const double *z, const double *sig, double rho, hipStream_t st);
-hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, int64_t nnz_border,
-                         int64_t kcsc_border, hipStream_t st);
+hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, hipStream_t st);
 hipError_t launch_factor_level(const DevArgs &a, const Work *wa, int na, const Work *wb, int nb, const Work *wc,
                                int nc, hipStream_t st);
 hipError_t launch_schur(const DevArgs &a, const Work *ws, int nw, hipStream_t st);
 hipError_t launch_factor_border(const DevArgs &a, hipStream_t st);
+size_t border_lds_bytes(int nbd);   // dynamic LDS of the dense border factor (largest border)
 hipError_t launch_solve_load(const DevArgs &a, const double *b, double *y, hipStream_t st);
 hipError_t launch_solve_fwd_level(const DevArgs &a, double *y, const Work *wf, int nf, const Work *wd, int nd,
                                   hipStream_t st);

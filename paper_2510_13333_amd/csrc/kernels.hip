@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -27,38 +28,78 @@ namespace ncl {
 constexpr int kWG = 256;                 // threads per workgroup of the list kernels (4 wavefronts)
 constexpr int kBorderThreads = 1024;
 
+// Schedule tables are read-only during a launch and indexed uniformly across
+// a wavefront; reading them through the constant address space lets the
+// compiler use scalar loads (one per wavefront, through the scalar cache)
+// instead of per-lane vector loads that each wait for memory.
+template <class T>
+__device__ inline const __attribute__((address_space(4))) T *cs(const T *p) {
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(int((blockIdx.x * kWG + threadIdx.x) >> 6)); }
 __device__ inline int lane_id() { return int(threadIdx.x & 63); }
 
-// sum_k a[k*st] d[k*sd] c[k*st] with four independent partial sums
-// (a, c: two rows of a panel, stride st; d: the panel's pivots, stride sd)
-__device__ inline double wdot(const double *__restrict__ a, const double *__restrict__ c,
-                              const double *__restrict__ d, int w, int64_t st, int64_t sd) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {
-        s0 += a[k * st] * d[k * sd] * c[k * st];
-        s1 += a[(k + 1) * st] * d[(k + 1) * sd] * c[(k + 1) * st];
-        s2 += a[(k + 2) * st] * d[(k + 2) * sd] * c[(k + 2) * st];
-        s3 += a[(k + 3) * st] * d[(k + 3) * sd] * c[(k + 3) * st];
+// Update sums over a contiguous run of terms [t0, t1).  Terms are taken in
+// rounds of 8, then 4, 2 and 1: each round loads its (uniform) descriptors,
+// then issues every vector load of the round before the first use, so that
+// a wavefront keeps many loads in flight instead of waiting on each product
+// in turn, and no load is wasted on padding.
+
+// L[a] d[k] L[c] for R consecutive terms, added into R partial sums
+template <int R>
+__device__ inline void tdot_round(const double *__restrict__ Lp, const double *__restrict__ Dv, int64_t nb,
+                                  const Term *__restrict__ tm, double *s) {
+    double p[R];
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const auto *q = cs(tm) + u;
+        p[u] = Lp[int64_t(q->a) * nb] * Dv[int64_t(q->k) * nb] * Lp[int64_t(q->c) * nb];
     }
-    for (; k < w; k++) s0 += a[k * st] * d[k * sd] * c[k * st];
-    return (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int u = 0; u < R; u++) s[u] += p[u];
 }
 
-// sum_k a[k*sa] y[k*sy]
-__device__ inline double rdot(const double *__restrict__ a, int64_t sa, const double *__restrict__ y, int64_t sy,
-                              int w) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {
-        s0 += a[k * sa] * y[k * sy];
-        s1 += a[(k + 1) * sa] * y[(k + 1) * sy];
-        s2 += a[(k + 2) * sa] * y[(k + 2) * sy];
-        s3 += a[(k + 3) * sa] * y[(k + 3) * sy];
+// sum over terms of L[a] d[k] L[c]
+__device__ inline double tdot(const double *__restrict__ Lp, const double *__restrict__ Dv, int64_t nb,
+                              const Term *__restrict__ tm, int t0, int t1) {
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s[u] = 0.0;
+    int t = t0;
+    for (; t + 8 <= t1; t += 8) tdot_round<8>(Lp, Dv, nb, tm + t, s);
+    if (t + 4 <= t1) { tdot_round<4>(Lp, Dv, nb, tm + t, s); t += 4; }
+    if (t + 2 <= t1) { tdot_round<2>(Lp, Dv, nb, tm + t, s + 4); t += 2; }
+    if (t < t1) tdot_round<1>(Lp, Dv, nb, tm + t, s + 6);
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// L[a] y[k] for R consecutive terms
+template <int R>
+__device__ inline void ydot_round(const double *__restrict__ Lp, const double *y, int64_t nb,
+                                  const Term *__restrict__ tm, double *s) {
+    double p[R];
+#pragma unroll
+    for (int u = 0; u < R; u++) {
+        const auto *q = cs(tm) + u;
+        p[u] = Lp[int64_t(q->a) * nb] * y[int64_t(q->k) * nb];
     }
-    for (; k < w; k++) s0 += a[k * sa] * y[k * sy];
-    return (s0 + s1) + (s2 + s3);
+#pragma unroll
+    for (int u = 0; u < R; u++) s[u] += p[u];
+}
+
+// sum over terms of L[a] y[k]
+__device__ inline double ydot(const double *__restrict__ Lp, const double *y, int64_t nb,
+                              const Term *__restrict__ tm, int t0, int t1) {
+    double s[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s[u] = 0.0;
+    int t = t0;
+    for (; t + 8 <= t1; t += 8) ydot_round<8>(Lp, y, nb, tm + t, s);
+    if (t + 4 <= t1) { ydot_round<4>(Lp, y, nb, tm + t, s); t += 4; }
+    if (t + 2 <= t1) { ydot_round<2>(Lp, y, nb, tm + t, s + 4); t += 2; }
+    if (t < t1) ydot_round<1>(Lp, y, nb, tm + t, s + 6);
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // template owning a flat interleaved index (binary search over the bases)
@@ -67,6 +108,17 @@ __device__ inline int find_tmpl(const DevArgs &a, int64_t idx, int64_t TemplDev:
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (a.tmpls[mid].*base <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// instance owning a flat index of a concatenated per-instance array
+__device__ inline int find_inst(const DevArgs &a, int64_t idx, int64_t InstDev::*base) {
+    int lo = 0, hi = a.ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.insts[mid].*base <= idx) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -125,49 +177,65 @@ struct AsmCtx {
     const DevArgs *a;
     int64_t kb;      // template K base + the lane's block
     int64_t nb;      // blocks of the template (stride)
+    int64_t kbb;     // the instance's K_bb values
 };
 
 __device__ inline void put(const AsmCtx &c, int32_t slot, double v) {
     if (slot < 0) return;
-    if (slot & kBorderFlag) c.a->kval[c.a->kint + (slot & ~kBorderFlag)] = v;
+    if (slot & kBorderFlag) c.a->kval[c.kbb + (slot & ~kBorderFlag)] = v;
     else c.a->kval[c.kb + int64_t(slot) * c.nb] = v;
 }
 
-__device__ inline int64_t zi(const DevArgs &a, const BlockDev &B, int n, int32_t x) {
-    return x < n ? B.col0 + x : a.bstart + (x - n);
+__device__ inline int64_t zi(int64_t bstart, const BlockDev &B, int n, int32_t x) {
+    return x < n ? B.col0 + x : bstart + (x - n);
 }
 
-// Threads: (bus, block) pairs, then (generator, block) pairs, then border pg;
-// the block index runs fastest so that neighbouring threads write
-// neighbouring interleaved values.
+// Threads: per template, (bus, block) pairs then (generator, block) pairs,
+// the block index running fastest so that neighbouring threads write
+// neighbouring interleaved values; then the border pg diagonal of every
+// instance.
 __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__restrict__ z,
                                                   const double *__restrict__ sig, double rho) {
     const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t nbus_t = int64_t(a.nblk) * a.nb;
-    const int64_t ngen_t = int64_t(a.nblk) * a.ng;
     const double irho = 1.0 / rho;
-    if (tid < nbus_t) {
-        const int blk = int(tid % a.nblk), i = int(tid / a.nblk);
-        const BlockDev B = a.blks[blk];
-        const TemplDev &T = a.tmpls[B.tmpl];
+    if (tid >= a.asm_threads) {
+        const int64_t gg = tid - a.asm_threads;
+        if (gg >= a.gp_tot) return;
+        const InstDev &I = a.insts[find_inst(a, gg, &InstDev::gp0)];
+        const int g = int(gg - I.gp0);
+        if (I.nbd == 0 || g >= I.ng) return;
+        const int bidx = I.border_pg[g];
+        const int32_t p = I.kbb_pos[size_t(bidx) * I.nbd + bidx];
+        const double h = 2.0 * I.gen_c2[g];
+        if (p >= 0) a.kval[a.kint + I.kbb0 + p] = h + fmax(0.0, -h) + sig[I.bstart + bidx];
+        return;
+    }
+    const TemplDev &T = a.tmpls[find_tmpl(a, tid, &TemplDev::abase)];
+    const int64_t u0 = tid - T.abase;
+    const int64_t nbus_t = int64_t(T.nblk) * T.nbus;
+    const int64_t bstart = a.insts[T.inst].bstart;
+    const int64_t kbb = a.kint + a.insts[T.inst].kbb0;
+    if (u0 < nbus_t) {
+        const int bl = int(u0 % T.nblk), i = int(u0 / T.nblk);
+        const BlockDev B = a.blks[T.blocks[bl]];
         const int n = T.n;
-        const AsmCtx cx{&a, T.kbase + B.bl, T.nblk};
+        const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb};
         const int32_t *bi = T.bus_idx + size_t(i) * BI_N;
         double Hvv = 0, Haa = 0, Hva = 0, dPv = 0, dPa = 0, dQv = 0, dQa = 0, absv = 0, absa = 0;
-        for (int q = T.bus_adj_ptr[i]; q < T.bus_adj_ptr[i + 1]; q++) {
+        for (int q = cs(T.bus_adj_ptr)[i]; q < cs(T.bus_adj_ptr)[i + 1]; q++) {
             const int32_t e = T.bus_adj[q];
             const bool self_from = e >= 0;
             const int l = self_from ? e : ~e;
             const int32_t *br = T.br_idx + size_t(l) * 4;
             const int f = br[2], t = br[3];
             const int32_t *bf = T.bus_idx + size_t(f) * BI_N, *bt = T.bus_idx + size_t(t) * BI_N;
-            const double vf = z[zi(a, B, n, bf[BI_VM])], vt = z[zi(a, B, n, bt[BI_VM])];
-            const double tf = z[zi(a, B, n, bf[BI_VA])], tt = z[zi(a, B, n, bt[BI_VA])];
-            const double yPf = z[zi(a, B, n, bf[BI_P])], yQf = z[zi(a, B, n, bf[BI_Q])];
-            const double yPt = z[zi(a, B, n, bt[BI_P])], yQt = z[zi(a, B, n, bt[BI_Q])];
-            const double yFf = z[zi(a, B, n, br[0])], yFt = z[zi(a, B, n, br[1])];
+            const double vf = z[zi(bstart, B, n, bf[BI_VM])], vt = z[zi(bstart, B, n, bt[BI_VM])];
+            const double tf = z[zi(bstart, B, n, bf[BI_VA])], tt = z[zi(bstart, B, n, bt[BI_VA])];
+            const double yPf = z[zi(bstart, B, n, bf[BI_P])], yQf = z[zi(bstart, B, n, bf[BI_Q])];
+            const double yPt = z[zi(bstart, B, n, bt[BI_P])], yQt = z[zi(bstart, B, n, bt[BI_Q])];
+            const double yFf = z[zi(bstart, B, n, br[0])], yFt = z[zi(bstart, B, n, br[1])];
             const double st = (l == B.outage) ? 0.0 : 1.0;
-            const double r = a.br_r[l], x = a.br_x[l];
+            const double r = T.br_r[l], x = T.br_x[l];
             const double den = r * r + x * x;
             const double g = st * (r / den), b = st * (-x / den);
             double W[4][4] = {};
@@ -222,8 +290,8 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         const double dv = fmax(0.0, absv + fabs(Hva) - Hvv);
         const double da = fmax(0.0, absa + fabs(Hva) - Haa);
         const int32_t *bs = T.bus_slot + size_t(i) * BS_N;
-        put(cx, bs[BS_VMVM], Hvv + dv + sig[zi(a, B, n, bi[BI_VM])]);
-        put(cx, bs[BS_VAVA], Haa + da + sig[zi(a, B, n, bi[BI_VA])]);
+        put(cx, bs[BS_VMVM], Hvv + dv + sig[zi(bstart, B, n, bi[BI_VM])]);
+        put(cx, bs[BS_VAVA], Haa + da + sig[zi(bstart, B, n, bi[BI_VA])]);
         put(cx, bs[BS_VMVA], Hva);
         put(cx, bs[BS_PVM], dPv);
         put(cx, bs[BS_PVA], dPa);
@@ -233,26 +301,25 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         put(cx, bs[BS_QQ], -irho);
         return;
     }
-    if (tid < nbus_t + ngen_t) {
-        const int64_t u = tid - nbus_t;
-        const int blk = int(u % a.nblk), g = int(u / a.nblk);
-        const BlockDev B = a.blks[blk];
-        const TemplDev &T = a.tmpls[B.tmpl];
+    {
+        const int64_t u = u0 - nbus_t;
+        const int bl = int(u % T.nblk), g = int(u / T.nblk);
+        const BlockDev B = a.blks[T.blocks[bl]];
         const int n = T.n;
-        const AsmCtx cx{&a, T.kbase + B.bl, T.nblk};
+        const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb};
         const int32_t *gi = T.gen_idx + size_t(g) * GI_N;
         const int32_t *gs = T.gen_slot + size_t(g) * GS_N;
         put(cx, gs[GS_PPG], -1.0);
         put(cx, gs[GS_QQG], -1.0);
-        put(cx, gs[GS_QGQG], sig[zi(a, B, n, gi[GI_QG])]);
+        put(cx, gs[GS_QGQG], sig[zi(bstart, B, n, gi[GI_QG])]);
         if (T.has_pg_local) {
-            const double h = 2.0 * a.gen_c2[g];
-            put(cx, gs[GS_PGPG], h + fmax(0.0, -h) + sig[zi(a, B, n, gi[GI_PG])]);
+            const double h = 2.0 * T.gen_c2[g];
+            put(cx, gs[GS_PGPG], h + fmax(0.0, -h) + sig[zi(bstart, B, n, gi[GI_PG])]);
         }
         if (T.pvpq_rows) {
-            const double nup = z[zi(a, B, n, gi[GI_NUP])], num = z[zi(a, B, n, gi[GI_NUM])];
-            const double sup = z[zi(a, B, n, gi[GI_SUP])], slo = z[zi(a, B, n, gi[GI_SLO])];
-            const int64_t cu = zi(a, B, n, gi[GI_CUP]), cl = zi(a, B, n, gi[GI_CLO]);
+            const double nup = z[zi(bstart, B, n, gi[GI_NUP])], num = z[zi(bstart, B, n, gi[GI_NUM])];
+            const double sup = z[zi(bstart, B, n, gi[GI_SUP])], slo = z[zi(bstart, B, n, gi[GI_SLO])];
+            const int64_t cu = zi(bstart, B, n, gi[GI_CUP]), cl = zi(bstart, B, n, gi[GI_CLO]);
             const double n0u = z[cu], n0l = z[cl];
             put(cx, gs[GS_LIN_NUP], 1.0);
             put(cx, gs[GS_LIN_NUM], -1.0);
@@ -268,30 +335,23 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
             put(cx, gs[GS_CLO_SLO], nup);
             put(cx, gs[GS_H_NUM_SUP], n0u);
             put(cx, gs[GS_H_NUP_SLO], n0l);
-            put(cx, gs[GS_NUPNUP], fabs(n0l) + sig[zi(a, B, n, gi[GI_NUP])]);
-            put(cx, gs[GS_NUMNUM], fabs(n0u) + sig[zi(a, B, n, gi[GI_NUM])]);
-            put(cx, gs[GS_SUPSUP], fabs(n0u) + sig[zi(a, B, n, gi[GI_SUP])]);
-            put(cx, gs[GS_SLOSLO], fabs(n0l) + sig[zi(a, B, n, gi[GI_SLO])]);
+            put(cx, gs[GS_NUPNUP], fabs(n0l) + sig[zi(bstart, B, n, gi[GI_NUP])]);
+            put(cx, gs[GS_NUMNUM], fabs(n0u) + sig[zi(bstart, B, n, gi[GI_NUM])]);
+            put(cx, gs[GS_SUPSUP], fabs(n0u) + sig[zi(bstart, B, n, gi[GI_SUP])]);
+            put(cx, gs[GS_SLOSLO], fabs(n0l) + sig[zi(bstart, B, n, gi[GI_SLO])]);
             put(cx, gs[GS_LL], -irho);
             put(cx, gs[GS_UU], -irho);
             put(cx, gs[GS_DD], -irho);
             put(cx, gs[GS_CUCU], -(irho + sig[cu] / n0u));
             put(cx, gs[GS_CLCL], -(irho + sig[cl] / n0l));
         }
-        return;
-    }
-    const int64_t g = tid - nbus_t - ngen_t;
-    if (g < a.ng && a.nbd > 0) {
-        const int bidx = a.border_pg[g];
-        const int32_t p = a.kbb_pos[size_t(bidx) * a.nbd + bidx];
-        const double h = 2.0 * a.gen_c2[g];
-        if (p >= 0) a.kval[a.kint + p] = h + fmax(0.0, -h) + sig[a.bstart + bidx];
     }
 }
 
-// Public lower-CSC values <-> internal (interleaved blocks, then K_bb).
+// Public lower-CSC values <-> internal (interleaved blocks, then each
+// instance's K_bb).
 __global__ __launch_bounds__(256) void k_values(DevArgs a, const double *__restrict__ src, double *__restrict__ dst,
-                                                int to_internal, int64_t nnz_border, int64_t kcsc_border) {
+                                                int to_internal) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx < a.kint) {
         const int ti = find_tmpl(a, idx, &TemplDev::kbase);
@@ -302,10 +362,12 @@ __global__ __launch_bounds__(256) void k_values(DevArgs a, const double *__restr
         const int64_t c = a.blks[T.blocks[bl]].kcsc + e;
         if (to_internal) dst[idx] = src[c];
         else dst[c] = src[idx];
-    } else if (idx < a.kint + nnz_border) {
+    } else if (idx < a.kint + a.nbb_tot) {
         const int64_t p = idx - a.kint;
-        if (to_internal) dst[idx] = src[kcsc_border + p];
-        else dst[kcsc_border + p] = src[idx];
+        const InstDev &I = a.insts[find_inst(a, p, &InstDev::kbb0)];
+        const int64_t c = I.kcsc_border + (p - I.kbb0);
+        if (to_internal) dst[idx] = src[c];
+        else dst[c] = src[idx];
     }
 }
 
@@ -330,46 +392,50 @@ __device__ inline Lane lane_work(const DevArgs &a, const Work *wl, int wid) {
 }
 
 // A: one lower panel entry = its K value minus the updates of all descendant
-// supernodes that hold the entry's row and column, in increasing order of
-// the descendant; two descendants are in flight at a time.
+// supernodes that hold the entry's row and column (one term per column of
+// each descendant).
 __global__ __launch_bounds__(kWG) void k_fac_gather(DevArgs a, const Work *__restrict__ wl, int nw) {
     const int wid = wave_id();
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
-    const double *__restrict__ Lp = a.lpan + T.lbase + W.bl;
-    const double *__restrict__ Dv = a.dval + T.dbase + W.bl;
     const int e = W.k;
-    const int kp = T.ent_kpos[e];
-    const int i1 = T.ent_iptr[e + 1];
-    int it = T.ent_iptr[e];
+    const int kp = cs(T.ent_kpos)[e];
     double v = kp >= 0 ? a.kval[T.kbase + W.bl + int64_t(kp) * nb] : 0.0;
-    for (; it + 2 <= i1; it += 2) {
-        const CItem c0 = T.citems[it], c1 = T.citems[it + 1];
-        const double u0 = wdot(Lp + int64_t(c0.ioff) * nb, Lp + int64_t(c0.coff) * nb, Dv + int64_t(c0.dcol) * nb,
-                               c0.meta >> 16, int64_t(c0.meta & 0xffff) * nb, nb);
-        const double u1 = wdot(Lp + int64_t(c1.ioff) * nb, Lp + int64_t(c1.coff) * nb, Dv + int64_t(c1.dcol) * nb,
-                               c1.meta >> 16, int64_t(c1.meta & 0xffff) * nb, nb);
-        v -= u0;
-        v -= u1;
-    }
-    if (it < i1) {
-        const CItem c0 = T.citems[it];
-        v -= wdot(Lp + int64_t(c0.ioff) * nb, Lp + int64_t(c0.coff) * nb, Dv + int64_t(c0.dcol) * nb, c0.meta >> 16,
-                  int64_t(c0.meta & 0xffff) * nb, nb);
-    }
-    if (W.on) a.lpan[T.lbase + W.bl + int64_t(T.ent_out[e]) * nb] = v;
+    v -= tdot(a.lpan + T.lbase + W.bl, a.dval + T.dbase + W.bl, nb, T.terms, cs(T.ent_tptr)[e], cs(T.ent_tptr)[e + 1]);
+    if (W.on) a.lpan[T.lbase + W.bl + int64_t(cs(T.ent_out)[e]) * nb] = v;
+}
+
+// Width classes: kernels that walk the columns of a supernode are
+// instantiated for W = 1, 2, 4, 8, 12, 16, 24, 32 and run the smallest class
+// holding the supernode's width w (a uniform branch).  Inside a class every
+// loop bound is a compile-time constant; loads past w are clamped to column
+// w-1 (a valid address) and their contributions masked, so no load waits on
+// a run-time branch.
+template <class F>
+__device__ inline void by_width(int w, F &&f) {
+    if (w <= 1) f(std::integral_constant<int, 1>());
+    else if (w <= 2) f(std::integral_constant<int, 2>());
+    else if (w <= 4) f(std::integral_constant<int, 4>());
+    else if (w <= 8) f(std::integral_constant<int, 8>());
+    else if (w <= 12) f(std::integral_constant<int, 12>());
+    else if (w <= 16) f(std::integral_constant<int, 16>());
+    else if (w <= 24) f(std::integral_constant<int, 24>());
+    else f(std::integral_constant<int, 32>());
 }
 
 // B: LDL^T of the diagonal block of a wide supernode.  Two blocks per
 // wavefront; lane i of each half holds row i of its block's diagonal block
-// in registers, and the right-looking elimination exchanges columns by
-// cross-lane shuffles.  Row i ends with l_ik (k < i) and d_i.
+// in registers.  Right-looking: at step j each row publishes its column-j
+// value through LDS, every lane reads the pivot and the column by broadcast
+// reads, and row i takes l_ij = a_ij / d_j and a_ik -= l_ij a_kj (k <= i).
+// Row i ends with l_ik (k < i) and d_i.
 __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restrict__ wl, int nw) {
+    __shared__ double cbuf[kWG / 64][2][2][kMaxW];     // wavefront, step parity, half, row
     const int wid = wave_id();
     if (wid >= nw) return;
-    const int lane = lane_id();
+    const int lane = lane_id(), wv = int(threadIdx.x >> 6);
     const int half = lane >> 5, i = lane & 31;
     const Work wk = wl[wid];
     const TemplDev &T = a.tmpls[wk.tg >> 16];
@@ -377,53 +443,61 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
     const int b = (wk.tg & 0xffff) * 2 + half;
     const int bl = b < nb ? b : 0;
     const int s = wk.k;
-    const int f = T.sup_first[s], w = T.sup_first[s + 1] - f;
-    const int r = T.sup_rowptr[s + 1] - T.sup_rowptr[s];
+    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
     const bool on = b < nb && i < w;
-    double *P = a.lpan + T.lbase + bl + int64_t(T.panel_off[s]) * nb;   // P(row, col) = P[(col * r + row) * nb]
-    double row[kMaxW];
+    double *P = a.lpan + T.lbase + bl + int64_t(cs(T.panel_off)[s]) * nb;   // P(row, col) = P[(col * r + row) * nb]
+    by_width(w, [&](auto Wc) {
+        constexpr int W = decltype(Wc)::value;
+        const int wl1 = w - 1, ic = i < w ? i : wl1;
+        double row[W];
 #pragma unroll
-    for (int k = 0; k < kMaxW; k++) row[k] = (k < w && k <= i && i < w) ? P[(int64_t(k) * r + i) * nb] : 0.0;
-    const int base = half << 5;
+        for (int k = 0; k < W; k++) {
+            const double v = P[(int64_t(k < w ? k : wl1) * r + ic) * nb];
+            row[k] = (k <= i && i < w && k < w) ? v : 0.0;
+        }
 #pragma unroll
-    for (int j = 0; j < kMaxW; j++) {
-        if (j < w) {
-            const double dj = __shfl(row[j], base + j);
-            const double lij = i > j ? row[j] / dj : 0.0;
+        for (int j = 0; j < W; j++) {
+            if (j < w) {
+                double *cb = cbuf[wv][j & 1][half];
+                if (i >= j && i < w) cb[i] = row[j];
+                __builtin_amdgcn_wave_barrier();
+                const double dj = cb[j];
+                const double lij = i > j ? row[j] / dj : 0.0;
 #pragma unroll
-            for (int k = j + 1; k < kMaxW; k++) {
-                if (k < w) {
-                    const double lkj = __shfl(lij, base + k);
-                    if (i >= k) row[k] -= lij * dj * lkj;
-                }
+                for (int k = j + 1; k < W; k++)
+                    if (i >= k && k < w) row[k] -= lij * cb[k];
+                if (i > j) row[j] = lij;
+                __builtin_amdgcn_wave_barrier();
             }
-            if (i > j) row[j] = lij;
         }
-    }
-    if (on) {
-        double di = 0.0;
+        if (on) {
+            double di = 0.0;
 #pragma unroll
-        for (int k = 0; k < kMaxW; k++) {
-            if (k < i) P[(int64_t(k) * r + i) * nb] = row[k];
-            if (k == i) di = row[k];
+            for (int k = 0; k < W; k++) {
+                if (k < i) P[(int64_t(k) * r + i) * nb] = row[k];
+                if (k == i) di = row[k];
+            }
+            a.dval[T.dbase + bl + int64_t(f + i) * nb] = di;
         }
-        a.dval[T.dbase + bl + int64_t(f + i) * nb] = di;
-    }
+    });
 }
 
 // C: pivot and off-diagonal rows.  Width-1 supernodes: d = P(0,0) and
-// L(p,0) = P(p,0) / d.  Wide supernodes: row p >= w solves
-// x_j = (P(p,j) - sum_{k<j} x_k d_k L(j,k)) / d_j.
+// L(p,0) = P(p,0) / d.  Row p >= w of a wide supernode: u_j = L(p,j) d_j
+// satisfies u_j = P(p,j) - sum_{k<j} L(j,k) u_k, solved right-looking
+// (u_k -= L(k,j) u_j for k > j; the loads of L do not depend on u), then
+// L(p,j) = u_j / d_j.
 __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restrict__ wl, int nw) {
     const int wid = wave_id();
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
-    const int s = T.task_s[W.k], p = T.task_p[W.k];
-    const int f = T.sup_first[s], w = T.sup_first[s + 1] - f;
-    const int r = T.sup_rowptr[s + 1] - T.sup_rowptr[s];
-    double *P = a.lpan + T.lbase + W.bl + int64_t(T.panel_off[s]) * nb;
+    const int s = cs(T.task_s)[W.k], p = cs(T.task_p)[W.k];
+    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
     double *Dv = a.dval + T.dbase + W.bl + int64_t(f) * nb;
     if (w == 1) {
         if (!W.on) return;
@@ -431,22 +505,29 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
         else P[int64_t(p) * nb] = P[int64_t(p) * nb] / P[0];
         return;
     }
-    double x[kMaxW];
+    by_width(w, [&](auto Wc) {
+        constexpr int W_ = decltype(Wc)::value;
+        const int wl1 = w - 1;
+        double u[W_];
 #pragma unroll
-    for (int j = 0; j < kMaxW; j++) {
-        if (j < w) {
-            double v = P[(int64_t(j) * r + p) * nb];
+        for (int j = 0; j < W_; j++) u[j] = P[(int64_t(j < w ? j : wl1) * r + p) * nb];
 #pragma unroll
-            for (int k = 0; k < kMaxW; k++)
-                if (k < j) v -= x[k] * Dv[int64_t(k) * nb] * P[(int64_t(k) * r + j) * nb];
-            x[j] = v / Dv[int64_t(j) * nb];
+        for (int j = 0; j < W_; j++) {
+            const int64_t cj = int64_t(j < w ? j : wl1) * r;
+#pragma unroll
+            for (int k = j + 1; k < W_; k++) {
+                const double l = P[(cj + (k < w ? k : wl1)) * nb];
+                u[k] -= (k < w ? l : 0.0) * u[j];
+            }
         }
-    }
-    if (W.on) {
+        if (W.on) {
 #pragma unroll
-        for (int j = 0; j < kMaxW; j++)
-            if (j < w) P[(int64_t(j) * r + p) * nb] = x[j];
-    }
+            for (int j = 0; j < W_; j++) {
+                const double d = Dv[int64_t(j < w ? j : wl1) * nb];
+                if (j < w) P[(int64_t(j) * r + p) * nb] = u[j] / d;
+            }
+        }
+    });
 }
 
 // Border Schur contribution S_k[e] = sum over common panels of L[i,:] D L[j,:]^T
@@ -456,19 +537,11 @@ __global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a, const Work *__r
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
-    const double *__restrict__ Lp = a.lpan + T.lbase + W.bl;
-    const double *__restrict__ Dv = a.dval + T.dbase + W.bl;
     const int e = W.k;
-    double sum = 0.0;
-    for (int it = T.sitem_ptr[e]; it < T.sitem_ptr[e + 1]; it++) {
-        const SItem si = T.sitems[it];
-        const int f = T.sup_first[si.s], w = T.sup_first[si.s + 1] - f;
-        const int r = T.sup_rowptr[si.s + 1] - T.sup_rowptr[si.s];
-        const int64_t po = T.panel_off[si.s];
-        sum += wdot(Lp + (po + si.pi) * nb, Lp + (po + si.pj) * nb, Dv + int64_t(f) * nb, w, int64_t(r) * nb, nb);
-    }
-    if (W.on) a.spart[int64_t(e) * a.nblk + T.blocks[W.bl]] = sum;
+    const double sum = tdot(a.lpan + T.lbase + W.bl, a.dval + T.dbase + W.bl, W.nb, T.sterms, cs(T.sterm_ptr)[e],
+                            cs(T.sterm_ptr)[e + 1]);
+    const InstDev &I = a.insts[T.inst];
+    if (W.on) a.spart[I.sp0 + int64_t(e) * I.nblk + (T.blocks[W.bl] - I.blk0)] = sum;
 }
 
 // ------------------------------------------------------------------ border
@@ -483,151 +556,149 @@ __device__ inline void unpack(int64_t e, int &i, int &j) {
 
 __device__ inline int pk(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// S[e] = K_bb[e] - sum_k S_k[e]: one wavefront per entry, blocks summed in a
-// fixed order (lane-strided partial sums, then a fixed shuffle tree).
+constexpr int kBB = 32;          // column block of the dense border factor and solves
+constexpr int kPS = kBB + 1;     // LDS row stride of a staged block column
+
+// S[e] = K_bb[e] - sum_k S_k[e]: one wavefront per packed entry of every
+// instance's border, blocks summed in a fixed order (lane-strided partial
+// sums, then a fixed shuffle tree).
 __global__ __launch_bounds__(kWG) void k_border_sum(DevArgs a) {
-    const int64_t npk = int64_t(a.nbd) * (a.nbd + 1) / 2;
-    const int64_t e = wave_id();
-    if (e >= npk) return;
+    const int64_t eg = wave_id();
+    if (eg >= a.npk_tot) return;
+    const InstDev &I = a.insts[find_inst(a, eg, &InstDev::npk0)];
+    const int64_t e = eg - I.npk0;
     const int lane = lane_id();
+    const double *sp = a.spart + I.sp0 + e * I.nblk;
     double s = 0.0;
-    for (int b = lane; b < a.nblk; b += 64) s += a.spart[e * a.nblk + b];
+    for (int b = lane; b < I.nblk; b += 64) s += sp[b];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) {
         int i, j;
         unpack(e, i, j);
-        const int32_t p = a.kbb_pos[size_t(i) * a.nbd + j];
-        a.sbb[e] = (p >= 0 ? a.kval[a.kint + p] : 0.0) - s;
+        const int32_t p = I.kbb_pos[size_t(i) * I.nbd + j];
+        a.sbb[I.sbb0 + e] = (p >= 0 ? a.kval[a.kint + I.kbb0 + p] : 0.0) - s;
     }
 }
 
-// Dense LDL^T of the packed border matrix.  The matrix is held in 4x4
-// register tiles spread over the workgroup (lower-triangular tiles, tile q
-// in thread q mod 1024); each pivot step broadcasts the current column
-// through a double-buffered LDS vector and every thread updates the tiles
-// right of the pivot.  Used when the tiles fit (border <= kTileMaxB);
-// otherwise the column-by-column version below runs in place.
-constexpr int kTileMaxB = 252;                 // 2 tiles per thread cover 63 tile rows
+// Dense LDL^T of the packed border matrix S (lower triangle packed by rows)
+// of one instance per workgroup, right-looking by blocks of kBB columns, in
+// place:
+//   1. wavefront 0 factors the diagonal block in registers (lane = row) with
+//      cross-lane shuffles;
+//   2. one thread per row below the block solves for that row's kBB entries
+//      of L against the block;
+//   3. the trailing lower triangle takes S_ik -= sum_j L_ij d_j L_kj, in 4x4
+//      register tiles that read the block column of L from LDS.
+// S ends with L strictly below the diagonal and 1 on it; D goes to dval.
+// The trailing matrix stays in global memory (L2-resident: 130 KB for a
+// 180-row border); the block column of L is staged in LDS.
+constexpr int kBFThreads = 512;    // 8 wavefronts: up to 256 registers each, no spills
 
-template <int kTPT>
-__global__ __launch_bounds__(kBorderThreads) void k_border_factor_tiles(DevArgs a) {
-    __shared__ double col[2][kTileMaxB + 4];
-    const int nbd = a.nbd;
-    const int nt = (nbd + 3) / 4;                  // tile rows
-    const int ntiles = nt * (nt + 1) / 2;
-    const int tid = threadIdx.x;
-    double S[kTPT][4][4];
-    int TI[kTPT], TK[kTPT];
+__global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
+    extern __shared__ double lds[];
+    double *Ld = lds;                  // [kBB][kPS] L of the diagonal block
+    double *dd = Ld + kBB * kPS;       // [kBB] its pivots
+    double *Pn = dd + kBB;             // [nbd - kBB][kPS] L of the rows below it
+    const InstDev &I = a.insts[blockIdx.x];
+    const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
+    double *S = a.sbb + I.sbb0;
+    double *Db = a.dval + a.dint + I.bd0;
+    for (int b0 = 0; b0 < nbd; b0 += kBB) {
+        const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
+        const int r0 = b0 + bs, m = nbd - r0;
+        if (tid < 64) {
+            // diagonal block: lane i < bs holds row i; column j is published
+            // through Ld's column j (its final L values are written there)
+            const int i = lane;
+            const bool on = i < bs;
+            double row[kBB];
 #pragma unroll
-    for (int q = 0; q < kTPT; q++) {
-        const int t = tid + q * kBorderThreads;
-        int I = 0, K = 0;
-        if (t < ntiles) {
-            int ii, jj;
-            unpack(t, ii, jj);
-            I = ii;
-            K = jj;
-        }
-        TI[q] = t < ntiles ? I : -1;
-        TK[q] = K;
+            for (int k = 0; k < kBB; k++) row[k] = (on && k <= i) ? S[pk(b0 + i, b0 + k)] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+            for (int j = 0; j < kBB; j++) {
+                if (j < bs) {
+                    if (on && i >= j) Ld[i * kPS + j] = row[j];
+                    __builtin_amdgcn_wave_barrier();
+                    const double dj = Ld[j * kPS + j];
+                    const double lij = i > j ? row[j] / dj : 0.0;
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int i = 4 * I + u, k = 4 * K + v;
-                S[q][u][v] = (t < ntiles && i < nbd && k <= i) ? a.sbb[pk(i, k)] : 0.0;
+                    for (int k = j + 1; k < kBB; k++)
+                        if (i >= k && k < bs) row[k] -= lij * Ld[k * kPS + j];
+                    if (i > j) row[j] = lij;
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
-    }
-    for (int j = 0; j < nbd; j++) {
-        double *cj = col[j & 1];
-        const int J = j >> 2, jv = j & 3;
-        // owners of tile column J publish column j (rows >= j)
+            if (on) {
 #pragma unroll
-        for (int q = 0; q < kTPT; q++)
-            if (TI[q] >= 0 && TK[q] == J)
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int i = 4 * TI[q] + u;
-                    if (i >= j && i < nbd) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int w = 0; w < 4; w++)
-                            if (w == jv) v = S[q][u][w];
-                        cj[i] = v;
+                for (int k = 0; k < kBB; k++) {
+                    if (k < i) {
+                        Ld[i * kPS + k] = row[k];
+                        S[pk(b0 + i, b0 + k)] = row[k];
+                    }
+                    if (k == i) {
+                        dd[i] = row[k];
+                        Db[b0 + i] = row[k];
+                        S[pk(b0 + i, b0 + i)] = 1.0;
                     }
                 }
+            }
+        }
         __syncthreads();
-        const double inv = 1.0 / cj[j];
+        // rows below the block: L_ij = (S_ij - sum_{k<j} L_ik d_k L_jk) / d_j
+        for (int t = tid; t < m; t += kBFThreads) {
+            double *si = S + pk(r0 + t, b0);
+            double x[kBB];
 #pragma unroll
-        for (int q = 0; q < kTPT; q++) {
-            if (TI[q] < 0 || 4 * TI[q] + 3 <= j || 4 * TK[q] + 3 <= j) continue;
-            double ci[4], ck[4];
+            for (int j = 0; j < kBB; j++) {
+                if (j < bs) {
+                    double v = si[j];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int i = 4 * TI[q] + u, k = 4 * TK[q] + u;
-                ci[u] = (i > j && i < nbd) ? cj[i] * inv : 0.0;
-                ck[u] = (k > j && k < nbd) ? cj[k] : 0.0;
+                    for (int k = 0; k < kBB; k++)
+                        if (k < j) v -= x[k] * dd[k] * Ld[j * kPS + k];
+                    x[j] = v / dd[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kBB; j++)
+                if (j < bs) {
+                    si[j] = x[j];
+                    Pn[t * kPS + j] = x[j];
+                }
+        }
+        __syncthreads();
+        const int mt = (m + 3) >> 2;
+        const int ntl = mt * (mt + 1) / 2;
+        for (int q = tid; q < ntl; q += kBFThreads) {
+            int I, K;
+            unpack(q, I, K);
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) acc[u][v] = 0.0;
+            for (int j = 0; j < bs; j++) {
+                const double dj = dd[j];
+                double pi[4], pc[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int ii = 4 * I + u, kk = 4 * K + u;
+                    pi[u] = ii < m ? Pn[ii * kPS + j] : 0.0;
+                    pc[u] = kk < m ? Pn[kk * kPS + j] * dj : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) acc[u][v] += pi[u] * pc[v];
             }
 #pragma unroll
             for (int u = 0; u < 4; u++)
 #pragma unroll
-                for (int v = 0; v < 4; v++) S[q][u][v] -= ci[u] * ck[v];
-        }
-        // next step writes the other buffer; a barrier every step keeps a
-        // buffer from being overwritten while a slow thread still reads it
-    }
-    __syncthreads();
-    // pivots: diagonal of the diagonal tiles
-    double *Db = a.dval + a.dint;
-#pragma unroll
-    for (int q = 0; q < kTPT; q++)
-        if (TI[q] >= 0 && TI[q] == TK[q])
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int i = 4 * TI[q] + u;
-                if (i < nbd) Db[i] = S[q][u][u];
-            }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kTPT; q++) {
-        if (TI[q] < 0) continue;
-#pragma unroll
-        for (int u = 0; u < 4; u++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int i = 4 * TI[q] + u, k = 4 * TK[q] + v;
-                if (i < nbd && k <= i) a.sbb[pk(i, k)] = (i == k) ? 1.0 : S[q][u][v] / Db[k];
-            }
-    }
-}
-
-// Column-by-column dense LDL^T of the packed border matrix in LDS, or in
-// place in global memory when it does not fit.
-__global__ __launch_bounds__(kBorderThreads) void k_border_factor(DevArgs a, int use_lds) {
-    extern __shared__ double lds[];
-    const int nbd = a.nbd;
-    const int npk = nbd * (nbd + 1) / 2;
-    const int tid = threadIdx.x;
-    double *S = use_lds ? lds : a.sbb;
-    if (use_lds)
-        for (int e = tid; e < npk; e += kBorderThreads) S[e] = a.sbb[e];
-    __syncthreads();
-    const int tx = tid & 31, ty = tid >> 5;
-    for (int j = 0; j < nbd; j++) {
-        const double inv = 1.0 / S[pk(j, j)];
-        for (int i = j + 1 + ty; i < nbd; i += 32) {
-            const double ci = S[pk(i, j)] * inv;
-            for (int k = j + 1 + tx; k <= i; k += 32) S[pk(i, k)] -= ci * S[pk(k, j)];
+                for (int v = 0; v < 4; v++) {
+                    const int i = r0 + 4 * I + u, k = r0 + 4 * K + v;
+                    if (i < nbd && k <= i) S[pk(i, k)] -= acc[u][v];
+                }
         }
         __syncthreads();
-    }
-    double *Db = a.dval + a.dint;
-    for (int j = tid; j < nbd; j += kBorderThreads) Db[j] = S[pk(j, j)];
-    __syncthreads();
-    for (int e = tid; e < npk; e += kBorderThreads) {
-        int i, j;
-        unpack(e, i, j);
-        a.sbb[e] = (i == j) ? 1.0 : S[e] / Db[j];
     }
 }
 
@@ -652,7 +723,7 @@ __device__ inline int pivot_code(double d, bool primal) {
 
 __global__ __launch_bounds__(256) void k_status(DevArgs a) {
     int64_t np = 0, nn = 0, nz = 0, bad = INT64_MAX, mn = INT64_MAX, mx = 0;
-    const int64_t total = a.dint + a.nbd;
+    const int64_t total = a.dint + a.nbd_tot;
     for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
          idx += int64_t(gridDim.x) * blockDim.x) {
         double d;
@@ -667,10 +738,11 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
             primal = T.col_primal[j] != 0;
             col = a.blks[T.blocks[bl]].col0 + j;
         } else {
-            const int j = int(idx - a.dint);
+            const int64_t j = idx - a.dint;
+            const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
             d = a.dval[idx];
             primal = a.bprim[j] != 0;
-            col = a.bstart + j;
+            col = I.bstart + (j - I.bd0);
         }
         const int code = pivot_code(d, primal);
         if (code == 0 || code == 1) {
@@ -748,27 +820,24 @@ __global__ __launch_bounds__(256) void k_sol_scale(DevArgs a, double *__restrict
 }
 
 // forward gather of a diagonal row: y_row -= sum over descendants L_d[row,:] y_d
+// (the terms of the row's diagonal panel entry)
 __global__ __launch_bounds__(kWG) void k_sol_fwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
     const int wid = wave_id();
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
-    const double *__restrict__ Lp = a.lpan + T.lbase + W.bl;
     double *yb = y + T.dbase + W.bl;
-    const int s = T.task_s[W.k], p = T.task_p[W.k];
-    const int col = T.sup_first[s] + p;
-    const int e = T.task_cbase[W.k] + p;
-    double v = 0.0;
-    for (int it = T.ent_iptr[e]; it < T.ent_iptr[e + 1]; it++) {
-        const CItem ci = T.citems[it];
-        const int ld = ci.meta & 0xffff, wd = ci.meta >> 16;
-        v += rdot(Lp + int64_t(ci.ioff) * nb, int64_t(ld) * nb, yb + int64_t(ci.dcol) * nb, nb, wd);
-    }
+    const int s = cs(T.task_s)[W.k], p = cs(T.task_p)[W.k];
+    const int col = cs(T.sup_first)[s] + p;
+    const int e = cs(T.task_cbase)[W.k] + p;
+    const double v = ydot(a.lpan + T.lbase + W.bl, yb, nb, T.terms, cs(T.ent_tptr)[e], cs(T.ent_tptr)[e + 1]);
     if (W.on) yb[int64_t(col) * nb] -= v;
 }
 
-// unit lower triangular solve with a wide supernode's diagonal block
+// unit lower triangular solve with a wide supernode's diagonal block,
+// right-looking: y_k -= L(k,j) y_j for k > j (the loads of L do not depend
+// on y)
 __global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
     const int wid = wave_id();
     if (wid >= nw) return;
@@ -776,26 +845,31 @@ __global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, cons
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
     const int s = W.k;
-    const int f = T.sup_first[s], w = T.sup_first[s + 1] - f;
-    const int r = T.sup_rowptr[s + 1] - T.sup_rowptr[s];
-    const double *P = a.lpan + T.lbase + W.bl + int64_t(T.panel_off[s]) * nb;
+    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    const double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
     double *yb = y + T.dbase + W.bl + int64_t(f) * nb;
-    double x[kMaxW];
+    by_width(w, [&](auto Wc) {
+        constexpr int W_ = decltype(Wc)::value;
+        const int wl1 = w - 1;
+        double x[W_];
 #pragma unroll
-    for (int j = 0; j < kMaxW; j++) {
-        if (j < w) {
-            double v = yb[int64_t(j) * nb];
+        for (int j = 0; j < W_; j++) x[j] = yb[int64_t(j < w ? j : wl1) * nb];
 #pragma unroll
-            for (int k = 0; k < kMaxW; k++)
-                if (k < j) v -= P[(int64_t(k) * r + j) * nb] * x[k];
-            x[j] = v;
+        for (int j = 0; j < W_; j++) {
+            const int64_t cj = int64_t(j < w ? j : wl1) * r;
+#pragma unroll
+            for (int k = j + 1; k < W_; k++) {
+                const double l = P[(cj + (k < w ? k : wl1)) * nb];
+                x[k] -= (k < w ? l : 0.0) * x[j];
+            }
         }
-    }
-    if (W.on) {
+        if (W.on) {
 #pragma unroll
-        for (int j = 1; j < kMaxW; j++)
-            if (j < w) yb[int64_t(j) * nb] = x[j];
-    }
+            for (int j = 1; j < W_; j++)
+                if (j < w) yb[int64_t(j) * nb] = x[j];
+        }
+    });
 }
 
 // this block's part of the border right-hand side: cpart[b][block] = L_bk y_k
@@ -805,94 +879,111 @@ __global__ __launch_bounds__(kWG) void k_sol_bpart(DevArgs a, const double *y, d
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
-    const double *__restrict__ Lp = a.lpan + T.lbase + W.bl;
-    const double *yb = y + T.dbase + W.bl;
     const int bi = W.k;
-    double v = 0.0;
-    for (int it = T.bpath_ptr[bi]; it < T.bpath_ptr[bi + 1]; it++) {
-        const int s = T.bpath_s[it];
-        const int f = T.sup_first[s], w = T.sup_first[s + 1] - f;
-        const int r = T.sup_rowptr[s + 1] - T.sup_rowptr[s];
-        v += rdot(Lp + int64_t(T.panel_off[s] + T.bpath_pos[it]) * nb, int64_t(r) * nb, yb + int64_t(f) * nb, nb, w);
-    }
-    if (W.on) cpart[int64_t(bi) * a.nblk + T.blocks[W.bl]] = v;
+    const double v = ydot(a.lpan + T.lbase + W.bl, y + T.dbase + W.bl, W.nb, T.bterms, cs(T.bterm_ptr)[bi],
+                          cs(T.bterm_ptr)[bi + 1]);
+    const InstDev &I = a.insts[T.inst];
+    if (W.on) cpart[I.cp0 + int64_t(bi) * I.nblk + (T.blocks[W.bl] - I.blk0)] = v;
 }
 
 // border: c = b_b - sum_k cpart; forward with L_bb, D_b^{-1}, backward with
-// L_bb^T.  Blocked by 32 rows: wavefront 0 solves a diagonal block with
-// cross-lane shuffles (lane = row), then the workgroup updates the other rows.
+// L_bb^T.  The block sum runs one wavefront per border row (lane-strided
+// partial sums, then a fixed shuffle tree).  The substitutions are blocked
+// by kBB rows: wavefront 0 solves a diagonal block with cross-lane shuffles
+// (lane = row, its kBB factor entries preloaded into registers), then the
+// workgroup updates the remaining rows.
 __global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const double *__restrict__ b, double *x,
                                                                double *y, const double *__restrict__ cpart) {
     extern __shared__ double c[];
-    const int nbd = a.nbd, tid = threadIdx.x, lane = lane_id();
-    const double *Db = a.dval + a.dint;
-    const double *Lb = a.sbb;
-    for (int i = tid; i < nbd; i += kBorderThreads) {
-        double v = 0.0;
-        for (int k = 0; k < a.nblk; k++) v += cpart[int64_t(i) * a.nblk + k];
-        c[i] = b[a.bstart + i] - v;
+    const InstDev &I = a.insts[blockIdx.x];
+    const int nbd = I.nbd, nblk = I.nblk, tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const double *Db = a.dval + a.dint + I.bd0;
+    const double *Lb = a.sbb + I.sbb0;
+    for (int i = wv; i < nbd; i += kBorderThreads / 64) {
+        const double *ci = cpart + I.cp0 + int64_t(i) * nblk;
+        double s0 = 0.0, s1 = 0.0;
+        int k = lane;
+        for (; k + 64 < nblk; k += 128) {
+            s0 += ci[k];
+            s1 += ci[k + 64];
+        }
+        if (k < nblk) s0 += ci[k];
+        double v = s0 + s1;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) c[i] = b[I.bstart + i] - v;
     }
     __syncthreads();
     // forward: L y = c
-    for (int b0 = 0; b0 < nbd; b0 += 32) {
-        const int bs = nbd - b0 < 32 ? nbd - b0 : 32;
+    for (int b0 = 0; b0 < nbd; b0 += kBB) {
+        const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
         if (tid < 64) {
             const int i = b0 + lane;
+            double l[kBB];
+#pragma unroll
+            for (int k = 0; k < kBB; k++) l[k] = (lane < bs && k < lane) ? Lb[pk(i, b0 + k)] : 0.0;
             double ci = lane < bs ? c[i] : 0.0;
-            for (int k = 0; k < bs - 1; k++) {
+#pragma unroll
+            for (int k = 0; k < kBB - 1; k++) {
                 const double xk = __shfl(ci, k);
-                if (lane > k && lane < bs) ci -= Lb[pk(i, b0 + k)] * xk;
+                ci -= l[k] * xk;
             }
             if (lane < bs) c[i] = ci;
         }
         __syncthreads();
         for (int i = b0 + bs + tid; i < nbd; i += kBorderThreads) {
             const double *li = Lb + pk(i, b0);
-            double s0 = 0.0, s1 = 0.0;
-            int k = 0;
-            for (; k + 2 <= bs; k += 2) {
-                s0 += li[k] * c[b0 + k];
-                s1 += li[k + 1] * c[b0 + k + 1];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBB; k += 4) {
+                if (k < bs) s0 += li[k] * c[b0 + k];
+                if (k + 1 < bs) s1 += li[k + 1] * c[b0 + k + 1];
+                if (k + 2 < bs) s2 += li[k + 2] * c[b0 + k + 2];
+                if (k + 3 < bs) s3 += li[k + 3] * c[b0 + k + 3];
             }
-            if (k < bs) s0 += li[k] * c[b0 + k];
-            c[i] -= s0 + s1;
+            c[i] -= (s0 + s1) + (s2 + s3);
         }
         __syncthreads();
     }
     for (int i = tid; i < nbd; i += kBorderThreads) c[i] /= Db[i];
     __syncthreads();
     // backward: L^T x = y, last block first
-    for (int b0 = ((nbd - 1) / 32) * 32; b0 >= 0; b0 -= 32) {
-        const int bs = nbd - b0 < 32 ? nbd - b0 : 32;
+    for (int b0 = ((nbd - 1) / kBB) * kBB; b0 >= 0; b0 -= kBB) {
+        const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
         if (tid < 64) {
+            double l[kBB];
+#pragma unroll
+            for (int i = 0; i < kBB; i++) l[i] = (i < bs && lane < i) ? Lb[pk(b0 + i, b0 + lane)] : 0.0;
             double cj = lane < bs ? c[b0 + lane] : 0.0;
-            for (int i = bs - 1; i > 0; i--) {
+#pragma unroll
+            for (int i = kBB - 1; i > 0; i--) {
                 const double xi = __shfl(cj, i);
-                if (lane < i) cj -= Lb[pk(b0 + i, b0 + lane)] * xi;
+                cj -= l[i] * xi;
             }
             if (lane < bs) c[b0 + lane] = cj;
         }
         __syncthreads();
         for (int j = tid; j < b0; j += kBorderThreads) {
-            double s0 = 0.0, s1 = 0.0;
-            int k = 0;
-            for (; k + 2 <= bs; k += 2) {
-                s0 += Lb[pk(b0 + k, j)] * c[b0 + k];
-                s1 += Lb[pk(b0 + k + 1, j)] * c[b0 + k + 1];
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+            for (int k = 0; k < kBB; k += 4) {
+                if (k < bs) s0 += Lb[pk(b0 + k, j)] * c[b0 + k];
+                if (k + 1 < bs) s1 += Lb[pk(b0 + k + 1, j)] * c[b0 + k + 1];
+                if (k + 2 < bs) s2 += Lb[pk(b0 + k + 2, j)] * c[b0 + k + 2];
+                if (k + 3 < bs) s3 += Lb[pk(b0 + k + 3, j)] * c[b0 + k + 3];
             }
-            if (k < bs) s0 += Lb[pk(b0 + k, j)] * c[b0 + k];
-            c[j] -= s0 + s1;
+            c[j] -= (s0 + s1) + (s2 + s3);
         }
         __syncthreads();
     }
     for (int i = tid; i < nbd; i += kBorderThreads) {
-        y[a.dint + i] = c[i];
-        x[a.bstart + i] = c[i];
+        y[a.dint + I.bd0 + i] = c[i];
+        x[I.bstart + i] = c[i];
     }
 }
 
-// backward gather of column p of a supernode: y_col -= sum_{i >= w} L(i, p) x_{row i}
+// backward gather of column p of a supernode: y_col -= sum_{i >= w} L(i, p) x_{row i},
+// in rounds of 8, 4, 2, 1 rows (row indices are uniform; border rows read the
+// border solution)
 __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
     const int wid = wave_id();
     if (wid >= nw) return;
@@ -900,30 +991,40 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, co
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
     const int n = T.n;
-    const int s = T.task_s[W.k], p = T.task_p[W.k];
-    const int f = T.sup_first[s], w = T.sup_first[s + 1] - f;
-    const int r = T.sup_rowptr[s + 1] - T.sup_rowptr[s];
-    const int32_t *R = T.sup_rows + T.sup_rowptr[s];
-    const double *Pc = a.lpan + T.lbase + W.bl + (int64_t(T.panel_off[s]) + int64_t(p) * r) * nb;
+    const int s = cs(T.task_s)[W.k], p = cs(T.task_p)[W.k];
+    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    const int32_t *__restrict__ R_ = T.sup_rows + cs(T.sup_rowptr)[s];
+    const double *__restrict__ Pc = a.lpan + T.lbase + W.bl + (int64_t(cs(T.panel_off)[s]) + int64_t(p) * r) * nb;
     double *yb = y + T.dbase + W.bl;
-    const double *xb = y + a.dint;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const double *xb = y + a.dint + T.bd0;
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) acc[u] = 0.0;
+    auto round = [&](auto R, int i) {
+        double q[R.value];
+#pragma unroll
+        for (int u = 0; u < R.value; u++) {
+            const int ri = cs(R_)[i + u];
+            const double *xp = ri < n ? yb + int64_t(ri) * nb : xb + (ri - n);
+            q[u] = Pc[int64_t(i + u) * nb] * *xp;
+        }
+#pragma unroll
+        for (int u = 0; u < R.value; u++) acc[u] += q[u];
+    };
     int i = w;
-    for (; i + 4 <= r; i += 4) {
-        const int r0 = R[i], r1 = R[i + 1], r2 = R[i + 2], r3 = R[i + 3];
-        s0 += Pc[int64_t(i) * nb] * (r0 < n ? yb[int64_t(r0) * nb] : xb[r0 - n]);
-        s1 += Pc[int64_t(i + 1) * nb] * (r1 < n ? yb[int64_t(r1) * nb] : xb[r1 - n]);
-        s2 += Pc[int64_t(i + 2) * nb] * (r2 < n ? yb[int64_t(r2) * nb] : xb[r2 - n]);
-        s3 += Pc[int64_t(i + 3) * nb] * (r3 < n ? yb[int64_t(r3) * nb] : xb[r3 - n]);
-    }
-    for (; i < r; i++) {
-        const int ri = R[i];
-        s0 += Pc[int64_t(i) * nb] * (ri < n ? yb[int64_t(ri) * nb] : xb[ri - n]);
-    }
-    if (W.on) yb[int64_t(f + p) * nb] -= (s0 + s1) + (s2 + s3);
+    for (; i + 8 <= r; i += 8) round(std::integral_constant<int, 8>(), i);
+    if (i + 4 <= r) { round(std::integral_constant<int, 4>(), i); i += 4; }
+    if (i + 2 <= r) { round(std::integral_constant<int, 2>(), i); i += 2; }
+    if (i < r) round(std::integral_constant<int, 1>(), i);
+    const double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    if (W.on) yb[int64_t(f + p) * nb] -= v;
 }
 
-// unit upper triangular solve with the transposed diagonal block
+// unit upper triangular solve with the transposed diagonal block:
+// x_k = y_k - sum_{j > k} L(j, k) x_j, taken right-looking from the last
+// column: once x_j is final, x_k -= L(j,k) x_j for every k < j (the loads
+// of L do not depend on x)
 __global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
     const int wid = wave_id();
     if (wid >= nw) return;
@@ -931,26 +1032,31 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, cons
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
     const int s = W.k;
-    const int f = T.sup_first[s], w = T.sup_first[s + 1] - f;
-    const int r = T.sup_rowptr[s + 1] - T.sup_rowptr[s];
-    const double *P = a.lpan + T.lbase + W.bl + int64_t(T.panel_off[s]) * nb;
+    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    const double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
     double *yb = y + T.dbase + W.bl + int64_t(f) * nb;
-    double x[kMaxW];
+    by_width(w, [&](auto Wc) {
+        constexpr int W_ = decltype(Wc)::value;
+        const int wl1 = w - 1;
+        double x[W_];
 #pragma unroll
-    for (int j = kMaxW - 1; j >= 0; j--) {
-        if (j < w) {
-            double v = yb[int64_t(j) * nb];
+        for (int j = 0; j < W_; j++) x[j] = yb[int64_t(j < w ? j : wl1) * nb];
 #pragma unroll
-            for (int k = 0; k < kMaxW; k++)
-                if (k > j && k < w) v -= P[(int64_t(j) * r + k) * nb] * x[k];
-            x[j] = v;
+        for (int j = W_ - 1; j > 0; j--) {
+            const int jc = j < w ? j : wl1;
+#pragma unroll
+            for (int k = 0; k < j; k++) {
+                const double l = P[(int64_t(k < w ? k : wl1) * r + jc) * nb];
+                x[k] -= (j < w ? l : 0.0) * x[j];
+            }
         }
-    }
-    if (W.on) {
+        if (W.on) {
 #pragma unroll
-        for (int j = 0; j < kMaxW - 1; j++)
-            if (j < w - 1) yb[int64_t(j) * nb] = x[j];
-    }
+            for (int j = 0; j < W_ - 1; j++)
+                if (j < w - 1) yb[int64_t(j) * nb] = x[j];
+        }
+    });
 }
 
 // ------------------------------------------------------------------ launchers
@@ -959,17 +1065,15 @@ static inline unsigned waves_grid(int nw) { return unsigned((nw + (kWG / 64) - 1
 static inline unsigned elems_grid(int64_t n) { return unsigned((n + 255) / 256); }
 
 hipError_t launch_assemble(const DevArgs &a, const double *z, const double *sig, double rho, hipStream_t st) {
-    const int64_t total = int64_t(a.nblk) * (a.nb + a.ng) + a.ng;
-    hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, z, sig, rho);
+    const int64_t total = a.asm_threads + a.gp_tot;
+    if (total) hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, z, sig, rho);
     return hipGetLastError();
 }
 
-hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, int64_t nnz_border,
-                         int64_t kcsc_border, hipStream_t st) {
-    const int64_t total = a.kint + nnz_border;
+hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, hipStream_t st) {
+    const int64_t total = a.kint + a.nbb_tot;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_values, dim3(elems_grid(total)), dim3(256), 0, st, a, src, dst, to_internal ? 1 : 0,
-                       nnz_border, kcsc_border);
+    hipLaunchKernelGGL(k_values, dim3(elems_grid(total)), dim3(256), 0, st, a, src, dst, to_internal ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -986,21 +1090,23 @@ hipError_t launch_schur(const DevArgs &a, const Work *ws, int nw, hipStream_t st
     return hipGetLastError();
 }
 
+size_t border_lds_bytes(int nbd) {
+    return size_t(kBB * kPS + kBB + (nbd > kBB ? nbd - kBB : 0) * kPS) * sizeof(double);
+}
+
 hipError_t launch_factor_border(const DevArgs &a, hipStream_t st) {
-    if (a.nbd > 0) {
-        const int64_t npk = int64_t(a.nbd) * (a.nbd + 1) / 2;
-        hipLaunchKernelGGL(k_border_sum, dim3(waves_grid(int(npk))), dim3(kWG), 0, st, a);
-        const int nt = (a.nbd + 3) / 4;
-        if (a.nbd <= kTileMaxB && nt * (nt + 1) / 2 <= 2 * kBorderThreads) {
-            hipLaunchKernelGGL(k_border_factor_tiles<2>, dim3(1), dim3(kBorderThreads), 0, st, a);
-        } else {
-            const size_t lbytes = size_t(npk) * sizeof(double);
-            const int use_lds = lbytes <= 150 * 1024 ? 1 : 0;
-            hipLaunchKernelGGL(k_border_factor, dim3(1), dim3(kBorderThreads), use_lds ? lbytes : 0, st, a, use_lds);
+    if (a.npk_tot > 0) {
+        hipLaunchKernelGGL(k_border_sum, dim3(waves_grid(int(a.npk_tot))), dim3(kWG), 0, st, a);
+        const size_t lbytes = border_lds_bytes(a.max_nbd);
+        if (lbytes > 65536) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_border_factor),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lbytes));
+            if (e != hipSuccess) return e;
         }
+        hipLaunchKernelGGL(k_border_factor, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
     }
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, a);
-    const int64_t ne = a.dint + a.nbd;
+    const int64_t ne = a.dint + a.nbd_tot;
     const unsigned sg = unsigned(ne / 256 / 16 + 1 < 1024 ? ne / 256 / 16 + 1 : 1024);
     hipLaunchKernelGGL(k_status, dim3(sg), dim3(256), 0, st, a);
     return hipGetLastError();
@@ -1026,8 +1132,8 @@ hipError_t launch_solve_bpart(const DevArgs &a, const double *y, double *cpart, 
 
 hipError_t launch_solve_border(const DevArgs &a, const double *b, double *x, double *y, const double *cpart,
                                hipStream_t st) {
-    if (a.nbd > 0)
-        hipLaunchKernelGGL(k_sol_border, dim3(1), dim3(kBorderThreads), size_t(a.nbd) * sizeof(double), st, a, b, x,
+    if (a.max_nbd > 0)
+        hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), size_t(a.max_nbd) * sizeof(double), st, a, b, x,
                            y, cpart);
     return hipGetLastError();
 }

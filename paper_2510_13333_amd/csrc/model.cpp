@@ -167,70 +167,84 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
             used[net.out[k]] = 1;
         }
     }
+    // append one instance: its templates, blocks and border
     h.from_network = true;
-    h.nb = net.nb; h.nl = net.nl; h.ng = net.ng; h.flags = nw->flags;
-    h.nblk = net.K + 1;
-    h.nbd = net.K == 0 ? 0 : net.ng * (net.pvpq ? 2 : 1);
-    h.gen_c2.assign(nw->gen_c2, nw->gen_c2 + net.ng);
-    h.br_r.assign(nw->br_r, nw->br_r + net.nl);
-    h.br_x.assign(nw->br_x, nw->br_x + net.nl);
+    h.inst.emplace_back();
+    Inst &I = h.inst.back();
+    I.nb = net.nb; I.nl = net.nl; I.ng = net.ng; I.flags = nw->flags;
+    I.blk0 = h.nblk;
+    I.nblk = net.K + 1;
+    I.nbd = net.K == 0 ? 0 : net.ng * (net.pvpq ? 2 : 1);
+    I.gen_c2.assign(nw->gen_c2, nw->gen_c2 + net.ng);
+    I.br_r.assign(nw->br_r, nw->br_r + net.nl);
+    I.br_x.assign(nw->br_x, nw->br_x + net.nl);
     std::vector<int> kinds;
     if (net.K == 0) kinds = {T_SINGLE};
     else if (!net.pvpq) kinds = {T_PLAIN};
     else kinds = {T_PVPQ_BASE, T_PVPQ_CONT};
-    h.tmpl.assign(kinds.size(), Template());
-    h.block_tmpl.assign(h.nblk, 0);
-    h.block_outage.assign(h.nblk, -1);
-    for (int k = 1; k < h.nblk; k++) {
-        h.block_tmpl[k] = net.pvpq ? 1 : 0;
-        h.block_outage[k] = net.out[k - 1];
+    const int t0 = int(h.tmpl.size());
+    I.t0 = t0;
+    I.nt = int(kinds.size());
+    h.tmpl.resize(t0 + kinds.size());
+    for (int k = 0; k < I.nblk; k++) {
+        h.block_tmpl.push_back(t0 + (k > 0 && net.pvpq ? 1 : 0));
+        h.block_outage.push_back(k > 0 ? net.out[k - 1] : -1);
+        h.block_inst.push_back(int32_t(h.inst.size() - 1));
     }
+    h.nblk += I.nblk;
     PairList border_pairs;
     std::vector<Local> locs(kinds.size());
-    for (size_t ti = 0; ti < kinds.size(); ti++) {
-        Template &t = h.tmpl[ti];
+    for (size_t q = 0; q < kinds.size(); q++) {
+        Template &t = h.tmpl[t0 + q];
         int n, nprim;
-        layout(net, kinds[ti], locs[ti], n, nprim, t.is_primal);
+        layout(net, kinds[q], locs[q], n, nprim, t.is_primal);
+        t.inst = int(h.inst.size()) - 1;
         t.n = n;
         t.nprim = nprim;
-        t.pvpq_rows = kinds[ti] == T_PVPQ_CONT;
-        t.pg_local = kinds[ti] == T_SINGLE;
+        t.pvpq_rows = kinds[q] == T_PVPQ_CONT;
+        t.pg_local = kinds[q] == T_SINGLE;
         PairList tp;
-        enumerate(net, kinds[ti], locs[ti], n, tp, border_pairs);
+        enumerate(net, kinds[q], locs[q], n, tp, border_pairs);
         to_csc(tp, n, t.colptr, t.rowind);
     }
-    for (int b = 0; b < h.nbd; b++) border_pairs.emplace_back(b, b);
-    to_csc(border_pairs, h.nbd, h.bcolptr, h.browind);
-    h.border_primal.assign(h.nbd, 1);
-    h.border_pg.assign(net.ng, -1);
-    if (h.nbd)
-        for (int g = 0; g < net.ng; g++) h.border_pg[g] = g;
-    // block offsets and K value bases
-    h.block_off.assign(h.nblk + 1, 0);
-    h.kbase.assign(h.nblk + 1, 0);
-    for (int k = 0; k < h.nblk; k++) {
+    for (int b = 0; b < I.nbd; b++) border_pairs.emplace_back(b, b);
+    to_csc(border_pairs, I.nbd, I.bcolptr, I.browind);
+    I.border_primal.assign(I.nbd, 1);
+    I.border_pg.assign(net.ng, -1);
+    if (I.nbd)
+        for (int g = 0; g < net.ng; g++) I.border_pg[g] = g;
+    // global columns and public CSC positions (layout order: the blocks, then the border)
+    I.col0 = h.N;
+    int64_t col = h.N;
+    for (int k = I.blk0; k < h.nblk; k++) {
         const Template &t = h.tmpl[h.block_tmpl[k]];
-        h.block_off[k + 1] = h.block_off[k] + t.n;
-        h.kbase[k + 1] = h.kbase[k] + t.colptr[t.n];
+        h.block_col0.push_back(col);
+        h.kbase.push_back(h.nnzK);
+        col += t.n;
+        h.nnzK += t.colptr[t.n];
+        I.nprimal += t.nprim;
     }
-    h.N = h.block_off[h.nblk] + h.nbd;
-    h.nnzK = h.kbase[h.nblk] + (h.nbd ? h.bcolptr[h.nbd] : 0);
-    h.nprimal = h.nbd;
-    for (int k = 0; k < h.nblk; k++) h.nprimal += h.tmpl[h.block_tmpl[k]].nprim;
-    h.kbb_pos.assign(size_t(h.nbd) * h.nbd, -1);
-    for (int c = 0; c < h.nbd; c++)
-        for (int64_t p = h.bcolptr[c]; p < h.bcolptr[c + 1]; p++) h.kbb_pos[size_t(h.browind[p]) * h.nbd + c] = int32_t(p);
+    I.bstart = col;
+    I.kcsc_border = h.nnzK;
+    I.N = col + I.nbd - I.col0;
+    I.nprimal += I.nbd;
+    h.N += I.N;
+    h.nnzK += I.nbb();
+    h.nprimal += I.nprimal;
+    I.kbb_pos.assign(size_t(I.nbd) * I.nbd, -1);
+    for (int c = 0; c < I.nbd; c++)
+        for (int64_t p = I.bcolptr[c]; p < I.bcolptr[c + 1]; p++) I.kbb_pos[size_t(I.browind[p]) * I.nbd + c] = int32_t(p);
 
     // assembly tables
-    for (size_t ti = 0; ti < kinds.size(); ti++) {
-        Template &t = h.tmpl[ti];
-        const Local &L = locs[ti];
+    for (size_t q = 0; q < kinds.size(); q++) {
+        Template &t = h.tmpl[t0 + q];
+        const Local &L = locs[q];
         const int n = t.n;
         auto slot = [&](int32_t a, int32_t b) -> int32_t {
             if (a < 0 || b < 0) return -1;
             int32_t r = std::max(a, b), c = std::min(a, b);
             if (c >= n) {
-                int32_t p = find_pos(h.bcolptr, h.browind, r - n, c - n);
+                int32_t p = find_pos(I.bcolptr, I.browind, r - n, c - n);
                 return p < 0 ? -1 : (kBorderFlag | p);
             }
             return find_pos(t.colptr, t.rowind, r, c);
@@ -347,14 +361,22 @@ int build_pattern_model(int64_t N, int nblk, const int64_t *block_off, const int
     for (int b = 0; b < nblk; b++)
         if (block_off[b + 1] <= block_off[b]) { err = "empty block"; return NCL_ERR_ARG; }
     const int64_t bstart = block_off[nblk];
-    if (N - bstart > 4096) { err = "border too large"; return NCL_ERR_ARG; }
+    if (N - bstart > NCL_MAX_BORDER) { err = "border too large"; return NCL_ERR_ARG; }
     h.from_network = false;
+    h.inst.assign(1, Inst());
+    Inst &I = h.inst[0];
+    I.blk0 = 0;
+    I.nblk = nblk;
+    I.nbd = int(N - bstart);
+    I.col0 = 0;
+    I.N = N;
+    I.bstart = bstart;
     h.nblk = nblk;
-    h.nbd = int(N - bstart);
-    h.block_off.assign(block_off, block_off + nblk + 1);
+    h.block_col0.assign(block_off, block_off + nblk);
     h.block_outage.assign(nblk, -1);
     h.block_tmpl.assign(nblk, -1);
-    h.kbase.assign(nblk + 1, 0);
+    h.block_inst.assign(nblk, 0);
+    h.kbase.assign(nblk, 0);
     h.N = N;
     // validate the pattern: lower, sorted, diagonal present, no block coupling
     for (int64_t j = 0; j < N; j++) {
@@ -398,21 +420,25 @@ int build_pattern_model(int64_t N, int nblk, const int64_t *block_off, const int
             found = int(h.tmpl.size()) - 1;
         }
         h.block_tmpl[b] = found;
-        h.kbase[b + 1] = h.kbase[b] + (colptr[block_off[b + 1]] - colptr[o]);
+        h.kbase[b] = colptr[o];
     }
-    h.bcolptr.assign(h.nbd + 1, 0);
-    for (int c = 0; c < h.nbd; c++) h.bcolptr[c + 1] = h.bcolptr[c] + (colptr[bstart + c + 1] - colptr[bstart + c]);
-    h.browind.resize(h.bcolptr[h.nbd]);
-    for (int c = 0; c < h.nbd; c++)
+    I.t0 = 0;
+    I.nt = int(h.tmpl.size());
+    I.bcolptr.assign(I.nbd + 1, 0);
+    for (int c = 0; c < I.nbd; c++) I.bcolptr[c + 1] = I.bcolptr[c] + (colptr[bstart + c + 1] - colptr[bstart + c]);
+    I.browind.resize(I.bcolptr[I.nbd]);
+    for (int c = 0; c < I.nbd; c++)
         for (int64_t p = colptr[bstart + c]; p < colptr[bstart + c + 1]; p++)
-            h.browind[h.bcolptr[c] + (p - colptr[bstart + c])] = int32_t(rowind[p] - bstart);
-    h.border_primal.assign(is_primal + bstart, is_primal + N);
+            I.browind[I.bcolptr[c] + (p - colptr[bstart + c])] = int32_t(rowind[p] - bstart);
+    I.border_primal.assign(is_primal + bstart, is_primal + N);
+    I.kcsc_border = colptr[bstart];
     h.nnzK = colptr[N];
     h.nprimal = 0;
     for (int64_t j = 0; j < N; j++) h.nprimal += is_primal[j] ? 1 : 0;
-    h.kbb_pos.assign(size_t(h.nbd) * h.nbd, -1);
-    for (int c = 0; c < h.nbd; c++)
-        for (int64_t p = h.bcolptr[c]; p < h.bcolptr[c + 1]; p++) h.kbb_pos[size_t(h.browind[p]) * h.nbd + c] = int32_t(p);
+    I.nprimal = h.nprimal;
+    I.kbb_pos.assign(size_t(I.nbd) * I.nbd, -1);
+    for (int c = 0; c < I.nbd; c++)
+        for (int64_t p = I.bcolptr[c]; p < I.bcolptr[c + 1]; p++) I.kbb_pos[size_t(I.browind[p]) * I.nbd + c] = int32_t(p);
     return NCL_OK;
 }
 

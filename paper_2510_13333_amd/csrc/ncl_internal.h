@@ -24,7 +24,7 @@ constexpr int32_t kBorderFlag = int32_t(1u << 30);   // slot refers to the borde
 // ---------------------------------------------------------------- device tables
 
 // One descendant supernode d's contribution to one entry (row, column c) of a
-// panel: sum_k L_d[row, k] d_k L_d[c, k], or (forward solve) to one column.
+// panel: sum_k L_d[row, k] d_k L_d[c, k] (host-side; flattened into Terms).
 struct CItem {
     int32_t ioff;    // panel element of L_d[row, 0] (template-relative)
     int32_t coff;    // panel element of L_d[c, 0]
@@ -32,9 +32,12 @@ struct CItem {
     int32_t meta;    // ld (16 bits) | wd << 16
 };
 
-// Common panels of two border rows (border Schur contribution).
-struct SItem {
-    int32_t s, pi, pj;
+// One product of an update sum: L[a] * d[k] * L[c] (factor, border Schur) or
+// L[a] * y[k] (solves), with a, c panel elements and k a column, all
+// template-relative.  Each entry's terms are contiguous, so that a kernel can
+// keep many independent loads in flight.
+struct Term {
+    int32_t a, c, k, pad;
 };
 
 // A unit of work of one launch: template (high 16 bits) and block group
@@ -65,14 +68,19 @@ enum BusIdx { BI_VM, BI_VA, BI_P, BI_Q, BI_N };
 enum GenIdx { GI_BUS, GI_QG, GI_PG, GI_NUP, GI_NUM, GI_SUP, GI_SLO, GI_LIN, GI_DUP, GI_DLO, GI_CUP, GI_CLO, GI_VM0, GI_N };
 
 struct TemplDev {
-    int32_t n, nsup, nblk, nbd;     // columns, supernodes, blocks using the template, border size
+    int32_t n, nsup, nblk, nbd;     // columns, supernodes, blocks using the template, its instance's border size
     int64_t kbase;                 // interleaved K values (nnz * nblk)
     int64_t lbase;                 // interleaved panels (panel_size * nblk)
     int64_t dbase;                 // interleaved pivots and solve vectors (n * nblk)
     int32_t nnz;                   // K entries of one block
     int32_t pvpq_rows;             // this template has the complementarity rows
     int32_t has_pg_local;          // single-block network: pg inside the block
-    int32_t pad;
+    int32_t inst;                  // instance (network) the template belongs to
+    int32_t nbus, ngen;            // network sizes (assembly threads per block)
+    int64_t abase;                 // first assembly thread of the template
+    int64_t bd0;                   // the instance's border pivots / solution at dint + bd0
+    const double *br_r, *br_x;     // the instance's branch data
+    const double *gen_c2;
     const int32_t *blocks;         // [nblk] global block ids
     // supernodes (block-local factor numbering; border rows are n + b)
     const int32_t *sup_first;      // [nsup+1]
@@ -85,15 +93,14 @@ struct TemplDev {
     const int32_t *task_cbase;     // [ntask+1] first entry of each task
     const int32_t *ent_kpos;       // [nent] K value of the entry or -1
     const int32_t *ent_out;        // [nent] panel element of the entry
-    const int32_t *ent_iptr;       // [nent+1] gather items of each entry
-    const CItem *citems;
-    // border rows: supernodes whose panel holds border row b, ascending
-    const int32_t *bpath_ptr;      // [nbd+1]
-    const int32_t *bpath_s;
-    const int32_t *bpath_pos;
-    // border Schur items of each packed border entry
-    const int32_t *sitem_ptr;      // [nbd*(nbd+1)/2 + 1]
-    const SItem *sitems;
+    const int32_t *ent_tptr;       // [nent+1] update terms of each entry
+    const Term *terms;
+    // border rows: terms L[b, k] y_k of the border right-hand side
+    const int32_t *bterm_ptr;      // [nbd+1]
+    const Term *bterms;
+    // border Schur terms of each packed border entry
+    const int32_t *sterm_ptr;      // [nbd*(nbd+1)/2 + 1]
+    const Term *sterms;
     // assembly
     const int32_t *bus_idx;        // [nb][BI_N]
     const int32_t *bus_slot;       // [nb][BS_N]
@@ -105,6 +112,24 @@ struct TemplDev {
     const int32_t *gen_slot;       // [ng][GS_N]
     const int32_t *perm;           // [n] factor order -> layout-local
     const uint8_t *col_primal;     // [n] expected pivot sign (1: positive) in factor order
+};
+
+// Per-instance (per-network) border data of a batch.
+struct InstDev {
+    int32_t nbd, nblk, blk0, ng;   // border size, blocks, first block, generators
+    int64_t bstart;                // first global column of the border
+    int64_t kbb0;                  // K_bb values at kval[kint + kbb0 ...]
+    int64_t sbb0;                  // packed border matrix / factor at sbb[sbb0 ...]
+    int64_t bd0;                   // border pivots at dval[dint + bd0 ...]
+    int64_t sp0;                   // border Schur partials at spart[sp0 + e * nblk + block]
+    int64_t cp0;                   // border right-hand-side partials at cpart[cp0 + b * nblk + block]
+    int64_t npk0;                  // first packed border entry (all instances together)
+    int64_t gp0;                   // first border-pg assembly thread
+    int64_t kcsc_border;           // first public CSC value of the border
+    int64_t nbb;                   // K_bb values
+    const int32_t *kbb_pos;        // [nbd*nbd]
+    const int32_t *border_pg;      // [ng]
+    const double *gen_c2;          // [ng]
 };
 
 struct BlockDev {
@@ -119,6 +144,7 @@ struct BlockDev {
 // ---------------------------------------------------------------- host symbolic
 
 struct Template {
+    int inst = 0;                  // instance (network) of the template
     int n = 0;                     // block columns
     int nprim = 0;
     bool pvpq_rows = false;
@@ -139,11 +165,9 @@ struct Template {
     // schedule
     int nlev = 0;
     std::vector<int32_t> level;         // [nsup]
-    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_iptr, bpath_ptr, bpath_s,
-        bpath_pos, sitem_ptr;
+    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr, bterm_ptr, sterm_ptr;
     std::vector<std::vector<int32_t>> lev_tasks;   // row tasks of each level
-    std::vector<CItem> citems;
-    std::vector<SItem> sitems;
+    std::vector<Term> terms, bterms, sterms;
 };
 
 // Work lists of every launch (all templates together), per level.
@@ -162,21 +186,22 @@ struct Schedule {
     std::vector<Work> schur;                            // border entries x block groups
 };
 
-struct Handle {
-    bool from_network = false;
-    int64_t N = 0, nprimal = 0;
-    int nblk = 0, nbd = 0;
+// One network (or one user pattern) of a handle: its blocks, its dense
+// first-stage border and the border's symbolic structure.
+struct Inst {
     int nb = 0, nl = 0, ng = 0;
     uint32_t flags = 0;
-    std::vector<int64_t> block_off;      // [nblk+1]
-    std::vector<int32_t> block_tmpl, block_outage, block_bl;
-    std::vector<Template> tmpl;
     std::vector<double> gen_c2, br_r, br_x;
-    std::vector<int32_t> border_pg;      // [ng] border index of pg_g
-    // K pattern (public lower CSC in layout order)
-    std::vector<int64_t> kbase;          // [nblk+1]: first value of each block, then of the border
-    int64_t nnzK = 0;
-    std::vector<int64_t> bcolptr;        // border K_bb lower CSC (border-local)
+    std::vector<int32_t> border_pg;      // [ng] border index of pg_g (or -1)
+    int blk0 = 0, nblk = 0;              // global block range
+    int t0 = 0, nt = 0;                  // template range
+    int nbd = 0;
+    int64_t col0 = 0, N = 0;             // first global column, columns of the instance
+    int64_t bstart = 0;                  // first global column of the border
+    int64_t kcsc_border = 0;             // first public CSC value of the border
+    int64_t nprimal = 0;
+    // border K_bb pattern (lower CSC, border-local) and pivot signs
+    std::vector<int64_t> bcolptr;
     std::vector<int32_t> browind;
     std::vector<int32_t> kbb_pos;        // [nbd*nbd]
     std::vector<uint8_t> border_primal;
@@ -185,10 +210,30 @@ struct Handle {
     std::vector<int64_t> bcolcount;
     std::vector<int32_t> blp, bli;
     std::vector<int32_t> bsup;
+    // offsets in the concatenated device border arrays
+    int64_t kbb0 = 0, sbb0 = 0, bd0 = 0, sp0 = 0, cp0 = 0, npk0 = 0, gp0 = 0;
+    int64_t nbb() const { return nbd ? bcolptr[nbd] : 0; }
+    int64_t npk() const { return int64_t(nbd) * (nbd + 1) / 2; }
+};
+
+struct Handle {
+    bool from_network = false;
+    int64_t N = 0, nprimal = 0;
+    int nblk = 0;
+    std::vector<Inst> inst;
+    std::vector<int64_t> block_col0;     // [nblk] first global column of each block
+    std::vector<int32_t> block_tmpl, block_outage, block_bl, block_inst;
+    std::vector<Template> tmpl;
+    std::vector<int64_t> kbase;          // [nblk] first public CSC value of each block
+    int64_t nnzK = 0;
+    // totals over instances
+    int64_t nbd_tot = 0, nbb_tot = 0, npk_tot = 0, sp_tot = 0, cp_tot = 0, gp_tot = 0;
+    int max_nbd = 0;
     // sizes
     int64_t nnzL = 0, nsuper = 0, npanel = 0;
     int64_t kint = 0, lint = 0, dint = 0;   // interleaved K values, panels, pivots (all templates)
-    std::vector<int64_t> t_kbase, t_lbase, t_dbase;
+    int64_t asm_threads = 0;                // template assembly threads (border pg threads follow)
+    std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase;
     Schedule sched;
     // numeric state
     int64_t nrhs_max = 0;
@@ -198,15 +243,14 @@ struct Handle {
     bool blocks_done = false;
     bool bound = false;
     struct Dev {
-        double *kval = nullptr;          // interleaved K, then border K_bb (CSC)
+        double *kval = nullptr;          // interleaved K, then the border K_bb values of every instance
         double *lpan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
-               *cpart = nullptr, *dmm = nullptr;
+               *cpart = nullptr;
         int64_t *stat = nullptr;
         TemplDev *tmpl = nullptr;
         BlockDev *blk = nullptr;
+        InstDev *inst = nullptr;
         Work *work = nullptr;            // all work lists
-        int32_t *kbb_pos = nullptr, *border_pg = nullptr;
-        double *gen_c2 = nullptr, *br_r = nullptr, *br_x = nullptr;
         const uint8_t *bprim = nullptr;
     } d;
     // offsets of each work list inside d.work
@@ -219,7 +263,7 @@ int build_pattern_model(int64_t N, int nblk, const int64_t *block_off, const int
                         const uint8_t *is_primal, Handle &h, std::string &err);
 // symbolic.cpp
 int analyze_template(Template &t, int nbd, int maxw, int znum, int zden);
-int analyze_border(Handle &h, int maxw, int znum, int zden);
+int analyze_border(Handle &h, Inst &I, int maxw, int znum, int zden);
 // schedule.cpp
 int build_template_schedule(Template &t, int nbd);
 int build_schedule(Handle &h);

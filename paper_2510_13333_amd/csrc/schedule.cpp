@@ -112,13 +112,10 @@ int build_template_schedule(Template &t, int nbd) {
             }
         }
     }
-    t.ent_iptr.assign(nent + 1, 0);
-    for (int e = 0; e < nent; e++) t.ent_iptr[e + 1] = t.ent_iptr[e] + int32_t(items[e].size());
-    t.citems.clear();
-    t.citems.reserve(t.ent_iptr[nent]);
-    for (auto &v : items) t.citems.insert(t.citems.end(), v.begin(), v.end());
+    std::vector<CItem> citems;
+    for (auto &v : items) citems.insert(citems.end(), v.begin(), v.end());
     // every element a kernel dereferences stays inside its panel
-    for (const CItem &g : t.citems) {
+    for (const CItem &g : citems) {
         const int ld = g.meta & 0xffff, wd = (g.meta >> 16) & 0xff;
         const int d = (g.dcol >= 0 && g.dcol < n) ? col2sup[g.dcol] : -1;
         if (d < 0 || t.sup[d] != g.dcol || wd != t.sup[d + 1] - t.sup[d] || ld != t.srp[d + 1] - t.srp[d])
@@ -129,38 +126,55 @@ int build_template_schedule(Template &t, int nbd) {
     }
     for (int e = 0; e < nent; e++)
         if (t.ent_kpos[e] >= int64_t(t.colptr[n])) return NCL_ERR_ARG;
-    // border rows: the supernodes whose panel holds them
+    // flatten: one term per (descendant, column of the descendant)
+    const int64_t kTermMax = INT32_MAX;
+    t.ent_tptr.assign(nent + 1, 0);
+    t.terms.clear();
+    for (int e = 0; e < nent; e++) {
+        for (const CItem &g : items[e]) {
+            const int ld = g.meta & 0xffff, wd = (g.meta >> 16) & 0xff;
+            for (int k = 0; k < wd; k++) t.terms.push_back(Term{g.ioff + k * ld, g.coff + k * ld, g.dcol + k, 0});
+        }
+        if (int64_t(t.terms.size()) > kTermMax) return NCL_ERR_ARG;
+        t.ent_tptr[e + 1] = int32_t(t.terms.size());
+    }
+    items.clear();
+    items.shrink_to_fit();
+    // border rows: the supernodes whose panel holds them, ascending
     std::vector<std::vector<std::pair<int32_t, int32_t>>> bp(nbd);
     for (int s = 0; s < ns; s++)
         for (int p = t.srp[s]; p < t.srp[s + 1]; p++)
             if (t.sri[p] >= n) bp[t.sri[p] - n].push_back({s, p - t.srp[s]});
-    t.bpath_ptr.assign(nbd + 1, 0);
-    t.bpath_s.clear();
-    t.bpath_pos.clear();
+    auto push_cols = [&](std::vector<Term> &out, int s, int pi, int pj) {
+        const int r = t.srp[s + 1] - t.srp[s], w = t.sup[s + 1] - t.sup[s];
+        for (int k = 0; k < w; k++)
+            out.push_back(Term{t.panel_off[s] + pi + k * r, t.panel_off[s] + pj + k * r, t.sup[s] + k, 0});
+    };
+    // border right-hand side terms: L[b, k] over the columns k of those panels
+    t.bterm_ptr.assign(nbd + 1, 0);
+    t.bterms.clear();
     for (int b = 0; b < nbd; b++) {
-        for (auto &x : bp[b]) {
-            t.bpath_s.push_back(x.first);
-            t.bpath_pos.push_back(x.second);
-        }
-        t.bpath_ptr[b + 1] = int32_t(t.bpath_s.size());
+        for (auto &x : bp[b]) push_cols(t.bterms, x.first, x.second, x.second);
+        t.bterm_ptr[b + 1] = int32_t(t.bterms.size());
     }
-    // border Schur items: common panels of each pair of border rows
+    // border Schur terms: the common panels of each pair of border rows
     const int64_t npk = int64_t(nbd) * (nbd + 1) / 2;
-    t.sitem_ptr.assign(npk + 1, 0);
-    t.sitems.clear();
+    t.sterm_ptr.assign(npk + 1, 0);
+    t.sterms.clear();
     int64_t e = 0;
     for (int i = 0; i < nbd; i++)
         for (int j = 0; j <= i; j++, e++) {
             size_t a = 0, b = 0;
             while (a < bp[i].size() && b < bp[j].size()) {
                 if (bp[i][a].first == bp[j][b].first) {
-                    t.sitems.push_back(SItem{bp[i][a].first, bp[i][a].second, bp[j][b].second});
+                    push_cols(t.sterms, bp[i][a].first, bp[i][a].second, bp[j][b].second);
                     a++;
                     b++;
                 } else if (bp[i][a].first < bp[j][b].first) a++;
                 else b++;
             }
-            t.sitem_ptr[e + 1] = int32_t(t.sitems.size());
+            if (int64_t(t.sterms.size()) > kTermMax) return NCL_ERR_ARG;
+            t.sterm_ptr[e + 1] = int32_t(t.sterms.size());
         }
     return NCL_OK;
 }
@@ -171,16 +185,19 @@ int build_schedule(Handle &h) {
     h.t_kbase.assign(h.tmpl.size(), 0);
     h.t_lbase.assign(h.tmpl.size(), 0);
     h.t_dbase.assign(h.tmpl.size(), 0);
-    h.kint = h.lint = h.dint = 0;
+    h.t_abase.assign(h.tmpl.size(), 0);
+    h.kint = h.lint = h.dint = h.asm_threads = 0;
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int64_t nb = int64_t(t.blocks.size());
         h.t_kbase[ti] = h.kint;
         h.t_lbase[ti] = h.lint;
         h.t_dbase[ti] = h.dint;
+        h.t_abase[ti] = h.asm_threads;
         h.kint += t.colptr[t.n] * nb;
         h.lint += int64_t(t.panel_off.back()) * nb;
         h.dint += int64_t(t.n) * nb;
+        if (h.from_network) h.asm_threads += nb * (h.inst[t.inst].nb + h.inst[t.inst].ng);
         S.nlev = std::max(S.nlev, t.nlev);
     }
     if (h.tmpl.size() > 32767) return NCL_ERR_ARG;
@@ -210,7 +227,7 @@ int build_schedule(Handle &h) {
                 if (p < w) {
                     // the diagonal entry's items are exactly the descendants holding this row
                     const int e = t.task_cbase[k] + p;
-                    if (t.ent_iptr[e + 1] > t.ent_iptr[e])
+                    if (t.ent_tptr[e + 1] > t.ent_tptr[e])
                         for (int g = 0; g < ng64; g++) S.f.push_back(Work{tg(ti, g), k});
                     for (int g = 0; g < ng64; g++) S.g.push_back(Work{tg(ti, g), k});
                 }
@@ -228,11 +245,12 @@ int build_schedule(Handle &h) {
         S.d_ptr.push_back(int32_t(S.d.size()));
         S.g_ptr.push_back(int32_t(S.g.size()));
     }
-    const int64_t npk = int64_t(h.nbd) * (h.nbd + 1) / 2;
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
+        const int nbd = h.inst[t.inst].nbd;
+        const int64_t npk = int64_t(nbd) * (nbd + 1) / 2;
         const int ng64 = groups(t, 64);
-        for (int b = 0; b < h.nbd; b++)
+        for (int b = 0; b < nbd; b++)
             for (int g = 0; g < ng64; g++) S.bpart.push_back(Work{tg(ti, g), b});
         for (int64_t e = 0; e < npk; e++)
             for (int g = 0; g < ng64; g++) S.schur.push_back(Work{tg(ti, g), int32_t(e)});

@@ -212,22 +212,22 @@ int analyze_template(Template &t, int nbd, int maxw, int znum, int zden) {
     return NCL_OK;
 }
 
-int analyze_border(Handle &h, int maxw, int znum, int zden) {
-    const int nbd = h.nbd;
-    h.bparent.assign(nbd, -1);
-    h.bcolcount.assign(nbd, 1);
-    h.blp.assign(nbd + 1, 0);
-    h.bli.clear();
-    h.bsup.clear();
+int analyze_border(Handle &h, Inst &I, int maxw, int znum, int zden) {
+    const int nbd = I.nbd;
+    I.bparent.assign(nbd, -1);
+    I.bcolcount.assign(nbd, 1);
+    I.blp.assign(nbd + 1, 0);
+    I.bli.clear();
+    I.bsup.clear();
     if (nbd == 0) return NCL_OK;
     // border rows of each template's roots, and how many blocks use each template
     std::vector<int> uses(h.tmpl.size(), 0);
-    for (int b = 0; b < h.nblk; b++) uses[h.block_tmpl[b]]++;
+    for (int b = I.blk0; b < I.blk0 + I.nblk; b++) uses[h.block_tmpl[b]]++;
     std::vector<std::vector<std::vector<int32_t>>> rootrows(h.tmpl.size());   // per template, per root
     std::vector<std::vector<int32_t>> root_kids(nbd);      // (template, root) -> child of border column
     std::vector<int64_t> nchild(nbd, 0);
     std::vector<std::vector<std::pair<int, int>>> kids(nbd);
-    for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
+    for (size_t ti = size_t(I.t0); ti < size_t(I.t0 + I.nt); ti++) {
         const Template &t = h.tmpl[ti];
         for (int j = 0; j < t.n; j++) {
             if (t.parent[j] >= 0) continue;
@@ -245,24 +245,24 @@ int analyze_border(Handle &h, int maxw, int znum, int zden) {
     for (int b = 0; b < nbd; b++) {
         buf.clear();
         mark[b] = b;
-        for (int64_t p = h.bcolptr[b]; p < h.bcolptr[b + 1]; p++) {
-            int32_t i = h.browind[p];
+        for (int64_t p = I.bcolptr[b]; p < I.bcolptr[b + 1]; p++) {
+            int32_t i = I.browind[p];
             if (i > b && mark[i] != b) { mark[i] = b; buf.push_back(i); }
         }
         for (auto &k : kids[b])
             for (int32_t i : rootrows[k.first][k.second])
                 if (i > b && mark[i] != b) { mark[i] = b; buf.push_back(i); }
         for (int32_t c = head[b]; c >= 0; c = next[c])
-            for (int32_t p = h.blp[c]; p < h.blp[c + 1]; p++) {
-                int32_t i = h.bli[p];
+            for (int32_t p = I.blp[c]; p < I.blp[c + 1]; p++) {
+                int32_t i = I.bli[p];
                 if (i > b && mark[i] != b) { mark[i] = b; buf.push_back(i); }
             }
         std::sort(buf.begin(), buf.end());
-        h.bli.insert(h.bli.end(), buf.begin(), buf.end());
-        h.blp[b + 1] = int32_t(h.bli.size());
-        h.bcolcount[b] = int64_t(buf.size()) + 1;
+        I.bli.insert(I.bli.end(), buf.begin(), buf.end());
+        I.blp[b + 1] = int32_t(I.bli.size());
+        I.bcolcount[b] = int64_t(buf.size()) + 1;
         if (!buf.empty()) {
-            h.bparent[b] = buf[0];
+            I.bparent[b] = buf[0];
             next[b] = head[buf[0]];
             head[buf[0]] = b;
             nchild[buf[0]]++;
@@ -271,7 +271,7 @@ int analyze_border(Handle &h, int maxw, int znum, int zden) {
     std::vector<int32_t> fs{0};
     int run = 1;
     for (int j = 0; j + 1 < nbd; j++) {
-        bool join = h.bparent[j] == j + 1 && h.bcolcount[j] == h.bcolcount[j + 1] + 1 && nchild[j + 1] == 1 && run < kMaxW;
+        bool join = I.bparent[j] == j + 1 && I.bcolcount[j] == I.bcolcount[j + 1] + 1 && nchild[j + 1] == 1 && run < kMaxW;
         if (join) run++;
         else { fs.push_back(j + 1); run = 1; }
     }
@@ -282,14 +282,14 @@ int analyze_border(Handle &h, int maxw, int znum, int zden) {
     for (size_t q = 1; q + 1 < fs.size(); q++) {
         int32_t pf = fs[q], pl = fs[q + 1] - 1;
         int64_t w = pl - cf + 1;
-        bool ok = h.bparent[cl] == pf && w <= maxw && w <= kMaxW;
+        bool ok = I.bparent[cl] == pf && w <= maxw && w <= kMaxW;
         if (ok) {
             stamp++;
             int64_t off = 0, truenz = 0;
             for (int32_t j = cf; j <= pl; j++) {
-                truenz += h.bcolcount[j];
-                for (int32_t p = h.blp[j]; p < h.blp[j + 1]; p++) {
-                    int32_t i = h.bli[p];
+                truenz += I.bcolcount[j];
+                for (int32_t p = I.blp[j]; p < I.blp[j + 1]; p++) {
+                    int32_t i = I.bli[p];
                     if (i > pl && rmark[i] != stamp) { rmark[i] = stamp; off++; }
                 }
             }
@@ -298,13 +298,13 @@ int analyze_border(Handle &h, int maxw, int znum, int zden) {
         }
         if (ok) cl = pl;
         else {
-            h.bsup.push_back(cf);
+            I.bsup.push_back(cf);
             cf = pf;
             cl = pl;
         }
     }
-    h.bsup.push_back(cf);
-    h.bsup.push_back(nbd);
+    I.bsup.push_back(cf);
+    I.bsup.push_back(nbd);
     return NCL_OK;
 }
 

@@ -70,6 +70,9 @@ def load():
     sig = {
         "ncl_kkt_analyze": ([P, P, pp], ctypes.c_int),
         "ncl_kkt_analyze_pattern": ([i64, i32, P, P, P, P, P, pp], ctypes.c_int),
+        "ncl_kkt_analyze_batch": ([P, i32, P, i32, pp], ctypes.c_int),
+        "ncl_kkt_instances": ([P, P], ctypes.c_int),
+        "ncl_kkt_instance": ([P, i32, P, P, P, P, P], ctypes.c_int),
         "ncl_kkt_dims": ([P, P, P, P, P, P, P], ctypes.c_int),
         "ncl_kkt_symbolic": ([P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ncl_kkt_pattern": ([P, P, P], ctypes.c_int),
@@ -110,28 +113,52 @@ def _stream_ptr():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-class KKT:
-    """One analysed KKT pattern (ncl_kkt handle) and, once bound, its workspace."""
+def _network_struct(net, keep):
+    arrs = dict(br_from=np.ascontiguousarray(net.br_from, np.int32),
+                br_to=np.ascontiguousarray(net.br_to, np.int32),
+                gen_bus=np.ascontiguousarray(net.gen_bus, np.int32),
+                outage=np.ascontiguousarray(net.outage, np.int32),
+                br_r=np.ascontiguousarray(net.br_r, np.float64),
+                br_x=np.ascontiguousarray(net.br_x, np.float64),
+                gen_c2=np.ascontiguousarray(net.gen_c2, np.float64))
+    keep.append(arrs)
+    return _Network(int(net.nb), int(net.nl), int(net.ng), int(arrs["outage"].shape[0]),
+                    *[_np_ptr(arrs[k]) for k in ("br_from", "br_to", "gen_bus", "outage", "br_r", "br_x", "gen_c2")],
+                    NCL_PVPQ if getattr(net, "pvpq", False) else 0)
 
-    def __init__(self, net=None, *, relax=None, pattern=None):
+
+class KKT:
+    """One analysed KKT pattern (ncl_kkt handle) and, once bound, its workspace.
+
+    ``KKT(net)`` analyses one network; ``KKT(nets=[...])`` analyses a batch
+    of independent networks in one handle (every launch then covers all of
+    them; vectors are the instances' layout-order vectors concatenated).
+    ``relax`` is one (maxw, znum, zden) triple, or with a batch optionally a
+    list with one triple per instance."""
+
+    def __init__(self, net=None, *, relax=None, pattern=None, nets=None):
         L = load()
         self._h = ctypes.c_void_p()
         self._keep = []
         opts = None
-        if relax is not None:
+        if relax is not None and not (nets is not None and isinstance(relax, (list, tuple))
+                                      and len(relax) and isinstance(relax[0], (list, tuple))):
             opts = _Opts(int(relax[0]), int(relax[1]), int(relax[2]))
-        if net is not None:
-            arrs = dict(br_from=np.ascontiguousarray(net.br_from, np.int32),
-                        br_to=np.ascontiguousarray(net.br_to, np.int32),
-                        gen_bus=np.ascontiguousarray(net.gen_bus, np.int32),
-                        outage=np.ascontiguousarray(net.outage, np.int32),
-                        br_r=np.ascontiguousarray(net.br_r, np.float64),
-                        br_x=np.ascontiguousarray(net.br_x, np.float64),
-                        gen_c2=np.ascontiguousarray(net.gen_c2, np.float64))
-            s = _Network(int(net.nb), int(net.nl), int(net.ng), int(arrs["outage"].shape[0]),
-                         *[_np_ptr(arrs[k]) for k in ("br_from", "br_to", "gen_bus", "outage", "br_r", "br_x",
-                                                     "gen_c2")],
-                         NCL_PVPQ if getattr(net, "pvpq", False) else 0)
+        if nets is not None:
+            nets = list(nets)
+            arr = (_Network * len(nets))(*[_network_struct(n, self._keep) for n in nets])
+            nopts = 0
+            optp = None
+            if opts is not None:
+                optp, nopts = ctypes.byref(opts), 1
+            elif relax is not None:
+                oarr = (_Opts * len(nets))(*[_Opts(int(r[0]), int(r[1]), int(r[2])) for r in relax])
+                self._keep.append(oarr)
+                optp, nopts = oarr, len(nets)
+            rc = L.ncl_kkt_analyze_batch(arr, len(nets), optp, nopts, ctypes.byref(self._h))
+            _check("ncl_kkt_analyze_batch", rc)
+        elif net is not None:
+            s = _network_struct(net, self._keep)
             rc = L.ncl_kkt_analyze(ctypes.byref(s), ctypes.byref(opts) if opts else None, ctypes.byref(self._h))
             _check("ncl_kkt_analyze", rc)
         elif pattern is not None:
@@ -151,6 +178,16 @@ class KKT:
         self.N, self.nprimal, self.nnzK, self.nnzL, self.nsuper, self.npanel = (int(x.value) for x in d)
         self.ws = None
         self.nrhs_max = 0
+        cnt = ctypes.c_int32()
+        _check("ncl_kkt_instances", L.ncl_kkt_instances(self._h, ctypes.byref(cnt)))
+        self.instances = []
+        for i in range(cnt.value):
+            c0, n, npr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            nbk, nbd = ctypes.c_int32(), ctypes.c_int32()
+            _check("ncl_kkt_instance", L.ncl_kkt_instance(self._h, i, ctypes.byref(c0), ctypes.byref(n),
+                                                          ctypes.byref(npr), ctypes.byref(nbk), ctypes.byref(nbd)))
+            self.instances.append(dict(col0=c0.value, N=n.value, nprimal=npr.value, nblk=nbk.value,
+                                       nbd=nbd.value))
 
     # ------------------------------------------------------------ symbolic (host)
     def symbolic(self):
