@@ -145,6 +145,30 @@ int ncl_kkt_analyze_pattern(int64_t N, int32_t nblk, const int64_t *block_off, c
                             const int32_t *rowind, const uint8_t *is_primal,
                             const ncl_analyze_opts *opts, ncl_kkt **out);
 
+/* Symbolic analysis of a batch of independent networks in one handle
+ * (batched workloads: many scenarios or snapshots factored together).
+ * Each network is analysed exactly as by ncl_kkt_analyze; the handle's
+ * matrix is block diagonal over the instances, and every vector is the
+ * instances' layout-order vectors concatenated in the order given (see
+ * ncl_kkt_instance for each instance's first column).  Every launch of
+ * assemble, factor and solve covers all instances at once; instance i's
+ * results are bitwise equal to those of a handle holding network i alone.
+ * opts: NULL with nopts = 0 (defaults), one set for all (nopts = 1), or one
+ * per instance (nopts = count), e.g. supernode amalgamation widths chosen
+ * per instance shape.  ncl_kkt_point.rho is shared by all instances.
+ * Returns NCL_ERR_ARG on a bad network (as ncl_kkt_analyze) or count < 1. */
+int ncl_kkt_analyze_batch(const ncl_network *nets, int32_t count, const ncl_analyze_opts *opts, int32_t nopts,
+                          ncl_kkt **out);
+
+/* Number of instances of a handle (1 unless made by ncl_kkt_analyze_batch). */
+int ncl_kkt_instances(const ncl_kkt *h, int32_t *count);
+
+/* Instance i: first global column col0, its size n (blocks then border),
+ * its primal count, its block count and border size.  Any output may be
+ * NULL.  NCL_ERR_ARG if i is out of range. */
+int ncl_kkt_instance(const ncl_kkt *h, int32_t i, int64_t *col0, int64_t *n, int64_t *nprimal, int32_t *nblk,
+                     int32_t *nbd);
+
 /* Sizes: N, primal count, nnz of K's lower triangle, nnz of L's strict
  * lower triangle (exact pattern), number of supernodes, number of panel
  * row indices (length of srowind below). */
