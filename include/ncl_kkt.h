@@ -248,6 +248,51 @@ int ncl_kkt_solve_adjoint(ncl_kkt *h, const double *db, double *dx, int32_t nrhs
 void ncl_kkt_destroy(ncl_kkt *h);
 const char *ncl_status_string(int status);
 
+/* ---------------------------------------------------------------- measurement
+ * Kernel kinds: every launch of the library runs exactly one kernel of one
+ * of these kinds.  A "step" below is one assemble, one factor and one solve
+ * with one right-hand side. */
+enum {
+    NCL_K_ASSEMBLE = 0,     /* k_assemble */
+    NCL_K_VALUES,           /* k_values (set/get values; not part of a step) */
+    NCL_K_FAC_GATHER,       /* k_fac_gather: panel entries minus descendant updates, one launch per level */
+    NCL_K_FAC_DIAG,         /* k_fac_diag: LDL^T of wide diagonal blocks, per level */
+    NCL_K_FAC_ROWS,         /* k_fac_rows: pivots and off-diagonal rows, per level */
+    NCL_K_BORDER_SCHUR,     /* k_border_schur: per-block border Schur contributions */
+    NCL_K_BORDER_SUM,       /* k_border_sum: fixed-order sum into the border matrix */
+    NCL_K_BORDER_FACTOR,    /* k_border_factor: dense border LDL^T */
+    NCL_K_STATUS_INIT,      /* k_status_init */
+    NCL_K_STATUS,           /* k_status: pivot signs and magnitudes */
+    NCL_K_SOL_LOAD,         /* k_sol_load */
+    NCL_K_SOL_FWD_GATHER,   /* k_sol_fwd_gather, per level */
+    NCL_K_SOL_FWD_DIAG,     /* k_sol_fwd_diag, per level */
+    NCL_K_SOL_BPART,        /* k_sol_bpart */
+    NCL_K_SOL_BORDER,       /* k_sol_border */
+    NCL_K_SOL_SCALE,        /* k_sol_scale */
+    NCL_K_SOL_BWD_GATHER,   /* k_sol_bwd_gather, per level */
+    NCL_K_SOL_BWD_DIAG,     /* k_sol_bwd_diag, per level */
+    NCL_K_SOL_STORE,        /* k_sol_store */
+    NCL_K_COUNT
+};
+
+/* Device kernel name of a kind ("k_fac_gather", ...), or NULL. */
+const char *ncl_kernel_name(int kind);
+
+/* Launches per step and algorithmic HBM bytes per step of a kernel kind:
+ * every distinct array element a launch must read or write counted once
+ * per launch (8 bytes per double; schedule tables not counted), summed over
+ * the step's launches.  Host only. */
+int ncl_kkt_kernel_model(const ncl_kkt *h, int32_t kind, int64_t *launches, int64_t *bytes);
+
+/* Bracket every later launch of one kernel kind with a pair of HIP events
+ * on the launch stream (kind = -1: stop).  Resets the accumulated record.
+ * Launches of other kinds are not touched. */
+int ncl_kkt_profile(ncl_kkt *h, int32_t kind);
+
+/* Number of bracketed launches since ncl_kkt_profile and the sum of their
+ * event-measured durations in milliseconds (waits for the last event). */
+int ncl_kkt_profile_read(ncl_kkt *h, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

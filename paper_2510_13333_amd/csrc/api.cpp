@@ -15,7 +15,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+void kernel_model(Handle &h);
 
 int relax_params(const ncl_analyze_opts *o, int &maxw, int &znum, int &zden) {
     maxw = 16;
@@ -100,6 +100,7 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts, int nopts) {
                     if (I.bli[p] > l && mk[I.bli[p]] != int(s)) { mk[I.bli[p]] = int(s); h.npanel++; }
         }
     }
+    kernel_model(h);
     return NCL_OK;
 }
 
@@ -241,6 +242,165 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.stat = h.d.stat;
     a.bprim = h.d.bprim;
     return a;
+}
+
+// Launches and algorithmic bytes per step of every kernel kind: each
+// distinct element a launch reads or writes counts once per launch.
+void kernel_model(Handle &h) {
+    constexpr int64_t D = sizeof(double);
+    h.km_launch.assign(NCL_K_COUNT, 0);
+    h.km_bytes.assign(NCL_K_COUNT, 0);
+    auto &L = h.km_launch;
+    auto &B = h.km_bytes;
+    const ncl::Schedule &S = h.sched;
+    auto levels = [&](int kind, const std::vector<int32_t> &ptr) {
+        for (size_t l = 0; l + 1 < ptr.size(); l++)
+            if (ptr[l + 1] > ptr[l]) L[kind]++;
+    };
+    levels(NCL_K_FAC_GATHER, S.a_ptr);
+    levels(NCL_K_FAC_DIAG, S.b_ptr);
+    levels(NCL_K_FAC_ROWS, S.c_ptr);
+    levels(NCL_K_SOL_FWD_GATHER, S.f_ptr);
+    levels(NCL_K_SOL_FWD_DIAG, S.d_ptr);
+    levels(NCL_K_SOL_BWD_GATHER, S.g_ptr);
+    levels(NCL_K_SOL_BWD_DIAG, S.d_ptr);
+    for (const Template &t : h.tmpl) {
+        const int64_t nb = int64_t(t.blocks.size());
+        const int n = t.n;
+        std::vector<int32_t> mp(size_t(t.panel_off.back()), -1), mk(size_t(n) + h.max_nbd + 1, -1);
+        int stamp = 0;
+        auto uniq = [&](const ncl::Term &q, bool two, int64_t &up, int64_t &uk) {
+            if (mp[q.a] != stamp) { mp[q.a] = stamp; up++; }
+            if (two && mp[q.c] != stamp) { mp[q.c] = stamp; up++; }
+            if (mk[q.k] != stamp) { mk[q.k] = stamp; uk++; }
+        };
+        for (int l = 0; l < t.nlev; l++) {
+            // factor: gather (A), diagonal blocks (B), rows (C)
+            int64_t ents = 0, kr = 0, up = 0, uk = 0, bdiag = 0, rows = 0;
+            stamp++;
+            int last_s = -1;
+            for (int32_t k : t.lev_tasks[l]) {
+                const int s = t.task_s[k], p = t.task_p[k];
+                const int w = t.sup[s + 1] - t.sup[s];
+                const int cend = p < w ? p + 1 : w;
+                for (int c = 0; c < cend; c++) {
+                    const int e = t.task_cbase[k] + c;
+                    ents++;
+                    if (t.ent_kpos[e] >= 0) kr++;
+                    for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq(t.terms[q], true, up, uk);
+                }
+                if (w == 1 || p >= w) rows += 2 * w;
+                if (w > 1 && s != last_s) {
+                    bdiag += int64_t(w) * (w + 1) + w;            // diagonal block read and written, pivots
+                    rows += int64_t(w) * (w - 1) / 2 + w;         // the block and pivots the rows read
+                }
+                last_s = s;
+            }
+            B[NCL_K_FAC_GATHER] += nb * D * (ents + kr + up + uk);
+            B[NCL_K_FAC_DIAG] += nb * D * bdiag;
+            B[NCL_K_FAC_ROWS] += nb * D * rows;
+            // solves: forward gather (F) and backward gather (G) of the diagonal rows, diagonal solves (D)
+            int64_t fr = 0, fup = 0, fuy = 0, gr = 0, gp = 0, guy = 0, dd = 0;
+            stamp++;
+            last_s = -1;
+            for (int32_t k : t.lev_tasks[l]) {
+                const int s = t.task_s[k], p = t.task_p[k];
+                const int w = t.sup[s + 1] - t.sup[s];
+                if (p >= w) continue;
+                const int e = t.task_cbase[k] + p;
+                if (t.ent_tptr[e + 1] > t.ent_tptr[e]) {
+                    fr += 2;
+                    for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq(t.terms[q], false, fup, fuy);
+                }
+                if (w > 1 && s != last_s) dd += int64_t(w) * (w - 1) / 2 + 2 * w - 1;
+                last_s = s;
+            }
+            stamp++;
+            for (int32_t k : t.lev_tasks[l]) {
+                const int s = t.task_s[k], p = t.task_p[k];
+                const int w = t.sup[s + 1] - t.sup[s];
+                if (p >= w) continue;
+                const int r = t.srp[s + 1] - t.srp[s];
+                gr += 2;
+                gp += r - w;
+                for (int i = t.srp[s] + w; i < t.srp[s + 1]; i++) {
+                    const int row = t.sri[i];
+                    if (mk[row] != stamp) { mk[row] = stamp; guy++; }
+                }
+            }
+            B[NCL_K_SOL_FWD_GATHER] += nb * D * (fr + fup + fuy);
+            B[NCL_K_SOL_FWD_DIAG] += nb * D * dd;
+            B[NCL_K_SOL_BWD_GATHER] += nb * D * (gr + gp + guy);
+            B[NCL_K_SOL_BWD_DIAG] += nb * D * dd;
+        }
+        const ncl::Inst &I = h.inst[t.inst];
+        if (I.nbd) {
+            int64_t up = 0, uk = 0;
+            stamp++;
+            for (const ncl::Term &q : t.sterms) uniq(q, true, up, uk);
+            B[NCL_K_BORDER_SCHUR] += nb * D * (I.npk() + up + uk);
+            up = uk = 0;
+            stamp++;
+            for (const ncl::Term &q : t.bterms) uniq(q, false, up, uk);
+            B[NCL_K_SOL_BPART] += nb * D * (I.nbd + up + uk);
+        }
+    }
+    L[NCL_K_ASSEMBLE] = 1;
+    B[NCL_K_ASSEMBLE] = D * (2 * h.N + h.kint + h.nbb_tot);
+    L[NCL_K_STATUS_INIT] = 1;
+    B[NCL_K_STATUS_INIT] = D * 6;
+    L[NCL_K_STATUS] = 1;
+    B[NCL_K_STATUS] = D * (h.dint + h.nbd_tot);
+    L[NCL_K_SOL_LOAD] = L[NCL_K_SOL_STORE] = L[NCL_K_SOL_SCALE] = 1;
+    B[NCL_K_SOL_LOAD] = B[NCL_K_SOL_STORE] = D * 2 * h.dint;
+    B[NCL_K_SOL_SCALE] = D * 3 * h.dint;
+    if (h.nbd_tot) {
+        L[NCL_K_BORDER_SCHUR] = L[NCL_K_BORDER_SUM] = L[NCL_K_BORDER_FACTOR] = 1;
+        L[NCL_K_SOL_BPART] = L[NCL_K_SOL_BORDER] = 1;
+        B[NCL_K_BORDER_SUM] = D * (h.sp_tot + h.nbb_tot + h.npk_tot);
+        B[NCL_K_BORDER_FACTOR] = D * (2 * h.npk_tot + h.nbd_tot);
+        B[NCL_K_SOL_BORDER] = D * (h.cp_tot + h.npk_tot + 4 * h.nbd_tot);
+    } else {
+        B[NCL_K_BORDER_SCHUR] = B[NCL_K_SOL_BPART] = 0;
+    }
+}
+
+// Whether a launch of this kind with these arguments runs a kernel.
+bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
+    switch (kind) {
+        case NCL_K_ASSEMBLE: return a.asm_threads + a.gp_tot > 0;
+        case NCL_K_VALUES: return a.kint + a.nbb_tot > 0;
+        case NCL_K_BORDER_SUM: return a.npk_tot > 0;
+        case NCL_K_BORDER_FACTOR:
+        case NCL_K_SOL_BORDER: return a.max_nbd > 0;
+        case NCL_K_STATUS_INIT:
+        case NCL_K_STATUS: return true;
+        case NCL_K_SOL_LOAD:
+        case NCL_K_SOL_SCALE:
+        case NCL_K_SOL_STORE: return a.dint > 0;
+        default: return l.nw > 0;
+    }
+}
+
+// Launch one kernel; bracket it with events when its kind is being profiled.
+hipError_t run(Handle &h, int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l, hipStream_t st) {
+    if (kind != h.prof_kind || !nonempty(kind, a, l)) return ncl::launch(kind, a, l, st);
+    if (2 * h.ev_used + 2 > h.ev.size()) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return hipErrorOutOfMemory;
+        }
+        h.ev.push_back(e0);
+        h.ev.push_back(e1);
+    }
+    hipEvent_t e0 = static_cast<hipEvent_t>(h.ev[2 * h.ev_used]), e1 = static_cast<hipEvent_t>(h.ev[2 * h.ev_used + 1]);
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = ncl::launch(kind, a, l, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) h.ev_used++;
+    return e;
 }
 
 int hip_rc(hipError_t e) { return e == hipSuccess ? NCL_OK : NCL_ERR_HIP; }
@@ -583,21 +743,33 @@ int ncl_kkt_assemble(ncl_kkt *k, const ncl_kkt_point *pt, void *stream) {
     if (!k || !pt || !pt->z || !pt->sigma || !(pt->rho > 0)) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound || !h.from_network) return NCL_ERR_STATE;
-    return hip_rc(ncl::launch_assemble(dev_args(h), pt->z, pt->sigma, pt->rho, reinterpret_cast<hipStream_t>(stream)));
+    ncl::LaunchArgs l;
+    l.z = pt->z;
+    l.sig = pt->sigma;
+    l.rho = pt->rho;
+    return hip_rc(run(h, NCL_K_ASSEMBLE, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_set_values(ncl_kkt *k, const double *dvals, void *stream) {
     if (!k || !dvals) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
-    return hip_rc(ncl::launch_values(dev_args(h), dvals, h.d.kval, true, reinterpret_cast<hipStream_t>(stream)));
+    ncl::LaunchArgs l;
+    l.src = dvals;
+    l.dst = h.d.kval;
+    l.to_internal = true;
+    return hip_rc(run(h, NCL_K_VALUES, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
     if (!k || !dvals) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound) return NCL_ERR_STATE;
-    return hip_rc(ncl::launch_values(dev_args(h), h.d.kval, dvals, false, reinterpret_cast<hipStream_t>(stream)));
+    ncl::LaunchArgs l;
+    l.src = h.d.kval;
+    l.dst = dvals;
+    l.to_internal = false;
+    return hip_rc(run(h, NCL_K_VALUES, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
@@ -609,13 +781,23 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
     const ncl::DevArgs a = dev_args(h);
     const ncl::Schedule &S = h.sched;
     const ncl::Work *W = h.d.work;
+    auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
+        ncl::LaunchArgs la;
+        la.wl = W + off + ptr[l];
+        la.nw = ptr[l + 1] - ptr[l];
+        return run(h, kind, a, la, st);
+    };
     for (int l = 0; l < S.nlev; l++) {
-        hipError_t e = ncl::launch_factor_level(a, W + h.w_a + S.a_ptr[l], S.a_ptr[l + 1] - S.a_ptr[l],
-                                                W + h.w_b + S.b_ptr[l], S.b_ptr[l + 1] - S.b_ptr[l],
-                                                W + h.w_c + S.c_ptr[l], S.c_ptr[l + 1] - S.c_ptr[l], st);
-        if (e != hipSuccess) return NCL_ERR_HIP;
+        if (list(NCL_K_FAC_GATHER, h.w_a, S.a_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+        if (list(NCL_K_FAC_DIAG, h.w_b, S.b_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+        if (list(NCL_K_FAC_ROWS, h.w_c, S.c_ptr, l) != hipSuccess) return NCL_ERR_HIP;
     }
-    if (h.nbd_tot && ncl::launch_schur(a, W + h.w_schur, int(S.schur.size()), st) != hipSuccess) return NCL_ERR_HIP;
+    if (h.nbd_tot) {
+        ncl::LaunchArgs la;
+        la.wl = W + h.w_schur;
+        la.nw = int(S.schur.size());
+        if (run(h, NCL_K_BORDER_SCHUR, a, la, st) != hipSuccess) return NCL_ERR_HIP;
+    }
     h.blocks_done = true;
     return NCL_OK;
 }
@@ -624,9 +806,13 @@ int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
     if (!k) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound || !h.blocks_done) return NCL_ERR_STATE;
-    int rc = hip_rc(ncl::launch_factor_border(dev_args(h), reinterpret_cast<hipStream_t>(stream)));
-    if (rc == NCL_OK) h.factored = true;
-    return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    const ncl::LaunchArgs none;
+    for (int kind : {NCL_K_BORDER_SUM, NCL_K_BORDER_FACTOR, NCL_K_STATUS_INIT, NCL_K_STATUS})
+        if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
+    h.factored = true;
+    return NCL_OK;
 }
 
 int ncl_kkt_factor(ncl_kkt *k, void *stream) {
@@ -722,22 +908,77 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
         double *x = dx + int64_t(rhs) * ld;
         double *y = h.d.ybuf + int64_t(rhs) * (h.dint + h.nbd_tot);
         double *cp = h.d.cpart + int64_t(rhs) * h.cp_tot;
-        if (ncl::launch_solve_load(a, b, y, st) != hipSuccess) return NCL_ERR_HIP;
-        for (int l = 0; l < S.nlev; l++)
-            if (ncl::launch_solve_fwd_level(a, y, W + h.w_f + S.f_ptr[l], S.f_ptr[l + 1] - S.f_ptr[l],
-                                            W + h.w_d + S.d_ptr[l], S.d_ptr[l + 1] - S.d_ptr[l], st) != hipSuccess)
-                return NCL_ERR_HIP;
-        if (h.nbd_tot) {
-            if (ncl::launch_solve_bpart(a, y, cp, W + h.w_bpart, int(S.bpart.size()), st) != hipSuccess) return NCL_ERR_HIP;
-            if (ncl::launch_solve_border(a, b, x, y, cp, st) != hipSuccess) return NCL_ERR_HIP;
+        ncl::LaunchArgs v;
+        v.b = b;
+        v.x = x;
+        v.y = y;
+        v.cpart = cp;
+        auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
+            ncl::LaunchArgs la = v;
+            la.wl = W + off + ptr[l];
+            la.nw = ptr[l + 1] - ptr[l];
+            return run(h, kind, a, la, st);
+        };
+        if (run(h, NCL_K_SOL_LOAD, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+        for (int l = 0; l < S.nlev; l++) {
+            if (list(NCL_K_SOL_FWD_GATHER, h.w_f, S.f_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+            if (list(NCL_K_SOL_FWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         }
-        if (ncl::launch_solve_scale(a, y, st) != hipSuccess) return NCL_ERR_HIP;
-        for (int l = S.nlev - 1; l >= 0; l--)
-            if (ncl::launch_solve_bwd_level(a, y, W + h.w_g + S.g_ptr[l], S.g_ptr[l + 1] - S.g_ptr[l],
-                                            W + h.w_d + S.d_ptr[l], S.d_ptr[l + 1] - S.d_ptr[l], st) != hipSuccess)
-                return NCL_ERR_HIP;
-        if (ncl::launch_solve_store(a, y, x, st) != hipSuccess) return NCL_ERR_HIP;
+        if (h.nbd_tot) {
+            ncl::LaunchArgs la = v;
+            la.wl = W + h.w_bpart;
+            la.nw = int(S.bpart.size());
+            if (run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess) return NCL_ERR_HIP;
+            if (run(h, NCL_K_SOL_BORDER, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+        }
+        if (run(h, NCL_K_SOL_SCALE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+        for (int l = S.nlev - 1; l >= 0; l--) {
+            if (list(NCL_K_SOL_BWD_GATHER, h.w_g, S.g_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+            if (list(NCL_K_SOL_BWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+        }
+        if (run(h, NCL_K_SOL_STORE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
     }
+    return NCL_OK;
+}
+
+const char *ncl_kernel_name(int kind) {
+    static const char *names[NCL_K_COUNT] = {
+        "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
+        "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
+        "k_sol_bpart", "k_sol_border", "k_sol_scale", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store"};
+    return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
+}
+
+int ncl_kkt_kernel_model(const ncl_kkt *k, int32_t kind, int64_t *launches, int64_t *bytes) {
+    if (!k || kind < 0 || kind >= NCL_K_COUNT) return NCL_ERR_ARG;
+    if (launches) *launches = k->h.km_launch[kind];
+    if (bytes) *bytes = k->h.km_bytes[kind];
+    return NCL_OK;
+}
+
+int ncl_kkt_profile(ncl_kkt *k, int32_t kind) {
+    if (!k || kind < -1 || kind >= NCL_K_COUNT) return NCL_ERR_ARG;
+    k->h.prof_kind = kind;
+    k->h.ev_used = 0;
+    return NCL_OK;
+}
+
+int ncl_kkt_profile_read(ncl_kkt *k, int64_t *launches, double *total_ms) {
+    if (!k) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    double ms = 0.0;
+    if (h.ev_used) {
+        if (hipEventSynchronize(static_cast<hipEvent_t>(h.ev[2 * h.ev_used - 1])) != hipSuccess) return NCL_ERR_HIP;
+        for (size_t i = 0; i < h.ev_used; i++) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, static_cast<hipEvent_t>(h.ev[2 * i]), static_cast<hipEvent_t>(h.ev[2 * i + 1])) !=
+                hipSuccess)
+                return NCL_ERR_HIP;
+            ms += double(t);
+        }
+    }
+    if (launches) *launches = int64_t(h.ev_used);
+    if (total_ms) *total_ms = ms;
     return NCL_OK;
 }
 
@@ -751,3 +992,7 @@ int ncl_kkt_solve_adjoint(ncl_kkt *k, const double *db, double *dx, int32_t nrhs
 }
 
 }  // extern "C"
+
+ncl_kkt::~ncl_kkt() {
+    for (void *e : h.ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+}

@@ -23,23 +23,21 @@ struct DevArgs {
     const uint8_t *bprim;       // [nbd_tot] expected sign of the border pivots
 };
 
-hipError_t launch_assemble(const DevArgs &a, const double *z, const double *sig, double rho, hipStream_t st);
-hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, hipStream_t st);
-hipError_t launch_factor_level(const DevArgs &a, const Work *wa, int na, const Work *wb, int nb, const Work *wc,
-                               int nc, hipStream_t st);
-hipError_t launch_schur(const DevArgs &a, const Work *ws, int nw, hipStream_t st);
-hipError_t launch_factor_border(const DevArgs &a, hipStream_t st);
+// Arguments of one launch (only those the kernel kind uses are read).
+struct LaunchArgs {
+    const Work *wl = nullptr;   // work list and its length
+    int nw = 0;
+    const double *z = nullptr, *sig = nullptr;   // assembly state
+    double rho = 0.0;
+    const double *src = nullptr;                 // value conversion
+    double *dst = nullptr;
+    bool to_internal = false;
+    const double *b = nullptr;                   // solve: right-hand side, solution, work vectors
+    double *x = nullptr, *y = nullptr, *cpart = nullptr;
+};
+
+// Launch one kernel of the given kind (NCL_K_* of ncl_kkt.h) on stream st.
+hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st);
 size_t border_lds_bytes(int nbd);   // dynamic LDS of the dense border factor (largest border)
-hipError_t launch_solve_load(const DevArgs &a, const double *b, double *y, hipStream_t st);
-hipError_t launch_solve_fwd_level(const DevArgs &a, double *y, const Work *wf, int nf, const Work *wd, int nd,
-                                  hipStream_t st);
-hipError_t launch_solve_bpart(const DevArgs &a, const double *y, double *cpart, const Work *wp, int np,
-                              hipStream_t st);
-hipError_t launch_solve_border(const DevArgs &a, const double *b, double *x, double *y, const double *cpart,
-                               hipStream_t st);
-hipError_t launch_solve_scale(const DevArgs &a, double *y, hipStream_t st);
-hipError_t launch_solve_bwd_level(const DevArgs &a, double *y, const Work *wg, int ng, const Work *wd, int nd,
-                                  hipStream_t st);
-hipError_t launch_solve_store(const DevArgs &a, const double *y, double *x, hipStream_t st);
 
 }  // namespace ncl

@@ -465,9 +465,12 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
                 const double dj = cb[j];
                 const double lij = i > j ? row[j] / dj : 0.0;
 #pragma unroll
-                for (int k = j + 1; k < W; k++)
-                    if (i >= k && k < w) row[k] -= lij * cb[k];
-                if (i > j) row[j] = lij;
+                for (int k = j + 1; k < W; k++) {
+                    const double ak = cb[k];
+                    const double upd = row[k] - lij * ak;
+                    row[k] = (i >= k && k < w) ? upd : row[k];          // select, no divergent branch
+                }
+                row[j] = i > j ? lij : row[j];
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -622,9 +625,12 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
                     const double dj = Ld[j * kPS + j];
                     const double lij = i > j ? row[j] / dj : 0.0;
 #pragma unroll
-                    for (int k = j + 1; k < kBB; k++)
-                        if (i >= k && k < bs) row[k] -= lij * Ld[k * kPS + j];
-                    if (i > j) row[j] = lij;
+                    for (int k = j + 1; k < kBB; k++) {
+                        const double ak = Ld[k * kPS + j];
+                        const double upd = row[k] - lij * ak;
+                        row[k] = (i >= k && k < bs) ? upd : row[k];     // select, no divergent branch
+                    }
+                    row[j] = i > j ? lij : row[j];
                     __builtin_amdgcn_wave_barrier();
                 }
             }
@@ -1064,94 +1070,94 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, cons
 static inline unsigned waves_grid(int nw) { return unsigned((nw + (kWG / 64) - 1) / (kWG / 64)); }
 static inline unsigned elems_grid(int64_t n) { return unsigned((n + 255) / 256); }
 
-hipError_t launch_assemble(const DevArgs &a, const double *z, const double *sig, double rho, hipStream_t st) {
-    const int64_t total = a.asm_threads + a.gp_tot;
-    if (total) hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, z, sig, rho);
-    return hipGetLastError();
-}
-
-hipError_t launch_values(const DevArgs &a, const double *src, double *dst, bool to_internal, hipStream_t st) {
-    const int64_t total = a.kint + a.nbb_tot;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_values, dim3(elems_grid(total)), dim3(256), 0, st, a, src, dst, to_internal ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_factor_level(const DevArgs &a, const Work *wa, int na, const Work *wb, int nb, const Work *wc,
-                               int nc, hipStream_t st) {
-    if (na) hipLaunchKernelGGL(k_fac_gather, dim3(waves_grid(na)), dim3(kWG), 0, st, a, wa, na);
-    if (nb) hipLaunchKernelGGL(k_fac_diag, dim3(waves_grid(nb)), dim3(kWG), 0, st, a, wb, nb);
-    if (nc) hipLaunchKernelGGL(k_fac_rows, dim3(waves_grid(nc)), dim3(kWG), 0, st, a, wc, nc);
-    return hipGetLastError();
-}
-
-hipError_t launch_schur(const DevArgs &a, const Work *ws, int nw, hipStream_t st) {
-    if (nw) hipLaunchKernelGGL(k_border_schur, dim3(waves_grid(nw)), dim3(kWG), 0, st, a, ws, nw);
-    return hipGetLastError();
-}
-
 size_t border_lds_bytes(int nbd) {
     return size_t(kBB * kPS + kBB + (nbd > kBB ? nbd - kBB : 0) * kPS) * sizeof(double);
 }
 
-hipError_t launch_factor_border(const DevArgs &a, hipStream_t st) {
-    if (a.npk_tot > 0) {
-        hipLaunchKernelGGL(k_border_sum, dim3(waves_grid(int(a.npk_tot))), dim3(kWG), 0, st, a);
-        const size_t lbytes = border_lds_bytes(a.max_nbd);
-        if (lbytes > 65536) {
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_border_factor),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lbytes));
-            if (e != hipSuccess) return e;
+// One kernel per call, so that a caller can bracket exactly one kernel
+// with events.
+hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st) {
+    switch (kind) {
+        case NCL_K_ASSEMBLE: {
+            const int64_t total = a.asm_threads + a.gp_tot;
+            if (total) hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, l.z, l.sig, l.rho);
+            break;
         }
-        hipLaunchKernelGGL(k_border_factor, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
+        case NCL_K_VALUES: {
+            const int64_t total = a.kint + a.nbb_tot;
+            if (total)
+                hipLaunchKernelGGL(k_values, dim3(elems_grid(total)), dim3(256), 0, st, a, l.src, l.dst,
+                                   l.to_internal ? 1 : 0);
+            break;
+        }
+        case NCL_K_FAC_GATHER:
+            if (l.nw) hipLaunchKernelGGL(k_fac_gather, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
+            break;
+        case NCL_K_FAC_DIAG:
+            if (l.nw) hipLaunchKernelGGL(k_fac_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
+            break;
+        case NCL_K_FAC_ROWS:
+            if (l.nw) hipLaunchKernelGGL(k_fac_rows, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
+            break;
+        case NCL_K_BORDER_SCHUR:
+            if (l.nw) hipLaunchKernelGGL(k_border_schur, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
+            break;
+        case NCL_K_BORDER_SUM:
+            if (a.npk_tot) hipLaunchKernelGGL(k_border_sum, dim3(waves_grid(int(a.npk_tot))), dim3(kWG), 0, st, a);
+            break;
+        case NCL_K_BORDER_FACTOR:
+            if (a.max_nbd) {
+                const size_t lbytes = border_lds_bytes(a.max_nbd);
+                if (lbytes > 65536) {
+                    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_border_factor),
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lbytes));
+                    if (e != hipSuccess) return e;
+                }
+                hipLaunchKernelGGL(k_border_factor, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
+            }
+            break;
+        case NCL_K_STATUS_INIT:
+            hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, a);
+            break;
+        case NCL_K_STATUS: {
+            const int64_t ne = a.dint + a.nbd_tot;
+            const unsigned sg = unsigned(ne / 256 / 16 + 1 < 1024 ? ne / 256 / 16 + 1 : 1024);
+            hipLaunchKernelGGL(k_status, dim3(sg), dim3(256), 0, st, a);
+            break;
+        }
+        case NCL_K_SOL_LOAD:
+            if (a.dint) hipLaunchKernelGGL(k_sol_load, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.b, l.y);
+            break;
+        case NCL_K_SOL_FWD_GATHER:
+            if (l.nw) hipLaunchKernelGGL(k_sol_fwd_gather, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            break;
+        case NCL_K_SOL_FWD_DIAG:
+            if (l.nw) hipLaunchKernelGGL(k_sol_fwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            break;
+        case NCL_K_SOL_BPART:
+            if (l.nw)
+                hipLaunchKernelGGL(k_sol_bpart, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
+            break;
+        case NCL_K_SOL_BORDER:
+            if (a.max_nbd > 0)
+                hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), size_t(a.max_nbd) * sizeof(double),
+                                   st, a, l.b, l.x, l.y, l.cpart);
+            break;
+        case NCL_K_SOL_SCALE:
+            if (a.dint) hipLaunchKernelGGL(k_sol_scale, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y);
+            break;
+        case NCL_K_SOL_BWD_GATHER:
+            if (l.nw) hipLaunchKernelGGL(k_sol_bwd_gather, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            break;
+        case NCL_K_SOL_BWD_DIAG:
+            if (l.nw) hipLaunchKernelGGL(k_sol_bwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            break;
+        case NCL_K_SOL_STORE:
+            if (a.dint) hipLaunchKernelGGL(k_sol_store, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y, l.x);
+            break;
+        default:
+            return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, a);
-    const int64_t ne = a.dint + a.nbd_tot;
-    const unsigned sg = unsigned(ne / 256 / 16 + 1 < 1024 ? ne / 256 / 16 + 1 : 1024);
-    hipLaunchKernelGGL(k_status, dim3(sg), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_load(const DevArgs &a, const double *b, double *y, hipStream_t st) {
-    if (a.dint) hipLaunchKernelGGL(k_sol_load, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, b, y);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_fwd_level(const DevArgs &a, double *y, const Work *wf, int nf, const Work *wd, int nd,
-                                  hipStream_t st) {
-    if (nf) hipLaunchKernelGGL(k_sol_fwd_gather, dim3(waves_grid(nf)), dim3(kWG), 0, st, a, y, wf, nf);
-    if (nd) hipLaunchKernelGGL(k_sol_fwd_diag, dim3(waves_grid(nd)), dim3(kWG), 0, st, a, y, wd, nd);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_bpart(const DevArgs &a, const double *y, double *cpart, const Work *wp, int np,
-                              hipStream_t st) {
-    if (np) hipLaunchKernelGGL(k_sol_bpart, dim3(waves_grid(np)), dim3(kWG), 0, st, a, y, cpart, wp, np);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_border(const DevArgs &a, const double *b, double *x, double *y, const double *cpart,
-                               hipStream_t st) {
-    if (a.max_nbd > 0)
-        hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), size_t(a.max_nbd) * sizeof(double), st, a, b, x,
-                           y, cpart);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_scale(const DevArgs &a, double *y, hipStream_t st) {
-    if (a.dint) hipLaunchKernelGGL(k_sol_scale, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, y);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_bwd_level(const DevArgs &a, double *y, const Work *wg, int ng, const Work *wd, int nd,
-                                  hipStream_t st) {
-    if (ng) hipLaunchKernelGGL(k_sol_bwd_gather, dim3(waves_grid(ng)), dim3(kWG), 0, st, a, y, wg, ng);
-    if (nd) hipLaunchKernelGGL(k_sol_bwd_diag, dim3(waves_grid(nd)), dim3(kWG), 0, st, a, y, wd, nd);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve_store(const DevArgs &a, const double *y, double *x, hipStream_t st) {
-    if (a.dint) hipLaunchKernelGGL(k_sol_store, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, y, x);
     return hipGetLastError();
 }
 

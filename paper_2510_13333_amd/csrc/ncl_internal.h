@@ -255,6 +255,12 @@ struct Handle {
     } d;
     // offsets of each work list inside d.work
     size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
+    // per kernel kind: launches and algorithmic bytes of one step
+    std::vector<int64_t> km_launch, km_bytes;
+    // event profiling of one kernel kind (events are hipEvent_t, in pairs)
+    int prof_kind = -1;
+    std::vector<void *> ev;
+    size_t ev_used = 0;
 };
 
 // model.cpp
@@ -272,4 +278,5 @@ int build_schedule(Handle &h);
 
 struct ncl_kkt {
     ncl::Handle h;
+    ~ncl_kkt();
 };

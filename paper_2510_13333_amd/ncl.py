@@ -18,6 +18,11 @@ _lib = None
 
 NCL_PVPQ = 1
 
+# kernel kinds (NCL_K_* of ncl_kkt.h), in enum order
+KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
+           "border_factor", "status_init", "status", "sol_load", "sol_fwd_gather", "sol_fwd_diag", "sol_bpart",
+           "sol_border", "sol_scale", "sol_bwd_gather", "sol_bwd_diag", "sol_store"]
+
 STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
           -4: "call out of order", -5: "zero pivot", -6: "pivot of the wrong sign (inertia)",
           -7: "non-finite pivot"}
@@ -89,6 +94,10 @@ def load():
         "ncl_kkt_solve": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_solve_adjoint": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_destroy": ([P], None),
+        "ncl_kernel_name": ([ctypes.c_int], ctypes.c_char_p),
+        "ncl_kkt_kernel_model": ([P, i32, P, P], ctypes.c_int),
+        "ncl_kkt_profile": ([P, i32], ctypes.c_int),
+        "ncl_kkt_profile_read": ([P, P, P], ctypes.c_int),
         "ncl_status_string": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -285,6 +294,29 @@ class KKT:
 
     def solve_adjoint(self, b, out=None):
         return self._solve("ncl_kkt_solve_adjoint", b, out)
+
+    # ------------------------------------------------------------ measurement
+    @staticmethod
+    def kernel_name(kind):
+        n = load().ncl_kernel_name(int(kind))
+        return n.decode() if n else None
+
+    def kernel_model(self, kind):
+        """(launches, algorithmic bytes) of one kernel kind per step."""
+        la, by = ctypes.c_int64(), ctypes.c_int64()
+        _check("ncl_kkt_kernel_model", load().ncl_kkt_kernel_model(self._h, int(kind), ctypes.byref(la),
+                                                                   ctypes.byref(by)))
+        return la.value, by.value
+
+    def profile(self, kind):
+        """Bracket later launches of one kernel kind with HIP events (-1 stops)."""
+        _check("ncl_kkt_profile", load().ncl_kkt_profile(self._h, int(kind)))
+
+    def profile_read(self):
+        """(bracketed launches, their summed event time in ms)."""
+        n, ms = ctypes.c_int64(), ctypes.c_double()
+        _check("ncl_kkt_profile_read", load().ncl_kkt_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     def __del__(self):
         try:

@@ -124,3 +124,66 @@ def test_batch_c4_workload():
         c0, n = I["col0"], I["N"]
         cp, ri, v, pos = O.kkt(net, zs[i], ss[i])
         assert O.backward_error(cp, ri, v, X[:, c0:c0 + n], B[:, c0:c0 + n]) <= 1e-12, i
+
+
+def test_graph_replay_matches_eager():
+    """The batched step captured once in a hipGraph: every replay (new state
+    copied into the captured inputs, eager work and synchronisation between
+    replays) is bitwise equal to the eager step on the same state."""
+    nets = mixed_networks()
+    rho = nets[0].rho
+    kb = KKT(nets=nets).bind(nrhs_max=1)
+    states = []
+    for it in range(3):
+        zs, ss = points(nets, 41, iteration=it)
+        states.append((dev(np.concatenate(zs)), dev(np.concatenate(ss)), dev(G.draw_rhs(kb.N, 1, 41, iteration=it)[0])))
+    zb, sb, bb = (t.clone() for t in states[0])
+    xb = torch.empty_like(bb)
+    kb.assemble(zb, sb, rho)                     # warm up outside the capture
+    kb.factor()
+    kb.solve(bb, out=xb)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        kb.assemble(zb, sb, rho)
+        kb.factor()
+        kb.solve(bb, out=xb)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for it, (z, s, b) in enumerate(states):
+            zb.copy_(z)
+            sb.copy_(s)
+            bb.copy_(b)
+            g.replay()
+            torch.cuda.synchronize()
+            xr = xb.clone()
+            kb.assemble(z, s, rho)
+            kb.factor()
+            xe = kb.solve(b)
+            torch.cuda.synchronize()
+            assert kb.info()["status"] == 0
+            assert torch.equal(xr, xe), (rep, it)
+
+
+def test_profiling_brackets_each_kind():
+    """ncl_kkt_profile brackets exactly the launches the per-kernel model
+    counts for one step, with non-negative event times."""
+    from paper_2510_13333_amd.ncl import KERNELS
+    nets = mixed_networks()
+    kb = KKT(nets=nets).bind(nrhs_max=1)
+    zs, ss = points(nets, 41)
+    z, s, b = dev(np.concatenate(zs)), dev(np.concatenate(ss)), dev(G.draw_rhs(kb.N, 1, 41)[0])
+    x = torch.empty_like(b)
+    for kind, name in enumerate(KERNELS):
+        if name == "values":
+            continue
+        kb.profile(kind)
+        kb.assemble(z, s, nets[0].rho)
+        kb.factor()
+        kb.solve(b, out=x)
+        n, ms = kb.profile_read()
+        launches, nbytes = kb.kernel_model(kind)
+        assert n == launches, (name, n, launches)
+        assert ms >= 0.0 and nbytes >= 0
+    kb.profile(-1)
+    assert kb.profile_read() == (0, 0.0)

@@ -122,3 +122,54 @@ def test_pattern_seam_rejects_block_coupling():
         cp[c + 1] = len(ri)
     with pytest.raises(NclError):
         KKT(pattern=(N, np.array([0, 2, 4]), cp, np.array(ri, np.int32), np.ones(N, np.uint8)))
+
+
+def test_batch_symbolic_is_per_instance_symbolic():
+    """A batched handle's symbolic result is the concatenation of each
+    network's own analysis (global indices offset by the instance's first
+    column), also with per-instance amalgamation parameters."""
+    nets = [G.make_network(41, 30, 41, 6, 0, instance=0), G.make_network(41, 60, 84, 11, 5, instance=1),
+            G.make_network(41, 24, 33, 4, 3, pvpq=True, instance=2)]
+    relax = [(8, 1, 4), (16, 1, 2), (4, 1, 4)]
+    kb = KKT(nets=nets, relax=relax)
+    sb = kb.symbolic()
+    cpb, rib = kb.pattern()
+    assert [i["N"] for i in kb.instances] == [KKT(n).N for n in nets]
+    nz = sp = 0
+    for i, (n, r) in enumerate(zip(nets, relax)):
+        k1 = KKT(n, relax=r)
+        s1 = k1.symbolic()
+        c0, N1 = kb.instances[i]["col0"], kb.instances[i]["N"]
+        sl = slice(c0, c0 + N1)
+        assert np.array_equal(sb["perm"][sl], s1["perm"] + c0)
+        e1 = np.where(s1["etree"] >= 0, s1["etree"] + c0, -1)
+        assert np.array_equal(sb["etree"][sl], e1)
+        assert np.array_equal(sb["colcount"][sl], s1["colcount"])
+        lo, hi = sb["lcolptr"][c0], sb["lcolptr"][c0 + N1]
+        assert np.array_equal(sb["lcolptr"][c0:c0 + N1 + 1] - lo, s1["lcolptr"])
+        assert np.array_equal(sb["lrowind"][lo:hi], s1["lrowind"] + c0)
+        ns = k1.nsuper
+        assert np.array_equal(sb["super_ptr"][sp:sp + ns], s1["super_ptr"][:ns] + c0)
+        sp += ns
+        cp1, ri1 = k1.pattern()
+        assert np.array_equal(cpb[c0:c0 + N1 + 1] - cpb[c0], cp1)
+        assert np.array_equal(rib[cpb[c0]:cpb[c0 + N1]], ri1 + c0)
+        nz += k1.nnzL
+    assert nz == kb.nnzL and sp == kb.nsuper
+
+
+def test_kernel_model_counts():
+    """Per-kernel launches per step follow the schedule: one launch per
+    non-empty level list, one for every once-per-step kernel."""
+    from paper_2510_13333_amd.ncl import KERNELS
+    k = KKT(G.config_network(2))
+    m = {n: k.kernel_model(i) for i, n in enumerate(KERNELS)}
+    assert m["values"] == (0, 0)
+    for n in ("assemble", "border_schur", "border_sum", "border_factor", "status", "sol_load", "sol_bpart",
+              "sol_border", "sol_scale", "sol_store"):
+        assert m[n][0] == 1 and m[n][1] > 0, n
+    for n in ("fac_gather", "fac_rows", "sol_bwd_gather"):
+        assert m[n][0] >= 5
+    assert m["sol_fwd_diag"] == m["sol_bwd_diag"]
+    # assembly reads z and sigma and writes every K value
+    assert m["assemble"][1] == 8 * (2 * k.N + k.nnzK)
