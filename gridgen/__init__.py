@@ -312,6 +312,19 @@ def draw_rhs(N: int, nrhs: int, cfg: int, instance: int = 0, iteration: int = 0)
     return g.standard_normal((nrhs, N))
 
 
+def draw_loads(net: Network, cfg: int, instance: int = 0, iteration: int = 0) -> np.ndarray:
+    """Active loads pd ~ U[0,1] p.u. per bus (reactive loads are 0.3 pd)."""
+    g = rng(cfg, instance, 7000 + iteration)
+    return g.uniform(0.0, 1.0, net.nb)
+
+
+def draw_directions(n: int, count: int, cfg: int, instance: int = 0) -> np.ndarray:
+    """Unit-norm random directions (count, n) for finite-difference checks."""
+    g = rng(cfg, instance, 8000)
+    d = g.standard_normal((count, n))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
 # ---------------------------------------------------------------- configurations
 
 CONFIGS = {

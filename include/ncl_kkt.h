@@ -103,13 +103,20 @@ typedef struct {
  * z: primal values at primal positions and multipliers at dual positions
  *    (CUP/CLO rows hold the complementarity multiplier nu0).
  * sigma: the barrier diagonal Sigma at primal positions (W0^{-1} Xi etc.,
- *    must be > 0); at CUP/CLO rows the slack s of W1 W2 e <= t; ignored
- *    elsewhere.
- * rho: augmented-Lagrangian penalty (> 0). */
+ *    must be > 0 unless the row's Hessian makes K11 definite); at CUP/CLO
+ *    rows the slack s of W1 W2 e <= t; at any other dual row an extra
+ *    diagonal omega >= 0 (an eliminated inequality slack, block C), so that
+ *    the row's diagonal is -(1/rho + omega).
+ * rho: augmented-Lagrangian penalty (> 0).
+ * flags: NCL_NO_SHIFT assembles K without the diagonal-dominance shift
+ *    delta (the exact Newton matrix, e.g. at a solution whose K11 is known
+ *    to be positive definite on the relevant subspace); 0 otherwise. */
+#define NCL_NO_SHIFT 1u
 typedef struct {
     const double *z;
     const double *sigma;
     double rho;
+    uint32_t flags;
 } ncl_kkt_point;
 
 /* Factorisation report (ncl_kkt_info).  npos/nneg/nzero count the signs of
@@ -248,6 +255,44 @@ int ncl_kkt_solve_adjoint(ncl_kkt *h, const double *db, double *dx, int32_t nrhs
 void ncl_kkt_destroy(ncl_kkt *h);
 const char *ncl_status_string(int status);
 
+/* ---------------------------------------------------------------- dispatch map
+ * The stationarity F(z; pd) = 0 of the NCL subproblem (Section III, fixed
+ * rho, multiplier estimate 0, barrier parameter mu) of the corrective SCOPF
+ * without PV/PQ rows: objective sum_g c2 pg^2 + log barriers of vm in
+ * [vmin, vmax], qg in [-qmax, qmax], pg in [0, pmax] + (eps/2) va_ref^2 per
+ * block (bus 0's angle), balance rows c(w; pd) with loads pd (P) and
+ * qd_ratio * pd (Q) in every block, flow rows h <= smax2 with an eliminated
+ * slack t = mu / y.  Its Jacobian is the KKT matrix assembled with
+ * NCL_NO_SHIFT and the sigma this call returns.  Networks with NCL_PVPQ are
+ * rejected. */
+typedef struct {
+    const double *pd;      /* DEVICE [nbus of the network] active loads */
+    double qd_ratio;
+    double mu, rho;
+    double vmin, vmax, qmax, pmax, smax2, eps;
+} ncl_nlp;
+
+/* Layout kinds (HOST out, [N]): for each global column, 1 vm, 2 va, 3 qg,
+ * 4 pg, 5 P balance row, 6 Q balance row, 7 flow row, 0 anything else
+ * (complementarity variables and rows, border vm0). */
+enum { NCL_L_OTHER = 0, NCL_L_VM, NCL_L_VA, NCL_L_QG, NCL_L_PG, NCL_L_ROWP, NCL_L_ROWQ, NCL_L_FLOW };
+int ncl_kkt_layout_kinds(const ncl_kkt *h, uint8_t *kinds);
+
+/* F (DEVICE [N]) = F(z; pd) and sigma (DEVICE [N]) = the barrier Hessian
+ * (+ eps on reference angles) at primal rows, mu / y^2 at flow rows, 0 at
+ * balance rows.  z, F and sigma in layout order; F and sigma must not
+ * alias z.  Asynchronous on stream.  NCL_ERR_ARG for a pattern handle, a
+ * batch of several networks or a network with PV/PQ rows; NCL_ERR_STATE if
+ * no workspace is bound. */
+int ncl_kkt_residual(ncl_kkt *h, const ncl_nlp *p, const double *z, double *F, double *sigma, void *stream);
+
+/* Fraction-to-boundary step: *alpha (DEVICE, one double) = the largest
+ * a <= 1 such that z + a dz keeps every barrier argument of the dispatch
+ * map at least (1 - tau) of its current value (vm, qg, pg inside their
+ * bounds, flow-row multipliers positive).  Asynchronous on stream. */
+int ncl_kkt_max_step(ncl_kkt *h, const ncl_nlp *p, const double *z, const double *dz, double tau, double *alpha,
+                     void *stream);
+
 /* ---------------------------------------------------------------- measurement
  * Kernel kinds: every launch of the library runs exactly one kernel of one
  * of these kinds.  A "step" below is one assemble, one factor and one solve
@@ -272,6 +317,8 @@ enum {
     NCL_K_SOL_BWD_GATHER,   /* k_sol_bwd_gather, per level */
     NCL_K_SOL_BWD_DIAG,     /* k_sol_bwd_diag, per level */
     NCL_K_SOL_STORE,        /* k_sol_store */
+    NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
+    NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */
     NCL_K_COUNT
 };
 

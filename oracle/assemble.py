@@ -15,7 +15,8 @@ What is built (Section IV-B, Newton system and the blocks A, B, C):
   nu0 entry on each (w1, w2) off-diagonal pair of the complementarity
   products (the V0 term of block A).
 * C = diag(1/rho) on every row, plus s/nu0 on the complementarity rows
-  (the V0^{-1} S term of block C).
+  (the V0^{-1} S term of block C), plus sigma on any other dual row (the
+  same term for an eliminated inequality slack; zero unless given).
 * Sigma = primal barrier diagonal (W0^{-1} Xi etc.), given as an input.
 * delta_i = max(0, sum_{j!=i} |H_ij| - H_ii): a per-row shift that makes
   H + diag(delta) diagonally dominant, so that K is quasi-definite at any
@@ -279,13 +280,17 @@ def assemble(net, z, sigma, diag_shift=True):
     np.add.at(jsum, inv, jv)
     Jr, Jc = uk // N, uk % N
 
-    # dual diagonal: -1/rho, and -(1/rho + s/nu0) on complementarity rows
+    # dual diagonal: -1/rho, -(1/rho + s/nu0) on complementarity rows, and
+    # -(1/rho + sigma) on any other row with a nonzero sigma (an eliminated
+    # inequality slack, block C)
     duals = np.flatnonzero(~pos.is_primal)
     ddiag = np.full(duals.shape[0], -1.0 / net.rho)
+    cmask = np.zeros(duals.shape[0], bool)
     if net.pvpq:
         crow = pos.rowC[1:, 3:5].ravel()
         cmask = np.isin(duals, crow)
         ddiag[cmask] -= sigma[duals[cmask]] / z[duals[cmask]]
+    ddiag[~cmask] -= sigma[duals[~cmask]]
 
     low = Hr >= Hc
     rows = np.concatenate([Hr[low], Jr, duals])

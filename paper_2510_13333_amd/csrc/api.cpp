@@ -188,6 +188,8 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(t.gen_slot));
         o.push_back(L.vec(t.perm));
         o.push_back(L.vec(col_primal(t)));
+        o.push_back(L.vec(t.bus_gen));
+        o.push_back(L.vec(t.lkind));
     }
     p.tdev = L.take(nullptr, sizeof(ncl::TemplDev) * h.tmpl.size());
     p.bdev = L.take(nullptr, sizeof(ncl::BlockDev) * size_t(h.nblk));
@@ -378,6 +380,8 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
         case NCL_K_SOL_LOAD:
         case NCL_K_SOL_SCALE:
         case NCL_K_SOL_STORE: return a.dint > 0;
+        case NCL_K_RESIDUAL: return a.asm_threads + a.gp_tot > 0;
+        case NCL_K_MAX_STEP: return true;
         default: return l.nw > 0;
     }
 }
@@ -681,6 +685,8 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.gen_slot = reinterpret_cast<const int32_t *>(at(23));
         d.perm = reinterpret_cast<const int32_t *>(at(24));
         d.col_primal = reinterpret_cast<const uint8_t *>(at(25));
+        d.bus_gen = reinterpret_cast<const int32_t *>(at(26));
+        d.lkind = reinterpret_cast<const uint8_t *>(at(27));
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
     std::vector<ncl::BlockDev> bdev(h.nblk);
@@ -743,10 +749,12 @@ int ncl_kkt_assemble(ncl_kkt *k, const ncl_kkt_point *pt, void *stream) {
     if (!k || !pt || !pt->z || !pt->sigma || !(pt->rho > 0)) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.bound || !h.from_network) return NCL_ERR_STATE;
+    if (pt->flags & ~NCL_NO_SHIFT) return NCL_ERR_ARG;
     ncl::LaunchArgs l;
     l.z = pt->z;
     l.sig = pt->sigma;
     l.rho = pt->rho;
+    l.flags = pt->flags;
     return hip_rc(run(h, NCL_K_ASSEMBLE, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
 }
 
@@ -941,11 +949,65 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
     return NCL_OK;
 }
 
+int ncl_kkt_layout_kinds(const ncl_kkt *k, uint8_t *kinds) {
+    if (!k || !kinds) return NCL_ERR_ARG;
+    const Handle &h = k->h;
+    if (!h.from_network) return NCL_ERR_ARG;
+    static_assert(int(ncl::LK_VM) == NCL_L_VM && int(ncl::LK_FLOW) == NCL_L_FLOW, "kind codes");
+    for (const ncl::Inst &I : h.inst) {
+        for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
+            const Template &t = h.tmpl[h.block_tmpl[b]];
+            std::memcpy(kinds + h.block_col0[b], t.lkind.data(), size_t(t.n));
+        }
+        for (int j = 0; j < I.nbd; j++) kinds[I.bstart + j] = j < I.ng ? NCL_L_PG : NCL_L_OTHER;
+    }
+    return NCL_OK;
+}
+
+static int nlp_check(const Handle &h, const ncl_nlp *p) {
+    if (!p || !p->pd || !(p->mu > 0) || !(p->rho > 0) || !(p->vmax > p->vmin) || !(p->qmax > 0) || !(p->pmax > 0) ||
+        !(p->smax2 > 0) || p->eps < 0)
+        return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_PVPQ)) return NCL_ERR_ARG;
+    if (!h.bound) return NCL_ERR_STATE;
+    return NCL_OK;
+}
+
+int ncl_kkt_residual(ncl_kkt *k, const ncl_nlp *p, const double *z, double *F, double *sigma, void *stream) {
+    if (!k || !z || !F || !sigma || F == z || sigma == z || F == sigma) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    const int rc = nlp_check(h, p);
+    if (rc) return rc;
+    ncl::LaunchArgs l;
+    l.z = z;
+    l.nlp = *p;
+    l.rho = p->rho;
+    l.F = F;
+    l.sigma_out = sigma;
+    return hip_rc(run(h, NCL_K_RESIDUAL, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ncl_kkt_max_step(ncl_kkt *k, const ncl_nlp *p, const double *z, const double *dz, double tau, double *alpha,
+                     void *stream) {
+    if (!k || !z || !dz || !alpha || !(tau > 0 && tau < 1)) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    const int rc = nlp_check(h, p);
+    if (rc) return rc;
+    ncl::LaunchArgs l;
+    l.z = z;
+    l.dz = dz;
+    l.nlp = *p;
+    l.tau = tau;
+    l.alpha = alpha;
+    return hip_rc(run(h, NCL_K_MAX_STEP, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
+}
+
 const char *ncl_kernel_name(int kind) {
     static const char *names[NCL_K_COUNT] = {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
-        "k_sol_bpart", "k_sol_border", "k_sol_scale", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store"};
+        "k_sol_bpart", "k_sol_border", "k_sol_scale", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
+        "k_residual", "k_max_step"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }
 

@@ -29,6 +29,12 @@ struct LaunchArgs {
     int nw = 0;
     const double *z = nullptr, *sig = nullptr;   // assembly state
     double rho = 0.0;
+    uint32_t flags = 0;                          // NCL_NO_SHIFT
+    ncl_nlp nlp{};                               // dispatch map: parameters, outputs, step
+    double *F = nullptr, *sigma_out = nullptr;
+    const double *dz = nullptr;
+    double tau = 0.0;
+    double *alpha = nullptr;
     const double *src = nullptr;                 // value conversion
     double *dst = nullptr;
     bool to_internal = false;

@@ -195,9 +195,10 @@ __device__ inline int64_t zi(int64_t bstart, const BlockDev &B, int n, int32_t x
 // neighbouring interleaved values; then the border pg diagonal of every
 // instance.
 __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__restrict__ z,
-                                                  const double *__restrict__ sig, double rho) {
+                                                  const double *__restrict__ sig, double rho, int noshift) {
     const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const double irho = 1.0 / rho;
+    const double shift = noshift ? 0.0 : 1.0;    // diagonal-dominance shift on (1) or off (0)
     if (tid >= a.asm_threads) {
         const int64_t gg = tid - a.asm_threads;
         if (gg >= a.gp_tot) return;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         const int bidx = I.border_pg[g];
         const int32_t p = I.kbb_pos[size_t(bidx) * I.nbd + bidx];
         const double h = 2.0 * I.gen_c2[g];
-        if (p >= 0) a.kval[a.kint + I.kbb0 + p] = h + fmax(0.0, -h) + sig[I.bstart + bidx];
+        if (p >= 0) a.kval[a.kint + I.kbb0 + p] = h + shift * fmax(0.0, -h) + sig[I.bstart + bidx];
         return;
     }
     const TemplDev &T = a.tmpls[find_tmpl(a, tid, &TemplDev::abase)];
@@ -283,12 +284,12 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
                 put(cx, s[LS_FT_VMT], ht[0]);
                 put(cx, s[LS_FT_VAF], ht[3]);
                 put(cx, s[LS_FT_VAT], ht[2]);
-                put(cx, s[LS_FFFF], -irho);
-                put(cx, s[LS_FTFT], -irho);
+                put(cx, s[LS_FFFF], -(irho + sig[zi(bstart, B, n, br[0])]));
+                put(cx, s[LS_FTFT], -(irho + sig[zi(bstart, B, n, br[1])]));
             }
         }
-        const double dv = fmax(0.0, absv + fabs(Hva) - Hvv);
-        const double da = fmax(0.0, absa + fabs(Hva) - Haa);
+        const double dv = shift * fmax(0.0, absv + fabs(Hva) - Hvv);
+        const double da = shift * fmax(0.0, absa + fabs(Hva) - Haa);
         const int32_t *bs = T.bus_slot + size_t(i) * BS_N;
         put(cx, bs[BS_VMVM], Hvv + dv + sig[zi(bstart, B, n, bi[BI_VM])]);
         put(cx, bs[BS_VAVA], Haa + da + sig[zi(bstart, B, n, bi[BI_VA])]);
@@ -297,8 +298,8 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         put(cx, bs[BS_PVA], dPa);
         put(cx, bs[BS_QVM], dQv);
         put(cx, bs[BS_QVA], dQa);
-        put(cx, bs[BS_PP], -irho);
-        put(cx, bs[BS_QQ], -irho);
+        put(cx, bs[BS_PP], -(irho + sig[zi(bstart, B, n, bi[BI_P])]));
+        put(cx, bs[BS_QQ], -(irho + sig[zi(bstart, B, n, bi[BI_Q])]));
         return;
     }
     {
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         put(cx, gs[GS_QGQG], sig[zi(bstart, B, n, gi[GI_QG])]);
         if (T.has_pg_local) {
             const double h = 2.0 * T.gen_c2[g];
-            put(cx, gs[GS_PGPG], h + fmax(0.0, -h) + sig[zi(bstart, B, n, gi[GI_PG])]);
+            put(cx, gs[GS_PGPG], h + shift * fmax(0.0, -h) + sig[zi(bstart, B, n, gi[GI_PG])]);
         }
         if (T.pvpq_rows) {
             const double nup = z[zi(bstart, B, n, gi[GI_NUP])], num = z[zi(bstart, B, n, gi[GI_NUM])];
@@ -335,13 +336,13 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
             put(cx, gs[GS_CLO_SLO], nup);
             put(cx, gs[GS_H_NUM_SUP], n0u);
             put(cx, gs[GS_H_NUP_SLO], n0l);
-            put(cx, gs[GS_NUPNUP], fabs(n0l) + sig[zi(bstart, B, n, gi[GI_NUP])]);
-            put(cx, gs[GS_NUMNUM], fabs(n0u) + sig[zi(bstart, B, n, gi[GI_NUM])]);
-            put(cx, gs[GS_SUPSUP], fabs(n0u) + sig[zi(bstart, B, n, gi[GI_SUP])]);
-            put(cx, gs[GS_SLOSLO], fabs(n0l) + sig[zi(bstart, B, n, gi[GI_SLO])]);
-            put(cx, gs[GS_LL], -irho);
-            put(cx, gs[GS_UU], -irho);
-            put(cx, gs[GS_DD], -irho);
+            put(cx, gs[GS_NUPNUP], shift * fabs(n0l) + sig[zi(bstart, B, n, gi[GI_NUP])]);
+            put(cx, gs[GS_NUMNUM], shift * fabs(n0u) + sig[zi(bstart, B, n, gi[GI_NUM])]);
+            put(cx, gs[GS_SUPSUP], shift * fabs(n0u) + sig[zi(bstart, B, n, gi[GI_SUP])]);
+            put(cx, gs[GS_SLOSLO], shift * fabs(n0l) + sig[zi(bstart, B, n, gi[GI_SLO])]);
+            put(cx, gs[GS_LL], -(irho + sig[zi(bstart, B, n, gi[GI_LIN])]));
+            put(cx, gs[GS_UU], -(irho + sig[zi(bstart, B, n, gi[GI_DUP])]));
+            put(cx, gs[GS_DD], -(irho + sig[zi(bstart, B, n, gi[GI_DLO])]));
             put(cx, gs[GS_CUCU], -(irho + sig[cu] / n0u));
             put(cx, gs[GS_CLCL], -(irho + sig[cl] / n0l));
         }
@@ -1065,6 +1066,199 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, cons
     });
 }
 
+// ------------------------------------------------------------------ dispatch map
+
+// Flow leaving end s of a branch (value and gradient in v_s, v_o, th_s, th_o).
+struct Flow {
+    double P, Q, gP[4], gQ[4];
+};
+
+__device__ inline void branch_flow(double g, double b, double vs, double vo, double ts, double to, Flow &e) {
+    double sn, cs;
+    sincos(ts - to, &sn, &cs);
+    const double A = g * cs + b * sn, Bq = g * sn - b * cs, vv = vs * vo;
+    e.P = g * vs * vs - vv * A;
+    e.Q = -b * vs * vs - vv * Bq;
+    e.gP[0] = 2.0 * g * vs - vo * A;
+    e.gP[1] = -vs * A;
+    e.gP[2] = vv * Bq;
+    e.gP[3] = -vv * Bq;
+    e.gQ[0] = -2.0 * b * vs - vo * Bq;
+    e.gQ[1] = -vs * Bq;
+    e.gQ[2] = -vv * A;
+    e.gQ[3] = vv * A;
+}
+
+// F(z; pd) and the barrier / dual diagonal sigma of the NCL subproblem
+// without PV/PQ rows.  Threads as in the assembly: per template (bus,
+// block) then (generator, block), then the border pg of every instance.
+// Every position of F and sigma is written by exactly one thread: a bus
+// thread writes its vm, va, P and Q rows and, for branches it is the from
+// end of, both flow rows; a generator thread its qg (and a single-block
+// network's pg); a border thread the shared pg, summing its balance-row
+// multipliers over the instance's blocks in block order.
+__global__ __launch_bounds__(256) void k_residual(DevArgs a, const double *__restrict__ z, ncl_nlp q,
+                                                  double *__restrict__ F, double *__restrict__ sg, double rho) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const double irho = 1.0 / rho, mu = q.mu;
+    if (tid >= a.asm_threads) {
+        const int64_t gg = tid - a.asm_threads;
+        if (gg >= a.gp_tot) return;
+        const InstDev &I = a.insts[find_inst(a, gg, &InstDev::gp0)];
+        const int g = int(gg - I.gp0);
+        if (I.nbd == 0 || g >= I.ng) return;
+        const int64_t col = I.bstart + I.border_pg[g];
+        double ysum = 0.0;
+        for (int blk = I.blk0; blk < I.blk0 + I.nblk; blk++) {
+            const BlockDev &B = a.blks[blk];
+            const TemplDev &T = a.tmpls[B.tmpl];
+            const int bus = T.gen_idx[size_t(g) * GI_N + GI_BUS];
+            ysum += z[zi(I.bstart, B, T.n, T.bus_idx[size_t(bus) * BI_N + BI_P])];
+        }
+        const double pg = z[col], lo = pg, hi = q.pmax - pg;
+        F[col] = 2.0 * I.gen_c2[g] * pg - ysum - mu / lo + mu / hi;
+        sg[col] = mu / (lo * lo) + mu / (hi * hi);
+        return;
+    }
+    const TemplDev &T = a.tmpls[find_tmpl(a, tid, &TemplDev::abase)];
+    const int64_t u0 = tid - T.abase;
+    const int64_t nbus_t = int64_t(T.nblk) * T.nbus;
+    const int64_t bstart = a.insts[T.inst].bstart;
+    const int n = T.n;
+    if (u0 < nbus_t) {
+        const int bl = int(u0 % T.nblk), i = int(u0 / T.nblk);
+        const BlockDev B = a.blks[T.blocks[bl]];
+        const int32_t *bi = T.bus_idx + size_t(i) * BI_N;
+        const double vi = z[zi(bstart, B, n, bi[BI_VM])], ti = z[zi(bstart, B, n, bi[BI_VA])];
+        const double yPi = z[zi(bstart, B, n, bi[BI_P])], yQi = z[zi(bstart, B, n, bi[BI_Q])];
+        double Pinj = 0.0, Qinj = 0.0, Fv = 0.0, Fa = 0.0;
+        for (int qa = T.bus_adj_ptr[i]; qa < T.bus_adj_ptr[i + 1]; qa++) {
+            const int32_t e = T.bus_adj[qa];
+            const bool self_from = e >= 0;
+            const int l = self_from ? e : ~e;
+            const int32_t *br = T.br_idx + size_t(l) * 4;
+            const int o = self_from ? br[3] : br[2];
+            const int32_t *bo = T.bus_idx + size_t(o) * BI_N;
+            const double vo = z[zi(bstart, B, n, bo[BI_VM])], to = z[zi(bstart, B, n, bo[BI_VA])];
+            const double yPo = z[zi(bstart, B, n, bo[BI_P])], yQo = z[zi(bstart, B, n, bo[BI_Q])];
+            const int64_t rs = zi(bstart, B, n, self_from ? br[0] : br[1]);   // flow row of the end at i
+            const int64_t ro = zi(bstart, B, n, self_from ? br[1] : br[0]);   // flow row of the other end
+            const double yFs = z[rs], yFo = z[ro];
+            const double st = (l == B.outage) ? 0.0 : 1.0;
+            const double r = T.br_r[l], x = T.br_x[l], den = r * r + x * x;
+            const double g = st * (r / den), b = st * (-x / den);
+            Flow es, eo;
+            branch_flow(g, b, vi, vo, ti, to, es);     // leaving i
+            branch_flow(g, b, vo, vi, to, ti, eo);     // leaving o
+            Pinj += es.P;
+            Qinj += es.Q;
+            // d/dv_i and d/dth_i: index 0/2 of es (i is its sending end), 1/3 of eo
+            const double hs0 = 2.0 * (es.P * es.gP[0] + es.Q * es.gQ[0]);
+            const double hs2 = 2.0 * (es.P * es.gP[2] + es.Q * es.gQ[2]);
+            const double ho1 = 2.0 * (eo.P * eo.gP[1] + eo.Q * eo.gQ[1]);
+            const double ho3 = 2.0 * (eo.P * eo.gP[3] + eo.Q * eo.gQ[3]);
+            Fv += yPi * es.gP[0] + yQi * es.gQ[0] + yPo * eo.gP[1] + yQo * eo.gQ[1] + yFs * hs0 + yFo * ho1;
+            Fa += yPi * es.gP[2] + yQi * es.gQ[2] + yPo * eo.gP[3] + yQo * eo.gQ[3] + yFs * hs2 + yFo * ho3;
+            if (self_from) {
+                const double hs = es.P * es.P + es.Q * es.Q, ho = eo.P * eo.P + eo.Q * eo.Q;
+                F[rs] = hs - q.smax2 - yFs * irho + mu / yFs;
+                sg[rs] = mu / (yFs * yFs);
+                F[ro] = ho - q.smax2 - yFo * irho + mu / yFo;
+                sg[ro] = mu / (yFo * yFo);
+            }
+        }
+        const int gat = T.bus_gen[i];
+        double pgv = 0.0, qgv = 0.0;
+        if (gat >= 0) {
+            const int32_t *gi = T.gen_idx + size_t(gat) * GI_N;
+            pgv = z[zi(bstart, B, n, gi[GI_PG])];
+            qgv = z[zi(bstart, B, n, gi[GI_QG])];
+        }
+        const double pd = q.pd[i];
+        const int64_t cP = zi(bstart, B, n, bi[BI_P]), cQ = zi(bstart, B, n, bi[BI_Q]);
+        F[cP] = Pinj - pgv + pd - yPi * irho;
+        sg[cP] = 0.0;
+        F[cQ] = Qinj - qgv + q.qd_ratio * pd - yQi * irho;
+        sg[cQ] = 0.0;
+        const int64_t cv = zi(bstart, B, n, bi[BI_VM]), ca = zi(bstart, B, n, bi[BI_VA]);
+        const double lo = vi - q.vmin, hi = q.vmax - vi;
+        F[cv] = Fv - mu / lo + mu / hi;
+        sg[cv] = mu / (lo * lo) + mu / (hi * hi);
+        F[ca] = Fa + (i == 0 ? q.eps * ti : 0.0);
+        sg[ca] = i == 0 ? q.eps : 0.0;
+        return;
+    }
+    {
+        const int64_t u = u0 - nbus_t;
+        const int bl = int(u % T.nblk), g = int(u / T.nblk);
+        const BlockDev B = a.blks[T.blocks[bl]];
+        const int32_t *gi = T.gen_idx + size_t(g) * GI_N;
+        const int bus = gi[GI_BUS];
+        const int32_t *bb = T.bus_idx + size_t(bus) * BI_N;
+        const int64_t cq = zi(bstart, B, n, gi[GI_QG]);
+        const double qg = z[cq], lo = qg + q.qmax, hi = q.qmax - qg;
+        F[cq] = -z[zi(bstart, B, n, bb[BI_Q])] - mu / lo + mu / hi;
+        sg[cq] = mu / (lo * lo) + mu / (hi * hi);
+        if (T.has_pg_local) {
+            const int64_t cp = zi(bstart, B, n, gi[GI_PG]);
+            const double pg = z[cp], pl = pg, ph = q.pmax - pg;
+            F[cp] = 2.0 * T.gen_c2[g] * pg - z[zi(bstart, B, n, bb[BI_P])] - mu / pl + mu / ph;
+            sg[cp] = mu / (pl * pl) + mu / (ph * ph);
+        }
+    }
+}
+
+// Fraction-to-boundary step over every barrier argument (one workgroup:
+// the elements are strided over its threads, then reduced in a fixed order).
+constexpr int kStepThreads = 1024;
+
+__device__ inline double step_limit(double x, double dx, double lo, double hi, double tau) {
+    double al = 1.0;
+    if (dx < 0.0 && lo > -INFINITY) al = fmin(al, tau * (x - lo) / -dx);
+    if (dx > 0.0 && hi < INFINITY) al = fmin(al, tau * (hi - x) / dx);
+    return al;
+}
+
+__global__ __launch_bounds__(kStepThreads) void k_max_step(DevArgs a, const double *__restrict__ z,
+                                                          const double *__restrict__ dz, ncl_nlp q, double tau,
+                                                          double *alpha) {
+    __shared__ double red[kStepThreads / 64];
+    double al = 1.0;
+    const int64_t total = a.dint + a.nbd_tot;
+    for (int64_t idx = threadIdx.x; idx < total; idx += kStepThreads) {
+        int64_t col;
+        uint8_t kind;
+        if (idx < a.dint) {
+            const TemplDev &T = a.tmpls[find_tmpl(a, idx, &TemplDev::dbase)];
+            const int64_t off = idx - T.dbase;
+            const int j = int(off / T.nblk), bl = int(off % T.nblk);
+            col = a.blks[T.blocks[bl]].col0 + j;
+            kind = T.lkind[j];
+        } else {
+            const int64_t j = idx - a.dint;
+            const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
+            col = I.bstart + (j - I.bd0);
+            kind = LK_PG;            // the border of a network without PV/PQ rows holds pg
+        }
+        const double x = z[col], dx = dz[col];
+        switch (kind) {
+            case LK_VM: al = fmin(al, step_limit(x, dx, q.vmin, q.vmax, tau)); break;
+            case LK_QG: al = fmin(al, step_limit(x, dx, -q.qmax, q.qmax, tau)); break;
+            case LK_PG: al = fmin(al, step_limit(x, dx, 0.0, q.pmax, tau)); break;
+            case LK_FLOW: al = fmin(al, step_limit(x, dx, 0.0, INFINITY, tau)); break;
+            default: break;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) al = fmin(al, __shfl_xor(al, o));
+    if (lane_id() == 0) red[threadIdx.x >> 6] = al;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < kStepThreads / 64; w++) m = fmin(m, red[w]);
+        *alpha = m;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline unsigned waves_grid(int nw) { return unsigned((nw + (kWG / 64) - 1) / (kWG / 64)); }
@@ -1080,7 +1274,9 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
     switch (kind) {
         case NCL_K_ASSEMBLE: {
             const int64_t total = a.asm_threads + a.gp_tot;
-            if (total) hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, l.z, l.sig, l.rho);
+            if (total)
+                hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, l.z, l.sig, l.rho,
+                                   (l.flags & NCL_NO_SHIFT) ? 1 : 0);
             break;
         }
         case NCL_K_VALUES: {
@@ -1154,6 +1350,16 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         case NCL_K_SOL_STORE:
             if (a.dint) hipLaunchKernelGGL(k_sol_store, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y, l.x);
+            break;
+        case NCL_K_RESIDUAL: {
+            const int64_t total = a.asm_threads + a.gp_tot;
+            if (total)
+                hipLaunchKernelGGL(k_residual, dim3(elems_grid(total)), dim3(256), 0, st, a, l.z, l.nlp, l.F,
+                                   l.sigma_out, l.rho);
+            break;
+        }
+        case NCL_K_MAX_STEP:
+            hipLaunchKernelGGL(k_max_step, dim3(1), dim3(kStepThreads), 0, st, a, l.z, l.dz, l.nlp, l.tau, l.alpha);
             break;
         default:
             return hipErrorInvalidValue;

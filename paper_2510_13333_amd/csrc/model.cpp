@@ -307,6 +307,21 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
             int32_t *bi = &t.br_idx[size_t(l) * 4];
             bi[0] = L.rFf[l]; bi[1] = L.rFt[l]; bi[2] = f; bi[3] = tt;
         }
+        t.bus_gen.assign(nb, -1);
+        for (int g = 0; g < ng; g++) t.bus_gen[net.gb[g]] = g;
+        t.lkind.assign(n, LK_OTHER);
+        auto kind = [&](const std::vector<int32_t> &v, LocalKind k) {
+            for (int32_t x : v)
+                if (x >= 0 && x < n) t.lkind[x] = k;
+        };
+        kind(L.vm, LK_VM);
+        kind(L.va, LK_VA);
+        kind(L.qg, LK_QG);
+        kind(L.pg, LK_PG);
+        kind(L.rP, LK_ROWP);
+        kind(L.rQ, LK_ROWQ);
+        kind(L.rFf, LK_FLOW);
+        kind(L.rFt, LK_FLOW);
         t.gen_idx.assign(size_t(ng) * GI_N, -1);
         t.gen_slot.assign(size_t(ng) * GS_N, -1);
         for (int g = 0; g < ng; g++) {

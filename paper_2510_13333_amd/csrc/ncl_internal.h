@@ -112,7 +112,12 @@ struct TemplDev {
     const int32_t *gen_slot;       // [ng][GS_N]
     const int32_t *perm;           // [n] factor order -> layout-local
     const uint8_t *col_primal;     // [n] expected pivot sign (1: positive) in factor order
+    const int32_t *bus_gen;        // [nb] generator at the bus or -1
+    const uint8_t *lkind;          // [n] layout-local kind (LK_*), for the dispatch map
 };
+
+// Layout-local kinds used by the dispatch-map kernels (bounds and rows).
+enum LocalKind : uint8_t { LK_OTHER = 0, LK_VM, LK_VA, LK_QG, LK_PG, LK_ROWP, LK_ROWQ, LK_FLOW };
 
 // Per-instance (per-network) border data of a batch.
 struct InstDev {
@@ -151,7 +156,8 @@ struct Template {
     bool pg_local = false;
     std::vector<int32_t> blocks;   // global ids of the blocks using this template
     // model tables (layout-local; border refs n + b)
-    std::vector<int32_t> bus_idx, bus_slot, bus_adj_ptr, bus_adj, br_slot, br_idx, gen_idx, gen_slot;
+    std::vector<int32_t> bus_idx, bus_slot, bus_adj_ptr, bus_adj, br_slot, br_idx, gen_idx, gen_slot, bus_gen;
+    std::vector<uint8_t> lkind;
     // lower CSC pattern in layout-local numbering (rows may be n + b)
     std::vector<int64_t> colptr;
     std::vector<int32_t> rowind;

@@ -21,7 +21,7 @@ NCL_PVPQ = 1
 # kernel kinds (NCL_K_* of ncl_kkt.h), in enum order
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
            "border_factor", "status_init", "status", "sol_load", "sol_fwd_gather", "sol_fwd_diag", "sol_bpart",
-           "sol_border", "sol_scale", "sol_bwd_gather", "sol_bwd_diag", "sol_store"]
+           "sol_border", "sol_scale", "sol_bwd_gather", "sol_bwd_diag", "sol_store", "residual", "max_step"]
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
           -4: "call out of order", -5: "zero pivot", -6: "pivot of the wrong sign (inertia)",
@@ -45,8 +45,19 @@ class _Opts(ctypes.Structure):
     _fields_ = [("relax_maxw", ctypes.c_int32), ("relax_znum", ctypes.c_int32), ("relax_zden", ctypes.c_int32)]
 
 
+NCL_NO_SHIFT = 1
+
+
 class _Point(ctypes.Structure):
-    _fields_ = [("z", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("rho", ctypes.c_double)]
+    _fields_ = [("z", ctypes.c_void_p), ("sigma", ctypes.c_void_p), ("rho", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+class _Nlp(ctypes.Structure):
+    _fields_ = [("pd", ctypes.c_void_p), ("qd_ratio", ctypes.c_double), ("mu", ctypes.c_double),
+                ("rho", ctypes.c_double), ("vmin", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("qmax", ctypes.c_double), ("pmax", ctypes.c_double), ("smax2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -98,6 +109,9 @@ def load():
         "ncl_kkt_kernel_model": ([P, i32, P, P], ctypes.c_int),
         "ncl_kkt_profile": ([P, i32], ctypes.c_int),
         "ncl_kkt_profile_read": ([P, P, P], ctypes.c_int),
+        "ncl_kkt_residual": ([P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_layout_kinds": ([P, P], ctypes.c_int),
+        "ncl_kkt_max_step": ([P, P, P, P, ctypes.c_double, P, P], ctypes.c_int),
         "ncl_status_string": ([ctypes.c_int], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -245,8 +259,9 @@ class KKT:
             raise ValueError("tensor too short")
         return ctypes.c_void_p(t.data_ptr())
 
-    def assemble(self, z, sigma, rho):
-        pt = _Point(self._dev(z, self.N), self._dev(sigma, self.N), float(rho))
+    def assemble(self, z, sigma, rho, shift=True):
+        """K at state (z, sigma); shift=False assembles without the diagonal-dominance shift."""
+        pt = _Point(self._dev(z, self.N), self._dev(sigma, self.N), float(rho), 0 if shift else NCL_NO_SHIFT)
         self._pt = (z, sigma)
         _check("ncl_kkt_assemble", load().ncl_kkt_assemble(self._h, ctypes.byref(pt), _stream_ptr()))
 
@@ -294,6 +309,40 @@ class KKT:
 
     def solve_adjoint(self, b, out=None):
         return self._solve("ncl_kkt_solve_adjoint", b, out)
+
+    # ------------------------------------------------------------ dispatch map
+    def layout_kinds(self):
+        """Kind code (NCL_L_*) of every global column, host uint8 array."""
+        out = np.empty(self.N, np.uint8)
+        _check("ncl_kkt_layout_kinds", load().ncl_kkt_layout_kinds(self._h, _np_ptr(out)))
+        return out
+
+    @staticmethod
+    def _nlp(pd, p):
+        return _Nlp(ctypes.c_void_p(pd.data_ptr()), float(p["qd_ratio"]), float(p["mu"]), float(p["rho"]),
+                    float(p["vmin"]), float(p["vmax"]), float(p["qmax"]), float(p["pmax"]), float(p["smax2"]),
+                    float(p["eps"]))
+
+    def residual(self, z, pd, p, F=None, sigma=None):
+        """F(z; pd) and sigma of the dispatch map (device tensors); p: dict of ncl_nlp fields."""
+        import torch
+        F = torch.empty_like(z) if F is None else F
+        sigma = torch.empty_like(z) if sigma is None else sigma
+        self._dev(pd)
+        q = self._nlp(pd, p)
+        _check("ncl_kkt_residual", load().ncl_kkt_residual(self._h, ctypes.byref(q), self._dev(z, self.N),
+                                                           self._dev(F, self.N), self._dev(sigma, self.N),
+                                                           _stream_ptr()))
+        return F, sigma
+
+    def max_step(self, z, dz, pd, p, tau, out):
+        """Writes the fraction-to-boundary step length into the 1-element device tensor out."""
+        self._dev(pd)
+        q = self._nlp(pd, p)
+        _check("ncl_kkt_max_step", load().ncl_kkt_max_step(self._h, ctypes.byref(q), self._dev(z, self.N),
+                                                           self._dev(dz, self.N), float(tau), self._dev(out),
+                                                           _stream_ptr()))
+        return out
 
     # ------------------------------------------------------------ measurement
     @staticmethod
