@@ -319,6 +319,7 @@ enum {
     NCL_K_SOL_STORE,        /* k_sol_store */
     NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
     NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */
+    NCL_K_INTERLEAVE,       /* k_interleave: the state transposed to the blocks' interleaved order (assembly) */
     NCL_K_COUNT
 };
 

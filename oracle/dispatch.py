@@ -201,6 +201,8 @@ def newton(net, pd, p: NLP, z0=None, step_tol=1e-10, maxit=100, verbose=False):
                 if nt <= (1.0 - 1e-4 * alpha) * nrm or alpha < 1e-10:
                     break
                 alpha *= 0.5
+            if alpha < 1e-10 and np.all(np.abs(dz) <= 1e-6 * (1.0 + np.abs(z))):
+                break                 # at the rounding floor of |F| with a tiny remaining step
             z, F, sig, nrm = zt, Ft, sigt, nt
             total += 1
             if verbose:

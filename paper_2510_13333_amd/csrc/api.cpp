@@ -127,7 +127,8 @@ struct Plan {
     std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
     std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
     size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, tables_end = 0;
-    size_t kval = 0, lpan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, stat = 0, total = 0;
+    size_t kval = 0, lpan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
+           total = 0;
 };
 
 std::vector<uint8_t> col_primal(const Template &t) {
@@ -212,6 +213,8 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     p.sbb = L.take(nullptr, sizeof(double) * size_t(h.npk_tot));
     p.ybuf = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot) * size_t(nrhs));
     p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.cp_tot));
+    p.zint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
+    p.sint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
     p.stat = L.take(nullptr, sizeof(int64_t) * 8);
     p.total = L.off;
     return p;
@@ -234,6 +237,9 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.npk_tot = h.npk_tot;
     a.asm_threads = h.asm_threads;
     a.gp_tot = h.gp_tot;
+    a.tiles = h.tiles;
+    a.zint = h.d.zint;
+    a.sint = h.d.sint;
     a.kval = h.d.kval;
     a.lpan = h.d.lpan;
     a.dval = h.d.dval;
@@ -347,8 +353,9 @@ void kernel_model(Handle &h) {
             B[NCL_K_SOL_BPART] += nb * D * (I.nbd + up + uk);
         }
     }
-    L[NCL_K_ASSEMBLE] = 1;
-    B[NCL_K_ASSEMBLE] = D * (2 * h.N + h.kint + h.nbb_tot);
+    L[NCL_K_INTERLEAVE] = L[NCL_K_ASSEMBLE] = h.from_network ? 1 : 0;
+    B[NCL_K_INTERLEAVE] = h.from_network ? D * 4 * (h.dint + h.nbd_tot) : 0;
+    B[NCL_K_ASSEMBLE] = h.from_network ? D * (2 * h.N + h.kint + h.nbb_tot) : 0;
     L[NCL_K_STATUS_INIT] = 1;
     B[NCL_K_STATUS_INIT] = D * 6;
     L[NCL_K_STATUS] = 1;
@@ -381,6 +388,7 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
         case NCL_K_SOL_SCALE:
         case NCL_K_SOL_STORE: return a.dint > 0;
         case NCL_K_RESIDUAL: return a.asm_threads + a.gp_tot > 0;
+        case NCL_K_INTERLEAVE: return a.tiles + a.nbd_tot > 0;
         case NCL_K_MAX_STEP: return true;
         default: return l.nw > 0;
     }
@@ -649,6 +657,7 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.nbus = I.nb;
         d.ngen = I.ng;
         d.abase = h.t_abase[ti];
+        d.tile0 = h.t_tile0[ti];
         d.bd0 = I.bd0;
         d.br_r = reinterpret_cast<const double *>(base + p.ioff[t.inst][3]);
         d.br_x = reinterpret_cast<const double *>(base + p.ioff[t.inst][4]);
@@ -738,6 +747,8 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.d.sbb = reinterpret_cast<double *>(base + p.sbb);
     h.d.ybuf = reinterpret_cast<double *>(base + p.ybuf);
     h.d.cpart = reinterpret_cast<double *>(base + p.cpart);
+    h.d.zint = reinterpret_cast<double *>(base + p.zint);
+    h.d.sint = reinterpret_cast<double *>(base + p.sint);
     h.d.stat = reinterpret_cast<int64_t *>(base + p.stat);
     h.bound = true;
     h.factored = false;
@@ -755,7 +766,10 @@ int ncl_kkt_assemble(ncl_kkt *k, const ncl_kkt_point *pt, void *stream) {
     l.sig = pt->sigma;
     l.rho = pt->rho;
     l.flags = pt->flags;
-    return hip_rc(run(h, NCL_K_ASSEMBLE, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
+    const ncl::DevArgs a = dev_args(h);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (run(h, NCL_K_INTERLEAVE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    return hip_rc(run(h, NCL_K_ASSEMBLE, a, l, st));
 }
 
 int ncl_kkt_set_values(ncl_kkt *k, const double *dvals, void *stream) {
@@ -1007,7 +1021,7 @@ const char *ncl_kernel_name(int kind) {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
         "k_sol_bpart", "k_sol_border", "k_sol_scale", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
-        "k_residual", "k_max_step"};
+        "k_residual", "k_max_step", "k_interleave"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }
 

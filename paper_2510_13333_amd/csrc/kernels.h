@@ -18,7 +18,9 @@ struct DevArgs {
     int64_t dint;               // interleaved pivots; the border pivots of every instance follow
     int64_t nbd_tot, nbb_tot, npk_tot;
     int64_t asm_threads, gp_tot;   // assembly threads of the templates, then of the border pg values
+    int64_t tiles;              // state transpose tiles of all templates
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
+    double *zint, *sint;        // interleaved copies of the state and Sigma (assembly input)
     int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits
     const uint8_t *bprim;       // [nbd_tot] expected sign of the border pivots
 };

@@ -37,7 +37,22 @@ __device__ inline const __attribute__((address_space(4))) T *cs(const T *p) {
     return (const __attribute__((address_space(4))) T *)p;
 }
 
-__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(int((blockIdx.x * kWG + threadIdx.x) >> 6)); }
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b mod 8).  The list kernels renumber them so that each XCD takes one
+// contiguous range of the work list (a bijection of [0, gridDim.x)): items
+// that share data then share an L2.
+constexpr int kXcd = 8;
+
+__device__ inline int xcd_workgroup() {
+    const int G = int(gridDim.x), b = int(blockIdx.x);
+    const int q = G / kXcd, r = G % kXcd;
+    const int x = b % kXcd, i = b / kXcd;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+__device__ inline int wave_id() {
+    return __builtin_amdgcn_readfirstlane(xcd_workgroup() * (kWG / 64) + int(threadIdx.x >> 6));
+}
 __device__ inline int lane_id() { return int(threadIdx.x & 63); }
 
 // Update sums over a contiguous run of terms [t0, t1).  Terms are taken in
@@ -135,8 +150,11 @@ struct EndDeriv {
 //   P = g vs^2 - vs vo (g cos th + b sin th),  Q = -b vs^2 - vs vo (g sin th - b cos th)
 // with th = th_s - th_o.  Adds wP * Hess P + wQ * Hess Q + wF * Hess(P^2 + Q^2)
 // into W (4x4 over v_s, v_o, th_s, th_o, mapped through idx into the branch order).
+// kSwap: the sending end is the branch's to-end, so variable a of the end
+// (v_s, v_o, th_s, th_o) is variable a ^ 1 of the branch order.
+template <bool kSwap>
 __device__ inline void branch_end(double g, double b, double vs, double vo, double ts, double to, double wP,
-                                  double wQ, double wF, const int idx[4], double W[4][4], EndDeriv &e) {
+                                  double wQ, double wF, double W[4][4], EndDeriv &e) {
     double sn, cs;
     sincos(ts - to, &sn, &cs);
     const double A = g * cs + b * sn;
@@ -167,10 +185,55 @@ __device__ inline void branch_end(double g, double b, double vs, double vo, doub
 #pragma unroll
         for (int c = a; c < 4; c++) {
             double h = al * HP[a][c] + be * HQ[a][c] + 2.0 * wF * (e.gP[a] * e.gP[c] + e.gQ[a] * e.gQ[c]);
-            int ia = idx[a], ic = idx[c];
+            const int ia = kSwap ? (a ^ 1) : a, ic = kSwap ? (c ^ 1) : c;
             W[ia][ic] += h;
             if (ia != ic) W[ic][ia] += h;
         }
+}
+
+// The state z and Sigma (layout order) transposed to the interleaved order
+// of the factor storage, layout-local element j of a template's block bl at
+// dbase + j * nblk + bl; the border values of every instance follow at
+// dint + bd0.  Per template the state is an [nblk][n] array (blocks of a
+// template are contiguous in layout order, one block after the other),
+// moved in 64 x 64 tiles through LDS: reads run along j, writes along bl,
+// both coalesced.
+constexpr int kTile = 64;
+
+__global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__restrict__ z,
+                                                    const double *__restrict__ sig) {
+    __shared__ double tile[kTile][kTile + 1];
+    const int64_t t = blockIdx.x;
+    if (t >= a.tiles) {
+        // border values: a plain copy
+        const int64_t i = (t - a.tiles) * 256 + threadIdx.x;
+        if (i < a.nbd_tot) {
+            const InstDev &I = a.insts[find_inst(a, i, &InstDev::bd0)];
+            const int64_t col = I.bstart + (i - I.bd0);
+            a.zint[a.dint + i] = z[col];
+            a.sint[a.dint + i] = sig[col];
+        }
+        return;
+    }
+    const TemplDev &T = a.tmpls[find_tmpl(a, t, &TemplDev::tile0)];
+    const int64_t tt = t - T.tile0;
+    const int nbt = (T.nblk + kTile - 1) / kTile;
+    const int j0 = int(tt / nbt) * kTile, b0 = int(tt % nbt) * kTile;
+    const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    for (int pass = 0; pass < 2; pass++) {
+        const double *src = pass ? sig : z;
+        double *dst = pass ? a.sint : a.zint;
+        for (int r = r0; r < kTile; r += 4) {
+            const int bl = b0 + r, j = j0 + c;
+            if (bl < T.nblk && j < T.n) tile[r][c] = src[a.blks[T.blocks[bl]].col0 + j];
+        }
+        __syncthreads();
+        for (int r = r0; r < kTile; r += 4) {
+            const int j = j0 + r, bl = b0 + c;
+            if (bl < T.nblk && j < T.n) dst[T.dbase + int64_t(j) * T.nblk + bl] = tile[c][r];
+        }
+        __syncthreads();
+    }
 }
 
 struct AsmCtx {
@@ -194,6 +257,13 @@ __device__ inline int64_t zi(int64_t bstart, const BlockDev &B, int n, int32_t x
 // the block index running fastest so that neighbouring threads write
 // neighbouring interleaved values; then the border pg diagonal of every
 // instance.
+// index of layout-local element x of the lane's block in the interleaved state
+struct StateIx {
+    int64_t base, nb, bord;
+    int n;
+    __device__ int64_t operator()(int32_t x) const { return x < n ? base + int64_t(x) * nb : bord + (x - n); }
+};
+
 __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__restrict__ z,
                                                   const double *__restrict__ sig, double rho, int noshift) {
     const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -208,19 +278,21 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         const int bidx = I.border_pg[g];
         const int32_t p = I.kbb_pos[size_t(bidx) * I.nbd + bidx];
         const double h = 2.0 * I.gen_c2[g];
-        if (p >= 0) a.kval[a.kint + I.kbb0 + p] = h + shift * fmax(0.0, -h) + sig[I.bstart + bidx];
+        if (p >= 0) a.kval[a.kint + I.kbb0 + p] = h + shift * fmax(0.0, -h) + a.sint[a.dint + I.bd0 + bidx];
         return;
     }
     const TemplDev &T = a.tmpls[find_tmpl(a, tid, &TemplDev::abase)];
     const int64_t u0 = tid - T.abase;
     const int64_t nbus_t = int64_t(T.nblk) * T.nbus;
-    const int64_t bstart = a.insts[T.inst].bstart;
     const int64_t kbb = a.kint + a.insts[T.inst].kbb0;
+    const double *__restrict__ zs = a.zint;
+    const double *__restrict__ ss = a.sint;
     if (u0 < nbus_t) {
         const int bl = int(u0 % T.nblk), i = int(u0 / T.nblk);
         const BlockDev B = a.blks[T.blocks[bl]];
         const int n = T.n;
         const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb};
+        const StateIx ix{T.dbase + bl, T.nblk, a.dint + T.bd0, n};
         const int32_t *bi = T.bus_idx + size_t(i) * BI_N;
         double Hvv = 0, Haa = 0, Hva = 0, dPv = 0, dPa = 0, dQv = 0, dQa = 0, absv = 0, absa = 0;
         for (int q = cs(T.bus_adj_ptr)[i]; q < cs(T.bus_adj_ptr)[i + 1]; q++) {
@@ -230,31 +302,30 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
             const int32_t *br = T.br_idx + size_t(l) * 4;
             const int f = br[2], t = br[3];
             const int32_t *bf = T.bus_idx + size_t(f) * BI_N, *bt = T.bus_idx + size_t(t) * BI_N;
-            const double vf = z[zi(bstart, B, n, bf[BI_VM])], vt = z[zi(bstart, B, n, bt[BI_VM])];
-            const double tf = z[zi(bstart, B, n, bf[BI_VA])], tt = z[zi(bstart, B, n, bt[BI_VA])];
-            const double yPf = z[zi(bstart, B, n, bf[BI_P])], yQf = z[zi(bstart, B, n, bf[BI_Q])];
-            const double yPt = z[zi(bstart, B, n, bt[BI_P])], yQt = z[zi(bstart, B, n, bt[BI_Q])];
-            const double yFf = z[zi(bstart, B, n, br[0])], yFt = z[zi(bstart, B, n, br[1])];
+            const double vf = zs[ix(bf[BI_VM])], vt = zs[ix(bt[BI_VM])];
+            const double tf = zs[ix(bf[BI_VA])], tt = zs[ix(bt[BI_VA])];
+            const double yPf = zs[ix(bf[BI_P])], yQf = zs[ix(bf[BI_Q])];
+            const double yPt = zs[ix(bt[BI_P])], yQt = zs[ix(bt[BI_Q])];
+            const double yFf = zs[ix(br[0])], yFt = zs[ix(br[1])];
             const double st = (l == B.outage) ? 0.0 : 1.0;
             const double r = T.br_r[l], x = T.br_x[l];
             const double den = r * r + x * x;
             const double g = st * (r / den), b = st * (-x / den);
             double W[4][4] = {};
             EndDeriv ef, et;
-            const int idf[4] = {0, 1, 2, 3}, idt[4] = {1, 0, 3, 2};
-            branch_end(g, b, vf, vt, tf, tt, yPf, yQf, yFf, idf, W, ef);
-            branch_end(g, b, vt, vf, tt, tf, yPt, yQt, yFt, idt, W, et);
-            const int sv = self_from ? 0 : 1, sa = self_from ? 2 : 3, ov = self_from ? 1 : 0, oa = self_from ? 3 : 2;
-            Hvv += W[sv][sv];
-            Haa += W[sa][sa];
-            Hva += W[sv][sa];
-            absv += fabs(W[sv][ov]) + fabs(W[sv][oa]);
-            absa += fabs(W[sa][ov]) + fabs(W[sa][oa]);
-            const EndDeriv &es = self_from ? ef : et;
-            dPv += es.gP[0];
-            dPa += es.gP[2];
-            dQv += es.gQ[0];
-            dQa += es.gQ[2];
+            branch_end<false>(g, b, vf, vt, tf, tt, yPf, yQf, yFf, W, ef);
+            branch_end<true>(g, b, vt, vf, tt, tf, yPt, yQt, yFt, W, et);
+            // this bus's variables are (v, th) = branch variables (0, 2) at the
+            // from end, (1, 3) at the to end; selects keep W in registers
+            Hvv += self_from ? W[0][0] : W[1][1];
+            Haa += self_from ? W[2][2] : W[3][3];
+            Hva += self_from ? W[0][2] : W[1][3];
+            absv += self_from ? fabs(W[0][1]) + fabs(W[0][3]) : fabs(W[1][0]) + fabs(W[1][2]);
+            absa += self_from ? fabs(W[2][1]) + fabs(W[2][3]) : fabs(W[3][0]) + fabs(W[3][2]);
+            dPv += self_from ? ef.gP[0] : et.gP[0];
+            dPa += self_from ? ef.gP[2] : et.gP[2];
+            dQv += self_from ? ef.gQ[0] : et.gQ[0];
+            dQa += self_from ? ef.gQ[2] : et.gQ[2];
             if (self_from) {
                 const int32_t *s = T.br_slot + size_t(l) * LS_N;
                 put(cx, s[LS_VMVM], W[0][1]);
@@ -284,22 +355,22 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
                 put(cx, s[LS_FT_VMT], ht[0]);
                 put(cx, s[LS_FT_VAF], ht[3]);
                 put(cx, s[LS_FT_VAT], ht[2]);
-                put(cx, s[LS_FFFF], -(irho + sig[zi(bstart, B, n, br[0])]));
-                put(cx, s[LS_FTFT], -(irho + sig[zi(bstart, B, n, br[1])]));
+                put(cx, s[LS_FFFF], -(irho + ss[ix(br[0])]));
+                put(cx, s[LS_FTFT], -(irho + ss[ix(br[1])]));
             }
         }
         const double dv = shift * fmax(0.0, absv + fabs(Hva) - Hvv);
         const double da = shift * fmax(0.0, absa + fabs(Hva) - Haa);
         const int32_t *bs = T.bus_slot + size_t(i) * BS_N;
-        put(cx, bs[BS_VMVM], Hvv + dv + sig[zi(bstart, B, n, bi[BI_VM])]);
-        put(cx, bs[BS_VAVA], Haa + da + sig[zi(bstart, B, n, bi[BI_VA])]);
+        put(cx, bs[BS_VMVM], Hvv + dv + ss[ix(bi[BI_VM])]);
+        put(cx, bs[BS_VAVA], Haa + da + ss[ix(bi[BI_VA])]);
         put(cx, bs[BS_VMVA], Hva);
         put(cx, bs[BS_PVM], dPv);
         put(cx, bs[BS_PVA], dPa);
         put(cx, bs[BS_QVM], dQv);
         put(cx, bs[BS_QVA], dQa);
-        put(cx, bs[BS_PP], -(irho + sig[zi(bstart, B, n, bi[BI_P])]));
-        put(cx, bs[BS_QQ], -(irho + sig[zi(bstart, B, n, bi[BI_Q])]));
+        put(cx, bs[BS_PP], -(irho + ss[ix(bi[BI_P])]));
+        put(cx, bs[BS_QQ], -(irho + ss[ix(bi[BI_Q])]));
         return;
     }
     {
@@ -308,20 +379,21 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         const BlockDev B = a.blks[T.blocks[bl]];
         const int n = T.n;
         const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb};
+        const StateIx ix{T.dbase + bl, T.nblk, a.dint + T.bd0, n};
         const int32_t *gi = T.gen_idx + size_t(g) * GI_N;
         const int32_t *gs = T.gen_slot + size_t(g) * GS_N;
         put(cx, gs[GS_PPG], -1.0);
         put(cx, gs[GS_QQG], -1.0);
-        put(cx, gs[GS_QGQG], sig[zi(bstart, B, n, gi[GI_QG])]);
+        put(cx, gs[GS_QGQG], ss[ix(gi[GI_QG])]);
         if (T.has_pg_local) {
             const double h = 2.0 * T.gen_c2[g];
-            put(cx, gs[GS_PGPG], h + shift * fmax(0.0, -h) + sig[zi(bstart, B, n, gi[GI_PG])]);
+            put(cx, gs[GS_PGPG], h + shift * fmax(0.0, -h) + ss[ix(gi[GI_PG])]);
         }
         if (T.pvpq_rows) {
-            const double nup = z[zi(bstart, B, n, gi[GI_NUP])], num = z[zi(bstart, B, n, gi[GI_NUM])];
-            const double sup = z[zi(bstart, B, n, gi[GI_SUP])], slo = z[zi(bstart, B, n, gi[GI_SLO])];
-            const int64_t cu = zi(bstart, B, n, gi[GI_CUP]), cl = zi(bstart, B, n, gi[GI_CLO]);
-            const double n0u = z[cu], n0l = z[cl];
+            const double nup = zs[ix(gi[GI_NUP])], num = zs[ix(gi[GI_NUM])];
+            const double sup = zs[ix(gi[GI_SUP])], slo = zs[ix(gi[GI_SLO])];
+            const int64_t cu = ix(gi[GI_CUP]), cl = ix(gi[GI_CLO]);
+            const double n0u = zs[cu], n0l = zs[cl];
             put(cx, gs[GS_LIN_NUP], 1.0);
             put(cx, gs[GS_LIN_NUM], -1.0);
             put(cx, gs[GS_LIN_VM], -1.0);
@@ -336,15 +408,15 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
             put(cx, gs[GS_CLO_SLO], nup);
             put(cx, gs[GS_H_NUM_SUP], n0u);
             put(cx, gs[GS_H_NUP_SLO], n0l);
-            put(cx, gs[GS_NUPNUP], shift * fabs(n0l) + sig[zi(bstart, B, n, gi[GI_NUP])]);
-            put(cx, gs[GS_NUMNUM], shift * fabs(n0u) + sig[zi(bstart, B, n, gi[GI_NUM])]);
-            put(cx, gs[GS_SUPSUP], shift * fabs(n0u) + sig[zi(bstart, B, n, gi[GI_SUP])]);
-            put(cx, gs[GS_SLOSLO], shift * fabs(n0l) + sig[zi(bstart, B, n, gi[GI_SLO])]);
-            put(cx, gs[GS_LL], -(irho + sig[zi(bstart, B, n, gi[GI_LIN])]));
-            put(cx, gs[GS_UU], -(irho + sig[zi(bstart, B, n, gi[GI_DUP])]));
-            put(cx, gs[GS_DD], -(irho + sig[zi(bstart, B, n, gi[GI_DLO])]));
-            put(cx, gs[GS_CUCU], -(irho + sig[cu] / n0u));
-            put(cx, gs[GS_CLCL], -(irho + sig[cl] / n0l));
+            put(cx, gs[GS_NUPNUP], shift * fabs(n0l) + ss[ix(gi[GI_NUP])]);
+            put(cx, gs[GS_NUMNUM], shift * fabs(n0u) + ss[ix(gi[GI_NUM])]);
+            put(cx, gs[GS_SUPSUP], shift * fabs(n0u) + ss[ix(gi[GI_SUP])]);
+            put(cx, gs[GS_SLOSLO], shift * fabs(n0l) + ss[ix(gi[GI_SLO])]);
+            put(cx, gs[GS_LL], -(irho + ss[ix(gi[GI_LIN])]));
+            put(cx, gs[GS_UU], -(irho + ss[ix(gi[GI_DUP])]));
+            put(cx, gs[GS_DD], -(irho + ss[ix(gi[GI_DLO])]));
+            put(cx, gs[GS_CUCU], -(irho + ss[cu] / n0u));
+            put(cx, gs[GS_CLCL], -(irho + ss[cl] / n0l));
         }
     }
 }
@@ -598,15 +670,25 @@ __global__ __launch_bounds__(kWG) void k_border_sum(DevArgs a) {
 // 180-row border); the block column of L is staged in LDS.
 constexpr int kBFThreads = 512;    // 8 wavefronts: up to 256 registers each, no spills
 
+// kRes: the whole packed matrix is resident in LDS for the factorisation
+// (copied in at the start and out at the end); otherwise it stays in global
+// memory and only the block column of L is staged in LDS.
+template <bool kRes>
 __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
     extern __shared__ double lds[];
     double *Ld = lds;                  // [kBB][kPS] L of the diagonal block
     double *dd = Ld + kBB * kPS;       // [kBB] its pivots
-    double *Pn = dd + kBB;             // [nbd - kBB][kPS] L of the rows below it
     const InstDev &I = a.insts[blockIdx.x];
     const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
-    double *S = a.sbb + I.sbb0;
+    const int npk = nbd * (nbd + 1) / 2;
+    double *Sg = a.sbb + I.sbb0;
+    double *S = kRes ? dd + kBB : Sg;              // the packed matrix being factored
+    double *Pn = kRes ? nullptr : dd + kBB;        // [nbd - kBB][kPS] L of the rows below the block
     double *Db = a.dval + a.dint + I.bd0;
+    if (kRes) {
+        for (int e = tid; e < npk; e += kBFThreads) S[e] = Sg[e];
+        __syncthreads();
+    }
     for (int b0 = 0; b0 < nbd; b0 += kBB) {
         const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
         const int r0 = b0 + bs, m = nbd - r0;
@@ -669,7 +751,7 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
             for (int j = 0; j < kBB; j++)
                 if (j < bs) {
                     si[j] = x[j];
-                    Pn[t * kPS + j] = x[j];
+                    if (!kRes) Pn[t * kPS + j] = x[j];
                 }
         }
         __syncthreads();
@@ -689,8 +771,11 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     const int ii = 4 * I + u, kk = 4 * K + u;
-                    pi[u] = ii < m ? Pn[ii * kPS + j] : 0.0;
-                    pc[u] = kk < m ? Pn[kk * kPS + j] * dj : 0.0;
+                    // rows of the block column: in S itself when resident
+                    const double *ri = kRes ? S + pk(r0 + ii, b0) : Pn + ii * kPS;
+                    const double *rk = kRes ? S + pk(r0 + kk, b0) : Pn + kk * kPS;
+                    pi[u] = ii < m ? ri[j] : 0.0;
+                    pc[u] = kk < m ? rk[j] * dj : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < 4; u++)
@@ -707,6 +792,8 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
         }
         __syncthreads();
     }
+    if (kRes)
+        for (int e = tid; e < npk; e += kBFThreads) Sg[e] = S[e];
 }
 
 // Pivot signs and magnitudes of the whole factorisation (integer atomics only).
@@ -1268,6 +1355,24 @@ size_t border_lds_bytes(int nbd) {
     return size_t(kBB * kPS + kBB + (nbd > kBB ? nbd - kBB : 0) * kPS) * sizeof(double);
 }
 
+// LDS of the border factor with the whole packed matrix resident
+static size_t border_lds_resident_bytes(int nbd) {
+    return size_t(kBB * kPS + kBB + nbd * (nbd + 1) / 2) * sizeof(double);
+}
+
+// Dynamic LDS a workgroup may use on the current device (queried once).
+static int max_lds_per_workgroup() {
+    static int bytes = -1;
+    if (bytes < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        bytes = v;
+    }
+    return bytes;
+}
+
 // One kernel per call, so that a caller can bracket exactly one kernel
 // with events.
 hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st) {
@@ -1303,13 +1408,17 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         case NCL_K_BORDER_FACTOR:
             if (a.max_nbd) {
-                const size_t lbytes = border_lds_bytes(a.max_nbd);
+                const size_t res = border_lds_resident_bytes(a.max_nbd);
+                const bool resident = res <= size_t(max_lds_per_workgroup());
+                const size_t lbytes = resident ? res : border_lds_bytes(a.max_nbd);
+                const void *fn = resident ? reinterpret_cast<const void *>(&k_border_factor<true>)
+                                          : reinterpret_cast<const void *>(&k_border_factor<false>);
                 if (lbytes > 65536) {
-                    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_border_factor),
-                                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lbytes));
+                    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lbytes));
                     if (e != hipSuccess) return e;
                 }
-                hipLaunchKernelGGL(k_border_factor, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
+                if (resident) hipLaunchKernelGGL(k_border_factor<true>, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
+                else hipLaunchKernelGGL(k_border_factor<false>, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
             }
             break;
         case NCL_K_STATUS_INIT:
@@ -1356,6 +1465,11 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (total)
                 hipLaunchKernelGGL(k_residual, dim3(elems_grid(total)), dim3(256), 0, st, a, l.z, l.nlp, l.F,
                                    l.sigma_out, l.rho);
+            break;
+        }
+        case NCL_K_INTERLEAVE: {
+            const int64_t nt = a.tiles + (a.nbd_tot + 255) / 256;
+            if (nt) hipLaunchKernelGGL(k_interleave, dim3(unsigned(nt)), dim3(256), 0, st, a, l.z, l.sig);
             break;
         }
         case NCL_K_MAX_STEP:

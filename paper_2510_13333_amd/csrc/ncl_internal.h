@@ -78,6 +78,7 @@ struct TemplDev {
     int32_t inst;                  // instance (network) the template belongs to
     int32_t nbus, ngen;            // network sizes (assembly threads per block)
     int64_t abase;                 // first assembly thread of the template
+    int64_t tile0;                 // first 64x64 transpose tile of the template (state interleaving)
     int64_t bd0;                   // the instance's border pivots / solution at dint + bd0
     const double *br_r, *br_x;     // the instance's branch data
     const double *gen_c2;
@@ -239,7 +240,8 @@ struct Handle {
     int64_t nnzL = 0, nsuper = 0, npanel = 0;
     int64_t kint = 0, lint = 0, dint = 0;   // interleaved K values, panels, pivots (all templates)
     int64_t asm_threads = 0;                // template assembly threads (border pg threads follow)
-    std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase;
+    int64_t tiles = 0;                      // 64x64 transpose tiles of all templates
+    std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase, t_tile0;
     Schedule sched;
     // numeric state
     int64_t nrhs_max = 0;
@@ -252,6 +254,7 @@ struct Handle {
         double *kval = nullptr;          // interleaved K, then the border K_bb values of every instance
         double *lpan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
                *cpart = nullptr;
+        double *zint = nullptr, *sint = nullptr;   // state and Sigma in the blocks' interleaved layout order
         int64_t *stat = nullptr;
         TemplDev *tmpl = nullptr;
         BlockDev *blk = nullptr;

@@ -186,7 +186,8 @@ int build_schedule(Handle &h) {
     h.t_lbase.assign(h.tmpl.size(), 0);
     h.t_dbase.assign(h.tmpl.size(), 0);
     h.t_abase.assign(h.tmpl.size(), 0);
-    h.kint = h.lint = h.dint = h.asm_threads = 0;
+    h.t_tile0.assign(h.tmpl.size(), 0);
+    h.kint = h.lint = h.dint = h.asm_threads = h.tiles = 0;
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int64_t nb = int64_t(t.blocks.size());
@@ -194,6 +195,8 @@ int build_schedule(Handle &h) {
         h.t_lbase[ti] = h.lint;
         h.t_dbase[ti] = h.dint;
         h.t_abase[ti] = h.asm_threads;
+        h.t_tile0[ti] = h.tiles;
+        h.tiles += int64_t((t.n + 63) / 64) * ((nb + 63) / 64);
         h.kint += t.colptr[t.n] * nb;
         h.lint += int64_t(t.panel_off.back()) * nb;
         h.dint += int64_t(t.n) * nb;
@@ -209,33 +212,43 @@ int build_schedule(Handle &h) {
     S.f_ptr.assign(1, 0);
     S.d_ptr.assign(1, 0);
     S.g_ptr.assign(1, 0);
+    // Work lists are group-major: within a (level, template) every item of
+    // one block group comes before the next group's, so that contiguous runs
+    // of a list share the same blocks' panels.  The list kernels map
+    // contiguous workgroup ranges to one XCD each, so such a run is served
+    // by one L2.
     for (int l = 0; l < S.nlev; l++) {
         for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
             const Template &t = h.tmpl[ti];
             if (l >= t.nlev) continue;
             const int ng64 = groups(t, 64), ng2 = groups(t, 2);
             if (ng64 > 65535 || ng2 > 65535) return NCL_ERR_ARG;
-            int last_s = -1;
-            for (int32_t k : t.lev_tasks[l]) {
-                const int s = t.task_s[k], p = t.task_p[k];
-                const int w = t.sup[s + 1] - t.sup[s];
-                const int cend = p < w ? p + 1 : w;     // lower triangle of the diagonal block
-                for (int c = 0; c < cend; c++)
-                    for (int g = 0; g < ng64; g++) S.a.push_back(Work{tg(ti, g), t.task_cbase[k] + c});
-                if (w == 1 || p >= w)
-                    for (int g = 0; g < ng64; g++) S.c.push_back(Work{tg(ti, g), k});
-                if (p < w) {
-                    // the diagonal entry's items are exactly the descendants holding this row
-                    const int e = t.task_cbase[k] + p;
-                    if (t.ent_tptr[e + 1] > t.ent_tptr[e])
-                        for (int g = 0; g < ng64; g++) S.f.push_back(Work{tg(ti, g), k});
-                    for (int g = 0; g < ng64; g++) S.g.push_back(Work{tg(ti, g), k});
+            for (int g = 0; g < ng64; g++) {
+                int last_s = -1;
+                for (int32_t k : t.lev_tasks[l]) {
+                    const int s = t.task_s[k], p = t.task_p[k];
+                    const int w = t.sup[s + 1] - t.sup[s];
+                    const int cend = p < w ? p + 1 : w;     // lower triangle of the diagonal block
+                    for (int c = 0; c < cend; c++) S.a.push_back(Work{tg(ti, g), t.task_cbase[k] + c});
+                    if (w == 1 || p >= w) S.c.push_back(Work{tg(ti, g), k});
+                    if (p < w) {
+                        // the diagonal entry's items are exactly the descendants holding this row
+                        const int e = t.task_cbase[k] + p;
+                        if (t.ent_tptr[e + 1] > t.ent_tptr[e]) S.f.push_back(Work{tg(ti, g), k});
+                        S.g.push_back(Work{tg(ti, g), k});
+                    }
+                    if (w > 1 && s != last_s) S.d.push_back(Work{tg(ti, g), s});
+                    last_s = s;
                 }
-                if (w > 1 && s != last_s) {
-                    for (int g = 0; g < ng2; g++) S.b.push_back(Work{tg(ti, g), s});
-                    for (int g = 0; g < ng64; g++) S.d.push_back(Work{tg(ti, g), s});
+            }
+            for (int g = 0; g < ng2; g++) {
+                int last_s = -1;
+                for (int32_t k : t.lev_tasks[l]) {
+                    const int s = t.task_s[k];
+                    const int w = t.sup[s + 1] - t.sup[s];
+                    if (w > 1 && s != last_s) S.b.push_back(Work{tg(ti, g), s});
+                    last_s = s;
                 }
-                last_s = s;
             }
         }
         S.a_ptr.push_back(int32_t(S.a.size()));
@@ -250,10 +263,10 @@ int build_schedule(Handle &h) {
         const int nbd = h.inst[t.inst].nbd;
         const int64_t npk = int64_t(nbd) * (nbd + 1) / 2;
         const int ng64 = groups(t, 64);
-        for (int b = 0; b < nbd; b++)
-            for (int g = 0; g < ng64; g++) S.bpart.push_back(Work{tg(ti, g), b});
-        for (int64_t e = 0; e < npk; e++)
-            for (int g = 0; g < ng64; g++) S.schur.push_back(Work{tg(ti, g), int32_t(e)});
+        for (int g = 0; g < ng64; g++) {
+            for (int b = 0; b < nbd; b++) S.bpart.push_back(Work{tg(ti, g), b});
+            for (int64_t e = 0; e < npk; e++) S.schur.push_back(Work{tg(ti, g), int32_t(e)});
+        }
     }
     return NCL_OK;
 }

@@ -26,6 +26,7 @@ from .ncl import KKT, NclError
 
 DEFAULTS = dict(qd_ratio=0.3, mu=0.3, vmin=0.9, vmax=1.1, qmax=3.0, pmax=8.0, smax2=100.0, eps=1.0)
 MU_SCHEDULE = (10.0, 3.0, 1.0, 0.3, 0.1, 0.03)
+FLOOR_TOL = 1e-6      # step accepted as converged when backtracking stalls at the rounding floor
 L_VM, L_VA, L_QG, L_PG, L_ROWP, L_ROWQ, L_FLOW = 1, 2, 3, 4, 5, 6, 7
 
 
@@ -132,6 +133,11 @@ class DispatchSolver:
                     if nt <= (1.0 - 1e-4 * a) * nrm or a < 1e-10:
                         break
                     a *= 0.5
+                if a < 1e-10 and bool(torch.all(dz.abs() <= FLOOR_TOL * (1.0 + z.abs()))):
+                    # |F| is at its rounding floor (variables pressed against
+                    # their bounds make the barrier curvature huge) and the
+                    # remaining step is tiny: converged as far as FP64 resolves
+                    break
                 z, F, sig, nrm = zt, Ft, sigt, nt
                 total += 1
             else:
