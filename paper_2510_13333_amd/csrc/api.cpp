@@ -177,8 +177,9 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(t.terms));
         o.push_back(L.vec(t.bterm_ptr));
         o.push_back(L.vec(t.bterms));
-        o.push_back(L.vec(t.sterm_ptr));
-        o.push_back(L.vec(t.sterms));
+        o.push_back(L.vec(t.stile_ij));
+        o.push_back(L.vec(t.stile_ptr));
+        o.push_back(L.vec(t.stiles));
         o.push_back(L.vec(t.bus_idx));
         o.push_back(L.vec(t.bus_slot));
         o.push_back(L.vec(t.bus_adj_ptr));
@@ -682,20 +683,21 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.terms = reinterpret_cast<const ncl::Term *>(at(11));
         d.bterm_ptr = reinterpret_cast<const int32_t *>(at(12));
         d.bterms = reinterpret_cast<const ncl::Term *>(at(13));
-        d.sterm_ptr = reinterpret_cast<const int32_t *>(at(14));
-        d.sterms = reinterpret_cast<const ncl::Term *>(at(15));
-        d.bus_idx = reinterpret_cast<const int32_t *>(at(16));
-        d.bus_slot = reinterpret_cast<const int32_t *>(at(17));
-        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(18));
-        d.bus_adj = reinterpret_cast<const int32_t *>(at(19));
-        d.br_slot = reinterpret_cast<const int32_t *>(at(20));
-        d.br_idx = reinterpret_cast<const int32_t *>(at(21));
-        d.gen_idx = reinterpret_cast<const int32_t *>(at(22));
-        d.gen_slot = reinterpret_cast<const int32_t *>(at(23));
-        d.perm = reinterpret_cast<const int32_t *>(at(24));
-        d.col_primal = reinterpret_cast<const uint8_t *>(at(25));
-        d.bus_gen = reinterpret_cast<const int32_t *>(at(26));
-        d.lkind = reinterpret_cast<const uint8_t *>(at(27));
+        d.stile_ij = reinterpret_cast<const int32_t *>(at(14));
+        d.stile_ptr = reinterpret_cast<const int32_t *>(at(15));
+        d.stiles = reinterpret_cast<const ncl::STile *>(at(16));
+        d.bus_idx = reinterpret_cast<const int32_t *>(at(17));
+        d.bus_slot = reinterpret_cast<const int32_t *>(at(18));
+        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(19));
+        d.bus_adj = reinterpret_cast<const int32_t *>(at(20));
+        d.br_slot = reinterpret_cast<const int32_t *>(at(21));
+        d.br_idx = reinterpret_cast<const int32_t *>(at(22));
+        d.gen_idx = reinterpret_cast<const int32_t *>(at(23));
+        d.gen_slot = reinterpret_cast<const int32_t *>(at(24));
+        d.perm = reinterpret_cast<const int32_t *>(at(25));
+        d.col_primal = reinterpret_cast<const uint8_t *>(at(26));
+        d.bus_gen = reinterpret_cast<const int32_t *>(at(27));
+        d.lkind = reinterpret_cast<const uint8_t *>(at(28));
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
     std::vector<ncl::BlockDev> bdev(h.nblk);

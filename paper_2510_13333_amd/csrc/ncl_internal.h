@@ -32,6 +32,17 @@ struct CItem {
     int32_t meta;    // ld (16 bits) | wd << 16
 };
 
+// Border Schur tiles: one wavefront computes the entries (i, j0 .. j0+7) of
+// the packed border matrix for its blocks.  Each item is one supernode s on
+// the path of border row i and of at least one row of the tile: row i's
+// panel element, the panel's leading dimension and width, s's first column,
+// the tile rows s holds (bit jj for row j0 + jj) and their panel elements.
+constexpr int kSchurTJ = 8;
+struct STile {
+    int32_t pi, r, w, dcol, mask, pad[3];
+    int32_t pj[kSchurTJ];
+};
+
 // One product of an update sum: L[a] * d[k] * L[c] (factor, border Schur) or
 // L[a] * y[k] (solves), with a, c panel elements and k a column, all
 // template-relative.  Each entry's terms are contiguous, so that a kernel can
@@ -99,9 +110,10 @@ struct TemplDev {
     // border rows: terms L[b, k] y_k of the border right-hand side
     const int32_t *bterm_ptr;      // [nbd+1]
     const Term *bterms;
-    // border Schur terms of each packed border entry
-    const int32_t *sterm_ptr;      // [nbd*(nbd+1)/2 + 1]
-    const Term *sterms;
+    // border Schur tiles: (i, j0) and item range of each tile
+    const int32_t *stile_ij;       // [ntiles][2]
+    const int32_t *stile_ptr;      // [ntiles + 1]
+    const STile *stiles;
     // assembly
     const int32_t *bus_idx;        // [nb][BI_N]
     const int32_t *bus_slot;       // [nb][BS_N]
@@ -172,7 +184,9 @@ struct Template {
     // schedule
     int nlev = 0;
     std::vector<int32_t> level;         // [nsup]
-    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr, bterm_ptr, sterm_ptr;
+    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr, bterm_ptr, sterm_ptr,
+        stile_ij, stile_ptr;
+    std::vector<STile> stiles;
     std::vector<std::vector<int32_t>> lev_tasks;   // row tasks of each level
     std::vector<Term> terms, bterms, sterms;
 };

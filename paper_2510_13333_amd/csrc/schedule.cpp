@@ -176,6 +176,38 @@ int build_template_schedule(Template &t, int nbd) {
             if (int64_t(t.sterms.size()) > kTermMax) return NCL_ERR_ARG;
             t.sterm_ptr[e + 1] = int32_t(t.sterms.size());
         }
+    // border Schur tiles: rows i, columns j0 .. j0+7 (j <= i); items are the
+    // supernodes on row i's path that also hold a row of the tile, in
+    // ascending order
+    t.stile_ij.clear();
+    t.stile_ptr.assign(1, 0);
+    t.stiles.clear();
+    for (int i = 0; i < nbd; i++)
+        for (int j0 = 0; j0 <= i; j0 += kSchurTJ) {
+            t.stile_ij.push_back(i);
+            t.stile_ij.push_back(j0);
+            for (auto &x : bp[i]) {
+                const int s = x.first;
+                STile it{};
+                it.pi = t.panel_off[s] + x.second;
+                it.r = t.srp[s + 1] - t.srp[s];
+                it.w = t.sup[s + 1] - t.sup[s];
+                it.dcol = t.sup[s];
+                for (int jj = 0; jj < kSchurTJ; jj++) {
+                    const int j = j0 + jj;
+                    it.pj[jj] = it.pi;                     // a valid element when the row is absent
+                    if (j > i) continue;
+                    for (auto &y : bp[j])
+                        if (y.first == s) {
+                            it.mask |= 1 << jj;
+                            it.pj[jj] = t.panel_off[s] + y.second;
+                        }
+                }
+                if (it.mask) t.stiles.push_back(it);
+            }
+            if (t.stiles.size() > size_t(INT32_MAX)) return NCL_ERR_ARG;
+            t.stile_ptr.push_back(int32_t(t.stiles.size()));
+        }
     return NCL_OK;
 }
 
@@ -261,11 +293,11 @@ int build_schedule(Handle &h) {
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int nbd = h.inst[t.inst].nbd;
-        const int64_t npk = int64_t(nbd) * (nbd + 1) / 2;
         const int ng64 = groups(t, 64);
+        const int ntile = int(t.stile_ptr.size()) - 1;
         for (int g = 0; g < ng64; g++) {
             for (int b = 0; b < nbd; b++) S.bpart.push_back(Work{tg(ti, g), b});
-            for (int64_t e = 0; e < npk; e++) S.schur.push_back(Work{tg(ti, g), int32_t(e)});
+            for (int q = 0; q < ntile; q++) S.schur.push_back(Work{tg(ti, g), q});
         }
     }
     return NCL_OK;
