@@ -712,29 +712,19 @@ __global__ __launch_bounds__(kWG) void k_border_sum(DevArgs a) {
 //   3. the trailing lower triangle takes S_ik -= sum_j L_ij d_j L_kj, in 4x4
 //      register tiles that read the block column of L from LDS.
 // S ends with L strictly below the diagonal and 1 on it; D goes to dval.
-// The trailing matrix stays in global memory (L2-resident: 130 KB for a
-// 180-row border); the block column of L is staged in LDS.
+// The trailing matrix stays in global memory (L2-resident); the block
+// column of L is staged in LDS.  Taken for borders too large for the
+// register-tiled factor below.
 constexpr int kBFThreads = 512;    // 8 wavefronts: up to 256 registers each, no spills
 
-// kRes: the whole packed matrix is resident in LDS for the factorisation
-// (copied in at the start and out at the end); otherwise it stays in global
-// memory and only the block column of L is staged in LDS.
-template <bool kRes>
-__global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
-    extern __shared__ double lds[];
+__device__ inline void border_factor_blocked(const DevArgs &a, const InstDev &I, double *lds) {
     double *Ld = lds;                  // [kBB][kPS] L of the diagonal block
     double *dd = Ld + kBB * kPS;       // [kBB] its pivots
-    const InstDev &I = a.insts[blockIdx.x];
     const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
-    const int npk = nbd * (nbd + 1) / 2;
     double *Sg = a.sbb + I.sbb0;
-    double *S = kRes ? dd + kBB : Sg;              // the packed matrix being factored
-    double *Pn = kRes ? nullptr : dd + kBB;        // [nbd - kBB][kPS] L of the rows below the block
+    double *S = Sg;                    // the packed matrix being factored
+    double *Pn = dd + kBB;             // [nbd - kBB][kPS] L of the rows below the block
     double *Db = a.dval + a.dint + I.bd0;
-    if (kRes) {
-        for (int e = tid; e < npk; e += kBFThreads) S[e] = Sg[e];
-        __syncthreads();
-    }
     for (int b0 = 0; b0 < nbd; b0 += kBB) {
         const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
         const int r0 = b0 + bs, m = nbd - r0;
@@ -797,7 +787,7 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
             for (int j = 0; j < kBB; j++)
                 if (j < bs) {
                     si[j] = x[j];
-                    if (!kRes) Pn[t * kPS + j] = x[j];
+                    Pn[t * kPS + j] = x[j];
                 }
         }
         __syncthreads();
@@ -817,9 +807,7 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     const int ii = 4 * I + u, kk = 4 * K + u;
-                    // rows of the block column: in S itself when resident
-                    const double *ri = kRes ? S + pk(r0 + ii, b0) : Pn + ii * kPS;
-                    const double *rk = kRes ? S + pk(r0 + kk, b0) : Pn + kk * kPS;
+                    const double *ri = Pn + ii * kPS, *rk = Pn + kk * kPS;
                     pi[u] = ii < m ? ri[j] : 0.0;
                     pc[u] = kk < m ? rk[j] * dj : 0.0;
                 }
@@ -838,8 +826,154 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
         }
         __syncthreads();
     }
-    if (kRes)
-        for (int e = tid; e < npk; e += kBFThreads) Sg[e] = S[e];
+}
+
+// Dense LDL^T of a border matrix held in registers.  The lower triangle is
+// cut into 4x4 tiles numbered column by column; thread t holds tiles t,
+// t + kBFThreads, ... (at most T).  For each panel p of 4 columns:
+//  (1) the owner of tile (p, p) factors it (pivots d_p, unit lower L_pp)
+//      and publishes it in LDS;
+//  (2) the owner of each tile (I, p), I > p, forms W = A_Ip L_pp^{-T}
+//      (= L_Ip D_p) and L_Ip = W D_p^{-1}, and publishes both rows;
+//  (3) every tile (I, K) with I >= K > p takes A_IK -= W_I L_K^T.
+// Two barriers a panel and no copy of the matrix in LDS.  Rows padded past
+// nbd carry pivot 1 and no coupling; only real entries are written out.
+constexpr int kBFRegMaxT = 3;      // tiles a thread can hold without spilling
+constexpr int kBFRegMaxNt = 54;    // tile rows that fit: 54 * 55 / 2 <= kBFRegMaxT * kBFThreads (nbd <= 216)
+
+template <int T>
+__device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, double *piv, double *pan) {
+    const int nbd = I.nbd, tid = threadIdx.x;
+    const int mt = (nbd + 3) >> 2, npad = 4 * mt, ntl = mt * (mt + 1) / 2;
+    double *Sg = a.sbb + I.sbb0;
+    double *Db = a.dval + a.dint + I.bd0;
+    double *Wp = pan, *Lp = pan + 4 * npad;      // [k][row] for k < 4, rows < npad
+    double A[T][16];
+    int ti[T], tk[T];
+#pragma unroll
+    for (int j = 0; j < T; j++) {
+        const int q = tid + j * kBFThreads;
+        int K = -1, i0 = -1;
+        if (q < ntl) {
+            int off = 0;
+            K = 0;
+            while (off + (mt - K) <= q) {
+                off += mt - K;
+                K++;
+            }
+            i0 = K + (q - off);
+        }
+        ti[j] = i0;
+        tk[j] = K;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int i = 4 * i0 + r, k = 4 * K + c;
+                double v = 0.0;
+                if (q < ntl) {
+                    if (i < nbd && k <= i) v = Sg[pk(i, k)];
+                    else if (i == k) v = 1.0;
+                }
+                A[j][4 * r + c] = v;
+            }
+    }
+    for (int p = 0; p < mt; p++) {
+        const int c0 = 4 * p;
+#pragma unroll
+        for (int j = 0; j < T; j++) {
+            if (tk[j] == p && ti[j] == p) {
+                const double *x = A[j];
+                const double d0 = x[0], r0 = 1.0 / d0;
+                const double l10 = x[4] * r0, l20 = x[8] * r0, l30 = x[12] * r0;
+                const double d1 = x[5] - l10 * x[4], r1 = 1.0 / d1;
+                const double w21 = x[9] - l20 * x[4], w31 = x[13] - l30 * x[4];
+                const double l21 = w21 * r1, l31 = w31 * r1;
+                const double d2 = x[10] - l20 * x[8] - l21 * w21, r2 = 1.0 / d2;
+                const double w32 = x[14] - l30 * x[8] - l31 * w21;
+                const double l32 = w32 * r2;
+                const double d3 = x[15] - l30 * x[12] - l31 * w31 - l32 * w32, r3 = 1.0 / d3;
+                piv[0] = d0; piv[1] = d1; piv[2] = d2; piv[3] = d3;
+                piv[4] = r0; piv[5] = r1; piv[6] = r2; piv[7] = r3;
+                piv[8] = l10; piv[9] = l20; piv[10] = l21; piv[11] = l30; piv[12] = l31; piv[13] = l32;
+                const double dv[4] = {d0, d1, d2, d3};
+                const double lv[6] = {l10, l20, l21, l30, l31, l32};
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int i = c0 + r;
+                    if (i < nbd) {
+                        Db[i] = dv[r];
+                        double *si = Sg + pk(i, c0);
+#pragma unroll
+                        for (int c = 0; c < r; c++) si[c] = lv[r * (r - 1) / 2 + c];
+                        si[r] = 1.0;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < T; j++) {
+            if (tk[j] == p && ti[j] > p) {
+                const double l10 = piv[8], l20 = piv[9], l21 = piv[10], l30 = piv[11], l31 = piv[12], l32 = piv[13];
+                const double r0 = piv[4], r1 = piv[5], r2 = piv[6], r3 = piv[7];
+                const int row0 = 4 * ti[j];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const double *x = A[j] + 4 * r;
+                    const double w0 = x[0];
+                    const double w1 = x[1] - w0 * l10;
+                    const double w2 = x[2] - w0 * l20 - w1 * l21;
+                    const double w3 = x[3] - w0 * l30 - w1 * l31 - w2 * l32;
+                    const double y0 = w0 * r0, y1 = w1 * r1, y2 = w2 * r2, y3 = w3 * r3;
+                    const int i = row0 + r;
+                    Wp[i] = w0; Wp[npad + i] = w1; Wp[2 * npad + i] = w2; Wp[3 * npad + i] = w3;
+                    Lp[i] = y0; Lp[npad + i] = y1; Lp[2 * npad + i] = y2; Lp[3 * npad + i] = y3;
+                    if (i < nbd) {
+                        double *si = Sg + pk(i, c0);
+                        si[0] = y0;
+                        if (c0 + 1 < nbd) si[1] = y1;
+                        if (c0 + 2 < nbd) si[2] = y2;
+                        if (c0 + 3 < nbd) si[3] = y3;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < T; j++) {
+            if (tk[j] > p) {
+                const int ri = 4 * ti[j], rk = 4 * tk[j];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const double2 wa = *reinterpret_cast<const double2 *>(Wp + k * npad + ri);
+                    const double2 wb = *reinterpret_cast<const double2 *>(Wp + k * npad + ri + 2);
+                    const double2 la = *reinterpret_cast<const double2 *>(Lp + k * npad + rk);
+                    const double2 lb = *reinterpret_cast<const double2 *>(Lp + k * npad + rk + 2);
+                    const double w[4] = {wa.x, wa.y, wb.x, wb.y};
+                    const double l[4] = {la.x, la.y, lb.x, lb.y};
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int c = 0; c < 4; c++) A[j][4 * r + c] -= w[r] * l[c];
+                }
+            }
+        }
+    }
+}
+
+// One workgroup per instance.  Each instance takes the register-tiled factor
+// when its tiles fit T per thread, else the blocked one, so that the path an
+// instance takes depends on its own border only (a batched launch and a
+// launch for that instance alone compute the same bits).
+template <int T>
+__global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
+    __shared__ double piv[16];    // d (0..3), 1/d (4..7), l10 l20 l21 l30 l31 l32 (8..13)
+    extern __shared__ __align__(16) double lds[];
+    const InstDev &I = a.insts[blockIdx.x];
+    const int mt = (I.nbd + 3) >> 2;
+    if (mt <= kBFRegMaxNt) border_factor_reg<T>(a, I, piv, lds);
+    else border_factor_blocked(a, I, lds);
 }
 
 // Pivot signs and magnitudes of the whole factorisation (integer atomics only).
@@ -1032,13 +1166,21 @@ __global__ __launch_bounds__(kWG) void k_sol_bpart(DevArgs a, const double *y, d
 // by kBB rows: wavefront 0 solves a diagonal block with cross-lane shuffles
 // (lane = row, its kBB factor entries preloaded into registers), then the
 // workgroup updates the remaining rows.
-__global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const double *__restrict__ b, double *x,
-                                                               double *y, const double *__restrict__ cpart) {
-    extern __shared__ double c[];
-    const InstDev &I = a.insts[blockIdx.x];
+// kRes: the packed factor is first copied into LDS (one coalesced sweep), so
+// that the substitutions wait on LDS rather than on global memory; taken by
+// each instance whose factor fits the LDS the launch provides.
+template <bool kRes>
+__device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c, const double *__restrict__ b,
+                                  double *x, double *y, const double *__restrict__ cpart) {
     const int nbd = I.nbd, nblk = I.nblk, tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const double *Db = a.dval + a.dint + I.bd0;
-    const double *Lb = a.sbb + I.sbb0;
+    const double *Lg = a.sbb + I.sbb0;
+    double *Ll = c + a.max_nbd;
+    if (kRes) {
+        const int npk = nbd * (nbd + 1) / 2;
+        for (int e = tid; e < npk; e += kBorderThreads) Ll[e] = Lg[e];
+    }
+    const double *Lb = kRes ? Ll : Lg;
     for (int i = wv; i < nbd; i += kBorderThreads / 64) {
         const double *ci = cpart + I.cp0 + int64_t(i) * nblk;
         double s0 = 0.0, s1 = 0.0;
@@ -1119,6 +1261,16 @@ __global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const 
         y[a.dint + I.bd0 + i] = c[i];
         x[I.bstart + i] = c[i];
     }
+}
+
+__global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const double *__restrict__ b, double *x,
+                                                               double *y, const double *__restrict__ cpart,
+                                                               int64_t lds_bytes) {
+    extern __shared__ double c[];
+    const InstDev &I = a.insts[blockIdx.x];
+    const int64_t need = (int64_t(a.max_nbd) + int64_t(I.nbd) * (I.nbd + 1) / 2) * int64_t(sizeof(double));
+    if (need <= lds_bytes) sol_border<true>(a, I, c, b, x, y, cpart);
+    else sol_border<false>(a, I, c, b, x, y, cpart);
 }
 
 // backward gather of column p of a supernode: y_col -= sum_{i >= w} L(i, p) x_{row i},
@@ -1401,11 +1553,6 @@ size_t border_lds_bytes(int nbd) {
     return size_t(kBB * kPS + kBB + (nbd > kBB ? nbd - kBB : 0) * kPS) * sizeof(double);
 }
 
-// LDS of the border factor with the whole packed matrix resident
-static size_t border_lds_resident_bytes(int nbd) {
-    return size_t(kBB * kPS + kBB + nbd * (nbd + 1) / 2) * sizeof(double);
-}
-
 // Dynamic LDS a workgroup may use on the current device (queried once).
 static int max_lds_per_workgroup() {
     static int bytes = -1;
@@ -1454,17 +1601,28 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         case NCL_K_BORDER_FACTOR:
             if (a.max_nbd) {
-                const size_t res = border_lds_resident_bytes(a.max_nbd);
-                const bool resident = res <= size_t(max_lds_per_workgroup());
-                const size_t lbytes = resident ? res : border_lds_bytes(a.max_nbd);
-                const void *fn = resident ? reinterpret_cast<const void *>(&k_border_factor<true>)
-                                          : reinterpret_cast<const void *>(&k_border_factor<false>);
-                if (lbytes > 65536) {
-                    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lbytes));
+                // tiles per thread of the register path: enough for the largest
+                // border that takes it (instances of more than kBFRegMaxNt tile rows take the
+                // blocked path inside the same kernel)
+                const int nreg = a.max_nbd < 4 * kBFRegMaxNt ? a.max_nbd : 4 * kBFRegMaxNt;
+                const int mt = (nreg + 3) / 4, tpt = (mt * (mt + 1) / 2 + kBFThreads - 1) / kBFThreads;
+                size_t lb = size_t(8) * 4 * mt * sizeof(double);
+                if (a.max_nbd > 4 * kBFRegMaxNt) {
+                    const size_t bb = border_lds_bytes(a.max_nbd);
+                    lb = bb > lb ? bb : lb;
+                }
+                const void *fn = tpt <= 1 ? reinterpret_cast<const void *>(&k_border_factor<1>)
+                               : tpt == 2 ? reinterpret_cast<const void *>(&k_border_factor<2>)
+                                          : reinterpret_cast<const void *>(&k_border_factor<3>);
+                if (lb > 65536) {
+                    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lb));
                     if (e != hipSuccess) return e;
                 }
-                if (resident) hipLaunchKernelGGL(k_border_factor<true>, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
-                else hipLaunchKernelGGL(k_border_factor<false>, dim3(a.ninst), dim3(kBFThreads), lbytes, st, a);
+                switch (tpt) {
+                    case 1: hipLaunchKernelGGL(k_border_factor<1>, dim3(a.ninst), dim3(kBFThreads), lb, st, a); break;
+                    case 2: hipLaunchKernelGGL(k_border_factor<2>, dim3(a.ninst), dim3(kBFThreads), lb, st, a); break;
+                    default: hipLaunchKernelGGL(k_border_factor<3>, dim3(a.ninst), dim3(kBFThreads), lb, st, a); break;
+                }
             }
             break;
         case NCL_K_STATUS_INIT:
@@ -1490,9 +1648,20 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                 hipLaunchKernelGGL(k_sol_bpart, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
             break;
         case NCL_K_SOL_BORDER:
-            if (a.max_nbd > 0)
-                hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), size_t(a.max_nbd) * sizeof(double),
-                                   st, a, l.b, l.x, l.y, l.cpart);
+            if (a.max_nbd > 0) {
+                // LDS for the largest factor that fits one workgroup; larger
+                // instances read theirs from global memory
+                const size_t cap = size_t(max_lds_per_workgroup());
+                size_t lb = size_t(a.max_nbd + a.max_nbd * (a.max_nbd + 1) / 2) * sizeof(double);
+                if (lb > cap) lb = cap;
+                if (lb > 65536) {
+                    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sol_border),
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lb));
+                    if (e != hipSuccess) return e;
+                }
+                hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), lb, st, a, l.b, l.x, l.y, l.cpart,
+                                   int64_t(lb));
+            }
             break;
         case NCL_K_SOL_SCALE:
             if (a.dint) hipLaunchKernelGGL(k_sol_scale, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y);
