@@ -838,8 +838,7 @@ __device__ inline void border_factor_blocked(const DevArgs &a, const InstDev &I,
 //  (3) every tile (I, K) with I >= K > p takes A_IK -= W_I L_K^T.
 // Two barriers a panel and no copy of the matrix in LDS.  Rows padded past
 // nbd carry pivot 1 and no coupling; only real entries are written out.
-constexpr int kBFRegMaxT = 3;      // tiles a thread can hold without spilling
-constexpr int kBFRegMaxNt = 54;    // tile rows that fit: 54 * 55 / 2 <= kBFRegMaxT * kBFThreads (nbd <= 216)
+constexpr int kBFRegMaxNt = 54;    // tile rows a thread's 3 tiles cover: 54 * 55 / 2 <= 3 * kBFThreads (nbd <= 216)
 
 template <int T>
 __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, double *piv, double *pan) {
@@ -879,7 +878,6 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
             }
     }
     for (int p = 0; p < mt; p++) {
-        const int c0 = 4 * p;
 #pragma unroll
         for (int j = 0; j < T; j++) {
             if (tk[j] == p && ti[j] == p) {
@@ -896,19 +894,9 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
                 piv[0] = d0; piv[1] = d1; piv[2] = d2; piv[3] = d3;
                 piv[4] = r0; piv[5] = r1; piv[6] = r2; piv[7] = r3;
                 piv[8] = l10; piv[9] = l20; piv[10] = l21; piv[11] = l30; piv[12] = l31; piv[13] = l32;
-                const double dv[4] = {d0, d1, d2, d3};
-                const double lv[6] = {l10, l20, l21, l30, l31, l32};
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int i = c0 + r;
-                    if (i < nbd) {
-                        Db[i] = dv[r];
-                        double *si = Sg + pk(i, c0);
-#pragma unroll
-                        for (int c = 0; c < r; c++) si[c] = lv[r * (r - 1) / 2 + c];
-                        si[r] = 1.0;
-                    }
-                }
+                // the tile now holds D on its diagonal and L below it
+                A[j][0] = d0; A[j][5] = d1; A[j][10] = d2; A[j][15] = d3;
+                A[j][4] = l10; A[j][8] = l20; A[j][9] = l21; A[j][12] = l30; A[j][13] = l31; A[j][14] = l32;
             }
         }
         __syncthreads();
@@ -929,13 +917,7 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
                     const int i = row0 + r;
                     Wp[i] = w0; Wp[npad + i] = w1; Wp[2 * npad + i] = w2; Wp[3 * npad + i] = w3;
                     Lp[i] = y0; Lp[npad + i] = y1; Lp[2 * npad + i] = y2; Lp[3 * npad + i] = y3;
-                    if (i < nbd) {
-                        double *si = Sg + pk(i, c0);
-                        si[0] = y0;
-                        if (c0 + 1 < nbd) si[1] = y1;
-                        if (c0 + 2 < nbd) si[2] = y2;
-                        if (c0 + 3 < nbd) si[3] = y3;
-                    }
+                    A[j][4 * r] = y0; A[j][4 * r + 1] = y1; A[j][4 * r + 2] = y2; A[j][4 * r + 3] = y3;
                 }
             }
         }
@@ -956,6 +938,29 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
                     for (int r = 0; r < 4; r++)
 #pragma unroll
                         for (int c = 0; c < 4; c++) A[j][4 * r + c] -= w[r] * l[c];
+                }
+            }
+        }
+    }
+    // write the factor out once, after the last barrier: global stores
+    // inside the panel loop would make every barrier wait for them
+#pragma unroll
+    for (int j = 0; j < T; j++) {
+        if (tk[j] < 0) continue;
+        const int c0 = 4 * tk[j];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int i = 4 * ti[j] + r;
+            if (i >= nbd) continue;
+            double *si = Sg + pk(i, c0);
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                if (c0 + c > i) continue;
+                if (c0 + c == i) {
+                    si[c] = 1.0;
+                    Db[i] = A[j][5 * r];
+                } else {
+                    si[c] = A[j][4 * r + c];
                 }
             }
         }
@@ -995,30 +1000,44 @@ __device__ inline int pivot_code(double d, bool primal) {
     return 0;
 }
 
+// Inertia and pivot report.  Each wavefront takes kStatusChunk consecutive
+// pivots (coalesced reads of D); the template owning them is found once per
+// wavefront and advanced only where a chunk crosses into the next one; the
+// column of a pivot is formed only for a bad one.
+constexpr int kStatusChunk = 1024;
+
 __global__ __launch_bounds__(256) void k_status(DevArgs a) {
     int64_t np = 0, nn = 0, nz = 0, bad = INT64_MAX, mn = INT64_MAX, mx = 0;
     const int64_t total = a.dint + a.nbd_tot;
-    for (int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
-         idx += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t c0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * kStatusChunk;
+    const int lane = lane_id();
+    int ti = (c0 < a.dint) ? find_tmpl(a, c0, &TemplDev::dbase) : 0;
+    const int64_t tend0 = ti + 1 < a.ntmpl ? a.tmpls[ti + 1].dbase : a.dint;
+    for (int k = 0; k < kStatusChunk / 64; k++) {
+        const int64_t idx = c0 + k * 64 + lane;
+        if (idx >= total) break;
         double d;
         bool primal;
-        int64_t col;
+        int code;
+        int64_t col = 0;
         if (idx < a.dint) {
-            const int ti = find_tmpl(a, idx, &TemplDev::dbase);
+            if (idx >= tend0)
+                while (ti + 1 < a.ntmpl && a.tmpls[ti + 1].dbase <= idx) ti++;
             const TemplDev &T = a.tmpls[ti];
-            const int64_t off = idx - T.dbase;
-            const int j = int(off / T.nblk), bl = int(off % T.nblk);
+            const uint32_t off = uint32_t(idx - T.dbase), nb = uint32_t(T.nblk);
+            const uint32_t j = off / nb;
             d = a.dval[idx];
             primal = T.col_primal[j] != 0;
-            col = a.blks[T.blocks[bl]].col0 + j;
+            code = pivot_code(d, primal);
+            if (code) col = a.blks[T.blocks[off - j * nb]].col0 + j;
         } else {
             const int64_t j = idx - a.dint;
             const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
             d = a.dval[idx];
             primal = a.bprim[j] != 0;
+            code = pivot_code(d, primal);
             col = I.bstart + (j - I.bd0);
         }
-        const int code = pivot_code(d, primal);
         if (code == 0 || code == 1) {
             if (d > 0) np++;
             else nn++;
@@ -1166,6 +1185,14 @@ __global__ __launch_bounds__(kWG) void k_sol_bpart(DevArgs a, const double *y, d
 // by kBB rows: wavefront 0 solves a diagonal block with cross-lane shuffles
 // (lane = row, its kBB factor entries preloaded into registers), then the
 // workgroup updates the remaining rows.
+// Value of v in lane k (k uniform), through two scalar lane reads.
+__device__ inline double lane_bcast(double v, int k) {
+    const int64_t b = __double_as_longlong(v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(b), k));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(b >> 32), k));
+    return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
 // kRes: the packed factor is first copied into LDS (one coalesced sweep), so
 // that the substitutions wait on LDS rather than on global memory; taken by
 // each instance whose factor fits the LDS the launch provides.
@@ -1206,7 +1233,7 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
             double ci = lane < bs ? c[i] : 0.0;
 #pragma unroll
             for (int k = 0; k < kBB - 1; k++) {
-                const double xk = __shfl(ci, k);
+                const double xk = lane_bcast(ci, k);
                 ci -= l[k] * xk;
             }
             if (lane < bs) c[i] = ci;
@@ -1238,7 +1265,7 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
             double cj = lane < bs ? c[b0 + lane] : 0.0;
 #pragma unroll
             for (int i = kBB - 1; i > 0; i--) {
-                const double xi = __shfl(cj, i);
+                const double xi = lane_bcast(cj, i);
                 cj -= l[i] * xi;
             }
             if (lane < bs) c[b0 + lane] = cj;
@@ -1630,8 +1657,8 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         case NCL_K_STATUS: {
             const int64_t ne = a.dint + a.nbd_tot;
-            const unsigned sg = unsigned(ne / 256 / 16 + 1 < 1024 ? ne / 256 / 16 + 1 : 1024);
-            hipLaunchKernelGGL(k_status, dim3(sg), dim3(256), 0, st, a);
+            const unsigned sg = unsigned((ne + 4 * kStatusChunk - 1) / (4 * kStatusChunk));
+            if (sg) hipLaunchKernelGGL(k_status, dim3(sg), dim3(256), 0, st, a);
             break;
         }
         case NCL_K_SOL_LOAD:
