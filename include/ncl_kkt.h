@@ -320,6 +320,7 @@ enum {
     NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
     NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */
     NCL_K_INTERLEAVE,       /* k_interleave: the state transposed to the blocks' interleaved order (assembly) */
+    NCL_K_FAC_PIVOTS,       /* k_fac_pivots: pivot and column of width-1 supernodes, per level */
     NCL_K_COUNT
 };
 

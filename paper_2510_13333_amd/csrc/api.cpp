@@ -147,6 +147,7 @@ std::vector<ncl::Work> all_work(Handle &h) {
     app(S.a, h.w_a);
     app(S.b, h.w_b);
     app(S.c, h.w_c);
+    app(S.p, h.w_p);
     app(S.f, h.w_f);
     app(S.d, h.w_d);
     app(S.g, h.w_g);
@@ -269,6 +270,7 @@ void kernel_model(Handle &h) {
     levels(NCL_K_FAC_GATHER, S.a_ptr);
     levels(NCL_K_FAC_DIAG, S.b_ptr);
     levels(NCL_K_FAC_ROWS, S.c_ptr);
+    levels(NCL_K_FAC_PIVOTS, S.p_ptr);
     levels(NCL_K_SOL_FWD_GATHER, S.f_ptr);
     levels(NCL_K_SOL_FWD_DIAG, S.d_ptr);
     levels(NCL_K_SOL_BWD_GATHER, S.g_ptr);
@@ -284,8 +286,8 @@ void kernel_model(Handle &h) {
             if (mk[q.k] != stamp) { mk[q.k] = stamp; uk++; }
         };
         for (int l = 0; l < t.nlev; l++) {
-            // factor: gather (A), diagonal blocks (B), rows (C)
-            int64_t ents = 0, kr = 0, up = 0, uk = 0, bdiag = 0, rows = 0;
+            // factor: gather (A), diagonal blocks (B), rows (C), width-1 pivots (P)
+            int64_t ents = 0, kr = 0, up = 0, uk = 0, bdiag = 0, rows = 0, piv = 0;
             stamp++;
             int last_s = -1;
             for (int32_t k : t.lev_tasks[l]) {
@@ -298,7 +300,8 @@ void kernel_model(Handle &h) {
                     if (t.ent_kpos[e] >= 0) kr++;
                     for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq(t.terms[q], true, up, uk);
                 }
-                if (w == 1 || p >= w) rows += 2 * w;
+                if (w == 1) piv += 2;                             // entry read, L (or d) written
+                else if (p >= w) rows += 2 * w;
                 if (w > 1 && s != last_s) {
                     bdiag += int64_t(w) * (w + 1) + w;            // diagonal block read and written, pivots
                     rows += int64_t(w) * (w - 1) / 2 + w;         // the block and pivots the rows read
@@ -308,6 +311,7 @@ void kernel_model(Handle &h) {
             B[NCL_K_FAC_GATHER] += nb * D * (ents + kr + up + uk);
             B[NCL_K_FAC_DIAG] += nb * D * bdiag;
             B[NCL_K_FAC_ROWS] += nb * D * rows;
+            B[NCL_K_FAC_PIVOTS] += nb * D * piv;
             // solves: forward gather (F) and backward gather (G) of the diagonal rows, diagonal solves (D)
             int64_t fr = 0, fup = 0, fuy = 0, gr = 0, gp = 0, guy = 0, dd = 0;
             stamp++;
@@ -814,6 +818,7 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
     for (int l = 0; l < S.nlev; l++) {
         if (list(NCL_K_FAC_GATHER, h.w_a, S.a_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_FAC_DIAG, h.w_b, S.b_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+        if (list(NCL_K_FAC_PIVOTS, h.w_p, S.p_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_FAC_ROWS, h.w_c, S.c_ptr, l) != hipSuccess) return NCL_ERR_HIP;
     }
     if (h.nbd_tot) {
@@ -1023,7 +1028,7 @@ const char *ncl_kernel_name(int kind) {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
         "k_sol_bpart", "k_sol_border", "k_sol_scale", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
-        "k_residual", "k_max_step", "k_interleave"};
+        "k_residual", "k_max_step", "k_interleave", "k_fac_pivots"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }
 

@@ -558,8 +558,34 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
     });
 }
 
-// C: pivot and off-diagonal rows.  Width-1 supernodes: d = P(0,0) and
-// L(p,0) = P(p,0) / d.  Row p >= w of a wide supernode: u_j = L(p,j) d_j
+// P: width-1 supernodes, one per wavefront: d = P(0,0) and L(p,0) =
+// P(p,0) / d for the rows p below it (their loads all in flight together).
+// A kernel of its own, so that these many small tasks run at the occupancy
+// of their few registers rather than that of the wide classes of C.
+__global__ __launch_bounds__(kWG) void k_fac_pivots(DevArgs a, const Work *__restrict__ wl, int nw) {
+    const int wid = wave_id();
+    if (wid >= nw) return;
+    const Lane W = lane_work(a, wl, wid);
+    if (!W.on) return;
+    const TemplDev &T = *W.T;
+    const int64_t nb = W.nb;
+    const int s = W.k;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
+    const double d = P[0];
+    a.dval[T.dbase + W.bl + int64_t(cs(T.sup_first)[s]) * nb] = d;
+    int p = 1;
+    for (; p + 4 <= r; p += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = P[int64_t(p + u) * nb];
+#pragma unroll
+        for (int u = 0; u < 4; u++) P[int64_t(p + u) * nb] = v[u] / d;
+    }
+    for (; p < r; p++) P[int64_t(p) * nb] = P[int64_t(p) * nb] / d;
+}
+
+// C: off-diagonal rows of wide supernodes.  Row p >= w: u_j = L(p,j) d_j
 // satisfies u_j = P(p,j) - sum_{k<j} L(j,k) u_k, solved right-looking
 // (u_k -= L(k,j) u_j for k > j; the loads of L do not depend on u), then
 // L(p,j) = u_j / d_j.
@@ -574,12 +600,6 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
     double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
     double *Dv = a.dval + T.dbase + W.bl + int64_t(f) * nb;
-    if (w == 1) {
-        if (!W.on) return;
-        if (p == 0) Dv[0] = P[0];
-        else P[int64_t(p) * nb] = P[int64_t(p) * nb] / P[0];
-        return;
-    }
     by_width(w, [&](auto Wc) {
         constexpr int W_ = decltype(Wc)::value;
         const int wl1 = w - 1;
@@ -1619,6 +1639,9 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         case NCL_K_FAC_ROWS:
             if (l.nw) hipLaunchKernelGGL(k_fac_rows, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
+            break;
+        case NCL_K_FAC_PIVOTS:
+            if (l.nw) hipLaunchKernelGGL(k_fac_pivots, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
             break;
         case NCL_K_BORDER_SCHUR:
             if (l.nw) hipLaunchKernelGGL(k_border_schur, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);

@@ -195,10 +195,11 @@ struct Template {
 struct Schedule {
     int nlev = 0;
     // factor: A gathers every lower panel entry (k = entry); B factors the
-    // diagonal blocks of wide supernodes (two blocks per wavefront); C pivots
-    // and off-diagonal rows (k = row task)
-    std::vector<int32_t> a_ptr, b_ptr, c_ptr;           // [nlev+1]
-    std::vector<Work> a, b, c;
+    // diagonal blocks of wide supernodes (two blocks per wavefront); C the
+    // off-diagonal rows of wide supernodes (k = row task); P the pivot and
+    // column of width-1 supernodes (k = supernode)
+    std::vector<int32_t> a_ptr, b_ptr, c_ptr, p_ptr;    // [nlev+1]
+    std::vector<Work> a, b, c, p;
     // solve: forward gathers of the diagonal rows, diagonal solves of wide supernodes
     // (backward: gathers of every diagonal row, then the same diagonal solves)
     std::vector<int32_t> f_ptr, d_ptr, g_ptr;           // [nlev+1]
@@ -277,7 +278,7 @@ struct Handle {
         const uint8_t *bprim = nullptr;
     } d;
     // offsets of each work list inside d.work
-    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
+    size_t w_a = 0, w_b = 0, w_c = 0, w_p = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
     // per kernel kind: launches and algorithmic bytes of one step
     std::vector<int64_t> km_launch, km_bytes;
     // event profiling of one kernel kind (events are hipEvent_t, in pairs)

@@ -241,6 +241,7 @@ int build_schedule(Handle &h) {
     S.a_ptr.assign(1, 0);
     S.b_ptr.assign(1, 0);
     S.c_ptr.assign(1, 0);
+    S.p_ptr.assign(1, 0);
     S.f_ptr.assign(1, 0);
     S.d_ptr.assign(1, 0);
     S.g_ptr.assign(1, 0);
@@ -262,7 +263,8 @@ int build_schedule(Handle &h) {
                     const int w = t.sup[s + 1] - t.sup[s];
                     const int cend = p < w ? p + 1 : w;     // lower triangle of the diagonal block
                     for (int c = 0; c < cend; c++) S.a.push_back(Work{tg(ti, g), t.task_cbase[k] + c});
-                    if (w == 1 || p >= w) S.c.push_back(Work{tg(ti, g), k});
+                    if (w == 1 && s != last_s) S.p.push_back(Work{tg(ti, g), s});
+                    if (w > 1 && p >= w) S.c.push_back(Work{tg(ti, g), k});
                     if (p < w) {
                         // the diagonal entry's items are exactly the descendants holding this row
                         const int e = t.task_cbase[k] + p;
@@ -286,6 +288,7 @@ int build_schedule(Handle &h) {
         S.a_ptr.push_back(int32_t(S.a.size()));
         S.b_ptr.push_back(int32_t(S.b.size()));
         S.c_ptr.push_back(int32_t(S.c.size()));
+        S.p_ptr.push_back(int32_t(S.p.size()));
         S.f_ptr.push_back(int32_t(S.f.size()));
         S.d_ptr.push_back(int32_t(S.d.size()));
         S.g_ptr.push_back(int32_t(S.g.size()));
