@@ -103,18 +103,59 @@ __device__ inline void ydot_round(const double *__restrict__ Lp, const double *y
     for (int u = 0; u < R; u++) s[u] += p[u];
 }
 
-// sum over terms of L[a] y[k]
-__device__ inline double ydot(const double *__restrict__ Lp, const double *y, int64_t nb,
-                              const Term *__restrict__ tm, int t0, int t1) {
+// Split sums.  A long run of terms is summed as four partials: full rounds
+// of 8 go round-robin to partials 0..3, the tail (rounds of 4, 2, 1) to
+// partial 0, and the total is (p0 + p1) + (p2 + p3).  One wavefront can
+// compute all four in turn, or four wavefronts one each (then a workgroup
+// combines them through LDS): the bits are the same either way, so a
+// launch may pick the split by how many tasks it has.
+constexpr int kSplit = 4;
+
+// partial q of the split sum of L[a] y[k] over terms [t0, t1)
+__device__ inline double ydot_q(const double *__restrict__ Lp, const double *y, int64_t nb,
+                                const Term *__restrict__ tm, int t0, int t1, int q) {
     double s[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) s[u] = 0.0;
-    int t = t0;
-    for (; t + 8 <= t1; t += 8) ydot_round<8>(Lp, y, nb, tm + t, s);
-    if (t + 4 <= t1) { ydot_round<4>(Lp, y, nb, tm + t, s); t += 4; }
-    if (t + 2 <= t1) { ydot_round<2>(Lp, y, nb, tm + t, s + 4); t += 2; }
-    if (t < t1) ydot_round<1>(Lp, y, nb, tm + t, s + 6);
+    const int nc = (t1 - t0) >> 3;
+    for (int c = q; c < nc; c += kSplit) ydot_round<8>(Lp, y, nb, tm + t0 + 8 * c, s);
+    if (q == 0) {
+        int t = t0 + 8 * nc;
+        if (t + 4 <= t1) { ydot_round<4>(Lp, y, nb, tm + t, s); t += 4; }
+        if (t + 2 <= t1) { ydot_round<2>(Lp, y, nb, tm + t, s + 4); t += 2; }
+        if (t < t1) ydot_round<1>(Lp, y, nb, tm + t, s + 6);
+    }
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+// Task and partial of the calling wavefront: NW = 1, one task per
+// wavefront computing every partial; NW = kSplit, one task per workgroup,
+// wavefront q computing partial q.
+template <int NW>
+__device__ inline int split_task() {
+    if (NW == 1) return wave_id();
+    return xcd_workgroup();
+}
+
+// Combine the partials of the split sum: v holds partial q (NW = kSplit) or
+// the caller's own total (NW = 1).  Returns the total in wavefront 0; the
+// other wavefronts get false and must not write.
+template <int NW>
+__device__ inline bool split_combine(double &v) {
+    if (NW == 1) return true;
+    __shared__ double red[kSplit][64];
+    const int q = int(threadIdx.x >> 6), lane = lane_id();
+    red[q][lane] = v;
+    __syncthreads();
+    if (q != 0) return false;
+    v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+    return true;
+}
+
+template <int NW, class F>
+__device__ inline double split_sum(F &&part) {
+    if (NW == 1) return (part(0) + part(1)) + (part(2) + part(3));
+    return part(int(threadIdx.x >> 6));
 }
 
 // template owning a flat interleaved index (binary search over the bases)
@@ -1134,17 +1175,21 @@ __global__ __launch_bounds__(256) void k_sol_scale(DevArgs a, double *__restrict
 
 // forward gather of a diagonal row: y_row -= sum over descendants L_d[row,:] y_d
 // (the terms of the row's diagonal panel entry)
+template <int NW>
 __global__ __launch_bounds__(kWG) void k_sol_fwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
-    const int wid = wave_id();
-    if (wid >= nw) return;
-    const Lane W = lane_work(a, wl, wid);
+    const int task = split_task<NW>();
+    if (task >= nw) return;
+    const Lane W = lane_work(a, wl, task);
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
     double *yb = y + T.dbase + W.bl;
     const int s = cs(T.task_s)[W.k], p = cs(T.task_p)[W.k];
     const int col = cs(T.sup_first)[s] + p;
     const int e = cs(T.task_cbase)[W.k] + p;
-    const double v = ydot(a.lpan + T.lbase + W.bl, yb, nb, T.terms, cs(T.ent_tptr)[e], cs(T.ent_tptr)[e + 1]);
+    const int t0 = cs(T.ent_tptr)[e], t1 = cs(T.ent_tptr)[e + 1];
+    const double *Lp = a.lpan + T.lbase + W.bl;
+    double v = split_sum<NW>([&](int q) { return ydot_q(Lp, yb, nb, T.terms, t0, t1, q); });
+    if (!split_combine<NW>(v)) return;
     if (W.on) yb[int64_t(col) * nb] -= v;
 }
 
@@ -1186,15 +1231,18 @@ __global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, cons
 }
 
 // this block's part of the border right-hand side: cpart[b][block] = L_bk y_k
+template <int NW>
 __global__ __launch_bounds__(kWG) void k_sol_bpart(DevArgs a, const double *y, double *cpart,
                                                    const Work *__restrict__ wl, int nw) {
-    const int wid = wave_id();
-    if (wid >= nw) return;
-    const Lane W = lane_work(a, wl, wid);
+    const int task = split_task<NW>();
+    if (task >= nw) return;
+    const Lane W = lane_work(a, wl, task);
     const TemplDev &T = *W.T;
     const int bi = W.k;
-    const double v = ydot(a.lpan + T.lbase + W.bl, y + T.dbase + W.bl, W.nb, T.bterms, cs(T.bterm_ptr)[bi],
-                          cs(T.bterm_ptr)[bi + 1]);
+    const int t0 = cs(T.bterm_ptr)[bi], t1 = cs(T.bterm_ptr)[bi + 1];
+    const double *Lp = a.lpan + T.lbase + W.bl, *yb = y + T.dbase + W.bl;
+    double v = split_sum<NW>([&](int q) { return ydot_q(Lp, yb, W.nb, T.bterms, t0, t1, q); });
+    if (!split_combine<NW>(v)) return;
     const InstDev &I = a.insts[T.inst];
     if (W.on) cpart[I.cp0 + int64_t(bi) * I.nblk + (T.blocks[W.bl] - I.blk0)] = v;
 }
@@ -1323,10 +1371,11 @@ __global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const 
 // backward gather of column p of a supernode: y_col -= sum_{i >= w} L(i, p) x_{row i},
 // in rounds of 8, 4, 2, 1 rows (row indices are uniform; border rows read the
 // border solution)
+template <int NW>
 __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
-    const int wid = wave_id();
-    if (wid >= nw) return;
-    const Lane W = lane_work(a, wl, wid);
+    const int task = split_task<NW>();
+    if (task >= nw) return;
+    const Lane W = lane_work(a, wl, task);
     const TemplDev &T = *W.T;
     const int64_t nb = W.nb;
     const int n = T.n;
@@ -1337,26 +1386,34 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, co
     const double *__restrict__ Pc = a.lpan + T.lbase + W.bl + (int64_t(cs(T.panel_off)[s]) + int64_t(p) * r) * nb;
     double *yb = y + T.dbase + W.bl;
     const double *xb = y + a.dint + T.bd0;
-    double acc[8];
+    // partial q: rounds of 8 rows c = q, q + 4, ... from row w; the tail to partial 0
+    auto part = [&](int q) {
+        double acc[8];
 #pragma unroll
-    for (int u = 0; u < 8; u++) acc[u] = 0.0;
-    auto round = [&](auto R, int i) {
-        double q[R.value];
+        for (int u = 0; u < 8; u++) acc[u] = 0.0;
+        auto round = [&](auto R, int i) {
+            double x[R.value];
 #pragma unroll
-        for (int u = 0; u < R.value; u++) {
-            const int ri = cs(R_)[i + u];
-            const double *xp = ri < n ? yb + int64_t(ri) * nb : xb + (ri - n);
-            q[u] = Pc[int64_t(i + u) * nb] * *xp;
+            for (int u = 0; u < R.value; u++) {
+                const int ri = cs(R_)[i + u];
+                const double *xp = ri < n ? yb + int64_t(ri) * nb : xb + (ri - n);
+                x[u] = Pc[int64_t(i + u) * nb] * *xp;
+            }
+#pragma unroll
+            for (int u = 0; u < R.value; u++) acc[u] += x[u];
+        };
+        const int nc = (r - w) >> 3;
+        for (int c = q; c < nc; c += kSplit) round(std::integral_constant<int, 8>(), w + 8 * c);
+        if (q == 0) {
+            int i = w + 8 * nc;
+            if (i + 4 <= r) { round(std::integral_constant<int, 4>(), i); i += 4; }
+            if (i + 2 <= r) { round(std::integral_constant<int, 2>(), i); i += 2; }
+            if (i < r) round(std::integral_constant<int, 1>(), i);
         }
-#pragma unroll
-        for (int u = 0; u < R.value; u++) acc[u] += q[u];
+        return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     };
-    int i = w;
-    for (; i + 8 <= r; i += 8) round(std::integral_constant<int, 8>(), i);
-    if (i + 4 <= r) { round(std::integral_constant<int, 4>(), i); i += 4; }
-    if (i + 2 <= r) { round(std::integral_constant<int, 2>(), i); i += 2; }
-    if (i < r) round(std::integral_constant<int, 1>(), i);
-    const double v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    double v = split_sum<NW>(part);
+    if (!split_combine<NW>(v)) return;
     if (W.on) yb[int64_t(f + p) * nb] -= v;
 }
 
@@ -1593,6 +1650,11 @@ __global__ __launch_bounds__(kStepThreads) void k_max_step(DevArgs a, const doub
 
 // ------------------------------------------------------------------ launchers
 
+// Task lists at most this long run one task per workgroup (four wavefronts
+// splitting each sum), longer ones one task per wavefront: either way the
+// GPU holds a few waves per SIMD.
+constexpr int kSplitTasks = 2048;
+
 static inline unsigned waves_grid(int nw) { return unsigned((nw + (kWG / 64) - 1) / (kWG / 64)); }
 static inline unsigned elems_grid(int64_t n) { return unsigned((n + 255) / 256); }
 
@@ -1688,14 +1750,17 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (a.dint) hipLaunchKernelGGL(k_sol_load, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.b, l.y);
             break;
         case NCL_K_SOL_FWD_GATHER:
-            if (l.nw) hipLaunchKernelGGL(k_sol_fwd_gather, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_fwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            else if (l.nw) hipLaunchKernelGGL(k_sol_fwd_gather<kSplit>, dim3(l.nw), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
             break;
         case NCL_K_SOL_FWD_DIAG:
             if (l.nw) hipLaunchKernelGGL(k_sol_fwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
             break;
         case NCL_K_SOL_BPART:
-            if (l.nw)
-                hipLaunchKernelGGL(k_sol_bpart, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
+            if (l.nw > kSplitTasks)
+                hipLaunchKernelGGL(k_sol_bpart<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
+            else if (l.nw)
+                hipLaunchKernelGGL(k_sol_bpart<kSplit>, dim3(l.nw), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
             break;
         case NCL_K_SOL_BORDER:
             if (a.max_nbd > 0) {
@@ -1717,7 +1782,8 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (a.dint) hipLaunchKernelGGL(k_sol_scale, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y);
             break;
         case NCL_K_SOL_BWD_GATHER:
-            if (l.nw) hipLaunchKernelGGL(k_sol_bwd_gather, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_bwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            else if (l.nw) hipLaunchKernelGGL(k_sol_bwd_gather<kSplit>, dim3(l.nw), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
             break;
         case NCL_K_SOL_BWD_DIAG:
             if (l.nw) hipLaunchKernelGGL(k_sol_bwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
