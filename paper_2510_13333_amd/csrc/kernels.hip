@@ -647,12 +647,13 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
         double u[W_];
 #pragma unroll
         for (int j = 0; j < W_; j++) u[j] = P[(int64_t(j < w ? j : wl1) * r + p) * nb];
+        // u_k -= L(k,j) u_j for j < k, row by row in increasing j
 #pragma unroll
-        for (int j = 0; j < W_; j++) {
-            const int64_t cj = int64_t(j < w ? j : wl1) * r;
+        for (int k = 1; k < W_; k++) {
+            const int kc = k < w ? k : wl1;
 #pragma unroll
-            for (int k = j + 1; k < W_; k++) {
-                const double l = P[(cj + (k < w ? k : wl1)) * nb];
+            for (int j = 0; j < k; j++) {
+                const double l = P[(int64_t(j < w ? j : wl1) * r + kc) * nb];
                 u[k] -= (k < w ? l : 0.0) * u[j];
             }
         }
@@ -1213,12 +1214,14 @@ __global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, cons
         double x[W_];
 #pragma unroll
         for (int j = 0; j < W_; j++) x[j] = yb[int64_t(j < w ? j : wl1) * nb];
+        // row by row: x_k -= L(k,j) x_j for j < k, in increasing j (the
+        // order of the column sweep, so the same bits)
 #pragma unroll
-        for (int j = 0; j < W_; j++) {
-            const int64_t cj = int64_t(j < w ? j : wl1) * r;
+        for (int k = 1; k < W_; k++) {
+            const int kc = k < w ? k : wl1;
 #pragma unroll
-            for (int k = j + 1; k < W_; k++) {
-                const double l = P[(cj + (k < w ? k : wl1)) * nb];
+            for (int j = 0; j < k; j++) {
+                const double l = P[(int64_t(j < w ? j : wl1) * r + kc) * nb];
                 x[k] -= (k < w ? l : 0.0) * x[j];
             }
         }
