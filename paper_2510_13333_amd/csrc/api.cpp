@@ -238,6 +238,7 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.nbb_tot = h.nbb_tot;
     a.npk_tot = h.npk_tot;
     a.asm_threads = h.asm_threads;
+    a.asm_wthreads = h.asm_wthreads;
     a.gp_tot = h.gp_tot;
     a.tiles = h.tiles;
     a.zint = h.d.zint;
@@ -662,6 +663,7 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.nbus = I.nb;
         d.ngen = I.ng;
         d.abase = h.t_abase[ti];
+        d.awbase = h.t_awbase[ti];
         d.tile0 = h.t_tile0[ti];
         d.bd0 = I.bd0;
         d.br_r = reinterpret_cast<const double *>(base + p.ioff[t.inst][3]);

@@ -17,7 +17,8 @@ struct DevArgs {
     int64_t kint;               // interleaved K values; the border K_bb values of every instance follow
     int64_t dint;               // interleaved pivots; the border pivots of every instance follow
     int64_t nbd_tot, nbb_tot, npk_tot;
-    int64_t asm_threads, gp_tot;   // assembly threads of the templates, then of the border pg values
+    int64_t asm_threads, gp_tot;   // residual threads of the templates, then of the border pg values
+    int64_t asm_wthreads;          // assembly threads of the templates (wavefront-aligned), then border pg
     int64_t tiles;              // state transpose tiles of all templates
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
     double *zint, *sint;        // interleaved copies of the state and Sigma (assembly input)

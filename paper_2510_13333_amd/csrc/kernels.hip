@@ -282,10 +282,11 @@ struct AsmCtx {
     int64_t kb;      // template K base + the lane's block
     int64_t nb;      // blocks of the template (stride)
     int64_t kbb;     // the instance's K_bb values
+    bool on;         // the lane holds a block (idle lanes write nothing)
 };
 
 __device__ inline void put(const AsmCtx &c, int32_t slot, double v) {
-    if (slot < 0) return;
+    if (slot < 0 || !c.on) return;
     if (slot & kBorderFlag) c.a->kval[c.kbb + (slot & ~kBorderFlag)] = v;
     else c.a->kval[c.kb + int64_t(slot) * c.nb] = v;
 }
@@ -294,10 +295,10 @@ __device__ inline int64_t zi(int64_t bstart, const BlockDev &B, int n, int32_t x
     return x < n ? B.col0 + x : bstart + (x - n);
 }
 
-// Threads: per template, (bus, block) pairs then (generator, block) pairs,
-// the block index running fastest so that neighbouring threads write
-// neighbouring interleaved values; then the border pg diagonal of every
-// instance.
+// Threads: per template, one wavefront per (bus, group of 64 blocks), then
+// per (generator, group), the lane running over the blocks of the group so
+// that neighbouring lanes write neighbouring interleaved values; then the
+// border pg diagonal of every instance.
 // index of layout-local element x of the lane's block in the interleaved state
 struct StateIx {
     int64_t base, nb, bord;
@@ -310,8 +311,8 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
     const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const double irho = 1.0 / rho;
     const double shift = noshift ? 0.0 : 1.0;    // diagonal-dominance shift on (1) or off (0)
-    if (tid >= a.asm_threads) {
-        const int64_t gg = tid - a.asm_threads;
+    if (tid >= a.asm_wthreads) {
+        const int64_t gg = tid - a.asm_wthreads;
         if (gg >= a.gp_tot) return;
         const InstDev &I = a.insts[find_inst(a, gg, &InstDev::gp0)];
         const int g = int(gg - I.gp0);
@@ -322,34 +323,41 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         if (p >= 0) a.kval[a.kint + I.kbb0 + p] = h + shift * fmax(0.0, -h) + a.sint[a.dint + I.bd0 + bidx];
         return;
     }
-    const TemplDev &T = a.tmpls[find_tmpl(a, tid, &TemplDev::abase)];
-    const int64_t u0 = tid - T.abase;
-    const int64_t nbus_t = int64_t(T.nblk) * T.nbus;
+    // one wavefront per (bus or generator j, group of 64 blocks): j and every
+    // table index are uniform, so the tables are read through scalar loads
+    const int64_t wt0 = int64_t(blockIdx.x) * blockDim.x + 64 * __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const TemplDev &T = a.tmpls[find_tmpl(a, wt0, &TemplDev::awbase)];
+    const int ngr = (T.nblk + 63) >> 6;
+    const int wloc = int((wt0 - T.awbase) >> 6);
+    const int j = wloc / ngr;
+    const int b = (wloc - j * ngr) * 64 + lane_id();
+    const bool on = b < T.nblk;
+    const int bl = on ? b : T.nblk - 1;           // idle lanes read a valid block and write nothing
     const int64_t kbb = a.kint + a.insts[T.inst].kbb0;
     const double *__restrict__ zs = a.zint;
     const double *__restrict__ ss = a.sint;
-    if (u0 < nbus_t) {
-        const int bl = int(u0 % T.nblk), i = int(u0 / T.nblk);
+    if (j < T.nbus) {
+        const int i = j;
         const BlockDev B = a.blks[T.blocks[bl]];
         const int n = T.n;
-        const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb};
+        const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb, on};
         const StateIx ix{T.dbase + bl, T.nblk, a.dint + T.bd0, n};
-        const int32_t *bi = T.bus_idx + size_t(i) * BI_N;
+        const auto *bi = cs(T.bus_idx) + size_t(i) * BI_N;
         double Hvv = 0, Haa = 0, Hva = 0, dPv = 0, dPa = 0, dQv = 0, dQa = 0, absv = 0, absa = 0;
         for (int q = cs(T.bus_adj_ptr)[i]; q < cs(T.bus_adj_ptr)[i + 1]; q++) {
-            const int32_t e = T.bus_adj[q];
+            const int32_t e = cs(T.bus_adj)[q];
             const bool self_from = e >= 0;
             const int l = self_from ? e : ~e;
-            const int32_t *br = T.br_idx + size_t(l) * 4;
+            const auto *br = cs(T.br_idx) + size_t(l) * 4;
             const int f = br[2], t = br[3];
-            const int32_t *bf = T.bus_idx + size_t(f) * BI_N, *bt = T.bus_idx + size_t(t) * BI_N;
+            const auto *bf = cs(T.bus_idx) + size_t(f) * BI_N, *bt = cs(T.bus_idx) + size_t(t) * BI_N;
             const double vf = zs[ix(bf[BI_VM])], vt = zs[ix(bt[BI_VM])];
             const double tf = zs[ix(bf[BI_VA])], tt = zs[ix(bt[BI_VA])];
             const double yPf = zs[ix(bf[BI_P])], yQf = zs[ix(bf[BI_Q])];
             const double yPt = zs[ix(bt[BI_P])], yQt = zs[ix(bt[BI_Q])];
             const double yFf = zs[ix(br[0])], yFt = zs[ix(br[1])];
             const double st = (l == B.outage) ? 0.0 : 1.0;
-            const double r = T.br_r[l], x = T.br_x[l];
+            const double r = cs(T.br_r)[l], x = cs(T.br_x)[l];
             const double den = r * r + x * x;
             const double g = st * (r / den), b = st * (-x / den);
             double W[4][4] = {};
@@ -368,7 +376,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
             dQv += self_from ? ef.gQ[0] : et.gQ[0];
             dQa += self_from ? ef.gQ[2] : et.gQ[2];
             if (self_from) {
-                const int32_t *s = T.br_slot + size_t(l) * LS_N;
+                const auto *s = cs(T.br_slot) + size_t(l) * LS_N;
                 put(cx, s[LS_VMVM], W[0][1]);
                 put(cx, s[LS_VMVA], W[0][3]);
                 put(cx, s[LS_VAVM], W[2][1]);
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         }
         const double dv = shift * fmax(0.0, absv + fabs(Hva) - Hvv);
         const double da = shift * fmax(0.0, absa + fabs(Hva) - Haa);
-        const int32_t *bs = T.bus_slot + size_t(i) * BS_N;
+        const auto *bs = cs(T.bus_slot) + size_t(i) * BS_N;
         put(cx, bs[BS_VMVM], Hvv + dv + ss[ix(bi[BI_VM])]);
         put(cx, bs[BS_VAVA], Haa + da + ss[ix(bi[BI_VA])]);
         put(cx, bs[BS_VMVA], Hva);
@@ -415,18 +423,17 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
         return;
     }
     {
-        const int64_t u = u0 - nbus_t;
-        const int bl = int(u % T.nblk), g = int(u / T.nblk);
+        const int g = j - T.nbus;
         const int n = T.n;
-        const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb};
+        const AsmCtx cx{&a, T.kbase + bl, T.nblk, kbb, on};
         const StateIx ix{T.dbase + bl, T.nblk, a.dint + T.bd0, n};
-        const int32_t *gi = T.gen_idx + size_t(g) * GI_N;
-        const int32_t *gs = T.gen_slot + size_t(g) * GS_N;
+        const auto *gi = cs(T.gen_idx) + size_t(g) * GI_N;
+        const auto *gs = cs(T.gen_slot) + size_t(g) * GS_N;
         put(cx, gs[GS_PPG], -1.0);
         put(cx, gs[GS_QQG], -1.0);
         put(cx, gs[GS_QGQG], ss[ix(gi[GI_QG])]);
         if (T.has_pg_local) {
-            const double h = 2.0 * T.gen_c2[g];
+            const double h = 2.0 * cs(T.gen_c2)[g];
             put(cx, gs[GS_PGPG], h + shift * fmax(0.0, -h) + ss[ix(gi[GI_PG])]);
         }
         if (T.pvpq_rows) {
@@ -1683,7 +1690,7 @@ static int max_lds_per_workgroup() {
 hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st) {
     switch (kind) {
         case NCL_K_ASSEMBLE: {
-            const int64_t total = a.asm_threads + a.gp_tot;
+            const int64_t total = a.asm_wthreads + a.gp_tot;
             if (total)
                 hipLaunchKernelGGL(k_assemble, dim3(elems_grid(total)), dim3(256), 0, st, a, l.z, l.sig, l.rho,
                                    (l.flags & NCL_NO_SHIFT) ? 1 : 0);

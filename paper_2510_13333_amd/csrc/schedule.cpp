@@ -218,8 +218,9 @@ int build_schedule(Handle &h) {
     h.t_lbase.assign(h.tmpl.size(), 0);
     h.t_dbase.assign(h.tmpl.size(), 0);
     h.t_abase.assign(h.tmpl.size(), 0);
+    h.t_awbase.assign(h.tmpl.size(), 0);
     h.t_tile0.assign(h.tmpl.size(), 0);
-    h.kint = h.lint = h.dint = h.asm_threads = h.tiles = 0;
+    h.kint = h.lint = h.dint = h.asm_threads = h.asm_wthreads = h.tiles = 0;
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int64_t nb = int64_t(t.blocks.size());
@@ -227,12 +228,16 @@ int build_schedule(Handle &h) {
         h.t_lbase[ti] = h.lint;
         h.t_dbase[ti] = h.dint;
         h.t_abase[ti] = h.asm_threads;
+        h.t_awbase[ti] = h.asm_wthreads;
         h.t_tile0[ti] = h.tiles;
         h.tiles += int64_t((t.n + 63) / 64) * ((nb + 63) / 64);
         h.kint += t.colptr[t.n] * nb;
         h.lint += int64_t(t.panel_off.back()) * nb;
         h.dint += int64_t(t.n) * nb;
-        if (h.from_network) h.asm_threads += nb * (h.inst[t.inst].nb + h.inst[t.inst].ng);
+        if (h.from_network) {
+            h.asm_threads += nb * (h.inst[t.inst].nb + h.inst[t.inst].ng);
+            h.asm_wthreads += (nb + 63) / 64 * 64 * (h.inst[t.inst].nb + h.inst[t.inst].ng);
+        }
         S.nlev = std::max(S.nlev, t.nlev);
     }
     if (h.tmpl.size() > 32767) return NCL_ERR_ARG;
