@@ -261,13 +261,21 @@ __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__r
     const int nbt = (T.nblk + kTile - 1) / kTile;
     const int j0 = int(tt / nbt) * kTile, b0 = int(tt % nbt) * kTile;
     const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    // every load of both arrays is issued before the first barrier
+    constexpr int kR = kTile / 4;
+    double vz[kR], vs[kR];
+#pragma unroll
+    for (int q = 0; q < kR; q++) {
+        const int bl = b0 + r0 + 4 * q, j = j0 + c;
+        const bool ok = bl < T.nblk && j < T.n;
+        const int64_t src = ok ? a.blks[T.blocks[bl]].col0 + j : 0;
+        vz[q] = ok ? z[src] : 0.0;
+        vs[q] = ok ? sig[src] : 0.0;
+    }
     for (int pass = 0; pass < 2; pass++) {
-        const double *src = pass ? sig : z;
         double *dst = pass ? a.sint : a.zint;
-        for (int r = r0; r < kTile; r += 4) {
-            const int bl = b0 + r, j = j0 + c;
-            if (bl < T.nblk && j < T.n) tile[r][c] = src[a.blks[T.blocks[bl]].col0 + j];
-        }
+#pragma unroll
+        for (int q = 0; q < kR; q++) tile[r0 + 4 * q][c] = pass ? vs[q] : vz[q];
         __syncthreads();
         for (int r = r0; r < kTile; r += 4) {
             const int j = j0 + r, bl = b0 + c;
