@@ -1086,7 +1086,7 @@ constexpr int kStatusChunk = 1024;
 __global__ __launch_bounds__(256) void k_status(DevArgs a) {
     int64_t np = 0, nn = 0, nz = 0, bad = INT64_MAX, mn = INT64_MAX, mx = 0;
     const int64_t total = a.dint + a.nbd_tot;
-    const int64_t c0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * kStatusChunk;
+    const int64_t c0 = (int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6))) * kStatusChunk;
     const int lane = lane_id();
     int ti = (c0 < a.dint) ? find_tmpl(a, c0, &TemplDev::dbase) : 0;
     const int64_t tend0 = ti + 1 < a.ntmpl ? a.tmpls[ti + 1].dbase : a.dint;
@@ -1164,24 +1164,37 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
 // ------------------------------------------------------------------ solve
 
 // y (interleaved, factor order) = b (layout order, one column)
+// Template, column and block of a flat interleaved pivot index: the
+// template is searched once per wavefront (for its first index, through
+// scalar loads) and advanced by the lanes past its end.
+struct DIdx {
+    int ti, j, bl;
+};
+
+__device__ inline DIdx d_index(const DevArgs &a, int64_t idx) {
+    const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + 64 * __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    int ti = find_tmpl(a, w0 < a.dint ? w0 : a.dint - 1, &TemplDev::dbase);
+    while (ti + 1 < a.ntmpl && a.tmpls[ti + 1].dbase <= idx) ti++;
+    const TemplDev &T = a.tmpls[ti];
+    const uint32_t off = uint32_t(idx - T.dbase), nb = uint32_t(T.nblk);
+    const uint32_t j = off / nb;
+    return DIdx{ti, int(j), int(off - j * nb)};
+}
+
 __global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__restrict__ b, double *__restrict__ y) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= a.dint) return;
-    const int ti = find_tmpl(a, idx, &TemplDev::dbase);
-    const TemplDev &T = a.tmpls[ti];
-    const int64_t off = idx - T.dbase;
-    const int j = int(off / T.nblk), bl = int(off % T.nblk);
-    y[idx] = b[a.blks[T.blocks[bl]].col0 + T.perm[j]];
+    const DIdx d = d_index(a, idx);
+    const TemplDev &T = a.tmpls[d.ti];
+    y[idx] = b[a.blks[T.blocks[d.bl]].col0 + T.perm[d.j]];
 }
 
 __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__restrict__ y, double *__restrict__ x) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= a.dint) return;
-    const int ti = find_tmpl(a, idx, &TemplDev::dbase);
-    const TemplDev &T = a.tmpls[ti];
-    const int64_t off = idx - T.dbase;
-    const int j = int(off / T.nblk), bl = int(off % T.nblk);
-    x[a.blks[T.blocks[bl]].col0 + T.perm[j]] = y[idx];
+    const DIdx d = d_index(a, idx);
+    const TemplDev &T = a.tmpls[d.ti];
+    x[a.blks[T.blocks[d.bl]].col0 + T.perm[d.j]] = y[idx];
 }
 
 __global__ __launch_bounds__(256) void k_sol_scale(DevArgs a, double *__restrict__ y) {

@@ -224,6 +224,7 @@ int build_schedule(Handle &h) {
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int64_t nb = int64_t(t.blocks.size());
+        if (int64_t(t.n) * nb >= (int64_t(1) << 31)) return NCL_ERR_ARG;   // 32-bit pivot offsets in a template
         h.t_kbase[ti] = h.kint;
         h.t_lbase[ti] = h.lint;
         h.t_dbase[ti] = h.dint;
