@@ -127,7 +127,7 @@ struct Plan {
     std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
     std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
     size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, tables_end = 0;
-    size_t kval = 0, lpan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
+    size_t kval = 0, lpan = 0, upan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
            total = 0;
 };
 
@@ -210,6 +210,7 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     L.stage = nullptr;
     p.kval = L.take(nullptr, sizeof(double) * size_t(h.kint + h.nbb_tot));
     p.lpan = L.take(nullptr, sizeof(double) * size_t(h.lint));
+    p.upan = L.take(nullptr, sizeof(double) * size_t(h.lint));
     p.dval = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
     p.spart = L.take(nullptr, sizeof(double) * size_t(h.sp_tot));
     p.sbb = L.take(nullptr, sizeof(double) * size_t(h.npk_tot));
@@ -245,6 +246,7 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.sint = h.d.sint;
     a.kval = h.d.kval;
     a.lpan = h.d.lpan;
+    a.upan = h.d.upan;
     a.dval = h.d.dval;
     a.spart = h.d.spart;
     a.sbb = h.d.sbb;
@@ -281,6 +283,12 @@ void kernel_model(Handle &h) {
         const int n = t.n;
         std::vector<int32_t> mp(size_t(t.panel_off.back()), -1), mk(size_t(n) + h.max_nbd + 1, -1);
         int stamp = 0;
+        std::vector<int32_t> mu(size_t(t.panel_off.back()), -1);
+        // factor updates read U[a] L[c]: distinct U and L elements
+        auto uniq_ul = [&](const ncl::Term &q, int64_t &uu, int64_t &ul) {
+            if (mu[q.a] != stamp) { mu[q.a] = stamp; uu++; }
+            if (mp[q.c] != stamp) { mp[q.c] = stamp; ul++; }
+        };
         auto uniq = [&](const ncl::Term &q, bool two, int64_t &up, int64_t &uk) {
             if (mp[q.a] != stamp) { mp[q.a] = stamp; up++; }
             if (two && mp[q.c] != stamp) { mp[q.c] = stamp; up++; }
@@ -299,10 +307,10 @@ void kernel_model(Handle &h) {
                     const int e = t.task_cbase[k] + c;
                     ents++;
                     if (t.ent_kpos[e] >= 0) kr++;
-                    for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq(t.terms[q], true, up, uk);
+                    for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq_ul(t.terms[q], up, uk);
                 }
-                if (w == 1) piv += 2;                             // entry read, L (or d) written
-                else if (p >= w) rows += 2 * w;
+                if (w == 1) piv += p > 0 ? 3 : 2;                // entry read, L and U (or d) written
+                else if (p >= w) rows += 3 * w;
                 if (w > 1 && s != last_s) {
                     bdiag += int64_t(w) * (w + 1) + w;            // diagonal block read and written, pivots
                     rows += int64_t(w) * (w - 1) / 2 + w;         // the block and pivots the rows read
@@ -351,7 +359,7 @@ void kernel_model(Handle &h) {
         if (I.nbd) {
             int64_t up = 0, uk = 0;
             stamp++;
-            for (const ncl::Term &q : t.sterms) uniq(q, true, up, uk);
+            for (const ncl::Term &q : t.sterms) uniq_ul(q, up, uk);
             B[NCL_K_BORDER_SCHUR] += nb * D * (I.npk() + up + uk);
             up = uk = 0;
             stamp++;
@@ -750,6 +758,7 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.d.bprim = reinterpret_cast<const uint8_t *>(base + p.bprim);
     h.d.kval = reinterpret_cast<double *>(base + p.kval);
     h.d.lpan = reinterpret_cast<double *>(base + p.lpan);
+    h.d.upan = reinterpret_cast<double *>(base + p.upan);
     h.d.dval = reinterpret_cast<double *>(base + p.dval);
     h.d.spart = reinterpret_cast<double *>(base + p.spart);
     h.d.sbb = reinterpret_cast<double *>(base + p.sbb);

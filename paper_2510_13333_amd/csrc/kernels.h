@@ -21,6 +21,7 @@ struct DevArgs {
     int64_t asm_wthreads;          // assembly threads of the templates (wavefront-aligned), then border pg
     int64_t tiles;              // state transpose tiles of all templates
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
+    double *upan;                  // U = L D on the off-diagonal panel rows (rows >= w), panel layout
     double *zint, *sint;        // interleaved copies of the state and Sigma (assembly input)
     int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits
     const uint8_t *bprim;       // [nbd_tot] expected sign of the border pivots

@@ -61,31 +61,32 @@ __device__ inline int lane_id() { return int(threadIdx.x & 63); }
 // a wavefront keeps many loads in flight instead of waiting on each product
 // in turn, and no load is wasted on padding.
 
-// L[a] d[k] L[c] for R consecutive terms, added into R partial sums
+// U[a] L[c] (= L[a] d[k] L[c], U = L D) for R consecutive terms, added
+// into R partial sums
 template <int R>
-__device__ inline void tdot_round(const double *__restrict__ Lp, const double *__restrict__ Dv, int64_t nb,
+__device__ inline void tdot_round(const double *__restrict__ Lp, const double *__restrict__ Up, int64_t nb,
                                   const Term *__restrict__ tm, double *s) {
     double p[R];
 #pragma unroll
     for (int u = 0; u < R; u++) {
         const auto *q = cs(tm) + u;
-        p[u] = Lp[int64_t(q->a) * nb] * Dv[int64_t(q->k) * nb] * Lp[int64_t(q->c) * nb];
+        p[u] = Up[int64_t(q->a) * nb] * Lp[int64_t(q->c) * nb];
     }
 #pragma unroll
     for (int u = 0; u < R; u++) s[u] += p[u];
 }
 
-// sum over terms of L[a] d[k] L[c]
-__device__ inline double tdot(const double *__restrict__ Lp, const double *__restrict__ Dv, int64_t nb,
+// sum over terms of U[a] L[c]
+__device__ inline double tdot(const double *__restrict__ Lp, const double *__restrict__ Up, int64_t nb,
                               const Term *__restrict__ tm, int t0, int t1) {
     double s[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) s[u] = 0.0;
     int t = t0;
-    for (; t + 8 <= t1; t += 8) tdot_round<8>(Lp, Dv, nb, tm + t, s);
-    if (t + 4 <= t1) { tdot_round<4>(Lp, Dv, nb, tm + t, s); t += 4; }
-    if (t + 2 <= t1) { tdot_round<2>(Lp, Dv, nb, tm + t, s + 4); t += 2; }
-    if (t < t1) tdot_round<1>(Lp, Dv, nb, tm + t, s + 6);
+    for (; t + 8 <= t1; t += 8) tdot_round<8>(Lp, Up, nb, tm + t, s);
+    if (t + 4 <= t1) { tdot_round<4>(Lp, Up, nb, tm + t, s); t += 4; }
+    if (t + 2 <= t1) { tdot_round<2>(Lp, Up, nb, tm + t, s + 4); t += 2; }
+    if (t < t1) tdot_round<1>(Lp, Up, nb, tm + t, s + 6);
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(kWG) void k_fac_gather(DevArgs a, const Work *__res
     const int e = W.k;
     const int kp = cs(T.ent_kpos)[e];
     double v = kp >= 0 ? a.kval[T.kbase + W.bl + int64_t(kp) * nb] : 0.0;
-    v -= tdot(a.lpan + T.lbase + W.bl, a.dval + T.dbase + W.bl, nb, T.terms, cs(T.ent_tptr)[e], cs(T.ent_tptr)[e + 1]);
+    v -= tdot(a.lpan + T.lbase + W.bl, a.upan + T.lbase + W.bl, nb, T.terms, cs(T.ent_tptr)[e], cs(T.ent_tptr)[e + 1]);
     if (W.on) a.lpan[T.lbase + W.bl + int64_t(cs(T.ent_out)[e]) * nb] = v;
 }
 
@@ -615,7 +616,8 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
 }
 
 // P: width-1 supernodes, one per wavefront: d = P(0,0) and L(p,0) =
-// P(p,0) / d for the rows p below it (their loads all in flight together).
+// P(p,0) / d for the rows p below it (their loads all in flight together);
+// U(p,0) = L(p,0) d is the row's value before the division.
 // A kernel of its own, so that these many small tasks run at the occupancy
 // of their few registers rather than that of the wide classes of C.
 __global__ __launch_bounds__(kWG) void k_fac_pivots(DevArgs a, const Work *__restrict__ wl, int nw) {
@@ -628,6 +630,7 @@ __global__ __launch_bounds__(kWG) void k_fac_pivots(DevArgs a, const Work *__res
     const int s = W.k;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
     double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
+    double *U = a.upan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
     const double d = P[0];
     a.dval[T.dbase + W.bl + int64_t(cs(T.sup_first)[s]) * nb] = d;
     int p = 1;
@@ -636,12 +639,19 @@ __global__ __launch_bounds__(kWG) void k_fac_pivots(DevArgs a, const Work *__res
 #pragma unroll
         for (int u = 0; u < 4; u++) v[u] = P[int64_t(p + u) * nb];
 #pragma unroll
-        for (int u = 0; u < 4; u++) P[int64_t(p + u) * nb] = v[u] / d;
+        for (int u = 0; u < 4; u++) {
+            P[int64_t(p + u) * nb] = v[u] / d;
+            U[int64_t(p + u) * nb] = v[u];
+        }
     }
-    for (; p < r; p++) P[int64_t(p) * nb] = P[int64_t(p) * nb] / d;
+    for (; p < r; p++) {
+        const double v = P[int64_t(p) * nb];
+        P[int64_t(p) * nb] = v / d;
+        U[int64_t(p) * nb] = v;
+    }
 }
 
-// C: off-diagonal rows of wide supernodes.  Row p >= w: u_j = L(p,j) d_j
+// C: off-diagonal rows of wide supernodes (U(p,j) = u_j is kept too).  Row p >= w: u_j = L(p,j) d_j
 // satisfies u_j = P(p,j) - sum_{k<j} L(j,k) u_k, solved right-looking
 // (u_k -= L(k,j) u_j for k > j; the loads of L do not depend on u), then
 // L(p,j) = u_j / d_j.
@@ -673,10 +683,14 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
             }
         }
         if (W.on) {
+            double *U = a.upan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
 #pragma unroll
             for (int j = 0; j < W_; j++) {
                 const double d = Dv[int64_t(j < w ? j : wl1) * nb];
-                if (j < w) P[(int64_t(j) * r + p) * nb] = u[j] / d;
+                if (j < w) {
+                    P[(int64_t(j) * r + p) * nb] = u[j] / d;
+                    U[(int64_t(j) * r + p) * nb] = u[j];
+                }
             }
         }
     });
@@ -685,19 +699,17 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
 // Border Schur contribution S_k[i, j] = sum over the supernodes s holding
 // border rows i and j of L_s[i,:] D_s L_s[j,:]^T.  One wavefront takes the
 // entries (i, j0 .. j0+7) of one tile: for every item (supernode) it loads
-// L_s[i, k] d_k once and reuses it for each tile row the supernode holds, so
-// a product costs about one load instead of three.  Columns are taken 8,
-// 4, 2, 1 at a time.  Written entry-major, block fastest.
+// U_s[i, k] = L_s[i, k] d_k once and reuses it for each tile row the
+// supernode holds, so a product costs about one load instead of three.
+// Columns are taken 8, 4, 2, 1 at a time.  Written entry-major, block
+// fastest.
 template <int C>
-__device__ inline void schur_round(const double *__restrict__ Lp, const double *__restrict__ Dv, int64_t nb,
+__device__ inline void schur_round(const double *__restrict__ Lp, const double *__restrict__ Up, int64_t nb,
                                    const __attribute__((address_space(4))) STile *st, int k0, double *acc) {
     const int64_t r = st->r;
     double li[C];
 #pragma unroll
-    for (int u = 0; u < C; u++) {
-        const int64_t k = k0 + u;
-        li[u] = Lp[(st->pi + k * r) * nb] * Dv[(st->dcol + k) * nb];
-    }
+    for (int u = 0; u < C; u++) li[u] = Up[(st->pi + int64_t(k0 + u) * r) * nb];
     const int mask = st->mask;
 #pragma unroll
     for (int jj = 0; jj < kSchurTJ; jj++) {
@@ -720,7 +732,7 @@ __global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a, const Work *__r
     const int q = W.k;
     const int i = cs(T.stile_ij)[2 * q], j0 = cs(T.stile_ij)[2 * q + 1];
     const double *__restrict__ Lp = a.lpan + T.lbase + W.bl;
-    const double *__restrict__ Dv = a.dval + T.dbase + W.bl;
+    const double *__restrict__ Up = a.upan + T.lbase + W.bl;
     double acc[kSchurTJ];
 #pragma unroll
     for (int jj = 0; jj < kSchurTJ; jj++) acc[jj] = 0.0;
@@ -729,10 +741,10 @@ __global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a, const Work *__r
         const auto *st = cs(T.stiles) + it;
         const int w = st->w;
         int k0 = 0;
-        for (; k0 + 8 <= w; k0 += 8) schur_round<8>(Lp, Dv, nb, st, k0, acc);
-        if (k0 + 4 <= w) { schur_round<4>(Lp, Dv, nb, st, k0, acc); k0 += 4; }
-        if (k0 + 2 <= w) { schur_round<2>(Lp, Dv, nb, st, k0, acc); k0 += 2; }
-        if (k0 < w) schur_round<1>(Lp, Dv, nb, st, k0, acc);
+        for (; k0 + 8 <= w; k0 += 8) schur_round<8>(Lp, Up, nb, st, k0, acc);
+        if (k0 + 4 <= w) { schur_round<4>(Lp, Up, nb, st, k0, acc); k0 += 4; }
+        if (k0 + 2 <= w) { schur_round<2>(Lp, Up, nb, st, k0, acc); k0 += 2; }
+        if (k0 < w) schur_round<1>(Lp, Up, nb, st, k0, acc);
     }
     if (!W.on) return;
     const InstDev &I = a.insts[T.inst];

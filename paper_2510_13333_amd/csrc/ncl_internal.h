@@ -269,7 +269,7 @@ struct Handle {
     bool bound = false;
     struct Dev {
         double *kval = nullptr;          // interleaved K, then the border K_bb values of every instance
-        double *lpan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
+        double *lpan = nullptr, *upan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
                *cpart = nullptr;
         double *zint = nullptr, *sint = nullptr;   // state and Sigma in the blocks' interleaved layout order
         int64_t *stat = nullptr;
