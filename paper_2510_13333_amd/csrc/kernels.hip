@@ -560,6 +560,52 @@ __device__ inline void by_width(int w, F &&f) {
 // value through LDS, every lane reads the pivot and the column by broadcast
 // reads, and row i takes l_ij = a_ij / d_j and a_ik -= l_ij a_kj (k <= i).
 // Row i ends with l_ik (k < i) and d_i.
+// Narrow diagonal blocks (w <= kNarrowW): one block per lane, the whole
+// block in registers, the same right-looking steps (and so the same bits)
+// as the wide path.
+template <int W>
+__device__ inline void diag_narrow(const DevArgs &a, const TemplDev &T, int s, int g) {
+    const int64_t nb = T.nblk;
+    const int b = g * 64 + lane_id();
+    if (b >= nb) return;
+    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    double *P = a.lpan + T.lbase + b + int64_t(cs(T.panel_off)[s]) * nb;
+    const int wl1 = w - 1;
+    double A[W][W];
+#pragma unroll
+    for (int i = 0; i < W; i++)
+#pragma unroll
+        for (int k = 0; k <= i; k++) {
+            const double v = P[(int64_t(k) * r + (i < w ? i : wl1)) * nb];
+            A[i][k] = (i < w) ? v : 0.0;
+        }
+#pragma unroll
+    for (int j = 0; j < W; j++) {
+        if (j < w) {
+            const double dj = A[j][j];
+            double l[W];
+#pragma unroll
+            for (int i = j + 1; i < W; i++) l[i] = A[i][j] / dj;
+            // A[k][j] is read before any row's column j is scaled
+#pragma unroll
+            for (int i = j + 1; i < W; i++)
+#pragma unroll
+                for (int k = j + 1; k <= i; k++) A[i][k] -= l[i] * A[k][j];
+#pragma unroll
+            for (int i = j + 1; i < W; i++) A[i][j] = l[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+        if (i < w) {
+#pragma unroll
+            for (int k = 0; k < i; k++) P[(int64_t(k) * r + i) * nb] = A[i][k];
+            a.dval[T.dbase + b + int64_t(f + i) * nb] = A[i][i];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restrict__ wl, int nw) {
     __shared__ double cbuf[kWG / 64][2][2][kMaxW];     // wavefront, step parity, half, row
     const int wid = wave_id();
@@ -568,6 +614,15 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
     const int half = lane >> 5, i = lane & 31;
     const Work wk = wl[wid];
     const TemplDev &T = a.tmpls[wk.tg >> 16];
+    if (wk.k & kNarrowFlag) {
+        const int sn = wk.k & ~kNarrowFlag;
+        const int wn = cs(T.sup_first)[sn + 1] - cs(T.sup_first)[sn];
+        const int g = wk.tg & 0xffff;
+        if (wn <= 2) diag_narrow<2>(a, T, sn, g);
+        else if (wn <= 4) diag_narrow<4>(a, T, sn, g);
+        else diag_narrow<kNarrowW>(a, T, sn, g);
+        return;
+    }
     const int nb = T.nblk;
     const int b = (wk.tg & 0xffff) * 2 + half;
     const int bl = b < nb ? b : 0;

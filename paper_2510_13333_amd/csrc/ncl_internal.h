@@ -19,6 +19,8 @@
 namespace ncl {
 
 constexpr int kMaxW = 32;            // widest supernode
+constexpr int kNarrowW = 8;          // diagonal blocks up to this width are factored one block per lane
+constexpr int32_t kNarrowFlag = 0x40000000;   // marks such a supernode in the diagonal-block work list
 constexpr int32_t kBorderFlag = int32_t(1u << 30);   // slot refers to the border K_bb pattern
 
 // ---------------------------------------------------------------- device tables

@@ -281,12 +281,23 @@ int build_schedule(Handle &h) {
                     last_s = s;
                 }
             }
+            // diagonal blocks: narrow ones per 64-block group (a block per
+            // lane), wide ones per 2-block group (a block per half wavefront)
+            for (int g = 0; g < ng64; g++) {
+                int last_s = -1;
+                for (int32_t k : t.lev_tasks[l]) {
+                    const int s = t.task_s[k];
+                    const int w = t.sup[s + 1] - t.sup[s];
+                    if (w > 1 && w <= kNarrowW && s != last_s) S.b.push_back(Work{tg(ti, g), s | kNarrowFlag});
+                    last_s = s;
+                }
+            }
             for (int g = 0; g < ng2; g++) {
                 int last_s = -1;
                 for (int32_t k : t.lev_tasks[l]) {
                     const int s = t.task_s[k];
                     const int w = t.sup[s + 1] - t.sup[s];
-                    if (w > 1 && s != last_s) S.b.push_back(Work{tg(ti, g), s});
+                    if (w > kNarrowW && s != last_s) S.b.push_back(Work{tg(ti, g), s});
                     last_s = s;
                 }
             }
