@@ -301,8 +301,8 @@ enum {
     NCL_K_ASSEMBLE = 0,     /* k_assemble */
     NCL_K_VALUES,           /* k_values (set/get values; not part of a step) */
     NCL_K_FAC_GATHER,       /* k_fac_gather: panel entries minus descendant updates, one launch per level */
-    NCL_K_FAC_DIAG,         /* k_fac_diag: LDL^T of wide diagonal blocks, per level */
-    NCL_K_FAC_ROWS,         /* k_fac_rows: pivots and off-diagonal rows, per level */
+    NCL_K_FAC_DIAG,         /* k_fac_diag: LDL^T of diagonal blocks, and the pivots of width-1 supernodes, per level */
+    NCL_K_FAC_ROWS,         /* k_fac_rows: off-diagonal rows of supernodes 2 or more wide, per level */
     NCL_K_BORDER_SCHUR,     /* k_border_schur: per-block border Schur contributions */
     NCL_K_BORDER_SUM,       /* k_border_sum: fixed-order sum into the border matrix */
     NCL_K_BORDER_FACTOR,    /* k_border_factor: dense border LDL^T */
@@ -313,14 +313,12 @@ enum {
     NCL_K_SOL_FWD_DIAG,     /* k_sol_fwd_diag, per level */
     NCL_K_SOL_BPART,        /* k_sol_bpart */
     NCL_K_SOL_BORDER,       /* k_sol_border */
-    NCL_K_SOL_SCALE,        /* k_sol_scale */
-    NCL_K_SOL_BWD_GATHER,   /* k_sol_bwd_gather, per level */
+    NCL_K_SOL_BWD_GATHER,   /* k_sol_bwd_gather, per level (applies D^-1 to its column first) */
     NCL_K_SOL_BWD_DIAG,     /* k_sol_bwd_diag, per level */
     NCL_K_SOL_STORE,        /* k_sol_store */
     NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
     NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */
     NCL_K_INTERLEAVE,       /* k_interleave: the state transposed to the blocks' interleaved order (assembly) */
-    NCL_K_FAC_PIVOTS,       /* k_fac_pivots: pivot and column of width-1 supernodes, per level */
     NCL_K_COUNT
 };
 

@@ -147,7 +147,6 @@ std::vector<ncl::Work> all_work(Handle &h) {
     app(S.a, h.w_a);
     app(S.b, h.w_b);
     app(S.c, h.w_c);
-    app(S.p, h.w_p);
     app(S.f, h.w_f);
     app(S.d, h.w_d);
     app(S.g, h.w_g);
@@ -273,7 +272,6 @@ void kernel_model(Handle &h) {
     levels(NCL_K_FAC_GATHER, S.a_ptr);
     levels(NCL_K_FAC_DIAG, S.b_ptr);
     levels(NCL_K_FAC_ROWS, S.c_ptr);
-    levels(NCL_K_FAC_PIVOTS, S.p_ptr);
     levels(NCL_K_SOL_FWD_GATHER, S.f_ptr);
     levels(NCL_K_SOL_FWD_DIAG, S.d_ptr);
     levels(NCL_K_SOL_BWD_GATHER, S.g_ptr);
@@ -295,8 +293,8 @@ void kernel_model(Handle &h) {
             if (mk[q.k] != stamp) { mk[q.k] = stamp; uk++; }
         };
         for (int l = 0; l < t.nlev; l++) {
-            // factor: gather (A), diagonal blocks (B), rows (C), width-1 pivots (P)
-            int64_t ents = 0, kr = 0, up = 0, uk = 0, bdiag = 0, rows = 0, piv = 0;
+            // factor: gather (A), diagonal blocks and width-1 pivots (B), rows (C)
+            int64_t ents = 0, kr = 0, up = 0, uk = 0, bdiag = 0, rows = 0;
             stamp++;
             int last_s = -1;
             for (int32_t k : t.lev_tasks[l]) {
@@ -309,7 +307,7 @@ void kernel_model(Handle &h) {
                     if (t.ent_kpos[e] >= 0) kr++;
                     for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq_ul(t.terms[q], up, uk);
                 }
-                if (w == 1) piv += p > 0 ? 3 : 2;                // entry read, L and U (or d) written
+                if (w == 1) bdiag += p > 0 ? 3 : 2;              // entry read, L and U (or d) written
                 else if (p >= w) rows += 3 * w;
                 if (w > 1 && s != last_s) {
                     bdiag += int64_t(w) * (w + 1) + w;            // diagonal block read and written, pivots
@@ -320,7 +318,6 @@ void kernel_model(Handle &h) {
             B[NCL_K_FAC_GATHER] += nb * D * (ents + kr + up + uk);
             B[NCL_K_FAC_DIAG] += nb * D * bdiag;
             B[NCL_K_FAC_ROWS] += nb * D * rows;
-            B[NCL_K_FAC_PIVOTS] += nb * D * piv;
             // solves: forward gather (F) and backward gather (G) of the diagonal rows, diagonal solves (D)
             int64_t fr = 0, fup = 0, fuy = 0, gr = 0, gp = 0, guy = 0, dd = 0;
             stamp++;
@@ -343,7 +340,7 @@ void kernel_model(Handle &h) {
                 const int w = t.sup[s + 1] - t.sup[s];
                 if (p >= w) continue;
                 const int r = t.srp[s + 1] - t.srp[s];
-                gr += 2;
+                gr += 3;                                          // y read and written, d read
                 gp += r - w;
                 for (int i = t.srp[s] + w; i < t.srp[s + 1]; i++) {
                     const int row = t.sri[i];
@@ -374,9 +371,8 @@ void kernel_model(Handle &h) {
     B[NCL_K_STATUS_INIT] = D * 6;
     L[NCL_K_STATUS] = 1;
     B[NCL_K_STATUS] = D * (h.dint + h.nbd_tot);
-    L[NCL_K_SOL_LOAD] = L[NCL_K_SOL_STORE] = L[NCL_K_SOL_SCALE] = 1;
+    L[NCL_K_SOL_LOAD] = L[NCL_K_SOL_STORE] = 1;
     B[NCL_K_SOL_LOAD] = B[NCL_K_SOL_STORE] = D * 2 * h.dint;
-    B[NCL_K_SOL_SCALE] = D * 3 * h.dint;
     if (h.nbd_tot) {
         L[NCL_K_BORDER_SCHUR] = L[NCL_K_BORDER_SUM] = L[NCL_K_BORDER_FACTOR] = 1;
         L[NCL_K_SOL_BPART] = L[NCL_K_SOL_BORDER] = 1;
@@ -399,7 +395,6 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
         case NCL_K_STATUS_INIT:
         case NCL_K_STATUS: return true;
         case NCL_K_SOL_LOAD:
-        case NCL_K_SOL_SCALE:
         case NCL_K_SOL_STORE: return a.dint > 0;
         case NCL_K_RESIDUAL: return a.asm_threads + a.gp_tot > 0;
         case NCL_K_INTERLEAVE: return a.tiles + a.nbd_tot > 0;
@@ -829,7 +824,6 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
     for (int l = 0; l < S.nlev; l++) {
         if (list(NCL_K_FAC_GATHER, h.w_a, S.a_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_FAC_DIAG, h.w_b, S.b_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-        if (list(NCL_K_FAC_PIVOTS, h.w_p, S.p_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_FAC_ROWS, h.w_c, S.c_ptr, l) != hipSuccess) return NCL_ERR_HIP;
     }
     if (h.nbd_tot) {
@@ -971,7 +965,6 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
             if (run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess) return NCL_ERR_HIP;
             if (run(h, NCL_K_SOL_BORDER, a, v, st) != hipSuccess) return NCL_ERR_HIP;
         }
-        if (run(h, NCL_K_SOL_SCALE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
         for (int l = S.nlev - 1; l >= 0; l--) {
             if (list(NCL_K_SOL_BWD_GATHER, h.w_g, S.g_ptr, l) != hipSuccess) return NCL_ERR_HIP;
             if (list(NCL_K_SOL_BWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
@@ -1038,8 +1031,8 @@ const char *ncl_kernel_name(int kind) {
     static const char *names[NCL_K_COUNT] = {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
-        "k_sol_bpart", "k_sol_border", "k_sol_scale", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
-        "k_residual", "k_max_step", "k_interleave", "k_fac_pivots"};
+        "k_sol_bpart", "k_sol_border", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
+        "k_residual", "k_max_step", "k_interleave"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }
 

@@ -560,6 +560,37 @@ __device__ inline void by_width(int w, F &&f) {
 // value through LDS, every lane reads the pivot and the column by broadcast
 // reads, and row i takes l_ij = a_ij / d_j and a_ik -= l_ij a_kj (k <= i).
 // Row i ends with l_ik (k < i) and d_i.
+// Width-1 supernodes, one per wavefront (in the diagonal-block launch, not
+// in the row kernel, whose wide classes would set their occupancy): d =
+// P(0,0) and L(p,0) = P(p,0) / d for the rows p below it, their loads all in
+// flight together; U(p,0) = L(p,0) d is the row's value before the division.
+__device__ inline void fac_pivots(const DevArgs &a, const TemplDev &T, int s, int g) {
+    const int64_t nb = T.nblk;
+    const int bl = g * 64 + lane_id();
+    if (bl >= nb) return;
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+    double *P = a.lpan + T.lbase + bl + int64_t(cs(T.panel_off)[s]) * nb;
+    double *U = a.upan + T.lbase + bl + int64_t(cs(T.panel_off)[s]) * nb;
+    const double d = P[0];
+    a.dval[T.dbase + bl + int64_t(cs(T.sup_first)[s]) * nb] = d;
+    int p = 1;
+    for (; p + 4 <= r; p += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = P[int64_t(p + u) * nb];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            P[int64_t(p + u) * nb] = v[u] / d;
+            U[int64_t(p + u) * nb] = v[u];
+        }
+    }
+    for (; p < r; p++) {
+        const double v = P[int64_t(p) * nb];
+        P[int64_t(p) * nb] = v / d;
+        U[int64_t(p) * nb] = v;
+    }
+}
+
 // Narrow diagonal blocks (w <= kNarrowW): one block per lane, the whole
 // block in registers, the same right-looking steps (and so the same bits)
 // as the wide path.
@@ -614,6 +645,10 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
     const int half = lane >> 5, i = lane & 31;
     const Work wk = wl[wid];
     const TemplDev &T = a.tmpls[wk.tg >> 16];
+    if (wk.k & kPivotFlag) {
+        fac_pivots(a, T, wk.k & ~kPivotFlag, wk.tg & 0xffff);
+        return;
+    }
     if (wk.k & kNarrowFlag) {
         const int sn = wk.k & ~kNarrowFlag;
         const int wn = cs(T.sup_first)[sn + 1] - cs(T.sup_first)[sn];
@@ -670,41 +705,6 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
     });
 }
 
-// P: width-1 supernodes, one per wavefront: d = P(0,0) and L(p,0) =
-// P(p,0) / d for the rows p below it (their loads all in flight together);
-// U(p,0) = L(p,0) d is the row's value before the division.
-// A kernel of its own, so that these many small tasks run at the occupancy
-// of their few registers rather than that of the wide classes of C.
-__global__ __launch_bounds__(kWG) void k_fac_pivots(DevArgs a, const Work *__restrict__ wl, int nw) {
-    const int wid = wave_id();
-    if (wid >= nw) return;
-    const Lane W = lane_work(a, wl, wid);
-    if (!W.on) return;
-    const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
-    const int s = W.k;
-    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
-    double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
-    double *U = a.upan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
-    const double d = P[0];
-    a.dval[T.dbase + W.bl + int64_t(cs(T.sup_first)[s]) * nb] = d;
-    int p = 1;
-    for (; p + 4 <= r; p += 4) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) v[u] = P[int64_t(p + u) * nb];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            P[int64_t(p + u) * nb] = v[u] / d;
-            U[int64_t(p + u) * nb] = v[u];
-        }
-    }
-    for (; p < r; p++) {
-        const double v = P[int64_t(p) * nb];
-        P[int64_t(p) * nb] = v / d;
-        U[int64_t(p) * nb] = v;
-    }
-}
 
 // C: off-diagonal rows of wide supernodes (U(p,j) = u_j is kept too).  Row p >= w: u_j = L(p,j) d_j
 // satisfies u_j = P(p,j) - sum_{k<j} L(j,k) u_k, solved right-looking
@@ -1264,11 +1264,6 @@ __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__re
     x[a.blks[T.blocks[d.bl]].col0 + T.perm[d.j]] = y[idx];
 }
 
-__global__ __launch_bounds__(256) void k_sol_scale(DevArgs a, double *__restrict__ y) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx < a.dint) y[idx] = y[idx] / a.dval[idx];
-}
-
 // forward gather of a diagonal row: y_row -= sum over descendants L_d[row,:] y_d
 // (the terms of the row's diagonal panel entry)
 template <int NW>
@@ -1466,7 +1461,7 @@ __global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const 
     else sol_border<false>(a, I, c, b, x, y, cpart);
 }
 
-// backward gather of column p of a supernode: y_col -= sum_{i >= w} L(i, p) x_{row i},
+// backward gather of column p of a supernode: y_col = y_col / d_col - sum_{i >= w} L(i, p) x_{row i},
 // in rounds of 8, 4, 2, 1 rows (row indices are uniform; border rows read the
 // border solution)
 template <int NW>
@@ -1512,7 +1507,9 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, co
     };
     double v = split_sum<NW>(part);
     if (!split_combine<NW>(v)) return;
-    if (W.on) yb[int64_t(f + p) * nb] -= v;
+    // the column's D^-1 is applied here, just before its update
+    const int64_t c = int64_t(f + p) * nb;
+    if (W.on) yb[c] = yb[c] / a.dval[T.dbase + W.bl + c] - v;
 }
 
 // unit upper triangular solve with the transposed diagonal block:
@@ -1800,9 +1797,6 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
         case NCL_K_FAC_ROWS:
             if (l.nw) hipLaunchKernelGGL(k_fac_rows, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
             break;
-        case NCL_K_FAC_PIVOTS:
-            if (l.nw) hipLaunchKernelGGL(k_fac_pivots, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
-            break;
         case NCL_K_BORDER_SCHUR:
             if (l.nw) hipLaunchKernelGGL(k_border_schur, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
             break;
@@ -1875,9 +1869,6 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                 hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), lb, st, a, l.b, l.x, l.y, l.cpart,
                                    int64_t(lb));
             }
-            break;
-        case NCL_K_SOL_SCALE:
-            if (a.dint) hipLaunchKernelGGL(k_sol_scale, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y);
             break;
         case NCL_K_SOL_BWD_GATHER:
             if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_bwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);

@@ -21,6 +21,7 @@ namespace ncl {
 constexpr int kMaxW = 32;            // widest supernode
 constexpr int kNarrowW = 8;          // diagonal blocks up to this width are factored one block per lane
 constexpr int32_t kNarrowFlag = 0x40000000;   // marks such a supernode in the diagonal-block work list
+constexpr int32_t kPivotFlag = 0x20000000;    // marks a width-1 supernode there (its pivot and column)
 constexpr int32_t kBorderFlag = int32_t(1u << 30);   // slot refers to the border K_bb pattern
 
 // ---------------------------------------------------------------- device tables
@@ -198,11 +199,12 @@ struct Template {
 struct Schedule {
     int nlev = 0;
     // factor: A gathers every lower panel entry (k = entry); B factors the
-    // diagonal blocks of wide supernodes (two blocks per wavefront); C the
-    // off-diagonal rows of wide supernodes (k = row task); P the pivot and
-    // column of width-1 supernodes (k = supernode)
-    std::vector<int32_t> a_ptr, b_ptr, c_ptr, p_ptr;    // [nlev+1]
-    std::vector<Work> a, b, c, p;
+    // diagonal blocks (narrow ones a block per lane, wide ones two blocks
+    // per wavefront) and the pivot and column of width-1 supernodes
+    // (k = supernode, flagged); C the off-diagonal rows of supernodes 2 or
+    // more wide (k = row task)
+    std::vector<int32_t> a_ptr, b_ptr, c_ptr;           // [nlev+1]
+    std::vector<Work> a, b, c;
     // solve: forward gathers of the diagonal rows, diagonal solves of wide supernodes
     // (backward: gathers of every diagonal row, then the same diagonal solves)
     std::vector<int32_t> f_ptr, d_ptr, g_ptr;           // [nlev+1]
@@ -282,7 +284,7 @@ struct Handle {
         const uint8_t *bprim = nullptr;
     } d;
     // offsets of each work list inside d.work
-    size_t w_a = 0, w_b = 0, w_c = 0, w_p = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
+    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
     // per kernel kind: launches and algorithmic bytes of one step
     std::vector<int64_t> km_launch, km_bytes;
     // event profiling of one kernel kind (events are hipEvent_t, in pairs)

@@ -247,7 +247,6 @@ int build_schedule(Handle &h) {
     S.a_ptr.assign(1, 0);
     S.b_ptr.assign(1, 0);
     S.c_ptr.assign(1, 0);
-    S.p_ptr.assign(1, 0);
     S.f_ptr.assign(1, 0);
     S.d_ptr.assign(1, 0);
     S.g_ptr.assign(1, 0);
@@ -269,7 +268,6 @@ int build_schedule(Handle &h) {
                     const int w = t.sup[s + 1] - t.sup[s];
                     const int cend = p < w ? p + 1 : w;     // lower triangle of the diagonal block
                     for (int c = 0; c < cend; c++) S.a.push_back(Work{tg(ti, g), t.task_cbase[k] + c});
-                    if (w == 1 && s != last_s) S.p.push_back(Work{tg(ti, g), s});
                     if (w > 1 && p >= w) S.c.push_back(Work{tg(ti, g), k});
                     if (p < w) {
                         // the diagonal entry's items are exactly the descendants holding this row
@@ -281,13 +279,15 @@ int build_schedule(Handle &h) {
                     last_s = s;
                 }
             }
-            // diagonal blocks: narrow ones per 64-block group (a block per
-            // lane), wide ones per 2-block group (a block per half wavefront)
+            // diagonal blocks: width-1 pivots and narrow blocks per 64-block
+            // group (a block per lane), wide ones per 2-block group (a block
+            // per half wavefront)
             for (int g = 0; g < ng64; g++) {
                 int last_s = -1;
                 for (int32_t k : t.lev_tasks[l]) {
                     const int s = t.task_s[k];
                     const int w = t.sup[s + 1] - t.sup[s];
+                    if (w == 1 && s != last_s) S.b.push_back(Work{tg(ti, g), s | kPivotFlag});
                     if (w > 1 && w <= kNarrowW && s != last_s) S.b.push_back(Work{tg(ti, g), s | kNarrowFlag});
                     last_s = s;
                 }
@@ -305,7 +305,6 @@ int build_schedule(Handle &h) {
         S.a_ptr.push_back(int32_t(S.a.size()));
         S.b_ptr.push_back(int32_t(S.b.size()));
         S.c_ptr.push_back(int32_t(S.c.size()));
-        S.p_ptr.push_back(int32_t(S.p.size()));
         S.f_ptr.push_back(int32_t(S.f.size()));
         S.d_ptr.push_back(int32_t(S.d.size()));
         S.g_ptr.push_back(int32_t(S.g.size()));
