@@ -49,6 +49,7 @@ WORKLOADS = {
     5: "2000-bus synthetic grid x 64 branch-outage contingencies (N=907760), rho=1e4, FP64",
 }
 COPY_DOUBLES = 64 * 2 ** 20          # the plain copy whose counters calibrate FETCH_SIZE / WRITE_SIZE
+PROFILE_STRIDE = 7                   # one launch in 7 of the dominant kernel is event-timed in the timed region
 KERNELS_SRC = os.path.join(ROOT, "paper_2510_13333_amd", "csrc", "kernels.hip")
 
 
@@ -101,7 +102,7 @@ def roofline(k, kind, n_launch, ms_total, cfg):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name, cfg), "kernel": name,
             "algorithmic_bytes_per_launch": per_launch_bytes, "launches_per_step": launches,
-            "avg_launch_us": t_launch * 1e6}
+            "avg_launch_us": t_launch * 1e6, "launches_timed": n_launch, "timed_every": PROFILE_STRIDE}
 
 
 def copy_calibration():
@@ -182,9 +183,12 @@ def run_single(args):
     torch.cuda.synchronize()
     info = k.info()
     dom, per_kind = dominant_kernel(k, step)
-    # timed region: wall clock over exactly `steps` steps; the dominant
-    # kernel's launches are bracketed by events on their stream meanwhile
+    # timed region: wall clock over exactly `steps` steps; meanwhile every
+    # PROFILE_STRIDE-th launch of the dominant kernel is bracketed by events
+    # on its stream (a stride coprime with the launches per step samples
+    # every level evenly and keeps the event records few)
     k.profile(dom)
+    k.profile_stride(PROFILE_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -195,7 +199,8 @@ def run_single(args):
     k.profile(-1)
     roof = roofline(k, dom, n_dom, ms_dom, cfg)
     print(f"[bench] timed {args.steps} steps: {wall / args.steps * 1e3:.3f} ms/step; dominant "
-          f"{roof['kernel']} {roof['avg_launch_us']:.1f} us/launch x {n_dom // args.steps}", file=sys.stderr,
+          f"{roof['kernel']} {roof['avg_launch_us']:.1f} us/launch x {roof['launches_per_step']} per step "
+          f"({n_dom} launches sampled)", file=sys.stderr,
           flush=True)
     # phase timing with events (separate pass over the same steps)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
@@ -300,6 +305,7 @@ def run_batched(args):
     info = kb.info()
     dom, per_kind = dominant_kernel(kb, step)
     kb.profile(dom)
+    kb.profile_stride(PROFILE_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

@@ -332,9 +332,15 @@ const char *ncl_kernel_name(int kind);
 int ncl_kkt_kernel_model(const ncl_kkt *h, int32_t kind, int64_t *launches, int64_t *bytes);
 
 /* Bracket every later launch of one kernel kind with a pair of HIP events
- * on the launch stream (kind = -1: stop).  Resets the accumulated record.
- * Launches of other kinds are not touched. */
+ * on the launch stream (kind = -1: stop).  Resets the accumulated record and
+ * the stride to 1.  Launches of other kinds are not touched. */
 int ncl_kkt_profile(ncl_kkt *h, int32_t kind);
+
+/* Bracket only every stride-th launch of the profiled kind (counted from
+ * the next launch; stride >= 1, else NCL_ERR_ARG).  A stride coprime with
+ * the kind's launches per step samples every level evenly over that many
+ * steps while adding fewer event records to the stream. */
+int ncl_kkt_profile_stride(ncl_kkt *h, int32_t stride);
 
 /* Number of bracketed launches since ncl_kkt_profile and the sum of their
  * event-measured durations in milliseconds (waits for the last event). */

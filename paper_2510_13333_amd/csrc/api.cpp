@@ -406,6 +406,7 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
 // Launch one kernel; bracket it with events when its kind is being profiled.
 hipError_t run(Handle &h, int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l, hipStream_t st) {
     if (kind != h.prof_kind || !nonempty(kind, a, l)) return ncl::launch(kind, a, l, st);
+    if (h.prof_seen++ % h.prof_stride != 0) return ncl::launch(kind, a, l, st);
     if (2 * h.ev_used + 2 > h.ev.size()) {
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return hipErrorOutOfMemory;
@@ -1047,6 +1048,15 @@ int ncl_kkt_profile(ncl_kkt *k, int32_t kind) {
     if (!k || kind < -1 || kind >= NCL_K_COUNT) return NCL_ERR_ARG;
     k->h.prof_kind = kind;
     k->h.ev_used = 0;
+    k->h.prof_stride = 1;
+    k->h.prof_seen = 0;
+    return NCL_OK;
+}
+
+int ncl_kkt_profile_stride(ncl_kkt *k, int32_t stride) {
+    if (!k || stride < 1) return NCL_ERR_ARG;
+    k->h.prof_stride = stride;
+    k->h.prof_seen = 0;
     return NCL_OK;
 }
 

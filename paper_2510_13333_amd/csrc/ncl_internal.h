@@ -289,6 +289,7 @@ struct Handle {
     std::vector<int64_t> km_launch, km_bytes;
     // event profiling of one kernel kind (events are hipEvent_t, in pairs)
     int prof_kind = -1;
+    int64_t prof_stride = 1, prof_seen = 0;   // bracket every prof_stride-th launch of prof_kind
     std::vector<void *> ev;
     size_t ev_used = 0;
 };

@@ -108,6 +108,7 @@ def load():
         "ncl_kernel_name": ([ctypes.c_int], ctypes.c_char_p),
         "ncl_kkt_kernel_model": ([P, i32, P, P], ctypes.c_int),
         "ncl_kkt_profile": ([P, i32], ctypes.c_int),
+        "ncl_kkt_profile_stride": ([P, i32], ctypes.c_int),
         "ncl_kkt_profile_read": ([P, P, P], ctypes.c_int),
         "ncl_kkt_residual": ([P, P, P, P, P, P], ctypes.c_int),
         "ncl_kkt_layout_kinds": ([P, P], ctypes.c_int),
@@ -360,6 +361,10 @@ class KKT:
     def profile(self, kind):
         """Bracket later launches of one kernel kind with HIP events (-1 stops)."""
         _check("ncl_kkt_profile", load().ncl_kkt_profile(self._h, int(kind)))
+
+    def profile_stride(self, stride):
+        """Bracket only every stride-th launch of the profiled kind."""
+        _check("ncl_kkt_profile_stride", load().ncl_kkt_profile_stride(self._h, int(stride)))
 
     def profile_read(self):
         """(bracketed launches, their summed event time in ms)."""

@@ -185,5 +185,14 @@ def test_profiling_brackets_each_kind():
         launches, nbytes = kb.kernel_model(kind)
         assert n == launches, (name, n, launches)
         assert ms >= 0.0 and nbytes >= 0
+    # a stride brackets every stride-th launch only (levels sampled in turn)
+    gather = KERNELS.index("fac_gather")
+    kb.profile(gather)
+    kb.profile_stride(2)
+    kb.assemble(z, s, nets[0].rho)
+    kb.factor()
+    kb.solve(b, out=x)
+    n, ms = kb.profile_read()
+    assert n == (kb.kernel_model(gather)[0] + 1) // 2 and ms > 0.0
     kb.profile(-1)
     assert kb.profile_read() == (0, 0.0)

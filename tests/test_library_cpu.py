@@ -173,3 +173,11 @@ def test_kernel_model_counts():
     assert m["sol_fwd_diag"] == m["sol_bwd_diag"]
     # assembly reads z and sigma and writes every K value
     assert m["assemble"][1] == 8 * (2 * k.N + k.nnzK)
+
+
+def test_profile_stride_arguments():
+    """The profiling stride is checked on the host (no GPU needed)."""
+    k = KKT(G.config_network(1))
+    k.profile_stride(3)
+    with pytest.raises(NclError):
+        k.profile_stride(0)
