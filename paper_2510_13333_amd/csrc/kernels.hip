@@ -43,6 +43,15 @@ __device__ inline const __attribute__((address_space(4))) T *cs(const T *p) {
 // that share data then share an L2.
 constexpr int kXcd = 8;
 
+// Element idx of a per-template array whose byte offsets fit 32 bits (a
+// bound checked at analysis): the uniform base stays in scalar registers
+// and the offset is one 32-bit vector value, so an address costs one
+// scalar multiply-add and one vector add instead of 64-bit scalar
+// arithmetic.
+__device__ inline double ld32(const double *base, uint32_t idx) {
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + (idx << 3));
+}
+
 __device__ inline int xcd_workgroup() {
     const int G = int(gridDim.x), b = int(blockIdx.x);
     const int q = G / kXcd, r = G % kXcd;
@@ -759,20 +768,23 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
 // Columns are taken 8, 4, 2, 1 at a time.  Written entry-major, block
 // fastest.
 template <int C>
-__device__ inline void schur_round(const double *__restrict__ Lp, const double *__restrict__ Up, int64_t nb,
-                                   const __attribute__((address_space(4))) STile *st, int k0, double *acc) {
-    const int64_t r = st->r;
+__device__ inline void schur_round(const double *__restrict__ Lb, const double *__restrict__ Ub, uint32_t nb,
+                                   uint32_t bl, const __attribute__((address_space(4))) STile *st, int k0,
+                                   double *acc) {
+    const uint32_t r = st->r, rs = r * nb;        // column stride of the panel, in elements
+    const uint32_t c0 = uint32_t(k0) * r;
     double li[C];
+    const uint32_t oi = (st->pi + c0) * nb + bl;
 #pragma unroll
-    for (int u = 0; u < C; u++) li[u] = Up[(st->pi + int64_t(k0 + u) * r) * nb];
+    for (int u = 0; u < C; u++) li[u] = ld32(Ub, oi + u * rs);
     const int mask = st->mask;
 #pragma unroll
     for (int jj = 0; jj < kSchurTJ; jj++) {
         if ((mask >> jj) & 1) {
-            const int64_t pj = st->pj[jj];
+            const uint32_t oj = (st->pj[jj] + c0) * nb + bl;
             double sj = 0.0;
 #pragma unroll
-            for (int u = 0; u < C; u++) sj += li[u] * Lp[(pj + (k0 + u) * r) * nb];
+            for (int u = 0; u < C; u++) sj += li[u] * ld32(Lb, oj + u * rs);
             acc[jj] += sj;
         }
     }
@@ -786,8 +798,9 @@ __global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a, const Work *__r
     const int64_t nb = W.nb;
     const int q = W.k;
     const int i = cs(T.stile_ij)[2 * q], j0 = cs(T.stile_ij)[2 * q + 1];
-    const double *__restrict__ Lp = a.lpan + T.lbase + W.bl;
-    const double *__restrict__ Up = a.upan + T.lbase + W.bl;
+    const double *__restrict__ Lb = a.lpan + T.lbase;
+    const double *__restrict__ Ub = a.upan + T.lbase;
+    const uint32_t nbu = uint32_t(nb), blu = uint32_t(W.bl);
     double acc[kSchurTJ];
 #pragma unroll
     for (int jj = 0; jj < kSchurTJ; jj++) acc[jj] = 0.0;
@@ -796,10 +809,10 @@ __global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a, const Work *__r
         const auto *st = cs(T.stiles) + it;
         const int w = st->w;
         int k0 = 0;
-        for (; k0 + 8 <= w; k0 += 8) schur_round<8>(Lp, Up, nb, st, k0, acc);
-        if (k0 + 4 <= w) { schur_round<4>(Lp, Up, nb, st, k0, acc); k0 += 4; }
-        if (k0 + 2 <= w) { schur_round<2>(Lp, Up, nb, st, k0, acc); k0 += 2; }
-        if (k0 < w) schur_round<1>(Lp, Up, nb, st, k0, acc);
+        for (; k0 + 8 <= w; k0 += 8) schur_round<8>(Lb, Ub, nbu, blu, st, k0, acc);
+        if (k0 + 4 <= w) { schur_round<4>(Lb, Ub, nbu, blu, st, k0, acc); k0 += 4; }
+        if (k0 + 2 <= w) { schur_round<2>(Lb, Ub, nbu, blu, st, k0, acc); k0 += 2; }
+        if (k0 < w) schur_round<1>(Lb, Ub, nbu, blu, st, k0, acc);
     }
     if (!W.on) return;
     const InstDev &I = a.insts[T.inst];

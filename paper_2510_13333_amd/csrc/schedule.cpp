@@ -224,7 +224,10 @@ int build_schedule(Handle &h) {
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int64_t nb = int64_t(t.blocks.size());
-        if (int64_t(t.n) * nb >= (int64_t(1) << 31)) return NCL_ERR_ARG;   // 32-bit pivot offsets in a template
+        // kernels address a template's panels, pivots and vectors with 32-bit
+        // byte offsets from the template's base
+        if (int64_t(t.n) * nb >= (int64_t(1) << 29) || int64_t(t.panel_off.back()) * nb >= (int64_t(1) << 29))
+            return NCL_ERR_ARG;
         h.t_kbase[ti] = h.kint;
         h.t_lbase[ti] = h.lint;
         h.t_dbase[ti] = h.dint;
