@@ -73,41 +73,41 @@ __device__ inline int lane_id() { return int(threadIdx.x & 63); }
 // U[a] L[c] (= L[a] d[k] L[c], U = L D) for R consecutive terms, added
 // into R partial sums
 template <int R>
-__device__ inline void tdot_round(const double *__restrict__ Lp, const double *__restrict__ Up, int64_t nb,
-                                  const Term *__restrict__ tm, double *s) {
+__device__ inline void tdot_round(const double *__restrict__ Lb, const double *__restrict__ Ub, uint32_t nb,
+                                  uint32_t bl, const Term *__restrict__ tm, double *s) {
     double p[R];
 #pragma unroll
     for (int u = 0; u < R; u++) {
         const auto *q = cs(tm) + u;
-        p[u] = Up[int64_t(q->a) * nb] * Lp[int64_t(q->c) * nb];
+        p[u] = ld32(Ub, uint32_t(q->a) * nb + bl) * ld32(Lb, uint32_t(q->c) * nb + bl);
     }
 #pragma unroll
     for (int u = 0; u < R; u++) s[u] += p[u];
 }
 
-// sum over terms of U[a] L[c]
-__device__ inline double tdot(const double *__restrict__ Lp, const double *__restrict__ Up, int64_t nb,
+// sum over terms of U[a] L[c] (template bases Lb, Ub; the lane's block bl)
+__device__ inline double tdot(const double *__restrict__ Lb, const double *__restrict__ Ub, uint32_t nb, uint32_t bl,
                               const Term *__restrict__ tm, int t0, int t1) {
     double s[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) s[u] = 0.0;
     int t = t0;
-    for (; t + 8 <= t1; t += 8) tdot_round<8>(Lp, Up, nb, tm + t, s);
-    if (t + 4 <= t1) { tdot_round<4>(Lp, Up, nb, tm + t, s); t += 4; }
-    if (t + 2 <= t1) { tdot_round<2>(Lp, Up, nb, tm + t, s + 4); t += 2; }
-    if (t < t1) tdot_round<1>(Lp, Up, nb, tm + t, s + 6);
+    for (; t + 8 <= t1; t += 8) tdot_round<8>(Lb, Ub, nb, bl, tm + t, s);
+    if (t + 4 <= t1) { tdot_round<4>(Lb, Ub, nb, bl, tm + t, s); t += 4; }
+    if (t + 2 <= t1) { tdot_round<2>(Lb, Ub, nb, bl, tm + t, s + 4); t += 2; }
+    if (t < t1) tdot_round<1>(Lb, Ub, nb, bl, tm + t, s + 6);
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // L[a] y[k] for R consecutive terms
 template <int R>
-__device__ inline void ydot_round(const double *__restrict__ Lp, const double *y, int64_t nb,
+__device__ inline void ydot_round(const double *__restrict__ Lb, const double *yb, uint32_t nb, uint32_t bl,
                                   const Term *__restrict__ tm, double *s) {
     double p[R];
 #pragma unroll
     for (int u = 0; u < R; u++) {
         const auto *q = cs(tm) + u;
-        p[u] = Lp[int64_t(q->a) * nb] * y[int64_t(q->k) * nb];
+        p[u] = ld32(Lb, uint32_t(q->a) * nb + bl) * ld32(yb, uint32_t(q->k) * nb + bl);
     }
 #pragma unroll
     for (int u = 0; u < R; u++) s[u] += p[u];
@@ -121,19 +121,20 @@ __device__ inline void ydot_round(const double *__restrict__ Lp, const double *y
 // launch may pick the split by how many tasks it has.
 constexpr int kSplit = 4;
 
-// partial q of the split sum of L[a] y[k] over terms [t0, t1)
-__device__ inline double ydot_q(const double *__restrict__ Lp, const double *y, int64_t nb,
+// partial q of the split sum of L[a] y[k] over terms [t0, t1) (template
+// bases Lb, yb; the lane's block bl)
+__device__ inline double ydot_q(const double *__restrict__ Lb, const double *yb, uint32_t nb, uint32_t bl,
                                 const Term *__restrict__ tm, int t0, int t1, int q) {
     double s[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) s[u] = 0.0;
     const int nc = (t1 - t0) >> 3;
-    for (int c = q; c < nc; c += kSplit) ydot_round<8>(Lp, y, nb, tm + t0 + 8 * c, s);
+    for (int c = q; c < nc; c += kSplit) ydot_round<8>(Lb, yb, nb, bl, tm + t0 + 8 * c, s);
     if (q == 0) {
         int t = t0 + 8 * nc;
-        if (t + 4 <= t1) { ydot_round<4>(Lp, y, nb, tm + t, s); t += 4; }
-        if (t + 2 <= t1) { ydot_round<2>(Lp, y, nb, tm + t, s + 4); t += 2; }
-        if (t < t1) ydot_round<1>(Lp, y, nb, tm + t, s + 6);
+        if (t + 4 <= t1) { ydot_round<4>(Lb, yb, nb, bl, tm + t, s); t += 4; }
+        if (t + 2 <= t1) { ydot_round<2>(Lb, yb, nb, bl, tm + t, s + 4); t += 2; }
+        if (t < t1) ydot_round<1>(Lb, yb, nb, bl, tm + t, s + 6);
     }
     return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
@@ -541,7 +542,8 @@ __global__ __launch_bounds__(kWG) void k_fac_gather(DevArgs a, const Work *__res
     const int e = W.k;
     const int kp = cs(T.ent_kpos)[e];
     double v = kp >= 0 ? a.kval[T.kbase + W.bl + int64_t(kp) * nb] : 0.0;
-    v -= tdot(a.lpan + T.lbase + W.bl, a.upan + T.lbase + W.bl, nb, T.terms, cs(T.ent_tptr)[e], cs(T.ent_tptr)[e + 1]);
+    v -= tdot(a.lpan + T.lbase, a.upan + T.lbase, uint32_t(nb), uint32_t(W.bl), T.terms, cs(T.ent_tptr)[e],
+              cs(T.ent_tptr)[e + 1]);
     if (W.on) a.lpan[T.lbase + W.bl + int64_t(cs(T.ent_out)[e]) * nb] = v;
 }
 
@@ -1291,8 +1293,9 @@ __global__ __launch_bounds__(kWG) void k_sol_fwd_gather(DevArgs a, double *y, co
     const int col = cs(T.sup_first)[s] + p;
     const int e = cs(T.task_cbase)[W.k] + p;
     const int t0 = cs(T.ent_tptr)[e], t1 = cs(T.ent_tptr)[e + 1];
-    const double *Lp = a.lpan + T.lbase + W.bl;
-    double v = split_sum<NW>([&](int q) { return ydot_q(Lp, yb, nb, T.terms, t0, t1, q); });
+    const double *Lb = a.lpan + T.lbase, *y0 = y + T.dbase;
+    const uint32_t nbu = uint32_t(nb), blu = uint32_t(W.bl);
+    double v = split_sum<NW>([&](int q) { return ydot_q(Lb, y0, nbu, blu, T.terms, t0, t1, q); });
     if (!split_combine<NW>(v)) return;
     if (W.on) yb[int64_t(col) * nb] -= v;
 }
@@ -1346,8 +1349,9 @@ __global__ __launch_bounds__(kWG) void k_sol_bpart(DevArgs a, const double *y, d
     const TemplDev &T = *W.T;
     const int bi = W.k;
     const int t0 = cs(T.bterm_ptr)[bi], t1 = cs(T.bterm_ptr)[bi + 1];
-    const double *Lp = a.lpan + T.lbase + W.bl, *yb = y + T.dbase + W.bl;
-    double v = split_sum<NW>([&](int q) { return ydot_q(Lp, yb, W.nb, T.bterms, t0, t1, q); });
+    const double *Lb = a.lpan + T.lbase, *y0 = y + T.dbase;
+    const uint32_t nbu = uint32_t(W.nb), blu = uint32_t(W.bl);
+    double v = split_sum<NW>([&](int q) { return ydot_q(Lb, y0, nbu, blu, T.bterms, t0, t1, q); });
     if (!split_combine<NW>(v)) return;
     const InstDev &I = a.insts[T.inst];
     if (W.on) cpart[I.cp0 + int64_t(bi) * I.nblk + (T.blocks[W.bl] - I.blk0)] = v;
@@ -1489,7 +1493,9 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, co
     const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
     const int32_t *__restrict__ R_ = T.sup_rows + cs(T.sup_rowptr)[s];
-    const double *__restrict__ Pc = a.lpan + T.lbase + W.bl + (int64_t(cs(T.panel_off)[s]) + int64_t(p) * r) * nb;
+    const double *__restrict__ Lb = a.lpan + T.lbase;
+    const double *y0 = y + T.dbase;
+    const uint32_t nbu = uint32_t(nb), blu = uint32_t(W.bl), pc0 = uint32_t(cs(T.panel_off)[s] + p * r);
     double *yb = y + T.dbase + W.bl;
     const double *xb = y + a.dint + T.bd0;
     // partial q: rounds of 8 rows c = q, q + 4, ... from row w; the tail to partial 0
@@ -1502,8 +1508,8 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, co
 #pragma unroll
             for (int u = 0; u < R.value; u++) {
                 const int ri = cs(R_)[i + u];
-                const double *xp = ri < n ? yb + int64_t(ri) * nb : xb + (ri - n);
-                x[u] = Pc[int64_t(i + u) * nb] * *xp;
+                const double xv = ri < n ? ld32(y0, uint32_t(ri) * nbu + blu) : xb[ri - n];
+                x[u] = ld32(Lb, (pc0 + uint32_t(i + u)) * nbu + blu) * xv;
             }
 #pragma unroll
             for (int u = 0; u < R.value; u++) acc[u] += x[u];
