@@ -51,6 +51,9 @@ constexpr int kXcd = 8;
 __device__ inline double ld32(const double *base, uint32_t idx) {
     return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + (idx << 3));
 }
+__device__ inline void st32(double *base, uint32_t idx, double v) {
+    *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + (idx << 3)) = v;
+}
 
 __device__ inline int xcd_workgroup() {
     const int G = int(gridDim.x), b = int(blockIdx.x);
@@ -576,29 +579,29 @@ __device__ inline void by_width(int w, F &&f) {
 // P(0,0) and L(p,0) = P(p,0) / d for the rows p below it, their loads all in
 // flight together; U(p,0) = L(p,0) d is the row's value before the division.
 __device__ inline void fac_pivots(const DevArgs &a, const TemplDev &T, int s, int g) {
-    const int64_t nb = T.nblk;
-    const int bl = g * 64 + lane_id();
+    const uint32_t nb = uint32_t(T.nblk);
+    const uint32_t bl = uint32_t(g * 64 + lane_id());
     if (bl >= nb) return;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
-    double *P = a.lpan + T.lbase + bl + int64_t(cs(T.panel_off)[s]) * nb;
-    double *U = a.upan + T.lbase + bl + int64_t(cs(T.panel_off)[s]) * nb;
-    const double d = P[0];
-    a.dval[T.dbase + bl + int64_t(cs(T.sup_first)[s]) * nb] = d;
+    double *Lb = a.lpan + T.lbase, *Ub = a.upan + T.lbase;
+    const uint32_t po = uint32_t(cs(T.panel_off)[s]);
+    const double d = ld32(Lb, po * nb + bl);
+    st32(a.dval + T.dbase, uint32_t(cs(T.sup_first)[s]) * nb + bl, d);
     int p = 1;
     for (; p + 4 <= r; p += 4) {
         double v[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) v[u] = P[int64_t(p + u) * nb];
+        for (int u = 0; u < 4; u++) v[u] = ld32(Lb, (po + uint32_t(p + u)) * nb + bl);
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            P[int64_t(p + u) * nb] = v[u] / d;
-            U[int64_t(p + u) * nb] = v[u];
+            st32(Lb, (po + uint32_t(p + u)) * nb + bl, v[u] / d);
+            st32(Ub, (po + uint32_t(p + u)) * nb + bl, v[u]);
         }
     }
     for (; p < r; p++) {
-        const double v = P[int64_t(p) * nb];
-        P[int64_t(p) * nb] = v / d;
-        U[int64_t(p) * nb] = v;
+        const double v = ld32(Lb, (po + uint32_t(p)) * nb + bl);
+        st32(Lb, (po + uint32_t(p)) * nb + bl, v / d);
+        st32(Ub, (po + uint32_t(p)) * nb + bl, v);
     }
 }
 
@@ -607,19 +610,22 @@ __device__ inline void fac_pivots(const DevArgs &a, const TemplDev &T, int s, in
 // as the wide path.
 template <int W>
 __device__ inline void diag_narrow(const DevArgs &a, const TemplDev &T, int s, int g) {
-    const int64_t nb = T.nblk;
-    const int b = g * 64 + lane_id();
+    const uint32_t nb = uint32_t(T.nblk);
+    const uint32_t b = uint32_t(g * 64 + lane_id());
     if (b >= nb) return;
     const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
-    double *P = a.lpan + T.lbase + b + int64_t(cs(T.panel_off)[s]) * nb;
+    double *Lb = a.lpan + T.lbase;
+    const uint32_t po = uint32_t(cs(T.panel_off)[s]);
+    // element (row, col) of the panel for this lane's block
+    auto at = [&](int col, int row) { return (po + uint32_t(col) * uint32_t(r) + uint32_t(row)) * nb + b; };
     const int wl1 = w - 1;
     double A[W][W];
 #pragma unroll
     for (int i = 0; i < W; i++)
 #pragma unroll
         for (int k = 0; k <= i; k++) {
-            const double v = P[(int64_t(k) * r + (i < w ? i : wl1)) * nb];
+            const double v = ld32(Lb, at(k < w ? k : wl1, i < w ? i : wl1));   // clamped inside the panel
             A[i][k] = (i < w) ? v : 0.0;
         }
 #pragma unroll
@@ -642,8 +648,8 @@ __device__ inline void diag_narrow(const DevArgs &a, const TemplDev &T, int s, i
     for (int i = 0; i < W; i++) {
         if (i < w) {
 #pragma unroll
-            for (int k = 0; k < i; k++) P[(int64_t(k) * r + i) * nb] = A[i][k];
-            a.dval[T.dbase + b + int64_t(f + i) * nb] = A[i][i];
+            for (int k = 0; k < i; k++) st32(Lb, at(k, i), A[i][k]);
+            st32(a.dval + T.dbase, uint32_t(f + i) * nb + b, A[i][i]);
         }
     }
 }
@@ -676,14 +682,17 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
     const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
     const bool on = b < nb && i < w;
-    double *P = a.lpan + T.lbase + bl + int64_t(cs(T.panel_off)[s]) * nb;   // P(row, col) = P[(col * r + row) * nb]
+    double *Lb = a.lpan + T.lbase;
+    const uint32_t po = uint32_t(cs(T.panel_off)[s]), nbu = uint32_t(nb), blu = uint32_t(bl);
+    // element (row, col) of the panel for this lane's block
+    auto at = [&](int col, int row) { return (po + uint32_t(col) * uint32_t(r) + uint32_t(row)) * nbu + blu; };
     by_width(w, [&](auto Wc) {
         constexpr int W = decltype(Wc)::value;
         const int wl1 = w - 1, ic = i < w ? i : wl1;
         double row[W];
 #pragma unroll
         for (int k = 0; k < W; k++) {
-            const double v = P[(int64_t(k < w ? k : wl1) * r + ic) * nb];
+            const double v = ld32(Lb, at(k < w ? k : wl1, ic));
             row[k] = (k <= i && i < w && k < w) ? v : 0.0;
         }
 #pragma unroll
@@ -708,10 +717,10 @@ __global__ __launch_bounds__(kWG) void k_fac_diag(DevArgs a, const Work *__restr
             double di = 0.0;
 #pragma unroll
             for (int k = 0; k < W; k++) {
-                if (k < i) P[(int64_t(k) * r + i) * nb] = row[k];
+                if (k < i) st32(Lb, at(k, i), row[k]);
                 if (k == i) di = row[k];
             }
-            a.dval[T.dbase + bl + int64_t(f + i) * nb] = di;
+            st32(a.dval + T.dbase, uint32_t(f + i) * nbu + blu, di);
         }
     });
 }
@@ -726,36 +735,39 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
+    const uint32_t nb = uint32_t(W.nb), bl = uint32_t(W.bl);
     const int s = cs(T.task_s)[W.k], p = cs(T.task_p)[W.k];
     const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
-    double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
-    double *Dv = a.dval + T.dbase + W.bl + int64_t(f) * nb;
+    double *Lb = a.lpan + T.lbase;
+    double *Db = a.dval + T.dbase;
+    const uint32_t po = uint32_t(cs(T.panel_off)[s]);
+    // element (row, col) of the panel for this lane's block
+    auto at = [&](int col, int row) { return (po + uint32_t(col) * uint32_t(r) + uint32_t(row)) * nb + bl; };
     by_width(w, [&](auto Wc) {
         constexpr int W_ = decltype(Wc)::value;
         const int wl1 = w - 1;
         double u[W_];
 #pragma unroll
-        for (int j = 0; j < W_; j++) u[j] = P[(int64_t(j < w ? j : wl1) * r + p) * nb];
+        for (int j = 0; j < W_; j++) u[j] = ld32(Lb, at(j < w ? j : wl1, p));
         // u_k -= L(k,j) u_j for j < k, row by row in increasing j
 #pragma unroll
         for (int k = 1; k < W_; k++) {
             const int kc = k < w ? k : wl1;
 #pragma unroll
             for (int j = 0; j < k; j++) {
-                const double l = P[(int64_t(j < w ? j : wl1) * r + kc) * nb];
+                const double l = ld32(Lb, at(j < w ? j : wl1, kc));
                 u[k] -= (k < w ? l : 0.0) * u[j];
             }
         }
         if (W.on) {
-            double *U = a.upan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
+            double *Ub = a.upan + T.lbase;
 #pragma unroll
             for (int j = 0; j < W_; j++) {
-                const double d = Dv[int64_t(j < w ? j : wl1) * nb];
+                const double d = ld32(Db, uint32_t(f + (j < w ? j : wl1)) * nb + bl);
                 if (j < w) {
-                    P[(int64_t(j) * r + p) * nb] = u[j] / d;
-                    U[(int64_t(j) * r + p) * nb] = u[j];
+                    st32(Lb, at(j, p), u[j] / d);
+                    st32(Ub, at(j, p), u[j]);
                 }
             }
         }
@@ -1540,31 +1552,34 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, cons
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
     const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
+    const uint32_t nb = uint32_t(W.nb), bl = uint32_t(W.bl);
     const int s = W.k;
     const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
     const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
-    const double *P = a.lpan + T.lbase + W.bl + int64_t(cs(T.panel_off)[s]) * nb;
-    double *yb = y + T.dbase + W.bl + int64_t(f) * nb;
+    const double *Lb = a.lpan + T.lbase;
+    double *y0 = y + T.dbase;
+    const uint32_t po = uint32_t(cs(T.panel_off)[s]);
+    auto at = [&](int col, int row) { return (po + uint32_t(col) * uint32_t(r) + uint32_t(row)) * nb + bl; };
+    auto yi = [&](int j) { return uint32_t(f + j) * nb + bl; };
     by_width(w, [&](auto Wc) {
         constexpr int W_ = decltype(Wc)::value;
         const int wl1 = w - 1;
         double x[W_];
 #pragma unroll
-        for (int j = 0; j < W_; j++) x[j] = yb[int64_t(j < w ? j : wl1) * nb];
+        for (int j = 0; j < W_; j++) x[j] = ld32(y0, yi(j < w ? j : wl1));
 #pragma unroll
         for (int j = W_ - 1; j > 0; j--) {
             const int jc = j < w ? j : wl1;
 #pragma unroll
             for (int k = 0; k < j; k++) {
-                const double l = P[(int64_t(k < w ? k : wl1) * r + jc) * nb];
+                const double l = ld32(Lb, at(k < w ? k : wl1, jc));
                 x[k] -= (j < w ? l : 0.0) * x[j];
             }
         }
         if (W.on) {
 #pragma unroll
             for (int j = 0; j < W_ - 1; j++)
-                if (j < w - 1) yb[int64_t(j) * nb] = x[j];
+                if (j < w - 1) st32(y0, yi(j), x[j]);
         }
     });
 }
