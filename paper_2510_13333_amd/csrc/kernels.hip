@@ -310,7 +310,7 @@ struct AsmCtx {
 __device__ inline void put(const AsmCtx &c, int32_t slot, double v) {
     if (slot < 0 || !c.on) return;
     if (slot & kBorderFlag) c.a->kval[c.kbb + (slot & ~kBorderFlag)] = v;
-    else c.a->kval[c.kb + int64_t(slot) * c.nb] = v;
+    else c.a->kval[c.kb + int64_t(uint32_t(slot) * uint32_t(c.nb))] = v;   // a template's K fits 2^29
 }
 
 __device__ inline int64_t zi(int64_t bstart, const BlockDev &B, int n, int32_t x) {
@@ -325,7 +325,10 @@ __device__ inline int64_t zi(int64_t bstart, const BlockDev &B, int n, int32_t x
 struct StateIx {
     int64_t base, nb, bord;
     int n;
-    __device__ int64_t operator()(int32_t x) const { return x < n ? base + int64_t(x) * nb : bord + (x - n); }
+    // x * nb in 32 bits: a template's pivots fit 2^29 (checked at analysis)
+    __device__ int64_t operator()(int32_t x) const {
+        return x < n ? base + int64_t(uint32_t(x) * uint32_t(nb)) : bord + (x - n);
+    }
 };
 
 __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__restrict__ z,

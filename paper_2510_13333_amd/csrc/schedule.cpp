@@ -226,7 +226,8 @@ int build_schedule(Handle &h) {
         const int64_t nb = int64_t(t.blocks.size());
         // kernels address a template's panels, pivots and vectors with 32-bit
         // byte offsets from the template's base
-        if (int64_t(t.n) * nb >= (int64_t(1) << 29) || int64_t(t.panel_off.back()) * nb >= (int64_t(1) << 29))
+        if (int64_t(t.n) * nb >= (int64_t(1) << 29) || int64_t(t.panel_off.back()) * nb >= (int64_t(1) << 29) ||
+            int64_t(t.colptr[t.n]) * nb >= (int64_t(1) << 29))
             return NCL_ERR_ARG;
         h.t_kbase[ti] = h.kint;
         h.t_lbase[ti] = h.lint;
