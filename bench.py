@@ -148,16 +148,18 @@ def run_single(args):
     t0 = time.perf_counter()
     k = KKT(net)
     t_analyze = time.perf_counter() - t0
-    k.bind(nrhs_max=1)
+    nrhs = args.nrhs
+    k.bind(nrhs_max=nrhs)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     nst = max(1, min(args.states, args.steps + args.warmup))
     z0, s0 = G.draw_point(net, cfg)
     states = []
     for it in range(nst):
         z, s = G.draw_trajectory_point(net, cfg, it, z0, s0)
-        b = G.draw_rhs(k.N, 1, cfg, iteration=it)[0]
+        b = G.draw_rhs(k.N, nrhs, cfg, iteration=it)
+        b = b[0] if nrhs == 1 else b
         states.append((dev(z), dev(s), dev(b)))
-    x = torch.empty(k.N, dtype=torch.float64, device="cuda")
+    x = torch.empty((k.N,) if nrhs == 1 else (nrhs, k.N), dtype=torch.float64, device="cuda")
     print(f"[bench] config {cfg}: N={k.N} nnzK={k.nnzK} nnzL={k.nnzL} supernodes={k.nsuper} "
           f"analyze={t_analyze:.3f}s states={nst}", file=sys.stderr, flush=True)
 
@@ -248,7 +250,7 @@ def run_single(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[cfg], "step": "assemble+factor+solve, nrhs=1", "N": k.N,
+        "config": {"workload": WORKLOADS[cfg], "step": f"assemble+factor+solve, nrhs={nrhs}", "N": k.N,
                    "nnzK_lower": k.nnzK, "nnzL": k.nnzL, "blocks": net.nblk, "border": nbd},
         "roofline": roof,
         "phases_ms": {"assemble": t_asm * 1e3, "factor_blocks": t_fblk * 1e3, "factor_border": t_fbrd * 1e3,
@@ -445,6 +447,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3, choices=sorted(WORKLOADS))
     ap.add_argument("--states", type=int, default=50, help="distinct trajectory states, cycled")
+    ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per solve (single-network workloads)")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed on the host")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
