@@ -1398,21 +1398,36 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
     double *Ll = c + a.max_nbd;
     if (kRes) {
         const int npk = nbd * (nbd + 1) / 2;
+#pragma unroll 8
         for (int e = tid; e < npk; e += kBorderThreads) Ll[e] = Lg[e];
     }
     const double *Lb = kRes ? Ll : Lg;
-    for (int i = wv; i < nbd; i += kBorderThreads / 64) {
-        const double *ci = cpart + I.cp0 + int64_t(i) * nblk;
-        double s0 = 0.0, s1 = 0.0;
-        int k = lane;
-        for (; k + 64 < nblk; k += 128) {
-            s0 += ci[k];
-            s1 += ci[k + 64];
+    // block sums of the border right-hand side, kRB rows per wavefront at a
+    // time so that their loads are in flight together (each row's sum is
+    // lane-strided in two partials, then a fixed shuffle tree)
+    constexpr int kRB = 4, kNW = kBorderThreads / 64;
+    for (int i0 = wv; i0 < nbd; i0 += kRB * kNW) {
+        double s0[kRB], s1[kRB];
+#pragma unroll
+        for (int q = 0; q < kRB; q++) s0[q] = s1[q] = 0.0;
+        for (int k = lane; k < nblk; k += 128) {
+#pragma unroll
+            for (int q = 0; q < kRB; q++) {
+                const int i = i0 + q * kNW;
+                if (i < nbd) {
+                    const double *ci = cpart + I.cp0 + int64_t(i) * nblk;
+                    s0[q] += ci[k];
+                    if (k + 64 < nblk) s1[q] += ci[k + 64];
+                }
+            }
         }
-        if (k < nblk) s0 += ci[k];
-        double v = s0 + s1;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) c[i] = b[I.bstart + i] - v;
+#pragma unroll
+        for (int q = 0; q < kRB; q++) {
+            const int i = i0 + q * kNW;
+            double v = s0[q] + s1[q];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0 && i < nbd) c[i] = b[I.bstart + i] - v;
+        }
     }
     __syncthreads();
     // forward: L y = c
