@@ -319,6 +319,8 @@ enum {
     NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
     NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */
     NCL_K_INTERLEAVE,       /* k_interleave: the state transposed to the blocks' interleaved order (assembly) */
+    NCL_K_BORDER_PANEL,     /* k_border_panel: borders over 216 rows, diagonal block and rows of one column block */
+    NCL_K_BORDER_UPDATE,    /* k_border_update: borders over 216 rows, trailing update by one column block */
     NCL_K_COUNT
 };
 

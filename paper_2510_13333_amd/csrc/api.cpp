@@ -256,6 +256,14 @@ ncl::DevArgs dev_args(const Handle &h) {
     return a;
 }
 
+// The largest border of an instance too large for the register factor (0: none).
+int large_border(const Handle &h) {
+    int m = 0;
+    for (const ncl::Inst &I : h.inst)
+        if (I.nbd > ncl::kBorderRegMax && I.nbd > m) m = I.nbd;
+    return m;
+}
+
 // Launches and algorithmic bytes per step of every kernel kind: each
 // distinct element a launch reads or writes counts once per launch.
 void kernel_model(Handle &h) {
@@ -377,7 +385,21 @@ void kernel_model(Handle &h) {
         L[NCL_K_BORDER_SCHUR] = L[NCL_K_BORDER_SUM] = L[NCL_K_BORDER_FACTOR] = 1;
         L[NCL_K_SOL_BPART] = L[NCL_K_SOL_BORDER] = 1;
         B[NCL_K_BORDER_SUM] = D * (h.sp_tot + h.nbb_tot + h.npk_tot);
-        B[NCL_K_BORDER_FACTOR] = D * (2 * h.npk_tot + h.nbd_tot);
+        B[NCL_K_BORDER_FACTOR] = 0;
+        const int lb = large_border(h);
+        if (lb) L[NCL_K_BORDER_PANEL] = L[NCL_K_BORDER_UPDATE] = (lb + ncl::kBorderBlock - 1) / ncl::kBorderBlock;
+        for (const ncl::Inst &I : h.inst) {
+            const int64_t n = I.nbd;
+            if (n <= ncl::kBorderRegMax) {
+                B[NCL_K_BORDER_FACTOR] += D * (n * (n + 1) + n);     // the packed matrix read and written, pivots
+                continue;
+            }
+            for (int64_t b0 = 0; b0 < n; b0 += ncl::kBorderBlock) {
+                const int64_t bs = std::min<int64_t>(ncl::kBorderBlock, n - b0), m = n - b0 - bs;
+                B[NCL_K_BORDER_PANEL] += D * (bs * (bs + 1) + 2 * m * bs + bs);
+                B[NCL_K_BORDER_UPDATE] += D * (m * (m + 1) + m * bs + bs);
+            }
+        }
         B[NCL_K_SOL_BORDER] = D * (h.cp_tot + h.npk_tot + 4 * h.nbd_tot);
     } else {
         B[NCL_K_BORDER_SCHUR] = B[NCL_K_SOL_BPART] = 0;
@@ -390,6 +412,8 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
         case NCL_K_ASSEMBLE: return a.asm_threads + a.gp_tot > 0;
         case NCL_K_VALUES: return a.kint + a.nbb_tot > 0;
         case NCL_K_BORDER_SUM: return a.npk_tot > 0;
+        case NCL_K_BORDER_PANEL:
+        case NCL_K_BORDER_UPDATE: return a.max_nbd > ncl::kBorderRegMax;
         case NCL_K_BORDER_FACTOR:
         case NCL_K_SOL_BORDER: return a.max_nbd > 0;
         case NCL_K_STATUS_INIT:
@@ -844,7 +868,16 @@ int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const ncl::DevArgs a = dev_args(h);
     const ncl::LaunchArgs none;
-    for (int kind : {NCL_K_BORDER_SUM, NCL_K_BORDER_FACTOR, NCL_K_STATUS_INIT, NCL_K_STATUS})
+    for (int kind : {NCL_K_BORDER_SUM, NCL_K_BORDER_FACTOR})
+        if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
+    // borders too large for the register factor: column blocks in turn
+    for (int b0 = 0; b0 < large_border(h); b0 += ncl::kBorderBlock) {
+        ncl::LaunchArgs l;
+        l.b0 = b0;
+        if (run(h, NCL_K_BORDER_PANEL, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+        if (run(h, NCL_K_BORDER_UPDATE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
         if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
     h.factored = true;
     return NCL_OK;
@@ -1033,7 +1066,7 @@ const char *ncl_kernel_name(int kind) {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
         "k_sol_bpart", "k_sol_border", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
-        "k_residual", "k_max_step", "k_interleave"};
+        "k_residual", "k_max_step", "k_interleave", "k_border_panel", "k_border_update"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }
 

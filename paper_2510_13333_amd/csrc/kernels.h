@@ -28,9 +28,16 @@ struct DevArgs {
 };
 
 // Arguments of one launch (only those the kernel kind uses are read).
+// Dense border factor: borders of up to kBorderRegMax rows are factored in
+// registers by one workgroup; larger ones by column blocks of kBorderBlock,
+// a panel launch and a trailing-update launch per block.
+constexpr int kBorderBlock = 32;
+constexpr int kBorderRegMax = 216;
+
 struct LaunchArgs {
     const Work *wl = nullptr;   // work list and its length
     int nw = 0;
+    int b0 = 0;                 // border column block (panel and update launches)
     const double *z = nullptr, *sig = nullptr;   // assembly state
     double rho = 0.0;
     uint32_t flags = 0;                          // NCL_NO_SHIFT
@@ -48,6 +55,5 @@ struct LaunchArgs {
 
 // Launch one kernel of the given kind (NCL_K_* of ncl_kkt.h) on stream st.
 hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st);
-size_t border_lds_bytes(int nbd);   // dynamic LDS of the dense border factor (largest border)
 
 }  // namespace ncl

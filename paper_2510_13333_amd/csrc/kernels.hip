@@ -876,131 +876,18 @@ __global__ __launch_bounds__(kWG) void k_border_sum(DevArgs a) {
     }
 }
 
-// Dense LDL^T of the packed border matrix S (lower triangle packed by rows)
-// of one instance per workgroup, right-looking by blocks of kBB columns, in
-// place:
-//   1. wavefront 0 factors the diagonal block in registers (lane = row) with
-//      cross-lane shuffles;
-//   2. one thread per row below the block solves for that row's kBB entries
-//      of L against the block;
-//   3. the trailing lower triangle takes S_ik -= sum_j L_ij d_j L_kj, in 4x4
-//      register tiles that read the block column of L from LDS.
-// S ends with L strictly below the diagonal and 1 on it; D goes to dval.
-// The trailing matrix stays in global memory (L2-resident); the block
-// column of L is staged in LDS.  Taken for borders too large for the
-// register-tiled factor below.
+// Dense LDL^T of the packed border matrix S (lower triangle packed by rows),
+// in place: S ends with L strictly below the diagonal and 1 on it; D goes
+// to dval.  Borders of up to kBorderRegMax rows: k_border_factor below, the
+// whole matrix in registers.  Larger ones: right-looking by column blocks
+// of kBB, the trailing matrix in global memory (L2-resident), two launches
+// a block:
+//   k_border_panel: wavefront 0 factors the diagonal block in registers
+//     (lane = row, columns published through LDS), then one thread per row
+//     below the block solves that row's kBB entries of L against it;
+//   k_border_update: the trailing lower triangle takes S_ik -= sum_j L_ij
+//     d_j L_kj, spread over one workgroup per 32x32 tile.
 constexpr int kBFThreads = 512;    // 8 wavefronts: up to 256 registers each, no spills
-
-__device__ inline void border_factor_blocked(const DevArgs &a, const InstDev &I, double *lds) {
-    double *Ld = lds;                  // [kBB][kPS] L of the diagonal block
-    double *dd = Ld + kBB * kPS;       // [kBB] its pivots
-    const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
-    double *Sg = a.sbb + I.sbb0;
-    double *S = Sg;                    // the packed matrix being factored
-    double *Pn = dd + kBB;             // [nbd - kBB][kPS] L of the rows below the block
-    double *Db = a.dval + a.dint + I.bd0;
-    for (int b0 = 0; b0 < nbd; b0 += kBB) {
-        const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
-        const int r0 = b0 + bs, m = nbd - r0;
-        if (tid < 64) {
-            // diagonal block: lane i < bs holds row i; column j is published
-            // through Ld's column j (its final L values are written there)
-            const int i = lane;
-            const bool on = i < bs;
-            double row[kBB];
-#pragma unroll
-            for (int k = 0; k < kBB; k++) row[k] = (on && k <= i) ? S[pk(b0 + i, b0 + k)] : 0.0;
-#pragma unroll
-            for (int j = 0; j < kBB; j++) {
-                if (j < bs) {
-                    if (on && i >= j) Ld[i * kPS + j] = row[j];
-                    __builtin_amdgcn_wave_barrier();
-                    const double dj = Ld[j * kPS + j];
-                    const double lij = i > j ? row[j] / dj : 0.0;
-#pragma unroll
-                    for (int k = j + 1; k < kBB; k++) {
-                        const double ak = Ld[k * kPS + j];
-                        const double upd = row[k] - lij * ak;
-                        row[k] = (i >= k && k < bs) ? upd : row[k];     // select, no divergent branch
-                    }
-                    row[j] = i > j ? lij : row[j];
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
-            if (on) {
-#pragma unroll
-                for (int k = 0; k < kBB; k++) {
-                    if (k < i) {
-                        Ld[i * kPS + k] = row[k];
-                        S[pk(b0 + i, b0 + k)] = row[k];
-                    }
-                    if (k == i) {
-                        dd[i] = row[k];
-                        Db[b0 + i] = row[k];
-                        S[pk(b0 + i, b0 + i)] = 1.0;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // rows below the block: L_ij = (S_ij - sum_{k<j} L_ik d_k L_jk) / d_j
-        for (int t = tid; t < m; t += kBFThreads) {
-            double *si = S + pk(r0 + t, b0);
-            double x[kBB];
-#pragma unroll
-            for (int j = 0; j < kBB; j++) {
-                if (j < bs) {
-                    double v = si[j];
-#pragma unroll
-                    for (int k = 0; k < kBB; k++)
-                        if (k < j) v -= x[k] * dd[k] * Ld[j * kPS + k];
-                    x[j] = v / dd[j];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kBB; j++)
-                if (j < bs) {
-                    si[j] = x[j];
-                    Pn[t * kPS + j] = x[j];
-                }
-        }
-        __syncthreads();
-        const int mt = (m + 3) >> 2;
-        const int ntl = mt * (mt + 1) / 2;
-        for (int q = tid; q < ntl; q += kBFThreads) {
-            int I, K;
-            unpack(q, I, K);
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) acc[u][v] = 0.0;
-            for (int j = 0; j < bs; j++) {
-                const double dj = dd[j];
-                double pi[4], pc[4];
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int ii = 4 * I + u, kk = 4 * K + u;
-                    const double *ri = Pn + ii * kPS, *rk = Pn + kk * kPS;
-                    pi[u] = ii < m ? ri[j] : 0.0;
-                    pc[u] = kk < m ? rk[j] * dj : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; u++)
-#pragma unroll
-                    for (int v = 0; v < 4; v++) acc[u][v] += pi[u] * pc[v];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int i = r0 + 4 * I + u, k = r0 + 4 * K + v;
-                    if (i < nbd && k <= i) S[pk(i, k)] -= acc[u][v];
-                }
-        }
-        __syncthreads();
-    }
-}
 
 // Dense LDL^T of a border matrix held in registers.  The lower triangle is
 // cut into 4x4 tiles numbered column by column; thread t holds tiles t,
@@ -1013,6 +900,7 @@ __device__ inline void border_factor_blocked(const DevArgs &a, const InstDev &I,
 // Two barriers a panel and no copy of the matrix in LDS.  Rows padded past
 // nbd carry pivot 1 and no coupling; only real entries are written out.
 constexpr int kBFRegMaxNt = 54;    // tile rows a thread's 3 tiles cover: 54 * 55 / 2 <= 3 * kBFThreads (nbd <= 216)
+static_assert(4 * kBFRegMaxNt == kBorderRegMax && kBB == kBorderBlock, "border factor split");
 
 template <int T>
 __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, double *piv, double *pan) {
@@ -1151,8 +1039,121 @@ __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
     extern __shared__ __align__(16) double lds[];
     const InstDev &I = a.insts[blockIdx.x];
     const int mt = (I.nbd + 3) >> 2;
-    if (mt <= kBFRegMaxNt) border_factor_reg<T>(a, I, piv, lds);
-    else border_factor_blocked(a, I, lds);
+    if (mt <= kBFRegMaxNt) border_factor_reg<T>(a, I, piv, lds);   // larger: k_border_panel / k_border_update
+}
+
+__global__ __launch_bounds__(kBFThreads) void k_border_panel(DevArgs a, int b0) {
+    extern __shared__ double lds[];
+    double *Ld = lds;                  // [kBB][kPS] L of the diagonal block
+    double *dd = Ld + kBB * kPS;       // [kBB] its pivots
+    const InstDev &I = a.insts[blockIdx.x];
+    const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
+    if (nbd <= kBorderRegMax || b0 >= nbd) return;
+    double *S = a.sbb + I.sbb0;
+    double *Db = a.dval + a.dint + I.bd0;
+    const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
+    const int r0 = b0 + bs, m = nbd - r0;
+    if (tid < 64) {
+        // diagonal block: lane i < bs holds row i; column j is published
+        // through Ld's column j (its final L values are written there)
+        const int i = lane;
+        const bool on = i < bs;
+        double row[kBB];
+#pragma unroll
+        for (int k = 0; k < kBB; k++) row[k] = (on && k <= i) ? S[pk(b0 + i, b0 + k)] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kBB; j++) {
+            if (j < bs) {
+                if (on && i >= j) Ld[i * kPS + j] = row[j];
+                __builtin_amdgcn_wave_barrier();
+                const double dj = Ld[j * kPS + j];
+                const double lij = i > j ? row[j] / dj : 0.0;
+#pragma unroll
+                for (int k = j + 1; k < kBB; k++) {
+                    const double ak = Ld[k * kPS + j];
+                    const double upd = row[k] - lij * ak;
+                    row[k] = (i >= k && k < bs) ? upd : row[k];     // select, no divergent branch
+                }
+                row[j] = i > j ? lij : row[j];
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (on) {
+#pragma unroll
+            for (int k = 0; k < kBB; k++) {
+                if (k < i) {
+                    Ld[i * kPS + k] = row[k];
+                    S[pk(b0 + i, b0 + k)] = row[k];
+                }
+                if (k == i) {
+                    dd[i] = row[k];
+                    Db[b0 + i] = row[k];
+                    S[pk(b0 + i, b0 + i)] = 1.0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // rows below the block: L_ij = (S_ij - sum_{k<j} L_ik d_k L_jk) / d_j
+    for (int t = tid; t < m; t += kBFThreads) {
+        double *si = S + pk(r0 + t, b0);
+        double x[kBB];
+#pragma unroll
+        for (int j = 0; j < kBB; j++) {
+            if (j < bs) {
+                double v = si[j];
+#pragma unroll
+                for (int k = 0; k < kBB; k++)
+                    if (k < j) v -= x[k] * dd[k] * Ld[j * kPS + k];
+                x[j] = v / dd[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kBB; j++)
+            if (j < bs) si[j] = x[j];
+    }
+}
+
+// Trailing update of a large border by column block b0: S_ik -= sum_j L_ij
+// d_j L_kj over the block's columns, one workgroup per 32x32 tile of the
+// trailing lower triangle (the tile's rows of the block column staged in
+// LDS, L_kj d_j formed there), each thread 2x2 entries, j ascending.
+__global__ __launch_bounds__(256) void k_border_update(DevArgs a, int b0) {
+    __shared__ double Li[kBB][kPS], Lk[kBB][kPS];
+    const InstDev &I = a.insts[blockIdx.y];
+    const int nbd = I.nbd;
+    if (nbd <= kBorderRegMax || b0 >= nbd) return;
+    const int bs = nbd - b0 < kBB ? nbd - b0 : kBB, r0 = b0 + bs, m = nbd - r0;
+    const int nsb = (m + kBB - 1) / kBB;
+    if (int(blockIdx.x) >= nsb * (nsb + 1) / 2) return;
+    int SI, SK;
+    unpack(blockIdx.x, SI, SK);
+    double *S = a.sbb + I.sbb0;
+    const double *Db = a.dval + a.dint + I.bd0;
+    const int i0 = r0 + kBB * SI, k0 = r0 + kBB * SK;
+    for (int t = threadIdx.x; t < kBB * kBB; t += 256) {
+        const int rr = t / kBB, j = t % kBB;
+        const int i = i0 + rr, k = k0 + rr;
+        Li[rr][j] = (i < nbd && j < bs) ? S[pk(i, b0 + j)] : 0.0;
+        Lk[rr][j] = (k < nbd && j < bs) ? S[pk(k, b0 + j)] * Db[b0 + j] : 0.0;
+    }
+    __syncthreads();
+    const int t = threadIdx.x, ii = 2 * (t >> 4), kk = 2 * (t & 15);
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int j = 0; j < bs; j++) {
+        const double p0 = Li[ii][j], p1 = Li[ii + 1][j], c0 = Lk[kk][j], c1 = Lk[kk + 1][j];
+        acc[0][0] += p0 * c0;
+        acc[0][1] += p0 * c1;
+        acc[1][0] += p1 * c0;
+        acc[1][1] += p1 * c1;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int v = 0; v < 2; v++) {
+            const int i = i0 + ii + u, k = k0 + kk + v;
+            if (i < nbd && k <= i) S[pk(i, k)] -= acc[u][v];
+        }
 }
 
 // Pivot signs and magnitudes of the whole factorisation (integer atomics only).
@@ -1805,10 +1806,6 @@ constexpr int kSplitTasks = 2048;
 static inline unsigned waves_grid(int nw) { return unsigned((nw + (kWG / 64) - 1) / (kWG / 64)); }
 static inline unsigned elems_grid(int64_t n) { return unsigned((n + 255) / 256); }
 
-size_t border_lds_bytes(int nbd) {
-    return size_t(kBB * kPS + kBB + (nbd > kBB ? nbd - kBB : 0) * kPS) * sizeof(double);
-}
-
 // Dynamic LDS a workgroup may use on the current device (queried once).
 static int max_lds_per_workgroup() {
     static int bytes = -1;
@@ -1862,11 +1859,7 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                 // blocked path inside the same kernel)
                 const int nreg = a.max_nbd < 4 * kBFRegMaxNt ? a.max_nbd : 4 * kBFRegMaxNt;
                 const int mt = (nreg + 3) / 4, tpt = (mt * (mt + 1) / 2 + kBFThreads - 1) / kBFThreads;
-                size_t lb = size_t(8) * 4 * mt * sizeof(double);
-                if (a.max_nbd > 4 * kBFRegMaxNt) {
-                    const size_t bb = border_lds_bytes(a.max_nbd);
-                    lb = bb > lb ? bb : lb;
-                }
+                const size_t lb = size_t(8) * 4 * mt * sizeof(double);
                 const void *fn = tpt <= 1 ? reinterpret_cast<const void *>(&k_border_factor<1>)
                                : tpt == 2 ? reinterpret_cast<const void *>(&k_border_factor<2>)
                                           : reinterpret_cast<const void *>(&k_border_factor<3>);
@@ -1881,6 +1874,20 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                 }
             }
             break;
+        case NCL_K_BORDER_PANEL:
+            if (a.max_nbd > kBorderRegMax)
+                hipLaunchKernelGGL(k_border_panel, dim3(a.ninst), dim3(kBFThreads), size_t(kBB * kPS + kBB) * sizeof(double),
+                                   st, a, l.b0);
+            break;
+        case NCL_K_BORDER_UPDATE: {
+            const int m = a.max_nbd - l.b0 - kBB;
+            if (a.max_nbd > kBorderRegMax && m > 0) {
+                const int nsb = (m + kBB - 1) / kBB;
+                hipLaunchKernelGGL(k_border_update, dim3(unsigned(nsb * (nsb + 1) / 2), unsigned(a.ninst)), dim3(256), 0,
+                                   st, a, l.b0);
+            }
+            break;
+        }
         case NCL_K_STATUS_INIT:
             hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, a);
             break;
