@@ -217,7 +217,7 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.cp_tot));
     p.zint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
     p.sint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
-    p.stat = L.take(nullptr, sizeof(int64_t) * 8);
+    p.stat = L.take(nullptr, sizeof(int64_t) * 6 * ncl::kStatStride);
     p.total = L.off;
     return p;
 }
@@ -892,9 +892,10 @@ int ncl_kkt_info(ncl_kkt *k, ncl_kkt_report *rep, void *stream) {
     if (!k || !rep) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.factored) return NCL_ERR_STATE;
-    int64_t s[6];
+    int64_t sw[6 * ncl::kStatStride], s[6];
     if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return NCL_ERR_HIP;
-    if (hipMemcpy(s, h.d.stat, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return NCL_ERR_HIP;
+    if (hipMemcpy(sw, h.d.stat, sizeof(sw), hipMemcpyDeviceToHost) != hipSuccess) return NCL_ERR_HIP;
+    for (int q = 0; q < 6; q++) s[q] = sw[q * ncl::kStatStride];
     rep->npos = s[0];
     rep->nneg = s[1];
     rep->nzero = s[2];

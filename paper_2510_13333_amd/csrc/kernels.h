@@ -32,6 +32,9 @@ struct DevArgs {
 // registers by one workgroup; larger ones by column blocks of kBorderBlock,
 // a panel launch and a trailing-update launch per block.
 constexpr int kBorderBlock = 32;
+// status words: 6 counters, each on a cache line of its own so that the
+// workgroups' atomics on different counters do not queue on one line
+constexpr int kStatStride = 16;
 constexpr int kBorderRegMax = 216;
 
 struct LaunchArgs {

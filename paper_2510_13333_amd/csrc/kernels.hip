@@ -1159,12 +1159,12 @@ __global__ __launch_bounds__(256) void k_border_update(DevArgs a, int b0) {
 // Pivot signs and magnitudes of the whole factorisation (integer atomics only).
 __global__ __launch_bounds__(64) void k_status_init(DevArgs a) {
     if (threadIdx.x == 0) {
-        a.stat[0] = 0;
-        a.stat[1] = 0;
-        a.stat[2] = 0;
-        a.stat[3] = INT64_MAX;
-        a.stat[4] = INT64_MAX;
-        a.stat[5] = 0;
+        a.stat[0 * kStatStride] = 0;
+        a.stat[1 * kStatStride] = 0;
+        a.stat[2 * kStatStride] = 0;
+        a.stat[3 * kStatStride] = INT64_MAX;
+        a.stat[4 * kStatStride] = INT64_MAX;
+        a.stat[5 * kStatStride] = 0;
     }
 }
 
@@ -1188,36 +1188,52 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
     const int lane = lane_id();
     int ti = (c0 < a.dint) ? find_tmpl(a, c0, &TemplDev::dbase) : 0;
     const int64_t tend0 = ti + 1 < a.ntmpl ? a.tmpls[ti + 1].dbase : a.dint;
-    for (int k = 0; k < kStatusChunk / 64; k++) {
+    // every pivot and sign flag of the chunk is loaded before any is used
+    // (indices past the end re-read the last pivot and are not counted)
+    constexpr int kQ = kStatusChunk / 64;
+    double dv[kQ];
+    uint8_t pf[kQ];
+    int tq[kQ];
+#pragma unroll
+    for (int k = 0; k < kQ; k++) {
         const int64_t idx = c0 + k * 64 + lane;
-        if (idx >= total) break;
-        double d;
-        bool primal;
-        int code;
-        int64_t col = 0;
-        if (idx < a.dint) {
-            if (idx >= tend0)
-                while (ti + 1 < a.ntmpl && a.tmpls[ti + 1].dbase <= idx) ti++;
+        const int64_t ic = idx < total ? idx : total - 1;
+        const uint8_t *pp;
+        if (ic < a.dint) {
+            if (ic >= tend0)
+                while (ti + 1 < a.ntmpl && a.tmpls[ti + 1].dbase <= ic) ti++;
             const TemplDev &T = a.tmpls[ti];
-            const uint32_t off = uint32_t(idx - T.dbase), nb = uint32_t(T.nblk);
-            const uint32_t j = off / nb;
-            d = a.dval[idx];
-            primal = T.col_primal[j] != 0;
-            code = pivot_code(d, primal);
-            if (code) col = a.blks[T.blocks[off - j * nb]].col0 + j;
+            pp = T.col_primal + uint32_t(ic - T.dbase) / uint32_t(T.nblk);
         } else {
-            const int64_t j = idx - a.dint;
-            const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
-            d = a.dval[idx];
-            primal = a.bprim[j] != 0;
-            code = pivot_code(d, primal);
-            col = I.bstart + (j - I.bd0);
+            pp = a.bprim + (ic - a.dint);
         }
+        tq[k] = ti;
+        dv[k] = a.dval[ic];
+        pf[k] = *pp;
+    }
+#pragma unroll
+    for (int k = 0; k < kQ; k++) {
+        const int64_t idx = c0 + k * 64 + lane;
+        if (idx >= total) continue;
+        const double d = dv[k];
+        const int code = pivot_code(d, pf[k] != 0);
         if (code == 0 || code == 1) {
             if (d > 0) np++;
             else nn++;
         } else if (code == 2) nz++;
-        if (code && col * 8 + code < bad) bad = col * 8 + code;
+        if (code) {
+            int64_t col;
+            if (idx < a.dint) {
+                const TemplDev &T = a.tmpls[tq[k]];
+                const uint32_t off = uint32_t(idx - T.dbase), nb = uint32_t(T.nblk), j = off / nb;
+                col = a.blks[T.blocks[off - j * nb]].col0 + j;
+            } else {
+                const int64_t j = idx - a.dint;
+                const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
+                col = I.bstart + (j - I.bd0);
+            }
+            if (col * 8 + code < bad) bad = col * 8 + code;
+        }
         const double ad = fabs(d);
         if (isfinite(ad)) {
             const int64_t bits = __double_as_longlong(ad);
@@ -1250,12 +1266,14 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
             red[5][0] = red[5][q] > red[5][0] ? red[5][q] : red[5][0];
         }
         unsigned long long *u = reinterpret_cast<unsigned long long *>(a.stat);
-        if (red[0][0]) atomicAdd(u + 0, (unsigned long long)red[0][0]);
-        if (red[1][0]) atomicAdd(u + 1, (unsigned long long)red[1][0]);
-        if (red[2][0]) atomicAdd(u + 2, (unsigned long long)red[2][0]);
-        if (red[3][0] != INT64_MAX) atomicMin(reinterpret_cast<long long *>(a.stat + 3), (long long)red[3][0]);
-        if (red[4][0] != INT64_MAX) atomicMin(reinterpret_cast<long long *>(a.stat + 4), (long long)red[4][0]);
-        if (red[5][0]) atomicMax(reinterpret_cast<long long *>(a.stat + 5), (long long)red[5][0]);
+        if (red[0][0]) atomicAdd(u + 0 * kStatStride, (unsigned long long)red[0][0]);
+        if (red[1][0]) atomicAdd(u + 1 * kStatStride, (unsigned long long)red[1][0]);
+        if (red[2][0]) atomicAdd(u + 2 * kStatStride, (unsigned long long)red[2][0]);
+        if (red[3][0] != INT64_MAX)
+            atomicMin(reinterpret_cast<long long *>(a.stat + 3 * kStatStride), (long long)red[3][0]);
+        if (red[4][0] != INT64_MAX)
+            atomicMin(reinterpret_cast<long long *>(a.stat + 4 * kStatStride), (long long)red[4][0]);
+        if (red[5][0]) atomicMax(reinterpret_cast<long long *>(a.stat + 5 * kStatStride), (long long)red[5][0]);
     }
 }
 
