@@ -1059,8 +1059,14 @@ __global__ __launch_bounds__(kBFThreads) void k_border_panel(DevArgs a, int b0) 
         const int i = lane;
         const bool on = i < bs;
         double row[kBB];
+        // every load issued up front: clamped to a valid entry of the block,
+        // the unused ones masked afterwards
+        const int ic = on ? i : bs - 1;
 #pragma unroll
-        for (int k = 0; k < kBB; k++) row[k] = (on && k <= i) ? S[pk(b0 + i, b0 + k)] : 0.0;
+        for (int k = 0; k < kBB; k++) {
+            const double v = S[pk(b0 + ic, b0 + (k <= ic ? k : ic))];
+            row[k] = (on && k <= i) ? v : 0.0;
+        }
 #pragma unroll
         for (int j = 0; j < kBB; j++) {
             if (j < bs) {
