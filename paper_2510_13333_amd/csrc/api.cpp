@@ -192,6 +192,7 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(col_primal(t)));
         o.push_back(L.vec(t.bus_gen));
         o.push_back(L.vec(t.lkind));
+        o.push_back(L.vec(t.iperm));
     }
     p.tdev = L.take(nullptr, sizeof(ncl::TemplDev) * h.tmpl.size());
     p.bdev = L.take(nullptr, sizeof(ncl::BlockDev) * size_t(h.nblk));
@@ -732,6 +733,7 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.col_primal = reinterpret_cast<const uint8_t *>(at(26));
         d.bus_gen = reinterpret_cast<const int32_t *>(at(27));
         d.lkind = reinterpret_cast<const uint8_t *>(at(28));
+        d.iperm = reinterpret_cast<const int32_t *>(at(29));
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
     std::vector<ncl::BlockDev> bdev(h.nblk);

@@ -251,13 +251,30 @@ __device__ inline void branch_end(double g, double b, double vs, double vo, doub
 // dbase + j * nblk + bl; the border values of every instance follow at
 // dint + bd0.  Per template the state is an [nblk][n] array (blocks of a
 // template are contiguous in layout order, one block after the other),
-// moved in 64 x 64 tiles through LDS: reads run along j, writes along bl,
-// both coalesced.
-constexpr int kTile = 64;
+// moved through LDS in tiles of kTileJ columns x kTileB blocks: reads run
+// along j (kTileJ contiguous values of one block), writes along bl (kTileB
+// contiguous values of one column).  The tile is narrow in j so that a
+// launch holds several workgroups per compute unit.
+struct TileIx {
+    const TemplDev *T;
+    int j0, b0;
+};
+
+__device__ inline TileIx tile_index(const DevArgs &a, int64_t t) {
+    const TemplDev &T = a.tmpls[find_tmpl(a, t, &TemplDev::tile0)];
+    const int64_t tt = t - T.tile0;
+    const int nbt = (T.nblk + kTileB - 1) / kTileB;
+    return TileIx{&T, int(tt / nbt) * kTileJ, int(tt % nbt) * kTileB};
+}
+
+// per thread: kTileJ * kTileB / 256 values in each phase
+constexpr int kTileR = kTileJ * kTileB / 256;
+constexpr int kTileRows = 256 / kTileJ;   // blocks read per pass in the first phase
+static_assert(kTileB == 64 && 256 % kTileJ == 0 && kTileR * 4 == kTileJ, "tile shape");
 
 __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__restrict__ z,
                                                     const double *__restrict__ sig) {
-    __shared__ double tile[kTile][kTile + 1];
+    __shared__ double tile[kTileB][kTileJ + 1];
     const int64_t t = blockIdx.x;
     if (t >= a.tiles) {
         // border values: a plain copy
@@ -270,17 +287,15 @@ __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__r
         }
         return;
     }
-    const TemplDev &T = a.tmpls[find_tmpl(a, t, &TemplDev::tile0)];
-    const int64_t tt = t - T.tile0;
-    const int nbt = (T.nblk + kTile - 1) / kTile;
-    const int j0 = int(tt / nbt) * kTile, b0 = int(tt % nbt) * kTile;
-    const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const TileIx x = tile_index(a, t);
+    const TemplDev &T = *x.T;
+    const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
+    const int cb = threadIdx.x & 63, rj = threadIdx.x >> 6;
     // every load of both arrays is issued before the first barrier
-    constexpr int kR = kTile / 4;
-    double vz[kR], vs[kR];
+    double vz[kTileR], vs[kTileR];
 #pragma unroll
-    for (int q = 0; q < kR; q++) {
-        const int bl = b0 + r0 + 4 * q, j = j0 + c;
+    for (int q = 0; q < kTileR; q++) {
+        const int bl = x.b0 + rb + kTileRows * q, j = x.j0 + cj;
         const bool ok = bl < T.nblk && j < T.n;
         const int64_t src = ok ? a.blks[T.blocks[bl]].col0 + j : 0;
         vz[q] = ok ? z[src] : 0.0;
@@ -289,11 +304,12 @@ __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__r
     for (int pass = 0; pass < 2; pass++) {
         double *dst = pass ? a.sint : a.zint;
 #pragma unroll
-        for (int q = 0; q < kR; q++) tile[r0 + 4 * q][c] = pass ? vs[q] : vz[q];
+        for (int q = 0; q < kTileR; q++) tile[rb + kTileRows * q][cj] = pass ? vs[q] : vz[q];
         __syncthreads();
-        for (int r = r0; r < kTile; r += 4) {
-            const int j = j0 + r, bl = b0 + c;
-            if (bl < T.nblk && j < T.n) dst[T.dbase + int64_t(j) * T.nblk + bl] = tile[c][r];
+#pragma unroll
+        for (int q = 0; q < kTileR; q++) {
+            const int j = x.j0 + rj + 4 * q, bl = x.b0 + cb;
+            if (bl < T.nblk && j < T.n) dst[T.dbase + int64_t(j) * T.nblk + bl] = tile[cb][rj + 4 * q];
         }
         __syncthreads();
     }
@@ -1285,38 +1301,46 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
 
 // ------------------------------------------------------------------ solve
 
-// y (interleaved, factor order) = b (layout order, one column)
-// Template, column and block of a flat interleaved pivot index: the
-// template is searched once per wavefront (for its first index, through
-// scalar loads) and advanced by the lanes past its end.
-struct DIdx {
-    int ti, j, bl;
-};
-
-__device__ inline DIdx d_index(const DevArgs &a, int64_t idx) {
-    const int64_t w0 = int64_t(blockIdx.x) * blockDim.x + 64 * __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    int ti = find_tmpl(a, w0 < a.dint ? w0 : a.dint - 1, &TemplDev::dbase);
-    while (ti + 1 < a.ntmpl && a.tmpls[ti + 1].dbase <= idx) ti++;
-    const TemplDev &T = a.tmpls[ti];
-    const uint32_t off = uint32_t(idx - T.dbase), nb = uint32_t(T.nblk);
-    const uint32_t j = off / nb;
-    return DIdx{ti, int(j), int(off - j * nb)};
-}
-
+// Right-hand side into the solve vector and solution out of it: the
+// caller's order (block by block, layout-local columns) and the factor's
+// interleaved order are transposed through the LDS tiles of k_interleave,
+// so that both the reads and the writes are coalesced.
 __global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__restrict__ b, double *__restrict__ y) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= a.dint) return;
-    const DIdx d = d_index(a, idx);
-    const TemplDev &T = a.tmpls[d.ti];
-    y[idx] = b[a.blks[T.blocks[d.bl]].col0 + T.perm[d.j]];
+    __shared__ double tile[kTileB][kTileJ + 1];
+    const TileIx x = tile_index(a, blockIdx.x);
+    const TemplDev &T = *x.T;
+    const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
+    const int cb = threadIdx.x & 63, rj = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kTileR; q++) {
+        const int bl = x.b0 + rb + kTileRows * q, j = x.j0 + cj;
+        if (bl < T.nblk && j < T.n) tile[rb + kTileRows * q][cj] = b[a.blks[T.blocks[bl]].col0 + j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kTileR; q++) {
+        const int j = x.j0 + rj + 4 * q, bl = x.b0 + cb;
+        if (bl < T.nblk && j < T.n) y[T.dbase + int64_t(T.iperm[j]) * T.nblk + bl] = tile[cb][rj + 4 * q];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__restrict__ y, double *__restrict__ x) {
-    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= a.dint) return;
-    const DIdx d = d_index(a, idx);
-    const TemplDev &T = a.tmpls[d.ti];
-    x[a.blks[T.blocks[d.bl]].col0 + T.perm[d.j]] = y[idx];
+__global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__restrict__ y, double *__restrict__ xo) {
+    __shared__ double tile[kTileB][kTileJ + 1];
+    const TileIx x = tile_index(a, blockIdx.x);
+    const TemplDev &T = *x.T;
+    const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
+    const int cb = threadIdx.x & 63, rj = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < kTileR; q++) {
+        const int j = x.j0 + rj + 4 * q, bl = x.b0 + cb;
+        if (bl < T.nblk && j < T.n) tile[cb][rj + 4 * q] = y[T.dbase + int64_t(T.iperm[j]) * T.nblk + bl];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kTileR; q++) {
+        const int bl = x.b0 + rb + kTileRows * q, j = x.j0 + cj;
+        if (bl < T.nblk && j < T.n) xo[a.blks[T.blocks[bl]].col0 + j] = tile[rb + kTileRows * q][cj];
+    }
 }
 
 // forward gather of a diagonal row: y_row -= sum over descendants L_d[row,:] y_d
@@ -1922,7 +1946,7 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         }
         case NCL_K_SOL_LOAD:
-            if (a.dint) hipLaunchKernelGGL(k_sol_load, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.b, l.y);
+            if (a.dint) hipLaunchKernelGGL(k_sol_load, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.b, l.y);
             break;
         case NCL_K_SOL_FWD_GATHER:
             if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_fwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
@@ -1961,7 +1985,7 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (l.nw) hipLaunchKernelGGL(k_sol_bwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
             break;
         case NCL_K_SOL_STORE:
-            if (a.dint) hipLaunchKernelGGL(k_sol_store, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.y, l.x);
+            if (a.dint) hipLaunchKernelGGL(k_sol_store, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.y, l.x);
             break;
         case NCL_K_RESIDUAL: {
             const int64_t total = a.asm_threads + a.gp_tot;

@@ -41,6 +41,10 @@ struct CItem {
 // panel element, the panel's leading dimension and width, s's first column,
 // the tile rows s holds (bit jj for row j0 + jj) and their panel elements.
 constexpr int kSchurTJ = 8;
+// transposes between layout order and the interleaved order move tiles of
+// kTileJ columns x kTileB blocks
+constexpr int kTileJ = 16;
+constexpr int kTileB = 64;
 struct STile {
     int32_t pi, r, w, dcol, mask, pad[3];
     int32_t pj[kSchurTJ];
@@ -128,6 +132,7 @@ struct TemplDev {
     const int32_t *gen_idx;        // [ng][GI_N]
     const int32_t *gen_slot;       // [ng][GS_N]
     const int32_t *perm;           // [n] factor order -> layout-local
+    const int32_t *iperm;          // [n] layout-local -> factor order
     const uint8_t *col_primal;     // [n] expected pivot sign (1: positive) in factor order
     const int32_t *bus_gen;        // [nb] generator at the bus or -1
     const uint8_t *lkind;          // [n] layout-local kind (LK_*), for the dispatch map

@@ -235,7 +235,7 @@ int build_schedule(Handle &h) {
         h.t_abase[ti] = h.asm_threads;
         h.t_awbase[ti] = h.asm_wthreads;
         h.t_tile0[ti] = h.tiles;
-        h.tiles += int64_t((t.n + 63) / 64) * ((nb + 63) / 64);
+        h.tiles += int64_t((t.n + kTileJ - 1) / kTileJ) * ((nb + kTileB - 1) / kTileB);
         h.kint += t.colptr[t.n] * nb;
         h.lint += int64_t(t.panel_off.back()) * nb;
         h.dint += int64_t(t.n) * nb;
