@@ -97,7 +97,7 @@ struct TemplDev {
     int32_t nbus, ngen;            // network sizes (assembly threads per block)
     int64_t abase;                 // first residual thread of the template
     int64_t awbase;                // first assembly thread of the template (wavefront-aligned)
-    int64_t tile0;                 // first 64x64 transpose tile of the template (state interleaving)
+    int64_t tile0;                 // first transpose tile of the template (kTileJ columns x kTileB blocks)
     int64_t bd0;                   // the instance's border pivots / solution at dint + bd0
     const double *br_r, *br_x;     // the instance's branch data
     const double *gen_c2;
@@ -266,7 +266,7 @@ struct Handle {
     int64_t kint = 0, lint = 0, dint = 0;   // interleaved K values, panels, pivots (all templates)
     int64_t asm_threads = 0;                // template residual threads (border pg threads follow)
     int64_t asm_wthreads = 0;               // template assembly threads, wavefront-aligned (border pg threads follow)
-    int64_t tiles = 0;                      // 64x64 transpose tiles of all templates
+    int64_t tiles = 0;                      // transpose tiles of all templates
     std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase, t_awbase, t_tile0;
     Schedule sched;
     // numeric state
