@@ -185,3 +185,22 @@ def backward_error(colptr, rowind, vals, x, b):
     R = B - (full @ X.T).T
     eta = np.abs(R).max(axis=1) / (knorm * np.abs(X).max(axis=1) + np.abs(B).max(axis=1))
     return float(eta.max())
+
+
+def componentwise_backward_error(colptr, rowind, vals, x, b):
+    """Componentwise (Oettli-Prager) backward error, max over columns of
+    max_i |b - Kx|_i / (|K| |x| + |b|)_i.  A row whose denominator is zero
+    counts 0 when its residual is zero and +inf otherwise.  Unlike the
+    normwise error it sees a wrong component in a row whose own scale is
+    far below ||K|| ||x||."""
+    import scipy.sparse as sp
+    N = colptr.shape[0] - 1
+    Lw = sp.csc_matrix((vals, rowind, colptr), shape=(N, N))
+    full = Lw + Lw.T - sp.diags(Lw.diagonal())
+    X = np.atleast_2d(x)
+    B = np.atleast_2d(b)
+    R = np.abs(B - (full @ X.T).T)
+    den = (abs(full) @ np.abs(X).T).T + np.abs(B)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        q = np.where(den > 0, R / np.where(den > 0, den, 1.0), np.where(R > 0, np.inf, 0.0))
+    return float(q.max())

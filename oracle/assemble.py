@@ -21,7 +21,7 @@ What is built (Section IV-B, Newton system and the blocks A, B, C):
 * delta_i = max(0, sum_{j!=i} |H_ij| - H_ii): a per-row shift that makes
   H + diag(delta) diagonally dominant, so that K is quasi-definite at any
   (non-optimal) synthetic state.  The paper handles the same issue with
-  inertia correction (Section V-D); this shift is the reading used here.
+  inertia correction (Section V-C); this shift is the reading used here.
 
 Power flow (the paper cites the textbook polar form without writing it):
 branch l = (f, t) with series admittance g + jb = 1/(r + jx), status 1 (0

@@ -84,7 +84,7 @@ class DispatchSolver:
         """Factor the exact Newton matrix; if its pivot signs (inertia) are
         wrong, add dw on the primal diagonal, dw growing from a fraction of
         the last accepted value (or 1e-4) by x8 until they are right (the
-        inertia correction of Section V-D, as a primal shift dw I)."""
+        inertia correction of Section V-C, as a primal shift dw I)."""
         if self._factor(z, sig, exact=True):
             self.dw_last = 0.0
             return 0.0
