@@ -92,11 +92,36 @@ typedef struct {
     uint32_t flags;
 } ncl_network;
 
-/* Supernode amalgamation: a supernode absorbs its parent supernode when the
+/* Options of the symbolic analysis (all zero / NULL: the defaults).
+ *
+ * Supernode amalgamation: a supernode absorbs its parent supernode when the
  * merged width is <= relax_maxw and explicit zeros * relax_zden <=
- * entries * relax_znum.  Defaults (all zero here): 16, 1, 4. */
+ * entries * relax_znum.  Defaults (zero here): 16, 1, 4.
+ *
+ * Ordering (Section IV-B, last paragraph: the regularisation block C makes
+ * K quasi-definite, so every symmetric ordering has an LDL^T factorisation
+ * with 1x1 pivots and no pivoting):
+ *   NCL_ORDER_MD (0, default): exact minimum degree per block, ties to the
+ *     smallest layout index, the border last;
+ *   NCL_ORDER_USER: user_perm[N] (host, new -> layout index of the
+ *     network, or of the pattern for ncl_kkt_analyze_pattern) gives the
+ *     elimination order.  It must respect the block-arrowhead structure:
+ *     every block's positions map onto that block's own columns, blocks
+ *     that share a pattern template (every contingency block of a network;
+ *     the base block too when it has no complementarity rows) use the same
+ *     local order, and the border maps to itself in layout order (it is
+ *     factored as a dense matrix).  NCL_ERR_ARG otherwise.  Within a block
+ *     the library relabels the given order by the DFS postorder of its
+ *     elimination forest (children in elimination order): the same
+ *     elimination, so the fill and the pivots are those of the given order,
+ *     only their positions move (ncl_kkt_symbolic reports the final perm).
+ * For ncl_kkt_analyze_batch, user_perm of instance i indexes that
+ * instance's own columns. */
+enum { NCL_ORDER_MD = 0, NCL_ORDER_USER = 1 };
 typedef struct {
     int32_t relax_maxw, relax_znum, relax_zden;
+    int32_t ordering;
+    const int32_t *user_perm;
 } ncl_analyze_opts;
 
 /* One primal-dual state, DEVICE arrays of length N in layout order.

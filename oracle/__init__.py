@@ -40,7 +40,7 @@ def _load():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
-        L.oracle_symbolic.argtypes = [i64, P, P, i32, P, i32, i32, i32, ctypes.POINTER(P)]
+        L.oracle_symbolic.argtypes = [i64, P, P, i32, P, i32, i32, i32, P, ctypes.POINTER(P)]
         L.oracle_symbolic.restype = ctypes.c_int
         for f in ("oracle_N", "oracle_nnzl", "oracle_nsuper", "oracle_npanel"):
             getattr(L, f).argtypes = [P]
@@ -74,9 +74,13 @@ def lower_csc(rows, cols, vals, N):
 
 
 class Factor:
-    """Symbolic analysis plus (after ``factor``) the numeric LDL^T."""
+    """Symbolic analysis plus (after ``factor``) the numeric LDL^T.
 
-    def __init__(self, N, colptr, rowind, block_off, relax=DEFAULT_RELAX):
+    ``perm``: a caller's elimination order (new -> layout index) in place of
+    minimum degree; it must keep every block's columns inside the block and
+    the border in layout order."""
+
+    def __init__(self, N, colptr, rowind, block_off, relax=DEFAULT_RELAX, perm=None):
         L = _load()
         self.N = int(N)
         self.colptr = np.ascontiguousarray(colptr, np.int64)
@@ -84,8 +88,9 @@ class Factor:
         self.block_off = np.ascontiguousarray(block_off, np.int64)
         nblk = self.block_off.shape[0] - 1
         h = ctypes.c_void_p()
+        up = None if perm is None else np.ascontiguousarray(perm, np.int32)
         rc = L.oracle_symbolic(self.N, _ptr(self.colptr), _ptr(self.rowind), nblk, _ptr(self.block_off),
-                               int(relax[0]), int(relax[1]), int(relax[2]), ctypes.byref(h))
+                               int(relax[0]), int(relax[1]), int(relax[2]), _ptr(up), ctypes.byref(h))
         if rc != 0:
             raise RuntimeError(f"oracle_symbolic failed: {rc}")
         self._h = h
@@ -107,11 +112,11 @@ class Factor:
         self.factored = False
 
     @classmethod
-    def from_network(cls, net, relax=DEFAULT_RELAX):
+    def from_network(cls, net, relax=DEFAULT_RELAX, perm=None):
         z = np.zeros(_asm.Positions(net).N)
         r, c, v, pos = _asm.assemble(net, z + 1.0, z + 1.0)
         colptr, rowind, _ = lower_csc(r, c, v, pos.N)
-        f = cls(pos.N, colptr, rowind, np.array(pos.block_off, np.int64), relax)
+        f = cls(pos.N, colptr, rowind, np.array(pos.block_off, np.int64), relax, perm)
         f.pos = pos
         return f
 

@@ -18,7 +18,9 @@
  *     border vertices it touches), with an explicit elimination graph: pick
  *     the non-border vertex of smallest current degree (border neighbours
  *     count), ties to the smallest layout index; its neighbours become a
- *     clique; border vertices are never picked;
+ *     clique; border vertices are never picked.  A caller may give the
+ *     elimination sequence of each block instead (block-respecting, the
+ *     border in layout order); rules 2-6 then apply to it unchanged;
  *  2. parent(v) = the neighbour of v at its elimination that is eliminated
  *     first (border vertices come after all block vertices, in layout
  *     order); the block order is the DFS postorder of this forest, children
@@ -74,12 +76,14 @@ typedef struct {
 
 /* ------------------------------------------------------------ ordering */
 
-/* dense bit-matrix exact minimum degree on one block graph.
+/* dense bit-matrix elimination on one block graph: exact minimum degree,
+ * or (given != NULL) the elimination sequence given[0..nv-1] (a caller's
+ * ordering, rule 1 replaced, rules 2-6 unchanged).
  * nloc = block vertices (0..nv-1) followed by nbd border vertices.
  * adjacency given as a list of undirected edges (a, b) in local indices.
  * Writes order[0..nv-1] = block vertices in the final (postordered) order. */
 static int block_order(int nv, int nbd, int64_t ne, const int32_t *ea, const int32_t *eb,
-                       int32_t *order) {
+                       const int32_t *given, int32_t *order) {
     int n = nv + nbd;
     if (nv == 0) return 0;
     int64_t W = (n + 63) / 64;
@@ -107,8 +111,13 @@ static int block_order(int nv, int nbd, int64_t ne, const int32_t *ea, const int
     for (int step = 0; step < nv; step++) {
         /* smallest current degree among remaining block vertices, ties to the smallest index */
         int v = -1;
-        for (int u = 0; u < nv; u++)
-            if (!gone[u] && (v < 0 || deg[u] < deg[v])) v = u;
+        if (given) {
+            v = given[step];
+            if (v < 0 || v >= nv || gone[v]) return -1;
+        } else {
+            for (int u = 0; u < nv; u++)
+                if (!gone[u] && (v < 0 || deg[u] < deg[v])) v = u;
+        }
         elim[step] = v;
         epos[v] = step;
         gone[v] = 1;
@@ -210,7 +219,7 @@ void oracle_free(oracle_sym *s) {
  * border is [block_off[nblk], N). */
 int oracle_symbolic(int64_t N, const int64_t *colptr, const int32_t *rowind, int32_t nblk,
                     const int64_t *block_off, int32_t maxw, int32_t znum, int32_t zden,
-                    oracle_sym **out) {
+                    const int32_t *user_perm, oracle_sym **out) {
     if (N <= 0 || nblk <= 0 || maxw < 1 || zden <= 0 || znum < 0) return -1;
     oracle_sym *s = (oracle_sym *)calloc(1, sizeof(oracle_sym));
     s->N = N;
@@ -251,7 +260,7 @@ int oracle_symbolic(int64_t N, const int64_t *colptr, const int32_t *rowind, int
         int64_t o = block_off[b];
         int nv = (int)(block_off[b + 1] - o);
         int reuse = -1;
-        for (int c = 0; c < b && reuse < 0; c++) {
+        for (int c = 0; c < b && reuse < 0 && !user_perm; c++) {
             int64_t oc = block_off[c];
             if (block_off[c + 1] - oc != nv) continue;
             int same = 1;
@@ -290,12 +299,27 @@ int oracle_symbolic(int64_t N, const int64_t *colptr, const int32_t *rowind, int
                 k++;
             }
         int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nv + 1));
-        if (rc == 0) rc = block_order(nv, nbd, k, ea, eb, ord);
+        int32_t *given = NULL;
+        if (user_perm) {
+            /* the caller's order of this block, in block-local indices */
+            given = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nv + 1));
+            for (int v = 0; v < nv; v++) {
+                int64_t x = (int64_t)user_perm[o + v] - o;
+                if (x < 0 || x >= nv) rc = -1;
+                given[v] = (int32_t)x;
+            }
+        }
+        if (rc == 0) rc = block_order(nv, nbd, k, ea, eb, given, ord);
+        free(given);
         for (int v = 0; v < nv && rc == 0; v++) s->perm[o + v] = (int32_t)(o + ord[v]);
         free(ea); free(eb); free(ord);
     }
     if (rc) { free(ap); free(ai); oracle_free(s); return rc; }
-    for (int64_t j = bstart; j < N; j++) s->perm[j] = (int32_t)j;
+    for (int64_t j = bstart; j < N; j++) {
+        s->perm[j] = (int32_t)j;
+        if (user_perm && user_perm[j] != j) rc = -1;    /* the border keeps its layout order */
+    }
+    if (rc) { free(ap); free(ai); oracle_free(s); return rc; }
     s->iperm = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     for (int64_t j = 0; j < N; j++) s->iperm[s->perm[j]] = (int32_t)j;
 

@@ -25,7 +25,33 @@ int relax_params(const ncl_analyze_opts *o, int &maxw, int &znum, int &zden) {
         if (o->relax_maxw) maxw = o->relax_maxw;
         if (o->relax_zden) { znum = o->relax_znum; zden = o->relax_zden; }
         if (maxw < 1 || zden <= 0 || znum < 0) return NCL_ERR_ARG;
+        if (o->ordering != NCL_ORDER_MD && o->ordering != NCL_ORDER_USER) return NCL_ERR_ARG;
+        if (o->ordering == NCL_ORDER_USER && !o->user_perm) return NCL_ERR_ARG;
     }
+    return NCL_OK;
+}
+
+// The local elimination order of template t from a caller's permutation of
+// its instance (new -> layout index, instance-local), checked to respect
+// the block structure: every block of the template takes the same local
+// order over its own columns, and the instance's border maps to itself.
+int user_order(const Handle &h, const Template &t, const int32_t *perm, std::vector<int32_t> &order) {
+    const ncl::Inst &I = h.inst[t.inst];
+    const int n = t.n;
+    order.assign(n, -1);
+    for (size_t q = 0; q < t.blocks.size(); q++) {
+        const int b = t.blocks[q];
+        const int64_t o = h.block_col0[b] - I.col0;
+        for (int j = 0; j < n; j++) {
+            const int64_t v = int64_t(perm[o + j]) - o;
+            if (v < 0 || v >= n) return NCL_ERR_ARG;
+            if (q == 0) order[j] = int32_t(v);
+            else if (order[j] != v) return NCL_ERR_ARG;
+        }
+    }
+    const int64_t bs = I.bstart - I.col0;
+    for (int j = 0; j < I.nbd; j++)
+        if (perm[bs + j] != bs + j) return NCL_ERR_ARG;
     return NCL_OK;
 }
 
@@ -49,7 +75,13 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts, int nopts) {
         int maxw, znum, zden;
         int rc = relax_params(opts_of(t.inst), maxw, znum, zden);
         if (rc) return rc;
-        rc = ncl::analyze_template(t, h.inst[t.inst].nbd, maxw, znum, zden);
+        const ncl_analyze_opts *o = opts_of(t.inst);
+        std::vector<int32_t> order;
+        if (o && o->ordering == NCL_ORDER_USER) {
+            rc = user_order(h, t, o->user_perm, order);
+            if (rc) return rc;
+        }
+        rc = ncl::analyze_template(t, h.inst[t.inst].nbd, maxw, znum, zden, order.empty() ? nullptr : order.data());
         if (rc) return rc;
         rc = ncl::build_template_schedule(t, h.inst[t.inst].nbd);
         if (rc) return rc;

@@ -304,7 +304,7 @@ int build_network_model(const ncl_network *net, Handle &h, std::string &err);
 int build_pattern_model(int64_t N, int nblk, const int64_t *block_off, const int64_t *colptr, const int32_t *rowind,
                         const uint8_t *is_primal, Handle &h, std::string &err);
 // symbolic.cpp
-int analyze_template(Template &t, int nbd, int maxw, int znum, int zden);
+int analyze_template(Template &t, int nbd, int maxw, int znum, int zden, const int32_t *order);
 int analyze_border(Handle &h, Inst &I, int maxw, int znum, int zden);
 // schedule.cpp
 int build_template_schedule(Template &t, int nbd);

@@ -5,10 +5,13 @@
 //   exact minimum degree on the template graph (its vertices plus the
 //   border vertices it touches): the non-border vertex of smallest current
 //   degree goes next (ties: smallest layout index), its neighbours become a
-//   clique, border vertices are never eliminated; the elimination forest's
-//   DFS postorder (children and roots by elimination position) is the
-//   block order; then the symbolic factorisation, the fundamental
-//   supernodes (at most kMaxW columns) and relaxed amalgamation.
+//   clique, border vertices are never eliminated -- or a caller-given
+//   elimination sequence instead; the elimination forest's DFS postorder
+//   (children and roots by elimination position) is the block order (a
+//   topological relabelling of the same elimination: the fill and the
+//   factor's entries are those of the sequence); then the symbolic
+//   factorisation, the fundamental supernodes (at most kMaxW columns) and
+//   relaxed amalgamation.
 // The border (first-stage variables) follows all blocks in layout order;
 // its structure collects the border rows of every block root.
 #include <algorithm>
@@ -20,11 +23,14 @@ namespace ncl {
 
 namespace {
 
-// Exact minimum degree.  adj: block vertices 0..n-1, border vertices n.. .
-// Returns the elimination sequence and, per vertex, the block neighbours
-// it had when it was eliminated.
-void min_degree(int n, std::vector<std::vector<int32_t>> &adj, std::vector<int32_t> &seq,
-                std::vector<std::vector<int32_t>> &bnbr) {
+// Elimination on the explicit elimination graph.  adj: block vertices
+// 0..n-1, border vertices n.. .  With given == nullptr the next vertex is
+// the one of smallest current degree (exact minimum degree, ties to the
+// smallest index); otherwise given[0..n) is the elimination sequence.
+// Returns the sequence and, per vertex, the block neighbours it had when it
+// was eliminated.
+void eliminate(int n, std::vector<std::vector<int32_t>> &adj, const int32_t *given, std::vector<int32_t> &seq,
+               std::vector<std::vector<int32_t>> &bnbr) {
     std::set<std::pair<int32_t, int32_t>> pq;
     std::vector<char> gone(n, 0);
     for (int v = 0; v < n; v++) pq.insert({int32_t(adj[v].size()), v});
@@ -32,8 +38,14 @@ void min_degree(int n, std::vector<std::vector<int32_t>> &adj, std::vector<int32
     bnbr.assign(n, {});
     std::vector<int32_t> merged;
     while (!pq.empty()) {
-        int v = pq.begin()->second;
-        pq.erase(pq.begin());
+        int v;
+        if (given) {
+            v = given[seq.size()];
+            pq.erase({int32_t(adj[v].size()), v});
+        } else {
+            v = pq.begin()->second;
+            pq.erase(pq.begin());
+        }
         gone[v] = 1;
         seq.push_back(v);
         const std::vector<int32_t> nv = adj[v];   // remaining neighbours (sorted)
@@ -56,7 +68,7 @@ void min_degree(int n, std::vector<std::vector<int32_t>> &adj, std::vector<int32
 
 }  // namespace
 
-int analyze_template(Template &t, int nbd, int maxw, int znum, int zden) {
+int analyze_template(Template &t, int nbd, int maxw, int znum, int zden, const int32_t *order) {
     const int n = t.n;
     // undirected adjacency of the template (border as n + b)
     std::vector<std::vector<int32_t>> adj(n);
@@ -73,7 +85,14 @@ int analyze_template(Template &t, int nbd, int maxw, int znum, int zden) {
     }
     std::vector<int32_t> seq;
     std::vector<std::vector<int32_t>> bnbr;
-    min_degree(n, adj, seq, bnbr);
+    if (order) {
+        std::vector<char> seen(n, 0);
+        for (int j = 0; j < n; j++) {
+            if (order[j] < 0 || order[j] >= n || seen[order[j]]) return NCL_ERR_ARG;
+            seen[order[j]] = 1;
+        }
+    }
+    eliminate(n, adj, order, seq, bnbr);
     std::vector<int32_t> epos(n);
     for (int s = 0; s < n; s++) epos[seq[s]] = s;
     std::vector<int32_t> mpar(n, -1);

@@ -43,7 +43,11 @@ class _Network(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("relax_maxw", ctypes.c_int32), ("relax_znum", ctypes.c_int32), ("relax_zden", ctypes.c_int32)]
+    _fields_ = [("relax_maxw", ctypes.c_int32), ("relax_znum", ctypes.c_int32), ("relax_zden", ctypes.c_int32),
+                ("ordering", ctypes.c_int32), ("user_perm", ctypes.c_void_p)]
+
+
+NCL_ORDER_MD, NCL_ORDER_USER = 0, 1
 
 
 NCL_NO_SHIFT = 1
@@ -159,16 +163,27 @@ class KKT:
     of independent networks in one handle (every launch then covers all of
     them; vectors are the instances' layout-order vectors concatenated).
     ``relax`` is one (maxw, znum, zden) triple, or with a batch optionally a
-    list with one triple per instance."""
+    list with one triple per instance.  ``perm`` (single network or
+    pattern): a caller-given elimination order, new -> layout index
+    (NCL_ORDER_USER); None takes minimum degree."""
 
-    def __init__(self, net=None, *, relax=None, pattern=None, nets=None):
+    def __init__(self, net=None, *, relax=None, pattern=None, nets=None, perm=None):
         L = load()
         self._h = ctypes.c_void_p()
         self._keep = []
         opts = None
         if relax is not None and not (nets is not None and isinstance(relax, (list, tuple))
                                       and len(relax) and isinstance(relax[0], (list, tuple))):
-            opts = _Opts(int(relax[0]), int(relax[1]), int(relax[2]))
+            opts = _Opts(int(relax[0]), int(relax[1]), int(relax[2]), NCL_ORDER_MD, None)
+        if perm is not None:
+            if nets is not None:
+                raise ValueError("perm is for a single network or pattern")
+            pa = np.ascontiguousarray(perm, np.int32)
+            self._keep.append(pa)
+            if opts is None:
+                opts = _Opts(0, 0, 0, NCL_ORDER_USER, None)
+            opts.ordering = NCL_ORDER_USER
+            opts.user_perm = _np_ptr(pa).value
         if nets is not None:
             nets = list(nets)
             arr = (_Network * len(nets))(*[_network_struct(n, self._keep) for n in nets])
@@ -177,7 +192,8 @@ class KKT:
             if opts is not None:
                 optp, nopts = ctypes.byref(opts), 1
             elif relax is not None:
-                oarr = (_Opts * len(nets))(*[_Opts(int(r[0]), int(r[1]), int(r[2])) for r in relax])
+                oarr = (_Opts * len(nets))(*[_Opts(int(r[0]), int(r[1]), int(r[2]), NCL_ORDER_MD, None)
+                                             for r in relax])
                 self._keep.append(oarr)
                 optp, nopts = oarr, len(nets)
             rc = L.ncl_kkt_analyze_batch(arr, len(nets), optp, nopts, ctypes.byref(self._h))

@@ -55,6 +55,69 @@ def test_symbolic_relax_parameters(relax):
     _compare(KKT(net, relax=relax), O.Factor.from_network(net, relax=relax))
 
 
+def block_respecting_perm(net, g):
+    """A random elimination order that keeps every block's columns inside the
+    block, the same local order for blocks that share a pattern (all blocks
+    but a complementarity base block), and the border in layout order."""
+    from oracle.assemble import Positions
+    pos = Positions(net)
+    off = pos.block_off
+    perm = np.arange(pos.N, dtype=np.int32)
+    local = {}
+    for b in range(net.nblk):
+        n = off[b + 1] - off[b]
+        key = (b == 0 and net.pvpq, n)
+        if key not in local:
+            local[key] = g.permutation(n)
+        perm[off[b]:off[b + 1]] = off[b] + local[key]
+    return perm
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_symbolic_user_order_c1(seed):
+    net = G.config_network(1)
+    p = block_respecting_perm(net, np.random.default_rng(seed))
+    k = KKT(net, perm=p)
+    F = O.Factor.from_network(net, perm=p)
+    _compare(k, F)
+    # the postorder relabels the given elimination: the etree of the final
+    # order is a topological order, and the fill is that of the given order
+    assert (F.parent[F.parent >= 0] > np.flatnonzero(F.parent >= 0)).all()
+
+
+@pytest.mark.parametrize("which", ["c2", "pvpq"])
+def test_symbolic_user_order_blocks(which):
+    net = G.config_network(2) if which == "c2" else G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5)
+    p = block_respecting_perm(net, np.random.default_rng(7))
+    _compare(KKT(net, perm=p), O.Factor.from_network(net, perm=p))
+
+
+def test_user_order_rejected_unless_block_respecting():
+    net = G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5)
+    from oracle.assemble import Positions
+    pos = Positions(net)
+    g = np.random.default_rng(1)
+    good = block_respecting_perm(net, g)
+    # two columns of different blocks swapped
+    bad = good.copy()
+    a, b = pos.block_off[1], pos.block_off[2]
+    bad[a], bad[b] = bad[b], bad[a]
+    # two contingency blocks (one template) in different local orders
+    mixed = good.copy()
+    s, e = pos.block_off[2], pos.block_off[3]
+    mixed[s:e] = s + g.permutation(e - s)
+    # the border permuted
+    bord = good.copy()
+    bord[-2], bord[-1] = bord[-1], bord[-2]
+    for p in (bad, mixed, bord):
+        with pytest.raises(NclError) as ei:
+            KKT(net, perm=p)
+        assert ei.value.code == -1
+    for p in (bad, bord):
+        with pytest.raises(RuntimeError):
+            O.Factor.from_network(net, perm=p)
+
+
 @pytest.mark.slow
 def test_symbolic_bit_exact_c5():
     net = G.config_network(5)
