@@ -145,21 +145,35 @@ typedef struct {
 } ncl_kkt_point;
 
 /* Factorisation report (ncl_kkt_info).  npos/nneg/nzero count the signs of
- * D; first_bad is the first pivot (factor order) that was zero, non-finite
- * or of the wrong sign (-1 if none); status is NCL_OK or the NCL_ERR_* of
- * that pivot. */
+ * D and nnonfinite its NaN or infinite pivots; first_bad is the first pivot
+ * (factor order) that was zero, non-finite or of the wrong sign (-1 if
+ * none); status is NCL_OK or the NCL_ERR_* of that pivot.
+ * solvable = 1 when the solves may use the factors: no zero or non-finite
+ * pivot and the inertia (npos, nneg) equal to (n, m) (the inertia a
+ * quasi-definite K has, Section IV-B).  A factor with the right inertia but
+ * individual pivots of the other sign (possible only when K11 is not
+ * definite, e.g. the exact Newton matrix at a local minimum, whose reduced
+ * Hessian is positive definite) reports NCL_ERR_INERTIA and stays
+ * solvable; the inertia-correction loop of Section V-C acts on the counts. */
 typedef struct {
     int64_t npos, nneg, nzero, first_bad;
     double min_absd, max_absd;
     int32_t status;
+    int32_t solvable;
+    int64_t nnonfinite;
 } ncl_kkt_report;
 
-/* Symbolic analysis of the KKT of a network (once per pattern).
+/* Symbolic analysis of the KKT of a network (once per pattern: between NCL
+ * outer iterations only the objective changes, Section IV-A, and inside an
+ * outer iteration only the values, Section IV-B).  The block-arrowhead
+ * structure is that of the SCOPF (Section II-B, eq. (scopf)): one block per
+ * scenario coupled through the first-stage border.
  * Builds the union pattern of K (an outaged branch keeps explicit zeros,
  * so every contingency block has the same pattern), a minimum-degree
- * ordering per block with the border last, the elimination tree, the
- * column counts, the supernode partition and all schedules.  Host only;
- * no device memory is touched.  opts may be NULL (defaults).
+ * ordering per block with the border last (or the caller's, see
+ * ncl_analyze_opts), the elimination tree, the column counts, the
+ * supernode partition and all schedules.  Host only; no device memory is
+ * touched.  opts may be NULL (defaults).
  * Returns NCL_ERR_ARG for out-of-range indices, unsorted or duplicate
  * branches, too many or bridge outages, and for a border of more than
  * NCL_MAX_BORDER variables (the dense border factor works on one compute
@@ -244,9 +258,15 @@ int ncl_kkt_set_values(ncl_kkt *h, const double *dvals, void *stream);
 /* Device copy of the current K values (lower CSC order) into dvals[nnzK]. */
 int ncl_kkt_get_values(ncl_kkt *h, double *dvals, void *stream);
 
-/* Pivot-free LDL^T of the current values: blocks in parallel, then the
- * fixed-order sum of their border Schur contributions and the dense LDL^T
- * of the border.  Asynchronous; see ncl_kkt_info. */
+/* Pivot-free LDL^T of the current values (Section IV-B, last paragraph:
+ * the regularisation block C makes K quasi-definite, so the 1x1 pivots of
+ * any symmetric ordering exist; the paper's signed Cholesky): blocks in
+ * parallel, then the fixed-order sum of their border Schur contributions
+ * and the dense LDL^T of the border.  Asynchronous; pivot signs, zeros and
+ * non-finite values are recorded on the device (see ncl_kkt_info).
+ * NCL_ERR_STATE without a bound workspace or before any assemble /
+ * set_values.  From the start of the call until it completes, the previous
+ * factors are gone: solves in between return NCL_ERR_STATE. */
 int ncl_kkt_factor(ncl_kkt *h, void *stream);
 
 /* The two phases of ncl_kkt_factor, callable separately (same result):
@@ -258,7 +278,12 @@ int ncl_kkt_factor(ncl_kkt *h, void *stream);
 int ncl_kkt_factor_blocks(ncl_kkt *h, void *stream);
 int ncl_kkt_factor_border(ncl_kkt *h, void *stream);
 
-/* Synchronises `stream` and reports the last factorisation. */
+/* Synchronises `stream` and reports the last factorisation: the inertia
+ * that the inertia correction of Section V-C acts on, and whether the
+ * factors may be solved with (ncl_kkt_report.solvable).  After a report
+ * with solvable = 0, solve, solve_adjoint and refine return NCL_ERR_STATE
+ * until the next factor.  (A solve issued before the report runs on the
+ * device, which finds the same failure and fills x with NaN.) */
 int ncl_kkt_info(ncl_kkt *h, ncl_kkt_report *rep, void *stream);
 
 /* Device copies of the factors: lx[nnzL] on the exact pattern of
@@ -267,8 +292,13 @@ int ncl_kkt_info(ncl_kkt *h, ncl_kkt_report *rep, void *stream);
 int ncl_kkt_get_factors(ncl_kkt *h, double *dlx, double *dd, void *stream);
 
 /* X = K^{-1} B for nrhs columns of length N in layout order, leading
- * dimension ld >= N (device).  dx may equal db.  nrhs <= the workspace's
- * nrhs_max.  NCL_ERR_STATE before the first factor. */
+ * dimension ld >= N (device): the Newton step of eq. (newtonsystem),
+ * [dw; dy] for the right-hand side (r1, r2) the interior-point method sets
+ * (Section IV-B).  Forward substitution by blocks, the border, D^{-1},
+ * backward substitution.  dx may equal db.  nrhs <= the workspace's
+ * nrhs_max.  NCL_ERR_STATE before the first factor, during one, or after a
+ * factor that ncl_kkt_info reported not solvable; NCL_ERR_ARG for nrhs or
+ * ld out of range. */
 int ncl_kkt_solve(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream);
 
 /* X = K^{-T} B on the stored factors (K is symmetric, so the same
@@ -276,6 +306,25 @@ int ncl_kkt_solve(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_
  * reverse-mode differentiation; it never refactors. */
 int ncl_kkt_solve_adjoint(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld,
                           void *stream);
+
+/* Accuracy gate (the residual of eq. (newtonsystem)): for each of nrhs
+ * columns (layout order, leading dimension ld, device) the normwise
+ * backward error eta = ||b - Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf)
+ * and the componentwise one omega = max_i |b - Kx|_i / (|K||x| + |b|)_i
+ * (0/0 counts 0), with K the current values (assembled or set), written to
+ * derr[2 rhs] and derr[2 rhs + 1] (device doubles).  No host
+ * synchronisation: the caller reads derr when it needs it.  A NaN in x or b
+ * makes both NaN.  NCL_ERR_STATE without values; NCL_ERR_ARG for
+ * ld < N or null pointers.  Uses the workspace's residual buffers, so calls
+ * on one handle must not overlap. */
+int ncl_kkt_backward_error(ncl_kkt *h, const double *db, const double *dx, int32_t nrhs, int64_t ld, double *derr,
+                           void *stream);
+
+/* One step of iterative refinement on the stored factors:
+ * x += K^{-1} (b - K x) for each of nrhs columns (device, in place), with K
+ * the current values (they must be the ones factored).  Errors as
+ * ncl_kkt_solve. */
+int ncl_kkt_refine(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream);
 
 void ncl_kkt_destroy(ncl_kkt *h);
 const char *ncl_status_string(int status);
@@ -346,6 +395,9 @@ enum {
     NCL_K_INTERLEAVE,       /* k_interleave: the state transposed to the blocks' interleaved order (assembly) */
     NCL_K_BORDER_PANEL,     /* k_border_panel: borders over 216 rows, diagonal block and rows of one column block */
     NCL_K_BORDER_UPDATE,    /* k_border_update: borders over 216 rows, trailing update by one column block */
+    NCL_K_BERR_ROWS,        /* k_berr_rows: residual of the block rows (backward error, refinement) */
+    NCL_K_BERR_BORDER,      /* k_berr_border: residual of the border rows */
+    NCL_K_BERR_FINAL,       /* k_berr_final: eta and omega from the partial maxima */
     NCL_K_COUNT
 };
 

@@ -91,6 +91,25 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts, int nopts) {
         int rc = relax_params(opts_of(i), maxw, znum, zden);
         if (!rc) rc = ncl::analyze_border(h, h.inst[i], maxw, znum, zden);
         if (rc) return rc;
+        // full symmetric rows of K_bb (residual of the border rows)
+        ncl::Inst &I = h.inst[i];
+        std::vector<std::vector<int32_t>> br(I.nbd);
+        for (int c = 0; c < I.nbd; c++)
+            for (int64_t p = I.bcolptr[c]; p < I.bcolptr[c + 1]; p++) {
+                const int32_t r = I.browind[p];
+                br[r].push_back(int32_t(p));
+                br[r].push_back(c);
+                if (r != c) {
+                    br[c].push_back(int32_t(p));
+                    br[c].push_back(r);
+                }
+            }
+        I.kbr_ptr.assign(1, 0);
+        I.kbr_ent.clear();
+        for (auto &r : br) {
+            I.kbr_ent.insert(I.kbr_ent.end(), r.begin(), r.end());
+            I.kbr_ptr.push_back(int32_t(I.kbr_ent.size() / 2));
+        }
     }
     int rc = ncl::build_schedule(h);
     if (rc) return rc;
@@ -160,8 +179,11 @@ struct Plan {
     std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
     size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, tables_end = 0;
     size_t kval = 0, lpan = 0, upan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
-           total = 0;
+           xint = 0, bint = 0, rint = 0, rbuf = 0, epart = 0, total = 0;
 };
+
+// Workgroups of the backward-error kernels (their partial maxima).
+int64_t berr_partials(const Handle &h) { return (h.rows_waves + 3) / 4 + (h.nbd_tot + 3) / 4; }
 
 std::vector<uint8_t> col_primal(const Template &t) {
     std::vector<uint8_t> cp(t.n);
@@ -225,6 +247,10 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(t.bus_gen));
         o.push_back(L.vec(t.lkind));
         o.push_back(L.vec(t.iperm));
+        o.push_back(L.vec(t.rr_ptr));
+        o.push_back(L.vec(t.rr_ent));
+        o.push_back(L.vec(t.rb_ptr));
+        o.push_back(L.vec(t.rb_ent));
     }
     p.tdev = L.take(nullptr, sizeof(ncl::TemplDev) * h.tmpl.size());
     p.bdev = L.take(nullptr, sizeof(ncl::BlockDev) * size_t(h.nblk));
@@ -234,7 +260,8 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     std::vector<uint8_t> bprim;
     for (size_t i = 0; i < h.inst.size(); i++) {
         const ncl::Inst &I = h.inst[i];
-        p.ioff[i] = {L.vec(I.kbb_pos), L.vec(I.border_pg), L.vec(I.gen_c2), L.vec(I.br_r), L.vec(I.br_x)};
+        p.ioff[i] = {L.vec(I.kbb_pos), L.vec(I.border_pg), L.vec(I.gen_c2), L.vec(I.br_r), L.vec(I.br_x),
+                     L.vec(I.kbr_ptr), L.vec(I.kbr_ent)};
         bprim.insert(bprim.end(), I.border_primal.begin(), I.border_primal.end());
     }
     p.bprim = L.vec(bprim);
@@ -250,7 +277,12 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.cp_tot));
     p.zint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
     p.sint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
-    p.stat = L.take(nullptr, sizeof(int64_t) * 6 * ncl::kStatStride);
+    p.xint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
+    p.bint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
+    p.rint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
+    p.rbuf = L.take(nullptr, sizeof(double) * size_t(h.N));
+    p.epart = L.take(nullptr, sizeof(double) * 8 * size_t(berr_partials(h)));
+    p.stat = L.take(nullptr, sizeof(int64_t) * ncl::kStatWords * ncl::kStatStride);
     p.total = L.off;
     return p;
 }
@@ -286,6 +318,14 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.cpart = h.d.cpart;
     a.stat = h.d.stat;
     a.bprim = h.d.bprim;
+    a.rows_waves = h.rows_waves;
+    a.nprimal = h.nprimal;
+    a.xint = h.d.xint;
+    a.bint = h.d.bint;
+    a.rint = h.d.rint;
+    a.rbuf = h.d.rbuf;
+    a.epart = h.d.epart;
+    a.rows_wg = int((h.rows_waves + 3) / 4);
     return a;
 }
 
@@ -456,6 +496,9 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
         case NCL_K_RESIDUAL: return a.asm_threads + a.gp_tot > 0;
         case NCL_K_INTERLEAVE: return a.tiles + a.nbd_tot > 0;
         case NCL_K_MAX_STEP: return true;
+        case NCL_K_BERR_ROWS: return a.rows_waves > 0;
+        case NCL_K_BERR_BORDER: return a.nbd_tot > 0;
+        case NCL_K_BERR_FINAL: return true;
         default: return l.nw > 0;
     }
 }
@@ -766,6 +809,11 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.bus_gen = reinterpret_cast<const int32_t *>(at(27));
         d.lkind = reinterpret_cast<const uint8_t *>(at(28));
         d.iperm = reinterpret_cast<const int32_t *>(at(29));
+        d.rr_ptr = reinterpret_cast<const int32_t *>(at(30));
+        d.rr_ent = reinterpret_cast<const int32_t *>(at(31));
+        d.rb_ptr = reinterpret_cast<const int32_t *>(at(32));
+        d.rb_ent = reinterpret_cast<const int32_t *>(at(33));
+        d.rwbase = h.t_rwbase[ti];
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
     std::vector<ncl::BlockDev> bdev(h.nblk);
@@ -798,6 +846,10 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.kbb_pos = reinterpret_cast<const int32_t *>(base + p.ioff[i][0]);
         d.border_pg = reinterpret_cast<const int32_t *>(base + p.ioff[i][1]);
         d.gen_c2 = reinterpret_cast<const double *>(base + p.ioff[i][2]);
+        d.kbr_ptr = reinterpret_cast<const int32_t *>(base + p.ioff[i][5]);
+        d.kbr_ent = reinterpret_cast<const int32_t *>(base + p.ioff[i][6]);
+        d.t0 = I.t0;
+        d.nt = I.nt;
     }
     std::memcpy(buf.data() + p.idev, idev.data(), sizeof(ncl::InstDev) * idev.size());
     if (hipMemcpyAsync(base, buf.data(), buf.size(), hipMemcpyHostToDevice, st) != hipSuccess) return NCL_ERR_HIP;
@@ -821,9 +873,16 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.d.zint = reinterpret_cast<double *>(base + p.zint);
     h.d.sint = reinterpret_cast<double *>(base + p.sint);
     h.d.stat = reinterpret_cast<int64_t *>(base + p.stat);
+    h.d.xint = reinterpret_cast<double *>(base + p.xint);
+    h.d.bint = reinterpret_cast<double *>(base + p.bint);
+    h.d.rint = reinterpret_cast<double *>(base + p.rint);
+    h.d.rbuf = reinterpret_cast<double *>(base + p.rbuf);
+    h.d.epart = reinterpret_cast<double *>(base + p.epart);
     h.bound = true;
     h.factored = false;
     h.blocks_done = false;
+    h.values_set = false;
+    h.factor_failed = false;
     return NCL_OK;
 }
 
@@ -839,8 +898,12 @@ int ncl_kkt_assemble(ncl_kkt *k, const ncl_kkt_point *pt, void *stream) {
     l.flags = pt->flags;
     const ncl::DevArgs a = dev_args(h);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    l.zdst = h.d.zint;
+    l.sdst = h.d.sint;
     if (run(h, NCL_K_INTERLEAVE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
-    return hip_rc(run(h, NCL_K_ASSEMBLE, a, l, st));
+    if (run(h, NCL_K_ASSEMBLE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    h.values_set = true;
+    return NCL_OK;
 }
 
 int ncl_kkt_set_values(ncl_kkt *k, const double *dvals, void *stream) {
@@ -851,7 +914,9 @@ int ncl_kkt_set_values(ncl_kkt *k, const double *dvals, void *stream) {
     l.src = dvals;
     l.dst = h.d.kval;
     l.to_internal = true;
-    return hip_rc(run(h, NCL_K_VALUES, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
+    if (run(h, NCL_K_VALUES, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return NCL_ERR_HIP;
+    h.values_set = true;
+    return NCL_OK;
 }
 
 int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
@@ -868,8 +933,11 @@ int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
 int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
     if (!k) return NCL_ERR_ARG;
     Handle &h = k->h;
-    if (!h.bound) return NCL_ERR_STATE;
+    if (!h.bound || !h.values_set) return NCL_ERR_STATE;
+    // the factors are overwritten from here on: no solve until the border is done
     h.blocks_done = false;
+    h.factored = false;
+    h.factor_failed = false;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const ncl::DevArgs a = dev_args(h);
     const ncl::Schedule &S = h.sched;
@@ -926,10 +994,10 @@ int ncl_kkt_info(ncl_kkt *k, ncl_kkt_report *rep, void *stream) {
     if (!k || !rep) return NCL_ERR_ARG;
     Handle &h = k->h;
     if (!h.factored) return NCL_ERR_STATE;
-    int64_t sw[6 * ncl::kStatStride], s[6];
+    int64_t sw[ncl::kStatWords * ncl::kStatStride], s[ncl::kStatWords];
     if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return NCL_ERR_HIP;
     if (hipMemcpy(sw, h.d.stat, sizeof(sw), hipMemcpyDeviceToHost) != hipSuccess) return NCL_ERR_HIP;
-    for (int q = 0; q < 6; q++) s[q] = sw[q * ncl::kStatStride];
+    for (int q = 0; q < ncl::kStatWords; q++) s[q] = sw[q * ncl::kStatStride];
     rep->npos = s[0];
     rep->nneg = s[1];
     rep->nzero = s[2];
@@ -946,6 +1014,10 @@ int ncl_kkt_info(ncl_kkt *k, ncl_kkt_report *rep, void *stream) {
         const int code = int(s[3] % 8);
         rep->status = code == 1 ? NCL_ERR_INERTIA : code == 2 ? NCL_ERR_ZERO_PIVOT : NCL_ERR_NONFINITE;
     }
+    rep->nnonfinite = s[6];
+    // the same test k_sol_load makes on the device
+    rep->solvable = (s[2] == 0 && s[6] == 0 && s[0] == h.nprimal) ? 1 : 0;
+    h.factor_failed = !rep->solvable;
     return NCL_OK;
 }
 
@@ -997,25 +1069,23 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
     return NCL_OK;
 }
 
-static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {
-    if (!k || !db || !dx || nrhs < 1) return NCL_ERR_ARG;
-    Handle &h = k->h;
-    if (!h.bound || !h.factored) return NCL_ERR_STATE;
-    if (nrhs > h.nrhs_max || ld < h.N) return NCL_ERR_ARG;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const ncl::DevArgs a = dev_args(h);
+// One right-hand side through the factors.  refine: the right-hand side is
+// the residual the backward-error kernels left (blocks interleaved in rint,
+// the border in rbuf) and the solution is added into x.
+static int solve_column(Handle &h, const ncl::DevArgs &a, const double *b, double *x, int rhs, bool refine,
+                        hipStream_t st) {
     const ncl::Schedule &S = h.sched;
     const ncl::Work *W = h.d.work;
-    for (int rhs = 0; rhs < nrhs; rhs++) {
-        const double *b = db + int64_t(rhs) * ld;
-        double *x = dx + int64_t(rhs) * ld;
+    {
         double *y = h.d.ybuf + int64_t(rhs) * (h.dint + h.nbd_tot);
         double *cp = h.d.cpart + int64_t(rhs) * h.cp_tot;
         ncl::LaunchArgs v;
-        v.b = b;
+        v.b = refine ? h.d.rbuf : b;
         v.x = x;
         v.y = y;
         v.cpart = cp;
+        v.src = refine ? h.d.rint : nullptr;
+        v.accumulate = refine;
         auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
             ncl::LaunchArgs la = v;
             la.wl = W + off + ptr[l];
@@ -1039,6 +1109,39 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
             if (list(NCL_K_SOL_BWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         }
         if (run(h, NCL_K_SOL_STORE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    return NCL_OK;
+}
+
+static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {
+    if (!k || !db || !dx || nrhs < 1) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound || !h.factored || h.factor_failed) return NCL_ERR_STATE;
+    if (nrhs > h.nrhs_max || ld < h.N) return NCL_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    for (int rhs = 0; rhs < nrhs; rhs++) {
+        const int rc = solve_column(h, a, db + int64_t(rhs) * ld, dx + int64_t(rhs) * ld, rhs, false, st);
+        if (rc) return rc;
+    }
+    return NCL_OK;
+}
+
+// r = b - K x of one column into rint (blocks) and rbuf (border), and the
+// partial maxima of the backward error; with derr, its final (eta, omega).
+static int residual_column(Handle &h, const ncl::DevArgs &a, const double *b, const double *x, double *derr,
+                           hipStream_t st) {
+    ncl::LaunchArgs l;
+    l.z = x;
+    l.sig = b;
+    l.zdst = h.d.xint;
+    l.sdst = h.d.bint;
+    if (run(h, NCL_K_INTERLEAVE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    if (run(h, NCL_K_BERR_ROWS, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    if (run(h, NCL_K_BERR_BORDER, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    if (derr) {
+        l.dst = derr;
+        if (run(h, NCL_K_BERR_FINAL, a, l, st) != hipSuccess) return NCL_ERR_HIP;
     }
     return NCL_OK;
 }
@@ -1101,7 +1204,8 @@ const char *ncl_kernel_name(int kind) {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
         "k_sol_bpart", "k_sol_border", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
-        "k_residual", "k_max_step", "k_interleave", "k_border_panel", "k_border_update"};
+        "k_residual", "k_max_step", "k_interleave", "k_border_panel", "k_border_update", "k_berr_rows",
+        "k_berr_border", "k_berr_final"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }
 
@@ -1154,6 +1258,37 @@ int ncl_kkt_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_
 int ncl_kkt_solve_adjoint(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {
     // K = K^T: the transposed system uses the same factors and the same kernels
     return do_solve(k, db, dx, nrhs, ld, stream);
+}
+
+int ncl_kkt_backward_error(ncl_kkt *k, const double *db, const double *dx, int32_t nrhs, int64_t ld, double *derr,
+                           void *stream) {
+    if (!k || !db || !dx || !derr || nrhs < 1) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound || !h.values_set) return NCL_ERR_STATE;
+    if (ld < h.N) return NCL_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    for (int rhs = 0; rhs < nrhs; rhs++) {
+        const int rc = residual_column(h, a, db + int64_t(rhs) * ld, dx + int64_t(rhs) * ld, derr + 2 * rhs, st);
+        if (rc) return rc;
+    }
+    return NCL_OK;
+}
+
+int ncl_kkt_refine(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {
+    if (!k || !db || !dx || nrhs < 1) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound || !h.factored || h.factor_failed || !h.values_set) return NCL_ERR_STATE;
+    if (nrhs > h.nrhs_max || ld < h.N) return NCL_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    for (int rhs = 0; rhs < nrhs; rhs++) {
+        double *x = dx + int64_t(rhs) * ld;
+        int rc = residual_column(h, a, db + int64_t(rhs) * ld, x, nullptr, st);
+        if (!rc) rc = solve_column(h, a, nullptr, x, rhs, true, st);
+        if (rc) return rc;
+    }
+    return NCL_OK;
 }
 
 }  // extern "C"

@@ -23,8 +23,14 @@ struct DevArgs {
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
     double *upan;                  // U = L D on the off-diagonal panel rows (rows >= w), panel layout
     double *zint, *sint;        // interleaved copies of the state and Sigma (assembly input)
-    int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits
+    int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits, non-finite
     const uint8_t *bprim;       // [nbd_tot] expected sign of the border pivots
+    int64_t rows_waves;         // residual-row wavefronts of all templates
+    int64_t nprimal;            // expected positive pivots
+    int rows_wg;                // workgroups of the residual-row kernel
+    double *xint, *bint, *rint; // residual: x, b and r in the interleaved layout order
+    double *rbuf;               // residual in layout order (border part)
+    double *epart;              // partial maxima of the backward error, 8 per workgroup
 };
 
 // Arguments of one launch (only those the kernel kind uses are read).
@@ -35,6 +41,7 @@ constexpr int kBorderBlock = 32;
 // status words: 6 counters, each on a cache line of its own so that the
 // workgroups' atomics on different counters do not queue on one line
 constexpr int kStatStride = 16;
+constexpr int kStatWords = 8;
 constexpr int kBorderRegMax = 216;
 
 struct LaunchArgs {
@@ -49,9 +56,11 @@ struct LaunchArgs {
     const double *dz = nullptr;
     double tau = 0.0;
     double *alpha = nullptr;
-    const double *src = nullptr;                 // value conversion
-    double *dst = nullptr;
+    double *zdst = nullptr, *sdst = nullptr;     // interleave: destinations of z and sig
+    const double *src = nullptr;                 // value conversion; solve load: interleaved right-hand side
+    double *dst = nullptr;                       // value conversion; backward error: (eta, omega)
     bool to_internal = false;
+    bool accumulate = false;                     // solve store: x += solution
     const double *b = nullptr;                   // solve: right-hand side, solution, work vectors
     double *x = nullptr, *y = nullptr, *cpart = nullptr;
 };

@@ -273,7 +273,8 @@ constexpr int kTileRows = 256 / kTileJ;   // blocks read per pass in the first p
 static_assert(kTileB == 64 && 256 % kTileJ == 0 && kTileR * 4 == kTileJ, "tile shape");
 
 __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__restrict__ z,
-                                                    const double *__restrict__ sig) {
+                                                    const double *__restrict__ sig, double *__restrict__ zd,
+                                                    double *__restrict__ sd) {
     __shared__ double tile[kTileB][kTileJ + 1];
     const int64_t t = blockIdx.x;
     if (t >= a.tiles) {
@@ -282,8 +283,8 @@ __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__r
         if (i < a.nbd_tot) {
             const InstDev &I = a.insts[find_inst(a, i, &InstDev::bd0)];
             const int64_t col = I.bstart + (i - I.bd0);
-            a.zint[a.dint + i] = z[col];
-            a.sint[a.dint + i] = sig[col];
+            zd[a.dint + i] = z[col];
+            sd[a.dint + i] = sig[col];
         }
         return;
     }
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(256) void k_interleave(DevArgs a, const double *__r
         vs[q] = ok ? sig[src] : 0.0;
     }
     for (int pass = 0; pass < 2; pass++) {
-        double *dst = pass ? a.sint : a.zint;
+        double *dst = pass ? sd : zd;
 #pragma unroll
         for (int q = 0; q < kTileR; q++) tile[rb + kTileRows * q][cj] = pass ? vs[q] : vz[q];
         __syncthreads();
@@ -1187,6 +1188,8 @@ __global__ __launch_bounds__(64) void k_status_init(DevArgs a) {
         a.stat[3 * kStatStride] = INT64_MAX;
         a.stat[4 * kStatStride] = INT64_MAX;
         a.stat[5 * kStatStride] = 0;
+        a.stat[6 * kStatStride] = 0;
+        a.stat[7 * kStatStride] = 0;
     }
 }
 
@@ -1204,7 +1207,7 @@ __device__ inline int pivot_code(double d, bool primal) {
 constexpr int kStatusChunk = 1024;
 
 __global__ __launch_bounds__(256) void k_status(DevArgs a) {
-    int64_t np = 0, nn = 0, nz = 0, bad = INT64_MAX, mn = INT64_MAX, mx = 0;
+    int64_t np = 0, nn = 0, nz = 0, nf = 0, bad = INT64_MAX, mn = INT64_MAX, mx = 0;
     const int64_t total = a.dint + a.nbd_tot;
     const int64_t c0 = (int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6))) * kStatusChunk;
     const int lane = lane_id();
@@ -1243,6 +1246,7 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
             if (d > 0) np++;
             else nn++;
         } else if (code == 2) nz++;
+        else if (code == 3) nf++;
         if (code) {
             int64_t col;
             if (idx < a.dint) {
@@ -1267,15 +1271,17 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
         np += __shfl_xor(np, o);
         nn += __shfl_xor(nn, o);
         nz += __shfl_xor(nz, o);
+        nf += __shfl_xor(nf, o);
         const int64_t ob = __shfl_xor(bad, o), om = __shfl_xor(mn, o), ox = __shfl_xor(mx, o);
         bad = ob < bad ? ob : bad;
         mn = om < mn ? om : mn;
         mx = ox > mx ? ox : mx;
     }
-    __shared__ int64_t red[6][4];
+    __shared__ int64_t red[7][4];
     const int wv = threadIdx.x >> 6;
     if (lane_id() == 0) {
         red[0][wv] = np; red[1][wv] = nn; red[2][wv] = nz; red[3][wv] = bad; red[4][wv] = mn; red[5][wv] = mx;
+        red[6][wv] = nf;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1283,6 +1289,7 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
             red[0][0] += red[0][q];
             red[1][0] += red[1][q];
             red[2][0] += red[2][q];
+            red[6][0] += red[6][q];
             red[3][0] = red[3][q] < red[3][0] ? red[3][q] : red[3][0];
             red[4][0] = red[4][q] < red[4][0] ? red[4][q] : red[4][0];
             red[5][0] = red[5][q] > red[5][0] ? red[5][q] : red[5][0];
@@ -1296,7 +1303,14 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
         if (red[4][0] != INT64_MAX)
             atomicMin(reinterpret_cast<long long *>(a.stat + 4 * kStatStride), (long long)red[4][0]);
         if (red[5][0]) atomicMax(reinterpret_cast<long long *>(a.stat + 5 * kStatStride), (long long)red[5][0]);
+        if (red[6][0]) atomicAdd(u + 6 * kStatStride, (unsigned long long)red[6][0]);
     }
+}
+
+// Whether the last factorisation may be solved with: no zero or non-finite
+// pivot and the inertia (n, m) (read from the status words k_status left).
+__device__ inline bool factor_usable(const DevArgs &a) {
+    return a.stat[2 * kStatStride] == 0 && a.stat[6 * kStatStride] == 0 && a.stat[0 * kStatStride] == a.nprimal;
 }
 
 // ------------------------------------------------------------------ solve
@@ -1305,10 +1319,13 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
 // caller's order (block by block, layout-local columns) and the factor's
 // interleaved order are transposed through the LDS tiles of k_interleave,
 // so that both the reads and the writes are coalesced.
+// A factorisation that may not be solved with (see factor_usable) makes
+// the solve write NaN: the caller who never read the status still sees it.
 __global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__restrict__ b, double *__restrict__ y) {
     __shared__ double tile[kTileB][kTileJ + 1];
     const TileIx x = tile_index(a, blockIdx.x);
     const TemplDev &T = *x.T;
+    const bool ok = factor_usable(a);
     const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
     const int cb = threadIdx.x & 63, rj = threadIdx.x >> 6;
 #pragma unroll
@@ -1320,10 +1337,24 @@ __global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__res
 #pragma unroll
     for (int q = 0; q < kTileR; q++) {
         const int j = x.j0 + rj + 4 * q, bl = x.b0 + cb;
-        if (bl < T.nblk && j < T.n) y[T.dbase + int64_t(T.iperm[j]) * T.nblk + bl] = tile[cb][rj + 4 * q];
+        if (bl < T.nblk && j < T.n)
+            y[T.dbase + int64_t(T.iperm[j]) * T.nblk + bl] = ok ? tile[cb][rj + 4 * q] : __builtin_nan("");
     }
 }
 
+// The same from a right-hand side already interleaved in layout order (the
+// residual of a refinement step): a permutation inside each template, one
+// element per thread, reads and writes along the blocks.
+__global__ __launch_bounds__(256) void k_sol_load_int(DevArgs a, const double *__restrict__ r, double *__restrict__ y) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= a.dint) return;
+    const TemplDev &T = a.tmpls[find_tmpl(a, idx, &TemplDev::dbase)];
+    const int64_t off = idx - T.dbase;
+    const int j = int(off / T.nblk), bl = int(off - int64_t(j) * T.nblk);
+    y[T.dbase + int64_t(T.iperm[j]) * T.nblk + bl] = factor_usable(a) ? r[idx] : __builtin_nan("");
+}
+
+template <bool kAdd>
 __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__restrict__ y, double *__restrict__ xo) {
     __shared__ double tile[kTileB][kTileJ + 1];
     const TileIx x = tile_index(a, blockIdx.x);
@@ -1339,7 +1370,10 @@ __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__re
 #pragma unroll
     for (int q = 0; q < kTileR; q++) {
         const int bl = x.b0 + rb + kTileRows * q, j = x.j0 + cj;
-        if (bl < T.nblk && j < T.n) xo[a.blks[T.blocks[bl]].col0 + j] = tile[rb + kTileRows * q][cj];
+        if (bl < T.nblk && j < T.n) {
+            const int64_t c = a.blks[T.blocks[bl]].col0 + j;
+            xo[c] = kAdd ? xo[c] + tile[rb + kTileRows * q][cj] : tile[rb + kTileRows * q][cj];
+        }
     }
 }
 
@@ -1440,7 +1474,7 @@ __device__ inline double lane_bcast(double v, int k) {
 // each instance whose factor fits the LDS the launch provides.
 template <bool kRes>
 __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c, const double *__restrict__ b,
-                                  double *x, double *y, const double *__restrict__ cpart) {
+                                  double *x, double *y, const double *__restrict__ cpart, bool add) {
     const int nbd = I.nbd, nblk = I.nblk, tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const double *Db = a.dval + a.dint + I.bd0;
     const double *Lg = a.sbb + I.sbb0;
@@ -1543,18 +1577,18 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
     }
     for (int i = tid; i < nbd; i += kBorderThreads) {
         y[a.dint + I.bd0 + i] = c[i];
-        x[I.bstart + i] = c[i];
+        x[I.bstart + i] = add ? x[I.bstart + i] + c[i] : c[i];
     }
 }
 
 __global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const double *__restrict__ b, double *x,
                                                                double *y, const double *__restrict__ cpart,
-                                                               int64_t lds_bytes) {
+                                                               int64_t lds_bytes, int add) {
     extern __shared__ double c[];
     const InstDev &I = a.insts[blockIdx.x];
     const int64_t need = (int64_t(a.max_nbd) + int64_t(I.nbd) * (I.nbd + 1) / 2) * int64_t(sizeof(double));
-    if (need <= lds_bytes) sol_border<true>(a, I, c, b, x, y, cpart);
-    else sol_border<false>(a, I, c, b, x, y, cpart);
+    if (need <= lds_bytes) sol_border<true>(a, I, c, b, x, y, cpart, add != 0);
+    else sol_border<false>(a, I, c, b, x, y, cpart, add != 0);
 }
 
 // backward gather of column p of a supernode: y_col = y_col / d_col - sum_{i >= w} L(i, p) x_{row i},
@@ -1649,6 +1683,165 @@ __global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, cons
                 if (j < w - 1) st32(y0, yi(j), x[j]);
         }
     });
+}
+
+// ------------------------------------------------------------------ backward error
+
+// Residual r = b - K x of one column and the quantities of its backward
+// errors: |r_i|, |r_i| / (|K||x| + |b|)_i, the row norm sum_j |K_ij|, |x_i|
+// and |b_i|.  Each workgroup leaves their maxima (non-negative, so order
+// does not matter; a NaN propagates) in epart[8 * workgroup + q]; the final
+// kernel reduces them.  x and b come interleaved (k_interleave into xint,
+// bint); r goes to rint (blocks) and rbuf (border, layout order), where a
+// refinement step's solve picks it up.
+enum { BE_R, BE_Q, BE_ROWN, BE_X, BE_B, BE_N };
+constexpr int kFinalThreads = 1024;
+
+__device__ inline double nanmax(double p, double q) { return (p > q || p != p) ? p : q; }
+
+__device__ inline void berr_commit(const DevArgs &a, int64_t slot, double v[BE_N]) {
+#pragma unroll
+    for (int q = 0; q < BE_N; q++)
+        for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o));
+    __shared__ double red[4][BE_N];
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        for (int q = 0; q < BE_N; q++) red[wv][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < BE_N) {
+        const int q = threadIdx.x;
+        a.epart[8 * slot + q] = nanmax(nanmax(red[0][q], red[1][q]), nanmax(red[2][q], red[3][q]));
+    }
+}
+
+__device__ inline double ratio(double r, double den) { return den > 0.0 ? r / den : (r > 0.0 ? INFINITY : r); }
+
+// one wavefront per (template row, group of 64 blocks), lane = block
+__global__ __launch_bounds__(256) void k_berr_rows(DevArgs a) {
+    const int64_t w = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    double v[BE_N] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (w < a.rows_waves) {
+        const TemplDev &T = a.tmpls[find_tmpl(a, w, &TemplDev::rwbase)];
+        const int ngr = (T.nblk + 63) >> 6;
+        const int64_t wl = w - T.rwbase;
+        const int j = int(wl / ngr), g = int(wl - int64_t(j) * ngr);
+        const int b = g * 64 + lane_id();
+        const bool on = b < T.nblk;
+        const uint32_t bl = on ? uint32_t(b) : 0u, nb = uint32_t(T.nblk);
+        const double *xb = a.xint + T.dbase, *Kb = a.kval + T.kbase;
+        const double *xbd = a.xint + a.dint + T.bd0;
+        const int n = T.n;
+        double s0 = 0.0, s1 = 0.0, d0 = 0.0, d1 = 0.0, rn = 0.0;
+        const int e1 = cs(T.rr_ptr)[j + 1];
+        int e = cs(T.rr_ptr)[j];
+        for (; e + 2 <= e1; e += 2) {
+            const int k0 = cs(T.rr_ent)[2 * e], c0 = cs(T.rr_ent)[2 * e + 1];
+            const int k1 = cs(T.rr_ent)[2 * e + 2], c1 = cs(T.rr_ent)[2 * e + 3];
+            const double v0 = ld32(Kb, uint32_t(k0) * nb + bl), v1 = ld32(Kb, uint32_t(k1) * nb + bl);
+            const double x0 = c0 < n ? ld32(xb, uint32_t(c0) * nb + bl) : xbd[c0 - n];
+            const double x1 = c1 < n ? ld32(xb, uint32_t(c1) * nb + bl) : xbd[c1 - n];
+            s0 += v0 * x0;
+            s1 += v1 * x1;
+            d0 += fabs(v0) * fabs(x0);
+            d1 += fabs(v1) * fabs(x1);
+            rn += fabs(v0) + fabs(v1);
+        }
+        if (e < e1) {
+            const int k0 = cs(T.rr_ent)[2 * e], c0 = cs(T.rr_ent)[2 * e + 1];
+            const double v0 = ld32(Kb, uint32_t(k0) * nb + bl);
+            const double x0 = c0 < n ? ld32(xb, uint32_t(c0) * nb + bl) : xbd[c0 - n];
+            s0 += v0 * x0;
+            d0 += fabs(v0) * fabs(x0);
+            rn += fabs(v0);
+        }
+        const uint32_t o = uint32_t(j) * nb + bl;
+        const double bv = ld32(a.bint + T.dbase, o), xj = ld32(xb, o);
+        const double r = bv - (s0 + s1);
+        if (on) {
+            st32(a.rint + T.dbase, o, r);
+            v[BE_R] = fabs(r);
+            v[BE_Q] = ratio(fabs(r), (d0 + d1) + fabs(bv));
+            v[BE_ROWN] = rn;
+            v[BE_X] = fabs(xj);
+            v[BE_B] = fabs(bv);
+        }
+    }
+    berr_commit(a, blockIdx.x, v);
+}
+
+// one wavefront per border row of every instance: the blocks' entries of
+// the row (lane = block, templates and groups in order), then K_bb's (lanes
+// strided), summed by a fixed shuffle tree
+__global__ __launch_bounds__(256) void k_berr_border(DevArgs a) {
+    const int64_t q = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    double v[BE_N] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (q < a.nbd_tot) {
+        const InstDev &I = a.insts[find_inst(a, q, &InstDev::bd0)];
+        const int bi = int(q - I.bd0), lane = lane_id();
+        double s = 0.0, den = 0.0, rn = 0.0;
+        for (int ti = I.t0; ti < I.t0 + I.nt; ti++) {
+            const TemplDev &T = a.tmpls[ti];
+            const int e0 = cs(T.rb_ptr)[bi], e1 = cs(T.rb_ptr)[bi + 1];
+            for (int g0 = 0; g0 < T.nblk; g0 += 64) {
+                const int b = g0 + lane;
+                if (b >= T.nblk) continue;
+                for (int e = e0; e < e1; e++) {
+                    const int kp = cs(T.rb_ent)[2 * e], c = cs(T.rb_ent)[2 * e + 1];
+                    const double kv = a.kval[T.kbase + int64_t(kp) * T.nblk + b];
+                    const double xv = a.xint[T.dbase + int64_t(c) * T.nblk + b];
+                    s += kv * xv;
+                    den += fabs(kv) * fabs(xv);
+                    rn += fabs(kv);
+                }
+            }
+        }
+        const double *xbd = a.xint + a.dint + I.bd0;
+        for (int e = I.kbr_ptr[bi] + lane; e < I.kbr_ptr[bi + 1]; e += 64) {
+            const double kv = a.kval[a.kint + I.kbb0 + I.kbr_ent[2 * e]];
+            const double xv = xbd[I.kbr_ent[2 * e + 1]];
+            s += kv * xv;
+            den += fabs(kv) * fabs(xv);
+            rn += fabs(kv);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            s += __shfl_xor(s, o);
+            den += __shfl_xor(den, o);
+            rn += __shfl_xor(rn, o);
+        }
+        const double bv = a.bint[a.dint + I.bd0 + bi], xv = xbd[bi];
+        const double r = bv - s;
+        if (lane == 0) a.rbuf[I.bstart + bi] = r;
+        v[BE_R] = fabs(r);
+        v[BE_Q] = ratio(fabs(r), den + fabs(bv));
+        v[BE_ROWN] = rn;
+        v[BE_X] = fabs(xv);
+        v[BE_B] = fabs(bv);
+    }
+    berr_commit(a, a.rows_wg + blockIdx.x, v);
+}
+
+// eta = max|r| / (max_i sum_j |K_ij| * max|x| + max|b|), omega = max ratio
+__global__ __launch_bounds__(kFinalThreads) void k_berr_final(DevArgs a, double *out) {
+    const int np = a.rows_wg + int((a.nbd_tot + 3) / 4);
+    double v[BE_N] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < np; i += kFinalThreads)
+#pragma unroll
+        for (int q = 0; q < BE_N; q++) v[q] = nanmax(v[q], a.epart[8 * int64_t(i) + q]);
+#pragma unroll
+    for (int q = 0; q < BE_N; q++)
+        for (int o = 32; o > 0; o >>= 1) v[q] = nanmax(v[q], __shfl_xor(v[q], o));
+    __shared__ double red[kFinalThreads / 64][BE_N];
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        for (int q = 0; q < BE_N; q++) red[wv][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kFinalThreads / 64; w++)
+            for (int q = 0; q < BE_N; q++) red[0][q] = nanmax(red[0][q], red[w][q]);
+        const double den = red[0][BE_ROWN] * red[0][BE_X] + red[0][BE_B];
+        out[0] = ratio(red[0][BE_R], den);
+        out[1] = red[0][BE_Q];
+    }
 }
 
 // ------------------------------------------------------------------ dispatch map
@@ -1946,7 +2139,10 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             break;
         }
         case NCL_K_SOL_LOAD:
-            if (a.dint) hipLaunchKernelGGL(k_sol_load, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.b, l.y);
+            if (a.dint && l.src)
+                hipLaunchKernelGGL(k_sol_load_int, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.src, l.y);
+            else if (a.dint)
+                hipLaunchKernelGGL(k_sol_load, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.b, l.y);
             break;
         case NCL_K_SOL_FWD_GATHER:
             if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_fwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
@@ -1974,7 +2170,7 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                     if (e != hipSuccess) return e;
                 }
                 hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), lb, st, a, l.b, l.x, l.y, l.cpart,
-                                   int64_t(lb));
+                                   int64_t(lb), l.accumulate ? 1 : 0);
             }
             break;
         case NCL_K_SOL_BWD_GATHER:
@@ -1985,7 +2181,21 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (l.nw) hipLaunchKernelGGL(k_sol_bwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
             break;
         case NCL_K_SOL_STORE:
-            if (a.dint) hipLaunchKernelGGL(k_sol_store, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.y, l.x);
+            if (a.dint && l.accumulate)
+                hipLaunchKernelGGL(k_sol_store<true>, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.y, l.x);
+            else if (a.dint)
+                hipLaunchKernelGGL(k_sol_store<false>, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.y, l.x);
+            break;
+        case NCL_K_BERR_ROWS:
+            if (a.rows_waves)
+                hipLaunchKernelGGL(k_berr_rows, dim3(unsigned(a.rows_wg)), dim3(256), 0, st, a);
+            break;
+        case NCL_K_BERR_BORDER:
+            if (a.nbd_tot)
+                hipLaunchKernelGGL(k_berr_border, dim3(unsigned((a.nbd_tot + 3) / 4)), dim3(256), 0, st, a);
+            break;
+        case NCL_K_BERR_FINAL:
+            hipLaunchKernelGGL(k_berr_final, dim3(1), dim3(kFinalThreads), 0, st, a, l.dst);
             break;
         case NCL_K_RESIDUAL: {
             const int64_t total = a.asm_threads + a.gp_tot;
@@ -1996,7 +2206,7 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
         }
         case NCL_K_INTERLEAVE: {
             const int64_t nt = a.tiles + (a.nbd_tot + 255) / 256;
-            if (nt) hipLaunchKernelGGL(k_interleave, dim3(unsigned(nt)), dim3(256), 0, st, a, l.z, l.sig);
+            if (nt) hipLaunchKernelGGL(k_interleave, dim3(unsigned(nt)), dim3(256), 0, st, a, l.z, l.sig, l.zdst, l.sdst);
             break;
         }
         case NCL_K_MAX_STEP:

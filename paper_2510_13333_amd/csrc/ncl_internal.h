@@ -136,6 +136,12 @@ struct TemplDev {
     const uint8_t *col_primal;     // [n] expected pivot sign (1: positive) in factor order
     const int32_t *bus_gen;        // [nb] generator at the bus or -1
     const uint8_t *lkind;          // [n] layout-local kind (LK_*), for the dispatch map
+    // residual rows (backward error and refinement)
+    const int32_t *rr_ptr;         // [n+1]
+    const int32_t *rr_ent;         // pairs (K value, column; n + b for border columns)
+    const int32_t *rb_ptr;         // [nbd+1]
+    const int32_t *rb_ent;         // pairs (K value, block column) of border row b
+    int64_t rwbase;                // first residual-row wavefront of the template
 };
 
 // Layout-local kinds used by the dispatch-map kernels (bounds and rows).
@@ -157,6 +163,9 @@ struct InstDev {
     const int32_t *kbb_pos;        // [nbd*nbd]
     const int32_t *border_pg;      // [ng]
     const double *gen_c2;          // [ng]
+    const int32_t *kbr_ptr;        // [nbd+1] full symmetric rows of K_bb
+    const int32_t *kbr_ent;        // pairs (K_bb value, border column)
+    int32_t t0, nt;                // the instance's templates
 };
 
 struct BlockDev {
@@ -198,6 +207,10 @@ struct Template {
     std::vector<STile> stiles;
     std::vector<std::vector<int32_t>> lev_tasks;   // row tasks of each level
     std::vector<Term> terms, bterms, sterms;
+    // residual rows: the full symmetric row j of the block (both triangles),
+    // as (K value, column) pairs; columns n + b are border columns; and per
+    // border row b the block's entries (K value, block column) of that row
+    std::vector<int32_t> rr_ptr, rr_ent, rb_ptr, rb_ent;
 };
 
 // Work lists of every launch (all templates together), per level.
@@ -242,6 +255,8 @@ struct Inst {
     std::vector<int64_t> bcolcount;
     std::vector<int32_t> blp, bli;
     std::vector<int32_t> bsup;
+    // full symmetric rows of K_bb: (value position, border column) pairs
+    std::vector<int32_t> kbr_ptr, kbr_ent;
     // offsets in the concatenated device border arrays
     int64_t kbb0 = 0, sbb0 = 0, bd0 = 0, sp0 = 0, cp0 = 0, npk0 = 0, gp0 = 0;
     int64_t nbb() const { return nbd ? bcolptr[nbd] : 0; }
@@ -267,7 +282,8 @@ struct Handle {
     int64_t asm_threads = 0;                // template residual threads (border pg threads follow)
     int64_t asm_wthreads = 0;               // template assembly threads, wavefront-aligned (border pg threads follow)
     int64_t tiles = 0;                      // transpose tiles of all templates
-    std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase, t_awbase, t_tile0;
+    int64_t rows_waves = 0;                 // residual-row wavefronts of all templates
+    std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase, t_awbase, t_tile0, t_rwbase;
     Schedule sched;
     // numeric state
     int64_t nrhs_max = 0;
@@ -276,11 +292,16 @@ struct Handle {
     bool factored = false;
     bool blocks_done = false;
     bool bound = false;
+    bool values_set = false;                // K values assembled or set since the bind
+    bool factor_failed = false;             // ncl_kkt_info saw a factor the solves may not use
     struct Dev {
         double *kval = nullptr;          // interleaved K, then the border K_bb values of every instance
         double *lpan = nullptr, *upan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
                *cpart = nullptr;
         double *zint = nullptr, *sint = nullptr;   // state and Sigma in the blocks' interleaved layout order
+        double *xint = nullptr, *bint = nullptr, *rint = nullptr;   // residual: x, b, r interleaved (one column)
+        double *rbuf = nullptr;          // residual in layout order (its border part feeds the border solve)
+        double *epart = nullptr;         // per-workgroup partial maxima of the backward error
         int64_t *stat = nullptr;
         TemplDev *tmpl = nullptr;
         BlockDev *blk = nullptr;

@@ -15,8 +15,47 @@
 
 namespace ncl {
 
+// Full symmetric rows of a template's K for the residual b - Kx: the lower
+// CSC entry (r, c) at position p counts in row r (times x_c) and, off the
+// diagonal, in row c (times x_r); a border row r = n + b collects the
+// block's entries of that row separately (its sum runs over the blocks).
+static void build_residual_rows(Template &t, int nbd) {
+    const int n = t.n;
+    std::vector<std::vector<int32_t>> rows(n), brows(nbd);
+    for (int c = 0; c < n; c++)
+        for (int64_t p = t.colptr[c]; p < t.colptr[c + 1]; p++) {
+            const int32_t r = t.rowind[p];
+            if (r < n) {
+                rows[r].push_back(int32_t(p));
+                rows[r].push_back(c);
+                if (r != c) {
+                    rows[c].push_back(int32_t(p));
+                    rows[c].push_back(r);
+                }
+            } else {
+                rows[c].push_back(int32_t(p));
+                rows[c].push_back(r);
+                brows[r - n].push_back(int32_t(p));
+                brows[r - n].push_back(c);
+            }
+        }
+    t.rr_ptr.assign(1, 0);
+    t.rr_ent.clear();
+    for (auto &r : rows) {
+        t.rr_ent.insert(t.rr_ent.end(), r.begin(), r.end());
+        t.rr_ptr.push_back(int32_t(t.rr_ent.size() / 2));
+    }
+    t.rb_ptr.assign(1, 0);
+    t.rb_ent.clear();
+    for (auto &r : brows) {
+        t.rb_ent.insert(t.rb_ent.end(), r.begin(), r.end());
+        t.rb_ptr.push_back(int32_t(t.rb_ent.size() / 2));
+    }
+}
+
 int build_template_schedule(Template &t, int nbd) {
     const int n = t.n;
+    build_residual_rows(t, nbd);
     const int ns = int(t.sup.size()) - 1;
     std::vector<int32_t> col2sup(n);
     for (int s = 0; s < ns; s++)
@@ -220,7 +259,8 @@ int build_schedule(Handle &h) {
     h.t_abase.assign(h.tmpl.size(), 0);
     h.t_awbase.assign(h.tmpl.size(), 0);
     h.t_tile0.assign(h.tmpl.size(), 0);
-    h.kint = h.lint = h.dint = h.asm_threads = h.asm_wthreads = h.tiles = 0;
+    h.t_rwbase.assign(h.tmpl.size(), 0);
+    h.kint = h.lint = h.dint = h.asm_threads = h.asm_wthreads = h.tiles = h.rows_waves = 0;
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];
         const int64_t nb = int64_t(t.blocks.size());
@@ -235,6 +275,8 @@ int build_schedule(Handle &h) {
         h.t_abase[ti] = h.asm_threads;
         h.t_awbase[ti] = h.asm_wthreads;
         h.t_tile0[ti] = h.tiles;
+        h.t_rwbase[ti] = h.rows_waves;
+        h.rows_waves += int64_t(t.n) * ((nb + 63) / 64);
         h.tiles += int64_t((t.n + kTileJ - 1) / kTileJ) * ((nb + kTileB - 1) / kTileB);
         h.kint += t.colptr[t.n] * nb;
         h.lint += int64_t(t.panel_off.back()) * nb;

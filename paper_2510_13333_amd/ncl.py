@@ -22,7 +22,7 @@ NCL_PVPQ = 1
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
            "border_factor", "status_init", "status", "sol_load", "sol_fwd_gather", "sol_fwd_diag", "sol_bpart",
            "sol_border", "sol_bwd_gather", "sol_bwd_diag", "sol_store", "residual", "max_step", "interleave",
-           "border_panel", "border_update"]
+           "border_panel", "border_update", "berr_rows", "berr_border", "berr_final"]
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
           -4: "call out of order", -5: "zero pivot", -6: "pivot of the wrong sign (inertia)",
@@ -68,7 +68,7 @@ class _Nlp(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("npos", ctypes.c_int64), ("nneg", ctypes.c_int64), ("nzero", ctypes.c_int64),
                 ("first_bad", ctypes.c_int64), ("min_absd", ctypes.c_double), ("max_absd", ctypes.c_double),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("solvable", ctypes.c_int32), ("nnonfinite", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -109,6 +109,8 @@ def load():
         "ncl_kkt_get_factors": ([P, P, P, P], ctypes.c_int),
         "ncl_kkt_solve": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_solve_adjoint": ([P, P, P, i32, i64, P], ctypes.c_int),
+        "ncl_kkt_backward_error": ([P, P, P, i32, i64, P, P], ctypes.c_int),
+        "ncl_kkt_refine": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_destroy": ([P], None),
         "ncl_kernel_name": ([ctypes.c_int], ctypes.c_char_p),
         "ncl_kkt_kernel_model": ([P, i32, P, P], ctypes.c_int),
@@ -327,6 +329,31 @@ class KKT:
 
     def solve_adjoint(self, b, out=None):
         return self._solve("ncl_kkt_solve_adjoint", b, out)
+
+    def backward_error(self, b, x, out=None):
+        """(eta, omega) per column, on the device (no synchronisation): a
+        (nrhs, 2) float64 tensor, or written into ``out``."""
+        import torch
+        b2 = b if b.dim() == 2 else b.reshape(1, -1)
+        x2 = x if x.dim() == 2 else x.reshape(1, -1)
+        if b2.shape != x2.shape:
+            raise ValueError("b and x differ in shape")
+        if out is None:
+            out = torch.empty((b2.shape[0], 2), dtype=torch.float64, device=b.device)
+        _check("ncl_kkt_backward_error", load().ncl_kkt_backward_error(
+            self._h, self._dev(b2), self._dev(x2), int(b2.shape[0]), int(b2.shape[1]), self._dev(out, 2 * b2.shape[0]),
+            _stream_ptr()))
+        return out
+
+    def refine(self, b, x):
+        """One step of iterative refinement of x (in place) on the stored factors."""
+        b2 = b if b.dim() == 2 else b.reshape(1, -1)
+        x2 = x if x.dim() == 2 else x.reshape(1, -1)
+        if b2.shape != x2.shape:
+            raise ValueError("b and x differ in shape")
+        _check("ncl_kkt_refine", load().ncl_kkt_refine(self._h, self._dev(b2), self._dev(x2), int(b2.shape[0]),
+                                                      int(b2.shape[1]), _stream_ptr()))
+        return x
 
     # ------------------------------------------------------------ dispatch map
     def layout_kinds(self):

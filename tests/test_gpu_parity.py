@@ -42,8 +42,8 @@ def check_assembly(kv, cp, ri, v):
     assert bad.size == 0, f"{bad.size} entries off, first at {bad[:5]}: {kv[bad[:5]]} vs {v[bad[:5]]}"
 
 
-def run_case(net, cfg, nrhs=1, iteration=0, factors=True, k=None):
-    z, s = G.draw_point(net, cfg, iteration=iteration)
+def run_case(net, cfg, nrhs=1, iteration=0, factors=True, k=None, state=None):
+    z, s = G.draw_point(net, cfg, iteration=iteration) if state is None else state
     if k is None:
         k = KKT(net).bind(nrhs_max=nrhs)
     k.assemble(dev(z), dev(s), net.rho)
@@ -93,6 +93,34 @@ def test_c2_refactor_same_pattern():
 
 def test_c3_full_size():
     run_case(G.config_network(3), 3, factors=False)
+
+
+def test_c3_trajectory_states_four_rhs():
+    """500-bus x 256 with PV/PQ rows at trajectory states 0, 24 and 49 (the
+    last), four right-hand sides each; the factors compared at state 49."""
+    net = G.config_network(3)
+    z0, s0 = G.draw_point(net, 3)
+    k = None
+    for it in (0, 24, 49):
+        st = G.draw_trajectory_point(net, 3, it, z0, s0)
+        k, _ = run_case(net, 3, nrhs=4, iteration=it, factors=(it == 49), k=k, state=st)
+
+
+def test_border_over_216_factors():
+    """A 230-generator border takes the blocked border factor (panel and
+    trailing-update launches) and the border solve from global memory."""
+    net = G.make_network(31, 1300, 1820, 230, 3, rho=1e4)
+    k, _ = run_case(net, 31, nrhs=2)
+    assert k.instances[0]["nbd"] == 230
+
+
+def test_c5_shift_on_factors():
+    run_case(G.config_network(5), 5, factors=True)
+
+
+def test_uniform_topology():
+    net = G.make_network(32, 300, 420, 54, 12, pvpq=True, rho=1e5, topology="uniform")
+    run_case(net, 32, nrhs=2)
 
 
 def test_determinism_and_adjoint():
