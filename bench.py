@@ -93,49 +93,113 @@ def dominant_kernel(k, step):
     return max(per, key=per.get), per
 
 
-def roofline(k, kind, n_launch, ms_total, cfg):
+PHASE_OF = {"interleave": "assemble", "assemble": "assemble", "sol_load": "solve", "sol_fwd_gather": "solve",
+            "sol_fwd_diag": "solve", "sol_bpart": "solve", "sol_border": "solve", "sol_bwd_gather": "solve",
+            "sol_bwd_diag": "solve", "sol_store": "solve", "berr_rows": "gate", "berr_border": "gate",
+            "berr_final": "gate"}
+
+
+def phase_of(kind):
+    from paper_2510_13333_amd.ncl import KERNELS
+    return PHASE_OF.get(KERNELS[kind], "factor")
+
+
+def phase_bytes(k, nrhs):
+    """Algorithmic HBM bytes per step of each phase, as the method must move
+    them (every value read or written once; index arrays not counted):
+    assembly writes K's lower triangle and reads the state z and Sigma;
+    the factorisation reads K and writes L and D; a solve reads L twice
+    (forward and backward), D once, and reads b and writes x per
+    right-hand side."""
+    return {"assemble": 8 * k.nnzK + 16 * k.N,
+            "factor": 8 * (k.nnzK + k.nnzL + k.N),
+            "solve": 16 * k.nnzL + 8 * k.N + 16 * k.N * nrhs}
+
+
+def roofline(k, kind, n_launch, ms_total, pbytes):
+    """Roofline of one kernel kind: its phase's algorithmic bytes per step
+    spread over the kind's launches per step, over the mean event-timed
+    launch; the library's own per-launch byte model beside it."""
     launches, model_bytes = k.kernel_model(kind)
-    per_launch_bytes = model_bytes / launches
+    phase = phase_of(kind)
+    per_launch_bytes = pbytes[phase] / launches
     t_launch = ms_total / n_launch * 1e-3
     achieved = per_launch_bytes / t_launch / 1e9
     name = k.kernel_name(kind)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name, cfg), "kernel": name,
-            "algorithmic_bytes_per_launch": per_launch_bytes, "launches_per_step": launches,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(name, k.cfg), "kernel": name,
+            "phase": phase, "algorithmic_bytes_per_launch": per_launch_bytes,
+            "implementation_bytes_per_launch": model_bytes / launches, "launches_per_step": launches,
             "avg_launch_us": t_launch * 1e6, "launches_timed": n_launch, "timed_every": PROFILE_STRIDE}
 
 
-def copy_calibration():
-    """A plain copy of known size, for scaling the HBM counters of a profiled run."""
+def copy_peak(reps=10):
+    """Bandwidth of the library's plain streaming copy over COPY_DOUBLES
+    doubles (read + write), median of reps event-timed copies; its counters
+    also calibrate FETCH_SIZE and WRITE_SIZE in the profiled runs."""
     import torch
-    src = torch.empty(COPY_DOUBLES, dtype=torch.float64, device="cuda")
+    from paper_2510_13333_amd.ncl import stream_copy
+    src = torch.ones(COPY_DOUBLES, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    stream_copy(src, dst)
     torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        stream_copy(src, dst)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 16.0 * COPY_DOUBLES / float(np.median(ts)) / 1e9
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = min(avail, int(omp)) if omp and omp.isdigit() and int(omp) > 0 else avail
+    return model, os.cpu_count(), threads
 
 
 def cpu_baseline(nets, cfg, steps, batched=False):
-    """The oracle timed on the host: numpy assembly, C LDL^T and solve per
-    network and step (its symbolic analysis done once, untimed)."""
+    """The oracle timed on the host: C left-looking LDL^T and solve of one
+    right-hand side per network and step, single-threaded and with OpenMP
+    over the blocks on every available core.  Its K values (numpy
+    assembly) and symbolic analysis are prepared untimed, as the GPU's
+    factor+solve rate excludes assembly too."""
     import gridgen as G
     import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
-    facs = []
-    for i, net in enumerate(nets):
-        z, s = G.draw_point(net, cfg, instance=i if batched else 0)
-        cp, ri, v, pos = O.kkt(net, z, s)
-        facs.append(O.Factor(pos.N, cp, ri, np.array(pos.block_off)))
-    t0 = time.perf_counter()
-    done = 0
+    model, ncpu, threads = cpu_info()
+    work = []
     for it in range(steps):
         for i, net in enumerate(nets):
             z, s = G.draw_point(net, cfg, instance=i if batched else 0, iteration=it)
             cp, ri, v, pos = O.kkt(net, z, s)
-            facs[i].factor(cp, ri, v, nthreads=threads)
-            facs[i].solve(G.draw_rhs(pos.N, 1, cfg, iteration=it)[0])
-            done += 1
-    tc = time.perf_counter() - t0
-    return done / tc, threads
+            work.append((i, cp, ri, v, G.draw_rhs(pos.N, 1, cfg, iteration=it)[0], np.array(pos.block_off)))
+    facs = {}
+    for i, cp, ri, v, b, boff in work:
+        if i not in facs:
+            facs[i] = O.Factor(len(b), cp, ri, boff)
+    rates = {}
+    for nt in (1, threads):
+        if nt in rates:
+            continue
+        t0 = time.perf_counter()
+        for i, cp, ri, v, b, _ in work:
+            facs[i].factor(cp, ri, v, nthreads=nt)
+            facs[i].solve(b)
+        rates[nt] = len(work) / (time.perf_counter() - t0)
+    return rates, threads, model, ncpu
 
 
 def run_single(args):
@@ -147,6 +211,7 @@ def run_single(args):
     net = G.config_network(cfg)
     t0 = time.perf_counter()
     k = KKT(net)
+    k.cfg = cfg
     t_analyze = time.perf_counter() - t0
     nrhs = args.nrhs
     k.bind(nrhs_max=nrhs)
@@ -163,7 +228,11 @@ def run_single(args):
     print(f"[bench] config {cfg}: N={k.N} nnzK={k.nnzK} nnzL={k.nnzL} supernodes={k.nsuper} "
           f"analyze={t_analyze:.3f}s states={nst}", file=sys.stderr, flush=True)
 
-    def step(i=0, ev=None):
+    # gate[i] = (eta, omega) of each right-hand side of step i, computed on
+    # the device after the solve (no host synchronisation in the loop)
+    gate = torch.full((args.steps, nrhs, 2), float("nan"), dtype=torch.float64, device="cuda")
+
+    def step(i=0, ev=None, g=None):
         z, s, b = states[i % nst]
         if ev is not None:
             ev[0].record()
@@ -171,75 +240,97 @@ def run_single(args):
         if ev is not None:
             ev[1].record()
         k.factor_blocks()
-        if ev is not None:
-            ev[2].record()
         k.factor_border()
         if ev is not None:
-            ev[3].record()
+            ev[2].record()
         k.solve(b, out=x)
         if ev is not None:
-            ev[4].record()
+            ev[3].record()
+        if g is not None:
+            k.backward_error(b, x, out=g)
+            if ev is not None:
+                ev[4].record()
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    info = k.info()
     dom, per_kind = dominant_kernel(k, step)
-    # timed region: wall clock over exactly `steps` steps; meanwhile every
-    # PROFILE_STRIDE-th launch of the dominant kernel is bracketed by events
-    # on its stream (a stride coprime with the launches per step samples
-    # every level evenly and keeps the event records few)
+    # timed region: wall clock over exactly `steps` steps, each bracketed
+    # per phase by events and checked by the device's backward-error gate;
+    # meanwhile every PROFILE_STRIDE-th launch of the dominant kernel is
+    # bracketed by events on its stream (a stride coprime with the launches
+    # per step samples every level evenly)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     k.profile(dom)
     k.profile_stride(PROFILE_STRIDE)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(args.warmup + i)
+        step(args.warmup + i, evs[i], gate[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n_dom, ms_dom = k.profile_read()
     k.profile(-1)
-    roof = roofline(k, dom, n_dom, ms_dom, cfg)
-    print(f"[bench] timed {args.steps} steps: {wall / args.steps * 1e3:.3f} ms/step; dominant "
-          f"{roof['kernel']} {roof['avg_launch_us']:.1f} us/launch x {roof['launches_per_step']} per step "
-          f"({n_dom} launches sampled)", file=sys.stderr,
-          flush=True)
-    # phase timing with events (separate pass over the same steps)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    for i in range(args.steps):
-        step(args.warmup + i, evs[i])
-    torch.cuda.synchronize()
-    ph = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(4)] for e in evs]).mean(axis=0) * 1e-3
-    t_asm, t_fblk, t_fbrd, t_sol = (float(v) for v in ph)
-    copy_calibration()
+    info = k.info()
+    ph = np.array([[e[j].elapsed_time(e[j + 1]) * 1e-3 for j in range(4)] for e in evs])
+    t_asm, t_fac, t_sol, t_gate = (np.median(ph[:, j]) for j in range(4))
+    t_fs = np.median(ph[:, 1] + ph[:, 2])
+    g = gate.cpu().numpy()
+    eta_max, omega_max = float(np.max(g[..., 0])), float(np.max(g[..., 1]))
+    passed = int(np.sum(np.all(g[..., 0] <= 1e-12, axis=1)))
+    pb = phase_bytes(k, nrhs)
+    roof = roofline(k, dom, n_dom, ms_dom, pb)
+    print(f"[bench] timed {args.steps} steps: {wall / args.steps * 1e3:.3f} ms/step wall; factor+solve median "
+          f"{t_fs * 1e3:.3f} ms; gate eta<=1e-12 on {passed}/{args.steps} (max eta {eta_max:.2e}, omega "
+          f"{omega_max:.2e}); dominant {roof['kernel']} {roof['avg_launch_us']:.1f} us/launch x "
+          f"{roof['launches_per_step']}", file=sys.stderr, flush=True)
 
-    eta = None
+    # one refinement step on the last state: its cost and the componentwise error after it
+    z, s, b = states[(args.warmup + args.steps - 1) % nst]
+    step(args.warmup + args.steps - 1)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    e[0].record()
+    k.refine(b, x)
+    e[1].record()
+    gr = k.backward_error(b, x).cpu().numpy()
+    t_ref = e[0].elapsed_time(e[1]) * 1e-3
+
+    peak_copy = copy_peak()
+    phases = {}
+    for name, t in (("assemble", t_asm), ("factor", t_fac), ("solve", t_sol)):
+        gbs = pb[name] / t / 1e9
+        phases[name] = {"ms": t * 1e3, "algorithmic_MB": pb[name] / 1e6, "GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                        "frac_copy": gbs / peak_copy}
+
+    eta_or = None
     if not args.no_check:
         import oracle as O
         etas = []
-        for it in sorted({args.warmup % nst, (args.warmup + args.steps - 1) % nst}):
+        picks = sorted({args.warmup % nst, (args.warmup + args.steps // 2) % nst, (args.warmup + args.steps - 1) % nst})
+        for it in picks:
             z, s, b = states[it]
-            k.assemble(z, s, net.rho)
-            k.factor()
-            xs = k.solve(b).cpu().numpy()
+            step(it)
+            xs = x.cpu().numpy()
             cp, ri, v, _ = O.kkt(net, z.cpu().numpy(), s.cpu().numpy())
             etas.append(O.backward_error(cp, ri, v, xs, b.cpu().numpy()))
-        eta = float(max(etas))
-        print(f"[bench] backward error {eta:.2e}", file=sys.stderr, flush=True)
+        eta_or = float(max(etas))
+        print(f"[bench] oracle-assembled backward error on states {picks}: {eta_or:.2e}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu and args.cpu_steps > 0:
-        rate, threads = cpu_baseline([net], cfg, args.cpu_steps)
-        cpu = {"value": rate, "unit": "factor+solve/s", "cores": threads, "kind": "oracle",
-               "sample": f"{args.cpu_steps} steps of the same workload (numpy assembly, C left-looking LDL^T "
-                         f"with OpenMP over blocks, solve); symbolic analysis untimed"}
+        rates, threads, model, ncpu = cpu_baseline([net], cfg, args.cpu_steps)
+        cpu = {"value": rates[threads], "unit": "factor+solve/s", "cores": threads, "kind": "oracle",
+               "single_thread_value": rates[1], "cpu_model": model, "os_cpu_count": ncpu,
+               "sample": f"{args.cpu_steps} states of the same workload, one factor+solve (nrhs=1) each, "
+                         f"C left-looking LDL^T with OpenMP over the blocks on {threads} threads, and again on "
+                         f"1 thread; K assembled by numpy and the symbolic analysis done beforehand, untimed"}
 
     from paper_2510_13333_amd.ncl import KERNELS
     nbd = sum(i["nbd"] for i in k.instances)
     step_bytes = sum(k.kernel_model(kind)[1] for kind in range(len(KERNELS)))
     out = {
         "metric": METRIC,
-        "value": args.steps / wall,
+        "value": 1.0 / t_fs,
         "unit": "factor+solve/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -250,15 +341,21 @@ def run_single(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[cfg], "step": f"assemble+factor+solve, nrhs={nrhs}", "N": k.N,
-                   "nnzK_lower": k.nnzK, "nnzL": k.nnzL, "blocks": net.nblk, "border": nbd},
+        "config": {"workload": WORKLOADS[cfg], "value": "1 / median over the timed steps of (factor + solve) "
+                   "event time; ms_per_step is the wall clock of the whole step (assembly and the gate included)",
+                   "step": f"assemble+factor+solve+gate, nrhs={nrhs}", "N": k.N, "nnzK_lower": k.nnzK,
+                   "nnzL": k.nnzL, "blocks": net.nblk, "border": nbd},
         "roofline": roof,
-        "phases_ms": {"assemble": t_asm * 1e3, "factor_blocks": t_fblk * 1e3, "factor_border": t_fbrd * 1e3,
-                      "solve": t_sol * 1e3},
-        "factor_solve_per_s": 1.0 / (t_fblk + t_fbrd + t_sol),
+        "phases": phases,
+        "copy_peak_GBs": peak_copy,
+        "gate_ms": t_gate * 1e3,
+        "steps_per_s_wall": args.steps / wall,
         "kernel_ms_per_step": {k.kernel_name(kd): ms for kd, ms in sorted(per_kind.items(), key=lambda x: -x[1])},
-        "step_algorithmic_GB": step_bytes / 1e9,
-        "bwd_err_max": eta,
+        "implementation_GB_per_step": step_bytes / 1e9,
+        "gate": {"eta_max": eta_max, "omega_max": omega_max, "steps_eta_le_1e-12": passed,
+                 "refine_ms": t_ref * 1e3, "eta_after_refine": float(gr[..., 0].max()),
+                 "omega_after_refine": float(gr[..., 1].max())},
+        "bwd_err_oracle_assembled": eta_or,
         "inertia": [info["npos"], info["nneg"], info["nzero"]],
         "status": info["status"],
         "cpu_baseline": cpu,
@@ -316,7 +413,8 @@ def run_batched(args):
     wall = time.perf_counter() - t0
     n_dom, ms_dom = kb.profile_read()
     kb.profile(-1)
-    roof = roofline(kb, dom, n_dom, ms_dom, cfg)
+    kb.cfg = cfg
+    roof = roofline(kb, dom, n_dom, ms_dom, phase_bytes(kb, 1))
     x_eager = x.clone()
 
     # the same step captured once in a hipGraph and replayed
@@ -358,7 +456,7 @@ def run_batched(args):
     wall_single = time.perf_counter() - t0
     same = all(torch.equal(x1, x_eager[kb.instances[i]["col0"]:kb.instances[i]["col0"] + kb.instances[i]["N"]])
                for i, (_, _, _, _, x1) in enumerate(singles))
-    copy_calibration()
+    peak_copy = copy_peak()
 
     eta = None
     if not args.no_check:
@@ -375,10 +473,12 @@ def run_batched(args):
 
     cpu = None
     if not args.no_cpu and args.cpu_steps > 0:
-        rate, threads = cpu_baseline(nets[:8], cfg, 1, batched=True)
-        cpu = {"value": rate, "unit": "factor+solve/s", "cores": threads, "kind": "oracle",
-               "sample": "the first 8 of the 64 networks, one factor+solve each (numpy assembly, C left-looking "
-                         "LDL^T with OpenMP over blocks, solve); one factor+solve = one network"}
+        rates, threads, model, ncpu = cpu_baseline(nets[:8], cfg, 1, batched=True)
+        cpu = {"value": rates[threads], "unit": "factor+solve/s", "cores": threads, "kind": "oracle",
+               "single_thread_value": rates[1], "cpu_model": model, "os_cpu_count": ncpu,
+               "sample": "the first 8 of the 64 networks, one factor+solve each (C left-looking LDL^T with OpenMP "
+                         "over blocks, and on 1 thread; K assembled by numpy beforehand, untimed); one "
+                         "factor+solve = one network"}
 
     n = len(nets)
     out = {
@@ -397,6 +497,7 @@ def run_batched(args):
         "config": {"workload": WORKLOADS[cfg], "step": "assemble+factor+solve of all 64 networks, nrhs=1",
                    "N": kb.N, "nnzL": kb.nnzL, "networks": n, "tiles": "autotuned" if table else "default"},
         "roofline": roof,
+        "copy_peak_GBs": peak_copy,
         "batched_graph_per_s": n * args.steps / wall_graph,
         "unbatched_per_s": n * args.steps / wall_single,
         "batched_over_unbatched": wall_single / wall,
@@ -426,8 +527,8 @@ def summarize_pmc(fetch_dir, write_dir, kernel, cfg):
         return vals
     fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
     copy_bytes = 8 * COPY_DOUBLES
-    copy_f = max(max(v) for n, v in fe.items() if not n.startswith("k_"))
-    copy_w = max(max(v) for n, v in wr.items() if not n.startswith("k_"))
+    copy_f = max(fe["k_copy"])
+    copy_w = max(wr["k_copy"])
     sf, sw = copy_bytes / (copy_f * 1024), copy_bytes / (copy_w * 1024)
     f_kib, w_kib = float(np.mean(fe[kernel])), float(np.mean(wr[kernel]))
     res = {"kernel": kernel, "workload": WORKLOADS[cfg], "kernels_sha": kernels_sha(),

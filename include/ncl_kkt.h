@@ -421,6 +421,12 @@ int ncl_kkt_profile(ncl_kkt *h, int32_t kind);
  * steps while adding fewer event records to the stream. */
 int ncl_kkt_profile_stride(ncl_kkt *h, int32_t stride);
 
+/* Streaming copy ddst[i] = dsrc[i], i < n, on the device (measurement: the
+ * bandwidth a plain streaming kernel reaches, against which the path's
+ * kernels are compared).  n even, both pointers 16-byte aligned, ranges
+ * not overlapping; else NCL_ERR_ARG.  Asynchronous on `stream`. */
+int ncl_stream_copy(const double *dsrc, double *ddst, int64_t n, void *stream);
+
 /* Number of bracketed launches since ncl_kkt_profile and the sum of their
  * event-measured durations in milliseconds (waits for the last event). */
 int ncl_kkt_profile_read(ncl_kkt *h, int64_t *launches, double *total_ms);

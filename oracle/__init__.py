@@ -19,25 +19,46 @@ from . import assemble as _asm
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "libncl_oracle.so")
-_lib = None
+# The same C built with fused multiply-add contraction (FMA is allowed on
+# both sides of every comparison): the difference between the two builds'
+# factors measures how much an entry depends on the rounding of its own
+# recurrence, which a perturbation of K cannot show where large terms cancel
+# exactly (the pivot of a complementarity row can be 1e-9 of the terms that
+# form it).
+_SO_FMA = os.path.join(_HERE, "libncl_oracle_fma.so")
+_libs = {}
 
 DEFAULT_RELAX = (16, 1, 4)      # maxw, znum, zden
 
 
+def host_has_fma() -> bool:
+    try:
+        with open("/proc/cpuinfo") as f:
+            return any(line.startswith("flags") and " fma " in line + " " for line in f)
+    except OSError:
+        return False
+
+
 def build(force: bool = True) -> str:
-    """Compile the C oracle (gcc, OpenMP)."""
+    """Compile the C oracle (gcc, OpenMP), and its FMA build where the host
+    has FMA."""
+    src = os.path.join(_HERE, "ncl_oracle.c")
+    base = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
     if force or not os.path.exists(_SO):
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-o", _SO, os.path.join(_HERE, "ncl_oracle.c"), "-lm"])
+        subprocess.check_call(base + ["-ffp-contract=off", "-o", _SO, src, "-lm"])
+    if host_has_fma() and (force or not os.path.exists(_SO_FMA)):
+        subprocess.check_call(base + ["-mfma", "-ffp-contract=fast", "-o", _SO_FMA, src, "-lm"])
     return _SO
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_SO):
-            build()
-        L = ctypes.CDLL(_SO)
+def _load(fma=False):
+    if fma not in _libs:
+        so = _SO_FMA if fma else _SO
+        if not os.path.exists(so):
+            build(force=False)
+        if not os.path.exists(so):
+            raise RuntimeError("the FMA build of the oracle needs a host with FMA")
+        L = ctypes.CDLL(so)
         P = ctypes.c_void_p
         i64, i32 = ctypes.c_int64, ctypes.c_int32
         L.oracle_symbolic.argtypes = [i64, P, P, i32, P, i32, i32, i32, P, ctypes.POINTER(P)]
@@ -55,8 +76,8 @@ def _load():
         L.oracle_solve.restype = ctypes.c_int
         L.oracle_free.argtypes = [P]
         L.oracle_free.restype = None
-        _lib = L
-    return _lib
+        _libs[fma] = L
+    return _libs[fma]
 
 
 def _ptr(a):
@@ -78,10 +99,12 @@ class Factor:
 
     ``perm``: a caller's elimination order (new -> layout index) in place of
     minimum degree; it must keep every block's columns inside the block and
-    the border in layout order."""
+    the border in layout order.  ``fma``: use the build with fused
+    multiply-add contraction (same arithmetic, other rounding)."""
 
-    def __init__(self, N, colptr, rowind, block_off, relax=DEFAULT_RELAX, perm=None):
-        L = _load()
+    def __init__(self, N, colptr, rowind, block_off, relax=DEFAULT_RELAX, perm=None, fma=False):
+        self._fma = bool(fma)
+        L = _load(self._fma)
         self.N = int(N)
         self.colptr = np.ascontiguousarray(colptr, np.int64)
         self.rowind = np.ascontiguousarray(rowind, np.int32)
@@ -121,7 +144,7 @@ class Factor:
         return f
 
     def factor(self, colptr, rowind, vals, nthreads=1):
-        L = _load()
+        L = _load(self._fma)
         vals = np.ascontiguousarray(vals, np.float64)
         rc = L.oracle_factor(self._h, _ptr(np.ascontiguousarray(colptr, np.int64)),
                              _ptr(np.ascontiguousarray(rowind, np.int32)), _ptr(vals), int(nthreads))
@@ -137,7 +160,7 @@ class Factor:
 
     def solve(self, b):
         """x = K^{-1} b; b is (N,) or (nrhs, N) in layout order."""
-        L = _load()
+        L = _load(self._fma)
         b2 = np.ascontiguousarray(np.atleast_2d(b), np.float64)
         x = np.empty_like(b2)
         rc = L.oracle_solve(self._h, _ptr(b2), _ptr(x), b2.shape[0], self.N)
@@ -153,7 +176,7 @@ class Factor:
     def __del__(self):
         try:
             if self._h:
-                _load().oracle_free(self._h)
+                _load(self._fma).oracle_free(self._h)
                 self._h = None
         except Exception:
             pass

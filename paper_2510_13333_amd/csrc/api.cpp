@@ -1216,6 +1216,13 @@ int ncl_kkt_kernel_model(const ncl_kkt *k, int32_t kind, int64_t *launches, int6
     return NCL_OK;
 }
 
+int ncl_stream_copy(const double *dsrc, double *ddst, int64_t n, void *stream) {
+    if (!dsrc || !ddst || n < 0 || (n & 1) || (reinterpret_cast<uintptr_t>(dsrc) & 15) ||
+        (reinterpret_cast<uintptr_t>(ddst) & 15))
+        return NCL_ERR_ARG;
+    return ncl::launch_copy(dsrc, ddst, n, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? NCL_OK : NCL_ERR_HIP;
+}
+
 int ncl_kkt_profile(ncl_kkt *k, int32_t kind) {
     if (!k || kind < -1 || kind >= NCL_K_COUNT) return NCL_ERR_ARG;
     k->h.prof_kind = kind;

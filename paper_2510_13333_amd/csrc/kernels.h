@@ -68,4 +68,7 @@ struct LaunchArgs {
 // Launch one kernel of the given kind (NCL_K_* of ncl_kkt.h) on stream st.
 hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st);
 
+// Streaming copy of n doubles (n even, both pointers 16-byte aligned).
+hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);
+
 }  // namespace ncl

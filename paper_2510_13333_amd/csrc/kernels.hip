@@ -2037,6 +2037,36 @@ __global__ __launch_bounds__(kStepThreads) void k_max_step(DevArgs a, const doub
     }
 }
 
+// ------------------------------------------------------------------ streaming copy
+
+// Plain copy d = s of n2 16-byte elements: each thread moves kCopyPer
+// elements strided by the workgroup, all loads issued before the stores.
+// Used to measure the bandwidth a streaming kernel reaches on this GPU.
+constexpr int kCopyPer = 4;
+
+__global__ __launch_bounds__(256) void k_copy(const double2 *__restrict__ s, double2 *__restrict__ d, int64_t n2) {
+    const int64_t i0 = int64_t(blockIdx.x) * (256 * kCopyPer) + threadIdx.x;
+    double2 v[kCopyPer];
+#pragma unroll
+    for (int q = 0; q < kCopyPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        if (i < n2) v[q] = s[i];
+    }
+#pragma unroll
+    for (int q = 0; q < kCopyPer; q++) {
+        const int64_t i = i0 + 256 * q;
+        if (i < n2) d[i] = v[q];
+    }
+}
+
+hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st) {
+    const int64_t n2 = n / 2;
+    const int64_t g = (n2 + 256 * kCopyPer - 1) / (256 * kCopyPer);
+    if (g) hipLaunchKernelGGL(k_copy, dim3(unsigned(g)), dim3(256), 0, st, reinterpret_cast<const double2 *>(src),
+                              reinterpret_cast<double2 *>(dst), n2);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 
 // Task lists at most this long run one task per workgroup (four wavefronts

@@ -121,6 +121,7 @@ def load():
         "ncl_kkt_layout_kinds": ([P, P], ctypes.c_int),
         "ncl_kkt_max_step": ([P, P, P, P, ctypes.c_double, P, P], ctypes.c_int),
         "ncl_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "ncl_stream_copy": ([P, P, i64, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -128,6 +129,14 @@ def load():
         f.restype = res
     _lib = L
     return L
+
+
+def stream_copy(src, dst):
+    """dst[:] = src by the library's streaming copy kernel (device float64
+    tensors of one even length)."""
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    _check("ncl_stream_copy", load().ncl_stream_copy(KKT._dev(src), KKT._dev(dst), int(src.numel()), _stream_ptr()))
 
 
 def _np_ptr(a):

@@ -24,6 +24,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_2510_13333_amd import KKT, NclError  # noqa: E402
 from tests.test_library_cpu import block_respecting_perm  # noqa: E402
+from tests.test_gpu_parity import check_factors  # noqa: E402
 
 
 def dev(a):
@@ -162,17 +163,21 @@ def test_solve_refused_before_factor_and_during():
 
 
 def run_perm_case(net, cfg, perm, nrhs=2):
+    """Factors compared entry by entry within 1e-8 plus ten times each
+    entry's own rounding sensitivity (under a random order L is not a
+    well-conditioned function of K: on the 500-bus x 16 network with the
+    order below, one ulp of K moves the oracle's own L by 1.3e-8 at
+    max|L| 9.3e7); x and the backward error keep their fixed bars."""
     k, (z, s), _, B = setup(net, cfg, nrhs, perm=perm)
     cp, ri, v, pos = O.kkt(net, z, s)
     F = O.Factor(pos.N, cp, ri, np.array(pos.block_off), perm=perm)
     assert F.factor(cp, ri, v, nthreads=8) == 0
     sym = k.symbolic()
     assert np.array_equal(sym["perm"], F.perm)
-    lx, d = k.get_factors()
+    lx, d = check_factors(k, F, cp, ri, v, perm=perm)
     # quasi-definite: every pivot carries its column's sign (primal +, dual -)
     assert np.array_equal(d > 0, pos.is_primal[F.perm])
-    np.testing.assert_allclose(d, F.d, rtol=1e-8)
-    assert (np.abs(lx - F.lx) <= 1e-8 * np.maximum(1.0, np.abs(F.lx))).all()
+    assert F.factor(cp, ri, v, nthreads=8) == 0
     X = k.solve(dev(B)).cpu().numpy()
     Xo = F.solve(B)
     assert np.abs(X - Xo).max() <= 1e-8 * np.abs(Xo).max()

@@ -3,7 +3,18 @@ same seeded inputs.
 
 Bars (FP64 throughout):
 * assembly: every K entry within 1e-12 * (|K_ij| + max_{j' != i} |K_ij'|);
-* factors: D within 1e-8 relative, L within 1e-8 of max(1, |L|) entrywise;
+* factors: the oracle factors the K values the GPU assembled (so that
+  assembly rounding, bounded above relative to each row's largest entry,
+  does not count against the factorisation), and every entry of D
+  (relative) and of L (of max(1, |L|)) agrees within 1e-8 plus ten times
+  its own rounding sensitivity: the largest change of that entry in the
+  oracle's factors when every K value is perturbed by one ulp (two random
+  perturbations) or when the oracle is built with FMA contraction.  The
+  pivot-free LDL^T is unique but some entries are ill-conditioned: at the
+  500-bus x 256 state 49 one ulp of K moves 43 pivots by more than 1e-8
+  (up to 8e-7), and two pivots formed by a 2e9-fold cancellation carry a
+  3e-8 rounding error in the FP64 oracle itself (against an extended-
+  precision factorisation of the same K);
 * solve: relative solution error <= 1e-8 and normwise backward error
   <= 1e-12, the residual taken with the oracle-assembled K;
 * inertia (n, m) and status NCL_OK; run-to-run results bitwise equal;
@@ -42,6 +53,43 @@ def check_assembly(kv, cp, ri, v):
     assert bad.size == 0, f"{bad.size} entries off, first at {bad[:5]}: {kv[bad[:5]]} vs {v[bad[:5]]}"
 
 
+def factor_sensitivity(F, cp, ri, v, perm=None):
+    """Per-entry rounding sensitivity of the oracle's (L, D): the largest
+    change of each entry under one-ulp random-sign perturbations of K (two
+    of them) and under the oracle's FMA build (same arithmetic, other
+    rounding: it shows the entries formed by exact cancellation of large
+    terms, which a perturbation of K leaves alone); d relative, L of
+    max(1, |L|)."""
+    d0, l0 = F.d.copy(), F.lx.copy()
+    sd, sl = np.zeros_like(d0), np.zeros_like(l0)
+    P = O.Factor(F.N, cp, ri, F.block_off, perm=perm)
+    runs = [(P, v * (1.0 + 2.0 ** -52 * np.random.default_rng(seed).choice([-1.0, 1.0], size=v.shape)))
+            for seed in (1, 2)]
+    if O.host_has_fma():
+        runs.append((O.Factor(F.N, cp, ri, F.block_off, perm=perm, fma=True), v))
+    for Q, vals in runs:
+        assert Q.factor(cp, ri, vals, nthreads=8) == 0
+        sd = np.maximum(sd, np.abs(Q.d - d0) / np.abs(d0))
+        sl = np.maximum(sl, np.abs(Q.lx - l0) / np.maximum(1.0, np.abs(l0)))
+    return sd, sl
+
+
+def check_factors(k, F, cp, ri, v, perm=None):
+    """The handle's factors against the oracle's factorisation of the
+    handle's own K values (F: an oracle Factor of the same pattern and
+    order; refactored here)."""
+    v = k.get_values().cpu().numpy()
+    assert F.factor(cp, ri, v, nthreads=8) == 0
+    lx, d = k.get_factors()
+    sd, sl = factor_sensitivity(F, cp, ri, v, perm)
+    ed = np.abs(d - F.d) / np.abs(F.d)
+    el = np.abs(lx - F.lx) / np.maximum(1.0, np.abs(F.lx))
+    bd, bl = np.flatnonzero(ed > 1e-8 + 10 * sd), np.flatnonzero(el > 1e-8 + 10 * sl)
+    assert bd.size == 0, f"{bd.size} pivots off, first {bd[:5]}: err {ed[bd[:5]]} sensitivity {sd[bd[:5]]}"
+    assert bl.size == 0, f"{bl.size} L entries off, first {bl[:5]}: err {el[bl[:5]]} sensitivity {sl[bl[:5]]}"
+    return lx, d
+
+
 def run_case(net, cfg, nrhs=1, iteration=0, factors=True, k=None, state=None):
     z, s = G.draw_point(net, cfg, iteration=iteration) if state is None else state
     if k is None:
@@ -57,9 +105,8 @@ def run_case(net, cfg, nrhs=1, iteration=0, factors=True, k=None, state=None):
     F = O.Factor(pos.N, cp, ri, np.array(pos.block_off))
     assert F.factor(cp, ri, v, nthreads=8) == 0
     if factors:
-        lx, d = k.get_factors()
-        np.testing.assert_allclose(d, F.d, rtol=1e-8)
-        assert (np.abs(lx - F.lx) <= 1e-8 * np.maximum(1.0, np.abs(F.lx))).all()
+        check_factors(k, F, cp, ri, v)
+        assert F.factor(cp, ri, v, nthreads=8) == 0
     B = G.draw_rhs(pos.N, nrhs, cfg, iteration=iteration)
     X = k.solve(dev(B)).cpu().numpy()
     Xo = F.solve(B)
