@@ -326,6 +326,24 @@ int ncl_kkt_backward_error(ncl_kkt *h, const double *db, const double *dx, int32
  * ncl_kkt_solve. */
 int ncl_kkt_refine(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream);
 
+/* For callers that cannot allocate device memory or use a workspace's
+ * staging (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): ncl_kkt_backward_error with its residual staging
+ * (x, b and r transposed to the blocks' interleaved order, r in layout
+ * order, per-workgroup partial maxima) in a device array the library holds
+ * on each GPU it runs on, from module load until the process ends, instead
+ * of in the bound workspace.  Same kernels, same results bit for bit.
+ * Allocates nothing (no hipMalloc, hipFree or allocating library call).
+ * The staging needs 3 * (N + 32) + N + 8 * (row wavefronts / 4 + border
+ * rows / 4) doubles, about 4 N; above NCL_NOALLOC_MAX_DOUBLES (48 MiB, so N
+ * up to about 1.5 million) the call returns NCL_ERR_ARG.  Every call on one
+ * GPU shares that GPU's array and leaves its contents behind (nothing in it
+ * needs to start at zero): calls that overlap on one GPU, from any handle
+ * or stream, race.  Other errors as ncl_kkt_backward_error. */
+#define NCL_NOALLOC_MAX_DOUBLES (6 * 1048576)
+int ncl_kkt_backward_error_noalloc(ncl_kkt *h, const double *db, const double *dx, int32_t nrhs, int64_t ld,
+                                   double *derr, void *stream);
+
 void ncl_kkt_destroy(ncl_kkt *h);
 const char *ncl_status_string(int status);
 

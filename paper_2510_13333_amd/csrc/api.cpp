@@ -1134,8 +1134,8 @@ static int residual_column(Handle &h, const ncl::DevArgs &a, const double *b, co
     ncl::LaunchArgs l;
     l.z = x;
     l.sig = b;
-    l.zdst = h.d.xint;
-    l.sdst = h.d.bint;
+    l.zdst = a.xint;
+    l.sdst = a.bint;
     if (run(h, NCL_K_INTERLEAVE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
     if (run(h, NCL_K_BERR_ROWS, a, l, st) != hipSuccess) return NCL_ERR_HIP;
     if (run(h, NCL_K_BERR_BORDER, a, l, st) != hipSuccess) return NCL_ERR_HIP;
@@ -1275,6 +1275,39 @@ int ncl_kkt_backward_error(ncl_kkt *k, const double *db, const double *dx, int32
     if (ld < h.N) return NCL_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const ncl::DevArgs a = dev_args(h);
+    for (int rhs = 0; rhs < nrhs; rhs++) {
+        const int rc = residual_column(h, a, db + int64_t(rhs) * ld, dx + int64_t(rhs) * ld, derr + 2 * rhs, st);
+        if (rc) return rc;
+    }
+    return NCL_OK;
+}
+
+// Doubles of residual staging one backward-error call needs: x, b and r in
+// the interleaved order, r in layout order and the partial maxima, each
+// rounded up to 256 bytes.
+static int64_t berr_staging(const Handle &h) {
+    auto up = [](int64_t n) { return (n + 31) / 32 * 32; };
+    const int64_t v = up(h.dint + h.nbd_tot);
+    return 3 * v + up(h.N) + up(8 * berr_partials(h));
+}
+
+int ncl_kkt_backward_error_noalloc(ncl_kkt *k, const double *db, const double *dx, int32_t nrhs, int64_t ld,
+                                   double *derr, void *stream) {
+    if (!k || !db || !dx || !derr || nrhs < 1) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (ld < h.N || berr_staging(h) > ncl::kScratchDoubles) return NCL_ERR_ARG;
+    if (!h.bound || !h.values_set) return NCL_ERR_STATE;
+    double *sc = nullptr;
+    if (ncl::scratch_address(&sc) != hipSuccess) return NCL_ERR_HIP;
+    auto up = [](int64_t n) { return (n + 31) / 32 * 32; };
+    const int64_t v = up(h.dint + h.nbd_tot);
+    ncl::DevArgs a = dev_args(h);
+    a.xint = sc;
+    a.bint = sc + v;
+    a.rint = sc + 2 * v;
+    a.rbuf = sc + 3 * v;
+    a.epart = sc + 3 * v + up(h.N);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     for (int rhs = 0; rhs < nrhs; rhs++) {
         const int rc = residual_column(h, a, db + int64_t(rhs) * ld, dx + int64_t(rhs) * ld, derr + 2 * rhs, st);
         if (rc) return rc;

@@ -68,6 +68,11 @@ struct LaunchArgs {
 // Launch one kernel of the given kind (NCL_K_* of ncl_kkt.h) on stream st.
 hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t st);
 
+// Library-held device scratch (doubles) of the entry points that allocate
+// nothing, and its address on the current device (looked up once per device).
+constexpr int64_t kScratchDoubles = int64_t(6) << 20;
+hipError_t scratch_address(double **out);
+
 // Streaming copy of n doubles (n even, both pointers 16-byte aligned).
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);
 

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.h"
@@ -2065,6 +2066,35 @@ hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st
     if (g) hipLaunchKernelGGL(k_copy, dim3(unsigned(g)), dim3(256), 0, st, reinterpret_cast<const double2 *>(src),
                               reinterpret_cast<double2 *>(dst), n2);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ library-held scratch
+
+// Device memory of the entry points that allocate nothing: one array per
+// GPU, held from module load until the process ends.  In host code the
+// array's name is only a stand-in for its device address; the address of
+// each device's copy comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is ever passed to a
+// kernel or a copy.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+hipError_t scratch_address(double **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------------ launchers

@@ -111,6 +111,7 @@ def load():
         "ncl_kkt_solve_adjoint": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_backward_error": ([P, P, P, i32, i64, P, P], ctypes.c_int),
         "ncl_kkt_refine": ([P, P, P, i32, i64, P], ctypes.c_int),
+        "ncl_kkt_backward_error_noalloc": ([P, P, P, i32, i64, P, P], ctypes.c_int),
         "ncl_kkt_destroy": ([P], None),
         "ncl_kernel_name": ([ctypes.c_int], ctypes.c_char_p),
         "ncl_kkt_kernel_model": ([P, i32, P, P], ctypes.c_int),
@@ -339,9 +340,10 @@ class KKT:
     def solve_adjoint(self, b, out=None):
         return self._solve("ncl_kkt_solve_adjoint", b, out)
 
-    def backward_error(self, b, x, out=None):
+    def backward_error(self, b, x, out=None, noalloc=False):
         """(eta, omega) per column, on the device (no synchronisation): a
-        (nrhs, 2) float64 tensor, or written into ``out``."""
+        (nrhs, 2) float64 tensor, or written into ``out``.  noalloc: the
+        library-held staging (ncl_kkt_backward_error_noalloc)."""
         import torch
         b2 = b if b.dim() == 2 else b.reshape(1, -1)
         x2 = x if x.dim() == 2 else x.reshape(1, -1)
@@ -349,7 +351,8 @@ class KKT:
             raise ValueError("b and x differ in shape")
         if out is None:
             out = torch.empty((b2.shape[0], 2), dtype=torch.float64, device=b.device)
-        _check("ncl_kkt_backward_error", load().ncl_kkt_backward_error(
+        fn = "ncl_kkt_backward_error_noalloc" if noalloc else "ncl_kkt_backward_error"
+        _check(fn, getattr(load(), fn)(
             self._h, self._dev(b2), self._dev(x2), int(b2.shape[0]), int(b2.shape[1]), self._dev(out, 2 * b2.shape[0]),
             _stream_ptr()))
         return out
