@@ -94,9 +94,10 @@ def dominant_kernel(k, step):
 
 
 PHASE_OF = {"interleave": "assemble", "assemble": "assemble", "sol_load": "solve", "sol_fwd_gather": "solve",
-            "sol_fwd_diag": "solve", "sol_bpart": "solve", "sol_border": "solve", "sol_bwd_gather": "solve",
-            "sol_bwd_diag": "solve", "sol_store": "solve", "berr_rows": "gate", "berr_border": "gate",
-            "berr_final": "gate"}
+            "sol_fwd_diag": "solve",
+            "sol_bpart": "solve", "sol_border": "solve", "sol_bwd_border": "solve", "sol_bwd": "solve",
+            "sol_store": "solve",
+            "berr_rows": "gate", "berr_border": "gate", "berr_final": "gate"}
 
 
 def phase_of(kind):

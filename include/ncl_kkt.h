@@ -401,12 +401,12 @@ enum {
     NCL_K_STATUS_INIT,      /* k_status_init */
     NCL_K_STATUS,           /* k_status: pivot signs and magnitudes */
     NCL_K_SOL_LOAD,         /* k_sol_load */
-    NCL_K_SOL_FWD_GATHER,   /* k_sol_fwd_gather, per level */
-    NCL_K_SOL_FWD_DIAG,     /* k_sol_fwd_diag, per level */
+    NCL_K_SOL_FWD_GATHER,   /* k_sol_fwd_gather: forward gathers of one level's diagonal rows */
+    NCL_K_SOL_FWD_DIAG,     /* k_sol_fwd_diag: unit lower diagonal blocks of one level's wide supernodes */
     NCL_K_SOL_BPART,        /* k_sol_bpart */
     NCL_K_SOL_BORDER,       /* k_sol_border */
-    NCL_K_SOL_BWD_GATHER,   /* k_sol_bwd_gather, per level (applies D^-1 to its column first) */
-    NCL_K_SOL_BWD_DIAG,     /* k_sol_bwd_diag, per level */
+    NCL_K_SOL_BWD_BORDER,   /* k_sol_bwd_border: D^-1 and the border rows' part of the backward sums, every column */
+    NCL_K_SOL_BWD,          /* k_sol_bwd: backward substitution of one level's supernodes (block rows, diagonal block) */
     NCL_K_SOL_STORE,        /* k_sol_store */
     NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
     NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */

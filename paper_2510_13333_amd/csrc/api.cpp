@@ -203,7 +203,8 @@ std::vector<ncl::Work> all_work(Handle &h) {
     app(S.c, h.w_c);
     app(S.f, h.w_f);
     app(S.d, h.w_d);
-    app(S.g, h.w_g);
+    app(S.sn, h.w_sn);
+    app(S.sb, h.w_sb);
     app(S.bpart, h.w_bpart);
     app(S.schur, h.w_schur);
     return w;
@@ -251,6 +252,8 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(t.rr_ent));
         o.push_back(L.vec(t.rb_ptr));
         o.push_back(L.vec(t.rb_ent));
+        o.push_back(L.vec(t.sup_rnb));
+        o.push_back(L.vec(t.col_sup));
     }
     p.tdev = L.take(nullptr, sizeof(ncl::TemplDev) * h.tmpl.size());
     p.bdev = L.take(nullptr, sizeof(ncl::BlockDev) * size_t(h.nblk));
@@ -355,8 +358,8 @@ void kernel_model(Handle &h) {
     levels(NCL_K_FAC_ROWS, S.c_ptr);
     levels(NCL_K_SOL_FWD_GATHER, S.f_ptr);
     levels(NCL_K_SOL_FWD_DIAG, S.d_ptr);
-    levels(NCL_K_SOL_BWD_GATHER, S.g_ptr);
-    levels(NCL_K_SOL_BWD_DIAG, S.d_ptr);
+    levels(NCL_K_SOL_BWD, S.sn_ptr);
+    L[NCL_K_SOL_BWD_BORDER] = S.sb.empty() ? 0 : 1;
     for (const Template &t : h.tmpl) {
         const int64_t nb = int64_t(t.blocks.size());
         const int n = t.n;
@@ -367,11 +370,6 @@ void kernel_model(Handle &h) {
         auto uniq_ul = [&](const ncl::Term &q, int64_t &uu, int64_t &ul) {
             if (mu[q.a] != stamp) { mu[q.a] = stamp; uu++; }
             if (mp[q.c] != stamp) { mp[q.c] = stamp; ul++; }
-        };
-        auto uniq = [&](const ncl::Term &q, bool two, int64_t &up, int64_t &uk) {
-            if (mp[q.a] != stamp) { mp[q.a] = stamp; up++; }
-            if (two && mp[q.c] != stamp) { mp[q.c] = stamp; up++; }
-            if (mk[q.k] != stamp) { mk[q.k] = stamp; uk++; }
         };
         for (int l = 0; l < t.nlev; l++) {
             // factor: gather (A), diagonal blocks and width-1 pivots (B), rows (C)
@@ -399,8 +397,8 @@ void kernel_model(Handle &h) {
             B[NCL_K_FAC_GATHER] += nb * D * (ents + kr + up + uk);
             B[NCL_K_FAC_DIAG] += nb * D * bdiag;
             B[NCL_K_FAC_ROWS] += nb * D * rows;
-            // solves: forward gather (F) and backward gather (G) of the diagonal rows, diagonal solves (D)
-            int64_t fr = 0, fup = 0, fuy = 0, gr = 0, gp = 0, guy = 0, dd = 0;
+            // forward solve: gathers of the diagonal rows (F), diagonal solves (D)
+            int64_t fr = 0, fup = 0, fuy = 0, dd = 0;
             stamp++;
             last_s = -1;
             for (int32_t k : t.lev_tasks[l]) {
@@ -410,28 +408,46 @@ void kernel_model(Handle &h) {
                 const int e = t.task_cbase[k] + p;
                 if (t.ent_tptr[e + 1] > t.ent_tptr[e]) {
                     fr += 2;
-                    for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) uniq(t.terms[q], false, fup, fuy);
+                    for (int q = t.ent_tptr[e]; q < t.ent_tptr[e + 1]; q++) {
+                        const ncl::Term &tm = t.terms[q];
+                        if (mp[tm.a] != stamp) { mp[tm.a] = stamp; fup++; }
+                        if (mk[tm.k] != stamp) { mk[tm.k] = stamp; fuy++; }
+                    }
                 }
                 if (w > 1 && s != last_s) dd += int64_t(w) * (w - 1) / 2 + 2 * w - 1;
                 last_s = s;
             }
-            stamp++;
-            for (int32_t k : t.lev_tasks[l]) {
-                const int s = t.task_s[k], p = t.task_p[k];
-                const int w = t.sup[s + 1] - t.sup[s];
-                if (p >= w) continue;
-                const int r = t.srp[s + 1] - t.srp[s];
-                gr += 3;                                          // y read and written, d read
-                gp += r - w;
-                for (int i = t.srp[s] + w; i < t.srp[s + 1]; i++) {
-                    const int row = t.sri[i];
-                    if (mk[row] != stamp) { mk[row] = stamp; guy++; }
-                }
-            }
             B[NCL_K_SOL_FWD_GATHER] += nb * D * (fr + fup + fuy);
             B[NCL_K_SOL_FWD_DIAG] += nb * D * dd;
-            B[NCL_K_SOL_BWD_GATHER] += nb * D * (gr + gp + guy);
-            B[NCL_K_SOL_BWD_DIAG] += nb * D * dd;
+            // backward, per supernode of the level: its diagonal block and the
+            // block rows below it read once, its y read and written, the
+            // solution of the distinct block rows below read
+            int64_t sb = 0, rowsx = 0;
+            stamp++;
+            last_s = -1;
+            for (int32_t k : t.lev_tasks[l]) {
+                const int s = t.task_s[k];
+                if (s == last_s) continue;
+                last_s = s;
+                const int w = t.sup[s + 1] - t.sup[s], rnb = t.sup_rnb[s];
+                sb += int64_t(w) * (w - 1) / 2 + int64_t(rnb - w) * w + 2 * w;
+                for (int i = t.srp[s] + w; i < t.srp[s] + rnb; i++) {
+                    const int row = t.sri[i];
+                    if (mk[row] != stamp) { mk[row] = stamp; rowsx++; }
+                }
+            }
+            B[NCL_K_SOL_BWD] += nb * D * (sb + rowsx);
+        }
+        // backward border step: every column's y and d read and y written,
+        // the border rows of every panel read
+        {
+            int64_t bb = 0;
+            const int ns = int(t.sup.size()) - 1;
+            for (int s = 0; s < ns; s++) {
+                const int w = t.sup[s + 1] - t.sup[s];
+                bb += 3 * int64_t(w) + int64_t(t.srp[s + 1] - t.srp[s] - t.sup_rnb[s]) * w;
+            }
+            B[NCL_K_SOL_BWD_BORDER] += nb * D * bb;
         }
         const ncl::Inst &I = h.inst[t.inst];
         if (I.nbd) {
@@ -441,7 +457,10 @@ void kernel_model(Handle &h) {
             B[NCL_K_BORDER_SCHUR] += nb * D * (I.npk() + up + uk);
             up = uk = 0;
             stamp++;
-            for (const ncl::Term &q : t.bterms) uniq(q, false, up, uk);
+            for (const ncl::Term &q : t.bterms) {
+                if (mp[q.a] != stamp) { mp[q.a] = stamp; up++; }
+                if (mk[q.k] != stamp) { mk[q.k] = stamp; uk++; }
+            }
             B[NCL_K_SOL_BPART] += nb * D * (I.nbd + up + uk);
         }
     }
@@ -813,6 +832,8 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.rr_ent = reinterpret_cast<const int32_t *>(at(31));
         d.rb_ptr = reinterpret_cast<const int32_t *>(at(32));
         d.rb_ent = reinterpret_cast<const int32_t *>(at(33));
+        d.sup_rnb = reinterpret_cast<const int32_t *>(at(34));
+        d.col_sup = reinterpret_cast<const int32_t *>(at(35));
         d.rwbase = h.t_rwbase[ti];
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
@@ -1069,47 +1090,61 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
     return NCL_OK;
 }
 
-// One right-hand side through the factors.  refine: the right-hand side is
+// nrhs right-hand sides (columns ld apart) through the factors, every
+// launch covering all of them.  refine: one column whose right-hand side is
 // the residual the backward-error kernels left (blocks interleaved in rint,
-// the border in rbuf) and the solution is added into x.
-static int solve_column(Handle &h, const ncl::DevArgs &a, const double *b, double *x, int rhs, bool refine,
-                        hipStream_t st) {
+// the border in rbuf); its solution is added into x.
+static int solve_columns(Handle &h, const ncl::DevArgs &a, const double *b, double *x, int nrhs, int64_t ld, bool refine,
+                         hipStream_t st) {
     const ncl::Schedule &S = h.sched;
     const ncl::Work *W = h.d.work;
-    {
-        double *y = h.d.ybuf + int64_t(rhs) * (h.dint + h.nbd_tot);
-        double *cp = h.d.cpart + int64_t(rhs) * h.cp_tot;
-        ncl::LaunchArgs v;
-        v.b = refine ? h.d.rbuf : b;
-        v.x = x;
-        v.y = y;
-        v.cpart = cp;
-        v.src = refine ? h.d.rint : nullptr;
-        v.accumulate = refine;
-        auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
-            ncl::LaunchArgs la = v;
-            la.wl = W + off + ptr[l];
-            la.nw = ptr[l + 1] - ptr[l];
-            return run(h, kind, a, la, st);
-        };
-        if (run(h, NCL_K_SOL_LOAD, a, v, st) != hipSuccess) return NCL_ERR_HIP;
-        for (int l = 0; l < S.nlev; l++) {
-            if (list(NCL_K_SOL_FWD_GATHER, h.w_f, S.f_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-            if (list(NCL_K_SOL_FWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-        }
-        if (h.nbd_tot) {
-            ncl::LaunchArgs la = v;
-            la.wl = W + h.w_bpart;
-            la.nw = int(S.bpart.size());
-            if (run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess) return NCL_ERR_HIP;
-            if (run(h, NCL_K_SOL_BORDER, a, v, st) != hipSuccess) return NCL_ERR_HIP;
-        }
-        for (int l = S.nlev - 1; l >= 0; l--) {
-            if (list(NCL_K_SOL_BWD_GATHER, h.w_g, S.g_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-            if (list(NCL_K_SOL_BWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-        }
-        if (run(h, NCL_K_SOL_STORE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+    ncl::LaunchArgs v;
+    v.b = refine ? h.d.rbuf : b;
+    v.x = x;
+    v.y = h.d.ybuf;
+    v.cpart = h.d.cpart;
+    v.src = refine ? h.d.rint : nullptr;
+    v.accumulate = refine;
+    v.nrhs = nrhs;
+    v.bld = ld;
+    v.ys = h.dint + h.nbd_tot;
+    v.cps = h.cp_tot;
+    auto level = [&](int kind, int l) {
+        ncl::LaunchArgs la = v;
+        la.wl = W + h.w_sn + S.sn_ptr[l];
+        la.nw = S.sn_ptr[l + 1] - S.sn_ptr[l];
+        la.nnar = S.sn_nar[l];
+        la.wmax = S.sn_wmax[l];
+        return run(h, kind, a, la, st);
+    };
+    auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
+        ncl::LaunchArgs la = v;
+        la.wl = W + off + ptr[l];
+        la.nw = ptr[l + 1] - ptr[l];
+        return run(h, kind, a, la, st);
+    };
+    if (run(h, NCL_K_SOL_LOAD, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+    for (int l = 0; l < S.nlev; l++) {
+        if (list(NCL_K_SOL_FWD_GATHER, h.w_f, S.f_ptr, l) != hipSuccess) return NCL_ERR_HIP;
+        if (list(NCL_K_SOL_FWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
     }
+    if (h.nbd_tot) {
+        ncl::LaunchArgs la = v;
+        la.wl = W + h.w_bpart;
+        la.nw = int(S.bpart.size());
+        if (run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess) return NCL_ERR_HIP;
+        if (run(h, NCL_K_SOL_BORDER, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    {
+        ncl::LaunchArgs la = v;
+        la.wl = W + h.w_sb;
+        la.nw = int(S.sb.size());
+        la.nnar = S.sb_nar;
+        if (run(h, NCL_K_SOL_BWD_BORDER, a, la, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    for (int l = S.nlev - 1; l >= 0; l--)
+        if (level(NCL_K_SOL_BWD, l) != hipSuccess) return NCL_ERR_HIP;
+    if (run(h, NCL_K_SOL_STORE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
     return NCL_OK;
 }
 
@@ -1120,11 +1155,7 @@ static int do_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int6
     if (nrhs > h.nrhs_max || ld < h.N) return NCL_ERR_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const ncl::DevArgs a = dev_args(h);
-    for (int rhs = 0; rhs < nrhs; rhs++) {
-        const int rc = solve_column(h, a, db + int64_t(rhs) * ld, dx + int64_t(rhs) * ld, rhs, false, st);
-        if (rc) return rc;
-    }
-    return NCL_OK;
+    return solve_columns(h, a, db, dx, nrhs, ld, false, st);
 }
 
 // r = b - K x of one column into rint (blocks) and rbuf (border), and the
@@ -1203,7 +1234,7 @@ const char *ncl_kernel_name(int kind) {
     static const char *names[NCL_K_COUNT] = {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
-        "k_sol_bpart", "k_sol_border", "k_sol_bwd_gather", "k_sol_bwd_diag", "k_sol_store",
+        "k_sol_bpart", "k_sol_border", "k_sol_bwd_border", "k_sol_bwd", "k_sol_store",
         "k_residual", "k_max_step", "k_interleave", "k_border_panel", "k_border_update", "k_berr_rows",
         "k_berr_border", "k_berr_final"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
@@ -1325,7 +1356,7 @@ int ncl_kkt_refine(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64
     for (int rhs = 0; rhs < nrhs; rhs++) {
         double *x = dx + int64_t(rhs) * ld;
         int rc = residual_column(h, a, db + int64_t(rhs) * ld, x, nullptr, st);
-        if (!rc) rc = solve_column(h, a, nullptr, x, rhs, true, st);
+        if (!rc) rc = solve_columns(h, a, nullptr, x, 1, ld, true, st);
         if (rc) return rc;
     }
     return NCL_OK;

@@ -63,6 +63,10 @@ struct LaunchArgs {
     bool accumulate = false;                     // solve store: x += solution
     const double *b = nullptr;                   // solve: right-hand side, solution, work vectors
     double *x = nullptr, *y = nullptr, *cpart = nullptr;
+    int nnar = 0;                                // solve levels: narrow items first in the list
+    int wmax = 0;                                // solve levels: widest supernode of the level (8, 16 or 32 class)
+    int nrhs = 1;                                // solve: right-hand sides of the launch (grid dimension y)
+    int64_t bld = 0, ys = 0, cps = 0;            // solve: strides between right-hand sides of b and x, y, cpart
 };
 
 // Launch one kernel of the given kind (NCL_K_* of ncl_kkt.h) on stream st.

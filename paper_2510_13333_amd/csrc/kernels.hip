@@ -577,6 +577,20 @@ __global__ __launch_bounds__(kWG) void k_fac_gather(DevArgs a, const Work *__res
 // loop bound is a compile-time constant; loads past w are clamped to column
 // w-1 (a valid address) and their contributions masked, so no load waits on
 // a run-time branch.
+// the same, for widths up to WMAX only (a launch whose items are all that
+// narrow keeps the register count of its narrow paths)
+template <int WMAX, class F>
+__device__ inline void by_width_max(int w, F &&f) {
+    if (w <= 1) f(std::integral_constant<int, 1>());
+    else if (w <= 2) f(std::integral_constant<int, 2>());
+    else if (w <= 4) f(std::integral_constant<int, 4>());
+    else if (w <= 8 || WMAX <= 8) f(std::integral_constant<int, 8>());
+    else if (w <= 12) f(std::integral_constant<int, (WMAX < 12 ? WMAX : 12)>());
+    else if (w <= 16 || WMAX <= 16) f(std::integral_constant<int, (WMAX < 16 ? WMAX : 16)>());
+    else if (w <= 24) f(std::integral_constant<int, (WMAX < 24 ? WMAX : 24)>());
+    else f(std::integral_constant<int, WMAX>());
+}
+
 template <class F>
 __device__ inline void by_width(int w, F &&f) {
     if (w <= 1) f(std::integral_constant<int, 1>());
@@ -1322,8 +1336,11 @@ __device__ inline bool factor_usable(const DevArgs &a) {
 // so that both the reads and the writes are coalesced.
 // A factorisation that may not be solved with (see factor_usable) makes
 // the solve write NaN: the caller who never read the status still sees it.
-__global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__restrict__ b, double *__restrict__ y) {
+__global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__restrict__ b, double *__restrict__ y,
+                                                  int64_t bld, int64_t ys) {
     __shared__ double tile[kTileB][kTileJ + 1];
+    b += blockIdx.y * bld;
+    y += blockIdx.y * ys;
     const TileIx x = tile_index(a, blockIdx.x);
     const TemplDev &T = *x.T;
     const bool ok = factor_usable(a);
@@ -1356,8 +1373,11 @@ __global__ __launch_bounds__(256) void k_sol_load_int(DevArgs a, const double *_
 }
 
 template <bool kAdd>
-__global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__restrict__ y, double *__restrict__ xo) {
+__global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__restrict__ y, double *__restrict__ xo,
+                                                   int64_t ys, int64_t bld) {
     __shared__ double tile[kTileB][kTileJ + 1];
+    y += blockIdx.y * ys;
+    xo += blockIdx.y * bld;
     const TileIx x = tile_index(a, blockIdx.x);
     const TemplDev &T = *x.T;
     const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
@@ -1378,10 +1398,19 @@ __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__re
     }
 }
 
+// Solves.  Forward (L y = b, levels upwards): per level, every diagonal
+// row gathers the products of its descendants' columns (pull), then the
+// wide supernodes' unit lower diagonal blocks are solved.  Backward: one
+// launch takes every column's border rows and D^-1, then one launch per
+// level (downwards) takes each supernode's block rows and its diagonal
+// block (see k_sol_bwd_border and k_sol_bwd below).
+
 // forward gather of a diagonal row: y_row -= sum over descendants L_d[row,:] y_d
 // (the terms of the row's diagonal panel entry)
 template <int NW>
-__global__ __launch_bounds__(kWG) void k_sol_fwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
+__global__ __launch_bounds__(kWG) void k_sol_fwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw,
+                                                        int64_t ys) {
+    y += blockIdx.y * ys;
     const int task = split_task<NW>();
     if (task >= nw) return;
     const Lane W = lane_work(a, wl, task);
@@ -1402,7 +1431,9 @@ __global__ __launch_bounds__(kWG) void k_sol_fwd_gather(DevArgs a, double *y, co
 // unit lower triangular solve with a wide supernode's diagonal block,
 // right-looking: y_k -= L(k,j) y_j for k > j (the loads of L do not depend
 // on y)
-__global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
+__global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, const Work *__restrict__ wl, int nw,
+                                                      int64_t ys) {
+    y += blockIdx.y * ys;
     const int wid = wave_id();
     if (wid >= nw) return;
     const Lane W = lane_work(a, wl, wid);
@@ -1438,10 +1469,53 @@ __global__ __launch_bounds__(kWG) void k_sol_fwd_diag(DevArgs a, double *y, cons
     });
 }
 
+struct SolTask {
+    const TemplDev *T;
+    int s, f, w, r, rnb;     // rows: 0 .. w-1 diagonal block, w .. rnb-1 block rows, rnb .. r-1 border rows
+    uint32_t nb, bl, po;
+    bool on;
+};
+
+__device__ __attribute__((always_inline)) inline SolTask sol_task(const DevArgs &a, const Work *wl, int item) {
+    const Lane W = lane_work(a, wl, item);
+    SolTask t;
+    t.T = W.T;
+    t.s = W.k & ~kWideFlag;
+    t.f = cs(W.T->sup_first)[t.s];
+    t.w = cs(W.T->sup_first)[t.s + 1] - t.f;
+    t.r = cs(W.T->sup_rowptr)[t.s + 1] - cs(W.T->sup_rowptr)[t.s];
+    t.rnb = cs(W.T->sup_rnb)[t.s];
+    t.nb = uint32_t(W.nb);
+    t.bl = uint32_t(W.bl);
+    t.po = uint32_t(cs(W.T->panel_off)[t.s]);
+    t.on = W.on;
+    return t;
+}
+
+// Work of a level launch: narrow items first (one wavefront each, four to a
+// workgroup), then wide ones (a workgroup each).  Returns false for a
+// wavefront with nothing to do.
+__device__ __attribute__((always_inline)) inline bool sol_item(int nw, int nnar, int &item, int &q, int &nwv) {
+    const int g = xcd_workgroup(), wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int ngn = (nnar + 3) >> 2;
+    if (g < ngn) {
+        item = 4 * g + wv;
+        q = 0;
+        nwv = 1;
+        return item < nnar;
+    }
+    item = nnar + (g - ngn);
+    q = wv;
+    nwv = 4;
+    return item < nw;
+}
+
 // this block's part of the border right-hand side: cpart[b][block] = L_bk y_k
 template <int NW>
 __global__ __launch_bounds__(kWG) void k_sol_bpart(DevArgs a, const double *y, double *cpart,
-                                                   const Work *__restrict__ wl, int nw) {
+                                                   const Work *__restrict__ wl, int nw, int64_t ys, int64_t cps) {
+    y += blockIdx.y * ys;
+    cpart += blockIdx.y * cps;
     const int task = split_task<NW>();
     if (task >= nw) return;
     const Lane W = lane_work(a, wl, task);
@@ -1584,106 +1658,211 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
 
 __global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const double *__restrict__ b, double *x,
                                                                double *y, const double *__restrict__ cpart,
-                                                               int64_t lds_bytes, int add) {
+                                                               int64_t lds_bytes, int add, int64_t bld, int64_t ys,
+                                                               int64_t cps) {
     extern __shared__ double c[];
+    b += blockIdx.y * bld;
+    x += blockIdx.y * bld;
+    y += blockIdx.y * ys;
+    cpart += blockIdx.y * cps;
     const InstDev &I = a.insts[blockIdx.x];
     const int64_t need = (int64_t(a.max_nbd) + int64_t(I.nbd) * (I.nbd + 1) / 2) * int64_t(sizeof(double));
     if (need <= lds_bytes) sol_border<true>(a, I, c, b, x, y, cpart, add != 0);
     else sol_border<false>(a, I, c, b, x, y, cpart, add != 0);
 }
 
-// backward gather of column p of a supernode: y_col = y_col / d_col - sum_{i >= w} L(i, p) x_{row i},
-// in rounds of 8, 4, 2, 1 rows (row indices are uniform; border rows read the
-// border solution)
-template <int NW>
-__global__ __launch_bounds__(kWG) void k_sol_bwd_gather(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
-    const int task = split_task<NW>();
-    if (task >= nw) return;
-    const Lane W = lane_work(a, wl, task);
-    const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
-    const int n = T.n;
-    const int s = cs(T.task_s)[W.k], p = cs(T.task_p)[W.k];
-    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
-    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
-    const int32_t *__restrict__ R_ = T.sup_rows + cs(T.sup_rowptr)[s];
-    const double *__restrict__ Lb = a.lpan + T.lbase;
+// Backward (D L^T x = y).  One launch over every block column first takes
+// the border rows (k_sol_bwd_border below), the border solution being
+// final.  Then the levels
+// downwards: v_p = sum over the block rows i below the diagonal block of
+// L(i, p) x_row(i) (ancestors, final), x_p = y_p - v_p, and the transposed
+// unit diagonal block, right-looking from the last column.  Both sums run
+// over a row range [i0, i1) as four partials (partial k takes rows i0 + k,
+// i0 + k + 4, ... in order, one accumulator per column), combined
+// (v0 + v1) + (v2 + v3).  A narrow task's wavefront computes all four
+// partials, a wide task's wavefront k partial k (exchanged through local
+// memory, 3 * w * 64 doubles); only wavefront 0 of a wide task returns true.
+template <int W_, int NP>
+__device__ __attribute__((always_inline)) inline bool bwd_rowsum(const DevArgs &a, const SolTask &t, const double *y,
+                                                                  int q, int i0, int i1, double *red, double v[W_]) {
+    const TemplDev &T = *t.T;
+    const double *Lb = a.lpan + T.lbase;
     const double *y0 = y + T.dbase;
-    const uint32_t nbu = uint32_t(nb), blu = uint32_t(W.bl), pc0 = uint32_t(cs(T.panel_off)[s] + p * r);
-    double *yb = y + T.dbase + W.bl;
     const double *xb = y + a.dint + T.bd0;
-    // partial q: rounds of 8 rows c = q, q + 4, ... from row w; the tail to partial 0
-    auto part = [&](int q) {
-        double acc[8];
+    const int n = T.n, w = t.w;
+    const uint32_t nb = t.nb, bl = t.bl, po = t.po, ur = uint32_t(t.r);
+    const int32_t *__restrict__ R_ = T.sup_rows + cs(T.sup_rowptr)[t.s];
+    auto at = [&](int col, int row) { return (po + uint32_t(col) * ur + uint32_t(row)) * nb + bl; };
+    double acc[NP][W_];
 #pragma unroll
-        for (int u = 0; u < 8; u++) acc[u] = 0.0;
-        auto round = [&](auto R, int i) {
-            double x[R.value];
+    for (int k = 0; k < NP; k++)
 #pragma unroll
-            for (int u = 0; u < R.value; u++) {
-                const int ri = cs(R_)[i + u];
-                const double xv = ri < n ? ld32(y0, uint32_t(ri) * nbu + blu) : xb[ri - n];
-                x[u] = ld32(Lb, (pc0 + uint32_t(i + u)) * nbu + blu) * xv;
-            }
+        for (int p = 0; p < W_; p++) acc[k][p] = 0.0;
+    // rows in groups of four (one per partial); a pass loads KP rows of a
+    // group (all four partials: KP = 2 or 4 by width) or G_ groups' row of
+    // the wavefront's own partial, so that about 16 loads are in flight
+    constexpr int KP = NP == 4 ? (W_ >= 8 ? 2 : 4) : 1;
+    constexpr int G_ = NP == 4 ? 1 : (W_ <= 4 ? 4 : (W_ <= 8 ? 2 : 1));
+    const int k0 = NP == 4 ? 0 : q;
+    for (int g0 = i0; g0 < i1; g0 += 4 * G_) {
 #pragma unroll
-            for (int u = 0; u < R.value; u++) acc[u] += x[u];
-        };
-        const int nc = (r - w) >> 3;
-        for (int c = q; c < nc; c += kSplit) round(std::integral_constant<int, 8>(), w + 8 * c);
-        if (q == 0) {
-            int i = w + 8 * nc;
-            if (i + 4 <= r) { round(std::integral_constant<int, 4>(), i); i += 4; }
-            if (i + 2 <= r) { round(std::integral_constant<int, 2>(), i); i += 2; }
-            if (i < r) round(std::integral_constant<int, 1>(), i);
+        for (int kh = 0; kh < NP; kh += KP) {
+            double xv[G_][KP], l[G_][KP][W_];
+#pragma unroll
+            for (int gg = 0; gg < G_; gg++)
+#pragma unroll
+                for (int k = 0; k < KP; k++) {
+                    const int i = g0 + 4 * gg + k0 + kh + k, ic = i < i1 ? i : i1 - 1;
+                    const int ri = cs(R_)[ic];
+                    xv[gg][k] = ri < n ? ld32(y0, uint32_t(ri) * nb + bl) : xb[ri - n];
+#pragma unroll
+                    for (int p = 0; p < W_; p++) l[gg][k][p] = p < w ? ld32(Lb, at(p, ic)) : 0.0;
+                }
+#pragma unroll
+            for (int gg = 0; gg < G_; gg++)
+#pragma unroll
+                for (int k = 0; k < KP; k++) {
+                    if (g0 + 4 * gg + k0 + kh + k >= i1) continue;
+#pragma unroll
+                    for (int p = 0; p < W_; p++)
+                        if (p < w) acc[kh + k][p] = fma(l[gg][k][p], xv[gg][k], acc[kh + k][p]);
+                }
         }
-        return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    };
-    double v = split_sum<NW>(part);
-    if (!split_combine<NW>(v)) return;
-    // the column's D^-1 is applied here, just before its update
-    const int64_t c = int64_t(f + p) * nb;
-    if (W.on) yb[c] = yb[c] / a.dval[T.dbase + W.bl + c] - v;
+    }
+    if constexpr (NP == 4) {
+#pragma unroll
+        for (int p = 0; p < W_; p++) v[p] = (acc[0][p] + acc[1][p]) + (acc[2][p] + acc[3][p]);
+        return true;
+    } else {
+        const int lane = lane_id();
+        if (q > 0) {
+#pragma unroll
+            for (int p = 0; p < W_; p++)
+                if (p < w) red[((q - 1) * w + p) * 64 + lane] = acc[0][p];
+        }
+        __syncthreads();
+        if (q > 0) return false;
+#pragma unroll
+        for (int p = 0; p < W_; p++)
+            v[p] = p < w ? (acc[0][p] + red[p * 64 + lane]) + (red[(w + p) * 64 + lane] + red[(2 * w + p) * 64 + lane])
+                         : 0.0;
+        return true;
+    }
 }
 
-// unit upper triangular solve with the transposed diagonal block:
-// x_k = y_k - sum_{j > k} L(j, k) x_j, taken right-looking from the last
-// column: once x_j is final, x_k -= L(j,k) x_j for every k < j (the loads
-// of L do not depend on x)
-__global__ __launch_bounds__(kWG) void k_sol_bwd_diag(DevArgs a, double *y, const Work *__restrict__ wl, int nw) {
-    const int wid = wave_id();
-    if (wid >= nw) return;
-    const Lane W = lane_work(a, wl, wid);
-    const TemplDev &T = *W.T;
-    const uint32_t nb = uint32_t(W.nb), bl = uint32_t(W.bl);
-    const int s = W.k;
-    const int f = cs(T.sup_first)[s], w = cs(T.sup_first)[s + 1] - f;
-    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s];
+template <int W_, int NP>
+__device__ __attribute__((always_inline)) inline void sol_bwd_task(const DevArgs &a, const SolTask &t, double *y, int q,
+                                                                    double *red) {
+    double v[W_];
+    if (!bwd_rowsum<W_, NP>(a, t, y, q, t.w, t.rnb, red, v)) return;
+    const TemplDev &T = *t.T;
     const double *Lb = a.lpan + T.lbase;
     double *y0 = y + T.dbase;
-    const uint32_t po = uint32_t(cs(T.panel_off)[s]);
-    auto at = [&](int col, int row) { return (po + uint32_t(col) * uint32_t(r) + uint32_t(row)) * nb + bl; };
-    auto yi = [&](int j) { return uint32_t(f + j) * nb + bl; };
-    by_width(w, [&](auto Wc) {
-        constexpr int W_ = decltype(Wc)::value;
-        const int wl1 = w - 1;
-        double x[W_];
+    const int w = t.w, wl1 = w - 1;
+    const uint32_t nb = t.nb, bl = t.bl, po = t.po, ur = uint32_t(t.r);
+    auto at = [&](int col, int row) { return (po + uint32_t(col) * ur + uint32_t(row)) * nb + bl; };
+    double x[W_];
 #pragma unroll
-        for (int j = 0; j < W_; j++) x[j] = ld32(y0, yi(j < w ? j : wl1));
+    for (int j = 0; j < W_; j++) x[j] = ld32(y0, uint32_t(t.f + (j < w ? j : wl1)) * nb + bl) - v[j];
 #pragma unroll
-        for (int j = W_ - 1; j > 0; j--) {
-            const int jc = j < w ? j : wl1;
+    for (int j = W_ - 1; j > 0; j--) {
+        const int jc = j < w ? j : wl1;
 #pragma unroll
-            for (int k = 0; k < j; k++) {
-                const double l = ld32(Lb, at(k < w ? k : wl1, jc));
-                x[k] -= (j < w ? l : 0.0) * x[j];
+        for (int k = 0; k < j; k++) {
+            const double l = ld32(Lb, at(k < w ? k : wl1, jc));
+            x[k] = fma(-(j < w ? l : 0.0), x[j], x[k]);
+        }
+    }
+    if (t.on) {
+#pragma unroll
+        for (int j = 0; j < W_; j++)
+            if (j < w) st32(y0, uint32_t(t.f + j) * nb + bl, x[j]);
+    }
+}
+
+// Border step of the backward pass, one task per block column j (of a group
+// of 64 blocks): y_j <- y_j / d_j - t_j, t_j = sum over the border rows b of
+// j's panel column of L(b, j) x_b, as four partials over those rows (partial
+// k takes rows k, k + 4, ... in order) combined (t0 + t1) + (t2 + t3).  The
+// rows of one panel column are contiguous.  A narrow task's wavefront
+// computes all four partials; a wide task (long border column) is a
+// workgroup whose wavefront k computes partial k.
+template <int NP>
+__device__ __attribute__((always_inline)) inline void bwd_col_partials(const DevArgs &a, const TemplDev &T, const double *y,
+                                                                        int s, int p, uint32_t nb, uint32_t bl, int k0,
+                                                                        double acc[NP]) {
+    const int r = cs(T.sup_rowptr)[s + 1] - cs(T.sup_rowptr)[s], rnb = cs(T.sup_rnb)[s];
+    const int32_t *__restrict__ R_ = T.sup_rows + cs(T.sup_rowptr)[s];
+    const double *Lc = a.lpan + T.lbase;
+    const uint32_t c0 = uint32_t(cs(T.panel_off)[s] + p * r);
+    const double *xb = y + a.dint + T.bd0;
+    const int n = T.n;
+#pragma unroll
+    for (int k = 0; k < NP; k++) acc[k] = 0.0;
+    constexpr int G_ = NP == 4 ? 2 : 8;          // row groups of four per pass (8 rows in flight)
+    for (int g0 = rnb; g0 < r; g0 += 4 * G_) {
+        double l[G_][NP], xv[G_][NP];
+#pragma unroll
+        for (int gg = 0; gg < G_; gg++)
+#pragma unroll
+            for (int k = 0; k < NP; k++) {
+                const int i = g0 + 4 * gg + k0 + k, ic = i < r ? i : r - 1;
+                l[gg][k] = ld32(Lc, (c0 + uint32_t(ic)) * nb + bl);
+                xv[gg][k] = xb[cs(R_)[ic] - n];
             }
-        }
-        if (W.on) {
 #pragma unroll
-            for (int j = 0; j < W_ - 1; j++)
-                if (j < w - 1) st32(y0, yi(j), x[j]);
-        }
-    });
+        for (int gg = 0; gg < G_; gg++)
+#pragma unroll
+            for (int k = 0; k < NP; k++)
+                if (g0 + 4 * gg + k0 + k < r) acc[k] = fma(l[gg][k], xv[gg][k], acc[k]);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_sol_bwd_border(DevArgs a, double *y, const Work *__restrict__ wl, int nw,
+                                                        int nnar, int64_t ys) {
+    __shared__ double red[3][64];
+    y += blockIdx.y * ys;
+    int item, q, nwv;
+    if (!sol_item(nw, nnar, item, q, nwv)) return;
+    const Lane W = lane_work(a, wl, item);
+    const TemplDev &T = *W.T;
+    const int j = W.k & ~kWideFlag;
+    const int s = cs(T.col_sup)[j], p = j - cs(T.sup_first)[s];
+    const uint32_t nb = uint32_t(W.nb), bl = uint32_t(W.bl);
+    double v;
+    if (nwv == 1) {
+        double acc[4];
+        bwd_col_partials<4>(a, T, y, s, p, nb, bl, 0, acc);
+        v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    } else {
+        double acc[1];
+        bwd_col_partials<1>(a, T, y, s, p, nb, bl, q, acc);
+        const int lane = lane_id();
+        if (q > 0) red[q - 1][lane] = acc[0];
+        __syncthreads();
+        if (q > 0) return;
+        v = (acc[0] + red[0][lane]) + (red[1][lane] + red[2][lane]);
+    }
+    if (!W.on) return;
+    double *y0 = y + T.dbase;
+    const double *d0 = a.dval + T.dbase;
+    const uint32_t c = uint32_t(j) * nb + bl;
+    st32(y0, c, ld32(y0, c) / ld32(d0, c) - v);
+}
+
+template <int WMAX>
+__global__ __launch_bounds__(kWG, WMAX <= 8 ? 4 : 2) void k_sol_bwd(DevArgs a, double *y, const Work *__restrict__ wl,
+                                                                    int nw, int nnar, int64_t ys) {
+    extern __shared__ double red[];
+    y += blockIdx.y * ys;
+    int item, q, nwv;
+    if (!sol_item(nw, nnar, item, q, nwv)) return;
+    const SolTask t = sol_task(a, wl, item);
+    if (nwv == 1) {
+        by_width_max<kNarrowW>(t.w, [&](auto Wc) { sol_bwd_task<decltype(Wc)::value, 4>(a, t, y, q, red); });
+    } else {
+        by_width_max<WMAX>(t.w, [&](auto Wc) { sol_bwd_task<decltype(Wc)::value, 1>(a, t, y, q, red); });
+    }
 }
 
 // ------------------------------------------------------------------ backward error
@@ -2202,20 +2381,29 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (a.dint && l.src)
                 hipLaunchKernelGGL(k_sol_load_int, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.src, l.y);
             else if (a.dint)
-                hipLaunchKernelGGL(k_sol_load, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.b, l.y);
+                hipLaunchKernelGGL(k_sol_load, dim3(unsigned(a.tiles), unsigned(l.nrhs)), dim3(256), 0, st, a, l.b, l.y,
+                                   l.bld, l.ys);
             break;
         case NCL_K_SOL_FWD_GATHER:
-            if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_fwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
-            else if (l.nw) hipLaunchKernelGGL(k_sol_fwd_gather<kSplit>, dim3(l.nw), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            if (l.nw > kSplitTasks)
+                hipLaunchKernelGGL(k_sol_fwd_gather<1>, dim3(waves_grid(l.nw), unsigned(l.nrhs)), dim3(kWG), 0, st, a, l.y,
+                                   l.wl, l.nw, l.ys);
+            else if (l.nw)
+                hipLaunchKernelGGL(k_sol_fwd_gather<kSplit>, dim3(unsigned(l.nw), unsigned(l.nrhs)), dim3(kWG), 0, st, a,
+                                   l.y, l.wl, l.nw, l.ys);
             break;
         case NCL_K_SOL_FWD_DIAG:
-            if (l.nw) hipLaunchKernelGGL(k_sol_fwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+            if (l.nw)
+                hipLaunchKernelGGL(k_sol_fwd_diag, dim3(waves_grid(l.nw), unsigned(l.nrhs)), dim3(kWG), 0, st, a, l.y, l.wl,
+                                   l.nw, l.ys);
             break;
         case NCL_K_SOL_BPART:
             if (l.nw > kSplitTasks)
-                hipLaunchKernelGGL(k_sol_bpart<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
+                hipLaunchKernelGGL(k_sol_bpart<1>, dim3(waves_grid(l.nw), unsigned(l.nrhs)), dim3(kWG), 0, st, a, l.y,
+                                   l.cpart, l.wl, l.nw, l.ys, l.cps);
             else if (l.nw)
-                hipLaunchKernelGGL(k_sol_bpart<kSplit>, dim3(l.nw), dim3(kWG), 0, st, a, l.y, l.cpart, l.wl, l.nw);
+                hipLaunchKernelGGL(k_sol_bpart<kSplit>, dim3(unsigned(l.nw), unsigned(l.nrhs)), dim3(kWG), 0, st, a, l.y,
+                                   l.cpart, l.wl, l.nw, l.ys, l.cps);
             break;
         case NCL_K_SOL_BORDER:
             if (a.max_nbd > 0) {
@@ -2229,22 +2417,32 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lb));
                     if (e != hipSuccess) return e;
                 }
-                hipLaunchKernelGGL(k_sol_border, dim3(a.ninst), dim3(kBorderThreads), lb, st, a, l.b, l.x, l.y, l.cpart,
-                                   int64_t(lb), l.accumulate ? 1 : 0);
+                hipLaunchKernelGGL(k_sol_border, dim3(unsigned(a.ninst), unsigned(l.nrhs)), dim3(kBorderThreads), lb, st, a,
+                                   l.b, l.x, l.y, l.cpart, int64_t(lb), l.accumulate ? 1 : 0, l.bld, l.ys, l.cps);
             }
             break;
-        case NCL_K_SOL_BWD_GATHER:
-            if (l.nw > kSplitTasks) hipLaunchKernelGGL(k_sol_bwd_gather<1>, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
-            else if (l.nw) hipLaunchKernelGGL(k_sol_bwd_gather<kSplit>, dim3(l.nw), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+        case NCL_K_SOL_BWD_BORDER:
+            if (l.nw)
+                hipLaunchKernelGGL(k_sol_bwd_border, dim3(unsigned((l.nnar + 3) / 4 + (l.nw - l.nnar)), unsigned(l.nrhs)),
+                                   dim3(kWG), 0, st, a, l.y, l.wl, l.nw, l.nnar, l.ys);
             break;
-        case NCL_K_SOL_BWD_DIAG:
-            if (l.nw) hipLaunchKernelGGL(k_sol_bwd_diag, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.y, l.wl, l.nw);
+        case NCL_K_SOL_BWD:
+            if (l.nw) {
+                const size_t lb = l.nw > l.nnar ? size_t(3) * size_t(l.wmax) * 64 * sizeof(double) : 0;
+                const dim3 g(unsigned((l.nnar + 3) / 4 + (l.nw - l.nnar)), unsigned(l.nrhs));
+                if (l.wmax <= 8) hipLaunchKernelGGL(k_sol_bwd<8>, g, dim3(kWG), lb, st, a, l.y, l.wl, l.nw, l.nnar, l.ys);
+                else if (l.wmax <= 16)
+                    hipLaunchKernelGGL(k_sol_bwd<16>, g, dim3(kWG), lb, st, a, l.y, l.wl, l.nw, l.nnar, l.ys);
+                else hipLaunchKernelGGL(k_sol_bwd<32>, g, dim3(kWG), lb, st, a, l.y, l.wl, l.nw, l.nnar, l.ys);
+            }
             break;
         case NCL_K_SOL_STORE:
             if (a.dint && l.accumulate)
-                hipLaunchKernelGGL(k_sol_store<true>, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.y, l.x);
+                hipLaunchKernelGGL(k_sol_store<true>, dim3(unsigned(a.tiles), unsigned(l.nrhs)), dim3(256), 0, st, a, l.y, l.x,
+                                   l.ys, l.bld);
             else if (a.dint)
-                hipLaunchKernelGGL(k_sol_store<false>, dim3(unsigned(a.tiles)), dim3(256), 0, st, a, l.y, l.x);
+                hipLaunchKernelGGL(k_sol_store<false>, dim3(unsigned(a.tiles), unsigned(l.nrhs)), dim3(256), 0, st, a, l.y,
+                                   l.x, l.ys, l.bld);
             break;
         case NCL_K_BERR_ROWS:
             if (a.rows_waves)

@@ -23,6 +23,12 @@ constexpr int kNarrowW = 8;          // diagonal blocks up to this width are fac
 constexpr int32_t kNarrowFlag = 0x40000000;   // marks such a supernode in the diagonal-block work list
 constexpr int32_t kPivotFlag = 0x20000000;    // marks a width-1 supernode there (its pivot and column)
 constexpr int32_t kBorderFlag = int32_t(1u << 30);   // slot refers to the border K_bb pattern
+// A supernode of a solve level is "wide" (a workgroup of four wavefronts
+// shares it) when it is wider than kNarrowW or has more than kSolWideRows
+// rows below its diagonal block; otherwise one wavefront takes it.
+constexpr int kSolWideRows = 24;
+constexpr int32_t kWideFlag = 0x40000000;     // marks a wide supernode in the solve work lists
+constexpr int kSolBorderWideRows = 32;        // a border column this long takes a workgroup
 
 // ---------------------------------------------------------------- device tables
 
@@ -118,6 +124,10 @@ struct TemplDev {
     // border rows: terms L[b, k] y_k of the border right-hand side
     const int32_t *bterm_ptr;      // [nbd+1]
     const Term *bterms;
+    // backward solve: a panel's block rows are its first sup_rnb[s] rows,
+    // its border rows the rest
+    const int32_t *sup_rnb;        // [nsup]
+    const int32_t *col_sup;        // [n] supernode of each column
     // border Schur tiles: (i, j0) and item range of each tile
     const int32_t *stile_ij;       // [ntiles][2]
     const int32_t *stile_ptr;      // [ntiles + 1]
@@ -202,8 +212,9 @@ struct Template {
     // schedule
     int nlev = 0;
     std::vector<int32_t> level;         // [nsup]
-    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr, bterm_ptr, sterm_ptr,
+    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr, sterm_ptr,
         stile_ij, stile_ptr;
+    std::vector<int32_t> bterm_ptr, sup_rnb, col_sup;   // solves: border terms, block rows per panel, column -> supernode
     std::vector<STile> stiles;
     std::vector<std::vector<int32_t>> lev_tasks;   // row tasks of each level
     std::vector<Term> terms, bterms, sterms;
@@ -223,10 +234,19 @@ struct Schedule {
     // more wide (k = row task)
     std::vector<int32_t> a_ptr, b_ptr, c_ptr;           // [nlev+1]
     std::vector<Work> a, b, c;
-    // solve: forward gathers of the diagonal rows, diagonal solves of wide supernodes
-    // (backward: gathers of every diagonal row, then the same diagonal solves)
-    std::vector<int32_t> f_ptr, d_ptr, g_ptr;           // [nlev+1]
-    std::vector<Work> f, d, g;
+    // solve, forward: gathers of the diagonal rows (k = row task), diagonal
+    // solves of wide supernodes (k = supernode)
+    std::vector<int32_t> f_ptr, d_ptr;                  // [nlev+1]
+    std::vector<Work> f, d;
+    // solve, backward: the supernodes of each level (k = supernode,
+    // kWideFlag on the wide ones), per level the narrow ones first
+    std::vector<int32_t> sn_ptr, sn_nar, sn_wmax;       // [nlev+1], [nlev] narrow items, widest supernode
+    std::vector<Work> sn;
+    // the backward border step: every block column (k = column, kWideFlag
+    // on long border columns; narrow first), its border rows' part of the
+    // backward sums and D^-1
+    std::vector<Work> sb;
+    int sb_nar = 0;
     std::vector<Work> bpart;                            // border rows x block groups (forward partials)
     std::vector<Work> schur;                            // border entries x block groups
 };
@@ -310,7 +330,7 @@ struct Handle {
         const uint8_t *bprim = nullptr;
     } d;
     // offsets of each work list inside d.work
-    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_g = 0, w_bpart = 0, w_schur = 0;
+    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_sn = 0, w_sb = 0, w_bpart = 0, w_schur = 0;
     // per kernel kind: launches and algorithmic bytes of one step
     std::vector<int64_t> km_launch, km_bytes;
     // event profiling of one kernel kind (events are hipEvent_t, in pairs)

@@ -194,7 +194,17 @@ int build_template_schedule(Template &t, int nbd) {
     t.bterms.clear();
     for (int b = 0; b < nbd; b++) {
         for (auto &x : bp[b]) push_cols(t.bterms, x.first, x.second, x.second);
+        if (int64_t(t.bterms.size()) > kTermMax) return NCL_ERR_ARG;
         t.bterm_ptr[b + 1] = int32_t(t.bterms.size());
+    }
+    // backward solve: block rows of each panel (border rows come last)
+    t.sup_rnb.assign(ns, 0);
+    t.col_sup = col2sup;
+    for (int s = 0; s < ns; s++) {
+        int rnb = t.srp[s + 1] - t.srp[s];
+        while (rnb > 0 && t.sri[t.srp[s] + rnb - 1] >= n) rnb--;
+        if (rnb < t.sup[s + 1] - t.sup[s]) return NCL_ERR_ARG;
+        t.sup_rnb[s] = rnb;
     }
     // border Schur terms: the common panels of each pair of border rows
     const int64_t npk = int64_t(nbd) * (nbd + 1) / 2;
@@ -295,13 +305,58 @@ int build_schedule(Handle &h) {
     S.c_ptr.assign(1, 0);
     S.f_ptr.assign(1, 0);
     S.d_ptr.assign(1, 0);
-    S.g_ptr.assign(1, 0);
+    S.sn_ptr.assign(1, 0);
+    S.sn_nar.clear();
+    S.sn_wmax.clear();
+    S.sn.clear();
+    // backward border step: every supernode of every template and group,
+    // narrow ones first
+    S.sb.clear();
+    for (int wide = 0; wide < 2; wide++) {
+        for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
+            const Template &t = h.tmpl[ti];
+            for (int g = 0; g < groups(t, 64); g++)
+                for (int j = 0; j < t.n; j++) {
+                    const int s = t.col_sup[j];
+                    const bool wd = t.srp[s + 1] - t.srp[s] - t.sup_rnb[s] > kSolBorderWideRows;
+                    if (wd != (wide == 1)) continue;
+                    S.sb.push_back(Work{tg(ti, g), j | (wd ? kWideFlag : 0)});
+                }
+        }
+        if (!wide) S.sb_nar = int32_t(S.sb.size());
+    }
     // Work lists are group-major: within a (level, template) every item of
     // one block group comes before the next group's, so that contiguous runs
     // of a list share the same blocks' panels.  The list kernels map
     // contiguous workgroup ranges to one XCD each, so such a run is served
     // by one L2.
     for (int l = 0; l < S.nlev; l++) {
+        // solve items: the level's narrow supernodes of every template and
+        // group, then the wide ones
+        int wmax = 1;
+        for (int wide = 0; wide < 2; wide++) {
+            for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
+                const Template &t = h.tmpl[ti];
+                if (l >= t.nlev) continue;
+                const int ng64 = groups(t, 64);
+                for (int g = 0; g < ng64; g++) {
+                    int last_s = -1;
+                    for (int32_t k : t.lev_tasks[l]) {
+                        const int s = t.task_s[k];
+                        if (s == last_s) continue;
+                        last_s = s;
+                        const int w = t.sup[s + 1] - t.sup[s];
+                        const bool wd = w > kNarrowW || t.sup_rnb[s] - w > kSolWideRows;
+                        if (wd != (wide == 1)) continue;
+                        S.sn.push_back(Work{tg(ti, g), s | (wd ? kWideFlag : 0)});
+                        wmax = std::max(wmax, w);
+                    }
+                }
+            }
+            if (!wide) S.sn_nar.push_back(int32_t(S.sn.size()) - S.sn_ptr.back());
+        }
+        S.sn_ptr.push_back(int32_t(S.sn.size()));
+        S.sn_wmax.push_back(wmax);
         for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
             const Template &t = h.tmpl[ti];
             if (l >= t.nlev) continue;
@@ -315,12 +370,10 @@ int build_schedule(Handle &h) {
                     const int cend = p < w ? p + 1 : w;     // lower triangle of the diagonal block
                     for (int c = 0; c < cend; c++) S.a.push_back(Work{tg(ti, g), t.task_cbase[k] + c});
                     if (w > 1 && p >= w) S.c.push_back(Work{tg(ti, g), k});
-                    if (p < w) {
-                        // the diagonal entry's items are exactly the descendants holding this row
-                        const int e = t.task_cbase[k] + p;
-                        if (t.ent_tptr[e + 1] > t.ent_tptr[e]) S.f.push_back(Work{tg(ti, g), k});
-                        S.g.push_back(Work{tg(ti, g), k});
-                    }
+                    // forward solve: the diagonal entry's terms are exactly the
+                    // descendants holding this row
+                    if (p < w && t.ent_tptr[t.task_cbase[k] + p + 1] > t.ent_tptr[t.task_cbase[k] + p])
+                        S.f.push_back(Work{tg(ti, g), k});
                     if (w > 1 && s != last_s) S.d.push_back(Work{tg(ti, g), s});
                     last_s = s;
                 }
@@ -349,11 +402,11 @@ int build_schedule(Handle &h) {
             }
         }
         S.a_ptr.push_back(int32_t(S.a.size()));
-        S.b_ptr.push_back(int32_t(S.b.size()));
-        S.c_ptr.push_back(int32_t(S.c.size()));
         S.f_ptr.push_back(int32_t(S.f.size()));
         S.d_ptr.push_back(int32_t(S.d.size()));
-        S.g_ptr.push_back(int32_t(S.g.size()));
+        S.b_ptr.push_back(int32_t(S.b.size()));
+        S.c_ptr.push_back(int32_t(S.c.size()));
+
     }
     for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
         const Template &t = h.tmpl[ti];

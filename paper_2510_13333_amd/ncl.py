@@ -21,7 +21,7 @@ NCL_PVPQ = 1
 # kernel kinds (NCL_K_* of ncl_kkt.h), in enum order
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
            "border_factor", "status_init", "status", "sol_load", "sol_fwd_gather", "sol_fwd_diag", "sol_bpart",
-           "sol_border", "sol_bwd_gather", "sol_bwd_diag", "sol_store", "residual", "max_step", "interleave",
+           "sol_border", "sol_bwd_border", "sol_bwd", "sol_store", "residual", "max_step", "interleave",
            "border_panel", "border_update", "berr_rows", "berr_border", "berr_final"]
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
@@ -332,6 +332,16 @@ class KKT:
             out = torch.empty_like(b2)
         _check(fn, getattr(load(), fn)(self._h, self._dev(b2), self._dev(out), int(nrhs), int(ld), _stream_ptr()))
         return out if b.dim() == 2 else out.reshape(-1)
+
+    def _solve_ld(self, b, out, ld):
+        """Solve nrhs columns stored ld apart (b, out: device tensors whose
+        data start at column 0 of the first right-hand side)."""
+        import torch  # noqa: F401
+        nrhs = b.shape[0]
+        _check("ncl_kkt_solve", load().ncl_kkt_solve(self._h, ctypes.c_void_p(b.data_ptr()),
+                                                     ctypes.c_void_p(out.data_ptr()), int(nrhs), int(ld),
+                                                     _stream_ptr()))
+        return out
 
     def solve(self, b, out=None):
         """x = K^{-1} b; b is (N,) or (nrhs, N) float64 on the device, layout order."""

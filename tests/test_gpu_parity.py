@@ -189,6 +189,30 @@ def test_determinism_and_adjoint():
     assert np.array_equal(Bi.cpu().numpy(), X1)
 
 
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_multi_rhs_bitwise_equals_single(cfg):
+    """Every launch of a solve covers all right-hand sides; each column's
+    arithmetic is the single-column solve's, bit for bit (also the adjoint
+    solve and a leading dimension above N)."""
+    net = G.config_network(cfg)
+    z, s = G.draw_point(net, cfg)
+    k = KKT(net).bind(nrhs_max=4)
+    k.assemble(dev(z), dev(s), net.rho)
+    k.factor()
+    B = G.draw_rhs(k.N, 4, cfg, iteration=3)
+    Bp = np.zeros((4, k.N + 7))
+    Bp[:, :k.N] = B
+    Bd = dev(Bp)[:, :k.N]                      # leading dimension N + 7
+    X4 = torch.empty((4, k.N + 7), dtype=torch.float64, device="cuda")
+    k._solve_ld(Bd, X4, k.N + 7)
+    X4 = X4[:, :k.N].cpu().numpy()
+    Xa = k.solve_adjoint(dev(B)).cpu().numpy()
+    for r in range(4):
+        x1 = k.solve(dev(B[r])).cpu().numpy()
+        assert np.array_equal(X4[r], x1), r
+        assert np.array_equal(Xa[r], x1), r
+
+
 def test_set_values_seam_random_quasidefinite():
     """Arbitrary quasi-definite values on a block-arrowhead pattern through
     ncl_kkt_analyze_pattern / ncl_kkt_set_values."""

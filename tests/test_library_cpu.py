@@ -231,9 +231,10 @@ def test_kernel_model_counts():
     for n in ("assemble", "border_schur", "border_sum", "border_factor", "status", "sol_load", "sol_bpart",
               "sol_border", "sol_store"):
         assert m[n][0] == 1 and m[n][1] > 0, n
-    for n in ("fac_gather", "fac_rows", "sol_bwd_gather"):
+    for n in ("fac_gather", "fac_rows", "sol_fwd_gather", "sol_bwd"):
         assert m[n][0] >= 5
-    assert m["sol_fwd_diag"] == m["sol_bwd_diag"]
+    # the backward pass: one launch per level, plus one border step
+    assert m["sol_bwd"][0] == m["fac_diag"][0] and m["sol_bwd_border"][0] == 1
     # assembly reads z and sigma and writes every K value
     assert m["assemble"][1] == 8 * (2 * k.N + k.nnzK)
 
