@@ -73,7 +73,8 @@ enum {
     NCL_ERR_STATE = -4,      /* call out of order (no workspace, not factored, ...) */
     NCL_ERR_ZERO_PIVOT = -5, /* a pivot was exactly zero */
     NCL_ERR_INERTIA = -6,    /* a pivot had the wrong sign (primal must be >0, dual <0) */
-    NCL_ERR_NONFINITE = -7   /* a pivot was NaN or infinite */
+    NCL_ERR_NONFINITE = -7,  /* a pivot was NaN or infinite */
+    NCL_ERR_NOT_CONVERGED = -8 /* the dispatch map's Newton method ran out of steps */
 };
 
 #define NCL_MAX_BORDER 600   /* largest first-stage border (dense factor in local memory) */
@@ -384,6 +385,54 @@ int ncl_kkt_residual(ncl_kkt *h, const ncl_nlp *p, const double *z, double *F, d
  * bounds, flow-row multipliers positive).  Asynchronous on stream. */
 int ncl_kkt_max_step(ncl_kkt *h, const ncl_nlp *p, const double *z, const double *dz, double tau, double *alpha,
                      void *stream);
+
+/* Newton solve of F(z; pd) = 0 for the dispatch map, every step of it in
+ * the library's kernels (the host only orders them and reads scalars back):
+ * per step the exact K at z (NCL_NO_SHIFT, sigma from ncl_kkt_residual),
+ * factored; if its inertia is not (n, m) (zero or non-finite pivots, or the
+ * wrong counts), dw is added on the primal diagonal, from a third of the
+ * last accepted dw (or 1e-4) growing x8 until it is (the inertia correction
+ * of Section V-C, as a primal shift); dz = -K^{-1} F; the fraction-to-
+ * boundary step (tau 0.995) and backtracking on |F|_2 (sufficient decrease
+ * 1e-4 alpha, halving down to 1e-10).  Converged when every |dz_i| <=
+ * step_tol (1 + |z_i|) (1e-6 at the continuation's intermediate barrier
+ * values), the last step then taken when feasible; also when backtracking
+ * stalls below 1e-10 with every |dz_i| <= floor_tol (1 + |z_i|) (|F| at its
+ * rounding floor).  With from_default the start is vm = 1, pg = pmax / 2,
+ * flow-row multipliers mu / smax2, and the barrier is continued through 10,
+ * 3, 1, 0.3, 0.1, 0.03 (those above mu) down to mu; else the solve starts
+ * from dz_state at mu.  On return the exact K at the solution is factored
+ * (for ncl_kkt_dispatch_vjp).  dz_state: DEVICE [N] state (in: start
+ * unless from_default; out: solution).  dwork: DEVICE, 7 N + 8 doubles.
+ * Synchronises the stream at every step.  NCL_ERR_NOT_CONVERGED after
+ * maxit steps at one barrier value; NCL_ERR_INERTIA if no shift up to 1e12
+ * gives the inertia, or the exact K at the solution lacks it. */
+typedef struct {
+    double step_tol;         /* e.g. 1e-10 */
+    double floor_tol;        /* e.g. 1e-6 */
+    int32_t maxit;           /* Newton steps per barrier value */
+    int32_t from_default;    /* 1: default start and barrier continuation */
+    int32_t iterations;      /* out: Newton steps taken */
+    int32_t pad;
+    double dw_last;          /* in/out: the last accepted inertia shift (0 at first) */
+} ncl_newton_opts;
+int ncl_kkt_dispatch_newton(ncl_kkt *h, const ncl_nlp *p, double *dz_state, double *dwork, ncl_newton_opts *opts,
+                            void *stream);
+
+/* Outputs of the map at state dz: *dphi (DEVICE, one double) = sum_g c2_g
+ * pg_g^2 (generators in order) and dpg (DEVICE [ng], may be NULL) = pg. */
+int ncl_kkt_dispatch_outputs(ncl_kkt *h, const double *dz, double *dphi, double *dpg, void *stream);
+
+/* Vector-Jacobian product of the map at its solution dz: with g the
+ * gradient of gphi phi + gpg . pg in z, a = K^{-T} g by one
+ * ncl_kkt_solve_adjoint on the stored factors (those ncl_kkt_dispatch_newton
+ * left), and dgpd[i] = -(sum over blocks of a at bus i's P row + qd_ratio
+ * times the same sum at its Q row) (implicit function theorem: loads enter
+ * F only through the balance rows).  dgphi: DEVICE one double; dgpg: DEVICE
+ * [ng] or NULL (zero); dgpd: DEVICE [nbus]; dwork: DEVICE 2 N doubles.
+ * NCL_ERR_STATE without usable factors. */
+int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const double *dgphi, const double *dgpg,
+                         double *dgpd, double *dwork, void *stream);
 
 /* ---------------------------------------------------------------- measurement
  * Kernel kinds: every launch of the library runs exactly one kernel of one

@@ -177,7 +177,7 @@ struct WsLayout {
 struct Plan {
     std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
     std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
-    size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, tables_end = 0;
+    size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, pg_col = 0, row_pq = 0, tables_end = 0;
     size_t kval = 0, lpan = 0, upan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
            xint = 0, bint = 0, rint = 0, rbuf = 0, epart = 0, total = 0;
 };
@@ -208,6 +208,42 @@ std::vector<ncl::Work> all_work(Handle &h) {
     app(S.bpart, h.w_bpart);
     app(S.schur, h.w_schur);
     return w;
+}
+
+// Dispatch-map tables of a single network without PV/PQ rows (empty
+// otherwise): the global column of each generator's pg, and the global P and
+// Q rows of every bus in every block.
+void dispatch_tables(Handle &h, std::vector<int64_t> &pgc, std::vector<int64_t> &rows) {
+    h.ng_disp = h.nbus_disp = 0;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_PVPQ)) return;
+    const ncl::Inst &I = h.inst[0];
+    for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
+        const Template &t = h.tmpl[h.block_tmpl[b]];
+        std::vector<int64_t> rp, rq;
+        for (int j = 0; j < t.n; j++) {
+            const int64_t c = h.block_col0[b] + j;
+            if (t.lkind[j] == ncl::LK_PG) pgc.push_back(c);
+            if (t.lkind[j] == ncl::LK_ROWP) rp.push_back(c);
+            if (t.lkind[j] == ncl::LK_ROWQ) rq.push_back(c);
+        }
+        if (int(rp.size()) != I.nb || int(rq.size()) != I.nb) {
+            pgc.clear();
+            rows.clear();
+            return;
+        }
+        for (int i = 0; i < I.nb; i++) {
+            rows.push_back(rp[i]);
+            rows.push_back(rq[i]);
+        }
+    }
+    for (int j = 0; j < std::min(I.nbd, I.ng); j++) pgc.push_back(I.bstart + j);
+    if (int(pgc.size()) != I.ng) {
+        pgc.clear();
+        rows.clear();
+        return;
+    }
+    h.ng_disp = I.ng;
+    h.nbus_disp = I.nb;
 }
 
 Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
@@ -268,6 +304,12 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         bprim.insert(bprim.end(), I.border_primal.begin(), I.border_primal.end());
     }
     p.bprim = L.vec(bprim);
+    {
+        std::vector<int64_t> pgc, rows;
+        dispatch_tables(h, pgc, rows);
+        p.pg_col = L.vec(pgc);
+        p.row_pq = L.vec(rows);
+    }
     p.tables_end = L.off;
     L.stage = nullptr;
     p.kval = L.take(nullptr, sizeof(double) * size_t(h.kint + h.nbb_tot));
@@ -329,6 +371,10 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.rbuf = h.d.rbuf;
     a.epart = h.d.epart;
     a.rows_wg = int((h.rows_waves + 3) / 4);
+    a.pg_col = h.d.pg_col;
+    a.row_pq = h.d.row_pq;
+    a.ng_disp = h.ng_disp;
+    a.nbus_disp = h.nbus_disp;
     return a;
 }
 
@@ -560,6 +606,7 @@ const char *ncl_status_string(int s) {
         case NCL_ERR_ZERO_PIVOT: return "zero pivot";
         case NCL_ERR_INERTIA: return "pivot of the wrong sign (inertia)";
         case NCL_ERR_NONFINITE: return "non-finite pivot";
+        case NCL_ERR_NOT_CONVERGED: return "Newton method did not converge";
         default: return "unknown status";
     }
 }
@@ -899,6 +946,8 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.d.rint = reinterpret_cast<double *>(base + p.rint);
     h.d.rbuf = reinterpret_cast<double *>(base + p.rbuf);
     h.d.epart = reinterpret_cast<double *>(base + p.epart);
+    h.d.pg_col = reinterpret_cast<const int64_t *>(base + p.pg_col);
+    h.d.row_pq = reinterpret_cast<const int64_t *>(base + p.row_pq);
     h.bound = true;
     h.factored = false;
     h.blocks_done = false;
@@ -1228,6 +1277,186 @@ int ncl_kkt_max_step(ncl_kkt *k, const ncl_nlp *p, const double *z, const double
     l.tau = tau;
     l.alpha = alpha;
     return hip_rc(run(h, NCL_K_MAX_STEP, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
+}
+
+// ---------------------------------------------------------------- dispatch map: Newton and adjoint
+
+namespace {
+
+struct Disp {
+    Handle &h;
+    ncl_kkt *k;
+    hipStream_t st;
+    ncl::DevArgs a;
+    double *sc;          // device scalars: norm, step excess, alpha
+    bool sync_read(const double *d, double &v) {
+        return hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess;
+    }
+    int residual(const ncl_nlp &q, const double *z, double *F, double *sig) {
+        ncl::LaunchArgs l;
+        l.z = z;
+        l.nlp = q;
+        l.rho = q.rho;
+        l.F = F;
+        l.sigma_out = sig;
+        return hip_rc(run(h, NCL_K_RESIDUAL, a, l, st));
+    }
+    int norm2(const double *x, double &v) {
+        if (ncl::launch_vec_reduce(h.N, x, nullptr, 0.0, 0, h.d.epart, sc, st) != hipSuccess) return NCL_ERR_HIP;
+        return sync_read(sc, v) ? NCL_OK : NCL_ERR_HIP;
+    }
+    // max_i |dz_i| - tol (1 + |z_i|): <= 0 when every step component is small
+    int excess(const double *z, const double *dz, double tol, double &v) {
+        if (ncl::launch_vec_reduce(h.N, dz, z, tol, 1, h.d.epart, sc + 1, st) != hipSuccess) return NCL_ERR_HIP;
+        return sync_read(sc + 1, v) ? NCL_OK : NCL_ERR_HIP;
+    }
+    int max_step(const ncl_nlp &q, const double *z, const double *dz, double &al) {
+        const int rc = ncl_kkt_max_step(k, &q, z, dz, 0.995, sc + 2, st);
+        if (rc) return rc;
+        return sync_read(sc + 2, al) ? NCL_OK : NCL_ERR_HIP;
+    }
+    int axpy(double al, const double *x, const double *y, double *out) {
+        return hip_rc(ncl::launch_vec_axpy(h.N, al, x, y, out, st));
+    }
+    // assemble the exact K (no diagonal shift) at (z, sig) and factor; ok:
+    // the inertia of a strict local minimum, (n, m), no zero or non-finite
+    // pivot (single pivots may carry the other sign)
+    int factor_min(const double *z, const double *sig, double rho, bool &ok) {
+        ncl_kkt_point pt{z, sig, rho, NCL_NO_SHIFT};
+        int rc = ncl_kkt_assemble(k, &pt, st);
+        if (!rc) rc = ncl_kkt_factor(k, st);
+        ncl_kkt_report rep{};
+        if (!rc) rc = ncl_kkt_info(k, &rep, st);
+        if (rc) return rc;
+        ok = (rep.status == NCL_OK || rep.status == NCL_ERR_INERTIA) && rep.nzero == 0 && rep.nnonfinite == 0 &&
+             rep.npos == h.nprimal && rep.nneg == h.N - h.nprimal;
+        return NCL_OK;
+    }
+};
+
+}  // namespace
+
+int ncl_kkt_dispatch_newton(ncl_kkt *k, const ncl_nlp *p, double *dz_state, double *dwork, ncl_newton_opts *o,
+                            void *stream) {
+    if (!k || !dz_state || !dwork || !o || !(o->step_tol > 0) || !(o->floor_tol > 0) || o->maxit < 1) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    int rc = nlp_check(h, p);
+    if (rc) return rc;
+    if (h.ng_disp == 0 || ncl::vec_reduce_partials(h.N) > 8 * berr_partials(h)) return NCL_ERR_ARG;
+    const int64_t N = h.N;
+    double *F = dwork, *sig = F + N, *dz = sig + N, *zt = dz + N, *Ft = zt + N, *sgt = Ft + N, *sgs = sgt + N;
+    Disp D{h, k, reinterpret_cast<hipStream_t>(stream), dev_args(h), sgs + N};
+    double *z = dz_state;
+    // barrier values: from the default start, 10, 3, 1, 0.3, 0.1, 0.03 down
+    // to (and ending at) p->mu; from a given state only p->mu
+    static const double kSchedule[] = {10.0, 3.0, 1.0, 0.3, 0.1, 0.03};
+    std::vector<double> mus;
+    if (o->from_default) {
+        if (ncl::launch_disp_point(D.a, *p, nullptr, 0.0, 0, z, D.st) != hipSuccess) return NCL_ERR_HIP;
+        for (double m : kSchedule)
+            if (m > p->mu) mus.push_back(m);
+    }
+    mus.push_back(p->mu);
+    int total = 0;
+    for (double mu : mus) {
+        ncl_nlp q = *p;
+        q.mu = mu;
+        const double tol = mu == p->mu ? o->step_tol : 1e-6;
+        double nrm = 0.0;
+        if ((rc = D.residual(q, z, F, sig)) || (rc = D.norm2(F, nrm))) return rc;
+        bool converged = false;
+        for (int it = 0; it < o->maxit && !converged; it++) {
+            // Newton matrix with the inertia of a minimum: the exact K, else
+            // with dw on the primal diagonal, dw from a third of the last
+            // accepted value (or 1e-4) growing x8 (the inertia correction of
+            // Section V-C as a primal shift)
+            bool ok = false;
+            if ((rc = D.factor_min(z, sig, q.rho, ok))) return rc;
+            if (ok) {
+                o->dw_last = 0.0;
+            } else {
+                double dw = o->dw_last > 0 ? o->dw_last / 3.0 : 1e-4;
+                for (; dw < 1e12 && !ok; dw *= 8.0) {
+                    if (ncl::launch_disp_point(D.a, q, sig, dw, 1, sgs, D.st) != hipSuccess) return NCL_ERR_HIP;
+                    if ((rc = D.factor_min(z, sgs, q.rho, ok))) return rc;
+                    if (ok) o->dw_last = dw;
+                }
+                if (!ok) return NCL_ERR_INERTIA;
+            }
+            // dz = -K^{-1} F (the solve is linear and rounding is symmetric
+            // under negation, so this equals the solve of -F bit for bit)
+            if ((rc = ncl_kkt_solve(k, F, dz, 1, N, D.st))) return rc;
+            if ((rc = D.axpy(-1.0, dz, nullptr, dz))) return rc;
+            double ex = 0.0, al = 1.0;
+            if ((rc = D.excess(z, dz, tol, ex))) return rc;
+            if (ex <= 0.0) {
+                // converged: take the last (tiny, quadratically accurate) step if it is feasible
+                if ((rc = D.max_step(q, z, dz, al))) return rc;
+                if (al >= 1.0) {
+                    if ((rc = D.axpy(1.0, dz, z, z)) || (rc = D.residual(q, z, F, sig))) return rc;
+                }
+                converged = true;
+                break;
+            }
+            if ((rc = D.max_step(q, z, dz, al))) return rc;
+            double nt = 0.0;
+            for (;;) {
+                if ((rc = D.axpy(al, dz, z, zt)) || (rc = D.residual(q, zt, Ft, sgt)) || (rc = D.norm2(Ft, nt)))
+                    return rc;
+                if (nt <= (1.0 - 1e-4 * al) * nrm || al < 1e-10) break;
+                al *= 0.5;
+            }
+            if (al < 1e-10) {
+                // |F| at its rounding floor (variables pressed against their
+                // bounds make the barrier curvature huge) with a tiny step
+                if ((rc = D.excess(z, dz, o->floor_tol, ex))) return rc;
+                if (ex <= 0.0) {
+                    converged = true;
+                    break;
+                }
+            }
+            if (hipMemcpyAsync(z, zt, sizeof(double) * size_t(N), hipMemcpyDeviceToDevice, D.st) != hipSuccess ||
+                hipMemcpyAsync(F, Ft, sizeof(double) * size_t(N), hipMemcpyDeviceToDevice, D.st) != hipSuccess ||
+                hipMemcpyAsync(sig, sgt, sizeof(double) * size_t(N), hipMemcpyDeviceToDevice, D.st) != hipSuccess)
+                return NCL_ERR_HIP;
+            nrm = nt;
+            total++;
+        }
+        if (!converged) {
+            o->iterations = total;
+            return NCL_ERR_NOT_CONVERGED;
+        }
+    }
+    // leave the exact K at the solution factored for the adjoint solves
+    bool ok = false;
+    if ((rc = D.residual(*p, z, F, sig)) || (rc = D.factor_min(z, sig, p->rho, ok))) return rc;
+    o->iterations = total;
+    return ok ? NCL_OK : NCL_ERR_INERTIA;
+}
+
+int ncl_kkt_dispatch_outputs(ncl_kkt *k, const double *dz, double *dphi, double *dpg, void *stream) {
+    if (!k || !dz || !dphi) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound) return NCL_ERR_STATE;
+    if (h.ng_disp == 0) return NCL_ERR_ARG;
+    return hip_rc(ncl::launch_disp_outputs(dev_args(h), dz, dphi, dpg, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ncl_kkt_dispatch_vjp(ncl_kkt *k, const ncl_nlp *p, const double *dz, const double *dgphi, const double *dgpg,
+                         double *dgpd, double *dwork, void *stream) {
+    if (!k || !dz || !dgphi || !dgpd || !dwork) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    int rc = nlp_check(h, p);
+    if (rc) return rc;
+    if (h.ng_disp == 0) return NCL_ERR_ARG;
+    if (!h.factored || h.factor_failed) return NCL_ERR_STATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    double *g = dwork, *adj = dwork + h.N;
+    if (ncl::launch_disp_adjoint(a, dz, dgphi, dgpg, g, st) != hipSuccess) return NCL_ERR_HIP;
+    if ((rc = ncl_kkt_solve_adjoint(k, g, adj, 1, h.N, stream))) return rc;
+    return hip_rc(ncl::launch_disp_load_grad(a, adj, p->qd_ratio, dgpd, st));
 }
 
 const char *ncl_kernel_name(int kind) {

@@ -31,6 +31,10 @@ struct DevArgs {
     double *xint, *bint, *rint; // residual: x, b and r in the interleaved layout order
     double *rbuf;               // residual in layout order (border part)
     double *epart;              // partial maxima of the backward error, 8 per workgroup
+    // dispatch map (a single network without PV/PQ rows)
+    int ng_disp, nbus_disp;
+    const int64_t *pg_col;      // [ng] global column of each generator's pg
+    const int64_t *row_pq;      // [nblk][nbus][2] global P and Q rows of each bus in each block
 };
 
 // Arguments of one launch (only those the kernel kind uses are read).
@@ -76,6 +80,19 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
 // nothing, and its address on the current device (looked up once per device).
 constexpr int64_t kScratchDoubles = int64_t(6) << 20;
 hipError_t scratch_address(double **out);
+
+// Dispatch map: vector steps of its Newton method (deterministic reductions
+// use part[] of vec_reduce_partials(n) doubles).
+hipError_t launch_vec_axpy(int64_t n, double al, const double *x, const double *y, double *out, hipStream_t st);
+hipError_t launch_vec_reduce(int64_t n, const double *x, const double *z, double tol, int mode, double *part,
+                             double *out, hipStream_t st);
+int64_t vec_reduce_partials(int64_t n);
+hipError_t launch_disp_point(const DevArgs &a, const ncl_nlp &q, const double *sig, double dw, int mode, double *out,
+                             hipStream_t st);
+hipError_t launch_disp_outputs(const DevArgs &a, const double *z, double *phi, double *pg, hipStream_t st);
+hipError_t launch_disp_adjoint(const DevArgs &a, const double *z, const double *gphi, const double *gpg, double *out,
+                               hipStream_t st);
+hipError_t launch_disp_load_grad(const DevArgs &a, const double *adj, double qd, double *gpd, hipStream_t st);
 
 // Streaming copy of n doubles (n even, both pointers 16-byte aligned).
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);

@@ -2177,6 +2177,23 @@ __device__ inline double step_limit(double x, double dx, double lo, double hi, d
     return al;
 }
 
+// Global column and layout kind of interleaved index idx < dint + nbd_tot
+// (dispatch-map networks: the border holds pg).
+__device__ inline void col_kind(const DevArgs &a, int64_t idx, int64_t &col, uint8_t &kind) {
+    if (idx < a.dint) {
+        const TemplDev &T = a.tmpls[find_tmpl(a, idx, &TemplDev::dbase)];
+        const int64_t off = idx - T.dbase;
+        const int j = int(off / T.nblk), bl = int(off % T.nblk);
+        col = a.blks[T.blocks[bl]].col0 + j;
+        kind = T.lkind[j];
+    } else {
+        const int64_t j = idx - a.dint;
+        const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
+        col = I.bstart + (j - I.bd0);
+        kind = LK_PG;            // the border of a network without PV/PQ rows holds pg
+    }
+}
+
 __global__ __launch_bounds__(kStepThreads) void k_max_step(DevArgs a, const double *__restrict__ z,
                                                           const double *__restrict__ dz, ncl_nlp q, double tau,
                                                           double *alpha) {
@@ -2186,18 +2203,7 @@ __global__ __launch_bounds__(kStepThreads) void k_max_step(DevArgs a, const doub
     for (int64_t idx = threadIdx.x; idx < total; idx += kStepThreads) {
         int64_t col;
         uint8_t kind;
-        if (idx < a.dint) {
-            const TemplDev &T = a.tmpls[find_tmpl(a, idx, &TemplDev::dbase)];
-            const int64_t off = idx - T.dbase;
-            const int j = int(off / T.nblk), bl = int(off % T.nblk);
-            col = a.blks[T.blocks[bl]].col0 + j;
-            kind = T.lkind[j];
-        } else {
-            const int64_t j = idx - a.dint;
-            const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
-            col = I.bstart + (j - I.bd0);
-            kind = LK_PG;            // the border of a network without PV/PQ rows holds pg
-        }
+        col_kind(a, idx, col, kind);
         const double x = z[col], dx = dz[col];
         switch (kind) {
             case LK_VM: al = fmin(al, step_limit(x, dx, q.vmin, q.vmax, tau)); break;
@@ -2215,6 +2221,185 @@ __global__ __launch_bounds__(kStepThreads) void k_max_step(DevArgs a, const doub
         for (int w = 1; w < kStepThreads / 64; w++) m = fmin(m, red[w]);
         *alpha = m;
     }
+}
+
+// ------------------------------------------------------------------ dispatch map: Newton steps
+
+// Elementwise steps of the dispatch map's Newton method over the N columns
+// (layout order), and its deterministic reductions: every sum has a fixed
+// order (each workgroup sums kRedPer consecutive elements, thread t taking
+// t, t + 256, ... in turn, then a fixed shuffle tree; the final kernel sums
+// the workgroups' partials in the same way), so results repeat bit for bit.
+constexpr int kRedPer = 4096;
+constexpr int kRedFinal = 1024;
+
+__device__ inline double tree_sum256(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out = y + a x  (y may be null: out = a x)
+__global__ __launch_bounds__(256) void k_vec_axpy(int64_t n, double al, const double *__restrict__ x,
+                                                  const double *__restrict__ y, double *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) out[i] = y ? fma(al, x[i], y[i]) : al * x[i];
+}
+
+// partial sums of squares (mode 0) or partial maxima of |dz_i| - tol (1 + |z_i|) (mode 1)
+__global__ __launch_bounds__(256) void k_vec_reduce(int64_t n, const double *__restrict__ x,
+                                                    const double *__restrict__ z, double tol, int mode,
+                                                    double *__restrict__ part) {
+    __shared__ double red[4];
+    const int64_t i0 = int64_t(blockIdx.x) * kRedPer;
+    double v = mode ? -INFINITY : 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i0 + kRedPer && i < n; i += 256) {
+        if (mode == 0) v = fma(x[i], x[i], v);
+        else {
+            const double e = fabs(x[i]) - tol * (1.0 + fabs(z[i]));
+            v = (e > v || e != e) ? e : v;
+        }
+    }
+    if (mode == 0) {
+        const double s = tree_sum256(v, red);
+        if (threadIdx.x == 0) part[blockIdx.x] = s;
+    } else {
+        for (int o = 32; o > 0; o >>= 1) {
+            const double w = __shfl_xor(v, o);
+            v = (w > v || w != w) ? w : v;
+        }
+        if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = red[0];
+            for (int q = 1; q < 4; q++) m = (red[q] > m || red[q] != red[q]) ? red[q] : m;
+            part[blockIdx.x] = m;
+        }
+    }
+}
+
+// out[0] = sqrt(sum of the partials) (mode 0) or their maximum (mode 1)
+__global__ __launch_bounds__(kRedFinal) void k_vec_reduce_final(int64_t np, const double *__restrict__ part, int mode,
+                                                                double *__restrict__ out) {
+    __shared__ double red[kRedFinal / 64];
+    double v = mode ? -INFINITY : 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += kRedFinal) v = mode ? ((part[i] > v || part[i] != part[i]) ? part[i] : v)
+                                                                  : v + part[i];
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o);
+        v = mode ? ((w > v || w != w) ? w : v) : v + w;
+    }
+    if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int q = 1; q < kRedFinal / 64; q++) t = mode ? ((red[q] > t || red[q] != red[q]) ? red[q] : t) : t + red[q];
+        out[0] = mode ? t : sqrt(t);
+    }
+}
+
+// the default start (vm = 1, pg = pmax / 2, flow-row multipliers mu / smax2,
+// everything else 0) and the primal shift out = sig + dw on vm, va, qg, pg
+__global__ __launch_bounds__(256) void k_disp_point(DevArgs a, ncl_nlp q, const double *__restrict__ sig, double dw,
+                                                    int mode, double *__restrict__ out) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= a.dint + a.nbd_tot) return;
+    int64_t col;
+    uint8_t kind;
+    col_kind(a, idx, col, kind);
+    if (mode == 0) {
+        out[col] = kind == LK_VM ? 1.0 : kind == LK_PG ? 0.5 * q.pmax : kind == LK_FLOW ? q.mu / q.smax2 : 0.0;
+    } else {
+        const bool primal = kind == LK_VM || kind == LK_VA || kind == LK_QG || kind == LK_PG;
+        out[col] = primal ? sig[col] + dw : sig[col];
+    }
+}
+
+// phi = sum_g c2_g pg_g^2 (generators in order) and pg (one thread)
+__global__ __launch_bounds__(64) void k_disp_outputs(DevArgs a, const double *__restrict__ z, double *__restrict__ phi,
+                                                     double *__restrict__ pg) {
+    if (threadIdx.x != 0) return;
+    const InstDev &I = a.insts[0];
+    double f = 0.0;
+    for (int g = 0; g < a.ng_disp; g++) {
+        const double p = z[a.pg_col[g]];
+        f = fma(I.gen_c2[g] * p, p, f);
+        if (pg) pg[g] = p;
+    }
+    *phi = f;
+}
+
+// adjoint right-hand side g = d(gphi phi + gpg . pg)/dz: 2 c2 pg gphi + gpg
+// on the pg columns, 0 elsewhere (mode 0 fills the zeros, then mode 1 the
+// pg columns)
+__global__ __launch_bounds__(256) void k_disp_adjoint_rhs(DevArgs a, const double *__restrict__ z,
+                                                          const double *__restrict__ gphi,
+                                                          const double *__restrict__ gpg, int mode,
+                                                          double *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (mode == 0) {
+        if (i < a.N) out[i] = 0.0;
+    } else if (i < a.ng_disp) {
+        const InstDev &I = a.insts[0];
+        const int64_t c = a.pg_col[i];
+        const double p = z[c];
+        out[c] = fma(2.0 * I.gen_c2[i] * p, *gphi, gpg ? gpg[i] : 0.0);
+    }
+}
+
+// load gradient: gpd_i = -(sum over blocks of adj at bus i's P row + qd
+// times the same sum at its Q row), blocks in order
+__global__ __launch_bounds__(256) void k_disp_load_grad(DevArgs a, const double *__restrict__ adj, double qd,
+                                                        double *__restrict__ gpd) {
+    const int i = int(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= a.nbus_disp) return;
+    double sp = 0.0, sq = 0.0;
+    for (int b = 0; b < a.nblk; b++) {
+        sp += adj[a.row_pq[2 * (int64_t(b) * a.nbus_disp + i)]];
+        sq += adj[a.row_pq[2 * (int64_t(b) * a.nbus_disp + i) + 1]];
+    }
+    gpd[i] = -(sp + qd * sq);
+}
+
+hipError_t launch_vec_axpy(int64_t n, double al, const double *x, const double *y, double *out, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_vec_axpy, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, n, al, x, y, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_vec_reduce(int64_t n, const double *x, const double *z, double tol, int mode, double *part,
+                             double *out, hipStream_t st) {
+    const int64_t np = (n + kRedPer - 1) / kRedPer;
+    if (np > 0) hipLaunchKernelGGL(k_vec_reduce, dim3(unsigned(np)), dim3(256), 0, st, n, x, z, tol, mode, part);
+    hipLaunchKernelGGL(k_vec_reduce_final, dim3(1), dim3(kRedFinal), 0, st, np, part, mode, out);
+    return hipGetLastError();
+}
+
+int64_t vec_reduce_partials(int64_t n) { return (n + kRedPer - 1) / kRedPer; }
+
+hipError_t launch_disp_point(const DevArgs &a, const ncl_nlp &q, const double *sig, double dw, int mode, double *out,
+                             hipStream_t st) {
+    const int64_t n = a.dint + a.nbd_tot;
+    if (n > 0) hipLaunchKernelGGL(k_disp_point, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, a, q, sig, dw, mode, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_disp_outputs(const DevArgs &a, const double *z, double *phi, double *pg, hipStream_t st) {
+    hipLaunchKernelGGL(k_disp_outputs, dim3(1), dim3(64), 0, st, a, z, phi, pg);
+    return hipGetLastError();
+}
+
+hipError_t launch_disp_adjoint(const DevArgs &a, const double *z, const double *gphi, const double *gpg, double *out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_disp_adjoint_rhs, dim3(unsigned((a.N + 255) / 256)), dim3(256), 0, st, a, z, gphi, gpg, 0, out);
+    hipLaunchKernelGGL(k_disp_adjoint_rhs, dim3(unsigned((a.ng_disp + 255) / 256)), dim3(256), 0, st, a, z, gphi, gpg, 1,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_disp_load_grad(const DevArgs &a, const double *adj, double qd, double *gpd, hipStream_t st) {
+    hipLaunchKernelGGL(k_disp_load_grad, dim3(unsigned((a.nbus_disp + 255) / 256)), dim3(256), 0, st, a, adj, qd, gpd);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ streaming copy

@@ -303,6 +303,7 @@ struct Handle {
     int64_t asm_wthreads = 0;               // template assembly threads, wavefront-aligned (border pg threads follow)
     int64_t tiles = 0;                      // transpose tiles of all templates
     int64_t rows_waves = 0;                 // residual-row wavefronts of all templates
+    int ng_disp = 0, nbus_disp = 0;         // dispatch map: generators and buses (0: not a dispatch network)
     std::vector<int64_t> t_kbase, t_lbase, t_dbase, t_abase, t_awbase, t_tile0, t_rwbase;
     Schedule sched;
     // numeric state
@@ -328,6 +329,7 @@ struct Handle {
         InstDev *inst = nullptr;
         Work *work = nullptr;            // all work lists
         const uint8_t *bprim = nullptr;
+        const int64_t *pg_col = nullptr, *row_pq = nullptr;   // dispatch-map tables
     } d;
     // offsets of each work list inside d.work
     size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_sn = 0, w_sb = 0, w_bpart = 0, w_schur = 0;

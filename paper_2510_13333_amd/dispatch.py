@@ -10,28 +10,30 @@ so that
     d phi*/d pd = -(K^{-1} grad phi)[P rows] - qd_ratio (K^{-1} grad phi)[Q rows]
 
 summed over the blocks (every block sees the same loads), and likewise for
-any cotangent of pg*.  The forward pass is a Newton solve on the library:
-F and Sigma from ncl_kkt_residual, K from ncl_kkt_assemble, the LDL^T
-factor and solve, the fraction-to-boundary step from ncl_kkt_max_step.
-The backward pass is one ncl_kkt_solve_adjoint on the factors the forward
-pass left (the exact K at the solution).  PyTorch holds the vectors and
-orders the calls; the arithmetic of every step runs in the library.
+any cotangent of pg*.  The forward pass is the library's Newton solve
+(ncl_kkt_dispatch_newton: residual, exact K, inertia correction, LDL^T
+factor and solve, fraction-to-boundary step, backtracking), the outputs
+come from ncl_kkt_dispatch_outputs, and the backward pass is
+ncl_kkt_dispatch_vjp: one ncl_kkt_solve_adjoint on the factors the
+forward pass left (the exact K at the solution) and the reduction to the
+loads.  PyTorch holds the vectors and orders the calls; every arithmetic
+step runs in the library.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
-from .ncl import KKT, NclError
+from .ncl import KKT, NclError, NewtonOpts
 
 DEFAULTS = dict(qd_ratio=0.3, mu=0.3, vmin=0.9, vmax=1.1, qmax=3.0, pmax=8.0, smax2=100.0, eps=1.0)
-MU_SCHEDULE = (10.0, 3.0, 1.0, 0.3, 0.1, 0.03)
 FLOOR_TOL = 1e-6      # step accepted as converged when backtracking stalls at the rounding floor
-L_VM, L_VA, L_QG, L_PG, L_ROWP, L_ROWQ, L_FLOW = 1, 2, 3, 4, 5, 6, 7
 
 
 class DispatchSolver:
-    """Newton solver of the dispatch map on one network (one GPU handle)."""
+    """The dispatch map on one network (one GPU handle): the Newton solve
+    (ncl_kkt_dispatch_newton), the outputs (ncl_kkt_dispatch_outputs) and
+    the adjoint (ncl_kkt_dispatch_vjp) all run in the library; this class
+    holds the device vectors and orders the calls."""
 
     def __init__(self, net, params=None, device="cuda"):
         self.net = net
@@ -39,132 +41,47 @@ class DispatchSolver:
         self.p.update(params or {})
         self.p["rho"] = float(net.rho)
         self.k = KKT(net).bind(nrhs_max=1, device=device)
-        kinds = self.k.layout_kinds()
-        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
-        self.kinds = dev(kinds)
-        self.pg_idx = dev(np.flatnonzero(kinds == L_PG))
-        self.c2 = dev(np.asarray(net.gen_c2, np.float64))
-        nb = int(net.nb)
-        rowP = np.flatnonzero(kinds == L_ROWP).reshape(-1, nb)    # [blocks, nb], layout order
-        rowQ = np.flatnonzero(kinds == L_ROWQ).reshape(-1, nb)
-        self.rowP, self.rowQ = dev(rowP), dev(rowQ)
         self.device = device
-        self.alpha = torch.empty(1, dtype=torch.float64, device=device)
-        self.primal = ((self.kinds >= L_VM) & (self.kinds <= L_PG)).to(torch.float64)
-        self.dw_last = 0.0
+        n = self.k.N
+        self.work = torch.empty(7 * n + 8, dtype=torch.float64, device=device)
+        self.vwork = torch.empty(2 * n, dtype=torch.float64, device=device)
+        self.opts = NewtonOpts(1e-10, FLOOR_TOL, 100, 1, 0, 0, 0.0)
         self.z_warm = None
         self.factored_at = None      # the state whose exact K is in the handle's factors
         self.iterations = 0
 
-    # -------------------------------------------------------------- pieces
-    def initial_point(self):
-        z = torch.zeros(self.k.N, dtype=torch.float64, device=self.device)
-        z[self.kinds == L_VM] = 1.0
-        z[self.kinds == L_PG] = 0.5 * self.p["pmax"]
-        z[self.kinds == L_FLOW] = self.p["mu"] / self.p["smax2"]
-        return z
-
-    def _params(self, mu):
-        q = dict(self.p)
-        q["mu"] = mu
-        return q
-
-    def _factor(self, z, sig, exact):
-        """Assemble and factor; True when the factorisation has the inertia of
-        a strict local minimum, (n, m) with no zero or non-finite pivot.
-        (Single pivots may carry the other sign when K11 is not definite:
-        the inertia, not each sign, is what a minimum fixes.)"""
-        self.k.assemble(z, sig, self.p["rho"], shift=not exact)
-        self.k.factor()
-        r = self.k.info()
-        return (r["status"] in (0, -6) and r["nzero"] == 0 and r["npos"] == self.k.nprimal
-                and r["nneg"] == self.k.N - self.k.nprimal)
-
-    def _factor_corrected(self, z, sig):
-        """Factor the exact Newton matrix; if its pivot signs (inertia) are
-        wrong, add dw on the primal diagonal, dw growing from a fraction of
-        the last accepted value (or 1e-4) by x8 until they are right (the
-        inertia correction of Section V-C, as a primal shift dw I)."""
-        if self._factor(z, sig, exact=True):
-            self.dw_last = 0.0
-            return 0.0
-        dw = self.dw_last / 3.0 if self.dw_last > 0 else 1e-4
-        while dw < 1e12:
-            if self._factor(z, sig + dw * self.primal, exact=True):
-                self.dw_last = dw
-                return dw
-            dw *= 8.0
-        raise NclError("dispatch Newton matrix: inertia correction failed", self.k.info()["status"])
-
     def newton(self, pd, z0=None, step_tol=1e-10, maxit=100):
-        """Solve F(z; pd) = 0: Newton steps with the exact K (inertia-corrected
-        when its pivot signs are wrong), a fraction-to-boundary step,
-        backtracking on |F|_2; converged when the full step is below
-        step_tol relative to z.  From the default start the barrier
-        parameter is continued down to mu."""
-        if z0 is None:
-            z = self.initial_point()
-            mus = [m for m in MU_SCHEDULE if m > self.p["mu"]] + [self.p["mu"]]
-        else:
-            z = z0.clone()
-            mus = [self.p["mu"]]
-        total = 0
-        for mu in mus:
-            q = self._params(mu)
-            tol = step_tol if mu == self.p["mu"] else 1e-6
-            F, sig = self.k.residual(z, pd, q)
-            nrm = float(torch.linalg.vector_norm(F))
-            for _ in range(maxit):
-                self._factor_corrected(z, sig)
-                dz = self.k.solve(-F)
-                if bool(torch.all(dz.abs() <= tol * (1.0 + z.abs()))):
-                    # take the (tiny, quadratically accurate) last step
-                    self.k.max_step(z, dz, pd, q, 0.995, self.alpha)
-                    if float(self.alpha) >= 1.0:
-                        z = z + dz
-                        F, sig = self.k.residual(z, pd, q)
-                    break
-                self.k.max_step(z, dz, pd, q, 0.995, self.alpha)
-                a = float(self.alpha)
-                while True:
-                    zt = z + a * dz
-                    Ft, sigt = self.k.residual(zt, pd, q)
-                    nt = float(torch.linalg.vector_norm(Ft))
-                    if nt <= (1.0 - 1e-4 * a) * nrm or a < 1e-10:
-                        break
-                    a *= 0.5
-                if a < 1e-10 and bool(torch.all(dz.abs() <= FLOOR_TOL * (1.0 + z.abs()))):
-                    # |F| is at its rounding floor (variables pressed against
-                    # their bounds make the barrier curvature huge) and the
-                    # remaining step is tiny: converged as far as FP64 resolves
-                    break
-                z, F, sig, nrm = zt, Ft, sigt, nt
-                total += 1
-            else:
-                raise RuntimeError(f"dispatch Newton did not converge at mu = {mu:g}")
-        # leave the exact K at the solution factored for the backward pass
-        if not self._factor(z, sig, exact=True):
-            raise NclError("dispatch KKT at the solution (not a strict local minimum)", self.k.info()["status"])
+        """Solve F(z; pd) = 0 in the library: from the default start with
+        barrier continuation, or from z0 at the target barrier value."""
+        z = torch.empty(self.k.N, dtype=torch.float64, device=self.device) if z0 is None else z0.clone()
+        self.opts.step_tol = step_tol
+        self.opts.maxit = maxit
+        self.opts.from_default = 1 if z0 is None else 0
+        self.k.dispatch_newton(pd, self.p, z, self.work, self.opts)
         self.factored_at = z
-        self.iterations = total
+        self.iterations = self.opts.iterations
         return z
 
     def outputs(self, z):
-        pg = z[self.pg_idx]
-        return torch.sum(self.c2 * pg * pg), pg
+        phi = torch.empty((), dtype=torch.float64, device=self.device)
+        pg = torch.empty(self.net.ng, dtype=torch.float64, device=self.device)
+        self.k.dispatch_outputs(z, phi, pg)
+        return phi, pg
 
     def vjp(self, z, gphi, gpg):
         """Cotangent of (phi*, pg*) -> cotangent of pd, by one adjoint solve."""
+        pd = self._pd_of[0]
         if self.factored_at is None or not torch.equal(self.factored_at, z):
-            _, sig = self.k.residual(z, self._pd_of[0], self.p)
-            if not self._factor(z, sig, exact=True):
-                raise NclError("dispatch KKT at the solution", self.k.info()["status"])
+            F, sig = self.k.residual(z, pd, self.p)
+            self.k.assemble(z, sig, self.p["rho"], shift=False)
+            self.k.factor()
+            r = self.k.info()
+            if not (r["solvable"] and r["npos"] == self.k.nprimal and r["nneg"] == self.k.N - self.k.nprimal):
+                raise NclError("dispatch KKT at the solution", r["status"])
             self.factored_at = z
-        pg = z[self.pg_idx]
-        g = torch.zeros_like(z)
-        g[self.pg_idx] = gphi * 2.0 * self.c2 * pg + gpg
-        a = self.k.solve_adjoint(g)
-        return -(a[self.rowP].sum(0) + self.p["qd_ratio"] * a[self.rowQ].sum(0))
+        gpd = torch.empty(self.net.nb, dtype=torch.float64, device=self.device)
+        return self.k.dispatch_vjp(pd, self.p, z, gphi.contiguous(), None if gpg is None else gpg.contiguous(),
+                                   gpd, self.vwork)
 
     def __call__(self, pd):
         return NCLDispatch.apply(pd, self)
@@ -188,6 +105,6 @@ class NCLDispatch(torch.autograd.Function):
     def backward(ctx, gphi, gpg):
         (z,) = ctx.saved_tensors
         s = ctx.solver
-        gphi = torch.zeros((), dtype=torch.float64, device=z.device) if gphi is None else gphi
-        gpg = torch.zeros_like(z[s.pg_idx]) if gpg is None else gpg
+        if gphi is None:
+            gphi = torch.zeros((), dtype=torch.float64, device=z.device)
         return s.vjp(z, gphi, gpg), None

@@ -26,7 +26,7 @@ KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_s
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
           -4: "call out of order", -5: "zero pivot", -6: "pivot of the wrong sign (inertia)",
-          -7: "non-finite pivot"}
+          -7: "non-finite pivot", -8: "Newton method did not converge"}
 
 
 class NclError(RuntimeError):
@@ -63,6 +63,12 @@ class _Nlp(ctypes.Structure):
                 ("rho", ctypes.c_double), ("vmin", ctypes.c_double), ("vmax", ctypes.c_double),
                 ("qmax", ctypes.c_double), ("pmax", ctypes.c_double), ("smax2", ctypes.c_double),
                 ("eps", ctypes.c_double)]
+
+
+class NewtonOpts(ctypes.Structure):
+    _fields_ = [("step_tol", ctypes.c_double), ("floor_tol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("from_default", ctypes.c_int32), ("iterations", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("dw_last", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -121,6 +127,9 @@ def load():
         "ncl_kkt_residual": ([P, P, P, P, P, P], ctypes.c_int),
         "ncl_kkt_layout_kinds": ([P, P], ctypes.c_int),
         "ncl_kkt_max_step": ([P, P, P, P, ctypes.c_double, P, P], ctypes.c_int),
+        "ncl_kkt_dispatch_newton": ([P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_dispatch_outputs": ([P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_dispatch_vjp": ([P, P, P, P, P, P, P, P], ctypes.c_int),
         "ncl_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "ncl_stream_copy": ([P, P, i64, P], ctypes.c_int),
     }
@@ -410,6 +419,31 @@ class KKT:
                                                            self._dev(dz, self.N), float(tau), self._dev(out),
                                                            _stream_ptr()))
         return out
+
+    def dispatch_newton(self, pd, p, z, work, opts):
+        """Newton solve of the dispatch map in the library (z in/out, work:
+        7 N + 8 doubles on the device, opts: NewtonOpts, updated)."""
+        self._dev(pd)
+        q = self._nlp(pd, p)
+        _check("ncl_kkt_dispatch_newton", load().ncl_kkt_dispatch_newton(
+            self._h, ctypes.byref(q), self._dev(z, self.N), self._dev(work, 7 * self.N + 8), ctypes.byref(opts),
+            _stream_ptr()))
+        return z
+
+    def dispatch_outputs(self, z, phi, pg=None):
+        _check("ncl_kkt_dispatch_outputs", load().ncl_kkt_dispatch_outputs(
+            self._h, self._dev(z, self.N), self._dev(phi), None if pg is None else self._dev(pg), _stream_ptr()))
+        return phi, pg
+
+    def dispatch_vjp(self, pd, p, z, gphi, gpg, gpd, work):
+        """gpd = the load cotangent of (gphi, gpg) at the solution z (one
+        adjoint solve on the stored factors; work: 2 N doubles)."""
+        self._dev(pd)
+        q = self._nlp(pd, p)
+        _check("ncl_kkt_dispatch_vjp", load().ncl_kkt_dispatch_vjp(
+            self._h, ctypes.byref(q), self._dev(z, self.N), self._dev(gphi), None if gpg is None else self._dev(gpg),
+            self._dev(gpd), self._dev(work, 2 * self.N), _stream_ptr()))
+        return gpd
 
     # ------------------------------------------------------------ measurement
     @staticmethod

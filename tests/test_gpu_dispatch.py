@@ -99,7 +99,7 @@ def test_small_forward_and_gradients():
     zg = s.z_warm.cpu().numpy()
     assert np.abs(zg - zo).max() <= 1e-7 * np.abs(zo).max()
     phi_o, pg_o = D.outputs(net, zo)
-    assert abs(float(phi) - phi_o) <= 1e-9 * abs(phi_o)
+    assert abs(float(phi.detach()) - phi_o) <= 1e-9 * abs(phi_o)
     (g,) = torch.autograd.grad(phi, pdt, retain_graph=True)
     g = g.cpu().numpy()
     assert np.abs(g - go).max() <= 1e-7 * np.abs(go).max()
@@ -143,3 +143,28 @@ def test_c5_gradients_vs_oracle_and_fd():
         worst = max(worst, rel)
     print(f"[c5] worst central-difference relative error {worst:.2e}", flush=True)
     assert worst <= 1e-5
+
+
+def test_outputs_and_vjp_entry_points():
+    """ncl_kkt_dispatch_outputs against the oracle's phi and pg at the
+    solution; ncl_kkt_dispatch_vjp against the oracle's pivot-free LDL^T
+    gradient for a random (gphi, gpg) cotangent, and linear in it."""
+    net = small_net()
+    p = D.NLP()
+    pd = G.draw_loads(net, 5)
+    s = DispatchSolver(net)
+    z = s.newton(dev(pd))
+    s._pd_of = (dev(pd),)
+    phi, pg = s.outputs(z)
+    zh = z.cpu().numpy()
+    phi_o, pg_o = D.outputs(net, zh)
+    assert abs(float(phi) - phi_o) <= 1e-14 * abs(phi_o)
+    assert np.array_equal(pg.cpu().numpy(), pg_o)
+    w = np.random.default_rng(4).standard_normal(net.ng)
+    g1 = s.vjp(z, dev(np.array(1.0)), None).cpu().numpy()
+    gw = s.vjp(z, dev(np.array(0.0)), dev(w)).cpu().numpy()
+    gb = s.vjp(z, dev(np.array(2.0)), dev(w)).cpu().numpy()
+    go, gwo = D.gradients(net, zh, pd, p, method="ldlt", cotangent=w)
+    assert np.abs(g1 - go).max() <= 1e-10 * np.abs(go).max()
+    assert np.abs(gw - gwo).max() <= 1e-10 * np.abs(gwo).max()
+    assert np.abs(gb - (2 * g1 + gw)).max() <= 1e-12 * np.abs(gb).max()
