@@ -47,6 +47,8 @@ WORKLOADS = {
     4: "64 uneven synthetic grids (118..2000 buses log-uniform, 4..32 branch-outage contingencies each) "
        "in one batched handle, rho=1e4, FP64",
     5: "2000-bus synthetic grid x 64 branch-outage contingencies (N=907760), rho=1e4, FP64",
+    6: "contingency screening of the 500-bus grid's 256 branch-outage contingencies with PV/PQ rows, "
+       "first-stage variables fixed: 256 independent blocks, no border (N=1100800), rho=1e5, FP64",
 }
 COPY_DOUBLES = 64 * 2 ** 20          # the plain copy whose counters calibrate FETCH_SIZE / WRITE_SIZE
 PROFILE_STRIDE = 7                   # one launch in 7 of the dominant kernel is event-timed in the timed region
@@ -326,6 +328,12 @@ def run_single(args):
                          f"C left-looking LDL^T with OpenMP over the blocks on {threads} threads, and again on "
                          f"1 thread; K assembled by numpy and the symbolic analysis done beforehand, untimed"}
 
+    disp = None
+    if cfg == 5 and not args.no_dispatch:
+        disp = dispatch_backward(net, args.steps)
+        print(f"[bench] dispatch map: forward {disp['forward_s']:.2f} s ({disp['newton_steps']} Newton steps), "
+              f"backward {disp['backward_ms']:.3f} ms", file=sys.stderr, flush=True)
+
     from paper_2510_13333_amd.ncl import KERNELS
     nbd = sum(i["nbd"] for i in k.instances)
     step_bytes = sum(k.kernel_model(kind)[1] for kind in range(len(KERNELS)))
@@ -361,7 +369,40 @@ def run_single(args):
         "status": info["status"],
         "cpu_baseline": cpu,
     }
+    if disp is not None:
+        out["dispatch_map"] = disp
     print(json.dumps(out), flush=True)
+
+
+def dispatch_backward(net, steps):
+    """The differentiable dispatch map on this network: one forward pass
+    (the library's Newton solve, untimed beyond its wall clock) and the
+    backward pass (adjoint right-hand side, one adjoint solve on the stored
+    factors, reduction to the loads) timed by events, median of `steps`."""
+    import torch
+    import gridgen as G
+    from paper_2510_13333_amd.dispatch import DispatchSolver
+    pd = torch.from_numpy(G.draw_loads(net, 5)).to("cuda")
+    s = DispatchSolver(net)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z = s.newton(pd)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    s._pd_of = (pd,)
+    gphi = torch.ones((), dtype=torch.float64, device="cuda")
+    s.vjp(z, gphi, None)
+    ts = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.vjp(z, gphi, None)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return {"what": "d phi*/d pd for the 2000 bus loads: adjoint right-hand side, one adjoint KKT solve on the "
+                    "factors of the converged forward pass, reduction over the blocks' balance rows",
+            "newton_steps": s.iterations, "forward_s": t_fwd, "backward_ms": float(np.median(ts))}
 
 
 def run_batched(args):
@@ -553,6 +594,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps timed on the host")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-dispatch", action="store_true", help="skip the dispatch-map backward timing (config 5)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default=None)
     args = ap.parse_args()

@@ -22,7 +22,9 @@ primal: vm[nb], va[nb], qg[ng], and with complementarity rows
 dual:   P[nb], Q[nb], Ffrom[nl], Fto[nl], and with complementarity rows
         LIN[ng], DUP[ng], DLO[ng], CUP[ng], CLO[ng]
 global: block 0 (base case), blocks 1..K (contingencies), then the border
-        pg[ng] followed (complementarity only) by vm0[ng].
+        pg[ng] followed (complementarity only) by vm0[ng].  A screening
+        network (first-stage pg and vm0 fixed) has the K contingency
+        blocks alone, with no base block and no border.
 
 Seeds: numpy PCG64 seeded by SeedSequence([2510, 13333, cfg, instance,
 iteration]); draws follow a fixed order.
@@ -59,6 +61,7 @@ class Network:
     outage: np.ndarray    # int32 [K] outaged branch of contingency k+1
     pvpq: bool            # complementarity (PV/PQ switching) rows present
     rho: float
+    screen: bool = False  # contingency screening: first-stage pg (and vm0) fixed, blocks = contingencies
 
     @property
     def ncont(self) -> int:
@@ -66,11 +69,21 @@ class Network:
 
     @property
     def nblk(self) -> int:
-        return self.ncont + 1
+        return self.ncont if self.screen else self.ncont + 1
 
     @property
     def single(self) -> bool:
-        return self.ncont == 0
+        return self.ncont == 0 and not self.screen
+
+    def cont_block(self, blk: int) -> bool:
+        """Whether block blk is a contingency block (its outage: outage_of)."""
+        return self.screen or blk > 0
+
+    def outage_of(self, blk: int) -> int:
+        """Outaged branch of block blk, or -1 for the base case."""
+        if self.screen:
+            return int(self.outage[blk])
+        return int(self.outage[blk - 1]) if blk > 0 else -1
 
 
 def _geo_topology(g: np.random.Generator, nb: int, nl: int):
@@ -160,7 +173,7 @@ def bridges(nb: int, f: np.ndarray, t: np.ndarray) -> np.ndarray:
 
 
 def make_network(cfg: int, nb: int, nl: int, ng: int, ncont: int, *, pvpq: bool = False,
-                 rho: float = 1e4, instance: int = 0, topology: str = "geo") -> Network:
+                 rho: float = 1e4, instance: int = 0, topology: str = "geo", screen: bool = False) -> Network:
     """Draw a network.  Draw order: topology, impedances, generators, costs,
     outages."""
     g = rng(cfg, instance, 0)
@@ -181,7 +194,9 @@ def make_network(cfg: int, nb: int, nl: int, ng: int, ncont: int, *, pvpq: bool 
         outage = np.sort(g.choice(cand, size=ncont, replace=False)).astype(np.int32)
     else:
         outage = np.zeros(0, dtype=np.int32)
-    return Network(nb, nl, ng, f, t, r, x, gen_bus, c2, outage, bool(pvpq), float(rho))
+    if screen and ncont == 0:
+        raise ValueError("screening needs contingencies")
+    return Network(nb, nl, ng, f, t, r, x, gen_bus, c2, outage, bool(pvpq), float(rho), bool(screen))
 
 
 # ---------------------------------------------------------------- layout kinds
@@ -198,13 +213,13 @@ def block_kinds(net: Network, blk: int):
         kinds.extend([k] * len(ids))
         idx.extend(ids)
 
-    base_c = net.pvpq and blk == 0
+    base_c = net.pvpq and not net.cont_block(blk)
     add(VM, [i for i in range(nb) if not (base_c and i in gb)])
     add(VA, range(nb))
     add(QG, range(ng))
     if net.single:
         add(PG, range(ng))
-    if net.pvpq and blk > 0:
+    if net.pvpq and net.cont_block(blk):
         for k in (NUP, NUM, SUP, SLO):
             add(k, range(ng))
     nprim = len(kinds)
@@ -212,7 +227,7 @@ def block_kinds(net: Network, blk: int):
     add(ROW_Q, range(nb))
     add(ROW_FF, range(nl))
     add(ROW_FT, range(nl))
-    if net.pvpq and blk > 0:
+    if net.pvpq and net.cont_block(blk):
         for k in (ROW_LIN, ROW_DUP, ROW_DLO, ROW_CUP, ROW_CLO):
             add(k, range(ng))
     return np.array(kinds, np.int32), np.array(idx, np.int32), nprim
@@ -227,7 +242,7 @@ def layout(net: Network):
         ids.append(i)
         bl.append(np.full(k.shape[0], b, np.int32))
         offs.append(offs[-1] + k.shape[0])
-    if not net.single:
+    if not net.single and not net.screen:
         ng = net.ng
         ks.append(np.full(ng, PG, np.int32))
         ids.append(np.arange(ng, dtype=np.int32))
@@ -332,14 +347,17 @@ CONFIGS = {
     2: dict(nb=500, nl=700, ng=90, ncont=16, pvpq=False, rho=1e4),
     3: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5),
     5: dict(nb=2000, nl=2800, ng=360, ncont=64, pvpq=False, rho=1e4),
+    # screening of the 500-bus x 256 grid's contingencies (the same grid and
+    # outages: drawn with config 3's seed), first-stage variables fixed
+    6: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, screen=True, seed_cfg=3),
 }
 
 
 def config_network(cfg: int, **over) -> Network:
     p = dict(CONFIGS[cfg])
     p.update(over)
-    return make_network(cfg, p["nb"], p["nl"], p["ng"], p["ncont"], pvpq=p["pvpq"],
-                        rho=p["rho"], topology=p.get("topology", "geo"))
+    return make_network(p.get("seed_cfg", cfg), p["nb"], p["nl"], p["ng"], p["ncont"], pvpq=p["pvpq"],
+                        rho=p["rho"], topology=p.get("topology", "geo"), screen=p.get("screen", False))
 
 
 def batched_networks(count: int = 64, cfg: int = 4):

@@ -33,6 +33,8 @@
  *             CLO[ng] (eq. (pvpq): linear row, the two slack definitions and
  *             the two complementarity products);
  *   blocks 0..K in order, then the border pg[ng] (and vm0[ng] with NCL_PVPQ).
+ *   With NCL_SCREEN the blocks are the K contingencies alone, each with the
+ *   contingency layout (pg and vm0 fixed, so neither a column nor a border).
  *
  * Conventions
  *   - Pointers named d* and the fields of ncl_kkt_point are DEVICE pointers;
@@ -79,6 +81,9 @@ enum {
 
 #define NCL_MAX_BORDER 600   /* largest first-stage border (dense factor in local memory) */
 #define NCL_PVPQ 1u          /* PV/PQ complementarity rows and the vm0 border (eq. (pvpq)) */
+#define NCL_SCREEN 2u        /* contingency screening (eq. (screening)): the first-stage variables are
+                                fixed, so the blocks are the K contingencies alone, with no base case
+                                and no border; each block's KKT is that of its own feasibility problem */
 
 /* Network topology and constants (host arrays, copied during analyze).
  * Branch l joins buses br_from[l] < br_to[l] with series impedance

@@ -59,6 +59,7 @@ class Positions:
         self.nblk = net.nblk
         self.pvpq = net.pvpq
         self.single = net.single
+        self.screen = bool(getattr(net, "screen", False))
         isgen = np.zeros(nb, bool)
         isgen[net.gen_bus] = True
         self.vm = np.full((self.nblk, nb), -1, np.int64)
@@ -70,14 +71,15 @@ class Positions:
         self.rowFf = np.zeros((self.nblk, nl), np.int64)
         self.rowFt = np.zeros((self.nblk, nl), np.int64)
         self.rowC = np.full((self.nblk, 5, ng), -1, np.int64)      # LIN, DUP, DLO, CUP, CLO
-        self.pg = np.zeros(ng, np.int64)
+        self.pg = np.zeros(0 if self.screen else ng, np.int64)
         self.vm0 = np.full(ng, -1, np.int64)
         self.primal = []
         off = 0
         self.block_off = []
         for k in range(self.nblk):
             self.block_off.append(off)
-            basec = self.pvpq and k == 0
+            cont = self.screen or k > 0          # a contingency block
+            basec = self.pvpq and not cont
             for i in range(nb):
                 if basec and isgen[i]:
                     continue
@@ -90,7 +92,7 @@ class Positions:
             if self.single:
                 self.pg = off + np.arange(ng)
                 off += ng
-            if self.pvpq and k > 0:
+            if self.pvpq and cont:
                 for c in range(4):
                     self.comp[k, c] = off + np.arange(ng)
                     off += ng
@@ -104,12 +106,12 @@ class Positions:
             off += nl
             self.rowFt[k] = off + np.arange(nl)
             off += nl
-            if self.pvpq and k > 0:
+            if self.pvpq and cont:
                 for c in range(5):
                     self.rowC[k, c] = off + np.arange(ng)
                     off += ng
         self.block_off.append(off)
-        if not self.single:
+        if not self.single and not self.screen:
             self.pg = off + np.arange(ng)
             off += ng
             if self.pvpq:
@@ -121,14 +123,19 @@ class Positions:
         self.is_primal = np.zeros(self.N, bool)
         for a, b in self.primal:
             self.is_primal[a:b] = True
-        if not self.single:
+        if not self.single and not self.screen:
             self.is_primal[self.block_off[-1]:] = True
         self.nborder = self.N - self.block_off[-1]
 
 
 def branch_status(net, k):
+    """Status of every branch in block k: 0 for the block's outaged branch
+    (block k > 0 is contingency k; with screening, block k is contingency
+    k + 1, there being no base block)."""
     st = np.ones(net.nl)
-    if k > 0:
+    if getattr(net, "screen", False):
+        st[net.outage[k]] = 0.0
+    elif k > 0:
         st[net.outage[k - 1]] = 0.0
     return st
 
@@ -223,14 +230,16 @@ def assemble(net, z, sigma, diag_shift=True):
         # generator columns of the balance rows
         gb = net.gen_bus.astype(np.int64)
         jac(pos.rowQ[k][gb], pos.qg[k], -1.0)
-        jac(pos.rowP[k][gb], pos.pg, -1.0)
-        if net.pvpq and k > 0:
+        if not pos.screen:                       # screening: pg fixed, no column
+            jac(pos.rowP[k][gb], pos.pg, -1.0)
+        if net.pvpq and (k > 0 or pos.screen):
             nup, num, sup, slo = pos.comp[k]
             lin, dup, dlo, cup, clo = pos.rowC[k]
             jac(lin, nup, 1.0)
             jac(lin, num, -1.0)
             jac(lin, vm_p[gb], -1.0)
-            jac(lin, pos.vm0, 1.0)
+            if not pos.screen:                   # screening: vm0 fixed, no column
+                jac(lin, pos.vm0, 1.0)
             jac(dup, sup, 1.0)
             jac(dup, pos.qg[k], 1.0)
             jac(dlo, slo, 1.0)
@@ -244,8 +253,9 @@ def assemble(net, z, sigma, diag_shift=True):
             hess(sup, num, z[cup])
             hess(nup, slo, z[clo])
             hess(slo, nup, z[clo])
-    # objective
-    hess(pos.pg, pos.pg, 2.0 * net.gen_c2)
+    # objective (screening: pg fixed, no objective term in the variables)
+    if not pos.screen:
+        hess(pos.pg, pos.pg, 2.0 * net.gen_c2)
     # every primal keeps its diagonal in the pattern
     prim = np.flatnonzero(pos.is_primal)
     hess(prim, prim, 0.0)
@@ -287,7 +297,7 @@ def assemble(net, z, sigma, diag_shift=True):
     ddiag = np.full(duals.shape[0], -1.0 / net.rho)
     cmask = np.zeros(duals.shape[0], bool)
     if net.pvpq:
-        crow = pos.rowC[1:, 3:5].ravel()
+        crow = pos.rowC[0 if pos.screen else 1:, 3:5].ravel()
         cmask = np.isin(duals, crow)
         ddiag[cmask] -= sigma[duals[cmask]] / z[duals[cmask]]
     ddiag[~cmask] -= sigma[duals[~cmask]]

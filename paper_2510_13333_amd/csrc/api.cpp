@@ -1245,7 +1245,7 @@ static int nlp_check(const Handle &h, const ncl_nlp *p) {
     if (!p || !p->pd || !(p->mu > 0) || !(p->rho > 0) || !(p->vmax > p->vmin) || !(p->qmax > 0) || !(p->pmax > 0) ||
         !(p->smax2 > 0) || p->eps < 0)
         return NCL_ERR_ARG;
-    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_PVPQ)) return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & (NCL_PVPQ | NCL_SCREEN))) return NCL_ERR_ARG;
     if (!h.bound) return NCL_ERR_STATE;
     return NCL_OK;
 }

@@ -16,11 +16,12 @@ namespace {
 struct Net {
     int nb, nl, ng, K;
     const int32_t *f, *t, *gb, *out;
-    bool pvpq;
+    bool pvpq, screen;
 };
 
-// template kinds
-enum { T_SINGLE, T_PLAIN, T_PVPQ_BASE, T_PVPQ_CONT };
+// template kinds; the screening ones are contingency blocks whose first-stage
+// variables (pg, and vm0 with PV/PQ rows) are fixed, so they have no border
+enum { T_SINGLE, T_PLAIN, T_PVPQ_BASE, T_PVPQ_CONT, T_SCREEN_PLAIN, T_SCREEN_PVPQ };
 
 struct Local {
     std::vector<int32_t> vm, va, qg, pg, nup, num, sup, slo, vm0, rP, rQ, rFf, rFt, rLin, rDup, rDlo, rCup, rClo;
@@ -29,6 +30,7 @@ struct Local {
 using PairList = std::vector<std::pair<int32_t, int32_t>>;   // (row, col), row >= col
 
 void add_pair(PairList &tp, PairList &bp, int n, int32_t a, int32_t b) {
+    if (a < 0 || b < 0) return;        // a fixed (screening) first-stage variable
     int32_t r = std::max(a, b), c = std::min(a, b);
     if (c >= n) bp.emplace_back(r - n, c - n);
     else tp.emplace_back(r, c);
@@ -38,7 +40,8 @@ void layout(const Net &net, int kind, Local &L, int &n, int &nprim, std::vector<
     const int nb = net.nb, nl = net.nl, ng = net.ng;
     std::vector<int> genat(nb, -1);
     for (int g = 0; g < ng; g++) genat[net.gb[g]] = g;
-    const bool base_pvpq = kind == T_PVPQ_BASE, cont_pvpq = kind == T_PVPQ_CONT;
+    const bool base_pvpq = kind == T_PVPQ_BASE, cont_pvpq = kind == T_PVPQ_CONT || kind == T_SCREEN_PVPQ;
+    const bool screen = kind == T_SCREEN_PLAIN || kind == T_SCREEN_PVPQ;
     nprim = (base_pvpq ? nb - ng : nb) + nb + ng + (kind == T_SINGLE ? ng : 0) + (cont_pvpq ? 4 * ng : 0);
     int ndual = 2 * nb + 2 * nl + (cont_pvpq ? 5 * ng : 0);
     n = nprim + ndual;
@@ -58,11 +61,11 @@ void layout(const Net &net, int kind, Local &L, int &n, int &nprim, std::vector<
     if (kind == T_SINGLE) seq(L.pg, ng);
     else {
         L.pg.resize(ng);
-        for (int g = 0; g < ng; g++) L.pg[g] = bpg + g;
+        for (int g = 0; g < ng; g++) L.pg[g] = screen ? -1 : bpg + g;
     }
     if (cont_pvpq) { seq(L.nup, ng); seq(L.num, ng); seq(L.sup, ng); seq(L.slo, ng); }
     L.vm0.resize(ng);
-    for (int g = 0; g < ng; g++) L.vm0[g] = net.pvpq ? bvm0 + g : -1;
+    for (int g = 0; g < ng; g++) L.vm0[g] = net.pvpq && !screen ? bvm0 + g : -1;
     seq(L.rP, nb); seq(L.rQ, nb); seq(L.rFf, nl); seq(L.rFt, nl);
     if (cont_pvpq) { seq(L.rLin, ng); seq(L.rDup, ng); seq(L.rDlo, ng); seq(L.rCup, ng); seq(L.rClo, ng); }
     isprim.assign(n, 0);
@@ -94,7 +97,7 @@ void enumerate(const Net &net, int kind, const Local &L, int n, PairList &tp, Pa
         add_pair(tp, bp, n, L.rQ[i], L.qg[g]);
         add_pair(tp, bp, n, L.qg[g], L.qg[g]);
         if (kind == T_SINGLE) add_pair(tp, bp, n, L.pg[g], L.pg[g]);
-        if (kind == T_PVPQ_CONT) {
+        if (kind == T_PVPQ_CONT || kind == T_SCREEN_PVPQ) {
             add_pair(tp, bp, n, L.rLin[g], L.nup[g]);
             add_pair(tp, bp, n, L.rLin[g], L.num[g]);
             add_pair(tp, bp, n, L.rLin[g], L.vm[i]);
@@ -143,8 +146,9 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
     if (!nw->br_from || !nw->br_to || !nw->br_r || !nw->br_x || (nw->ngen && (!nw->gen_bus || !nw->gen_c2)) ||
         (nw->ncont && !nw->outage)) { err = "null array"; return NCL_ERR_ARG; }
     Net net{nw->nbus, nw->nbranch, nw->ngen, nw->ncont, nw->br_from, nw->br_to, nw->gen_bus, nw->outage,
-            (nw->flags & NCL_PVPQ) != 0};
+            (nw->flags & NCL_PVPQ) != 0, (nw->flags & NCL_SCREEN) != 0};
     if (net.pvpq && net.K == 0) { err = "PV/PQ rows need contingencies"; return NCL_ERR_ARG; }
+    if (net.screen && net.K == 0) { err = "screening needs contingencies"; return NCL_ERR_ARG; }
     for (int l = 0; l < net.nl; l++) {
         if (net.f[l] < 0 || net.t[l] >= net.nb || net.f[l] >= net.t[l]) { err = "branch endpoints"; return NCL_ERR_ARG; }
         if (l && (net.f[l] < net.f[l - 1] || (net.f[l] == net.f[l - 1] && net.t[l] <= net.t[l - 1]))) {
@@ -173,13 +177,14 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
     Inst &I = h.inst.back();
     I.nb = net.nb; I.nl = net.nl; I.ng = net.ng; I.flags = nw->flags;
     I.blk0 = h.nblk;
-    I.nblk = net.K + 1;
-    I.nbd = net.K == 0 ? 0 : net.ng * (net.pvpq ? 2 : 1);
+    I.nblk = net.screen ? net.K : net.K + 1;
+    I.nbd = net.K == 0 || net.screen ? 0 : net.ng * (net.pvpq ? 2 : 1);
     I.gen_c2.assign(nw->gen_c2, nw->gen_c2 + net.ng);
     I.br_r.assign(nw->br_r, nw->br_r + net.nl);
     I.br_x.assign(nw->br_x, nw->br_x + net.nl);
     std::vector<int> kinds;
-    if (net.K == 0) kinds = {T_SINGLE};
+    if (net.screen) kinds = {net.pvpq ? T_SCREEN_PVPQ : T_SCREEN_PLAIN};
+    else if (net.K == 0) kinds = {T_SINGLE};
     else if (!net.pvpq) kinds = {T_PLAIN};
     else kinds = {T_PVPQ_BASE, T_PVPQ_CONT};
     const int t0 = int(h.tmpl.size());
@@ -187,8 +192,9 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
     I.nt = int(kinds.size());
     h.tmpl.resize(t0 + kinds.size());
     for (int k = 0; k < I.nblk; k++) {
-        h.block_tmpl.push_back(t0 + (k > 0 && net.pvpq ? 1 : 0));
-        h.block_outage.push_back(k > 0 ? net.out[k - 1] : -1);
+        // screening: block k is contingency k; otherwise block 0 is the base case
+        h.block_tmpl.push_back(t0 + (k > 0 && net.pvpq && !net.screen ? 1 : 0));
+        h.block_outage.push_back(net.screen ? net.out[k] : k > 0 ? net.out[k - 1] : -1);
         h.block_inst.push_back(int32_t(h.inst.size() - 1));
     }
     h.nblk += I.nblk;
@@ -201,7 +207,7 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
         t.inst = int(h.inst.size()) - 1;
         t.n = n;
         t.nprim = nprim;
-        t.pvpq_rows = kinds[q] == T_PVPQ_CONT;
+        t.pvpq_rows = kinds[q] == T_PVPQ_CONT || kinds[q] == T_SCREEN_PVPQ;
         t.pg_local = kinds[q] == T_SINGLE;
         PairList tp;
         enumerate(net, kinds[q], locs[q], n, tp, border_pairs);

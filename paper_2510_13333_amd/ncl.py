@@ -17,6 +17,7 @@ _SO = os.path.join(_HERE, "libnclkkt.so")
 _lib = None
 
 NCL_PVPQ = 1
+NCL_SCREEN = 2
 
 # kernel kinds (NCL_K_* of ncl_kkt.h), in enum order
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
@@ -174,7 +175,7 @@ def _network_struct(net, keep):
     keep.append(arrs)
     return _Network(int(net.nb), int(net.nl), int(net.ng), int(arrs["outage"].shape[0]),
                     *[_np_ptr(arrs[k]) for k in ("br_from", "br_to", "gen_bus", "outage", "br_r", "br_x", "gen_c2")],
-                    NCL_PVPQ if getattr(net, "pvpq", False) else 0)
+                    (NCL_PVPQ if getattr(net, "pvpq", False) else 0) | (NCL_SCREEN if getattr(net, "screen", False) else 0))
 
 
 class KKT:

@@ -245,3 +245,21 @@ def test_profile_stride_arguments():
     k.profile_stride(3)
     with pytest.raises(NclError):
         k.profile_stride(0)
+
+
+@pytest.mark.parametrize("pvpq", [False, True])
+def test_screening_symbolic_matches_oracle(pvpq):
+    """Screening networks (NCL_SCREEN): no border, the contingency blocks
+    alone; pattern and symbolic analysis bit-exact with the oracle's."""
+    net = G.make_network(43, 60, 84, 9, 6, pvpq=pvpq, rho=1e5, screen=True)
+    z, s = G.draw_point(net, 43)
+    cp, ri, v, pos = O.kkt(net, z, s)
+    k = KKT(net)
+    assert k.N == pos.N and k.instances[0]["nbd"] == 0 and k.instances[0]["nblk"] == 6
+    cpl, ril = k.pattern()
+    assert np.array_equal(cpl, cp) and np.array_equal(ril, ri)
+    F = O.Factor(pos.N, cp, ri, np.array(pos.block_off))
+    sym = k.symbolic()
+    assert np.array_equal(sym["perm"], F.perm) and np.array_equal(sym["etree"], F.parent)
+    assert np.array_equal(sym["lcolptr"], F.lp) and np.array_equal(sym["lrowind"], F.li)
+    assert np.array_equal(sym["super_ptr"], F.sup)

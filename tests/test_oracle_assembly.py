@@ -220,3 +220,30 @@ def test_union_pattern_is_value_independent():
         pats.append((rr, c1[m] - a))
     for p in pats[1:]:
         assert np.array_equal(p[0], pats[0][0]) and np.array_equal(p[1], pats[0][1])
+
+
+def test_screening_blocks_equal_contingency_blocks():
+    """Contingency screening (eq. (screening)) fixes the first-stage
+    variables, so each screening block is the KKT of its contingency alone:
+    block k of the screening network must equal, entry for entry, block k+1
+    of the corrective network on the same grid and outages (the part of K
+    inside that block), at the same block state; the screening network has
+    no base block and no border."""
+    for pvpq in (False, True):
+        full = G.make_network(41, 24, 33, 5, 3, pvpq=pvpq, rho=1e5)
+        scr = G.make_network(41, 24, 33, 5, 3, pvpq=pvpq, rho=1e5, screen=True)
+        assert np.array_equal(full.outage, scr.outage) and scr.nblk == full.nblk - 1
+        zf, sf = G.draw_point(full, 41)
+        pf = A.Positions(full)
+        ps = A.Positions(scr)
+        assert ps.N == pf.block_off[-1] - pf.block_off[1] and ps.nborder == 0
+        zs = zf[pf.block_off[1]:pf.block_off[-1]].copy()
+        ss = sf[pf.block_off[1]:pf.block_off[-1]].copy()
+        Kf = A.to_dense(*A.assemble(full, zf, sf)[:3], pf.N)
+        Ks = A.to_dense(*A.assemble(scr, zs, ss)[:3], ps.N)
+        for k in range(scr.nblk):
+            a0, a1 = pf.block_off[k + 1], pf.block_off[k + 2]
+            b0, b1 = ps.block_off[k], ps.block_off[k + 1]
+            assert np.array_equal(Ks[b0:b1, b0:b1], Kf[a0:a1, a0:a1]), (pvpq, k)
+            # no coupling between screening blocks
+            assert not Ks[b0:b1, :b0].any() and not Ks[b0:b1, b1:].any()
