@@ -433,7 +433,7 @@ def run_batched(args):
     x = torch.empty_like(b)
     rho = nets[0].rho
     print(f"[bench] batched: {len(nets)} networks N={kb.N} nnzL={kb.nnzL} analyze={t_analyze:.2f}s "
-          f"tiles={'autotuned' if table else 'default'}", file=sys.stderr, flush=True)
+          f"amalgamation={sorted(set(relax)) if relax else 'default'}", file=sys.stderr, flush=True)
 
     def step():
         kb.assemble(z, s, rho)
@@ -537,7 +537,9 @@ def run_batched(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[cfg], "step": "assemble+factor+solve of all 64 networks, nrhs=1",
-                   "N": kb.N, "nnzL": kb.nnzL, "networks": n, "tiles": "autotuned" if table else "default"},
+                   "N": kb.N, "nnzL": kb.nnzL, "networks": n,
+                   "amalgamation": ("per size class from the tuner's table: " + ", ".join(
+                       "/".join(map(str, r)) for r in sorted(set(relax)))) if relax else "default 16/1/4"},
         "roofline": roof,
         "copy_peak_GBs": peak_copy,
         "batched_graph_per_s": n * args.steps / wall_graph,
