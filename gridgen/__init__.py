@@ -340,6 +340,58 @@ def draw_directions(n: int, count: int, cfg: int, instance: int = 0) -> np.ndarr
     return d / np.linalg.norm(d, axis=1, keepdims=True)
 
 
+def draw_ipm_point(net: Network, cfg: int, instance: int = 0, iteration: int = 0):
+    """One interior point of the NCL subproblem's primal-dual IPM: a dict of
+    arrays in layout order (bounds lo/hi, z, rt, s, zl, zu, y_n) and the
+    loads pd.
+
+    Bounds (the subproblem's data): vm and vm0 in [0.9, 1.1]; pg in [0, 8];
+    qg in [-3, 3] in blocks without complementarity rows (in the others the
+    DUP/DLO rows bound it through s_up, s_lo); the complementarity variables
+    >= 0; angles free.  Values strictly inside: z as draw_point gives it
+    except the flow-row multipliers, 10^U(-3, 0) (> 0, they are inequality
+    multipliers); slacks 10^U(-2, 1) on flow rows and draw_point's s on
+    CUP/CLO rows; bound multipliers 10^U(-3, 1); rt ~ 1e-3 N(0, 1);
+    y_n = y + 0.1 N(0, 1) at dual rows.
+
+    Draw order: draw_point's, then flow multipliers, flow slacks, zl, zu,
+    rt, y_n, loads (a stream of its own)."""
+    kind, _, block, _ = layout(net)
+    z, sig = draw_point(net, cfg, instance, iteration)
+    g = rng(cfg, instance, 11000 + iteration)
+    N = kind.shape[0]
+    inf = np.inf
+    lo = np.full(N, -inf)
+    hi = np.full(N, inf)
+    for k in (VM, VM0):
+        lo[kind == k], hi[kind == k] = 0.9, 1.1
+    lo[kind == PG], hi[kind == PG] = 0.0, 8.0
+    comp_blk = np.array([net.pvpq and b >= 0 and net.cont_block(int(b)) for b in block])
+    q = (kind == QG) & ~comp_blk
+    lo[q], hi[q] = -3.0, 3.0
+    for k in (NUP, NUM, SUP, SLO):
+        lo[kind == k] = 0.0
+    flow = (kind == ROW_FF) | (kind == ROW_FT)
+    comp = (kind == ROW_CUP) | (kind == ROW_CLO)
+    z[flow] = 10.0 ** g.uniform(-3.0, 0.0, int(flow.sum()))
+    s = np.zeros(N)
+    s[flow] = 10.0 ** g.uniform(-2.0, 1.0, int(flow.sum()))
+    s[comp] = sig[comp]
+    pm = is_primal(kind)
+    zl = np.zeros(N)
+    zu = np.zeros(N)
+    a = pm & np.isfinite(lo)
+    zl[a] = 10.0 ** g.uniform(-3.0, 1.0, int(a.sum()))
+    a = pm & np.isfinite(hi)
+    zu[a] = 10.0 ** g.uniform(-3.0, 1.0, int(a.sum()))
+    rt = np.zeros(N)
+    rt[~pm] = 1e-3 * g.standard_normal(int((~pm).sum()))
+    y_n = np.zeros(N)
+    y_n[~pm] = z[~pm] + 0.1 * g.standard_normal(int((~pm).sum()))
+    pd = draw_loads(net, cfg, instance, 11000 + iteration)
+    return dict(lo=lo, hi=hi, z=z, rt=rt, s=s, zl=zl, zu=zu, y_n=y_n), pd
+
+
 # ---------------------------------------------------------------- configurations
 
 CONFIGS = {
