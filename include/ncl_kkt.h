@@ -371,9 +371,12 @@ typedef struct {
 } ncl_nlp;
 
 /* Layout kinds (HOST out, [N]): for each global column, 1 vm, 2 va, 3 qg,
- * 4 pg, 5 P balance row, 6 Q balance row, 7 flow row, 0 anything else
- * (complementarity variables and rows, border vm0). */
-enum { NCL_L_OTHER = 0, NCL_L_VM, NCL_L_VA, NCL_L_QG, NCL_L_PG, NCL_L_ROWP, NCL_L_ROWQ, NCL_L_FLOW };
+ * 4 pg, 5 P balance row, 6 Q balance row, 7 flow row, 8..11 the
+ * complementarity variables nu_plus, nu_minus, s_up, s_lo, 12..16 the rows
+ * LIN, DUP, DLO, CUP, CLO, 17 the border vm0. */
+enum { NCL_L_OTHER = 0, NCL_L_VM, NCL_L_VA, NCL_L_QG, NCL_L_PG, NCL_L_ROWP, NCL_L_ROWQ, NCL_L_FLOW,
+       NCL_L_NUP, NCL_L_NUM, NCL_L_SUP, NCL_L_SLO, NCL_L_LIN, NCL_L_DUP, NCL_L_DLO, NCL_L_CUP, NCL_L_CLO,
+       NCL_L_VM0 };
 int ncl_kkt_layout_kinds(const ncl_kkt *h, uint8_t *kinds);
 
 /* F (DEVICE [N]) = F(z; pd) and sigma (DEVICE [N]) = the barrier Hessian
@@ -438,6 +441,112 @@ int ncl_kkt_dispatch_outputs(ncl_kkt *h, const double *dz, double *dphi, double 
  * NCL_ERR_STATE without usable factors. */
 int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const double *dgphi, const double *dgpg,
                          double *dgpd, double *dwork, void *stream);
+
+/* ---------------------------------------------------------------- IPM step
+ * One Newton direction of the primal-dual interior-point method that
+ * solves the NCL subproblem (Section IV-A, eq. (nclsubpb); its KKT
+ * conditions eq. (kktncl) with the complementarity products perturbed to
+ * mu, Section IV-B) of the corrective SCOPF, PV/PQ rows included:
+ *
+ *   min  phi(w) + lam_n' r + nu0_n' t + rho/2 (|r|^2 + |t|^2)
+ *   s.t. c_E(w) - r = 0            balance, LIN, DUP, DLO rows
+ *        c_I(w) + s - r = 0, s >= 0  flow rows (h <= smax2) and CUP/CLO rows
+ *        lo <= w <= hi             (finite bounds only)
+ *
+ * phi = sum_g c2_g pg_g^2 + (eps/2) sum over blocks of bus 0's angle^2.
+ * c: P_i = sum of branch-end P leaving bus i - pg at i + pd_i; Q_i likewise
+ * with qg and qd_ratio pd_i; flow rows P^2 + Q^2 - smax2 at both ends;
+ * LIN = nu_plus - nu_minus - vm_i + vm0_g, DUP = s_up - (qmax - qg),
+ * DLO = s_lo - (qg + qmax), CUP = nu_minus s_up, CLO = nu_plus s_lo.  The
+ * slack of an inequality row has the row multiplier as its bound
+ * multiplier (S V0 = mu e for the complementarity rows; the flow rows take
+ * the same form).  Unknowns: w and y (the state vector z), the
+ * regularisation rt (r on the rows of c, t on CUP/CLO), the slacks s and
+ * the bound multipliers zl, zu.  Eliminating rt, s, zl, zu from the Newton
+ * equations leaves eq. (newtonsystem), K [dw; dy] = [r1; r2], where K is
+ * the assembled matrix (NCL_NO_SHIFT) at
+ *   sigma = zl/(w - lo) + zu/(hi - w) (+ eps at the reference angles) on
+ *   primal positions, s on CUP/CLO rows, s/y on flow rows, 0 elsewhere,
+ * and
+ *   r1 = -(grad phi + J' y) + mu/(w - lo) - mu/(hi - w)
+ *   r2 = -c(w) + (y - y_n)/rho - [inequality row] mu/y.
+ * The eliminated directions follow from (dw, dy); their signs are those of
+ * the linearisation (the printed recovery formulas of Section IV-B carry
+ * the opposite sign on the mu terms and on d lam):
+ *   d rt = (dy + y - y_n - rho rt)/rho                (dual rows)
+ *   d s  = mu/y - s - (s/y) dy                         (inequality rows)
+ *   d zl = (mu - (w - lo) zl - zl dw)/(w - lo)         (finite lo)
+ *   d zu = (mu - (hi - w) zu + zu dw)/(hi - w)         (finite hi).
+ * Handles of one network only: NCL_SCREEN networks (no pg variable),
+ * batches of several networks and pattern handles are rejected
+ * (NCL_ERR_ARG). */
+typedef struct {
+    const double *pd;        /* DEVICE [nbus] active loads */
+    const double *lo, *hi;   /* DEVICE [N] bounds at primal positions (-inf/+inf: none; dual rows ignored) */
+    const double *y_n;       /* DEVICE [N] multiplier estimates lam_n, nu0_n at dual rows */
+    double qd_ratio, qmax, smax2, eps;
+    double mu, rho;
+} ncl_ipm_problem;
+
+/* A primal-dual point, DEVICE [N] each, layout order (entries outside the
+ * positions named are not read). */
+typedef struct {
+    const double *z;         /* w at primal positions, y at dual rows (inequality rows: y > 0) */
+    const double *rt;        /* dual rows */
+    const double *s;         /* inequality rows (s > 0) */
+    const double *zl, *zu;   /* primal positions with a finite lo, resp. hi */
+} ncl_ipm_state;
+
+/* A direction, DEVICE [N] each, written at every position (zero where the
+ * unknown does not exist). */
+typedef struct {
+    double *dz;              /* (dw, dy) */
+    double *drt, *ds, *dzl, *dzu;
+} ncl_ipm_direction;
+
+/* sigma (DEVICE out [N]) of the Newton matrix at the point (see above).
+ * Asynchronous. */
+int ncl_kkt_ipm_sigma(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *s, double *dsigma, void *stream);
+
+/* The reduced right-hand side (r1, r2) (DEVICE out [N]).  J' y is taken
+ * from the K values the handle holds, which must have been assembled at
+ * the same z (any sigma, any diagonal shift: only the Jacobian blocks are
+ * read).  dwork: DEVICE 2 N doubles.  NCL_ERR_STATE without values.
+ * Asynchronous. */
+int ncl_kkt_ipm_rhs(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *s, double *drhs, double *dwork,
+                    void *stream);
+
+/* The eliminated directions from ddz = (dw, dy): writes d->drt, d->ds,
+ * d->dzl, d->dzu (d->dz is not touched).  Asynchronous. */
+int ncl_kkt_ipm_recover(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *s, const double *ddz,
+                        const ncl_ipm_direction *d, void *stream);
+
+/* Inertia correction (Section V-C: the Newton matrix must have n positive
+ * and m negative eigenvalues; when it does not, a primal shift is added and
+ * the matrix factored again): assembles K at (dz, dsigma) with
+ * NCL_NO_SHIFT and factors it; while its inertia is not (n, m) (or a pivot
+ * is zero or not finite) it adds dw to sigma on the primal positions and
+ * assembles and factors again, dw taking 0, then dw_last/3 (1e-4 if
+ * dw_last is 0), growing x8 below 1e12.  On success the factors of the
+ * accepted matrix are held (solvable), o->dw_last is the accepted shift
+ * (0 when the exact matrix had the inertia) and o->nfactor the number of
+ * factorisations.  dwork: DEVICE N doubles (the shifted sigma).
+ * Synchronises the stream after every factorisation.  NCL_ERR_INERTIA when
+ * no shift below 1e12 gives the inertia. */
+typedef struct {
+    double dw_last;          /* in: the last accepted shift (0 at the first step); out: this one */
+    int32_t nfactor;         /* out: factorisations made */
+    int32_t pad;
+} ncl_inertia_opts;
+int ncl_kkt_factor_inertia(ncl_kkt *h, const double *dz, const double *dsigma, double rho, ncl_inertia_opts *o,
+                           double *dwork, void *stream);
+
+/* The whole Newton direction: sigma, the inertia-corrected factorisation,
+ * the right-hand side, one solve and the recovery, all on the device (the
+ * host reads the inertia reports).  rho is p->rho.  dwork: DEVICE 3 N
+ * doubles.  Errors as ncl_kkt_factor_inertia. */
+int ncl_kkt_ipm_step(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *s, const ncl_ipm_direction *d,
+                     ncl_inertia_opts *o, double *dwork, void *stream);
 
 /* ---------------------------------------------------------------- measurement
  * Kernel kinds: every launch of the library runs exactly one kernel of one

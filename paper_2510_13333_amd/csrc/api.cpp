@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -1230,13 +1231,15 @@ int ncl_kkt_layout_kinds(const ncl_kkt *k, uint8_t *kinds) {
     if (!k || !kinds) return NCL_ERR_ARG;
     const Handle &h = k->h;
     if (!h.from_network) return NCL_ERR_ARG;
-    static_assert(int(ncl::LK_VM) == NCL_L_VM && int(ncl::LK_FLOW) == NCL_L_FLOW, "kind codes");
+    static_assert(int(ncl::LK_VM) == NCL_L_VM && int(ncl::LK_FLOW) == NCL_L_FLOW && int(ncl::LK_NUP) == NCL_L_NUP &&
+                      int(ncl::LK_CLO) == NCL_L_CLO && int(ncl::LK_VM0) == NCL_L_VM0,
+                  "kind codes");
     for (const ncl::Inst &I : h.inst) {
         for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
             const Template &t = h.tmpl[h.block_tmpl[b]];
             std::memcpy(kinds + h.block_col0[b], t.lkind.data(), size_t(t.n));
         }
-        for (int j = 0; j < I.nbd; j++) kinds[I.bstart + j] = j < I.ng ? NCL_L_PG : NCL_L_OTHER;
+        for (int j = 0; j < I.nbd; j++) kinds[I.bstart + j] = j < I.ng ? NCL_L_PG : NCL_L_VM0;
     }
     return NCL_OK;
 }
@@ -1279,6 +1282,55 @@ int ncl_kkt_max_step(ncl_kkt *k, const ncl_nlp *p, const double *z, const double
     return hip_rc(run(h, NCL_K_MAX_STEP, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
 }
 
+// ---------------------------------------------------------------- inertia correction
+
+namespace {
+
+// Assemble the exact K (no diagonal shift) at (z, sig) and factor it; ok:
+// the inertia (n, m) of the Newton matrix of a minimum, no zero or
+// non-finite pivot (single pivots may carry the other sign).
+int factor_exact(Handle &h, ncl_kkt *k, const double *z, const double *sig, double rho, bool &ok, hipStream_t st) {
+    ncl_kkt_point pt{z, sig, rho, NCL_NO_SHIFT};
+    int rc = ncl_kkt_assemble(k, &pt, st);
+    if (!rc) rc = ncl_kkt_factor(k, st);
+    ncl_kkt_report rep{};
+    if (!rc) rc = ncl_kkt_info(k, &rep, st);
+    if (rc) return rc;
+    ok = (rep.status == NCL_OK || rep.status == NCL_ERR_INERTIA) && rep.nzero == 0 && rep.nnonfinite == 0 &&
+         rep.npos == h.nprimal && rep.nneg == h.N - h.nprimal;
+    return NCL_OK;
+}
+
+// The inertia correction of Section V-C as a primal shift: the exact K,
+// then sig + dw on the primal positions with dw from a third of the last
+// accepted shift (or 1e-4), growing x8 below 1e12.  sgs: N doubles.
+int inertia_loop(Handle &h, ncl_kkt *k, const double *z, const double *sig, double rho, double &dw_last, int &nfac,
+                 double *sgs, hipStream_t st) {
+    const ncl::DevArgs a = dev_args(h);
+    bool ok = false;
+    nfac = 1;
+    int rc = factor_exact(h, k, z, sig, rho, ok, st);
+    if (rc) return rc;
+    if (ok) {
+        dw_last = 0.0;
+        return NCL_OK;
+    }
+    for (double dw = dw_last > 0 ? dw_last / 3.0 : 1e-4; dw < 1e12; dw *= 8.0) {
+        if (ncl::launch_ipm_point(a, ncl::IpmArgs{}, ncl::IPM_SHIFT, sig, dw, sgs, nullptr, nullptr, nullptr, st) !=
+            hipSuccess)
+            return NCL_ERR_HIP;
+        nfac++;
+        if ((rc = factor_exact(h, k, z, sgs, rho, ok, st))) return rc;
+        if (ok) {
+            dw_last = dw;
+            return NCL_OK;
+        }
+    }
+    return NCL_ERR_INERTIA;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- dispatch map: Newton and adjoint
 
 namespace {
@@ -1319,19 +1371,8 @@ struct Disp {
     int axpy(double al, const double *x, const double *y, double *out) {
         return hip_rc(ncl::launch_vec_axpy(h.N, al, x, y, out, st));
     }
-    // assemble the exact K (no diagonal shift) at (z, sig) and factor; ok:
-    // the inertia of a strict local minimum, (n, m), no zero or non-finite
-    // pivot (single pivots may carry the other sign)
     int factor_min(const double *z, const double *sig, double rho, bool &ok) {
-        ncl_kkt_point pt{z, sig, rho, NCL_NO_SHIFT};
-        int rc = ncl_kkt_assemble(k, &pt, st);
-        if (!rc) rc = ncl_kkt_factor(k, st);
-        ncl_kkt_report rep{};
-        if (!rc) rc = ncl_kkt_info(k, &rep, st);
-        if (rc) return rc;
-        ok = (rep.status == NCL_OK || rep.status == NCL_ERR_INERTIA) && rep.nzero == 0 && rep.nnonfinite == 0 &&
-             rep.npos == h.nprimal && rep.nneg == h.N - h.nprimal;
-        return NCL_OK;
+        return factor_exact(h, k, z, sig, rho, ok, st);
     }
 };
 
@@ -1367,23 +1408,9 @@ int ncl_kkt_dispatch_newton(ncl_kkt *k, const ncl_nlp *p, double *dz_state, doub
         if ((rc = D.residual(q, z, F, sig)) || (rc = D.norm2(F, nrm))) return rc;
         bool converged = false;
         for (int it = 0; it < o->maxit && !converged; it++) {
-            // Newton matrix with the inertia of a minimum: the exact K, else
-            // with dw on the primal diagonal, dw from a third of the last
-            // accepted value (or 1e-4) growing x8 (the inertia correction of
-            // Section V-C as a primal shift)
-            bool ok = false;
-            if ((rc = D.factor_min(z, sig, q.rho, ok))) return rc;
-            if (ok) {
-                o->dw_last = 0.0;
-            } else {
-                double dw = o->dw_last > 0 ? o->dw_last / 3.0 : 1e-4;
-                for (; dw < 1e12 && !ok; dw *= 8.0) {
-                    if (ncl::launch_disp_point(D.a, q, sig, dw, 1, sgs, D.st) != hipSuccess) return NCL_ERR_HIP;
-                    if ((rc = D.factor_min(z, sgs, q.rho, ok))) return rc;
-                    if (ok) o->dw_last = dw;
-                }
-                if (!ok) return NCL_ERR_INERTIA;
-            }
+            // Newton matrix with the inertia of a minimum (the inertia correction)
+            int nfac = 0;
+            if ((rc = inertia_loop(h, k, z, sig, q.rho, o->dw_last, nfac, sgs, D.st))) return rc;
             // dz = -K^{-1} F (the solve is linear and rounding is symmetric
             // under negation, so this equals the solve of -F bit for bit)
             if ((rc = ncl_kkt_solve(k, F, dz, 1, N, D.st))) return rc;
@@ -1457,6 +1484,120 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *k, const ncl_nlp *p, const double *dz, const d
     if (ncl::launch_disp_adjoint(a, dz, dgphi, dgpg, g, st) != hipSuccess) return NCL_ERR_HIP;
     if ((rc = ncl_kkt_solve_adjoint(k, g, adj, 1, h.N, stream))) return rc;
     return hip_rc(ncl::launch_disp_load_grad(a, adj, p->qd_ratio, dgpd, st));
+}
+
+// ---------------------------------------------------------------- IPM step
+
+static int ipm_check(const Handle &h, const ncl_ipm_problem *p, const ncl_ipm_state *s) {
+    if (!p || !s || !p->pd || !p->lo || !p->hi || !p->y_n || !s->z || !s->rt || !s->s || !s->zl || !s->zu)
+        return NCL_ERR_ARG;
+    if (!(p->mu > 0) || !(p->rho > 0) || !(p->smax2 > 0) || !(p->qmax > 0) || !(p->eps >= 0) ||
+        !std::isfinite(p->qd_ratio) || !std::isfinite(p->mu) || !std::isfinite(p->rho))
+        return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_SCREEN)) return NCL_ERR_ARG;
+    if (!h.bound) return NCL_ERR_STATE;
+    return NCL_OK;
+}
+
+static ncl::IpmArgs ipm_args(const ncl_ipm_problem &p, const ncl_ipm_state &s) {
+    ncl::IpmArgs q;
+    q.pd = p.pd;
+    q.lo = p.lo;
+    q.hi = p.hi;
+    q.yn = p.y_n;
+    q.z = s.z;
+    q.rt = s.rt;
+    q.s = s.s;
+    q.zl = s.zl;
+    q.zu = s.zu;
+    q.qd_ratio = p.qd_ratio;
+    q.qmax = p.qmax;
+    q.smax2 = p.smax2;
+    q.eps = p.eps;
+    q.mu = p.mu;
+    q.rho = p.rho;
+    return q;
+}
+
+// r = (r1, r2): the multipliers masked to the dual rows (xm), the residual
+// xm - K xm, whose primal rows are -J'y, c and grad phi (cg), combined
+static int ipm_rhs(Handle &h, const ncl::IpmArgs &q, double *r, double *work, hipStream_t st) {
+    const ncl::DevArgs a = dev_args(h);
+    double *xm = work, *cg = work + h.N;
+    if (ncl::launch_ipm_point(a, q, ncl::IPM_MASK, nullptr, 0.0, xm, nullptr, nullptr, nullptr, st) != hipSuccess)
+        return NCL_ERR_HIP;
+    int rc = residual_column(h, a, xm, xm, nullptr, st);
+    if (rc) return rc;
+    if (ncl::launch_ipm_cons(a, q, cg, st) != hipSuccess) return NCL_ERR_HIP;
+    return hip_rc(ncl::launch_ipm_point(a, q, ncl::IPM_RHS, cg, 0.0, r, nullptr, nullptr, nullptr, st));
+}
+
+int ncl_kkt_ipm_sigma(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_ipm_state *s, double *dsigma, void *stream) {
+    if (!k || !dsigma) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    const int rc = ipm_check(h, p, s);
+    if (rc) return rc;
+    return hip_rc(ncl::launch_ipm_point(dev_args(h), ipm_args(*p, *s), ncl::IPM_SIGMA, nullptr, 0.0, dsigma, nullptr,
+                                        nullptr, nullptr, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ncl_kkt_ipm_rhs(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_ipm_state *s, double *drhs, double *dwork,
+                    void *stream) {
+    if (!k || !drhs || !dwork) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    const int rc = ipm_check(h, p, s);
+    if (rc) return rc;
+    if (!h.values_set) return NCL_ERR_STATE;
+    return ipm_rhs(h, ipm_args(*p, *s), drhs, dwork, reinterpret_cast<hipStream_t>(stream));
+}
+
+int ncl_kkt_ipm_recover(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_ipm_state *s, const double *ddz,
+                        const ncl_ipm_direction *d, void *stream) {
+    if (!k || !ddz || !d || !d->drt || !d->ds || !d->dzl || !d->dzu) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    const int rc = ipm_check(h, p, s);
+    if (rc) return rc;
+    return hip_rc(ncl::launch_ipm_point(dev_args(h), ipm_args(*p, *s), ncl::IPM_RECOVER, ddz, 0.0, d->drt, d->ds,
+                                        d->dzl, d->dzu, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ncl_kkt_factor_inertia(ncl_kkt *k, const double *dz, const double *dsigma, double rho, ncl_inertia_opts *o,
+                           double *dwork, void *stream) {
+    if (!k || !dz || !dsigma || !o || !dwork || !(rho > 0) || !(o->dw_last >= 0)) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.from_network || h.inst.size() != 1) return NCL_ERR_ARG;
+    if (!h.bound) return NCL_ERR_STATE;
+    int nfac = 0;
+    const int rc = inertia_loop(h, k, dz, dsigma, rho, o->dw_last, nfac, dwork, reinterpret_cast<hipStream_t>(stream));
+    o->nfactor = nfac;
+    return rc;
+}
+
+int ncl_kkt_ipm_step(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_ipm_state *s, const ncl_ipm_direction *d,
+                     ncl_inertia_opts *o, double *dwork, void *stream) {
+    if (!k || !d || !d->dz || !d->drt || !d->ds || !d->dzl || !d->dzu || !o || !dwork || !(o->dw_last >= 0))
+        return NCL_ERR_ARG;
+    Handle &h = k->h;
+    int rc = ipm_check(h, p, s);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    const ncl::IpmArgs q = ipm_args(*p, *s);
+    const int64_t N = h.N;
+    // sigma, then the inertia-corrected factorisation; once factored, the
+    // same dwork holds the right-hand side (first N) and its work (2 N)
+    double *sg = dwork, *sgs = dwork + N;
+    if (ncl::launch_ipm_point(a, q, ncl::IPM_SIGMA, nullptr, 0.0, sg, nullptr, nullptr, nullptr, st) != hipSuccess)
+        return NCL_ERR_HIP;
+    int nfac = 0;
+    rc = inertia_loop(h, k, s->z, sg, p->rho, o->dw_last, nfac, sgs, st);
+    o->nfactor = nfac;
+    if (rc) return rc;
+    double *r = dwork;
+    if ((rc = ipm_rhs(h, q, r, dwork + N, st))) return rc;
+    if ((rc = ncl_kkt_solve(k, r, d->dz, 1, N, st))) return rc;
+    return hip_rc(
+        ncl::launch_ipm_point(a, q, ncl::IPM_RECOVER, d->dz, 0.0, d->drt, d->ds, d->dzl, d->dzu, st));
 }
 
 const char *ncl_kernel_name(int kind) {

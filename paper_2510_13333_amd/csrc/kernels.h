@@ -94,6 +94,18 @@ hipError_t launch_disp_adjoint(const DevArgs &a, const double *z, const double *
                                hipStream_t st);
 hipError_t launch_disp_load_grad(const DevArgs &a, const double *adj, double qd, double *gpd, hipStream_t st);
 
+// IPM step of the NCL subproblem: its data and point (layout order) and
+// the elementwise modes of launch_ipm_point.
+struct IpmArgs {
+    const double *pd = nullptr, *lo = nullptr, *hi = nullptr, *yn = nullptr;
+    const double *z = nullptr, *rt = nullptr, *s = nullptr, *zl = nullptr, *zu = nullptr;
+    double qd_ratio = 0.0, qmax = 0.0, smax2 = 0.0, eps = 0.0, mu = 0.0, rho = 0.0;
+};
+enum IpmMode { IPM_SIGMA = 0, IPM_MASK, IPM_RHS, IPM_RECOVER, IPM_SHIFT };
+hipError_t launch_ipm_point(const DevArgs &a, const IpmArgs &q, int mode, const double *in, double dw, double *o0,
+                            double *o1, double *o2, double *o3, hipStream_t st);
+hipError_t launch_ipm_cons(const DevArgs &a, const IpmArgs &q, double *cg, hipStream_t st);
+
 // Streaming copy of n doubles (n even, both pointers 16-byte aligned).
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);
 

@@ -2190,7 +2190,7 @@ __device__ inline void col_kind(const DevArgs &a, int64_t idx, int64_t &col, uin
         const int64_t j = idx - a.dint;
         const InstDev &I = a.insts[find_inst(a, j, &InstDev::bd0)];
         col = I.bstart + (j - I.bd0);
-        kind = LK_PG;            // the border of a network without PV/PQ rows holds pg
+        kind = j - I.bd0 < I.ng ? LK_PG : LK_VM0;
     }
 }
 
@@ -2399,6 +2399,223 @@ hipError_t launch_disp_adjoint(const DevArgs &a, const double *z, const double *
 
 hipError_t launch_disp_load_grad(const DevArgs &a, const double *adj, double qd, double *gpd, hipStream_t st) {
     hipLaunchKernelGGL(k_disp_load_grad, dim3(unsigned((a.nbus_disp + 255) / 256)), dim3(256), 0, st, a, adj, qd, gpd);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ IPM step
+
+// Block (or border), residual index and kind of layout column col of a
+// network handle: the last block starting at or before col holds it, or,
+// past that block's columns, the border of its network follows.
+struct LayPos {
+    int64_t rint;                 // interleaved residual index, -1 in the border
+    uint8_t kind;
+    bool vref;                    // bus 0's angle of its block
+};
+
+__device__ inline LayPos lay_pos(const DevArgs &a, int64_t col) {
+    int lo = 0, hi = a.nblk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.blks[mid].col0 <= col) lo = mid;
+        else hi = mid - 1;
+    }
+    const BlockDev &B = a.blks[lo];
+    const TemplDev &T = a.tmpls[B.tmpl];
+    const int64_t j = col - B.col0;
+    LayPos p;
+    if (j < T.n) {
+        p.rint = T.dbase + j * T.nblk + B.bl;
+        p.kind = T.lkind[j];
+        p.vref = j == T.bus_idx[BI_VA];
+    } else {
+        const InstDev &I = a.insts[T.inst];
+        p.rint = -1;
+        p.kind = col - I.bstart < I.ng ? LK_PG : LK_VM0;
+        p.vref = false;
+    }
+    return p;
+}
+
+// Elementwise steps of the IPM direction, one thread per layout column:
+// sigma of the Newton matrix, the multiplier vector (z on dual rows, 0 on
+// primal positions), the reduced right-hand side from c / grad phi (in)
+// and the residual -J'y the row kernels left in rint / rbuf, the recovery
+// of the eliminated directions from dz (in), and the primal shift of a
+// sigma (in).
+__global__ __launch_bounds__(256) void k_ipm_point(DevArgs a, IpmArgs q, int mode, const double *__restrict__ in,
+                                                   double dw, double *__restrict__ o0, double *__restrict__ o1,
+                                                   double *__restrict__ o2, double *__restrict__ o3) {
+    const int64_t col = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (col >= a.N) return;
+    const LayPos p = lay_pos(a, col);
+    const bool primal = lk_primal(p.kind);
+    const bool comp = p.kind == LK_CUP || p.kind == LK_CLO, flow = p.kind == LK_FLOW;
+    if (mode == IPM_SHIFT) {
+        o0[col] = primal ? in[col] + dw : in[col];
+        return;
+    }
+    const double z = q.z[col];
+    if (mode == IPM_MASK) {
+        o0[col] = primal ? 0.0 : z;
+    } else if (mode == IPM_SIGMA) {
+        double v = 0.0;
+        if (primal) {
+            const double lo = q.lo[col], hi = q.hi[col];
+            if (lo > -INFINITY) v += q.zl[col] / (z - lo);
+            if (hi < INFINITY) v += q.zu[col] / (hi - z);
+            if (p.vref) v += q.eps;
+        } else if (comp) {
+            v = q.s[col];
+        } else if (flow) {
+            v = q.s[col] / z;
+        }
+        o0[col] = v;
+    } else if (mode == IPM_RHS) {
+        double v;
+        if (primal) {
+            v = -in[col] + (p.rint >= 0 ? a.rint[p.rint] : a.rbuf[col]);
+            const double lo = q.lo[col], hi = q.hi[col];
+            if (lo > -INFINITY) v += q.mu / (z - lo);
+            if (hi < INFINITY) v -= q.mu / (hi - z);
+        } else {
+            v = -in[col] + (z - q.yn[col]) / q.rho;
+            if (comp || flow) v -= q.mu / z;
+        }
+        o0[col] = v;
+    } else {
+        const double dz = in[col];
+        double drt = 0.0, ds = 0.0, dzl = 0.0, dzu = 0.0;
+        if (primal) {
+            const double lo = q.lo[col], hi = q.hi[col];
+            if (lo > -INFINITY) {
+                const double gap = z - lo, zl = q.zl[col];
+                dzl = (q.mu - gap * zl - zl * dz) / gap;
+            }
+            if (hi < INFINITY) {
+                const double gap = hi - z, zu = q.zu[col];
+                dzu = (q.mu - gap * zu + zu * dz) / gap;
+            }
+        } else {
+            drt = (dz + z - q.yn[col] - q.rho * q.rt[col]) / q.rho;
+            if (comp || flow) {
+                const double sv = q.s[col];
+                ds = q.mu / z - sv - sv / z * dz;
+            }
+        }
+        o0[col] = drt;
+        o1[col] = ds;
+        o2[col] = dzl;
+        o3[col] = dzu;
+    }
+}
+
+// Constraint values c(w) at every dual row and grad phi at every primal
+// position.  Threads as in the assembly: per template (bus, block), then
+// (generator, block), then one per generator of the network's border.  A
+// bus thread writes its vm (when in the block), va, P and Q rows and, for
+// the branches it is the from end of, both flow rows; a generator thread
+// its qg (and a single block's pg) and, with PV/PQ rows, its four
+// complementarity variables and five rows; a border thread pg and vm0.
+__global__ __launch_bounds__(256) void k_ipm_cons(DevArgs a, IpmArgs q, double *__restrict__ cg) {
+    const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const double *z = q.z;
+    if (tid >= a.asm_threads) {
+        const int64_t gg = tid - a.asm_threads;
+        if (gg >= a.gp_tot) return;
+        const InstDev &I = a.insts[find_inst(a, gg, &InstDev::gp0)];
+        const int g = int(gg - I.gp0);
+        if (I.nbd == 0 || g >= I.ng) return;
+        const int64_t col = I.bstart + I.border_pg[g];
+        cg[col] = 2.0 * I.gen_c2[g] * z[col];
+        if (I.nbd > I.ng) cg[I.bstart + I.ng + g] = 0.0;
+        return;
+    }
+    const TemplDev &T = a.tmpls[find_tmpl(a, tid, &TemplDev::abase)];
+    const int64_t u0 = tid - T.abase;
+    const int64_t nbus_t = int64_t(T.nblk) * T.nbus;
+    const int64_t bstart = a.insts[T.inst].bstart;
+    const int n = T.n;
+    if (u0 < nbus_t) {
+        const int bl = int(u0 % T.nblk), i = int(u0 / T.nblk);
+        const BlockDev B = a.blks[T.blocks[bl]];
+        const int32_t *bi = T.bus_idx + size_t(i) * BI_N;
+        const double vi = z[zi(bstart, B, n, bi[BI_VM])], ti = z[zi(bstart, B, n, bi[BI_VA])];
+        double Pinj = 0.0, Qinj = 0.0;
+        for (int qa = T.bus_adj_ptr[i]; qa < T.bus_adj_ptr[i + 1]; qa++) {
+            const int32_t e = T.bus_adj[qa];
+            const bool self_from = e >= 0;
+            const int l = self_from ? e : ~e;
+            const int32_t *br = T.br_idx + size_t(l) * 4;
+            const int o = self_from ? br[3] : br[2];
+            const int32_t *bo = T.bus_idx + size_t(o) * BI_N;
+            const double vo = z[zi(bstart, B, n, bo[BI_VM])], to = z[zi(bstart, B, n, bo[BI_VA])];
+            const double st = (l == B.outage) ? 0.0 : 1.0;
+            const double r = T.br_r[l], x = T.br_x[l], den = r * r + x * x;
+            const double g = st * (r / den), b = st * (-x / den);
+            Flow es, eo;
+            branch_flow(g, b, vi, vo, ti, to, es);
+            Pinj += es.P;
+            Qinj += es.Q;
+            if (self_from) {
+                branch_flow(g, b, vo, vi, to, ti, eo);
+                cg[zi(bstart, B, n, br[0])] = es.P * es.P + es.Q * es.Q - q.smax2;
+                cg[zi(bstart, B, n, br[1])] = eo.P * eo.P + eo.Q * eo.Q - q.smax2;
+            }
+        }
+        const int gat = T.bus_gen[i];
+        double pgv = 0.0, qgv = 0.0;
+        if (gat >= 0) {
+            const int32_t *gi = T.gen_idx + size_t(gat) * GI_N;
+            pgv = z[zi(bstart, B, n, gi[GI_PG])];
+            qgv = z[zi(bstart, B, n, gi[GI_QG])];
+        }
+        const double pd = q.pd[i];
+        cg[zi(bstart, B, n, bi[BI_P])] = Pinj - pgv + pd;
+        cg[zi(bstart, B, n, bi[BI_Q])] = Qinj - qgv + q.qd_ratio * pd;
+        if (bi[BI_VM] < n) cg[zi(bstart, B, n, bi[BI_VM])] = 0.0;
+        cg[zi(bstart, B, n, bi[BI_VA])] = i == 0 ? q.eps * ti : 0.0;
+        return;
+    }
+    const int64_t u = u0 - nbus_t;
+    const int bl = int(u % T.nblk), g = int(u / T.nblk);
+    const BlockDev B = a.blks[T.blocks[bl]];
+    const int32_t *gi = T.gen_idx + size_t(g) * GI_N;
+    const int64_t cq = zi(bstart, B, n, gi[GI_QG]);
+    cg[cq] = 0.0;
+    if (T.has_pg_local) {
+        const int64_t cp = zi(bstart, B, n, gi[GI_PG]);
+        cg[cp] = 2.0 * T.gen_c2[g] * z[cp];
+    }
+    if (T.pvpq_rows) {
+        const int64_t cnup = zi(bstart, B, n, gi[GI_NUP]), cnum = zi(bstart, B, n, gi[GI_NUM]);
+        const int64_t csup = zi(bstart, B, n, gi[GI_SUP]), cslo = zi(bstart, B, n, gi[GI_SLO]);
+        const double nup = z[cnup], num = z[cnum], sup = z[csup], slo = z[cslo], qg = z[cq];
+        const int32_t *bb = T.bus_idx + size_t(gi[GI_BUS]) * BI_N;
+        const double vi = z[zi(bstart, B, n, bb[BI_VM])], v0 = z[zi(bstart, B, n, gi[GI_VM0])];
+        cg[cnup] = 0.0;
+        cg[cnum] = 0.0;
+        cg[csup] = 0.0;
+        cg[cslo] = 0.0;
+        cg[zi(bstart, B, n, gi[GI_LIN])] = nup - num - vi + v0;
+        cg[zi(bstart, B, n, gi[GI_DUP])] = sup - (q.qmax - qg);
+        cg[zi(bstart, B, n, gi[GI_DLO])] = slo - (qg + q.qmax);
+        cg[zi(bstart, B, n, gi[GI_CUP])] = num * sup;
+        cg[zi(bstart, B, n, gi[GI_CLO])] = nup * slo;
+    }
+}
+
+hipError_t launch_ipm_point(const DevArgs &a, const IpmArgs &q, int mode, const double *in, double dw, double *o0,
+                            double *o1, double *o2, double *o3, hipStream_t st) {
+    if (a.N > 0)
+        hipLaunchKernelGGL(k_ipm_point, dim3(unsigned((a.N + 255) / 256)), dim3(256), 0, st, a, q, mode, in, dw, o0, o1,
+                           o2, o3);
+    return hipGetLastError();
+}
+
+hipError_t launch_ipm_cons(const DevArgs &a, const IpmArgs &q, double *cg, hipStream_t st) {
+    const int64_t n = a.asm_threads + a.gp_tot;
+    if (n > 0) hipLaunchKernelGGL(k_ipm_cons, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, a, q, cg);
     return hipGetLastError();
 }
 

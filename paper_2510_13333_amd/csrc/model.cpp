@@ -328,6 +328,15 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
         kind(L.rQ, LK_ROWQ);
         kind(L.rFf, LK_FLOW);
         kind(L.rFt, LK_FLOW);
+        kind(L.nup, LK_NUP);
+        kind(L.num, LK_NUM);
+        kind(L.sup, LK_SUP);
+        kind(L.slo, LK_SLO);
+        kind(L.rLin, LK_LIN);
+        kind(L.rDup, LK_DUP);
+        kind(L.rDlo, LK_DLO);
+        kind(L.rCup, LK_CUP);
+        kind(L.rClo, LK_CLO);
         t.gen_idx.assign(size_t(ng) * GI_N, -1);
         t.gen_slot.assign(size_t(ng) * GS_N, -1);
         for (int g = 0; g < ng; g++) {

@@ -154,8 +154,13 @@ struct TemplDev {
     int64_t rwbase;                // first residual-row wavefront of the template
 };
 
-// Layout-local kinds used by the dispatch-map kernels (bounds and rows).
-enum LocalKind : uint8_t { LK_OTHER = 0, LK_VM, LK_VA, LK_QG, LK_PG, LK_ROWP, LK_ROWQ, LK_FLOW };
+// Layout-local kinds used by the dispatch-map and IPM kernels (bounds and
+// rows); the codes are those of NCL_L_* in the public header.
+enum LocalKind : uint8_t {
+    LK_OTHER = 0, LK_VM, LK_VA, LK_QG, LK_PG, LK_ROWP, LK_ROWQ, LK_FLOW,
+    LK_NUP, LK_NUM, LK_SUP, LK_SLO, LK_LIN, LK_DUP, LK_DLO, LK_CUP, LK_CLO, LK_VM0
+};
+inline constexpr bool lk_primal(int k) { return (k >= LK_VM && k <= LK_PG) || (k >= LK_NUP && k <= LK_SLO) || k == LK_VM0; }
 
 // Per-instance (per-network) border data of a batch.
 struct InstDev {

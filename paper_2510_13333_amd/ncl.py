@@ -72,6 +72,26 @@ class NewtonOpts(ctypes.Structure):
                 ("dw_last", ctypes.c_double)]
 
 
+class _IpmProblem(ctypes.Structure):
+    _fields_ = [("pd", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("y_n", ctypes.c_void_p),
+                ("qd_ratio", ctypes.c_double), ("qmax", ctypes.c_double), ("smax2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double)]
+
+
+class _IpmState(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("rt", ctypes.c_void_p), ("s", ctypes.c_void_p), ("zl", ctypes.c_void_p),
+                ("zu", ctypes.c_void_p)]
+
+
+class _IpmDirection(ctypes.Structure):
+    _fields_ = [("dz", ctypes.c_void_p), ("drt", ctypes.c_void_p), ("ds", ctypes.c_void_p),
+                ("dzl", ctypes.c_void_p), ("dzu", ctypes.c_void_p)]
+
+
+class InertiaOpts(ctypes.Structure):
+    _fields_ = [("dw_last", ctypes.c_double), ("nfactor", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class Report(ctypes.Structure):
     _fields_ = [("npos", ctypes.c_int64), ("nneg", ctypes.c_int64), ("nzero", ctypes.c_int64),
                 ("first_bad", ctypes.c_int64), ("min_absd", ctypes.c_double), ("max_absd", ctypes.c_double),
@@ -133,6 +153,11 @@ def load():
         "ncl_kkt_dispatch_vjp": ([P, P, P, P, P, P, P, P], ctypes.c_int),
         "ncl_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "ncl_stream_copy": ([P, P, i64, P], ctypes.c_int),
+        "ncl_kkt_ipm_sigma": ([P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_ipm_rhs": ([P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_ipm_recover": ([P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_factor_inertia": ([P, P, P, ctypes.c_double, P, P, P], ctypes.c_int),
+        "ncl_kkt_ipm_step": ([P, P, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -445,6 +470,60 @@ class KKT:
             self._h, ctypes.byref(q), self._dev(z, self.N), self._dev(gphi), None if gpg is None else self._dev(gpg),
             self._dev(gpd), self._dev(work, 2 * self.N), _stream_ptr()))
         return gpd
+
+    # ------------------------------------------------------------ IPM step
+    def _ipm(self, prob, state):
+        """Marshal the IPM problem (dict: pd, lo, hi, y_n device tensors and
+        the scalars qd_ratio, qmax, smax2, eps, mu, rho) and state (dict: z,
+        rt, s, zl, zu device tensors)."""
+        p = _IpmProblem(self._dev(prob["pd"]), self._dev(prob["lo"], self.N), self._dev(prob["hi"], self.N),
+                        self._dev(prob["y_n"], self.N), float(prob["qd_ratio"]), float(prob["qmax"]),
+                        float(prob["smax2"]), float(prob["eps"]), float(prob["mu"]), float(prob["rho"]))
+        st = _IpmState(*[self._dev(state[k], self.N) for k in ("z", "rt", "s", "zl", "zu")])
+        return p, st
+
+    def _ipm_dir(self, d):
+        return _IpmDirection(*[self._dev(d[k], self.N) for k in ("dz", "drt", "ds", "dzl", "dzu")])
+
+    def ipm_sigma(self, prob, state, out):
+        p, st = self._ipm(prob, state)
+        _check("ncl_kkt_ipm_sigma", load().ncl_kkt_ipm_sigma(self._h, ctypes.byref(p), ctypes.byref(st),
+                                                             self._dev(out, self.N), _stream_ptr()))
+        return out
+
+    def ipm_rhs(self, prob, state, out, work):
+        """The reduced right-hand side; J'y from the K values held (assembled at state z); work: 2 N doubles."""
+        p, st = self._ipm(prob, state)
+        _check("ncl_kkt_ipm_rhs", load().ncl_kkt_ipm_rhs(self._h, ctypes.byref(p), ctypes.byref(st),
+                                                         self._dev(out, self.N), self._dev(work, 2 * self.N),
+                                                         _stream_ptr()))
+        return out
+
+    def ipm_recover(self, prob, state, dz, d):
+        """Writes d["drt"], d["ds"], d["dzl"], d["dzu"] from dz = (dw, dy)."""
+        p, st = self._ipm(prob, state)
+        dd = _IpmDirection(None, *[self._dev(d[k], self.N) for k in ("drt", "ds", "dzl", "dzu")])
+        _check("ncl_kkt_ipm_recover", load().ncl_kkt_ipm_recover(self._h, ctypes.byref(p), ctypes.byref(st),
+                                                                 self._dev(dz, self.N), ctypes.byref(dd),
+                                                                 _stream_ptr()))
+        return d
+
+    def factor_inertia(self, z, sigma, rho, opts, work):
+        """Inertia-corrected factorisation at (z, sigma); opts: InertiaOpts (updated); work: N doubles."""
+        _check("ncl_kkt_factor_inertia", load().ncl_kkt_factor_inertia(
+            self._h, self._dev(z, self.N), self._dev(sigma, self.N), float(rho), ctypes.byref(opts),
+            self._dev(work, self.N), _stream_ptr()))
+        return opts
+
+    def ipm_step(self, prob, state, d, opts, work):
+        """One IPM direction into d (dict of device tensors dz, drt, ds, dzl,
+        dzu); opts: InertiaOpts (updated); work: 3 N doubles."""
+        p, st = self._ipm(prob, state)
+        dd = self._ipm_dir(d)
+        _check("ncl_kkt_ipm_step", load().ncl_kkt_ipm_step(self._h, ctypes.byref(p), ctypes.byref(st),
+                                                           ctypes.byref(dd), ctypes.byref(opts),
+                                                           self._dev(work, 3 * self.N), _stream_ptr()))
+        return d
 
     # ------------------------------------------------------------ measurement
     @staticmethod

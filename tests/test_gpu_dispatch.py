@@ -124,7 +124,7 @@ def test_c5_gradients_vs_oracle_and_fd():
     s = DispatchSolver(net)
     pdt = dev(pd).requires_grad_(True)
     phi, pg = s(pdt)
-    print(f"[c5] Newton iterations {s.iterations}, phi {float(phi):.6f}", flush=True)
+    print(f"[c5] Newton iterations {s.iterations}, phi {float(phi.detach()):.6f}", flush=True)
     w = np.random.default_rng(2).standard_normal(net.ng)
     (g,) = torch.autograd.grad(phi, pdt, retain_graph=True)
     (gw,) = torch.autograd.grad(pg, pdt, grad_outputs=dev(w))

@@ -263,3 +263,18 @@ def test_screening_symbolic_matches_oracle(pvpq):
     assert np.array_equal(sym["perm"], F.perm) and np.array_equal(sym["etree"], F.parent)
     assert np.array_equal(sym["lcolptr"], F.lp) and np.array_equal(sym["lrowind"], F.li)
     assert np.array_equal(sym["super_ptr"], F.sup)
+
+
+@pytest.mark.parametrize("pvpq", [False, True])
+def test_layout_kinds_match_the_layout(pvpq):
+    """The kind codes the IPM kernels read (NCL_L_*) name every column as the
+    documented layout does: balance and flow rows, the complementarity
+    variables and rows, the border pg and vm0."""
+    net = G.make_network(99, 9, 12, 3, 2, pvpq=pvpq, rho=1e5)
+    k = KKT(net)
+    kinds = k.layout_kinds()
+    gk, _, _, _ = G.layout(net)
+    code = {G.VM: 1, G.VA: 2, G.QG: 3, G.PG: 4, G.ROW_P: 5, G.ROW_Q: 6, G.ROW_FF: 7, G.ROW_FT: 7,
+            G.NUP: 8, G.NUM: 9, G.SUP: 10, G.SLO: 11, G.ROW_LIN: 12, G.ROW_DUP: 13, G.ROW_DLO: 14,
+            G.ROW_CUP: 15, G.ROW_CLO: 16, G.VM0: 17}
+    assert np.array_equal(kinds, np.array([code[int(x)] for x in gk], np.uint8))
