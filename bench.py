@@ -328,6 +328,12 @@ def run_single(args):
                          f"C left-looking LDL^T with OpenMP over the blocks on {threads} threads, and again on "
                          f"1 thread; K assembled by numpy and the symbolic analysis done beforehand, untimed"}
 
+    ipm = None
+    if not args.no_ipm and not getattr(net, "screen", False):
+        ipm = ipm_steps(k, net, cfg, args.ipm_steps)
+        print(f"[bench] IPM step: {ipm['ms_median']:.3f} ms median over {ipm['steps']} points, "
+              f"{ipm['factorizations_mean']:.1f} factorisations each", file=sys.stderr, flush=True)
+
     disp = None
     if cfg == 5 and not args.no_dispatch:
         disp = dispatch_backward(net, args.steps)
@@ -371,7 +377,48 @@ def run_single(args):
     }
     if disp is not None:
         out["dispatch_map"] = disp
+    if ipm is not None:
+        out["ipm_step"] = ipm
     print(json.dumps(out), flush=True)
+
+
+def ipm_steps(k, net, cfg, steps):
+    """The IPM step of the NCL subproblem on this network (ncl_kkt_ipm_step:
+    sigma, the inertia-corrected factorisation, the right-hand side, one
+    solve and the recovery) at `steps` seeded interior points, each shift
+    warm-started from the previous point's as an IPM run does; wall clock
+    per step (the inertia loop reads each factorisation's report)."""
+    import torch
+    import gridgen as G
+    from paper_2510_13333_amd.ncl import InertiaOpts
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).to("cuda")
+    N = k.N
+    pts = []
+    for it in range(steps + 1):
+        d, pd = G.draw_ipm_point(net, cfg, iteration=it)
+        prob = dict(pd=dev(pd), lo=dev(d["lo"]), hi=dev(d["hi"]), y_n=dev(d["y_n"]), qd_ratio=0.3, qmax=3.0,
+                    smax2=100.0, eps=1.0, mu=0.1, rho=net.rho)
+        pts.append((prob, {n: dev(d[n]) for n in ("z", "rt", "s", "zl", "zu")}))
+    dirs = {n: torch.empty(N, dtype=torch.float64, device="cuda") for n in ("dz", "drt", "ds", "dzl", "dzu")}
+    work = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    opts = InertiaOpts(0.0, 0, 0)
+    k.ipm_step(*pts[0], dirs, opts, work)          # warm-up
+    torch.cuda.synchronize()
+    ts, nf, dws = [], [], []
+    for prob, st in pts[1:]:
+        t0 = time.perf_counter()
+        k.ipm_step(prob, st, dirs, opts, work)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        nf.append(opts.nfactor)
+        dws.append(opts.dw_last)
+    ms = np.array(ts) * 1e3
+    return {"what": "one Newton direction of the NCL subproblem's IPM at seeded interior points: sigma, "
+                    "inertia-corrected assemble+factor (shift sequence warm-started from the previous point), "
+                    "right-hand side from the KKT residuals, one solve, recovery of the eliminated directions",
+            "steps": steps, "ms_median": float(np.median(ms)), "ms_min": float(ms.min()),
+            "factorizations_mean": float(np.mean(nf)), "factorizations": nf,
+            "ms_per_factorization": float(np.median(ms / np.array(nf))), "shifts": dws}
 
 
 def dispatch_backward(net, steps):
@@ -597,6 +644,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-dispatch", action="store_true", help="skip the dispatch-map backward timing (config 5)")
+    ap.add_argument("--no-ipm", action="store_true", help="skip the IPM-step timing")
+    ap.add_argument("--ipm-steps", type=int, default=5, help="interior points of the IPM-step timing")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default=None)
     args = ap.parse_args()
