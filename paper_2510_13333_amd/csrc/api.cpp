@@ -123,7 +123,7 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts, int nopts) {
         h.nsuper += int64_t(t.sup.size()) - 1;
         h.npanel += int64_t(t.sri.size());
     }
-    h.nbd_tot = h.nbb_tot = h.npk_tot = h.sp_tot = h.cp_tot = h.gp_tot = 0;
+    h.nbd_tot = h.nbb_tot = h.npk_tot = h.sp_tot = h.cp_tot = h.gp_tot = h.mw_tot = h.pe_tot = 0;
     h.max_nbd = 0;
     for (auto &I : h.inst) {
         I.kbb0 = h.nbb_tot;
@@ -136,7 +136,11 @@ int finish_analyze(Handle &h, const ncl_analyze_opts *opts, int nopts) {
         h.nbb_tot += I.nbb();
         h.npk_tot += I.npk();
         h.nbd_tot += I.nbd;
-        h.sp_tot += I.npk() * I.nblk;
+        I.mw0 = h.mw_tot;
+        h.mw_tot += int64_t(I.mdesc.size());
+        I.pe0 = h.pe_tot;
+        h.pe_tot += int64_t(I.npair) * ncl::kMT * ncl::kMT;
+        h.sp_tot += int64_t(I.mdesc.size()) * ncl::kMT * ncl::kMT;
         h.cp_tot += int64_t(I.nbd) * I.nblk;
         if (I.nbd) h.gp_tot += I.ng;
         h.max_nbd = std::max(h.max_nbd, I.nbd);
@@ -207,7 +211,6 @@ std::vector<ncl::Work> all_work(Handle &h) {
     app(S.sn, h.w_sn);
     app(S.sb, h.w_sb);
     app(S.bpart, h.w_bpart);
-    app(S.schur, h.w_schur);
     return w;
 }
 
@@ -269,9 +272,6 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         o.push_back(L.vec(t.terms));
         o.push_back(L.vec(t.bterm_ptr));
         o.push_back(L.vec(t.bterms));
-        o.push_back(L.vec(t.stile_ij));
-        o.push_back(L.vec(t.stile_ptr));
-        o.push_back(L.vec(t.stiles));
         o.push_back(L.vec(t.bus_idx));
         o.push_back(L.vec(t.bus_slot));
         o.push_back(L.vec(t.bus_adj_ptr));
@@ -301,7 +301,8 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     for (size_t i = 0; i < h.inst.size(); i++) {
         const ncl::Inst &I = h.inst[i];
         p.ioff[i] = {L.vec(I.kbb_pos), L.vec(I.border_pg), L.vec(I.gen_c2), L.vec(I.br_r), L.vec(I.br_x),
-                     L.vec(I.kbr_ptr), L.vec(I.kbr_ent)};
+                     L.vec(I.kbr_ptr), L.vec(I.kbr_ent), L.vec(I.mdesc_ptr), L.vec(I.mdesc), L.vec(I.mitems),
+                     L.vec(I.bperm)};
         bprim.insert(bprim.end(), I.border_primal.begin(), I.border_primal.end());
     }
     p.bprim = L.vec(bprim);
@@ -351,6 +352,8 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.asm_threads = h.asm_threads;
     a.asm_wthreads = h.asm_wthreads;
     a.gp_tot = h.gp_tot;
+    a.mw_tot = h.mw_tot;
+    a.pe_tot = h.pe_tot;
     a.tiles = h.tiles;
     a.zint = h.d.zint;
     a.sint = h.d.sint;
@@ -498,10 +501,17 @@ void kernel_model(Handle &h) {
         }
         const ncl::Inst &I = h.inst[t.inst];
         if (I.nbd) {
+            // border Schur products: the tile rows each item holds, over its
+            // columns and the template's blocks
+            int64_t el = 0;
+            for (const ncl::MItem &it : I.mitems) {
+                if (it.tmpl != int(&t - h.tmpl.data())) continue;
+                int cnt = 0;
+                for (int q = 0; q < ncl::kMT; q++) cnt += (it.ri[q] >= 0) + (it.rj[q] >= 0);
+                el += int64_t(it.w) * cnt;
+            }
+            B[NCL_K_BORDER_SCHUR] += nb * D * el;
             int64_t up = 0, uk = 0;
-            stamp++;
-            for (const ncl::Term &q : t.sterms) uniq_ul(q, up, uk);
-            B[NCL_K_BORDER_SCHUR] += nb * D * (I.npk() + up + uk);
             up = uk = 0;
             stamp++;
             for (const ncl::Term &q : t.bterms) {
@@ -523,6 +533,7 @@ void kernel_model(Handle &h) {
     if (h.nbd_tot) {
         L[NCL_K_BORDER_SCHUR] = L[NCL_K_BORDER_SUM] = L[NCL_K_BORDER_FACTOR] = 1;
         L[NCL_K_SOL_BPART] = L[NCL_K_SOL_BORDER] = 1;
+        B[NCL_K_BORDER_SCHUR] += D * h.sp_tot;     // the partial tiles written
         B[NCL_K_BORDER_SUM] = D * (h.sp_tot + h.nbb_tot + h.npk_tot);
         B[NCL_K_BORDER_FACTOR] = 0;
         const int lb = large_border(h);
@@ -550,7 +561,8 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
     switch (kind) {
         case NCL_K_ASSEMBLE: return a.asm_threads + a.gp_tot > 0;
         case NCL_K_VALUES: return a.kint + a.nbb_tot > 0;
-        case NCL_K_BORDER_SUM: return a.npk_tot > 0;
+        case NCL_K_BORDER_SUM: return a.pe_tot > 0;
+        case NCL_K_BORDER_SCHUR: return a.mw_tot > 0;
         case NCL_K_BORDER_PANEL:
         case NCL_K_BORDER_UPDATE: return a.max_nbd > ncl::kBorderRegMax;
         case NCL_K_BORDER_FACTOR:
@@ -860,28 +872,25 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.terms = reinterpret_cast<const ncl::Term *>(at(11));
         d.bterm_ptr = reinterpret_cast<const int32_t *>(at(12));
         d.bterms = reinterpret_cast<const ncl::Term *>(at(13));
-        d.stile_ij = reinterpret_cast<const int32_t *>(at(14));
-        d.stile_ptr = reinterpret_cast<const int32_t *>(at(15));
-        d.stiles = reinterpret_cast<const ncl::STile *>(at(16));
-        d.bus_idx = reinterpret_cast<const int32_t *>(at(17));
-        d.bus_slot = reinterpret_cast<const int32_t *>(at(18));
-        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(19));
-        d.bus_adj = reinterpret_cast<const int32_t *>(at(20));
-        d.br_slot = reinterpret_cast<const int32_t *>(at(21));
-        d.br_idx = reinterpret_cast<const int32_t *>(at(22));
-        d.gen_idx = reinterpret_cast<const int32_t *>(at(23));
-        d.gen_slot = reinterpret_cast<const int32_t *>(at(24));
-        d.perm = reinterpret_cast<const int32_t *>(at(25));
-        d.col_primal = reinterpret_cast<const uint8_t *>(at(26));
-        d.bus_gen = reinterpret_cast<const int32_t *>(at(27));
-        d.lkind = reinterpret_cast<const uint8_t *>(at(28));
-        d.iperm = reinterpret_cast<const int32_t *>(at(29));
-        d.rr_ptr = reinterpret_cast<const int32_t *>(at(30));
-        d.rr_ent = reinterpret_cast<const int32_t *>(at(31));
-        d.rb_ptr = reinterpret_cast<const int32_t *>(at(32));
-        d.rb_ent = reinterpret_cast<const int32_t *>(at(33));
-        d.sup_rnb = reinterpret_cast<const int32_t *>(at(34));
-        d.col_sup = reinterpret_cast<const int32_t *>(at(35));
+        d.bus_idx = reinterpret_cast<const int32_t *>(at(14));
+        d.bus_slot = reinterpret_cast<const int32_t *>(at(15));
+        d.bus_adj_ptr = reinterpret_cast<const int32_t *>(at(16));
+        d.bus_adj = reinterpret_cast<const int32_t *>(at(17));
+        d.br_slot = reinterpret_cast<const int32_t *>(at(18));
+        d.br_idx = reinterpret_cast<const int32_t *>(at(19));
+        d.gen_idx = reinterpret_cast<const int32_t *>(at(20));
+        d.gen_slot = reinterpret_cast<const int32_t *>(at(21));
+        d.perm = reinterpret_cast<const int32_t *>(at(22));
+        d.col_primal = reinterpret_cast<const uint8_t *>(at(23));
+        d.bus_gen = reinterpret_cast<const int32_t *>(at(24));
+        d.lkind = reinterpret_cast<const uint8_t *>(at(25));
+        d.iperm = reinterpret_cast<const int32_t *>(at(26));
+        d.rr_ptr = reinterpret_cast<const int32_t *>(at(27));
+        d.rr_ent = reinterpret_cast<const int32_t *>(at(28));
+        d.rb_ptr = reinterpret_cast<const int32_t *>(at(29));
+        d.rb_ent = reinterpret_cast<const int32_t *>(at(30));
+        d.sup_rnb = reinterpret_cast<const int32_t *>(at(31));
+        d.col_sup = reinterpret_cast<const int32_t *>(at(32));
         d.rwbase = h.t_rwbase[ti];
     }
     std::memcpy(buf.data() + p.tdev, tdev.data(), sizeof(ncl::TemplDev) * tdev.size());
@@ -917,6 +926,13 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.gen_c2 = reinterpret_cast<const double *>(base + p.ioff[i][2]);
         d.kbr_ptr = reinterpret_cast<const int32_t *>(base + p.ioff[i][5]);
         d.kbr_ent = reinterpret_cast<const int32_t *>(base + p.ioff[i][6]);
+        d.mdesc_ptr = reinterpret_cast<const int32_t *>(base + p.ioff[i][7]);
+        d.mdesc = reinterpret_cast<const ncl::MDesc *>(base + p.ioff[i][8]);
+        d.mitems = reinterpret_cast<const ncl::MItem *>(base + p.ioff[i][9]);
+        d.bperm = reinterpret_cast<const int32_t *>(base + p.ioff[i][10]);
+        d.mw0 = I.mw0;
+        d.pe0 = I.pe0;
+        d.npair = I.npair;
         d.t0 = I.t0;
         d.nt = I.nt;
     }
@@ -1024,12 +1040,7 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
         if (list(NCL_K_FAC_DIAG, h.w_b, S.b_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_FAC_ROWS, h.w_c, S.c_ptr, l) != hipSuccess) return NCL_ERR_HIP;
     }
-    if (h.nbd_tot) {
-        ncl::LaunchArgs la;
-        la.wl = W + h.w_schur;
-        la.nw = int(S.schur.size());
-        if (run(h, NCL_K_BORDER_SCHUR, a, la, st) != hipSuccess) return NCL_ERR_HIP;
-    }
+    if (h.nbd_tot && run(h, NCL_K_BORDER_SCHUR, a, ncl::LaunchArgs{}, st) != hipSuccess) return NCL_ERR_HIP;
     h.blocks_done = true;
     return NCL_OK;
 }

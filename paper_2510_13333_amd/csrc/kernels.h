@@ -19,6 +19,8 @@ struct DevArgs {
     int64_t nbd_tot, nbb_tot, npk_tot;
     int64_t asm_threads, gp_tot;   // residual threads of the templates, then of the border pg values
     int64_t asm_wthreads;          // assembly threads of the templates (wavefront-aligned), then border pg
+    int64_t mw_tot;                // border Schur wavefronts of all instances
+    int64_t pe_tot;                // border partial-sum threads (tile-pair entries) of all instances
     int64_t tiles;              // state transpose tiles of all templates
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
     double *upan;                  // U = L D on the off-diagonal panel rows (rows >= w), panel layout

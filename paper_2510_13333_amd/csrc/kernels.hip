@@ -809,67 +809,100 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
     });
 }
 
-// Border Schur contribution S_k[i, j] = sum over the supernodes s holding
-// border rows i and j of L_s[i,:] D_s L_s[j,:]^T.  One wavefront takes the
-// entries (i, j0 .. j0+7) of one tile: for every item (supernode) it loads
-// U_s[i, k] = L_s[i, k] d_k once and reuses it for each tile row the
-// supernode holds, so a product costs about one load instead of three.
-// Columns are taken 8, 4, 2, 1 at a time.  Written entry-major, block
-// fastest.
-template <int C>
-__device__ inline void schur_round(const double *__restrict__ Lb, const double *__restrict__ Ub, uint32_t nb,
-                                   uint32_t bl, const __attribute__((address_space(4))) STile *st, int k0,
-                                   double *acc) {
-    const uint32_t r = st->r, rs = r * nb;        // column stride of the panel, in elements
-    const uint32_t c0 = uint32_t(k0) * r;
-    double li[C];
-    const uint32_t oi = (st->pi + c0) * nb + bl;
+// Border Schur products on the matrix cores.  One wavefront per slice: a
+// run of one tile pair's items (supernodes of one template holding rows of
+// both border tiles I >= J) and one chunk of kMC blocks.  It sums
+//     P[m][n] += U[I_m, k] L[J_n, k]        (U = L D on the panel rows)
+// over the items' columns k and the chunk's blocks with v_mfma_f64_16x16x4:
+// A[m][q] (the q-th of four products) sits in lane m + 16 q, B[q][n] in lane
+// n + 16 q, and D[m][n] comes back in lane n + 16 (m % 4), register m / 4.
+// A full chunk puts four blocks of one column on the inner dimension (two
+// accumulators alternate over the column's four block quads); a chunk of
+// fewer blocks (the base case's single block, the last chunk of a template)
+// runs over (column, block) pairs in order, four at a time.  Rows an item
+// does not hold enter as zeros.  Each slice writes its own partial tile to
+// spart, and k_border_sum adds a pair's slices in order, so every entry has
+// one fixed order of additions.
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a) {
+    const int64_t wg = int64_t(blockIdx.x) * (kWG / 64) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (wg >= a.mw_tot) return;
+    const InstDev &I = a.insts[find_inst(a, wg, &InstDev::mw0)];
+    const int64_t wl = wg - I.mw0;
+    const auto *dsc = cs(I.mdesc) + wl;
+    const int ib = dsc->ib, ie = dsc->ie, chunk = dsc->chunk;
+    const int lane = lane_id(), m = lane & 15, qd = lane >> 4;
+    mfma_f64x4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    const auto *items = cs(I.mitems);
+    // the next item's tile rows are loaded while the current item runs
+    int ra_n = items[ib].ri[m], rb_n = items[ib].rj[m];
+    for (int it = ib; it < ie; it++) {
+        const TemplDev &T = a.tmpls[items[it].tmpl];
+        const int nb = T.nblk, b0 = kMC * chunk, csz = min(kMC, nb - b0);
+        const int ra = ra_n, rb = rb_n;
+        if (it + 1 < ie) {
+            ra_n = items[it + 1].ri[m];
+            rb_n = items[it + 1].rj[m];
+        }
+        const int r = items[it].r, w = items[it].w, poff = items[it].poff;
+        const double *__restrict__ Ub = a.upan + T.lbase;
+        const double *__restrict__ Lb = a.lpan + T.lbase;
+        const uint32_t nbu = uint32_t(nb), step = uint32_t(r) * nbu;
+        const uint32_t ba = uint32_t(poff + (ra < 0 ? 0 : ra)) * nbu + uint32_t(b0);
+        const uint32_t bb = uint32_t(poff + (rb < 0 ? 0 : rb)) * nbu + uint32_t(b0);
+        const bool va = ra >= 0, vb = rb >= 0;
+        if (csz == kMC) {
+            uint32_t oa = ba + uint32_t(qd), ob = bb + uint32_t(qd);
+            // two columns a round: 16 loads in flight before their 8 products
+            int k = 0;
+            for (; k + 2 <= w; k += 2, oa += 2 * step, ob += 2 * step) {
+                double av[8], bv[8];
 #pragma unroll
-    for (int u = 0; u < C; u++) li[u] = ld32(Ub, oi + u * rs);
-    const int mask = st->mask;
+                for (int g = 0; g < 8; g++) {
+                    const uint32_t o = (g < 4 ? 0u : step) + 4u * uint32_t(g & 3);
+                    av[g] = va ? ld32(Ub, oa + o) : 0.0;
+                    bv[g] = vb ? ld32(Lb, ob + o) : 0.0;
+                }
 #pragma unroll
-    for (int jj = 0; jj < kSchurTJ; jj++) {
-        if ((mask >> jj) & 1) {
-            const uint32_t oj = (st->pj[jj] + c0) * nb + bl;
-            double sj = 0.0;
+                for (int g = 0; g < 8; g += 2) {
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g], bv[g], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g + 1], bv[g + 1], acc1, 0, 0, 0);
+                }
+            }
+            if (k < w) {
+                double av[4], bv[4];
 #pragma unroll
-            for (int u = 0; u < C; u++) sj += li[u] * ld32(Lb, oj + u * rs);
-            acc[jj] += sj;
+                for (int g = 0; g < 4; g++) {
+                    av[g] = va ? ld32(Ub, oa + 4 * g) : 0.0;
+                    bv[g] = vb ? ld32(Lb, ob + 4 * g) : 0.0;
+                }
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bv[0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bv[1], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2], bv[2], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[3], bv[3], acc1, 0, 0, 0);
+            }
+        } else {
+            // (column, block) pair t = k * csz + bl; lane quad qd takes t = t0 + qd
+            const int tot = w * csz;
+            int k = qd / csz, bl = qd - k * csz;
+            for (int t0 = 0; t0 < tot; t0 += 4) {
+                const bool in = t0 + qd < tot;
+                const uint32_t o = uint32_t(k) * step + uint32_t(bl);
+                const double av = (in && va) ? ld32(Ub, ba + o) : 0.0;
+                const double bv = (in && vb) ? ld32(Lb, bb + o) : 0.0;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
+                bl += 4;
+                while (bl >= csz) {
+                    bl -= csz;
+                    k++;
+                }
+            }
         }
     }
-}
-
-__global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a, const Work *__restrict__ wl, int nw) {
-    const int wid = wave_id();
-    if (wid >= nw) return;
-    const Lane W = lane_work(a, wl, wid);
-    const TemplDev &T = *W.T;
-    const int64_t nb = W.nb;
-    const int q = W.k;
-    const int i = cs(T.stile_ij)[2 * q], j0 = cs(T.stile_ij)[2 * q + 1];
-    const double *__restrict__ Lb = a.lpan + T.lbase;
-    const double *__restrict__ Ub = a.upan + T.lbase;
-    const uint32_t nbu = uint32_t(nb), blu = uint32_t(W.bl);
-    double acc[kSchurTJ];
+    double *out = a.spart + I.sp0 + wl * (kMT * kMT);
 #pragma unroll
-    for (int jj = 0; jj < kSchurTJ; jj++) acc[jj] = 0.0;
-    const int it1 = cs(T.stile_ptr)[q + 1];
-    for (int it = cs(T.stile_ptr)[q]; it < it1; it++) {
-        const auto *st = cs(T.stiles) + it;
-        const int w = st->w;
-        int k0 = 0;
-        for (; k0 + 8 <= w; k0 += 8) schur_round<8>(Lb, Ub, nbu, blu, st, k0, acc);
-        if (k0 + 4 <= w) { schur_round<4>(Lb, Ub, nbu, blu, st, k0, acc); k0 += 4; }
-        if (k0 + 2 <= w) { schur_round<2>(Lb, Ub, nbu, blu, st, k0, acc); k0 += 2; }
-        if (k0 < w) schur_round<1>(Lb, Ub, nbu, blu, st, k0, acc);
-    }
-    if (!W.on) return;
-    const InstDev &I = a.insts[T.inst];
-    const int64_t blk = T.blocks[W.bl] - I.blk0;
-    const int64_t ei = int64_t(i) * (i + 1) / 2;
-#pragma unroll
-    for (int jj = 0; jj < kSchurTJ; jj++)
-        if (j0 + jj <= i) a.spart[I.sp0 + (ei + j0 + jj) * I.nblk + blk] = acc[jj];
+    for (int q = 0; q < 4; q++) out[(4 * q + qd) * kMT + m] = acc0[q] + acc1[q];
 }
 
 // ------------------------------------------------------------------ border
@@ -887,25 +920,40 @@ __device__ inline int pk(int i, int j) { return i * (i + 1) / 2 + j; }
 constexpr int kBB = 32;          // column block of the dense border factor and solves
 constexpr int kPS = kBB + 1;     // LDS row stride of a staged block column
 
-// S[e] = K_bb[e] - sum_k S_k[e]: one wavefront per packed entry of every
-// instance's border, blocks summed in a fixed order (lane-strided partial
-// sums, then a fixed shuffle tree).
-__global__ __launch_bounds__(kWG) void k_border_sum(DevArgs a) {
-    const int64_t eg = wave_id();
-    if (eg >= a.npk_tot) return;
-    const InstDev &I = a.insts[find_inst(a, eg, &InstDev::npk0)];
-    const int64_t e = eg - I.npk0;
-    const int lane = lane_id();
-    const double *sp = a.spart + I.sp0 + e * I.nblk;
+// S = K_bb - (the partial tiles of each tile pair summed in slice order):
+// one thread per entry of every tile pair (neighbouring threads read
+// neighbouring entries of each partial tile, up to 16 in flight).  Tile
+// position q holds border row bperm[q]; an entry goes to the packed lower
+// triangle at (max, min) of its two border rows, each unordered pair once
+// (on a diagonal tile pair, the entries with m >= n).
+__global__ __launch_bounds__(256) void k_border_sum(DevArgs a) {
+    const int64_t tg = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (tg >= a.pe_tot) return;
+    const InstDev &I = a.insts[find_inst(a, tg, &InstDev::pe0)];
+    const int64_t u = tg - I.pe0;
+    const int pq = int(u / (kMT * kMT)), e = int(u % (kMT * kMT));
+    int ti = int((sqrt(8.0 * double(pq) + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > pq) ti--;
+    while ((ti + 1) * (ti + 2) / 2 <= pq) ti++;
+    const int tj = pq - ti * (ti + 1) / 2;
+    const int qi = ti * kMT + e / kMT, qj = tj * kMT + e % kMT;
+    if (qi >= I.nbd || qj >= I.nbd || (ti == tj && qj > qi)) return;
+    const double *src = a.spart + I.sp0 + e;
     double s = 0.0;
-    for (int b = lane; b < I.nblk; b += 64) s += sp[b];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) {
-        int i, j;
-        unpack(e, i, j);
-        const int32_t p = I.kbb_pos[size_t(i) * I.nbd + j];
-        a.sbb[I.sbb0 + e] = (p >= 0 ? a.kval[a.kint + I.kbb0 + p] : 0.0) - s;
+    const int d1 = I.mdesc_ptr[pq + 1];
+    int d = I.mdesc_ptr[pq];
+    for (; d + 16 <= d1; d += 16) {
+        double x[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) x[q] = src[int64_t(d + q) * (kMT * kMT)];
+#pragma unroll
+        for (int q = 0; q < 16; q++) s += x[q];
     }
+    for (; d < d1; d++) s += src[int64_t(d) * (kMT * kMT)];
+    const int bi = I.bperm[qi], bj = I.bperm[qj];
+    const int i = max(bi, bj), j = min(bi, bj);
+    const int32_t p = I.kbb_pos[size_t(i) * I.nbd + j];
+    a.sbb[I.sbb0 + int64_t(i) * (i + 1) / 2 + j] = (p >= 0 ? a.kval[a.kint + I.kbb0 + p] : 0.0) - s;
 }
 
 // Dense LDL^T of the packed border matrix S (lower triangle packed by rows),
@@ -2729,10 +2777,12 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (l.nw) hipLaunchKernelGGL(k_fac_rows, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
             break;
         case NCL_K_BORDER_SCHUR:
-            if (l.nw) hipLaunchKernelGGL(k_border_schur, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
+            if (a.mw_tot)
+                hipLaunchKernelGGL(k_border_schur, dim3(unsigned((a.mw_tot + kWG / 64 - 1) / (kWG / 64))), dim3(kWG), 0,
+                                   st, a);
             break;
         case NCL_K_BORDER_SUM:
-            if (a.npk_tot) hipLaunchKernelGGL(k_border_sum, dim3(waves_grid(int(a.npk_tot))), dim3(kWG), 0, st, a);
+            if (a.pe_tot) hipLaunchKernelGGL(k_border_sum, dim3(unsigned((a.pe_tot + 255) / 256)), dim3(256), 0, st, a);
             break;
         case NCL_K_BORDER_FACTOR:
             if (a.max_nbd) {

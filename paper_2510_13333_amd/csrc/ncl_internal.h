@@ -41,20 +41,30 @@ struct CItem {
     int32_t meta;    // ld (16 bits) | wd << 16
 };
 
-// Border Schur tiles: one wavefront computes the entries (i, j0 .. j0+7) of
-// the packed border matrix for its blocks.  Each item is one supernode s on
-// the path of border row i and of at least one row of the tile: row i's
-// panel element, the panel's leading dimension and width, s's first column,
-// the tile rows s holds (bit jj for row j0 + jj) and their panel elements.
-constexpr int kSchurTJ = 8;
+// Border Schur products on the matrix cores: the border matrix is cut into
+// tiles of kMT rows; for a pair of tiles (I >= J) the products U[i, k] L[j, k]
+// over every supernode holding rows of both tiles, its columns k and the
+// blocks are summed with FP64 MFMA (16 x 16 outputs, 4 products a lane
+// group per instruction).  An item is one supernode of one template: its
+// panel (first element, rows, columns) and the panel row of each tile row
+// it holds (-1 where it holds none).  A wavefront takes a slice of one
+// pair's items (of one template) for one chunk of kMC blocks, about
+// kMSlice instructions, and writes its own partial tile.
+constexpr int kMT = 16;
+constexpr int kMC = 16;
+constexpr int kMSlice = 128;
+constexpr int kMItemCost = 16;     // slicing cost of an item beyond its instructions (its dependent loads)
+struct MItem {
+    int32_t tmpl, poff, r, w;
+    int16_t ri[kMT], rj[kMT];
+};
+struct MDesc {
+    int32_t pair, chunk, ib, ie;   // tile pair, block chunk, item range
+};
 // transposes between layout order and the interleaved order move tiles of
 // kTileJ columns x kTileB blocks
 constexpr int kTileJ = 16;
 constexpr int kTileB = 64;
-struct STile {
-    int32_t pi, r, w, dcol, mask, pad[3];
-    int32_t pj[kSchurTJ];
-};
 
 // One product of an update sum: L[a] * d[k] * L[c] (factor, border Schur) or
 // L[a] * y[k] (solves), with a, c panel elements and k a column, all
@@ -128,10 +138,6 @@ struct TemplDev {
     // its border rows the rest
     const int32_t *sup_rnb;        // [nsup]
     const int32_t *col_sup;        // [n] supernode of each column
-    // border Schur tiles: (i, j0) and item range of each tile
-    const int32_t *stile_ij;       // [ntiles][2]
-    const int32_t *stile_ptr;      // [ntiles + 1]
-    const STile *stiles;
     // assembly
     const int32_t *bus_idx;        // [nb][BI_N]
     const int32_t *bus_slot;       // [nb][BS_N]
@@ -169,7 +175,14 @@ struct InstDev {
     int64_t kbb0;                  // K_bb values at kval[kint + kbb0 ...]
     int64_t sbb0;                  // packed border matrix / factor at sbb[sbb0 ...]
     int64_t bd0;                   // border pivots at dval[dint + bd0 ...]
-    int64_t sp0;                   // border Schur partials at spart[sp0 + e * nblk + block]
+    int64_t sp0;                   // border Schur partial tiles at spart[sp0 + slice * kMT * kMT]
+    int64_t mw0;                   // first border Schur wavefront (one per slice)
+    int64_t pe0;                   // first thread of the partial-tile sum (one per tile-pair entry)
+    int32_t npair, pad_m;
+    const int32_t *mdesc_ptr;      // [npair + 1] slices of each tile pair
+    const int32_t *bperm;          // [nbd] border row at each tile position
+    const MDesc *mdesc;            // the slices, pair-major
+    const MItem *mitems;
     int64_t cp0;                   // border right-hand-side partials at cpart[cp0 + b * nblk + block]
     int64_t npk0;                  // first packed border entry (all instances together)
     int64_t gp0;                   // first border-pg assembly thread
@@ -217,12 +230,12 @@ struct Template {
     // schedule
     int nlev = 0;
     std::vector<int32_t> level;         // [nsup]
-    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr, sterm_ptr,
-        stile_ij, stile_ptr;
+    std::vector<int32_t> panel_off, task_s, task_p, task_cbase, ent_kpos, ent_out, ent_tptr;
     std::vector<int32_t> bterm_ptr, sup_rnb, col_sup;   // solves: border terms, block rows per panel, column -> supernode
-    std::vector<STile> stiles;
     std::vector<std::vector<int32_t>> lev_tasks;   // row tasks of each level
-    std::vector<Term> terms, bterms, sterms;
+    std::vector<Term> terms, bterms;
+    // border rows held by each supernode: (border row, panel row), ascending
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> brow;
     // residual rows: the full symmetric row j of the block (both triangles),
     // as (K value, column) pairs; columns n + b are border columns; and per
     // border row b the block's entries (K value, block column) of that row
@@ -284,6 +297,14 @@ struct Inst {
     std::vector<int32_t> kbr_ptr, kbr_ent;
     // offsets in the concatenated device border arrays
     int64_t kbb0 = 0, sbb0 = 0, bd0 = 0, sp0 = 0, cp0 = 0, npk0 = 0, gp0 = 0;
+    // border Schur items of every tile pair (all templates, in order) and
+    // the wavefront slices over them
+    std::vector<MItem> mitems;
+    std::vector<int32_t> mdesc_ptr;
+    std::vector<int32_t> bperm;          // tile position -> border row
+    std::vector<MDesc> mdesc;
+    int32_t npair = 0;
+    int64_t mw0 = 0, pe0 = 0;
     int64_t nbb() const { return nbd ? bcolptr[nbd] : 0; }
     int64_t npk() const { return int64_t(nbd) * (nbd + 1) / 2; }
 };
@@ -299,7 +320,7 @@ struct Handle {
     std::vector<int64_t> kbase;          // [nblk] first public CSC value of each block
     int64_t nnzK = 0;
     // totals over instances
-    int64_t nbd_tot = 0, nbb_tot = 0, npk_tot = 0, sp_tot = 0, cp_tot = 0, gp_tot = 0;
+    int64_t nbd_tot = 0, nbb_tot = 0, npk_tot = 0, sp_tot = 0, cp_tot = 0, gp_tot = 0, mw_tot = 0, pe_tot = 0;
     int max_nbd = 0;
     // sizes
     int64_t nnzL = 0, nsuper = 0, npanel = 0;
@@ -337,7 +358,7 @@ struct Handle {
         const int64_t *pg_col = nullptr, *row_pq = nullptr;   // dispatch-map tables
     } d;
     // offsets of each work list inside d.work
-    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_sn = 0, w_sb = 0, w_bpart = 0, w_schur = 0;
+    size_t w_a = 0, w_b = 0, w_c = 0, w_f = 0, w_d = 0, w_sn = 0, w_sb = 0, w_bpart = 0;
     // per kernel kind: launches and algorithmic bytes of one step
     std::vector<int64_t> km_launch, km_bytes;
     // event profiling of one kernel kind (events are hipEvent_t, in pairs)

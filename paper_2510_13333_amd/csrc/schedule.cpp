@@ -206,57 +206,11 @@ int build_template_schedule(Template &t, int nbd) {
         if (rnb < t.sup[s + 1] - t.sup[s]) return NCL_ERR_ARG;
         t.sup_rnb[s] = rnb;
     }
-    // border Schur terms: the common panels of each pair of border rows
-    const int64_t npk = int64_t(nbd) * (nbd + 1) / 2;
-    t.sterm_ptr.assign(npk + 1, 0);
-    t.sterms.clear();
-    int64_t e = 0;
-    for (int i = 0; i < nbd; i++)
-        for (int j = 0; j <= i; j++, e++) {
-            size_t a = 0, b = 0;
-            while (a < bp[i].size() && b < bp[j].size()) {
-                if (bp[i][a].first == bp[j][b].first) {
-                    push_cols(t.sterms, bp[i][a].first, bp[i][a].second, bp[j][b].second);
-                    a++;
-                    b++;
-                } else if (bp[i][a].first < bp[j][b].first) a++;
-                else b++;
-            }
-            if (int64_t(t.sterms.size()) > kTermMax) return NCL_ERR_ARG;
-            t.sterm_ptr[e + 1] = int32_t(t.sterms.size());
-        }
-    // border Schur tiles: rows i, columns j0 .. j0+7 (j <= i); items are the
-    // supernodes on row i's path that also hold a row of the tile, in
-    // ascending order
-    t.stile_ij.clear();
-    t.stile_ptr.assign(1, 0);
-    t.stiles.clear();
-    for (int i = 0; i < nbd; i++)
-        for (int j0 = 0; j0 <= i; j0 += kSchurTJ) {
-            t.stile_ij.push_back(i);
-            t.stile_ij.push_back(j0);
-            for (auto &x : bp[i]) {
-                const int s = x.first;
-                STile it{};
-                it.pi = t.panel_off[s] + x.second;
-                it.r = t.srp[s + 1] - t.srp[s];
-                it.w = t.sup[s + 1] - t.sup[s];
-                it.dcol = t.sup[s];
-                for (int jj = 0; jj < kSchurTJ; jj++) {
-                    const int j = j0 + jj;
-                    it.pj[jj] = it.pi;                     // a valid element when the row is absent
-                    if (j > i) continue;
-                    for (auto &y : bp[j])
-                        if (y.first == s) {
-                            it.mask |= 1 << jj;
-                            it.pj[jj] = t.panel_off[s] + y.second;
-                        }
-                }
-                if (it.mask) t.stiles.push_back(it);
-            }
-            if (t.stiles.size() > size_t(INT32_MAX)) return NCL_ERR_ARG;
-            t.stile_ptr.push_back(int32_t(t.stiles.size()));
-        }
+    // border rows of each supernode (the border Schur items are built per
+    // instance, over a permutation of the border shared by its templates)
+    t.brow.assign(ns, {});
+    for (int b = 0; b < nbd; b++)
+        for (auto &x : bp[b]) t.brow[x.first].push_back({b, x.second});
     return NCL_OK;
 }
 
@@ -412,10 +366,100 @@ int build_schedule(Handle &h) {
         const Template &t = h.tmpl[ti];
         const int nbd = h.inst[t.inst].nbd;
         const int ng64 = groups(t, 64);
-        const int ntile = int(t.stile_ptr.size()) - 1;
-        for (int g = 0; g < ng64; g++) {
+        for (int g = 0; g < ng64; g++)
             for (int b = 0; b < nbd; b++) S.bpart.push_back(Work{tg(ti, g), b});
-            for (int q = 0; q < ntile; q++) S.schur.push_back(Work{tg(ti, g), q});
+    }
+    // border Schur items of each instance.  The border rows are placed in
+    // tiles of kMT in the order of the first supernode (elimination order)
+    // of the instance's largest template that holds them, so that the rows
+    // of a supernode share few tiles; then per pair of tiles (I >= J), one
+    // item per supernode (every template in order) holding rows of both.
+    // The wavefront slices: per pair, per chunk of kMC blocks, the items of
+    // the templates with blocks in the chunk cut (never across a template)
+    // into runs of about kMSlice instructions, an item counting kMItemCost
+    // more for its dependent loads.
+    for (Inst &I : h.inst) {
+        I.mitems.clear();
+        I.mdesc.clear();
+        I.mdesc_ptr.assign(1, 0);
+        const int nbd = I.nbd;
+        int tbig = I.t0, maxnb = 0;
+        for (int ti = I.t0; ti < I.t0 + I.nt; ti++)
+            if (int(h.tmpl[ti].blocks.size()) > maxnb) {
+                maxnb = int(h.tmpl[ti].blocks.size());
+                tbig = ti;
+            }
+        std::vector<int32_t> first(nbd, INT32_MAX);
+        if (nbd) {
+            const Template &t = h.tmpl[tbig];
+            for (size_t s = 0; s < t.brow.size(); s++)
+                for (auto &y : t.brow[s]) first[y.first] = std::min(first[y.first], int32_t(s));
+        }
+        I.bperm.resize(nbd);
+        for (int b = 0; b < nbd; b++) I.bperm[b] = b;
+        std::stable_sort(I.bperm.begin(), I.bperm.end(), [&](int32_t x, int32_t y) { return first[x] < first[y]; });
+        std::vector<int32_t> tpos(nbd);
+        for (int q = 0; q < nbd; q++) tpos[I.bperm[q]] = q;
+        const int nmt = (nbd + kMT - 1) / kMT;
+        I.npair = nmt * (nmt + 1) / 2;
+        std::vector<std::vector<MItem>> pairs(size_t(I.npair) * I.nt);   // [pair][template]
+        for (int q = 0; q < I.nt; q++) {
+            const Template &t = h.tmpl[I.t0 + q];
+            for (size_t s = 0; s < t.brow.size(); s++) {
+                if (t.brow[s].empty()) continue;
+                std::vector<int> tiles;
+                for (auto &y : t.brow[s]) tiles.push_back(tpos[y.first] / kMT);
+                std::sort(tiles.begin(), tiles.end());
+                tiles.erase(std::unique(tiles.begin(), tiles.end()), tiles.end());
+                const int r = t.srp[s + 1] - t.srp[s], w = t.sup[s + 1] - t.sup[s];
+                if (r > INT16_MAX) return NCL_ERR_ARG;
+                for (int TI : tiles)
+                    for (int TJ : tiles) {
+                        if (TJ > TI) break;
+                        MItem it{};
+                        it.tmpl = I.t0 + q;
+                        it.poff = t.panel_off[s];
+                        it.r = r;
+                        it.w = w;
+                        for (int u = 0; u < kMT; u++) it.ri[u] = it.rj[u] = -1;
+                        for (auto &y : t.brow[s]) {
+                            const int tp = tpos[y.first];
+                            if (tp / kMT == TI) it.ri[tp % kMT] = int16_t(y.second);
+                            if (tp / kMT == TJ) it.rj[tp % kMT] = int16_t(y.second);
+                        }
+                        pairs[(size_t(TI) * (TI + 1) / 2 + TJ) * I.nt + q].push_back(it);
+                    }
+            }
+        }
+        const int nch = (maxnb + kMC - 1) / kMC;
+        for (int pq = 0; pq < I.npair; pq++) {
+            std::vector<std::pair<int32_t, int32_t>> trange;      // per template: item range
+            for (int q = 0; q < I.nt; q++) {
+                const int32_t ib = int32_t(I.mitems.size());
+                const auto &v = pairs[size_t(pq) * I.nt + q];
+                I.mitems.insert(I.mitems.end(), v.begin(), v.end());
+                trange.push_back({ib, int32_t(I.mitems.size())});
+            }
+            if (I.mitems.size() > size_t(INT32_MAX)) return NCL_ERR_ARG;
+            for (int c = 0; c < nch; c++)
+                for (int q = 0; q < I.nt; q++) {
+                    const int nb = int(h.tmpl[I.t0 + q].blocks.size()), cs = std::min(kMC, nb - kMC * c);
+                    if (cs <= 0) continue;
+                    int32_t ib = trange[q].first;
+                    int64_t cost = 0;
+                    for (int32_t it = trange[q].first; it < trange[q].second; it++) {
+                        const int64_t ci = (int64_t(I.mitems[it].w) * cs + 3) / 4 + kMItemCost;
+                        if (it > ib && cost + ci > kMSlice) {
+                            I.mdesc.push_back(MDesc{pq, c, ib, it});
+                            ib = it;
+                            cost = 0;
+                        }
+                        cost += ci;
+                    }
+                    if (ib < trange[q].second) I.mdesc.push_back(MDesc{pq, c, ib, trange[q].second});
+                }
+            if (I.mdesc.size() > size_t(INT32_MAX)) return NCL_ERR_ARG;
+            I.mdesc_ptr.push_back(int32_t(I.mdesc.size()));
         }
     }
     return NCL_OK;
