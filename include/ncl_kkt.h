@@ -558,9 +558,9 @@ enum {
     NCL_K_FAC_GATHER,       /* k_fac_gather: panel entries minus descendant updates, one launch per level */
     NCL_K_FAC_DIAG,         /* k_fac_diag: LDL^T of diagonal blocks, and the pivots of width-1 supernodes, per level */
     NCL_K_FAC_ROWS,         /* k_fac_rows: off-diagonal rows of supernodes 2 or more wide, per level */
-    NCL_K_BORDER_SCHUR,     /* k_border_schur: per-block border Schur contributions */
-    NCL_K_BORDER_SUM,       /* k_border_sum: fixed-order sum into the border matrix */
-    NCL_K_BORDER_FACTOR,    /* k_border_factor: dense border LDL^T */
+    NCL_K_BORDER_SCHUR,     /* k_border_schur: border Schur products on FP64 MFMA, partial tiles */
+    NCL_K_BORDER_SUM,       /* k_border_sum: fixed-order sum of the partial tiles into the border matrix */
+    NCL_K_BORDER_FACTOR,    /* k_border_factor (borders up to 216 rows, in registers) and k_border_step (larger, one launch per 32-column block): dense border LDL^T */
     NCL_K_STATUS_INIT,      /* k_status_init */
     NCL_K_STATUS,           /* k_status: pivot signs and magnitudes */
     NCL_K_SOL_LOAD,         /* k_sol_load */
@@ -574,8 +574,6 @@ enum {
     NCL_K_RESIDUAL,         /* k_residual (dispatch map; not part of a step) */
     NCL_K_MAX_STEP,         /* k_max_step (dispatch map; not part of a step) */
     NCL_K_INTERLEAVE,       /* k_interleave: the state transposed to the blocks' interleaved order (assembly) */
-    NCL_K_BORDER_PANEL,     /* k_border_panel: borders over 216 rows, diagonal block and rows of one column block */
-    NCL_K_BORDER_UPDATE,    /* k_border_update: borders over 216 rows, trailing update by one column block */
     NCL_K_BERR_ROWS,        /* k_berr_rows: residual of the block rows (backward error, refinement) */
     NCL_K_BERR_BORDER,      /* k_berr_border: residual of the border rows */
     NCL_K_BERR_FINAL,       /* k_berr_final: eta and omega from the partial maxima */

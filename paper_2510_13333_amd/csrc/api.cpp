@@ -183,7 +183,7 @@ struct Plan {
     std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
     std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
     size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, pg_col = 0, row_pq = 0, tables_end = 0;
-    size_t kval = 0, lpan = 0, upan = 0, dval = 0, spart = 0, sbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
+    size_t kval = 0, lpan = 0, upan = 0, dval = 0, spart = 0, sbb = 0, lbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
            xint = 0, bint = 0, rint = 0, rbuf = 0, epart = 0, total = 0;
 };
 
@@ -320,6 +320,7 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     p.dval = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
     p.spart = L.take(nullptr, sizeof(double) * size_t(h.sp_tot));
     p.sbb = L.take(nullptr, sizeof(double) * size_t(h.npk_tot));
+    p.lbb = L.take(nullptr, sizeof(double) * size_t(h.npk_tot));
     p.ybuf = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot) * size_t(nrhs));
     p.cpart = L.take(nullptr, sizeof(double) * size_t(nrhs) * size_t(h.cp_tot));
     p.zint = L.take(nullptr, sizeof(double) * size_t(h.dint + h.nbd_tot));
@@ -363,6 +364,7 @@ ncl::DevArgs dev_args(const Handle &h) {
     a.dval = h.d.dval;
     a.spart = h.d.spart;
     a.sbb = h.d.sbb;
+    a.lbb = h.d.lbb;
     a.ybuf = h.d.ybuf;
     a.cpart = h.d.cpart;
     a.stat = h.d.stat;
@@ -383,15 +385,17 @@ ncl::DevArgs dev_args(const Handle &h) {
 }
 
 // The largest border of an instance too large for the register factor (0: none).
-int large_border(const Handle &h) {
+
+// Launches and algorithmic bytes per step of every kernel kind: each
+// distinct element a launch reads or writes counts once per launch.
+// The largest border over kBorderRegMax rows (0 if none): the blocked path.
+int big_border(const Handle &h) {
     int m = 0;
     for (const ncl::Inst &I : h.inst)
         if (I.nbd > ncl::kBorderRegMax && I.nbd > m) m = I.nbd;
     return m;
 }
 
-// Launches and algorithmic bytes per step of every kernel kind: each
-// distinct element a launch reads or writes counts once per launch.
 void kernel_model(Handle &h) {
     constexpr int64_t D = sizeof(double);
     h.km_launch.assign(NCL_K_COUNT, 0);
@@ -531,23 +535,27 @@ void kernel_model(Handle &h) {
     L[NCL_K_SOL_LOAD] = L[NCL_K_SOL_STORE] = 1;
     B[NCL_K_SOL_LOAD] = B[NCL_K_SOL_STORE] = D * 2 * h.dint;
     if (h.nbd_tot) {
-        L[NCL_K_BORDER_SCHUR] = L[NCL_K_BORDER_SUM] = L[NCL_K_BORDER_FACTOR] = 1;
+        L[NCL_K_BORDER_SCHUR] = L[NCL_K_BORDER_SUM] = 1;
         L[NCL_K_SOL_BPART] = L[NCL_K_SOL_BORDER] = 1;
         B[NCL_K_BORDER_SCHUR] += D * h.sp_tot;     // the partial tiles written
         B[NCL_K_BORDER_SUM] = D * (h.sp_tot + h.nbb_tot + h.npk_tot);
+        const int bb = big_border(h);
+        L[NCL_K_BORDER_FACTOR] = 1 + (bb + ncl::kBorderBlock - 1) / ncl::kBorderBlock;
         B[NCL_K_BORDER_FACTOR] = 0;
-        const int lb = large_border(h);
-        if (lb) L[NCL_K_BORDER_PANEL] = L[NCL_K_BORDER_UPDATE] = (lb + ncl::kBorderBlock - 1) / ncl::kBorderBlock;
         for (const ncl::Inst &I : h.inst) {
             const int64_t n = I.nbd;
             if (n <= ncl::kBorderRegMax) {
-                B[NCL_K_BORDER_FACTOR] += D * (n * (n + 1) + n);     // the packed matrix read and written, pivots
+                B[NCL_K_BORDER_FACTOR] += D * (n * (n + 1) + n);     // the packed matrix read, L written, pivots
                 continue;
             }
-            for (int64_t b0 = 0; b0 < n; b0 += ncl::kBorderBlock) {
-                const int64_t bs = std::min<int64_t>(ncl::kBorderBlock, n - b0), m = n - b0 - bs;
-                B[NCL_K_BORDER_PANEL] += D * (bs * (bs + 1) + 2 * m * bs + bs);
-                B[NCL_K_BORDER_UPDATE] += D * (m * (m + 1) + m * bs + bs);
+            // blocked: per column block (bs x bs tiles) every trailing tile
+            // reads the block's factor and the block column rows of its two
+            // tile rows (one on the diagonal), reads and writes itself; the
+            // diagonal tiles write L; the diagonal blocks and pivots once
+            const int64_t bs = ncl::kBorderBlock, nb = (n + bs - 1) / bs, t2 = bs * bs;
+            for (int64_t b = 0; b < nb; b++) {
+                const int64_t rem = nb - b - 1, tiles = rem * (rem + 1) / 2;
+                B[NCL_K_BORDER_FACTOR] += D * (t2 * tiles + t2 * (2 * tiles - rem) + 2 * t2 * tiles + t2 * rem + t2 + bs);
             }
         }
         B[NCL_K_SOL_BORDER] = D * (h.cp_tot + h.npk_tot + 4 * h.nbd_tot);
@@ -563,8 +571,6 @@ bool nonempty(int kind, const ncl::DevArgs &a, const ncl::LaunchArgs &l) {
         case NCL_K_VALUES: return a.kint + a.nbb_tot > 0;
         case NCL_K_BORDER_SUM: return a.pe_tot > 0;
         case NCL_K_BORDER_SCHUR: return a.mw_tot > 0;
-        case NCL_K_BORDER_PANEL:
-        case NCL_K_BORDER_UPDATE: return a.max_nbd > ncl::kBorderRegMax;
         case NCL_K_BORDER_FACTOR:
         case NCL_K_SOL_BORDER: return a.max_nbd > 0;
         case NCL_K_STATUS_INIT:
@@ -953,6 +959,7 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
     h.d.dval = reinterpret_cast<double *>(base + p.dval);
     h.d.spart = reinterpret_cast<double *>(base + p.spart);
     h.d.sbb = reinterpret_cast<double *>(base + p.sbb);
+    h.d.lbb = reinterpret_cast<double *>(base + p.lbb);
     h.d.ybuf = reinterpret_cast<double *>(base + p.ybuf);
     h.d.cpart = reinterpret_cast<double *>(base + p.cpart);
     h.d.zint = reinterpret_cast<double *>(base + p.zint);
@@ -1052,14 +1059,20 @@ int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const ncl::DevArgs a = dev_args(h);
     const ncl::LaunchArgs none;
-    for (int kind : {NCL_K_BORDER_SUM, NCL_K_BORDER_FACTOR})
-        if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
-    // borders too large for the register factor: column blocks in turn
-    for (int b0 = 0; b0 < large_border(h); b0 += ncl::kBorderBlock) {
+    if (run(h, NCL_K_BORDER_SUM, a, none, st) != hipSuccess) return NCL_ERR_HIP;
+    // the dense border factor: the register path for borders of up to
+    // kBorderRegMax rows, then one launch per column block of the largest
+    // larger border
+    {
         ncl::LaunchArgs l;
-        l.b0 = b0;
-        if (run(h, NCL_K_BORDER_PANEL, a, l, st) != hipSuccess) return NCL_ERR_HIP;
-        if (run(h, NCL_K_BORDER_UPDATE, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+        l.b0 = -2;
+        if (run(h, NCL_K_BORDER_FACTOR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    const int nbk = (big_border(h) + ncl::kBorderBlock - 1) / ncl::kBorderBlock;
+    for (int b = -1; b < nbk - 1; b++) {
+        ncl::LaunchArgs l;
+        l.b0 = b;
+        if (run(h, NCL_K_BORDER_FACTOR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
     }
     for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
         if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
@@ -1114,7 +1127,7 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
         return NCL_ERR_HIP;
     if (!dv.empty() && hipMemcpy(dv.data(), h.d.dval, sizeof(double) * dv.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
-    if (!sbb.empty() && hipMemcpy(sbb.data(), h.d.sbb, sizeof(double) * sbb.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    if (!sbb.empty() && hipMemcpy(sbb.data(), h.d.lbb, sizeof(double) * sbb.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return NCL_ERR_HIP;
     int64_t q = 0;
     for (const ncl::Inst &I : h.inst) {
@@ -1616,7 +1629,7 @@ const char *ncl_kernel_name(int kind) {
         "k_assemble", "k_values", "k_fac_gather", "k_fac_diag", "k_fac_rows", "k_border_schur", "k_border_sum",
         "k_border_factor", "k_status_init", "k_status", "k_sol_load", "k_sol_fwd_gather", "k_sol_fwd_diag",
         "k_sol_bpart", "k_sol_border", "k_sol_bwd_border", "k_sol_bwd", "k_sol_store",
-        "k_residual", "k_max_step", "k_interleave", "k_border_panel", "k_border_update", "k_berr_rows",
+        "k_residual", "k_max_step", "k_interleave", "k_berr_rows",
         "k_berr_border", "k_berr_final"};
     return kind >= 0 && kind < NCL_K_COUNT ? names[kind] : nullptr;
 }

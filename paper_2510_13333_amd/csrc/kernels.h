@@ -23,6 +23,7 @@ struct DevArgs {
     int64_t pe_tot;                // border partial-sum threads (tile-pair entries) of all instances
     int64_t tiles;              // state transpose tiles of all templates
     double *kval, *lpan, *dval, *spart, *sbb, *ybuf, *cpart;
+    double *lbb;                   // the border factor L (packed like sbb)
     double *upan;                  // U = L D on the off-diagonal panel rows (rows >= w), panel layout
     double *zint, *sint;        // interleaved copies of the state and Sigma (assembly input)
     int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits, non-finite
@@ -40,20 +41,21 @@ struct DevArgs {
 };
 
 // Arguments of one launch (only those the kernel kind uses are read).
-// Dense border factor: borders of up to kBorderRegMax rows are factored in
-// registers by one workgroup; larger ones by column blocks of kBorderBlock,
-// a panel launch and a trailing-update launch per block.
+// Dense border factor: borders of up to kBorderRegMax rows in registers by
+// one workgroup (b0 = -2); larger ones right-looking by column blocks of
+// kBorderBlock, one launch per block (b0 = block index, -1 for the first
+// diagonal block).
 constexpr int kBorderBlock = 32;
+constexpr int kBorderRegMax = 216;
 // status words: 6 counters, each on a cache line of its own so that the
 // workgroups' atomics on different counters do not queue on one line
 constexpr int kStatStride = 16;
 constexpr int kStatWords = 8;
-constexpr int kBorderRegMax = 216;
 
 struct LaunchArgs {
     const Work *wl = nullptr;   // work list and its length
     int nw = 0;
-    int b0 = 0;                 // border column block (panel and update launches)
+    int b0 = 0;                 // border column block of a border factor launch (-1: the first diagonal block)
     const double *z = nullptr, *sig = nullptr;   // assembly state
     double rho = 0.0;
     uint32_t flags = 0;                          // NCL_NO_SHIFT

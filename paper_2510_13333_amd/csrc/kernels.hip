@@ -956,17 +956,61 @@ __global__ __launch_bounds__(256) void k_border_sum(DevArgs a) {
     a.sbb[I.sbb0 + int64_t(i) * (i + 1) / 2 + j] = (p >= 0 ? a.kval[a.kint + I.kbb0 + p] : 0.0) - s;
 }
 
-// Dense LDL^T of the packed border matrix S (lower triangle packed by rows),
-// in place: S ends with L strictly below the diagonal and 1 on it; D goes
-// to dval.  Borders of up to kBorderRegMax rows: k_border_factor below, the
-// whole matrix in registers.  Larger ones: right-looking by column blocks
-// of kBB, the trailing matrix in global memory (L2-resident), two launches
-// a block:
-//   k_border_panel: wavefront 0 factors the diagonal block in registers
-//     (lane = row, columns published through LDS), then one thread per row
-//     below the block solves that row's kBB entries of L against it;
-//   k_border_update: the trailing lower triangle takes S_ik -= sum_j L_ij
-//     d_j L_kj, spread over one workgroup per 32x32 tile.
+// Dense LDL^T of the packed border matrix S (lower triangle packed by
+// rows); the factor L (unit lower, packed the same way) goes to lbb and D to
+// dval.  Borders of up to kBorderRegMax rows: k_border_factor, one
+// workgroup per instance with the whole matrix in registers.  Larger ones:
+// k_border_step, right-looking by column blocks of kBB, one launch per
+// block, S left as the trailing matrices.
+//   launch b = -1: one workgroup factors the diagonal block 0.
+//   launch b >= 0: one workgroup per tile (I, K), b < K <= I, of the
+//     trailing lower triangle.  It solves the rows of tiles I and K in block
+//     column b against the block's factor (W = A L^-T, L = W D^-1, one
+//     thread a row), takes S_IK -= W_I L_K^T, and, on the diagonal tile
+//     I = K, writes L of tile I's rows in block column b.  The workgroup of
+//     tile (b + 1, b + 1) then factors that updated diagonal block.
+// Every workgroup reads only block column b of S and writes only its own
+// tile, and L goes to a separate array, so no workgroup reads what another
+// writes in the same launch.  Each entry's sums run in column order.
+
+// LDL^T of the kBB x kBB block T (LDS, rows < bs, lower part valid) by
+// wavefront 0, lane i holding row i, column j published through T's column
+// j; L (strict lower, 1 on the diagonal) to Lg rows b0.., pivots to Dg.
+__device__ inline void border_diag_ldlt(double (*T)[kPS], int bs, int b0, double *Lg, double *Dg) {
+    const int i = lane_id();
+    const bool on = i < bs;
+    double row[kBB];
+#pragma unroll
+    for (int k = 0; k < kBB; k++) row[k] = (on && k <= i) ? T[on ? i : 0][k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBB; j++) {
+        if (j < bs) {
+            if (on && i >= j) T[i][j] = row[j];
+            __builtin_amdgcn_wave_barrier();
+            const double dj = T[j][j];
+            const double lij = i > j ? row[j] / dj : 0.0;
+#pragma unroll
+            for (int k = j + 1; k < kBB; k++) {
+                const double ak = T[k][j];
+                const double upd = row[k] - lij * ak;
+                row[k] = (i >= k && k < bs) ? upd : row[k];
+            }
+            row[j] = i > j ? lij : row[j];
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < kBB; k++) {
+            if (k < i) Lg[pk(b0 + i, b0 + k)] = row[k];
+            if (k == i) {
+                Lg[pk(b0 + i, b0 + i)] = 1.0;
+                Dg[b0 + i] = row[k];
+            }
+        }
+    }
+}
+
 constexpr int kBFThreads = 512;    // 8 wavefronts: up to 256 registers each, no spills
 
 // Dense LDL^T of a border matrix held in registers.  The lower triangle is
@@ -986,7 +1030,8 @@ template <int T>
 __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, double *piv, double *pan) {
     const int nbd = I.nbd, tid = threadIdx.x;
     const int mt = (nbd + 3) >> 2, npad = 4 * mt, ntl = mt * (mt + 1) / 2;
-    double *Sg = a.sbb + I.sbb0;
+    const double *Sg = a.sbb + I.sbb0;
+    double *Lo = a.lbb + I.sbb0;
     double *Db = a.dval + a.dint + I.bd0;
     double *Wp = pan, *Lp = pan + 4 * npad;      // [k][row] for k < 4, rows < npad
     double A[T][16];
@@ -1094,7 +1139,7 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
         for (int r = 0; r < 4; r++) {
             const int i = 4 * ti[j] + r;
             if (i >= nbd) continue;
-            double *si = Sg + pk(i, c0);
+            double *si = Lo + pk(i, c0);
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 if (c0 + c > i) continue;
@@ -1110,136 +1155,128 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
 }
 
 // One workgroup per instance.  Each instance takes the register-tiled factor
-// when its tiles fit T per thread, else the blocked one, so that the path an
-// instance takes depends on its own border only (a batched launch and a
-// launch for that instance alone compute the same bits).
+// when its tiles fit T per thread, else the blocked one (k_border_step), so
+// that the path an instance takes depends on its own border only (a batched
+// launch and a launch for that instance alone compute the same bits).
 template <int T>
 __global__ __launch_bounds__(kBFThreads) void k_border_factor(DevArgs a) {
     __shared__ double piv[16];    // d (0..3), 1/d (4..7), l10 l20 l21 l30 l31 l32 (8..13)
     extern __shared__ __align__(16) double lds[];
     const InstDev &I = a.insts[blockIdx.x];
     const int mt = (I.nbd + 3) >> 2;
-    if (mt <= kBFRegMaxNt) border_factor_reg<T>(a, I, piv, lds);   // larger: k_border_panel / k_border_update
+    if (mt <= kBFRegMaxNt) border_factor_reg<T>(a, I, piv, lds);   // larger: k_border_step
 }
 
-__global__ __launch_bounds__(kBFThreads) void k_border_panel(DevArgs a, int b0) {
-    extern __shared__ double lds[];
-    double *Ld = lds;                  // [kBB][kPS] L of the diagonal block
-    double *dd = Ld + kBB * kPS;       // [kBB] its pivots
-    const InstDev &I = a.insts[blockIdx.x];
-    const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
-    if (nbd <= kBorderRegMax || b0 >= nbd) return;
-    double *S = a.sbb + I.sbb0;
-    double *Db = a.dval + a.dint + I.bd0;
-    const int bs = nbd - b0 < kBB ? nbd - b0 : kBB;
-    const int r0 = b0 + bs, m = nbd - r0;
-    if (tid < 64) {
-        // diagonal block: lane i < bs holds row i; column j is published
-        // through Ld's column j (its final L values are written there)
-        const int i = lane;
-        const bool on = i < bs;
-        double row[kBB];
-        // every load issued up front: clamped to a valid entry of the block,
-        // the unused ones masked afterwards
-        const int ic = on ? i : bs - 1;
-#pragma unroll
-        for (int k = 0; k < kBB; k++) {
-            const double v = S[pk(b0 + ic, b0 + (k <= ic ? k : ic))];
-            row[k] = (on && k <= i) ? v : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kBB; j++) {
-            if (j < bs) {
-                if (on && i >= j) Ld[i * kPS + j] = row[j];
-                __builtin_amdgcn_wave_barrier();
-                const double dj = Ld[j * kPS + j];
-                const double lij = i > j ? row[j] / dj : 0.0;
-#pragma unroll
-                for (int k = j + 1; k < kBB; k++) {
-                    const double ak = Ld[k * kPS + j];
-                    const double upd = row[k] - lij * ak;
-                    row[k] = (i >= k && k < bs) ? upd : row[k];     // select, no divergent branch
-                }
-                row[j] = i > j ? lij : row[j];
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-        if (on) {
-#pragma unroll
-            for (int k = 0; k < kBB; k++) {
-                if (k < i) {
-                    Ld[i * kPS + k] = row[k];
-                    S[pk(b0 + i, b0 + k)] = row[k];
-                }
-                if (k == i) {
-                    dd[i] = row[k];
-                    Db[b0 + i] = row[k];
-                    S[pk(b0 + i, b0 + i)] = 1.0;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // rows below the block: L_ij = (S_ij - sum_{k<j} L_ik d_k L_jk) / d_j
-    for (int t = tid; t < m; t += kBFThreads) {
-        double *si = S + pk(r0 + t, b0);
-        double x[kBB];
-#pragma unroll
-        for (int j = 0; j < kBB; j++) {
-            if (j < bs) {
-                double v = si[j];
-#pragma unroll
-                for (int k = 0; k < kBB; k++)
-                    if (k < j) v -= x[k] * dd[k] * Ld[j * kPS + k];
-                x[j] = v / dd[j];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kBB; j++)
-            if (j < bs) si[j] = x[j];
-    }
-}
 
-// Trailing update of a large border by column block b0: S_ik -= sum_j L_ij
-// d_j L_kj over the block's columns, one workgroup per 32x32 tile of the
-// trailing lower triangle (the tile's rows of the block column staged in
-// LDS, L_kj d_j formed there), each thread 2x2 entries, j ascending.
-__global__ __launch_bounds__(256) void k_border_update(DevArgs a, int b0) {
-    __shared__ double Li[kBB][kPS], Lk[kBB][kPS];
+constexpr int kBSThreads = 256;
+
+__global__ __launch_bounds__(kBSThreads) void k_border_step(DevArgs a, int b) {
+    __shared__ double Lbb[kBB][kPS];   // L of block b's diagonal block
+    __shared__ double db[kBB];         // its pivots
+    __shared__ double Wi[kBB][kPS];    // W of tile I's rows in block column b
+    __shared__ double Lk[kBB][kPS];    // L of tile K's rows in block column b
+    __shared__ double Tn[kBB][kPS];    // the next diagonal block, updated
     const InstDev &I = a.insts[blockIdx.y];
-    const int nbd = I.nbd;
-    if (nbd <= kBorderRegMax || b0 >= nbd) return;
-    const int bs = nbd - b0 < kBB ? nbd - b0 : kBB, r0 = b0 + bs, m = nbd - r0;
-    const int nsb = (m + kBB - 1) / kBB;
-    if (int(blockIdx.x) >= nsb * (nsb + 1) / 2) return;
-    int SI, SK;
-    unpack(blockIdx.x, SI, SK);
+    const int n = I.nbd, nbk = (n + kBB - 1) / kBB, tid = threadIdx.x;
+    if (n <= kBorderRegMax) return;
     double *S = a.sbb + I.sbb0;
-    const double *Db = a.dval + a.dint + I.bd0;
-    const int i0 = r0 + kBB * SI, k0 = r0 + kBB * SK;
-    for (int t = threadIdx.x; t < kBB * kBB; t += 256) {
-        const int rr = t / kBB, j = t % kBB;
-        const int i = i0 + rr, k = k0 + rr;
-        Li[rr][j] = (i < nbd && j < bs) ? S[pk(i, b0 + j)] : 0.0;
-        Lk[rr][j] = (k < nbd && j < bs) ? S[pk(k, b0 + j)] * Db[b0 + j] : 0.0;
-    }
-    __syncthreads();
-    const int t = threadIdx.x, ii = 2 * (t >> 4), kk = 2 * (t & 15);
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int j = 0; j < bs; j++) {
-        const double p0 = Li[ii][j], p1 = Li[ii + 1][j], c0 = Lk[kk][j], c1 = Lk[kk + 1][j];
-        acc[0][0] += p0 * c0;
-        acc[0][1] += p0 * c1;
-        acc[1][0] += p1 * c0;
-        acc[1][1] += p1 * c1;
-    }
-#pragma unroll
-    for (int u = 0; u < 2; u++)
-#pragma unroll
-        for (int v = 0; v < 2; v++) {
-            const int i = i0 + ii + u, k = k0 + kk + v;
-            if (i < nbd && k <= i) S[pk(i, k)] -= acc[u][v];
+    double *Lg = a.lbb + I.sbb0;
+    double *Dg = a.dval + a.dint + I.bd0;
+    // the diagonal block this workgroup factors at the end (none: -1)
+    int dg0 = -1, dgs = 0;
+    if (b < 0) {
+        if (blockIdx.x != 0 || n == 0) return;
+        dgs = n < kBB ? n : kBB;
+        dg0 = 0;
+        for (int e = tid; e < kBB * kBB; e += kBSThreads) {
+            const int r = e / kBB, c = e % kBB;
+            Tn[r][c] = (r < dgs && c <= r) ? S[pk(r, c)] : 0.0;
         }
+    } else {
+        const int rem = nbk - b - 1;
+        if (rem <= 0 || int(blockIdx.x) >= rem * (rem + 1) / 2) return;
+        int ti, tk;
+        unpack(blockIdx.x, ti, tk);
+        const int TI = b + 1 + ti, TK = b + 1 + tk;
+        const int b0 = b * kBB, i0 = TI * kBB, k0 = TK * kBB;
+        const int bsb = n - b0 < kBB ? n - b0 : kBB;
+        const int bsi = n - i0 < kBB ? n - i0 : kBB;
+        const int bsk = n - k0 < kBB ? n - k0 : kBB;
+        for (int e = tid; e < kBB * kBB; e += kBSThreads) {
+            const int r = e / kBB, c = e % kBB;
+            Lbb[r][c] = (r < bsb && c < r) ? Lg[pk(b0 + r, b0 + c)] : (r == c ? 1.0 : 0.0);
+        }
+        if (tid < kBB) db[tid] = tid < bsb ? Dg[b0 + tid] : 1.0;
+        __syncthreads();
+        // rows of tile I (threads 0..31, into Wi) and of tile K (threads 32..63,
+        // K != I, into Lk): w_j = a_j - sum_{k<j} w_k L_jk, the row in
+        // registers (every index known at compile time)
+        if (tid < 2 * kBB) {
+            const bool rowsI = tid < kBB;
+            const int rr = tid & (kBB - 1);
+            const int bsr = rowsI ? bsi : bsk, r0 = rowsI ? i0 : k0;
+            if (rowsI || TK != TI) {
+                const bool on = rr < bsr;
+                const double *src = S + pk(on ? r0 + rr : r0, b0);
+                double w[kBB];
+#pragma unroll
+                for (int j = 0; j < kBB; j++) w[j] = (on && j < bsb) ? src[j] : 0.0;
+#pragma unroll
+                for (int j = 1; j < kBB; j++) {
+                    double v = w[j];
+#pragma unroll
+                    for (int k = 0; k < j; k++) v -= w[k] * Lbb[j][k];
+                    w[j] = v;
+                }
+                double *dst = rowsI ? Wi[rr] : Lk[rr];
+#pragma unroll
+                for (int j = 0; j < kBB; j++) dst[j] = w[j];
+            }
+        }
+        __syncthreads();
+        // L_K = W_K D^-1 (the I rows themselves on a diagonal tile); the diagonal
+        // tile writes L of tile I's rows in block column b
+        for (int e = tid; e < kBB * kBB; e += kBSThreads) {
+            const int rr = e / kBB, j = e % kBB;
+            if (TK == TI) {
+                const double l = Wi[rr][j] / db[j];
+                Lk[rr][j] = l;
+                if (rr < bsi && j < bsb) Lg[pk(i0 + rr, b0 + j)] = l;
+            } else {
+                Lk[rr][j] = Lk[rr][j] / db[j];
+            }
+        }
+        __syncthreads();
+        // S_IK -= W_I L_K^T: thread t takes row t / 8 and columns 4 (t % 8) .. + 3
+        const bool next = TI == b + 1 && TK == b + 1;
+        {
+            const int r = tid >> 3, c0 = (tid & 7) * 4;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int j = 0; j < bsb; j++) {
+                const double wv = Wi[r][j];
+#pragma unroll
+                for (int u = 0; u < 4; u++) acc[u] += wv * Lk[c0 + u][j];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int c = c0 + u;
+                const bool in = r < bsi && c < bsk && (TI != TK || c <= r);
+                double v = 0.0;
+                if (in) {
+                    v = S[pk(i0 + r, k0 + c)] - acc[u];
+                    S[pk(i0 + r, k0 + c)] = v;
+                }
+                if (next) Tn[r][c] = v;
+            }
+        }
+        if (next) {
+            dg0 = i0;
+            dgs = bsi;
+        }
+    }
+    if (dg0 < 0) return;
+    __syncthreads();
+    if (tid < 64) border_diag_ldlt(Tn, dgs, dg0, Lg, Dg);
 }
 
 // Pivot signs and magnitudes of the whole factorisation (integer atomics only).
@@ -1600,7 +1637,7 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
                                   double *x, double *y, const double *__restrict__ cpart, bool add) {
     const int nbd = I.nbd, nblk = I.nblk, tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const double *Db = a.dval + a.dint + I.bd0;
-    const double *Lg = a.sbb + I.sbb0;
+    const double *Lg = a.lbb + I.sbb0;
     double *Ll = c + a.max_nbd;
     if (kRes) {
         const int npk = nbd * (nbd + 1) / 2;
@@ -2785,10 +2822,9 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (a.pe_tot) hipLaunchKernelGGL(k_border_sum, dim3(unsigned((a.pe_tot + 255) / 256)), dim3(256), 0, st, a);
             break;
         case NCL_K_BORDER_FACTOR:
-            if (a.max_nbd) {
-                // tiles per thread of the register path: enough for the largest
-                // border that takes it (instances of more than kBFRegMaxNt tile rows take the
-                // blocked path inside the same kernel)
+            if (!a.max_nbd) break;
+            if (l.b0 == -2) {
+                // the register path; tiles per thread: enough for the largest border that takes it
                 const int nreg = a.max_nbd < 4 * kBFRegMaxNt ? a.max_nbd : 4 * kBFRegMaxNt;
                 const int mt = (nreg + 3) / 4, tpt = (mt * (mt + 1) / 2 + kBFThreads - 1) / kBFThreads;
                 const size_t lb = size_t(8) * 4 * mt * sizeof(double);
@@ -2804,22 +2840,13 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                     case 2: hipLaunchKernelGGL(k_border_factor<2>, dim3(a.ninst), dim3(kBFThreads), lb, st, a); break;
                     default: hipLaunchKernelGGL(k_border_factor<3>, dim3(a.ninst), dim3(kBFThreads), lb, st, a); break;
                 }
+            } else {
+                // blocked path: column block b = -1 .. (blocks of the largest border) - 2
+                const int nbk = (a.max_nbd + kBB - 1) / kBB, rem = nbk - l.b0 - 1;
+                const unsigned nt = l.b0 < 0 ? 1u : unsigned(rem > 0 ? rem * (rem + 1) / 2 : 0);
+                if (nt) hipLaunchKernelGGL(k_border_step, dim3(nt, unsigned(a.ninst)), dim3(kBSThreads), 0, st, a, l.b0);
             }
             break;
-        case NCL_K_BORDER_PANEL:
-            if (a.max_nbd > kBorderRegMax)
-                hipLaunchKernelGGL(k_border_panel, dim3(a.ninst), dim3(kBFThreads), size_t(kBB * kPS + kBB) * sizeof(double),
-                                   st, a, l.b0);
-            break;
-        case NCL_K_BORDER_UPDATE: {
-            const int m = a.max_nbd - l.b0 - kBB;
-            if (a.max_nbd > kBorderRegMax && m > 0) {
-                const int nsb = (m + kBB - 1) / kBB;
-                hipLaunchKernelGGL(k_border_update, dim3(unsigned(nsb * (nsb + 1) / 2), unsigned(a.ninst)), dim3(256), 0,
-                                   st, a, l.b0);
-            }
-            break;
-        }
         case NCL_K_STATUS_INIT:
             hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, a);
             break;

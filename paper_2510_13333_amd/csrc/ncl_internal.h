@@ -53,7 +53,7 @@ struct CItem {
 constexpr int kMT = 16;
 constexpr int kMC = 16;
 constexpr int kMSlice = 128;
-constexpr int kMItemCost = 16;     // slicing cost of an item beyond its instructions (its dependent loads)
+constexpr int kMItemCost = 8;      // slicing cost of an item beyond its instructions (its dependent loads)
 struct MItem {
     int32_t tmpl, poff, r, w;
     int16_t ri[kMT], rj[kMT];
@@ -343,7 +343,8 @@ struct Handle {
     bool factor_failed = false;             // ncl_kkt_info saw a factor the solves may not use
     struct Dev {
         double *kval = nullptr;          // interleaved K, then the border K_bb values of every instance
-        double *lpan = nullptr, *upan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *ybuf = nullptr,
+        double *lpan = nullptr, *upan = nullptr, *dval = nullptr, *spart = nullptr, *sbb = nullptr, *lbb = nullptr,
+               *ybuf = nullptr,
                *cpart = nullptr;
         double *zint = nullptr, *sint = nullptr;   // state and Sigma in the blocks' interleaved layout order
         double *xint = nullptr, *bint = nullptr, *rint = nullptr;   // residual: x, b, r interleaved (one column)

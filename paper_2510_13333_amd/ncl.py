@@ -23,7 +23,7 @@ NCL_SCREEN = 2
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
            "border_factor", "status_init", "status", "sol_load", "sol_fwd_gather", "sol_fwd_diag", "sol_bpart",
            "sol_border", "sol_bwd_border", "sol_bwd", "sol_store", "residual", "max_step", "interleave",
-           "border_panel", "border_update", "berr_rows", "berr_border", "berr_final"]
+           "berr_rows", "berr_border", "berr_final"]
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "host allocation failed", -3: "HIP runtime error",
           -4: "call out of order", -5: "zero pivot", -6: "pivot of the wrong sign (inertia)",

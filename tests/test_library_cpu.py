@@ -228,9 +228,13 @@ def test_kernel_model_counts():
     k = KKT(G.config_network(2))
     m = {n: k.kernel_model(i) for i, n in enumerate(KERNELS)}
     assert m["values"] == (0, 0)
-    for n in ("assemble", "border_schur", "border_sum", "border_factor", "status", "sol_load", "sol_bpart",
+    for n in ("assemble", "border_schur", "border_sum", "status", "sol_load", "sol_bpart",
               "sol_border", "sol_store"):
         assert m[n][0] == 1 and m[n][1] > 0, n
+    # the dense border factor: the register launch, plus one launch per
+    # 32-column block for borders over 216 rows
+    nbd = k.instances[0]["nbd"]
+    assert m["border_factor"][0] == 1 + ((nbd + 31) // 32 if nbd > 216 else 0) and m["border_factor"][1] > 0
     for n in ("fac_gather", "fac_rows", "sol_fwd_gather", "sol_bwd"):
         assert m[n][0] >= 5
     # the backward pass: one launch per level, plus one border step
