@@ -297,6 +297,21 @@ int ncl_kkt_info(ncl_kkt *h, ncl_kkt_report *rep, void *stream);
  * factor order. */
 int ncl_kkt_get_factors(ncl_kkt *h, double *dlx, double *dd, void *stream);
 
+/* Factor and solve in one call.  The blocks couple only through the
+ * border (Section II-B, eq. (scopf)), so the forward substitution of the
+ * blocks does not need the border's factor: the blocks are factored on
+ * `stream`, then the border's Schur products, their sum and the dense
+ * border factor run on a second stream that the library creates on first
+ * use (default priority, on the device current then) while `stream` runs
+ * the forward substitution of the blocks; `stream` then waits for the border
+ * and finishes the solve.  Results equal those of ncl_kkt_factor followed
+ * by ncl_kkt_solve bit for bit, ncl_kkt_info reports the same, and a
+ * factorisation that may not be solved with gives NaN in dx.  Arguments and
+ * errors as ncl_kkt_solve, except that the handle needs values, not factors
+ * (NCL_ERR_STATE without them).  The second stream is joined back to
+ * `stream` within the call, so a stream capture of the call is complete. */
+int ncl_kkt_factor_solve(ncl_kkt *h, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream);
+
 /* X = K^{-1} B for nrhs columns of length N in layout order, leading
  * dimension ld >= N (device): the Newton step of eq. (newtonsystem),
  * [dw; dy] for the right-hand side (r1, r2) the interior-point method sets

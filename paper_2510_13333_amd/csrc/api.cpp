@@ -1024,16 +1024,8 @@ int ncl_kkt_get_values(ncl_kkt *k, double *dvals, void *stream) {
     return hip_rc(run(h, NCL_K_VALUES, dev_args(h), l, reinterpret_cast<hipStream_t>(stream)));
 }
 
-int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
-    if (!k) return NCL_ERR_ARG;
-    Handle &h = k->h;
-    if (!h.bound || !h.values_set) return NCL_ERR_STATE;
-    // the factors are overwritten from here on: no solve until the border is done
-    h.blocks_done = false;
-    h.factored = false;
-    h.factor_failed = false;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const ncl::DevArgs a = dev_args(h);
+// The blocks' factorisation: per level the gathers, diagonal blocks and rows.
+static int factor_levels(Handle &h, const ncl::DevArgs &a, hipStream_t st) {
     const ncl::Schedule &S = h.sched;
     const ncl::Work *W = h.d.work;
     auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
@@ -1047,6 +1039,47 @@ int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
         if (list(NCL_K_FAC_DIAG, h.w_b, S.b_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_FAC_ROWS, h.w_c, S.c_ptr, l) != hipSuccess) return NCL_ERR_HIP;
     }
+    return NCL_OK;
+}
+
+// The border: the Schur products (schur = true; beside other work when
+// shared), their sum and the dense border factor.
+static int border_launches(Handle &h, const ncl::DevArgs &a, bool schur, bool shared, hipStream_t st) {
+    const ncl::LaunchArgs none;
+    if (schur) {
+        ncl::LaunchArgs l;
+        l.shared_gpu = shared;
+        if (run(h, NCL_K_BORDER_SCHUR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    if (run(h, NCL_K_BORDER_SUM, a, none, st) != hipSuccess) return NCL_ERR_HIP;
+    // the register path for borders of up to kBorderRegMax rows, then one
+    // launch per column block of the largest larger border
+    {
+        ncl::LaunchArgs l;
+        l.b0 = -2;
+        if (run(h, NCL_K_BORDER_FACTOR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    const int nbk = (big_border(h) + ncl::kBorderBlock - 1) / ncl::kBorderBlock;
+    for (int b = -1; b < nbk - 1; b++) {
+        ncl::LaunchArgs l;
+        l.b0 = b;
+        if (run(h, NCL_K_BORDER_FACTOR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    }
+    return NCL_OK;
+}
+
+int ncl_kkt_factor_blocks(ncl_kkt *k, void *stream) {
+    if (!k) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound || !h.values_set) return NCL_ERR_STATE;
+    // the factors are overwritten from here on: no solve until the border is done
+    h.blocks_done = false;
+    h.factored = false;
+    h.factor_failed = false;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    int rc = factor_levels(h, a, st);
+    if (rc) return rc;
     if (h.nbd_tot && run(h, NCL_K_BORDER_SCHUR, a, ncl::LaunchArgs{}, st) != hipSuccess) return NCL_ERR_HIP;
     h.blocks_done = true;
     return NCL_OK;
@@ -1059,20 +1092,9 @@ int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const ncl::DevArgs a = dev_args(h);
     const ncl::LaunchArgs none;
-    if (run(h, NCL_K_BORDER_SUM, a, none, st) != hipSuccess) return NCL_ERR_HIP;
-    // the dense border factor: the register path for borders of up to
-    // kBorderRegMax rows, then one launch per column block of the largest
-    // larger border
-    {
-        ncl::LaunchArgs l;
-        l.b0 = -2;
-        if (run(h, NCL_K_BORDER_FACTOR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
-    }
-    const int nbk = (big_border(h) + ncl::kBorderBlock - 1) / ncl::kBorderBlock;
-    for (int b = -1; b < nbk - 1; b++) {
-        ncl::LaunchArgs l;
-        l.b0 = b;
-        if (run(h, NCL_K_BORDER_FACTOR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
+    if (h.nbd_tot) {
+        const int rc = border_launches(h, a, false, false, st);
+        if (rc) return rc;
     }
     for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
         if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
@@ -1168,10 +1190,14 @@ int ncl_kkt_get_factors(ncl_kkt *k, double *lx, double *dd, void *stream) {
 // launch covering all of them.  refine: one column whose right-hand side is
 // the residual the backward-error kernels left (blocks interleaved in rint,
 // the border in rbuf); its solution is added into x.
-static int solve_columns(Handle &h, const ncl::DevArgs &a, const double *b, double *x, int nrhs, int64_t ld, bool refine,
-                         hipStream_t st) {
-    const ncl::Schedule &S = h.sched;
-    const ncl::Work *W = h.d.work;
+// The solve in two halves.  The first (right-hand side in, forward
+// substitution of the blocks, the blocks' parts of the border right-hand
+// side) needs only the blocks' factors; the second (the border solve, the
+// backward substitution, the solution out) needs the border's factor and
+// the factorisation status.  check = false: the load does not consult the
+// status (the combined factor+solve computes it between the halves; the
+// store writes NaN for an unusable factorisation either way).
+static ncl::LaunchArgs solve_args(Handle &h, const double *b, double *x, int nrhs, int64_t ld, bool refine) {
     ncl::LaunchArgs v;
     v.b = refine ? h.d.rbuf : b;
     v.x = x;
@@ -1183,21 +1209,23 @@ static int solve_columns(Handle &h, const ncl::DevArgs &a, const double *b, doub
     v.bld = ld;
     v.ys = h.dint + h.nbd_tot;
     v.cps = h.cp_tot;
-    auto level = [&](int kind, int l) {
-        ncl::LaunchArgs la = v;
-        la.wl = W + h.w_sn + S.sn_ptr[l];
-        la.nw = S.sn_ptr[l + 1] - S.sn_ptr[l];
-        la.nnar = S.sn_nar[l];
-        la.wmax = S.sn_wmax[l];
-        return run(h, kind, a, la, st);
-    };
+    return v;
+}
+
+static int solve_first_half(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, bool check, hipStream_t st) {
+    const ncl::Schedule &S = h.sched;
+    const ncl::Work *W = h.d.work;
     auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
         ncl::LaunchArgs la = v;
         la.wl = W + off + ptr[l];
         la.nw = ptr[l + 1] - ptr[l];
         return run(h, kind, a, la, st);
     };
-    if (run(h, NCL_K_SOL_LOAD, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+    {
+        ncl::LaunchArgs la = v;
+        la.nocheck = !check;
+        if (run(h, NCL_K_SOL_LOAD, a, la, st) != hipSuccess) return NCL_ERR_HIP;
+    }
     for (int l = 0; l < S.nlev; l++) {
         if (list(NCL_K_SOL_FWD_GATHER, h.w_f, S.f_ptr, l) != hipSuccess) return NCL_ERR_HIP;
         if (list(NCL_K_SOL_FWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
@@ -1207,8 +1235,14 @@ static int solve_columns(Handle &h, const ncl::DevArgs &a, const double *b, doub
         la.wl = W + h.w_bpart;
         la.nw = int(S.bpart.size());
         if (run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess) return NCL_ERR_HIP;
-        if (run(h, NCL_K_SOL_BORDER, a, v, st) != hipSuccess) return NCL_ERR_HIP;
     }
+    return NCL_OK;
+}
+
+static int solve_second_half(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, hipStream_t st) {
+    const ncl::Schedule &S = h.sched;
+    const ncl::Work *W = h.d.work;
+    if (h.nbd_tot && run(h, NCL_K_SOL_BORDER, a, v, st) != hipSuccess) return NCL_ERR_HIP;
     {
         ncl::LaunchArgs la = v;
         la.wl = W + h.w_sb;
@@ -1216,9 +1250,41 @@ static int solve_columns(Handle &h, const ncl::DevArgs &a, const double *b, doub
         la.nnar = S.sb_nar;
         if (run(h, NCL_K_SOL_BWD_BORDER, a, la, st) != hipSuccess) return NCL_ERR_HIP;
     }
-    for (int l = S.nlev - 1; l >= 0; l--)
-        if (level(NCL_K_SOL_BWD, l) != hipSuccess) return NCL_ERR_HIP;
+    for (int l = S.nlev - 1; l >= 0; l--) {
+        ncl::LaunchArgs la = v;
+        la.wl = W + h.w_sn + S.sn_ptr[l];
+        la.nw = S.sn_ptr[l + 1] - S.sn_ptr[l];
+        la.nnar = S.sn_nar[l];
+        la.wmax = S.sn_wmax[l];
+        if (run(h, NCL_K_SOL_BWD, a, la, st) != hipSuccess) return NCL_ERR_HIP;
+    }
     if (run(h, NCL_K_SOL_STORE, a, v, st) != hipSuccess) return NCL_ERR_HIP;
+    return NCL_OK;
+}
+
+static int solve_columns(Handle &h, const ncl::DevArgs &a, const double *b, double *x, int nrhs, int64_t ld, bool refine,
+                         hipStream_t st) {
+    const ncl::LaunchArgs v = solve_args(h, b, x, nrhs, ld, refine);
+    const int rc = solve_first_half(h, a, v, true, st);
+    return rc ? rc : solve_second_half(h, a, v, st);
+}
+
+// The library's second stream and its fork and join events, created on
+// first use (on the device current then).
+static int side_stream(Handle &h) {
+    if (h.side) return NCL_OK;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return NCL_ERR_HIP;
+    if (hipEventCreateWithFlags(&e0, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipStreamDestroy(s);
+        return NCL_ERR_HIP;
+    }
+    h.side = s;
+    h.ev_fork = e0;
+    h.ev_join = e1;
     return NCL_OK;
 }
 
@@ -1687,6 +1753,43 @@ int ncl_kkt_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_
     return do_solve(k, db, dx, nrhs, ld, stream);
 }
 
+int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {
+    if (!k || !db || !dx || nrhs < 1) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    if (!h.bound || !h.values_set) return NCL_ERR_STATE;
+    if (nrhs > h.nrhs_max || ld < h.N) return NCL_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ncl::DevArgs a = dev_args(h);
+    h.blocks_done = false;
+    h.factored = false;
+    h.factor_failed = false;
+    int rc = factor_levels(h, a, st);
+    if (rc) return rc;
+    const bool fork = h.nbd_tot > 0;
+    hipStream_t side = nullptr;
+    if (fork) {
+        if ((rc = side_stream(h))) return rc;
+        side = static_cast<hipStream_t>(h.side);
+        hipEvent_t ef = static_cast<hipEvent_t>(h.ev_fork);
+        if (hipEventRecord(ef, st) != hipSuccess || hipStreamWaitEvent(side, ef, 0) != hipSuccess) return NCL_ERR_HIP;
+        // a border in registers is short work next to the forward
+        // substitution, which then keeps most compute units; the blocked
+        // path of a larger border is the longer chain and takes them all
+        if ((rc = border_launches(h, a, true, big_border(h) == 0, side))) return rc;
+    }
+    // the status needs only the pivots: it closes the side stream's work
+    const ncl::LaunchArgs none;
+    for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
+        if (run(h, kind, a, none, fork ? side : st) != hipSuccess) return NCL_ERR_HIP;
+    if (fork && hipEventRecord(static_cast<hipEvent_t>(h.ev_join), side) != hipSuccess) return NCL_ERR_HIP;
+    const ncl::LaunchArgs v = solve_args(h, db, dx, nrhs, ld, false);
+    if ((rc = solve_first_half(h, a, v, false, st))) return rc;
+    if (fork && hipStreamWaitEvent(st, static_cast<hipEvent_t>(h.ev_join), 0) != hipSuccess) return NCL_ERR_HIP;
+    h.blocks_done = true;
+    h.factored = true;
+    return solve_second_half(h, a, v, st);
+}
+
 int ncl_kkt_solve_adjoint(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64_t ld, void *stream) {
     // K = K^T: the transposed system uses the same factors and the same kernels
     return do_solve(k, db, dx, nrhs, ld, stream);
@@ -1760,4 +1863,7 @@ int ncl_kkt_refine(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64
 
 ncl_kkt::~ncl_kkt() {
     for (void *e : h.ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    if (h.ev_fork) (void)hipEventDestroy(static_cast<hipEvent_t>(h.ev_fork));
+    if (h.ev_join) (void)hipEventDestroy(static_cast<hipEvent_t>(h.ev_join));
+    if (h.side) (void)hipStreamDestroy(static_cast<hipStream_t>(h.side));
 }

@@ -69,6 +69,8 @@ struct LaunchArgs {
     double *dst = nullptr;                       // value conversion; backward error: (eta, omega)
     bool to_internal = false;
     bool accumulate = false;                     // solve store: x += solution
+    bool nocheck = false;                        // solve load: do not consult the factorisation status
+    bool shared_gpu = false;                     // border Schur: other work runs beside it (a smaller grid)
     const double *b = nullptr;                   // solve: right-hand side, solution, work vectors
     double *x = nullptr, *y = nullptr, *cpart = nullptr;
     int nnar = 0;                                // solve levels: narrow items first in the list

@@ -825,9 +825,14 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
 // one fixed order of additions.
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a) {
-    const int64_t wg = int64_t(blockIdx.x) * (kWG / 64) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    if (wg >= a.mw_tot) return;
+// Slices are taken by a grid of workgroups each wave of which takes every
+// (grid waves)-th slice: one wave per slice alone, at most kSchurGrid
+// workgroups when the kernel runs beside the blocks' forward substitution
+// (the combined factor and solve), so that it leaves compute units to it.
+// A slice's result does not depend on which wave takes it.
+constexpr int kSchurGrid = 128;
+
+__device__ __attribute__((always_inline)) inline void border_schur_slice(const DevArgs &a, int64_t wg) {
     const InstDev &I = a.insts[find_inst(a, wg, &InstDev::mw0)];
     const int64_t wl = wg - I.mw0;
     const auto *dsc = cs(I.mdesc) + wl;
@@ -903,6 +908,13 @@ __global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a) {
     double *out = a.spart + I.sp0 + wl * (kMT * kMT);
 #pragma unroll
     for (int q = 0; q < 4; q++) out[(4 * q + qd) * kMT + m] = acc0[q] + acc1[q];
+}
+
+__global__ __launch_bounds__(kWG) void k_border_schur(DevArgs a) {
+    const int64_t stride = int64_t(gridDim.x) * (kWG / 64);
+    for (int64_t wg = int64_t(blockIdx.x) * (kWG / 64) + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+         wg < a.mw_tot; wg += stride)
+        border_schur_slice(a, wg);
 }
 
 // ------------------------------------------------------------------ border
@@ -1422,13 +1434,13 @@ __device__ inline bool factor_usable(const DevArgs &a) {
 // A factorisation that may not be solved with (see factor_usable) makes
 // the solve write NaN: the caller who never read the status still sees it.
 __global__ __launch_bounds__(256) void k_sol_load(DevArgs a, const double *__restrict__ b, double *__restrict__ y,
-                                                  int64_t bld, int64_t ys) {
+                                                  int64_t bld, int64_t ys, int check) {
     __shared__ double tile[kTileB][kTileJ + 1];
     b += blockIdx.y * bld;
     y += blockIdx.y * ys;
     const TileIx x = tile_index(a, blockIdx.x);
     const TemplDev &T = *x.T;
-    const bool ok = factor_usable(a);
+    const bool ok = !check || factor_usable(a);
     const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
     const int cb = threadIdx.x & 63, rj = threadIdx.x >> 6;
 #pragma unroll
@@ -1465,6 +1477,7 @@ __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__re
     xo += blockIdx.y * bld;
     const TileIx x = tile_index(a, blockIdx.x);
     const TemplDev &T = *x.T;
+    const bool ok = factor_usable(a);
     const int cj = threadIdx.x % kTileJ, rb = threadIdx.x / kTileJ;
     const int cb = threadIdx.x & 63, rj = threadIdx.x >> 6;
 #pragma unroll
@@ -1478,7 +1491,8 @@ __global__ __launch_bounds__(256) void k_sol_store(DevArgs a, const double *__re
         const int bl = x.b0 + rb + kTileRows * q, j = x.j0 + cj;
         if (bl < T.nblk && j < T.n) {
             const int64_t c = a.blks[T.blocks[bl]].col0 + j;
-            xo[c] = kAdd ? xo[c] + tile[rb + kTileRows * q][cj] : tile[rb + kTileRows * q][cj];
+            const double v = ok ? tile[rb + kTileRows * q][cj] : __builtin_nan("");
+            xo[c] = kAdd ? xo[c] + v : v;
         }
     }
 }
@@ -1735,9 +1749,11 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
         }
         __syncthreads();
     }
+    const bool ok = factor_usable(a);
     for (int i = tid; i < nbd; i += kBorderThreads) {
-        y[a.dint + I.bd0 + i] = c[i];
-        x[I.bstart + i] = add ? x[I.bstart + i] + c[i] : c[i];
+        const double v = ok ? c[i] : __builtin_nan("");
+        y[a.dint + I.bd0 + i] = v;
+        x[I.bstart + i] = add ? x[I.bstart + i] + v : v;
     }
 }
 
@@ -2814,9 +2830,11 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
             if (l.nw) hipLaunchKernelGGL(k_fac_rows, dim3(waves_grid(l.nw)), dim3(kWG), 0, st, a, l.wl, l.nw);
             break;
         case NCL_K_BORDER_SCHUR:
-            if (a.mw_tot)
-                hipLaunchKernelGGL(k_border_schur, dim3(unsigned((a.mw_tot + kWG / 64 - 1) / (kWG / 64))), dim3(kWG), 0,
-                                   st, a);
+            if (a.mw_tot) {
+                const int64_t need = (a.mw_tot + kWG / 64 - 1) / (kWG / 64);
+                const int64_t grid = l.shared_gpu && need > kSchurGrid ? kSchurGrid : need;
+                hipLaunchKernelGGL(k_border_schur, dim3(unsigned(grid)), dim3(kWG), 0, st, a);
+            }
             break;
         case NCL_K_BORDER_SUM:
             if (a.pe_tot) hipLaunchKernelGGL(k_border_sum, dim3(unsigned((a.pe_tot + 255) / 256)), dim3(256), 0, st, a);
@@ -2861,7 +2879,7 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                 hipLaunchKernelGGL(k_sol_load_int, dim3(elems_grid(a.dint)), dim3(256), 0, st, a, l.src, l.y);
             else if (a.dint)
                 hipLaunchKernelGGL(k_sol_load, dim3(unsigned(a.tiles), unsigned(l.nrhs)), dim3(256), 0, st, a, l.b, l.y,
-                                   l.bld, l.ys);
+                                   l.bld, l.ys, l.nocheck ? 0 : 1);
             break;
         case NCL_K_SOL_FWD_GATHER:
             if (l.nw > kSplitTasks)

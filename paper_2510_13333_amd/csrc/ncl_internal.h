@@ -367,6 +367,9 @@ struct Handle {
     int64_t prof_stride = 1, prof_seen = 0;   // bracket every prof_stride-th launch of prof_kind
     std::vector<void *> ev;
     size_t ev_used = 0;
+    // the second stream of the combined factor and solve, and its fork and
+    // join events (hipStream_t, hipEvent_t; created on first use)
+    void *side = nullptr, *ev_fork = nullptr, *ev_join = nullptr;
 };
 
 // model.cpp

@@ -135,6 +135,7 @@ def load():
         "ncl_kkt_info": ([P, P, P], ctypes.c_int),
         "ncl_kkt_get_factors": ([P, P, P, P], ctypes.c_int),
         "ncl_kkt_solve": ([P, P, P, i32, i64, P], ctypes.c_int),
+        "ncl_kkt_factor_solve": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_solve_adjoint": ([P, P, P, i32, i64, P], ctypes.c_int),
         "ncl_kkt_backward_error": ([P, P, P, i32, i64, P, P], ctypes.c_int),
         "ncl_kkt_refine": ([P, P, P, i32, i64, P], ctypes.c_int),
@@ -381,6 +382,11 @@ class KKT:
     def solve(self, b, out=None):
         """x = K^{-1} b; b is (N,) or (nrhs, N) float64 on the device, layout order."""
         return self._solve("ncl_kkt_solve", b, out)
+
+    def factor_solve(self, b, out=None):
+        """Factor the current values and solve, the border's factorisation
+        overlapped with the blocks' forward substitution on a second stream."""
+        return self._solve("ncl_kkt_factor_solve", b, out)
 
     def solve_adjoint(self, b, out=None):
         return self._solve("ncl_kkt_solve_adjoint", b, out)

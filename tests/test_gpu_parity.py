@@ -270,3 +270,46 @@ def test_wrong_sign_pivot_reported():
     prim_new = pos.is_primal[F.perm]
     wrong = np.flatnonzero((F.d > 0) != prim_new)
     assert info["first_bad"] == wrong[0]
+
+
+@pytest.mark.parametrize("which", ["c1", "pvpq", "c2", "big_border", "c3"])
+def test_factor_solve_equals_factor_then_solve(which):
+    """The combined call (the border factored on a second stream while the
+    blocks' forward substitution runs) gives the bits of factor + solve."""
+    nets = {"c1": lambda: (G.config_network(1), 1), "pvpq": lambda: (small_pvpq(), 99),
+            "c2": lambda: (G.config_network(2), 2), "c3": lambda: (G.config_network(3), 3),
+            "big_border": lambda: (G.make_network(31, 1300, 1820, 230, 3, rho=1e4), 31)}
+    net, cfg = nets[which]()
+    k = KKT(net).bind(nrhs_max=2)
+    for it in range(2):
+        z, s = G.draw_point(net, cfg, iteration=it)
+        b = dev(G.draw_rhs(k.N, 2, cfg, iteration=it))
+        k.assemble(dev(z), dev(s), net.rho)
+        k.factor()
+        x0 = k.solve(b)
+        info0 = k.info()
+        x1 = k.factor_solve(b)
+        info1 = k.info()
+        assert torch.equal(x0, x1), which
+        assert info0 == info1
+        # and after the combined call the factors serve further solves
+        assert torch.equal(k.solve(b), x0)
+
+
+def test_factor_solve_failed_factor_gives_nan():
+    net = G.config_network(1)
+    k0 = KKT(net)
+    cp, ri = k0.pattern()
+    z, s = G.draw_point(net, 1)
+    cpo, rio, v, pos = O.kkt(net, z, s)
+    col = np.repeat(np.arange(pos.N), np.diff(cp))
+    j = int(np.flatnonzero(pos.is_primal)[5])
+    q = np.flatnonzero((ri == j) & (col == j))[0]
+    v = v.copy()
+    v[q] = -1e9
+    k = KKT(pattern=(pos.N, np.array(pos.block_off), cp, ri, pos.is_primal.astype(np.uint8))).bind()
+    k.set_values(dev(v))
+    x = k.factor_solve(dev(G.draw_rhs(pos.N, 1, 1)[0]))
+    assert torch.isnan(x).all()
+    info = k.info()
+    assert info["status"] == -6 and info["solvable"] == 0
