@@ -276,9 +276,10 @@ int ncl_kkt_get_values(ncl_kkt *h, double *dvals, void *stream);
 int ncl_kkt_factor(ncl_kkt *h, void *stream);
 
 /* The two phases of ncl_kkt_factor, callable separately (same result):
- * factor_blocks factors every block and forms each block's border Schur
- * contribution K_bk K_kk^{-1} K_kb; factor_border sums those
- * contributions in block order, subtracts them from K_bb and factors the
+ * factor_blocks factors every block and forms the border Schur products
+ * sum_k K_bk K_kk^{-1} K_kb as partial tiles (tile pairs of the border,
+ * slices of supernodes, chunks of 16 blocks); factor_border sums the
+ * partials in a fixed order, subtracts them from K_bb and factors the
  * dense border.  factor_border returns NCL_ERR_STATE unless factor_blocks
  * ran since the last bind. */
 int ncl_kkt_factor_blocks(ncl_kkt *h, void *stream);
@@ -304,7 +305,8 @@ int ncl_kkt_get_factors(ncl_kkt *h, double *dlx, double *dd, void *stream);
  * border factor run on a second stream that the library creates on first
  * use (default priority, on the device current then) while `stream` runs
  * the forward substitution of the blocks; `stream` then waits for the border
- * and finishes the solve.  Results equal those of ncl_kkt_factor followed
+ * and finishes the solve (a border of fewer than 128 rows is factored in
+ * line on `stream`).  Results equal those of ncl_kkt_factor followed
  * by ncl_kkt_solve bit for bit, ncl_kkt_info reports the same, and a
  * factorisation that may not be solved with gives NaN in dx.  Arguments and
  * errors as ncl_kkt_solve, except that the handle needs values, not factors

@@ -1765,7 +1765,11 @@ int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs,
     h.factor_failed = false;
     int rc = factor_levels(h, a, st);
     if (rc) return rc;
-    const bool fork = h.nbd_tot > 0;
+    // a border of fewer than kForkMinBorder rows is factored in line: its
+    // work is too short to hide behind the forward substitution, and the
+    // fork and join would cost more than they save
+    constexpr int kForkMinBorder = 128;
+    const bool fork = h.max_nbd >= kForkMinBorder;
     hipStream_t side = nullptr;
     if (fork) {
         if ((rc = side_stream(h))) return rc;
@@ -1777,6 +1781,7 @@ int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs,
         // path of a larger border is the longer chain and takes them all
         if ((rc = border_launches(h, a, true, big_border(h) == 0, side))) return rc;
     }
+    if (!fork && h.nbd_tot && (rc = border_launches(h, a, true, false, st))) return rc;
     // the status needs only the pivots: it closes the side stream's work
     const ncl::LaunchArgs none;
     for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})

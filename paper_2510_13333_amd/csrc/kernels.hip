@@ -1647,9 +1647,8 @@ __device__ inline double lane_bcast(double v, int k) {
 // that the substitutions wait on LDS rather than on global memory; taken by
 // each instance whose factor fits the LDS the launch provides.
 template <bool kRes>
-__device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c, const double *__restrict__ b,
-                                  double *x, double *y, const double *__restrict__ cpart, bool add) {
-    const int nbd = I.nbd, nblk = I.nblk, tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+__device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c, double *x, double *y, bool add) {
+    const int nbd = I.nbd, tid = threadIdx.x, lane = lane_id();
     const double *Db = a.dval + a.dint + I.bd0;
     const double *Lg = a.lbb + I.sbb0;
     double *Ll = c + a.max_nbd;
@@ -1659,33 +1658,8 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
         for (int e = tid; e < npk; e += kBorderThreads) Ll[e] = Lg[e];
     }
     const double *Lb = kRes ? Ll : Lg;
-    // block sums of the border right-hand side, kRB rows per wavefront at a
-    // time so that their loads are in flight together (each row's sum is
-    // lane-strided in two partials, then a fixed shuffle tree)
-    constexpr int kRB = 4, kNW = kBorderThreads / 64;
-    for (int i0 = wv; i0 < nbd; i0 += kRB * kNW) {
-        double s0[kRB], s1[kRB];
-#pragma unroll
-        for (int q = 0; q < kRB; q++) s0[q] = s1[q] = 0.0;
-        for (int k = lane; k < nblk; k += 128) {
-#pragma unroll
-            for (int q = 0; q < kRB; q++) {
-                const int i = i0 + q * kNW;
-                if (i < nbd) {
-                    const double *ci = cpart + I.cp0 + int64_t(i) * nblk;
-                    s0[q] += ci[k];
-                    if (k + 64 < nblk) s1[q] += ci[k + 64];
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kRB; q++) {
-            const int i = i0 + q * kNW;
-            double v = s0[q] + s1[q];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if (lane == 0 && i < nbd) c[i] = b[I.bstart + i] - v;
-        }
-    }
+    // the border right-hand side (k_sol_bsum left it in y's border part)
+    for (int i = tid; i < nbd; i += kBorderThreads) c[i] = y[a.dint + I.bd0 + i];
     __syncthreads();
     // forward: L y = c
     for (int b0 = 0; b0 < nbd; b0 += kBB) {
@@ -1757,19 +1731,41 @@ __device__ inline void sol_border(const DevArgs &a, const InstDev &I, double *c,
     }
 }
 
-__global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, const double *__restrict__ b, double *x,
-                                                               double *y, const double *__restrict__ cpart,
-                                                               int64_t lds_bytes, int add, int64_t bld, int64_t ys,
-                                                               int64_t cps) {
-    extern __shared__ double c[];
+// The border right-hand side c_i = b_i - (sum over the blocks of the
+// partials k_sol_bpart left), one wavefront per border row of every
+// instance: lane-strided in two partials (blocks lane, lane + 128, ... and
+// lane + 64, lane + 192, ...), then a fixed shuffle tree; into y's border
+// part, which the border solve reads.
+__global__ __launch_bounds__(256) void k_sol_bsum(DevArgs a, const double *__restrict__ b, double *y,
+                                                  const double *__restrict__ cpart, int64_t bld, int64_t ys,
+                                                  int64_t cps) {
+    const int64_t q = int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    if (q >= a.nbd_tot) return;
     b += blockIdx.y * bld;
-    x += blockIdx.y * bld;
     y += blockIdx.y * ys;
     cpart += blockIdx.y * cps;
+    const InstDev &I = a.insts[find_inst(a, q, &InstDev::bd0)];
+    const int i = int(q - I.bd0), nblk = I.nblk, lane = lane_id();
+    const double *ci = cpart + I.cp0 + int64_t(i) * nblk;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = lane; k < nblk; k += 128) {
+        s0 += ci[k];
+        if (k + 64 < nblk) s1 += ci[k + 64];
+    }
+    double v = s0 + s1;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) y[a.dint + I.bd0 + i] = b[I.bstart + i] - v;
+}
+
+__global__ __launch_bounds__(kBorderThreads) void k_sol_border(DevArgs a, double *x, double *y, int64_t lds_bytes,
+                                                               int add, int64_t bld, int64_t ys) {
+    extern __shared__ double c[];
+    x += blockIdx.y * bld;
+    y += blockIdx.y * ys;
     const InstDev &I = a.insts[blockIdx.x];
     const int64_t need = (int64_t(a.max_nbd) + int64_t(I.nbd) * (I.nbd + 1) / 2) * int64_t(sizeof(double));
-    if (need <= lds_bytes) sol_border<true>(a, I, c, b, x, y, cpart, add != 0);
-    else sol_border<false>(a, I, c, b, x, y, cpart, add != 0);
+    if (need <= lds_bytes) sol_border<true>(a, I, c, x, y, add != 0);
+    else sol_border<false>(a, I, c, x, y, add != 0);
 }
 
 // Backward (D L^T x = y).  One launch over every block column first takes
@@ -2914,8 +2910,10 @@ hipError_t launch(int kind, const DevArgs &a, const LaunchArgs &l, hipStream_t s
                                                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lb));
                     if (e != hipSuccess) return e;
                 }
+                hipLaunchKernelGGL(k_sol_bsum, dim3(unsigned((a.nbd_tot + 3) / 4), unsigned(l.nrhs)), dim3(256), 0, st, a, l.b,
+                                   l.y, l.cpart, l.bld, l.ys, l.cps);
                 hipLaunchKernelGGL(k_sol_border, dim3(unsigned(a.ninst), unsigned(l.nrhs)), dim3(kBorderThreads), lb, st, a,
-                                   l.b, l.x, l.y, l.cpart, int64_t(lb), l.accumulate ? 1 : 0, l.bld, l.ys, l.cps);
+                                   l.x, l.y, int64_t(lb), l.accumulate ? 1 : 0, l.bld, l.ys);
             }
             break;
         case NCL_K_SOL_BWD_BORDER:
