@@ -18,9 +18,13 @@ primal: vm[nb], va[nb], qg[ng], and with complementarity rows
         nu_plus[ng], nu_minus[ng], s_up[ng], s_lo[ng]
         (a single-block network also has pg[ng] after qg; in the
         complementarity base block vm at generator buses is absent: those
-        voltages are the border variables vm0)
+        voltages are the border variables vm0); with AGC rows a
+        contingency block then adds pgk[ng], pi_plus[ng], pi_minus[ng],
+        sp_up[ng], sp_lo[ng] and its adjustment delta[1]
 dual:   P[nb], Q[nb], Ffrom[nl], Fto[nl], and with complementarity rows
-        LIN[ng], DUP[ng], DLO[ng], CUP[ng], CLO[ng]
+        LIN[ng], DUP[ng], DLO[ng], CUP[ng], CLO[ng]; with AGC rows a
+        contingency block then adds ALIN[ng], ADUP[ng], ADLO[ng],
+        ACUP[ng], ACLO[ng]
 global: block 0 (base case), blocks 1..K (contingencies), then the border
         pg[ng] followed (complementarity only) by vm0[ng].  A screening
         network (first-stage pg and vm0 fixed) has the K contingency
@@ -37,9 +41,10 @@ import math
 import numpy as np
 
 # kind codes of layout positions
-VM, VA, QG, PG, NUP, NUM, SUP, SLO, VM0 = range(9)
+VM, VA, QG, PG, NUP, NUM, SUP, SLO, VM0, PGK, PIP, PIM, SPU, SPL, DELTA = range(15)
 ROW_P, ROW_Q, ROW_FF, ROW_FT, ROW_LIN, ROW_DUP, ROW_DLO, ROW_CUP, ROW_CLO = range(16, 25)
-PRIMAL_KINDS = (VM, VA, QG, PG, NUP, NUM, SUP, SLO, VM0)
+ROW_ALIN, ROW_ADUP, ROW_ADLO, ROW_ACUP, ROW_ACLO = range(25, 30)
+PRIMAL_KINDS = (VM, VA, QG, PG, NUP, NUM, SUP, SLO, VM0, PGK, PIP, PIM, SPU, SPL, DELTA)
 
 
 def rng(cfg: int, instance: int = 0, iteration: int = 0) -> np.random.Generator:
@@ -62,6 +67,8 @@ class Network:
     pvpq: bool            # complementarity (PV/PQ switching) rows present
     rho: float
     screen: bool = False  # contingency screening: first-stage pg (and vm0) fixed, blocks = contingencies
+    agc: bool = False     # AGC droop complementarity rows in the contingency blocks
+    gen_alpha: np.ndarray = None   # float64 [ng] participation factors (AGC only)
 
     @property
     def ncont(self) -> int:
@@ -173,9 +180,12 @@ def bridges(nb: int, f: np.ndarray, t: np.ndarray) -> np.ndarray:
 
 
 def make_network(cfg: int, nb: int, nl: int, ng: int, ncont: int, *, pvpq: bool = False,
-                 rho: float = 1e4, instance: int = 0, topology: str = "geo", screen: bool = False) -> Network:
+                 rho: float = 1e4, instance: int = 0, topology: str = "geo", screen: bool = False,
+                 agc: bool = False) -> Network:
     """Draw a network.  Draw order: topology, impedances, generators, costs,
-    outages."""
+    outages, and with AGC rows the participation factors alpha_g ~
+    U[0.5, 1.5] scaled to sum to 1 (drawn last, so the rest of the network
+    is that of the same seed without AGC)."""
     g = rng(cfg, instance, 0)
     if topology == "geo":
         f, t = _geo_topology(g, nb, nl)
@@ -196,7 +206,14 @@ def make_network(cfg: int, nb: int, nl: int, ng: int, ncont: int, *, pvpq: bool 
         outage = np.zeros(0, dtype=np.int32)
     if screen and ncont == 0:
         raise ValueError("screening needs contingencies")
-    return Network(nb, nl, ng, f, t, r, x, gen_bus, c2, outage, bool(pvpq), float(rho), bool(screen))
+    alpha = None
+    if agc:
+        if ncont == 0:
+            raise ValueError("AGC rows need contingencies")
+        alpha = g.uniform(0.5, 1.5, ng)
+        alpha = alpha / alpha.sum()
+    return Network(nb, nl, ng, f, t, r, x, gen_bus, c2, outage, bool(pvpq), float(rho), bool(screen),
+                   bool(agc), alpha)
 
 
 # ---------------------------------------------------------------- layout kinds
@@ -222,6 +239,10 @@ def block_kinds(net: Network, blk: int):
     if net.pvpq and net.cont_block(blk):
         for k in (NUP, NUM, SUP, SLO):
             add(k, range(ng))
+    if net.agc and net.cont_block(blk):
+        for k in (PGK, PIP, PIM, SPU, SPL):
+            add(k, range(ng))
+        add(DELTA, [0])
     nprim = len(kinds)
     add(ROW_P, range(nb))
     add(ROW_Q, range(nb))
@@ -229,6 +250,9 @@ def block_kinds(net: Network, blk: int):
     add(ROW_FT, range(nl))
     if net.pvpq and net.cont_block(blk):
         for k in (ROW_LIN, ROW_DUP, ROW_DLO, ROW_CUP, ROW_CLO):
+            add(k, range(ng))
+    if net.agc and net.cont_block(blk):
+        for k in (ROW_ALIN, ROW_ADUP, ROW_ADLO, ROW_ACUP, ROW_ACLO):
             add(k, range(ng))
     return np.array(kinds, np.int32), np.array(idx, np.int32), nprim
 
@@ -267,11 +291,16 @@ def draw_point(net: Network, cfg: int, instance: int = 0, iteration: int = 0):
     """One primal/dual state in layout order.
 
     Returns (z, sigma): z[N] holds primal values at primal positions and
-    multipliers at dual positions (the CUP/CLO rows hold nu0); sigma[N]
-    holds the barrier diagonal at primal positions and the complementarity
-    slack s at CUP/CLO rows (zero elsewhere).
+    multipliers at dual positions (the CUP/CLO and ACUP/ACLO rows hold
+    nu0); sigma[N] holds the barrier diagonal at primal positions and the
+    complementarity slack s at those rows (zero elsewhere).
 
-    Draw order: primal values by kind, multipliers, nu0 and s, Sigma.
+    Draw order: primal values by kind, multipliers, nu0 and s, Sigma; a
+    network with AGC rows then draws its AGC values (pgk ~ U[0, 1], the
+    four complementarity variables 10^U(-8, 0), delta ~ 0.1 N(0, 1), row
+    multipliers N(0, 1), nu0 10^U(-4, 2) and s 10^U(-8, 0)) after the
+    rest, so that the other values stay those of the same network without
+    them, except Sigma, whose draw covers every primal.
     """
     kind, _, _, _ = layout(net)
     g = rng(cfg, instance, 1000 + iteration)
@@ -300,6 +329,17 @@ def draw_point(net: Network, cfg: int, instance: int = 0, iteration: int = 0):
         sig[m] = 10.0 ** g.uniform(-8.0, 0.0, int(m.sum()))
     pm = is_primal(kind)
     sig[pm] = 10.0 ** g.uniform(-8.0, 8.0, int(pm.sum()))
+    if net.agc:
+        fill(PGK, lambda n: g.uniform(0.0, 1.0, n))
+        for k in (PIP, PIM, SPU, SPL):
+            fill(k, lambda n: 10.0 ** g.uniform(-8.0, 0.0, n))
+        fill(DELTA, lambda n: 0.1 * g.standard_normal(n))
+        for k in (ROW_ALIN, ROW_ADUP, ROW_ADLO):
+            fill(k, lambda n: g.standard_normal(n))
+        for k in (ROW_ACUP, ROW_ACLO):
+            fill(k, lambda n: 10.0 ** g.uniform(-4.0, 2.0, n))
+            m = kind == k
+            sig[m] = 10.0 ** g.uniform(-8.0, 0.0, int(m.sum()))
     return z, sig
 
 
@@ -313,10 +353,10 @@ def draw_trajectory_point(net: Network, cfg: int, iteration: int, z0: np.ndarray
     g = rng(cfg, 0, 5000 + iteration)
     pm = is_primal(kind)
     step = z0 + 0.01 * g.standard_normal(z0.shape[0])
-    lo = np.select([kind == VM, kind == VM0, kind == VA, kind == QG, kind == PG],
-                   [0.95, 0.95, -0.3, -0.5, 0.0], 1e-8)
-    hi = np.select([kind == VM, kind == VM0, kind == VA, kind == QG, kind == PG],
-                   [1.05, 1.05, 0.3, 0.5, 1.0], 1.0)
+    lo = np.select([kind == VM, kind == VM0, kind == VA, kind == QG, kind == PG, kind == PGK, kind == DELTA],
+                   [0.95, 0.95, -0.3, -0.5, 0.0, 0.0, -1.0], 1e-8)
+    hi = np.select([kind == VM, kind == VM0, kind == VA, kind == QG, kind == PG, kind == PGK, kind == DELTA],
+                   [1.05, 1.05, 0.3, 0.5, 1.0, 1.0, 1.0], 1.0)
     z[pm] = np.clip(step, lo, hi)[pm]
     return z, sig
 
@@ -348,7 +388,8 @@ def draw_ipm_point(net: Network, cfg: int, instance: int = 0, iteration: int = 0
     Bounds (the subproblem's data): vm and vm0 in [0.9, 1.1]; pg in [0, 8];
     qg in [-3, 3] in blocks without complementarity rows (in the others the
     DUP/DLO rows bound it through s_up, s_lo); the complementarity variables
-    >= 0; angles free.  Values strictly inside: z as draw_point gives it
+    (with AGC rows also pi+, pi-, sp_up, sp_lo) >= 0; angles free, and so
+    are pgk and delta (the ADUP/ADLO rows bound pgk).  Values strictly inside: z as draw_point gives it
     except the flow-row multipliers, 10^U(-3, 0) (> 0, they are inequality
     multipliers); slacks 10^U(-2, 1) on flow rows and draw_point's s on
     CUP/CLO rows; bound multipliers 10^U(-3, 1); rt ~ 1e-3 N(0, 1);
@@ -369,10 +410,10 @@ def draw_ipm_point(net: Network, cfg: int, instance: int = 0, iteration: int = 0
     comp_blk = np.array([net.pvpq and b >= 0 and net.cont_block(int(b)) for b in block])
     q = (kind == QG) & ~comp_blk
     lo[q], hi[q] = -3.0, 3.0
-    for k in (NUP, NUM, SUP, SLO):
+    for k in (NUP, NUM, SUP, SLO, PIP, PIM, SPU, SPL):
         lo[kind == k] = 0.0
     flow = (kind == ROW_FF) | (kind == ROW_FT)
-    comp = (kind == ROW_CUP) | (kind == ROW_CLO)
+    comp = (kind == ROW_CUP) | (kind == ROW_CLO) | (kind == ROW_ACUP) | (kind == ROW_ACLO)
     z[flow] = 10.0 ** g.uniform(-3.0, 0.0, int(flow.sum()))
     s = np.zeros(N)
     s[flow] = 10.0 ** g.uniform(-2.0, 1.0, int(flow.sum()))
@@ -402,6 +443,9 @@ CONFIGS = {
     # screening of the 500-bus x 256 grid's contingencies (the same grid and
     # outages: drawn with config 3's seed), first-stage variables fixed
     6: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, screen=True, seed_cfg=3),
+    # the 500-bus x 256 grid with AGC droop rows added to the PV/PQ rows of
+    # every contingency block (the same grid and outages: config 3's seed)
+    7: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, agc=True, seed_cfg=3),
 }
 
 
@@ -409,7 +453,8 @@ def config_network(cfg: int, **over) -> Network:
     p = dict(CONFIGS[cfg])
     p.update(over)
     return make_network(p.get("seed_cfg", cfg), p["nb"], p["nl"], p["ng"], p["ncont"], pvpq=p["pvpq"],
-                        rho=p["rho"], topology=p.get("topology", "geo"), screen=p.get("screen", False))
+                        rho=p["rho"], topology=p.get("topology", "geo"), screen=p.get("screen", False),
+                        agc=p.get("agc", False))
 
 
 def batched_networks(count: int = 64, cfg: int = 4):

@@ -36,6 +36,13 @@ Q_i likewise with qg; flow-limit rows h = P_so^2 + Q_so^2 at both ends;
 complementarity rows (PV/PQ switching, eq. pvpq):
 LIN_g = nu+ - nu- - v_i + v0_i, DUP_g = s_up - (qmax - qg),
 DLO_g = s_lo - (qg - qmin), CUP_g = nu- * s_up, CLO_g = nu+ * s_lo.
+AGC droop rows (eq. droopmpec) in a contingency block, when present: the
+block's own generation pgk replaces the first-stage pg in its P balance,
+and per generator ALIN_g = pi+ - pi- - pgk + pg_g + alpha_g delta (delta
+the block's one adjustment variable, alpha the participation factors),
+ADUP_g = sp_up - (pmax - pgk), ADLO_g = sp_lo - (pgk - pmin),
+ACUP_g = pi- * sp_up, ACLO_g = pi+ * sp_lo; the last two are
+complementarity rows like CUP and CLO (nu0 Hessian pair, s/nu0 in C).
 Objective phi = sum_g c2_g pg_g^2.
 
 Output: the lower triangle (row >= col) in layout order as COO arrays.
@@ -58,6 +65,7 @@ class Positions:
         self.nb, self.nl, self.ng = nb, nl, ng
         self.nblk = net.nblk
         self.pvpq = net.pvpq
+        self.agc = bool(getattr(net, "agc", False))
         self.single = net.single
         self.screen = bool(getattr(net, "screen", False))
         isgen = np.zeros(nb, bool)
@@ -71,6 +79,10 @@ class Positions:
         self.rowFf = np.zeros((self.nblk, nl), np.int64)
         self.rowFt = np.zeros((self.nblk, nl), np.int64)
         self.rowC = np.full((self.nblk, 5, ng), -1, np.int64)      # LIN, DUP, DLO, CUP, CLO
+        self.pgk = np.full((self.nblk, ng), -1, np.int64)
+        self.acomp = np.full((self.nblk, 4, ng), -1, np.int64)     # pi+, pi-, sp_up, sp_lo
+        self.delta = np.full(self.nblk, -1, np.int64)
+        self.rowA = np.full((self.nblk, 5, ng), -1, np.int64)      # ALIN, ADUP, ADLO, ACUP, ACLO
         self.pg = np.zeros(0 if self.screen else ng, np.int64)
         self.vm0 = np.full(ng, -1, np.int64)
         self.primal = []
@@ -96,6 +108,14 @@ class Positions:
                 for c in range(4):
                     self.comp[k, c] = off + np.arange(ng)
                     off += ng
+            if self.agc and cont:
+                self.pgk[k] = off + np.arange(ng)
+                off += ng
+                for c in range(4):
+                    self.acomp[k, c] = off + np.arange(ng)
+                    off += ng
+                self.delta[k] = off
+                off += 1
             nprim_end = off
             self.primal.append((self.block_off[-1], nprim_end))
             self.rowP[k] = off + np.arange(nb)
@@ -109,6 +129,10 @@ class Positions:
             if self.pvpq and cont:
                 for c in range(5):
                     self.rowC[k, c] = off + np.arange(ng)
+                    off += ng
+            if self.agc and cont:
+                for c in range(5):
+                    self.rowA[k, c] = off + np.arange(ng)
                     off += ng
         self.block_off.append(off)
         if not self.single and not self.screen:
@@ -230,8 +254,33 @@ def assemble(net, z, sigma, diag_shift=True):
         # generator columns of the balance rows
         gb = net.gen_bus.astype(np.int64)
         jac(pos.rowQ[k][gb], pos.qg[k], -1.0)
-        if not pos.screen:                       # screening: pg fixed, no column
+        agc_blk = pos.agc and (k > 0 or pos.screen)
+        if agc_blk:                              # the block's own generation
+            jac(pos.rowP[k][gb], pos.pgk[k], -1.0)
+        elif not pos.screen:                     # screening: pg fixed, no column
             jac(pos.rowP[k][gb], pos.pg, -1.0)
+        if agc_blk:
+            pip, pim, spu, spl = pos.acomp[k]
+            pgk = pos.pgk[k]
+            alin, adup, adlo, acup, aclo = pos.rowA[k]
+            jac(alin, pip, 1.0)
+            jac(alin, pim, -1.0)
+            jac(alin, pgk, -1.0)
+            if not pos.screen:                   # screening: pg fixed, no column
+                jac(alin, pos.pg, 1.0)
+            jac(alin, np.full(ng, pos.delta[k]), net.gen_alpha)
+            jac(adup, spu, 1.0)
+            jac(adup, pgk, 1.0)
+            jac(adlo, spl, 1.0)
+            jac(adlo, pgk, -1.0)
+            jac(acup, pim, z[spu])
+            jac(acup, spu, z[pim])
+            jac(aclo, pip, z[spl])
+            jac(aclo, spl, z[pip])
+            hess(pim, spu, z[acup])
+            hess(spu, pim, z[acup])
+            hess(pip, spl, z[aclo])
+            hess(spl, pip, z[aclo])
         if net.pvpq and (k > 0 or pos.screen):
             nup, num, sup, slo = pos.comp[k]
             lin, dup, dlo, cup, clo = pos.rowC[k]
@@ -290,14 +339,17 @@ def assemble(net, z, sigma, diag_shift=True):
     np.add.at(jsum, inv, jv)
     Jr, Jc = uk // N, uk % N
 
-    # dual diagonal: -1/rho, -(1/rho + s/nu0) on complementarity rows, and
+    # dual diagonal: -1/rho, -(1/rho + s/nu0) on complementarity rows (CUP,
+    # CLO, ACUP, ACLO), and
     # -(1/rho + sigma) on any other row with a nonzero sigma (an eliminated
     # inequality slack, block C)
     duals = np.flatnonzero(~pos.is_primal)
     ddiag = np.full(duals.shape[0], -1.0 / net.rho)
     cmask = np.zeros(duals.shape[0], bool)
-    if net.pvpq:
-        crow = pos.rowC[0 if pos.screen else 1:, 3:5].ravel()
+    c0 = 0 if pos.screen else 1
+    crow = np.concatenate([pos.rowC[c0:, 3:5].ravel() if pos.pvpq else np.zeros(0, np.int64),
+                           pos.rowA[c0:, 3:5].ravel() if pos.agc else np.zeros(0, np.int64)])
+    if crow.size:
         cmask = np.isin(duals, crow)
         ddiag[cmask] -= sigma[duals[cmask]] / z[duals[cmask]]
     ddiag[~cmask] -= sigma[duals[~cmask]]

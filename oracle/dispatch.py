@@ -59,8 +59,8 @@ class NLP:
 def residual(net, z, pd, p: NLP):
     """F(z; pd) and the diagonal Sigma (primal barrier Hessian + eps, dual
     flow-row mu/y^2) of the NCL subproblem, both in layout order."""
-    if net.pvpq:
-        raise ValueError("the dispatch map is defined for networks without PV/PQ rows")
+    if net.pvpq or getattr(net, "agc", False):
+        raise ValueError("the dispatch map is defined for networks without PV/PQ or AGC rows")
     pos = _asm.Positions(net)
     z = np.asarray(z)
     if not np.iscomplexobj(z):

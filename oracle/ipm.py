@@ -109,6 +109,8 @@ class Masks:
 def masks(net, prob: Problem) -> Masks:
     if getattr(net, "screen", False):
         raise ValueError("the IPM step is defined for corrective networks (pg is a variable)")
+    if getattr(net, "agc", False):
+        raise ValueError("the IPM step is defined for networks without AGC rows")
     pos = _asm.Positions(net)
     N = pos.N
     primal = pos.is_primal.copy()

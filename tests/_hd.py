@@ -67,6 +67,7 @@ def constraints_and_objective(net, var, extra):
     den = net.br_r ** 2 + net.br_x ** 2
     gs, bs = net.br_r / den, -net.br_x / den
     rows = []
+    agc = bool(getattr(net, "agc", False))
     for k in range(net.nblk):
         st = np.ones(nl)
         if k > 0:
@@ -99,7 +100,8 @@ def constraints_and_objective(net, var, extra):
                 Q = Q + vv * (G[i, j] * sn - B[i, j] * cs)
             for g in range(ng):
                 if net.gen_bus[g] == i:
-                    P = P - var("pg", k, g)
+                    # with AGC rows a contingency block has its own generation
+                    P = P - var("pgk" if agc and k > 0 else "pg", k, g)
                     Q = Q - var("qg", k, g)
             rows.append((("P", k, i), P))
             rows.append((("Q", k, i), Q))
@@ -126,6 +128,20 @@ def constraints_and_objective(net, var, extra):
                 rows.append((("DLO", k, g), HD.lift(slo) - var("qg", k, g)))
                 rows.append((("CUP", k, g), HD.lift(num) * sup))
                 rows.append((("CLO", k, g), HD.lift(nup) * slo))
+        if agc and k > 0:
+            # eq. (droopmpec): pi+ - pi- = p^k - (p^0 + alpha Delta), the two
+            # slacks (constants dropped: they do not enter derivatives) and
+            # the complementarity products pi- (pmax - p^k), pi+ (p^k - pmin)
+            dk = var("delta", k, 0)
+            for g in range(ng):
+                pip, pim = var("pip", k, g), var("pim", k, g)
+                spu, spl = var("spu", k, g), var("spl", k, g)
+                pk = var("pgk", k, g)
+                rows.append((("ALIN", k, g), HD.lift(pip) - pim - (HD.lift(pk) - (HD.lift(var("pg", 0, g)) + net.gen_alpha[g] * dk))))
+                rows.append((("ADUP", k, g), HD.lift(spu) + pk))
+                rows.append((("ADLO", k, g), HD.lift(spl) - pk))
+                rows.append((("ACUP", k, g), HD.lift(pim) * spu))
+                rows.append((("ACLO", k, g), HD.lift(pip) * spl))
     obj = HD(0.0)
     for g in range(ng):
         p = var("pg", 0, g)

@@ -23,6 +23,10 @@ def small_pvpq():
     return G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5)
 
 
+def small_agc(pvpq=True):
+    return G.make_network(99, 9, 12, 3, 2, pvpq=pvpq, rho=1e5, agc=True)
+
+
 def _positions(net):
     kind, index, block, _ = G.layout(net)
     pm = {}
@@ -40,13 +44,15 @@ def _positions(net):
             return pm[(G.PG, bb, i)]
         if name == "vm0":
             return pm[(G.VM0, -1, i)]
-        code = dict(va=G.VA, qg=G.QG, nup=G.NUP, num=G.NUM, sup=G.SUP, slo=G.SLO)[name]
+        code = dict(va=G.VA, qg=G.QG, nup=G.NUP, num=G.NUM, sup=G.SUP, slo=G.SLO, pgk=G.PGK, pip=G.PIP,
+                    pim=G.PIM, spu=G.SPU, spl=G.SPL, delta=G.DELTA)[name]
         return pm[(code, k, i)]
 
     def row_pos(key):
         name, k, i = key
         code = dict(P=G.ROW_P, Q=G.ROW_Q, Ff=G.ROW_FF, Ft=G.ROW_FT, LIN=G.ROW_LIN, DUP=G.ROW_DUP,
-                    DLO=G.ROW_DLO, CUP=G.ROW_CUP, CLO=G.ROW_CLO)[name]
+                    DLO=G.ROW_DLO, CUP=G.ROW_CUP, CLO=G.ROW_CLO, ALIN=G.ROW_ALIN, ADUP=G.ROW_ADUP,
+                    ADLO=G.ROW_ADLO, ACUP=G.ROW_ACUP, ACLO=G.ROW_ACLO)[name]
         return pm[(code, k, i)]
 
     return kind, var_pos, row_pos
@@ -85,10 +91,18 @@ def hd_jacobian_hessian(net, z):
     return J, H, prim
 
 
-@pytest.mark.parametrize("which", ["single", "pvpq"])
+NETS = {
+    "single": lambda: (G.config_network(1), 1),
+    "pvpq": lambda: (small_pvpq(), 99),
+    "agc": lambda: (small_agc(), 99),
+    "agc_plain": lambda: (small_agc(pvpq=False), 99),
+}
+
+
+@pytest.mark.parametrize("which", list(NETS))
 def test_jacobian_hessian_exact(which):
-    net = G.config_network(1) if which == "single" else small_pvpq()
-    z, sig = G.draw_point(net, 1 if which == "single" else 99)
+    net, cfg = NETS[which]()
+    z, sig = G.draw_point(net, cfg)
     r, c, v, pos = A.assemble(net, z, np.zeros_like(sig), diag_shift=False)
     K = A.to_dense(r, c, v, pos.N)
     J, H, prim = hd_jacobian_hessian(net, z)
@@ -100,16 +114,17 @@ def test_jacobian_hessian_exact(which):
     assert np.abs(Kj - J[np.ix_(~isp, isp)]).max() <= 1e-13 * max(1.0, np.abs(J).max())
 
 
-def test_dual_diagonal_and_comp_rows():
-    net = small_pvpq()
+@pytest.mark.parametrize("which", ["pvpq", "agc"])
+def test_dual_diagonal_and_comp_rows(which):
+    net, _ = NETS[which]()
     z, sig = G.draw_point(net, 99)
     r, c, v, pos = A.assemble(net, z, sig)
     K = A.to_dense(r, c, v, pos.N)
     kind, _, _, _ = G.layout(net)
     d = np.diag(K)
-    for k in range(16, 25):
+    for k in range(16, 30):
         m = kind == k
-        if k in (G.ROW_CUP, G.ROW_CLO):
+        if k in (G.ROW_CUP, G.ROW_CLO, G.ROW_ACUP, G.ROW_ACLO):
             np.testing.assert_allclose(d[m], -(1.0 / net.rho + sig[m] / z[m]), rtol=1e-15)
         else:
             np.testing.assert_allclose(d[m], -1.0 / net.rho, rtol=1e-15)
@@ -185,9 +200,9 @@ def test_two_bus_closed_form():
     assert abs(K[pos.rowQ[0][0], pos.vm[0][1]] - dQ0dv1) < 1e-14
 
 
-@pytest.mark.parametrize("which", ["c1", "pvpq"])
+@pytest.mark.parametrize("which", ["single", "pvpq", "agc", "agc_plain"])
 def test_quasi_definite(which):
-    net = G.config_network(1) if which == "c1" else small_pvpq()
+    net, _ = NETS[which]()
     z, sig = G.draw_point(net, 1)
     r, c, v, pos = A.assemble(net, z, sig)
     K = A.to_dense(r, c, v, pos.N)
@@ -203,8 +218,9 @@ def test_quasi_definite(which):
     assert (ev > 0).sum() == isp.sum() and (ev < 0).sum() == (~isp).sum()
 
 
-def test_union_pattern_is_value_independent():
-    net = small_pvpq()
+@pytest.mark.parametrize("which", ["pvpq", "agc"])
+def test_union_pattern_is_value_independent(which):
+    net, _ = NETS[which]()
     z1, s1 = G.draw_point(net, 99, iteration=0)
     z2, s2 = G.draw_point(net, 99, iteration=1)
     r1, c1, _, _ = A.assemble(net, z1, s1)
@@ -229,9 +245,9 @@ def test_screening_blocks_equal_contingency_blocks():
     of the corrective network on the same grid and outages (the part of K
     inside that block), at the same block state; the screening network has
     no base block and no border."""
-    for pvpq in (False, True):
-        full = G.make_network(41, 24, 33, 5, 3, pvpq=pvpq, rho=1e5)
-        scr = G.make_network(41, 24, 33, 5, 3, pvpq=pvpq, rho=1e5, screen=True)
+    for pvpq, agc in ((False, False), (True, False), (False, True), (True, True)):
+        full = G.make_network(41, 24, 33, 5, 3, pvpq=pvpq, rho=1e5, agc=agc)
+        scr = G.make_network(41, 24, 33, 5, 3, pvpq=pvpq, rho=1e5, screen=True, agc=agc)
         assert np.array_equal(full.outage, scr.outage) and scr.nblk == full.nblk - 1
         zf, sf = G.draw_point(full, 41)
         pf = A.Positions(full)

@@ -23,7 +23,8 @@ def small_pvpq():
 
 def nets():
     return [("c1", G.config_network(1)), ("pvpq", small_pvpq()),
-            ("c2small", G.make_network(2, 30, 41, 6, 4, rho=1e4))]
+            ("c2small", G.make_network(2, 30, 41, 6, 4, rho=1e4)),
+            ("agc", G.make_network(99, 9, 12, 3, 2, pvpq=False, rho=1e5, agc=True))]
 
 
 def _pattern(net):
