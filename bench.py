@@ -49,6 +49,8 @@ WORKLOADS = {
     5: "2000-bus synthetic grid x 64 branch-outage contingencies (N=907760), rho=1e4, FP64",
     6: "contingency screening of the 500-bus grid's 256 branch-outage contingencies with PV/PQ rows, "
        "first-stage variables fixed: 256 independent blocks, no border (N=1100800), rho=1e5, FP64",
+    7: "500-bus synthetic grid x 256 branch-outage contingencies with PV/PQ and AGC droop complementarity "
+       "rows (N=1335036), rho=1e5, FP64",
 }
 COPY_DOUBLES = 64 * 2 ** 20          # the plain copy whose counters calibrate FETCH_SIZE / WRITE_SIZE
 PROFILE_STRIDE = 7                   # one launch in 7 of the dominant kernel is event-timed in the timed region
@@ -344,7 +346,7 @@ def run_single(args):
                          f"1 thread; K assembled by numpy and the symbolic analysis done beforehand, untimed"}
 
     ipm = None
-    if not args.no_ipm and not getattr(net, "screen", False):
+    if not args.no_ipm and not getattr(net, "screen", False) and not getattr(net, "agc", False):
         ipm = ipm_steps(k, net, cfg, args.ipm_steps)
         print(f"[bench] IPM step: {ipm['ms_median']:.3f} ms median over {ipm['steps']} points, "
               f"{ipm['factorizations_mean']:.1f} factorisations each", file=sys.stderr, flush=True)

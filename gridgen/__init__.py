@@ -433,6 +433,49 @@ def draw_ipm_point(net: Network, cfg: int, instance: int = 0, iteration: int = 0
     return dict(lo=lo, hi=hi, z=z, rt=rt, s=s, zl=zl, zu=zu, y_n=y_n), pd
 
 
+def ncl_bounds(net: Network):
+    """Bounds of the NCL subproblem's variables, layout order (the problem's
+    data, as draw_ipm_point sets them): vm, vm0 in [0.9, 1.1]; pg in [0, 8];
+    qg in [-3, 3] in blocks without PV/PQ rows; the complementarity
+    variables >= 0; everything else free."""
+    kind, _, block, _ = layout(net)
+    N = kind.shape[0]
+    lo = np.full(N, -np.inf)
+    hi = np.full(N, np.inf)
+    for k in (VM, VM0):
+        lo[kind == k], hi[kind == k] = 0.9, 1.1
+    lo[kind == PG], hi[kind == PG] = 0.0, 8.0
+    comp_blk = np.array([net.pvpq and b >= 0 and net.cont_block(int(b)) for b in block])
+    q = (kind == QG) & ~comp_blk
+    lo[q], hi[q] = -3.0, 3.0
+    for k in (NUP, NUM, SUP, SLO, PIP, PIM, SPU, SPL):
+        lo[kind == k] = 0.0
+    return lo, hi
+
+
+def ncl_start(net: Network):
+    """A strictly interior start of the NCL solve, layout order (fixed
+    values, no draws): vm, vm0 = 1, va = 0, pg = 4, qg = 0; nu+, nu- = 1 and
+    s_up, s_lo = 3 (so that DUP and DLO hold at qg = 0); multipliers 0 on
+    equality rows and 1 on inequality rows (flow, CUP, CLO) with slacks 1;
+    rt = 0; bound multipliers 1 where the bound is finite."""
+    kind, _, _, _ = layout(net)
+    lo, hi = ncl_bounds(net)
+    N = kind.shape[0]
+    z = np.zeros(N)
+    z[(kind == VM) | (kind == VM0)] = 1.0
+    z[kind == PG] = 4.0
+    z[(kind == NUP) | (kind == NUM)] = 1.0
+    z[(kind == SUP) | (kind == SLO)] = 3.0
+    ineq = (kind == ROW_FF) | (kind == ROW_FT) | (kind == ROW_CUP) | (kind == ROW_CLO)
+    z[ineq] = 1.0
+    s = np.where(ineq, 1.0, 0.0)
+    pm = is_primal(kind)
+    zl = np.where(pm & np.isfinite(lo), 1.0, 0.0)
+    zu = np.where(pm & np.isfinite(hi), 1.0, 0.0)
+    return dict(lo=lo, hi=hi, z=z, rt=np.zeros(N), s=s, zl=zl, zu=zu)
+
+
 # ---------------------------------------------------------------- configurations
 
 CONFIGS = {

@@ -28,10 +28,18 @@
  *             with NCL_PVPQ the contingency blocks add nu_plus[ng],
  *             nu_minus[ng], s_up[ng], s_lo[ng], and the base block omits vm
  *             at generator buses (those voltages are the border vm0);
+ *             with NCL_AGC the contingency blocks then add pgk[ng] (their
+ *             own generation, which takes the place of pg in their P rows),
+ *             pi_plus[ng], pi_minus[ng], sp_up[ng], sp_lo[ng] and one
+ *             adjustment delta;
  *     dual:   P[nb], Q[nb], Ffrom[nl], Fto[nl]; with NCL_PVPQ the
  *             contingency blocks add LIN[ng], DUP[ng], DLO[ng], CUP[ng],
  *             CLO[ng] (eq. (pvpq): linear row, the two slack definitions and
- *             the two complementarity products);
+ *             the two complementarity products); with NCL_AGC they then add
+ *             ALIN[ng], ADUP[ng], ADLO[ng], ACUP[ng], ACLO[ng], the same five
+ *             rows of eq. (droopmpec): pi_plus - pi_minus - pgk + pg +
+ *             alpha_g delta, sp_up - (pmax - pgk), sp_lo - (pgk - pmin),
+ *             pi_minus sp_up and pi_plus sp_lo;
  *   blocks 0..K in order, then the border pg[ng] (and vm0[ng] with NCL_PVPQ).
  *   With NCL_SCREEN the blocks are the K contingencies alone, each with the
  *   contingency layout (pg and vm0 fixed, so neither a column nor a border).
@@ -84,18 +92,23 @@ enum {
 #define NCL_SCREEN 2u        /* contingency screening (eq. (screening)): the first-stage variables are
                                 fixed, so the blocks are the K contingencies alone, with no base case
                                 and no border; each block's KKT is that of its own feasibility problem */
+#define NCL_AGC 4u           /* AGC droop recourse (eq. (agc) as its complementarity form (droopmpec))
+                                in every contingency block; needs gen_alpha */
 
 /* Network topology and constants (host arrays, copied during analyze).
  * Branch l joins buses br_from[l] < br_to[l] with series impedance
  * br_r[l] + j br_x[l] (no shunts, no taps); generator g sits at bus
  * gen_bus[g] (distinct buses) with cost gen_c2[g] * pg^2; contingency k+1
  * (k = 0..ncont-1) removes branch outage[k] (a non-bridge branch).
- * Branches must be sorted by (from, to) without duplicates. */
+ * Branches must be sorted by (from, to) without duplicates.  gen_alpha[g]
+ * is the AGC participation factor of generator g (read only with NCL_AGC,
+ * which needs contingencies; finite values; NULL otherwise). */
 typedef struct {
     int32_t nbus, nbranch, ngen, ncont;
     const int32_t *br_from, *br_to, *gen_bus, *outage;
     const double *br_r, *br_x, *gen_c2;
     uint32_t flags;
+    const double *gen_alpha;
 } ncl_network;
 
 /* Options of the symbolic analysis (all zero / NULL: the defaults).
@@ -378,8 +391,8 @@ const char *ncl_status_string(int status);
  * block (bus 0's angle), balance rows c(w; pd) with loads pd (P) and
  * qd_ratio * pd (Q) in every block, flow rows h <= smax2 with an eliminated
  * slack t = mu / y.  Its Jacobian is the KKT matrix assembled with
- * NCL_NO_SHIFT and the sigma this call returns.  Networks with NCL_PVPQ are
- * rejected. */
+ * NCL_NO_SHIFT and the sigma this call returns.  Networks with NCL_PVPQ or
+ * NCL_AGC are rejected. */
 typedef struct {
     const double *pd;      /* DEVICE [nbus of the network] active loads */
     double qd_ratio;
@@ -390,10 +403,13 @@ typedef struct {
 /* Layout kinds (HOST out, [N]): for each global column, 1 vm, 2 va, 3 qg,
  * 4 pg, 5 P balance row, 6 Q balance row, 7 flow row, 8..11 the
  * complementarity variables nu_plus, nu_minus, s_up, s_lo, 12..16 the rows
- * LIN, DUP, DLO, CUP, CLO, 17 the border vm0. */
+ * LIN, DUP, DLO, CUP, CLO, 17 the border vm0, and with NCL_AGC 18 pgk,
+ * 19..22 pi_plus, pi_minus, sp_up, sp_lo, 23 delta, 24..28 the rows ALIN,
+ * ADUP, ADLO, ACUP, ACLO. */
 enum { NCL_L_OTHER = 0, NCL_L_VM, NCL_L_VA, NCL_L_QG, NCL_L_PG, NCL_L_ROWP, NCL_L_ROWQ, NCL_L_FLOW,
        NCL_L_NUP, NCL_L_NUM, NCL_L_SUP, NCL_L_SLO, NCL_L_LIN, NCL_L_DUP, NCL_L_DLO, NCL_L_CUP, NCL_L_CLO,
-       NCL_L_VM0 };
+       NCL_L_VM0, NCL_L_PGK, NCL_L_PIP, NCL_L_PIM, NCL_L_SPU, NCL_L_SPL, NCL_L_DELTA, NCL_L_ALIN,
+       NCL_L_ADUP, NCL_L_ADLO, NCL_L_ACUP, NCL_L_ACLO };
 int ncl_kkt_layout_kinds(const ncl_kkt *h, uint8_t *kinds);
 
 /* F (DEVICE [N]) = F(z; pd) and sigma (DEVICE [N]) = the barrier Hessian
@@ -495,8 +511,8 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const d
  *   d zl = (mu - (w - lo) zl - zl dw)/(w - lo)         (finite lo)
  *   d zu = (mu - (hi - w) zu + zu dw)/(hi - w)         (finite hi).
  * Handles of one network only: NCL_SCREEN networks (no pg variable),
- * batches of several networks and pattern handles are rejected
- * (NCL_ERR_ARG). */
+ * NCL_AGC networks, batches of several networks and pattern handles are
+ * rejected (NCL_ERR_ARG). */
 typedef struct {
     const double *pd;        /* DEVICE [nbus] active loads */
     const double *lo, *hi;   /* DEVICE [N] bounds at primal positions (-inf/+inf: none; dual rows ignored) */

@@ -181,7 +181,7 @@ struct WsLayout {
 
 struct Plan {
     std::vector<std::vector<size_t>> toff;   // per template, in TemplDev pointer order
-    std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x
+    std::vector<std::vector<size_t>> ioff;   // per instance: kbb_pos, border_pg, gen_c2, br_r, br_x, ..., gen_alpha
     size_t tdev = 0, bdev = 0, idev = 0, work = 0, bprim = 0, pg_col = 0, row_pq = 0, tables_end = 0;
     size_t kval = 0, lpan = 0, upan = 0, dval = 0, spart = 0, sbb = 0, lbb = 0, ybuf = 0, cpart = 0, zint = 0, sint = 0, stat = 0,
            xint = 0, bint = 0, rint = 0, rbuf = 0, epart = 0, total = 0;
@@ -219,7 +219,7 @@ std::vector<ncl::Work> all_work(Handle &h) {
 // Q rows of every bus in every block.
 void dispatch_tables(Handle &h, std::vector<int64_t> &pgc, std::vector<int64_t> &rows) {
     h.ng_disp = h.nbus_disp = 0;
-    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_PVPQ)) return;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & (NCL_PVPQ | NCL_AGC))) return;
     const ncl::Inst &I = h.inst[0];
     for (int b = I.blk0; b < I.blk0 + I.nblk; b++) {
         const Template &t = h.tmpl[h.block_tmpl[b]];
@@ -302,7 +302,7 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
         const ncl::Inst &I = h.inst[i];
         p.ioff[i] = {L.vec(I.kbb_pos), L.vec(I.border_pg), L.vec(I.gen_c2), L.vec(I.br_r), L.vec(I.br_x),
                      L.vec(I.kbr_ptr), L.vec(I.kbr_ent), L.vec(I.mdesc_ptr), L.vec(I.mdesc), L.vec(I.mitems),
-                     L.vec(I.bperm)};
+                     L.vec(I.bperm), L.vec(I.gen_alpha)};
         bprim.insert(bprim.end(), I.border_primal.begin(), I.border_primal.end());
     }
     p.bprim = L.vec(bprim);
@@ -858,12 +858,14 @@ int ncl_kkt_bind_workspace(ncl_kkt *k, void *dptr, size_t bytes, int32_t nrhs_ma
         d.br_r = reinterpret_cast<const double *>(base + p.ioff[t.inst][3]);
         d.br_x = reinterpret_cast<const double *>(base + p.ioff[t.inst][4]);
         d.gen_c2 = reinterpret_cast<const double *>(base + p.ioff[t.inst][2]);
+        d.gen_alpha = reinterpret_cast<const double *>(base + p.ioff[t.inst][11]);
         d.kbase = h.t_kbase[ti];
         d.lbase = h.t_lbase[ti];
         d.dbase = h.t_dbase[ti];
         d.nnz = int32_t(t.colptr[t.n]);
         d.pvpq_rows = t.pvpq_rows;
         d.has_pg_local = t.pg_local;
+        d.agc_rows = t.agc_rows;
         d.blocks = reinterpret_cast<const int32_t *>(at(0));
         d.sup_first = reinterpret_cast<const int32_t *>(at(1));
         d.sup_rowptr = reinterpret_cast<const int32_t *>(at(2));
@@ -1338,7 +1340,7 @@ static int nlp_check(const Handle &h, const ncl_nlp *p) {
     if (!p || !p->pd || !(p->mu > 0) || !(p->rho > 0) || !(p->vmax > p->vmin) || !(p->qmax > 0) || !(p->pmax > 0) ||
         !(p->smax2 > 0) || p->eps < 0)
         return NCL_ERR_ARG;
-    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & (NCL_PVPQ | NCL_SCREEN))) return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & (NCL_PVPQ | NCL_SCREEN | NCL_AGC))) return NCL_ERR_ARG;
     if (!h.bound) return NCL_ERR_STATE;
     return NCL_OK;
 }
@@ -1584,7 +1586,7 @@ static int ipm_check(const Handle &h, const ncl_ipm_problem *p, const ncl_ipm_st
     if (!(p->mu > 0) || !(p->rho > 0) || !(p->smax2 > 0) || !(p->qmax > 0) || !(p->eps >= 0) ||
         !std::isfinite(p->qd_ratio) || !std::isfinite(p->mu) || !std::isfinite(p->rho))
         return NCL_ERR_ARG;
-    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_SCREEN)) return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & (NCL_SCREEN | NCL_AGC))) return NCL_ERR_ARG;
     if (!h.bound) return NCL_ERR_STATE;
     return NCL_OK;
 }

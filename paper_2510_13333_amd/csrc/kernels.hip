@@ -508,6 +508,41 @@ __global__ __launch_bounds__(256) void k_assemble(DevArgs a, const double *__res
             put(cx, gs[GS_CUCU], -(irho + ss[cu] / n0u));
             put(cx, gs[GS_CLCL], -(irho + ss[cl] / n0l));
         }
+        if (T.agc_rows) {
+            // eq. (droopmpec): ALIN = pi+ - pi- - pgk + pg0 + alpha delta, the
+            // two slack rows, and the products pi- sp_up, pi+ sp_lo with their
+            // nu0 Hessian pairs; pgk and delta have no Hessian (no shift)
+            const double pip = zs[ix(gi[GI_PIP])], pim = zs[ix(gi[GI_PIM])];
+            const double spu = zs[ix(gi[GI_SPU])], spl = zs[ix(gi[GI_SPL])];
+            const int64_t au = ix(gi[GI_ACUP]), al = ix(gi[GI_ACLO]);
+            const double n0u = zs[au], n0l = zs[al];
+            put(cx, gs[GS_ALIN_PIP], 1.0);
+            put(cx, gs[GS_ALIN_PIM], -1.0);
+            put(cx, gs[GS_ALIN_PGK], -1.0);
+            put(cx, gs[GS_ALIN_PG0], 1.0);
+            put(cx, gs[GS_ALIN_DEL], cs(T.gen_alpha)[g]);
+            put(cx, gs[GS_ADUP_SPU], 1.0);
+            put(cx, gs[GS_ADUP_PGK], 1.0);
+            put(cx, gs[GS_ADLO_SPL], 1.0);
+            put(cx, gs[GS_ADLO_PGK], -1.0);
+            put(cx, gs[GS_ACUP_PIM], spu);
+            put(cx, gs[GS_ACUP_SPU], pim);
+            put(cx, gs[GS_ACLO_PIP], spl);
+            put(cx, gs[GS_ACLO_SPL], pip);
+            put(cx, gs[GS_H_PIM_SPU], n0u);
+            put(cx, gs[GS_H_PIP_SPL], n0l);
+            put(cx, gs[GS_PIPPIP], shift * fabs(n0l) + ss[ix(gi[GI_PIP])]);
+            put(cx, gs[GS_PIMPIM], shift * fabs(n0u) + ss[ix(gi[GI_PIM])]);
+            put(cx, gs[GS_SPUSPU], shift * fabs(n0u) + ss[ix(gi[GI_SPU])]);
+            put(cx, gs[GS_SPLSPL], shift * fabs(n0l) + ss[ix(gi[GI_SPL])]);
+            put(cx, gs[GS_PGKPGK], ss[ix(gi[GI_PG])]);
+            put(cx, gs[GS_AL], -(irho + ss[ix(gi[GI_ALIN])]));
+            put(cx, gs[GS_AU], -(irho + ss[ix(gi[GI_ADUP])]));
+            put(cx, gs[GS_AD], -(irho + ss[ix(gi[GI_ADLO])]));
+            put(cx, gs[GS_ACUACU], -(irho + ss[au] / n0u));
+            put(cx, gs[GS_ACLACL], -(irho + ss[al] / n0l));
+            if (gs[GS_DELDEL] >= 0) put(cx, gs[GS_DELDEL], ss[ix(gi[GI_DELTA])]);
+        }
     }
 }
 

@@ -2,8 +2,10 @@
 // pattern of K (lower triangle), and the tables the assembly kernel uses to
 // find where each value goes.  Structure of K follows the Newton system of
 // Section IV-B (blocks A, B, C) for the corrective SCOPF of Section II-B
-// with the PV/PQ complementarity rows of eq. (pvpq).
+// with the PV/PQ complementarity rows of eq. (pvpq) and the AGC droop rows
+// of eq. (droopmpec).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 
@@ -16,15 +18,24 @@ namespace {
 struct Net {
     int nb, nl, ng, K;
     const int32_t *f, *t, *gb, *out;
-    bool pvpq, screen;
+    bool pvpq, screen, agc;
 };
 
 // template kinds; the screening ones are contingency blocks whose first-stage
-// variables (pg, and vm0 with PV/PQ rows) are fixed, so they have no border
+// variables (pg, and vm0 with PV/PQ rows) are fixed, so they have no border.
+// Any contingency kind may also carry the AGC droop rows (TemplKind::agc).
 enum { T_SINGLE, T_PLAIN, T_PVPQ_BASE, T_PVPQ_CONT, T_SCREEN_PLAIN, T_SCREEN_PVPQ };
+
+struct TemplKind {
+    int kind;
+    bool agc;
+};
 
 struct Local {
     std::vector<int32_t> vm, va, qg, pg, nup, num, sup, slo, vm0, rP, rQ, rFf, rFt, rLin, rDup, rDlo, rCup, rClo;
+    // AGC rows: pg holds the block's own pgk and pg0 the first-stage pg
+    std::vector<int32_t> pg0, pip, pim, spu, spl, rAlin, rAdup, rAdlo, rAcup, rAclo;
+    int32_t delta = -1;
 };
 
 using PairList = std::vector<std::pair<int32_t, int32_t>>;   // (row, col), row >= col
@@ -36,14 +47,17 @@ void add_pair(PairList &tp, PairList &bp, int n, int32_t a, int32_t b) {
     else tp.emplace_back(r, c);
 }
 
-void layout(const Net &net, int kind, Local &L, int &n, int &nprim, std::vector<uint8_t> &isprim) {
+void layout(const Net &net, TemplKind tk, Local &L, int &n, int &nprim, std::vector<uint8_t> &isprim) {
     const int nb = net.nb, nl = net.nl, ng = net.ng;
+    const int kind = tk.kind;
+    const bool agc = tk.agc;
     std::vector<int> genat(nb, -1);
     for (int g = 0; g < ng; g++) genat[net.gb[g]] = g;
     const bool base_pvpq = kind == T_PVPQ_BASE, cont_pvpq = kind == T_PVPQ_CONT || kind == T_SCREEN_PVPQ;
     const bool screen = kind == T_SCREEN_PLAIN || kind == T_SCREEN_PVPQ;
-    nprim = (base_pvpq ? nb - ng : nb) + nb + ng + (kind == T_SINGLE ? ng : 0) + (cont_pvpq ? 4 * ng : 0);
-    int ndual = 2 * nb + 2 * nl + (cont_pvpq ? 5 * ng : 0);
+    nprim = (base_pvpq ? nb - ng : nb) + nb + ng + (kind == T_SINGLE ? ng : 0) + (cont_pvpq ? 4 * ng : 0) +
+            (agc ? 5 * ng + 1 : 0);
+    int ndual = 2 * nb + 2 * nl + (cont_pvpq ? 5 * ng : 0) + (agc ? 5 * ng : 0);
     n = nprim + ndual;
     const int bpg = n, bvm0 = n + ng;   // border local indices
     int k = 0;
@@ -64,16 +78,24 @@ void layout(const Net &net, int kind, Local &L, int &n, int &nprim, std::vector<
         for (int g = 0; g < ng; g++) L.pg[g] = screen ? -1 : bpg + g;
     }
     if (cont_pvpq) { seq(L.nup, ng); seq(L.num, ng); seq(L.sup, ng); seq(L.slo, ng); }
+    if (agc) {
+        L.pg0 = L.pg;
+        seq(L.pg, ng);
+        seq(L.pip, ng); seq(L.pim, ng); seq(L.spu, ng); seq(L.spl, ng);
+        L.delta = k++;
+    }
     L.vm0.resize(ng);
     for (int g = 0; g < ng; g++) L.vm0[g] = net.pvpq && !screen ? bvm0 + g : -1;
     seq(L.rP, nb); seq(L.rQ, nb); seq(L.rFf, nl); seq(L.rFt, nl);
     if (cont_pvpq) { seq(L.rLin, ng); seq(L.rDup, ng); seq(L.rDlo, ng); seq(L.rCup, ng); seq(L.rClo, ng); }
+    if (agc) { seq(L.rAlin, ng); seq(L.rAdup, ng); seq(L.rAdlo, ng); seq(L.rAcup, ng); seq(L.rAclo, ng); }
     isprim.assign(n, 0);
     for (int i = 0; i < nprim; i++) isprim[i] = 1;
 }
 
-void enumerate(const Net &net, int kind, const Local &L, int n, PairList &tp, PairList &bp) {
+void enumerate(const Net &net, TemplKind tk, const Local &L, int n, PairList &tp, PairList &bp) {
     const int nb = net.nb, nl = net.nl, ng = net.ng;
+    const int kind = tk.kind;
     for (int l = 0; l < nl; l++) {
         int f = net.f[l], t = net.t[l];
         int32_t V[4] = {L.vm[f], L.vm[t], L.va[f], L.va[t]};
@@ -115,7 +137,28 @@ void enumerate(const Net &net, int kind, const Local &L, int n, PairList &tp, Pa
             for (auto v : {L.nup[g], L.num[g], L.sup[g], L.slo[g], L.rLin[g], L.rDup[g], L.rDlo[g], L.rCup[g], L.rClo[g]})
                 add_pair(tp, bp, n, v, v);
         }
+        if (tk.agc) {
+            add_pair(tp, bp, n, L.rAlin[g], L.pip[g]);
+            add_pair(tp, bp, n, L.rAlin[g], L.pim[g]);
+            add_pair(tp, bp, n, L.rAlin[g], L.pg[g]);
+            add_pair(tp, bp, n, L.rAlin[g], L.pg0[g]);
+            add_pair(tp, bp, n, L.rAlin[g], L.delta);
+            add_pair(tp, bp, n, L.rAdup[g], L.spu[g]);
+            add_pair(tp, bp, n, L.rAdup[g], L.pg[g]);
+            add_pair(tp, bp, n, L.rAdlo[g], L.spl[g]);
+            add_pair(tp, bp, n, L.rAdlo[g], L.pg[g]);
+            add_pair(tp, bp, n, L.rAcup[g], L.pim[g]);
+            add_pair(tp, bp, n, L.rAcup[g], L.spu[g]);
+            add_pair(tp, bp, n, L.rAclo[g], L.pip[g]);
+            add_pair(tp, bp, n, L.rAclo[g], L.spl[g]);
+            add_pair(tp, bp, n, L.pim[g], L.spu[g]);
+            add_pair(tp, bp, n, L.pip[g], L.spl[g]);
+            for (auto v : {L.pg[g], L.pip[g], L.pim[g], L.spu[g], L.spl[g], L.rAlin[g], L.rAdup[g], L.rAdlo[g],
+                           L.rAcup[g], L.rAclo[g]})
+                add_pair(tp, bp, n, v, v);
+        }
     }
+    if (tk.agc) add_pair(tp, bp, n, L.delta, L.delta);
 }
 
 void to_csc(PairList &p, int ncol, std::vector<int64_t> &colptr, std::vector<int32_t> &rowind) {
@@ -146,8 +189,13 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
     if (!nw->br_from || !nw->br_to || !nw->br_r || !nw->br_x || (nw->ngen && (!nw->gen_bus || !nw->gen_c2)) ||
         (nw->ncont && !nw->outage)) { err = "null array"; return NCL_ERR_ARG; }
     Net net{nw->nbus, nw->nbranch, nw->ngen, nw->ncont, nw->br_from, nw->br_to, nw->gen_bus, nw->outage,
-            (nw->flags & NCL_PVPQ) != 0, (nw->flags & NCL_SCREEN) != 0};
+            (nw->flags & NCL_PVPQ) != 0, (nw->flags & NCL_SCREEN) != 0, (nw->flags & NCL_AGC) != 0};
     if (net.pvpq && net.K == 0) { err = "PV/PQ rows need contingencies"; return NCL_ERR_ARG; }
+    if (net.agc && net.K == 0) { err = "AGC rows need contingencies"; return NCL_ERR_ARG; }
+    if (net.agc && net.ng && !nw->gen_alpha) { err = "AGC rows need participation factors"; return NCL_ERR_ARG; }
+    if (net.agc)
+        for (int g = 0; g < net.ng; g++)
+            if (!std::isfinite(nw->gen_alpha[g])) { err = "participation factor not finite"; return NCL_ERR_ARG; }
     if (net.screen && net.K == 0) { err = "screening needs contingencies"; return NCL_ERR_ARG; }
     for (int l = 0; l < net.nl; l++) {
         if (net.f[l] < 0 || net.t[l] >= net.nb || net.f[l] >= net.t[l]) { err = "branch endpoints"; return NCL_ERR_ARG; }
@@ -180,20 +228,26 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
     I.nblk = net.screen ? net.K : net.K + 1;
     I.nbd = net.K == 0 || net.screen ? 0 : net.ng * (net.pvpq ? 2 : 1);
     I.gen_c2.assign(nw->gen_c2, nw->gen_c2 + net.ng);
+    if (net.agc) I.gen_alpha.assign(nw->gen_alpha, nw->gen_alpha + net.ng);
+    else I.gen_alpha.assign(net.ng, 0.0);
     I.br_r.assign(nw->br_r, nw->br_r + net.nl);
     I.br_x.assign(nw->br_x, nw->br_x + net.nl);
-    std::vector<int> kinds;
-    if (net.screen) kinds = {net.pvpq ? T_SCREEN_PVPQ : T_SCREEN_PLAIN};
-    else if (net.K == 0) kinds = {T_SINGLE};
-    else if (!net.pvpq) kinds = {T_PLAIN};
-    else kinds = {T_PVPQ_BASE, T_PVPQ_CONT};
+    std::vector<TemplKind> kinds;
+    if (net.screen) kinds = {{net.pvpq ? T_SCREEN_PVPQ : T_SCREEN_PLAIN, net.agc}};
+    else if (net.K == 0) kinds = {{T_SINGLE, false}};
+    else if (!net.pvpq) {
+        // the base and contingency blocks share one template unless the
+        // contingencies carry AGC rows
+        if (net.agc) kinds = {{T_PLAIN, false}, {T_PLAIN, true}};
+        else kinds = {{T_PLAIN, false}};
+    } else kinds = {{T_PVPQ_BASE, false}, {T_PVPQ_CONT, net.agc}};
     const int t0 = int(h.tmpl.size());
     I.t0 = t0;
     I.nt = int(kinds.size());
     h.tmpl.resize(t0 + kinds.size());
     for (int k = 0; k < I.nblk; k++) {
         // screening: block k is contingency k; otherwise block 0 is the base case
-        h.block_tmpl.push_back(t0 + (k > 0 && net.pvpq && !net.screen ? 1 : 0));
+        h.block_tmpl.push_back(t0 + (k > 0 && kinds.size() > 1 ? 1 : 0));
         h.block_outage.push_back(net.screen ? net.out[k] : k > 0 ? net.out[k - 1] : -1);
         h.block_inst.push_back(int32_t(h.inst.size() - 1));
     }
@@ -207,8 +261,9 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
         t.inst = int(h.inst.size()) - 1;
         t.n = n;
         t.nprim = nprim;
-        t.pvpq_rows = kinds[q] == T_PVPQ_CONT || kinds[q] == T_SCREEN_PVPQ;
-        t.pg_local = kinds[q] == T_SINGLE;
+        t.pvpq_rows = kinds[q].kind == T_PVPQ_CONT || kinds[q].kind == T_SCREEN_PVPQ;
+        t.pg_local = kinds[q].kind == T_SINGLE;
+        t.agc_rows = kinds[q].agc;
         PairList tp;
         enumerate(net, kinds[q], locs[q], n, tp, border_pairs);
         to_csc(tp, n, t.colptr, t.rowind);
@@ -337,6 +392,19 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
         kind(L.rDlo, LK_DLO);
         kind(L.rCup, LK_CUP);
         kind(L.rClo, LK_CLO);
+        if (t.agc_rows) {
+            kind(L.pg, LK_PGK);
+            kind(L.pip, LK_PIP);
+            kind(L.pim, LK_PIM);
+            kind(L.spu, LK_SPU);
+            kind(L.spl, LK_SPL);
+            kind({L.delta}, LK_DELTA);
+            kind(L.rAlin, LK_ALIN);
+            kind(L.rAdup, LK_ADUP);
+            kind(L.rAdlo, LK_ADLO);
+            kind(L.rAcup, LK_ACUP);
+            kind(L.rAclo, LK_ACLO);
+        }
         t.gen_idx.assign(size_t(ng) * GI_N, -1);
         t.gen_slot.assign(size_t(ng) * GS_N, -1);
         for (int g = 0; g < ng; g++) {
@@ -378,6 +446,37 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
                 gs[GS_DD] = slot(L.rDlo[g], L.rDlo[g]);
                 gs[GS_CUCU] = slot(L.rCup[g], L.rCup[g]);
                 gs[GS_CLCL] = slot(L.rClo[g], L.rClo[g]);
+            }
+            if (t.agc_rows) {
+                gi[GI_PIP] = L.pip[g]; gi[GI_PIM] = L.pim[g]; gi[GI_SPU] = L.spu[g]; gi[GI_SPL] = L.spl[g];
+                gi[GI_ALIN] = L.rAlin[g]; gi[GI_ADUP] = L.rAdup[g]; gi[GI_ADLO] = L.rAdlo[g];
+                gi[GI_ACUP] = L.rAcup[g]; gi[GI_ACLO] = L.rAclo[g]; gi[GI_DELTA] = L.delta;
+                gs[GS_ALIN_PIP] = slot(L.rAlin[g], L.pip[g]);
+                gs[GS_ALIN_PIM] = slot(L.rAlin[g], L.pim[g]);
+                gs[GS_ALIN_PGK] = slot(L.rAlin[g], L.pg[g]);
+                gs[GS_ALIN_PG0] = slot(L.rAlin[g], L.pg0[g]);
+                gs[GS_ALIN_DEL] = slot(L.rAlin[g], L.delta);
+                gs[GS_ADUP_SPU] = slot(L.rAdup[g], L.spu[g]);
+                gs[GS_ADUP_PGK] = slot(L.rAdup[g], L.pg[g]);
+                gs[GS_ADLO_SPL] = slot(L.rAdlo[g], L.spl[g]);
+                gs[GS_ADLO_PGK] = slot(L.rAdlo[g], L.pg[g]);
+                gs[GS_ACUP_PIM] = slot(L.rAcup[g], L.pim[g]);
+                gs[GS_ACUP_SPU] = slot(L.rAcup[g], L.spu[g]);
+                gs[GS_ACLO_PIP] = slot(L.rAclo[g], L.pip[g]);
+                gs[GS_ACLO_SPL] = slot(L.rAclo[g], L.spl[g]);
+                gs[GS_H_PIM_SPU] = slot(L.pim[g], L.spu[g]);
+                gs[GS_H_PIP_SPL] = slot(L.pip[g], L.spl[g]);
+                gs[GS_PIPPIP] = slot(L.pip[g], L.pip[g]);
+                gs[GS_PIMPIM] = slot(L.pim[g], L.pim[g]);
+                gs[GS_SPUSPU] = slot(L.spu[g], L.spu[g]);
+                gs[GS_SPLSPL] = slot(L.spl[g], L.spl[g]);
+                gs[GS_PGKPGK] = slot(L.pg[g], L.pg[g]);
+                gs[GS_AL] = slot(L.rAlin[g], L.rAlin[g]);
+                gs[GS_AU] = slot(L.rAdup[g], L.rAdup[g]);
+                gs[GS_AD] = slot(L.rAdlo[g], L.rAdlo[g]);
+                gs[GS_ACUACU] = slot(L.rAcup[g], L.rAcup[g]);
+                gs[GS_ACLACL] = slot(L.rAclo[g], L.rAclo[g]);
+                gs[GS_DELDEL] = g == 0 ? slot(L.delta, L.delta) : -1;
             }
         }
     }

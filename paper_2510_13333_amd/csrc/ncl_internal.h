@@ -95,11 +95,20 @@ enum GenSlot {
     GS_PPG, GS_QQG, GS_QGQG, GS_PGPG,
     GS_LIN_NUP, GS_LIN_NUM, GS_LIN_VM, GS_LIN_VM0, GS_DUP_SUP, GS_DUP_QG, GS_DLO_SLO, GS_DLO_QG,
     GS_CUP_NUM, GS_CUP_SUP, GS_CLO_NUP, GS_CLO_SLO, GS_H_NUM_SUP, GS_H_NUP_SLO,
-    GS_NUPNUP, GS_NUMNUM, GS_SUPSUP, GS_SLOSLO, GS_LL, GS_UU, GS_DD, GS_CUCU, GS_CLCL, GS_N
+    GS_NUPNUP, GS_NUMNUM, GS_SUPSUP, GS_SLOSLO, GS_LL, GS_UU, GS_DD, GS_CUCU, GS_CLCL,
+    // AGC droop rows (eq. droopmpec): ALIN x (pi+, pi-, pgk, pg0, delta), the
+    // slack rows, the complementarity products and their nu0 pairs, diagonals
+    GS_ALIN_PIP, GS_ALIN_PIM, GS_ALIN_PGK, GS_ALIN_PG0, GS_ALIN_DEL, GS_ADUP_SPU, GS_ADUP_PGK,
+    GS_ADLO_SPL, GS_ADLO_PGK, GS_ACUP_PIM, GS_ACUP_SPU, GS_ACLO_PIP, GS_ACLO_SPL, GS_H_PIM_SPU, GS_H_PIP_SPL,
+    GS_PIPPIP, GS_PIMPIM, GS_SPUSPU, GS_SPLSPL, GS_PGKPGK, GS_AL, GS_AU, GS_AD, GS_ACUACU, GS_ACLACL,
+    GS_DELDEL,                     // the block's delta diagonal (generator 0 only)
+    GS_N
 };
 // State index tables per bus / generator: layout-local positions (n + b for border refs).
 enum BusIdx { BI_VM, BI_VA, BI_P, BI_Q, BI_N };
-enum GenIdx { GI_BUS, GI_QG, GI_PG, GI_NUP, GI_NUM, GI_SUP, GI_SLO, GI_LIN, GI_DUP, GI_DLO, GI_CUP, GI_CLO, GI_VM0, GI_N };
+// With AGC rows GI_PG is the block's own generation pgk.
+enum GenIdx { GI_BUS, GI_QG, GI_PG, GI_NUP, GI_NUM, GI_SUP, GI_SLO, GI_LIN, GI_DUP, GI_DLO, GI_CUP, GI_CLO, GI_VM0,
+              GI_PIP, GI_PIM, GI_SPU, GI_SPL, GI_ALIN, GI_ADUP, GI_ADLO, GI_ACUP, GI_ACLO, GI_DELTA, GI_N };
 
 struct TemplDev {
     int32_t n, nsup, nblk, nbd;     // columns, supernodes, blocks using the template, its instance's border size
@@ -109,6 +118,7 @@ struct TemplDev {
     int32_t nnz;                   // K entries of one block
     int32_t pvpq_rows;             // this template has the complementarity rows
     int32_t has_pg_local;          // single-block network: pg inside the block
+    int32_t agc_rows;              // this template has the AGC droop rows
     int32_t inst;                  // instance (network) the template belongs to
     int32_t nbus, ngen;            // network sizes (assembly threads per block)
     int64_t abase;                 // first residual thread of the template
@@ -117,6 +127,7 @@ struct TemplDev {
     int64_t bd0;                   // the instance's border pivots / solution at dint + bd0
     const double *br_r, *br_x;     // the instance's branch data
     const double *gen_c2;
+    const double *gen_alpha;       // AGC participation factors (zeros without AGC rows)
     const int32_t *blocks;         // [nblk] global block ids
     // supernodes (block-local factor numbering; border rows are n + b)
     const int32_t *sup_first;      // [nsup+1]
@@ -164,9 +175,12 @@ struct TemplDev {
 // rows); the codes are those of NCL_L_* in the public header.
 enum LocalKind : uint8_t {
     LK_OTHER = 0, LK_VM, LK_VA, LK_QG, LK_PG, LK_ROWP, LK_ROWQ, LK_FLOW,
-    LK_NUP, LK_NUM, LK_SUP, LK_SLO, LK_LIN, LK_DUP, LK_DLO, LK_CUP, LK_CLO, LK_VM0
+    LK_NUP, LK_NUM, LK_SUP, LK_SLO, LK_LIN, LK_DUP, LK_DLO, LK_CUP, LK_CLO, LK_VM0,
+    LK_PGK, LK_PIP, LK_PIM, LK_SPU, LK_SPL, LK_DELTA, LK_ALIN, LK_ADUP, LK_ADLO, LK_ACUP, LK_ACLO
 };
-inline constexpr bool lk_primal(int k) { return (k >= LK_VM && k <= LK_PG) || (k >= LK_NUP && k <= LK_SLO) || k == LK_VM0; }
+inline constexpr bool lk_primal(int k) {
+    return (k >= LK_VM && k <= LK_PG) || (k >= LK_NUP && k <= LK_SLO) || (k >= LK_VM0 && k <= LK_DELTA);
+}
 
 // Per-instance (per-network) border data of a batch.
 struct InstDev {
@@ -213,6 +227,7 @@ struct Template {
     int nprim = 0;
     bool pvpq_rows = false;
     bool pg_local = false;
+    bool agc_rows = false;
     std::vector<int32_t> blocks;   // global ids of the blocks using this template
     // model tables (layout-local; border refs n + b)
     std::vector<int32_t> bus_idx, bus_slot, bus_adj_ptr, bus_adj, br_slot, br_idx, gen_idx, gen_slot, bus_gen;
@@ -275,6 +290,7 @@ struct Inst {
     int nb = 0, nl = 0, ng = 0;
     uint32_t flags = 0;
     std::vector<double> gen_c2, br_r, br_x;
+    std::vector<double> gen_alpha;       // [ng] AGC participation factors (zeros without AGC)
     std::vector<int32_t> border_pg;      // [ng] border index of pg_g (or -1)
     int blk0 = 0, nblk = 0;              // global block range
     int t0 = 0, nt = 0;                  // template range

@@ -18,6 +18,7 @@ _lib = None
 
 NCL_PVPQ = 1
 NCL_SCREEN = 2
+NCL_AGC = 4
 
 # kernel kinds (NCL_K_* of ncl_kkt.h), in enum order
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
@@ -40,7 +41,8 @@ class _Network(ctypes.Structure):
     _fields_ = [("nbus", ctypes.c_int32), ("nbranch", ctypes.c_int32), ("ngen", ctypes.c_int32),
                 ("ncont", ctypes.c_int32), ("br_from", ctypes.c_void_p), ("br_to", ctypes.c_void_p),
                 ("gen_bus", ctypes.c_void_p), ("outage", ctypes.c_void_p), ("br_r", ctypes.c_void_p),
-                ("br_x", ctypes.c_void_p), ("gen_c2", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+                ("br_x", ctypes.c_void_p), ("gen_c2", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("gen_alpha", ctypes.c_void_p)]
 
 
 class _Opts(ctypes.Structure):
@@ -198,10 +200,15 @@ def _network_struct(net, keep):
                 br_r=np.ascontiguousarray(net.br_r, np.float64),
                 br_x=np.ascontiguousarray(net.br_x, np.float64),
                 gen_c2=np.ascontiguousarray(net.gen_c2, np.float64))
+    agc = bool(getattr(net, "agc", False))
+    if agc:
+        arrs["gen_alpha"] = np.ascontiguousarray(net.gen_alpha, np.float64)
     keep.append(arrs)
+    flags = ((NCL_PVPQ if getattr(net, "pvpq", False) else 0) | (NCL_SCREEN if getattr(net, "screen", False) else 0) |
+             (NCL_AGC if agc else 0))
     return _Network(int(net.nb), int(net.nl), int(net.ng), int(arrs["outage"].shape[0]),
                     *[_np_ptr(arrs[k]) for k in ("br_from", "br_to", "gen_bus", "outage", "br_r", "br_x", "gen_c2")],
-                    (NCL_PVPQ if getattr(net, "pvpq", False) else 0) | (NCL_SCREEN if getattr(net, "screen", False) else 0))
+                    flags, _np_ptr(arrs["gen_alpha"]) if agc else None)
 
 
 class KKT:

@@ -165,6 +165,30 @@ def test_c5_shift_on_factors():
     run_case(G.config_network(5), 5, factors=True)
 
 
+@pytest.mark.parametrize("pvpq", [True, False])
+def test_agc_small(pvpq):
+    """AGC droop rows (eq. droopmpec) in the contingency blocks: the block's
+    own generation, pi+-, the two slacks and the adjustment column delta
+    (one entry per generator), with and without the PV/PQ rows."""
+    net = G.make_network(99, 9, 12, 3, 2, pvpq=pvpq, rho=1e5, agc=True)
+    run_case(net, 99, nrhs=2)
+
+
+def test_agc_screening():
+    """Screening with AGC rows: no pg0 column in ALIN, no border."""
+    net = G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True, agc=True)
+    k, _ = run_case(net, 43, nrhs=2)
+    assert k.instances[0]["nbd"] == 0
+
+
+def test_agc_full_size():
+    """The 500-bus x 256 grid with PV/PQ and AGC rows (5201-column
+    contingency blocks), two states, factors compared at the second."""
+    net = G.config_network(7)
+    k, _ = run_case(net, 7, factors=False)
+    run_case(net, 7, iteration=1, factors=True, k=k)
+
+
 def test_uniform_topology():
     net = G.make_network(32, 300, 420, 54, 12, pvpq=True, rho=1e5, topology="uniform")
     run_case(net, 32, nrhs=2)
@@ -272,13 +296,14 @@ def test_wrong_sign_pivot_reported():
     assert info["first_bad"] == wrong[0]
 
 
-@pytest.mark.parametrize("which", ["c1", "pvpq", "c2", "big_border", "c3"])
+@pytest.mark.parametrize("which", ["c1", "pvpq", "c2", "big_border", "c3", "agc"])
 def test_factor_solve_equals_factor_then_solve(which):
     """The combined call (the border factored on a second stream while the
     blocks' forward substitution runs) gives the bits of factor + solve."""
     nets = {"c1": lambda: (G.config_network(1), 1), "pvpq": lambda: (small_pvpq(), 99),
             "c2": lambda: (G.config_network(2), 2), "c3": lambda: (G.config_network(3), 3),
-            "big_border": lambda: (G.make_network(31, 1300, 1820, 230, 3, rho=1e4), 31)}
+            "big_border": lambda: (G.make_network(31, 1300, 1820, 230, 3, rho=1e4), 31),
+            "agc": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True), 99)}
     net, cfg = nets[which]()
     k = KKT(net).bind(nrhs_max=2)
     for it in range(2):

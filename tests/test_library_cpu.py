@@ -45,7 +45,8 @@ def test_symbolic_bit_exact_random_small(seed):
     ng = int(g.integers(2, max(3, nb // 4)))
     nl = int(nb - 1 + g.integers(2, nb // 2 + 3))
     pvpq = bool(seed % 2)
-    net = G.make_network(50 + seed, nb, nl, ng, int(g.integers(1, 5)), pvpq=pvpq, topology="uniform" if seed >= 2 else "geo")
+    net = G.make_network(50 + seed, nb, nl, ng, int(g.integers(1, 5)), pvpq=pvpq, topology="uniform" if seed >= 2 else "geo",
+                         agc=seed >= 2)
     _compare(KKT(net), O.Factor.from_network(net))
 
 
@@ -124,9 +125,17 @@ def test_symbolic_bit_exact_c5():
     _compare(KKT(net), O.Factor.from_network(net))
 
 
-@pytest.mark.parametrize("cfg", [1, 3])
+SMALL = {
+    1: lambda: G.config_network(1),
+    3: lambda: G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5),
+    7: lambda: G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True),
+    8: lambda: G.make_network(99, 9, 12, 3, 2, pvpq=False, rho=1e5, agc=True),
+}
+
+
+@pytest.mark.parametrize("cfg", list(SMALL))
 def test_pattern_matches_oracle(cfg):
-    net = G.config_network(cfg) if cfg == 1 else G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5)
+    net = SMALL[cfg]()
     k = KKT(net)
     z, s = G.draw_point(net, cfg)
     cp, ri, _, pos = O.kkt(net, z, s)
@@ -251,11 +260,11 @@ def test_profile_stride_arguments():
         k.profile_stride(0)
 
 
-@pytest.mark.parametrize("pvpq", [False, True])
-def test_screening_symbolic_matches_oracle(pvpq):
+@pytest.mark.parametrize("pvpq,agc", [(False, False), (True, False), (True, True)])
+def test_screening_symbolic_matches_oracle(pvpq, agc):
     """Screening networks (NCL_SCREEN): no border, the contingency blocks
     alone; pattern and symbolic analysis bit-exact with the oracle's."""
-    net = G.make_network(43, 60, 84, 9, 6, pvpq=pvpq, rho=1e5, screen=True)
+    net = G.make_network(43, 60, 84, 9, 6, pvpq=pvpq, rho=1e5, screen=True, agc=agc)
     z, s = G.draw_point(net, 43)
     cp, ri, v, pos = O.kkt(net, z, s)
     k = KKT(net)
@@ -269,16 +278,31 @@ def test_screening_symbolic_matches_oracle(pvpq):
     assert np.array_equal(sym["super_ptr"], F.sup)
 
 
-@pytest.mark.parametrize("pvpq", [False, True])
-def test_layout_kinds_match_the_layout(pvpq):
+@pytest.mark.parametrize("pvpq,agc", [(False, False), (True, False), (True, True), (False, True)])
+def test_layout_kinds_match_the_layout(pvpq, agc):
     """The kind codes the IPM kernels read (NCL_L_*) name every column as the
     documented layout does: balance and flow rows, the complementarity
-    variables and rows, the border pg and vm0."""
-    net = G.make_network(99, 9, 12, 3, 2, pvpq=pvpq, rho=1e5)
+    variables and rows, the border pg and vm0, the AGC variables and rows."""
+    net = G.make_network(99, 9, 12, 3, 2, pvpq=pvpq, rho=1e5, agc=agc)
     k = KKT(net)
     kinds = k.layout_kinds()
     gk, _, _, _ = G.layout(net)
     code = {G.VM: 1, G.VA: 2, G.QG: 3, G.PG: 4, G.ROW_P: 5, G.ROW_Q: 6, G.ROW_FF: 7, G.ROW_FT: 7,
             G.NUP: 8, G.NUM: 9, G.SUP: 10, G.SLO: 11, G.ROW_LIN: 12, G.ROW_DUP: 13, G.ROW_DLO: 14,
-            G.ROW_CUP: 15, G.ROW_CLO: 16, G.VM0: 17}
+            G.ROW_CUP: 15, G.ROW_CLO: 16, G.VM0: 17, G.PGK: 18, G.PIP: 19, G.PIM: 20, G.SPU: 21, G.SPL: 22,
+            G.DELTA: 23, G.ROW_ALIN: 24, G.ROW_ADUP: 25, G.ROW_ADLO: 26, G.ROW_ACUP: 27, G.ROW_ACLO: 28}
     assert np.array_equal(kinds, np.array([code[int(x)] for x in gk], np.uint8))
+
+
+def test_agc_network_checks():
+    """NCL_AGC needs contingencies and finite participation factors."""
+    bad = G.make_network(99, 9, 12, 3, 2, pvpq=False, rho=1e5, agc=True)
+    bad.gen_alpha = bad.gen_alpha.copy()
+    bad.gen_alpha[1] = np.nan
+    with pytest.raises(NclError):
+        KKT(bad)
+    single = G.make_network(1, 30, 41, 6, 0)
+    single.agc = True
+    single.gen_alpha = np.full(6, 1.0 / 6)
+    with pytest.raises(NclError):
+        KKT(single)
