@@ -346,10 +346,16 @@ def run_single(args):
                          f"1 thread; K assembled by numpy and the symbolic analysis done beforehand, untimed"}
 
     ipm = None
-    if not args.no_ipm and not getattr(net, "screen", False) and not getattr(net, "agc", False):
+    if not args.no_ipm and not getattr(net, "screen", False):
         ipm = ipm_steps(k, net, cfg, args.ipm_steps)
         print(f"[bench] IPM step: {ipm['ms_median']:.3f} ms median over {ipm['steps']} points, "
               f"{ipm['factorizations_mean']:.1f} factorisations each", file=sys.stderr, flush=True)
+
+    ncl = None
+    if not args.no_ncl and args.gpus == 1:
+        ncl = ncl_solve_run(args.ncl_config)
+        print(f"[bench] NCL solve: {ncl['s']:.3f} s, status {ncl['status']}, {ncl['outer']} outer / {ncl['inner']} "
+              f"inner iterations, {ncl['factorizations']} factorisations", file=sys.stderr, flush=True)
 
     disp = None
     if cfg == 5 and not args.no_dispatch:
@@ -400,6 +406,8 @@ def run_single(args):
         out["dispatch_map"] = disp
     if ipm is not None:
         out["ipm_step"] = ipm
+    if ncl is not None:
+        out["ncl_solve"] = ncl
     print(json.dumps(out), flush=True)
 
 
@@ -417,7 +425,7 @@ def ipm_steps(k, net, cfg, steps):
     pts = []
     for it in range(steps + 1):
         d, pd = G.draw_ipm_point(net, cfg, iteration=it)
-        prob = dict(pd=dev(pd), lo=dev(d["lo"]), hi=dev(d["hi"]), y_n=dev(d["y_n"]), qd_ratio=0.3, qmax=3.0,
+        prob = dict(pd=dev(pd), lo=dev(d["lo"]), hi=dev(d["hi"]), y_n=dev(d["y_n"]), qd_ratio=0.3, qmax=3.0, pmax=8.0,
                     smax2=100.0, eps=1.0, mu=0.1, rho=net.rho)
         pts.append((prob, {n: dev(d[n]) for n in ("z", "rt", "s", "zl", "zu")}))
     dirs = {n: torch.empty(N, dtype=torch.float64, device="cuda") for n in ("dz", "drt", "ds", "dzl", "dzu")}
@@ -440,6 +448,49 @@ def ipm_steps(k, net, cfg, steps):
             "steps": steps, "ms_median": float(np.median(ms)), "ms_min": float(ms.min()),
             "factorizations_mean": float(np.mean(nf)), "factorizations": nf,
             "ms_per_factorization": float(np.median(ms / np.array(nf))), "shifts": dws}
+
+
+NCL_LOAD_SCALE = 0.1     # the NCL workload's loads: this fraction of the seeded pd
+
+
+def ncl_solve_run(cfg):
+    """The NCL method end to end (ncl_kkt_ncl_solve) on config cfg's network
+    (the 500-bus x 256 grid with PV/PQ and AGC droop rows): from the fixed
+    interior start, loads NCL_LOAD_SCALE x the seeded pd, the network's rho
+    as the first penalty, tolerance 1e-6 and smallest barrier parameter 1e-7
+    (Section V); wall clock of the whole solve, the analysis before it
+    untimed.  One warm-up solve of the same problem first."""
+    import torch
+    import gridgen as G
+    from paper_2510_13333_amd import KKT
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).to("cuda")
+    net = G.config_network(cfg)
+    t0 = time.perf_counter()
+    k = KKT(net).bind(nrhs_max=1)
+    t_an = time.perf_counter() - t0
+    st0 = G.ncl_start(net)
+    pd = NCL_LOAD_SCALE * G.draw_loads(net, cfg)
+    prob = dict(pd=dev(pd), lo=dev(st0["lo"]), hi=dev(st0["hi"]), qd_ratio=0.3, qmax=3.0, pmax=8.0, smax2=100.0,
+                eps=1.0, rho=net.rho)
+    work = torch.empty(17 * k.N + 64, dtype=torch.float64, device="cuda")
+
+    def run():
+        state = {n: dev(st0[n]) for n in ("z", "rt", "s", "zl", "zu")}
+        state["y_n"] = torch.zeros(k.N, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rep = k.ncl_solve(prob, state, work=work)
+        torch.cuda.synchronize()
+        return rep, time.perf_counter() - t
+
+    run()
+    rep, t = run()
+    return {"what": "the NCL method end to end (outer multiplier / penalty updates around the subproblem's "
+                    "primal-dual IPM, every step on the GPU) on " + WORKLOADS[cfg] + f", loads {NCL_LOAD_SCALE} x "
+                    "the seeded pd, from the fixed interior start; tol 1e-6, smallest mu 1e-7",
+            "N": k.N, "s": t, "status": rep["status"], "outer": rep["outer"], "inner": rep["inner"],
+            "factorizations": rep["factorizations"], "ms_per_inner": 1e3 * t / max(1, rep["inner"]),
+            "rho": rep["rho"], "r_inf": rep["r_inf"], "kkt_err": rep["kkt_err"], "analyze_s": t_an}
 
 
 def dispatch_backward(net, steps):
@@ -666,6 +717,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-dispatch", action="store_true", help="skip the dispatch-map backward timing (config 5)")
     ap.add_argument("--no-ipm", action="store_true", help="skip the IPM-step timing")
+    ap.add_argument("--no-ncl", action="store_true", help="skip the NCL-solve timing")
+    ap.add_argument("--ncl-config", type=int, default=7, help="network of the NCL-solve timing")
     ap.add_argument("--ipm-steps", type=int, default=5, help="interior points of the IPM-step timing")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default=None)

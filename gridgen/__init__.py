@@ -453,23 +453,30 @@ def ncl_bounds(net: Network):
     return lo, hi
 
 
-def ncl_start(net: Network):
-    """A strictly interior start of the NCL solve, layout order (fixed
-    values, no draws): vm, vm0 = 1, va = 0, pg = 4, qg = 0; nu+, nu- = 1 and
-    s_up, s_lo = 3 (so that DUP and DLO hold at qg = 0); multipliers 0 on
-    equality rows and 1 on inequality rows (flow, CUP, CLO) with slacks 1;
-    rt = 0; bound multipliers 1 where the bound is finite."""
+def ncl_start(net: Network, smax2: float = 100.0, mu0: float = 0.1):
+    """A strictly interior, centred start of the NCL solve, layout order
+    (fixed values, no draws), at the flat voltage profile where every branch
+    flow is zero: vm, vm0 = 1, va = 0, pg = 4, qg = 0; nu+, nu- = 0.01 and
+    s_up, s_lo = 3 (DUP and DLO hold at qg = 0); with AGC rows pgk = 4,
+    pi+, pi- = 0.01, sp_up, sp_lo = 4, delta = 0 (ALIN, ADUP and ADLO
+    hold); flow-row slacks smax2 (the flow rows hold at zero flow), the
+    other inequality rows' slacks 1, and every inequality row's multiplier
+    mu0 / s (each product s y starts at mu0); multipliers 0 on equality
+    rows; rt = 0; bound multipliers 1 where the bound is finite."""
     kind, _, _, _ = layout(net)
     lo, hi = ncl_bounds(net)
     N = kind.shape[0]
     z = np.zeros(N)
     z[(kind == VM) | (kind == VM0)] = 1.0
-    z[kind == PG] = 4.0
-    z[(kind == NUP) | (kind == NUM)] = 1.0
+    z[(kind == PG) | (kind == PGK)] = 4.0
+    z[(kind == NUP) | (kind == NUM) | (kind == PIP) | (kind == PIM)] = 0.01
     z[(kind == SUP) | (kind == SLO)] = 3.0
-    ineq = (kind == ROW_FF) | (kind == ROW_FT) | (kind == ROW_CUP) | (kind == ROW_CLO)
-    z[ineq] = 1.0
-    s = np.where(ineq, 1.0, 0.0)
+    z[(kind == SPU) | (kind == SPL)] = 4.0
+    flow = (kind == ROW_FF) | (kind == ROW_FT)
+    comp = (kind == ROW_CUP) | (kind == ROW_CLO) | (kind == ROW_ACUP) | (kind == ROW_ACLO)
+    s = np.where(flow, smax2, np.where(comp, 1.0, 0.0))
+    ineq = flow | comp
+    z[ineq] = mu0 / s[ineq]
     pm = is_primal(kind)
     zl = np.where(pm & np.isfinite(lo), 1.0, 0.0)
     zu = np.where(pm & np.isfinite(hi), 1.0, 0.0)

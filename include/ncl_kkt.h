@@ -490,7 +490,12 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const d
  * c: P_i = sum of branch-end P leaving bus i - pg at i + pd_i; Q_i likewise
  * with qg and qd_ratio pd_i; flow rows P^2 + Q^2 - smax2 at both ends;
  * LIN = nu_plus - nu_minus - vm_i + vm0_g, DUP = s_up - (qmax - qg),
- * DLO = s_lo - (qg + qmax), CUP = nu_minus s_up, CLO = nu_plus s_lo.  The
+ * DLO = s_lo - (qg + qmax), CUP = nu_minus s_up, CLO = nu_plus s_lo; with
+ * NCL_AGC the contingency blocks' P rows take their own pgk, and
+ * ALIN = pi_plus - pi_minus - pgk + pg + alpha_g delta,
+ * ADUP = sp_up - (pmax - pgk), ADLO = sp_lo - pgk (pmin = 0),
+ * ACUP = pi_minus sp_up, ACLO = pi_plus sp_lo, ACUP/ACLO inequality rows
+ * like CUP/CLO.  The
  * slack of an inequality row has the row multiplier as its bound
  * multiplier (S V0 = mu e for the complementarity rows; the flow rows take
  * the same form).  Unknowns: w and y (the state vector z), the
@@ -499,7 +504,8 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const d
  * equations leaves eq. (newtonsystem), K [dw; dy] = [r1; r2], where K is
  * the assembled matrix (NCL_NO_SHIFT) at
  *   sigma = zl/(w - lo) + zu/(hi - w) (+ eps at the reference angles) on
- *   primal positions, s on CUP/CLO rows, s/y on flow rows, 0 elsewhere,
+ *   primal positions, s on CUP/CLO (ACUP/ACLO) rows, s/y on flow rows, 0
+ *   elsewhere,
  * and
  *   r1 = -(grad phi + J' y) + mu/(w - lo) - mu/(hi - w)
  *   r2 = -c(w) + (y - y_n)/rho - [inequality row] mu/y.
@@ -511,13 +517,13 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const d
  *   d zl = (mu - (w - lo) zl - zl dw)/(w - lo)         (finite lo)
  *   d zu = (mu - (hi - w) zu + zu dw)/(hi - w)         (finite hi).
  * Handles of one network only: NCL_SCREEN networks (no pg variable),
- * NCL_AGC networks, batches of several networks and pattern handles are
- * rejected (NCL_ERR_ARG). */
+ * batches of several networks and pattern handles are rejected
+ * (NCL_ERR_ARG), and so are qmax, pmax or smax2 <= 0. */
 typedef struct {
     const double *pd;        /* DEVICE [nbus] active loads */
     const double *lo, *hi;   /* DEVICE [N] bounds at primal positions (-inf/+inf: none; dual rows ignored) */
     const double *y_n;       /* DEVICE [N] multiplier estimates lam_n, nu0_n at dual rows */
-    double qd_ratio, qmax, smax2, eps;
+    double qd_ratio, qmax, pmax, smax2, eps;
     double mu, rho;
 } ncl_ipm_problem;
 
@@ -580,6 +586,53 @@ int ncl_kkt_factor_inertia(ncl_kkt *h, const double *dz, const double *dsigma, d
  * doubles.  Errors as ncl_kkt_factor_inertia. */
 int ncl_kkt_ipm_step(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *s, const ncl_ipm_direction *d,
                      ncl_inertia_opts *o, double *dwork, void *stream);
+
+/* ---------------------------------------------------------------- NCL solve
+ * The NCL method end to end (Section IV-A): outer iterations update the
+ * penalty rho and the multiplier estimates y_n from the solution of the
+ * subproblem eq. (nclsubpb), which inner iterations solve with the
+ * primal-dual IPM above, warm-started from the previous point.  Section V
+ * fixes tol = 1e-6 and the smallest barrier parameter 1e-7; the paper
+ * defers the update rules, and these are the library's:
+ *   outer: solve the subproblem; r_inf = max |rt| over the dual rows;
+ *     r_inf <= tol: converged; r_inf <= eta: y_n = y at the dual rows (the
+ *     first-order update y_n + rho r) and eta = max(eta / eta_shrink, tol);
+ *     otherwise rho = min(rho_grow rho, rho_max); the next subproblem
+ *     starts at mu_warm (the first at mu0);
+ *   inner: E0 = max |G| at mu = 0 (G the barrier KKT residual of
+ *     ncl_kkt_ipm_step's unknowns, largest component magnitude); stop at
+ *     E0 <= tol; while max |G| at mu <= kappa_eps mu and mu > mu_min, mu =
+ *     max(mu_min, min(kappa_mu mu, mu^theta_mu)); an inertia-corrected
+ *     Newton direction (ncl_kkt_ipm_step); fraction to the boundary with
+ *     tau = max(tau_min, 1 - mu): alpha_p keeps w within its bounds and the
+ *     slacks s, alpha_d keeps zl, zu and y at inequality rows, each above
+ *     (1 - tau) of its value; w, y at equality rows, rt and s move by
+ *     alpha_p, zl, zu and y at inequality rows by alpha_d.
+ * p: the subproblem data as for ncl_kkt_ipm_step; p->rho is the first
+ * penalty; p->y_n and p->mu are not read.  s: DEVICE [N] arrays, in: a
+ * strictly interior start and the first y_n; out: the last iterate and
+ * y_n.  dwork: DEVICE 17 N + 64 doubles.  Synchronises the stream several
+ * times per inner iteration (it reads the inertia, the error norms and the
+ * step lengths).  Returns NCL_OK with rep->status 0 (converged), 1 (outer
+ * limit) or 2 (inner limit); numerical failures of a step as
+ * ncl_kkt_ipm_step (rep then holds the counts so far). */
+typedef struct {
+    double tol, mu_min;                 /* 1e-6, 1e-7 */
+    double mu0, mu_warm;                /* 0.1, 1e-5 */
+    double kappa_eps, kappa_mu, theta_mu, tau_min;   /* 10, 0.2, 1.5, 0.99 */
+    double eta0, eta_shrink;            /* 1e-2, 10 */
+    double rho_grow, rho_max;           /* 10, 1e12 */
+    int32_t max_inner, max_outer;       /* per subproblem 300, 30 */
+} ncl_solve_opts;
+typedef struct {
+    int32_t status, outer, inner, factorizations;
+    double rho, mu, r_inf, kkt_err;     /* at the last iterate (kkt_err = E0) */
+} ncl_solve_report;
+typedef struct {
+    double *z, *rt, *s, *zl, *zu, *y_n;
+} ncl_solve_state;
+int ncl_kkt_ncl_solve(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_solve_state *s, const ncl_solve_opts *o,
+                      ncl_solve_report *rep, double *dwork, void *stream);
 
 /* ---------------------------------------------------------------- measurement
  * Kernel kinds: every launch of the library runs exactly one kernel of one

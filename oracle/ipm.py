@@ -24,7 +24,12 @@ Constraint values c(w) (loads pd on P rows, qd_ratio pd on Q rows):
     Q_i = sum of Q_so over branch ends at bus i - qg at i + qd_ratio pd_i
     F   = P_so^2 + Q_so^2 - smax2               (each branch end)
     LIN = nu+ - nu- - vm_i + vm0_g,   DUP = s_up - (qmax - qg),
-    DLO = s_lo - (qg + qmax),         CUP = nu- s_up,   CLO = nu+ s_lo.
+    DLO = s_lo - (qg + qmax),         CUP = nu- s_up,   CLO = nu+ s_lo,
+and with AGC rows (eq. (droopmpec); the block's own pgk then takes the
+place of pg in its P rows, and pmin = 0, the lower bound of pg):
+    ALIN = pi+ - pi- - pgk + pg + alpha delta,   ADUP = sp_up - (pmax - pgk),
+    ADLO = sp_lo - (pgk - pmin),   ACUP = pi- sp_up,   ACLO = pi+ sp_lo.
+ACUP and ACLO are inequality rows like CUP and CLO.
 
 Barrier form of the KKT conditions (eq. (kktncl); the complementarity
 conditions replaced by their mu-perturbed products as Section IV-B
@@ -76,6 +81,7 @@ class Problem:
     rho: float = 1e5
     qd_ratio: float = 0.3
     qmax: float = 3.0
+    pmax: float = 8.0
     smax2: float = 100.0
     eps: float = 1.0
 
@@ -97,8 +103,8 @@ class State:
 class Masks:
     primal: np.ndarray
     dual: np.ndarray
-    ineq: np.ndarray                    # flow rows and CUP/CLO rows
-    comp: np.ndarray                    # CUP/CLO rows
+    ineq: np.ndarray                    # flow rows and CUP/CLO (ACUP/ACLO) rows
+    comp: np.ndarray                    # CUP/CLO (ACUP/ACLO) rows
     flow: np.ndarray
     has_lo: np.ndarray
     has_hi: np.ndarray
@@ -109,8 +115,6 @@ class Masks:
 def masks(net, prob: Problem) -> Masks:
     if getattr(net, "screen", False):
         raise ValueError("the IPM step is defined for corrective networks (pg is a variable)")
-    if getattr(net, "agc", False):
-        raise ValueError("the IPM step is defined for networks without AGC rows")
     pos = _asm.Positions(net)
     N = pos.N
     primal = pos.is_primal.copy()
@@ -121,10 +125,10 @@ def masks(net, prob: Problem) -> Masks:
         flow[pos.rowFf[k]] = True
         flow[pos.rowFt[k]] = True
         vref[pos.va[k][0]] = True
-        rc = pos.rowC[k]
-        if rc[3][0] >= 0:
-            comp[rc[3]] = True
-            comp[rc[4]] = True
+        for rc in (pos.rowC[k], pos.rowA[k]):
+            if rc[3][0] >= 0:
+                comp[rc[3]] = True
+                comp[rc[4]] = True
     lo, hi = np.asarray(prob.lo), np.asarray(prob.hi)
     return Masks(primal=primal, dual=~primal, ineq=flow | comp, comp=comp, flow=flow,
                  has_lo=primal & np.isfinite(lo), has_hi=primal & np.isfinite(hi), vref=vref, pos=pos)
@@ -168,7 +172,9 @@ def constraints(net, z, prob: Problem, m: Masks = None):
             np.add.at(Qinj, s_bus, Q)
             c[rowF] = P * P + Q * Q - prob.smax2
         qg = z[pos.qg[k]]
-        np.add.at(Pinj, gb, -pg)
+        agc = pos.pgk[k][0] >= 0
+        pgk = z[pos.pgk[k]] if agc else pg
+        np.add.at(Pinj, gb, -pgk)
         np.add.at(Qinj, gb, -qg)
         c[pos.rowP[k]] = Pinj + prob.pd
         c[pos.rowQ[k]] = Qinj + prob.qd_ratio * prob.pd
@@ -180,6 +186,14 @@ def constraints(net, z, prob: Problem, m: Masks = None):
             c[dlo] = slo - (qg + prob.qmax)
             c[cup] = num * sup
             c[clo] = nup * slo
+        if agc:
+            alin, adup, adlo, acup, aclo = pos.rowA[k]
+            pip, pim, spu, spl = (z[i] for i in pos.acomp[k])
+            c[alin] = pip - pim - pgk + pg + net.gen_alpha * z[pos.delta[k]]
+            c[adup] = spu - (prob.pmax - pgk)
+            c[adlo] = spl - pgk
+            c[acup] = pim * spu
+            c[aclo] = pip * spl
     return c
 
 
@@ -215,7 +229,19 @@ def grad_lagrangian(net, z, prob: Problem, m: Masks = None):
             var = np.stack([vm_p[s_bus], vm_p[o_bus], va_p[s_bus], va_p[o_bus]], 1)
             np.add.at(gL, var, yP[s_bus][:, None] * dP + yQ[s_bus][:, None] * dQ + yF[:, None] * dh)
         np.add.at(gL, pos.qg[k], -yQ[gb])
-        np.add.at(gL, pos.pg, -yP[gb])
+        agc = pos.pgk[k][0] >= 0
+        np.add.at(gL, pos.pgk[k] if agc else pos.pg, -yP[gb])
+        if agc:
+            alin, adup, adlo, acup, aclo = pos.rowA[k]
+            ipip, ipim, ispu, ispl = pos.acomp[k]
+            ya, yu, yd, ycu, ycl = z[alin], z[adup], z[adlo], z[acup], z[aclo]
+            np.add.at(gL, ipip, ya + ycl * z[ispl])
+            np.add.at(gL, ipim, -ya + ycu * z[ispu])
+            np.add.at(gL, ispu, yu + ycu * z[ipim])
+            np.add.at(gL, ispl, yd + ycl * z[ipip])
+            np.add.at(gL, pos.pgk[k], -ya + yu - yd)
+            np.add.at(gL, pos.pg, ya)
+            gL[pos.delta[k]] += np.sum(net.gen_alpha * ya)
         lin, dup, dlo, cup, clo = pos.rowC[k]
         if lin[0] >= 0:
             inup, inum, isup, islo = pos.comp[k]

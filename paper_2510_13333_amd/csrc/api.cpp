@@ -1583,10 +1583,10 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *k, const ncl_nlp *p, const double *dz, const d
 static int ipm_check(const Handle &h, const ncl_ipm_problem *p, const ncl_ipm_state *s) {
     if (!p || !s || !p->pd || !p->lo || !p->hi || !p->y_n || !s->z || !s->rt || !s->s || !s->zl || !s->zu)
         return NCL_ERR_ARG;
-    if (!(p->mu > 0) || !(p->rho > 0) || !(p->smax2 > 0) || !(p->qmax > 0) || !(p->eps >= 0) ||
+    if (!(p->mu > 0) || !(p->rho > 0) || !(p->smax2 > 0) || !(p->qmax > 0) || !(p->pmax > 0) || !(p->eps >= 0) ||
         !std::isfinite(p->qd_ratio) || !std::isfinite(p->mu) || !std::isfinite(p->rho))
         return NCL_ERR_ARG;
-    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & (NCL_SCREEN | NCL_AGC))) return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_SCREEN)) return NCL_ERR_ARG;
     if (!h.bound) return NCL_ERR_STATE;
     return NCL_OK;
 }
@@ -1604,6 +1604,7 @@ static ncl::IpmArgs ipm_args(const ncl_ipm_problem &p, const ncl_ipm_state &s) {
     q.zu = s.zu;
     q.qd_ratio = p.qd_ratio;
     q.qmax = p.qmax;
+    q.pmax = p.pmax;
     q.smax2 = p.smax2;
     q.eps = p.eps;
     q.mu = p.mu;
@@ -1690,6 +1691,162 @@ int ncl_kkt_ipm_step(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_ipm_state *
     if ((rc = ncl_kkt_solve(k, r, d->dz, 1, N, st))) return rc;
     return hip_rc(
         ncl::launch_ipm_point(a, q, ncl::IPM_RECOVER, d->dz, 0.0, d->drt, d->ds, d->dzl, d->dzu, st));
+}
+
+namespace {
+
+// The NCL solve's device evaluations: the barrier KKT error at the current
+// point (largest |G| at mu and at 0, largest |rt|), the step lengths, the
+// update; every reduction deterministic, read back as a few scalars.
+struct NclRun {
+    Handle &h;
+    ncl_kkt *k;
+    hipStream_t st;
+    ncl::DevArgs a;
+    int64_t N;
+    double *cg, *e0, *e1, *e2, *zero, *part, *sc;
+    double hs[4] = {0, 0, 0, 0};
+    int read(int n) {
+        if (hipMemcpyAsync(hs, sc, sizeof(double) * size_t(n), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return NCL_ERR_HIP;
+        return NCL_OK;
+    }
+    int reduce_max(const double *x, int slot) {
+        return hip_rc(ncl::launch_vec_reduce(N, x, x, 0.0, 1, part, sc + slot, st));
+    }
+    // J'y at the point (K's Jacobian blocks at z), c(w) and grad phi
+    int prepare(const ncl_ipm_problem &p, const ncl_ipm_state &s, double rho) {
+        ncl_kkt_point pt{s.z, zero, rho, NCL_NO_SHIFT};
+        int rc = ncl_kkt_assemble(k, &pt, st);
+        if (rc) return rc;
+        const ncl::IpmArgs q = ipm_args(p, s);
+        if (ncl::launch_ipm_point(a, q, ncl::IPM_MASK, nullptr, 0.0, e0, nullptr, nullptr, nullptr, st) != hipSuccess)
+            return NCL_ERR_HIP;
+        if ((rc = residual_column(h, a, e0, e0, nullptr, st))) return rc;
+        return hip_rc(ncl::launch_ipm_cons(a, q, cg, st));
+    }
+    // hs[0] = max |G| at p.mu, hs[1] = at 0, hs[2] = max |rt| (dual rows)
+    int errors(const ncl_ipm_problem &p, const ncl_ipm_state &s, bool all) {
+        const ncl::IpmArgs q = ipm_args(p, s);
+        if (ncl::launch_ipm_point(a, q, ncl::IPM_ERROR, cg, 0.0, e0, e1, e2, nullptr, st) != hipSuccess)
+            return NCL_ERR_HIP;
+        int rc = reduce_max(e0, 0);
+        if (!rc && all) rc = reduce_max(e1, 1);
+        if (!rc && all) rc = reduce_max(e2, 2);
+        return rc ? rc : read(all ? 3 : 1);
+    }
+};
+
+int solve_opts_ok(const ncl_solve_opts *o, double rho) {
+    return o->tol > 0 && o->mu_min > 0 && o->mu0 >= o->mu_min && o->mu_warm >= o->mu_min && o->kappa_eps > 0 &&
+           o->kappa_mu > 0 && o->kappa_mu < 1 && o->theta_mu > 1 && o->tau_min > 0 && o->tau_min < 1 &&
+           o->eta0 > 0 && o->eta_shrink > 1 && o->rho_grow > 1 && o->rho_max >= rho && o->max_inner >= 1 &&
+           o->max_outer >= 1;
+}
+
+}  // namespace
+
+int ncl_kkt_ncl_solve(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_solve_state *s, const ncl_solve_opts *o,
+                      ncl_solve_report *rep, double *dwork, void *stream) {
+    if (!k || !p || !s || !o || !rep || !dwork || !s->z || !s->rt || !s->s || !s->zl || !s->zu || !s->y_n)
+        return NCL_ERR_ARG;
+    if (!solve_opts_ok(o, p->rho)) return NCL_ERR_ARG;
+    Handle &h = k->h;
+    ncl_ipm_problem pr = *p;
+    pr.y_n = s->y_n;
+    pr.mu = o->mu0;
+    const ncl_ipm_state cs{s->z, s->rt, s->s, s->zl, s->zu};
+    int rc = ipm_check(h, &pr, &cs);
+    if (rc) return rc;
+    const int64_t N = h.N;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // dwork: the direction (5 N), ncl_kkt_ipm_step's work (3 N), c and grad
+    // phi, three error vectors, a zero sigma, reduction partials, scalars
+    double *dz = dwork, *drt = dz + N, *ds = drt + N, *dzl = ds + N, *dzu = dzl + N, *wk = dzu + N;
+    NclRun R{h, k, st, dev_args(h), N};
+    R.cg = wk + 3 * N;
+    R.e0 = R.cg + N;
+    R.e1 = R.e0 + N;
+    R.e2 = R.e1 + N;
+    R.zero = R.e2 + N;
+    R.part = R.zero + N;
+    R.sc = R.part + ncl::vec_reduce_partials(N);
+    if (R.sc + 8 > dwork + 17 * N + 64) return NCL_ERR_ARG;
+    if (hipMemsetAsync(R.zero, 0, sizeof(double) * size_t(N), st) != hipSuccess) return NCL_ERR_HIP;
+    *rep = ncl_solve_report{};
+    rep->status = 1;
+    double eta = o->eta0, mu = o->mu0;
+    const ncl_ipm_direction dir{dz, drt, ds, dzl, dzu};
+    const ncl::IpmMove mv{s->z, s->rt, s->s, s->zl, s->zu, dz, drt, ds, dzl, dzu};
+    for (int outer = 0; outer < o->max_outer; outer++) {
+        // the subproblem at (y_n, rho), from the current point
+        double dw_last = 0.0;
+        pr.mu = mu;
+        if ((rc = R.prepare(pr, cs, pr.rho)) || (rc = R.errors(pr, cs, true))) return rc;
+        double emu = R.hs[0], e0 = R.hs[1], r_inf = R.hs[2];
+        int its = 0;
+        bool ok = true;
+        for (;;) {
+            rep->kkt_err = e0;
+            if (e0 <= o->tol) break;
+            while (emu <= o->kappa_eps * mu && mu > o->mu_min) {
+                mu = std::max(o->mu_min, std::min(o->kappa_mu * mu, std::pow(mu, o->theta_mu)));
+                pr.mu = mu;
+                if ((rc = R.errors(pr, cs, false))) return rc;
+                emu = R.hs[0];
+            }
+            if (its == o->max_inner) {
+                ok = false;
+                break;
+            }
+            ncl_inertia_opts io{dw_last, 0, 0};
+            rc = ncl_kkt_ipm_step(k, &pr, &cs, &dir, &io, wk, stream);
+            rep->factorizations += io.nfactor;
+            if (rc) {
+                rep->inner += its;
+                return rc;
+            }
+            dw_last = io.dw_last;
+            const ncl::IpmArgs q = ipm_args(pr, cs);
+            const double tau = std::max(o->tau_min, 1.0 - mu);
+            if (ncl::launch_ipm_line(R.a, q, mv, ncl::IPM_FTB, tau, 0.0, R.e0, R.e1, st) != hipSuccess)
+                return NCL_ERR_HIP;
+            if ((rc = R.reduce_max(R.e0, 0)) || (rc = R.reduce_max(R.e1, 1)) || (rc = R.read(2))) return rc;
+            const double ap = 1.0 / R.hs[0], ad = 1.0 / R.hs[1];
+            if (ncl::launch_ipm_line(R.a, q, mv, ncl::IPM_UPDATE, ap, ad, nullptr, nullptr, st) != hipSuccess)
+                return NCL_ERR_HIP;
+            its++;
+            if ((rc = R.prepare(pr, cs, pr.rho)) || (rc = R.errors(pr, cs, true))) return rc;
+            emu = R.hs[0];
+            e0 = R.hs[1];
+            r_inf = R.hs[2];
+        }
+        rep->inner += its;
+        rep->outer = outer + 1;
+        rep->mu = mu;
+        rep->rho = pr.rho;
+        rep->r_inf = r_inf;
+        if (!ok) {
+            rep->status = 2;
+            return NCL_OK;
+        }
+        if (r_inf <= o->tol) {
+            rep->status = 0;
+            return NCL_OK;
+        }
+        if (r_inf <= eta) {
+            const ncl::IpmArgs q = ipm_args(pr, cs);
+            if (ncl::launch_ipm_point(R.a, q, ncl::IPM_YN, nullptr, 0.0, s->y_n, nullptr, nullptr, nullptr, st) !=
+                hipSuccess)
+                return NCL_ERR_HIP;
+            eta = std::max(eta / o->eta_shrink, o->tol);
+        } else {
+            pr.rho = std::min(o->rho_grow * pr.rho, o->rho_max);
+        }
+        mu = o->mu_warm;
+    }
+    return NCL_OK;
 }
 
 const char *ncl_kernel_name(int kind) {

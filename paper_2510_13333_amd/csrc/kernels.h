@@ -105,12 +105,24 @@ hipError_t launch_disp_load_grad(const DevArgs &a, const double *adj, double qd,
 struct IpmArgs {
     const double *pd = nullptr, *lo = nullptr, *hi = nullptr, *yn = nullptr;
     const double *z = nullptr, *rt = nullptr, *s = nullptr, *zl = nullptr, *zu = nullptr;
-    double qd_ratio = 0.0, qmax = 0.0, smax2 = 0.0, eps = 0.0, mu = 0.0, rho = 0.0;
+    double qd_ratio = 0.0, qmax = 0.0, pmax = 0.0, smax2 = 0.0, eps = 0.0, mu = 0.0, rho = 0.0;
 };
-enum IpmMode { IPM_SIGMA = 0, IPM_MASK, IPM_RHS, IPM_RECOVER, IPM_SHIFT };
+enum IpmMode { IPM_SIGMA = 0, IPM_MASK, IPM_RHS, IPM_RECOVER, IPM_SHIFT, IPM_ERROR, IPM_YN };
 hipError_t launch_ipm_point(const DevArgs &a, const IpmArgs &q, int mode, const double *in, double dw, double *o0,
                             double *o1, double *o2, double *o3, hipStream_t st);
 hipError_t launch_ipm_cons(const DevArgs &a, const IpmArgs &q, double *cg, hipStream_t st);
+// The IPM state (written in place by IPM_UPDATE) and a direction.
+struct IpmMove {
+    double *z = nullptr, *rt = nullptr, *s = nullptr, *zl = nullptr, *zu = nullptr;
+    const double *dz = nullptr, *drt = nullptr, *ds = nullptr, *dzl = nullptr, *dzu = nullptr;
+};
+enum IpmLineMode { IPM_FTB = 0, IPM_UPDATE };
+// IPM_FTB: per position the reciprocals of the largest primal (o0) and dual
+// (o1) steps in (0, 1] that keep the bounded quantities above (1 - tau) of
+// their values (1 where nothing limits); IPM_UPDATE: the state moves by ap
+// (w, y at equality rows, rt, s) and ad (zl, zu, y at inequality rows).
+hipError_t launch_ipm_line(const DevArgs &a, const IpmArgs &q, const IpmMove &m, int mode, double tau_or_ap,
+                           double ad, double *o0, double *o1, hipStream_t st);
 
 // Streaming copy of n doubles (n even, both pointers 16-byte aligned).
 hipError_t launch_copy(const double *src, double *dst, int64_t n, hipStream_t st);

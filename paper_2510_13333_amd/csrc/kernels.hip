@@ -2582,7 +2582,8 @@ __global__ __launch_bounds__(256) void k_ipm_point(DevArgs a, IpmArgs q, int mod
     if (col >= a.N) return;
     const LayPos p = lay_pos(a, col);
     const bool primal = lk_primal(p.kind);
-    const bool comp = p.kind == LK_CUP || p.kind == LK_CLO, flow = p.kind == LK_FLOW;
+    const bool comp = p.kind == LK_CUP || p.kind == LK_CLO || p.kind == LK_ACUP || p.kind == LK_ACLO;
+    const bool flow = p.kind == LK_FLOW;
     if (mode == IPM_SHIFT) {
         o0[col] = primal ? in[col] + dw : in[col];
         return;
@@ -2590,6 +2591,48 @@ __global__ __launch_bounds__(256) void k_ipm_point(DevArgs a, IpmArgs q, int mod
     const double z = q.z[col];
     if (mode == IPM_MASK) {
         o0[col] = primal ? 0.0 : z;
+    } else if (mode == IPM_YN) {
+        // the first-order multiplier update: y_n takes y at the dual rows
+        if (!primal) o0[col] = z;
+    } else if (mode == IPM_ERROR) {
+        // the barrier KKT residual G at this position, at mu (o0) and at 0
+        // (o1), as the largest magnitude of its components, and |rt| at dual
+        // rows (o2); in = c(w) and grad phi, J'y from the residual buffers
+        double em = 0.0, e0 = 0.0, ar = 0.0;
+        if (primal) {
+            const double lo = q.lo[col], hi = q.hi[col];
+            double gw = in[col] - (p.rint >= 0 ? a.rint[p.rint] : a.rbuf[col]);
+            if (lo > -INFINITY) {
+                const double c = (z - lo) * q.zl[col];
+                gw -= q.zl[col];
+                em = fmax(em, fabs(c - q.mu));
+                e0 = fmax(e0, fabs(c));
+            }
+            if (hi < INFINITY) {
+                const double c = (hi - z) * q.zu[col];
+                gw += q.zu[col];
+                em = fmax(em, fabs(c - q.mu));
+                e0 = fmax(e0, fabs(c));
+            }
+            em = fmax(em, fabs(gw));
+            e0 = fmax(e0, fabs(gw));
+        } else {
+            const double rt = q.rt[col];
+            double gy = in[col] - rt;
+            const double grt = q.yn[col] + q.rho * rt - z;
+            if (comp || flow) {
+                const double sv = q.s[col];
+                gy += sv;
+                em = fmax(em, fabs(sv * z - q.mu));
+                e0 = fmax(e0, fabs(sv * z));
+            }
+            em = fmax(em, fmax(fabs(gy), fabs(grt)));
+            e0 = fmax(e0, fmax(fabs(gy), fabs(grt)));
+            ar = fabs(rt);
+        }
+        o0[col] = em;
+        o1[col] = e0;
+        o2[col] = ar;
     } else if (mode == IPM_SIGMA) {
         double v = 0.0;
         if (primal) {
@@ -2648,7 +2691,9 @@ __global__ __launch_bounds__(256) void k_ipm_point(DevArgs a, IpmArgs q, int mod
 // bus thread writes its vm (when in the block), va, P and Q rows and, for
 // the branches it is the from end of, both flow rows; a generator thread
 // its qg (and a single block's pg) and, with PV/PQ rows, its four
-// complementarity variables and five rows; a border thread pg and vm0.
+// complementarity variables and five rows, with AGC rows its pgk, pi+-,
+// the two slacks (generator 0 also delta) and the five AGC rows; a border
+// thread pg and vm0.
 __global__ __launch_bounds__(256) void k_ipm_cons(DevArgs a, IpmArgs q, double *__restrict__ cg) {
     const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const double *z = q.z;
@@ -2735,6 +2780,26 @@ __global__ __launch_bounds__(256) void k_ipm_cons(DevArgs a, IpmArgs q, double *
         cg[zi(bstart, B, n, gi[GI_CUP])] = num * sup;
         cg[zi(bstart, B, n, gi[GI_CLO])] = nup * slo;
     }
+    if (T.agc_rows) {
+        // eq. (droopmpec); phi does not depend on pgk, pi+-, the slacks or delta
+        const int64_t cpk = zi(bstart, B, n, gi[GI_PG]);
+        const int64_t cpip = zi(bstart, B, n, gi[GI_PIP]), cpim = zi(bstart, B, n, gi[GI_PIM]);
+        const int64_t cspu = zi(bstart, B, n, gi[GI_SPU]), cspl = zi(bstart, B, n, gi[GI_SPL]);
+        const int64_t cdel = zi(bstart, B, n, gi[GI_DELTA]);
+        const double pk = z[cpk], pip = z[cpip], pim = z[cpim], spu = z[cspu], spl = z[cspl];
+        const double p0 = gi[GI_PG0] >= 0 ? z[zi(bstart, B, n, gi[GI_PG0])] : 0.0;
+        cg[cpk] = 0.0;
+        cg[cpip] = 0.0;
+        cg[cpim] = 0.0;
+        cg[cspu] = 0.0;
+        cg[cspl] = 0.0;
+        if (g == 0) cg[cdel] = 0.0;
+        cg[zi(bstart, B, n, gi[GI_ALIN])] = pip - pim - pk + p0 + T.gen_alpha[g] * z[cdel];
+        cg[zi(bstart, B, n, gi[GI_ADUP])] = spu - (q.pmax - pk);
+        cg[zi(bstart, B, n, gi[GI_ADLO])] = spl - pk;
+        cg[zi(bstart, B, n, gi[GI_ACUP])] = pim * spu;
+        cg[zi(bstart, B, n, gi[GI_ACLO])] = pip * spl;
+    }
 }
 
 hipError_t launch_ipm_point(const DevArgs &a, const IpmArgs &q, int mode, const double *in, double dw, double *o0,
@@ -2742,6 +2807,60 @@ hipError_t launch_ipm_point(const DevArgs &a, const IpmArgs &q, int mode, const 
     if (a.N > 0)
         hipLaunchKernelGGL(k_ipm_point, dim3(unsigned((a.N + 255) / 256)), dim3(256), 0, st, a, q, mode, in, dw, o0, o1,
                            o2, o3);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_ipm_line(DevArgs a, IpmArgs q, IpmMove m, int mode, double t,
+                                                  double ad, double *__restrict__ o0, double *__restrict__ o1) {
+    const int64_t col = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (col >= a.N) return;
+    const LayPos p = lay_pos(a, col);
+    const bool primal = lk_primal(p.kind);
+    const bool ineq = p.kind == LK_CUP || p.kind == LK_CLO || p.kind == LK_ACUP || p.kind == LK_ACLO ||
+                      p.kind == LK_FLOW;
+    const double dz = m.dz[col];
+    if (mode == IPM_FTB) {
+        // 1 / alpha limits: x + alpha dx >= (1 - tau) x for x > 0, dx < 0
+        const double tau = t;
+        double ip = 1.0, id = 1.0;
+        if (primal) {
+            const double w = m.z[col], lo = q.lo[col], hi = q.hi[col];
+            if (lo > -INFINITY) {
+                if (dz < 0.0) ip = fmax(ip, -dz / (tau * (w - lo)));
+                const double dl = m.dzl[col];
+                if (dl < 0.0) id = fmax(id, -dl / (tau * m.zl[col]));
+            }
+            if (hi < INFINITY) {
+                if (dz > 0.0) ip = fmax(ip, dz / (tau * (hi - w)));
+                const double du = m.dzu[col];
+                if (du < 0.0) id = fmax(id, -du / (tau * m.zu[col]));
+            }
+        } else if (ineq) {
+            const double ds = m.ds[col];
+            if (ds < 0.0) ip = fmax(ip, -ds / (tau * m.s[col]));
+            if (dz < 0.0) id = fmax(id, -dz / (tau * m.z[col]));
+        }
+        o0[col] = ip;
+        o1[col] = id;
+        return;
+    }
+    const double ap = t;
+    if (primal) {
+        m.z[col] += ap * dz;
+        if (q.lo[col] > -INFINITY) m.zl[col] += ad * m.dzl[col];
+        if (q.hi[col] < INFINITY) m.zu[col] += ad * m.dzu[col];
+    } else {
+        m.z[col] += (ineq ? ad : ap) * dz;
+        m.rt[col] += ap * m.drt[col];
+        if (ineq) m.s[col] += ap * m.ds[col];
+    }
+}
+
+hipError_t launch_ipm_line(const DevArgs &a, const IpmArgs &q, const IpmMove &m, int mode, double tau_or_ap,
+                           double ad, double *o0, double *o1, hipStream_t st) {
+    if (a.N > 0)
+        hipLaunchKernelGGL(k_ipm_line, dim3(unsigned((a.N + 255) / 256)), dim3(256), 0, st, a, q, m, mode, tau_or_ap,
+                           ad, o0, o1);
     return hipGetLastError();
 }
 

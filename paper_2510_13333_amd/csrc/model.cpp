@@ -451,6 +451,7 @@ int build_network_model(const ncl_network *nw, Handle &h, std::string &err) {
                 gi[GI_PIP] = L.pip[g]; gi[GI_PIM] = L.pim[g]; gi[GI_SPU] = L.spu[g]; gi[GI_SPL] = L.spl[g];
                 gi[GI_ALIN] = L.rAlin[g]; gi[GI_ADUP] = L.rAdup[g]; gi[GI_ADLO] = L.rAdlo[g];
                 gi[GI_ACUP] = L.rAcup[g]; gi[GI_ACLO] = L.rAclo[g]; gi[GI_DELTA] = L.delta;
+                gi[GI_PG0] = L.pg0[g];
                 gs[GS_ALIN_PIP] = slot(L.rAlin[g], L.pip[g]);
                 gs[GS_ALIN_PIM] = slot(L.rAlin[g], L.pim[g]);
                 gs[GS_ALIN_PGK] = slot(L.rAlin[g], L.pg[g]);

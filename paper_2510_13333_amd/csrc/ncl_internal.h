@@ -106,9 +106,10 @@ enum GenSlot {
 };
 // State index tables per bus / generator: layout-local positions (n + b for border refs).
 enum BusIdx { BI_VM, BI_VA, BI_P, BI_Q, BI_N };
-// With AGC rows GI_PG is the block's own generation pgk.
+// With AGC rows GI_PG is the block's own generation pgk and GI_PG0 the
+// first-stage pg (or -1 when it is fixed).
 enum GenIdx { GI_BUS, GI_QG, GI_PG, GI_NUP, GI_NUM, GI_SUP, GI_SLO, GI_LIN, GI_DUP, GI_DLO, GI_CUP, GI_CLO, GI_VM0,
-              GI_PIP, GI_PIM, GI_SPU, GI_SPL, GI_ALIN, GI_ADUP, GI_ADLO, GI_ACUP, GI_ACLO, GI_DELTA, GI_N };
+              GI_PIP, GI_PIM, GI_SPU, GI_SPL, GI_ALIN, GI_ADUP, GI_ADLO, GI_ACUP, GI_ACLO, GI_DELTA, GI_PG0, GI_N };
 
 struct TemplDev {
     int32_t n, nsup, nblk, nbd;     // columns, supernodes, blocks using the template, its instance's border size

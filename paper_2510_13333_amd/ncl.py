@@ -76,8 +76,8 @@ class NewtonOpts(ctypes.Structure):
 
 class _IpmProblem(ctypes.Structure):
     _fields_ = [("pd", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("y_n", ctypes.c_void_p),
-                ("qd_ratio", ctypes.c_double), ("qmax", ctypes.c_double), ("smax2", ctypes.c_double),
-                ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double)]
+                ("qd_ratio", ctypes.c_double), ("qmax", ctypes.c_double), ("pmax", ctypes.c_double),
+                ("smax2", ctypes.c_double), ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double)]
 
 
 class _IpmState(ctypes.Structure):
@@ -92,6 +92,32 @@ class _IpmDirection(ctypes.Structure):
 
 class InertiaOpts(ctypes.Structure):
     _fields_ = [("dw_last", ctypes.c_double), ("nfactor", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    """Options of the NCL solve (ncl_solve_opts); the defaults below."""
+    _fields_ = [("tol", ctypes.c_double), ("mu_min", ctypes.c_double), ("mu0", ctypes.c_double),
+                ("mu_warm", ctypes.c_double), ("kappa_eps", ctypes.c_double), ("kappa_mu", ctypes.c_double),
+                ("theta_mu", ctypes.c_double), ("tau_min", ctypes.c_double), ("eta0", ctypes.c_double),
+                ("eta_shrink", ctypes.c_double), ("rho_grow", ctypes.c_double), ("rho_max", ctypes.c_double),
+                ("max_inner", ctypes.c_int32), ("max_outer", ctypes.c_int32)]
+
+    def __init__(self, **kw):
+        d = dict(tol=1e-6, mu_min=1e-7, mu0=0.1, mu_warm=1e-5, kappa_eps=10.0, kappa_mu=0.2, theta_mu=1.5,
+                 tau_min=0.99, eta0=1e-2, eta_shrink=10.0, rho_grow=10.0, rho_max=1e12, max_inner=300, max_outer=30)
+        d.update(kw)
+        super().__init__(**d)
+
+
+class _SolveReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer", ctypes.c_int32), ("inner", ctypes.c_int32),
+                ("factorizations", ctypes.c_int32), ("rho", ctypes.c_double), ("mu", ctypes.c_double),
+                ("r_inf", ctypes.c_double), ("kkt_err", ctypes.c_double)]
+
+
+class _SolveState(ctypes.Structure):
+    _fields_ = [("z", ctypes.c_void_p), ("rt", ctypes.c_void_p), ("s", ctypes.c_void_p), ("zl", ctypes.c_void_p),
+                ("zu", ctypes.c_void_p), ("y_n", ctypes.c_void_p)]
 
 
 class Report(ctypes.Structure):
@@ -161,6 +187,7 @@ def load():
         "ncl_kkt_ipm_recover": ([P, P, P, P, P, P], ctypes.c_int),
         "ncl_kkt_factor_inertia": ([P, P, P, ctypes.c_double, P, P, P], ctypes.c_int),
         "ncl_kkt_ipm_step": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "ncl_kkt_ncl_solve": ([P, P, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -487,11 +514,12 @@ class KKT:
     # ------------------------------------------------------------ IPM step
     def _ipm(self, prob, state):
         """Marshal the IPM problem (dict: pd, lo, hi, y_n device tensors and
-        the scalars qd_ratio, qmax, smax2, eps, mu, rho) and state (dict: z,
-        rt, s, zl, zu device tensors)."""
+        the scalars qd_ratio, qmax, pmax (default 8), smax2, eps, mu, rho) and
+        state (dict: z, rt, s, zl, zu device tensors)."""
         p = _IpmProblem(self._dev(prob["pd"]), self._dev(prob["lo"], self.N), self._dev(prob["hi"], self.N),
                         self._dev(prob["y_n"], self.N), float(prob["qd_ratio"]), float(prob["qmax"]),
-                        float(prob["smax2"]), float(prob["eps"]), float(prob["mu"]), float(prob["rho"]))
+                        float(prob.get("pmax", 8.0)), float(prob["smax2"]), float(prob["eps"]), float(prob["mu"]),
+                        float(prob["rho"]))
         st = _IpmState(*[self._dev(state[k], self.N) for k in ("z", "rt", "s", "zl", "zu")])
         return p, st
 
@@ -537,6 +565,27 @@ class KKT:
                                                            ctypes.byref(dd), ctypes.byref(opts),
                                                            self._dev(work, 3 * self.N), _stream_ptr()))
         return d
+
+    def ncl_solve(self, prob, state, opts=None, work=None):
+        """The NCL method end to end (ncl_kkt_ncl_solve).  prob: as for the
+        IPM step (its y_n and mu are not read; rho is the first penalty);
+        state: dict of device tensors z, rt, s, zl, zu, y_n, updated in place
+        to the last iterate; work: 17 N + 64 doubles (allocated if None).
+        Returns the report as a dict."""
+        import torch
+        if work is None:
+            work = torch.empty(17 * self.N + 64, dtype=torch.float64, device=state["z"].device)
+        prob = dict(prob)
+        prob.setdefault("y_n", state["y_n"])
+        prob.setdefault("mu", 0.1)
+        p, _ = self._ipm(prob, state)
+        s = _SolveState(*[self._dev(state[k], self.N) for k in ("z", "rt", "s", "zl", "zu", "y_n")])
+        o = opts if opts is not None else SolveOpts()
+        r = _SolveReport()
+        _check("ncl_kkt_ncl_solve", load().ncl_kkt_ncl_solve(self._h, ctypes.byref(p), ctypes.byref(s),
+                                                             ctypes.byref(o), ctypes.byref(r),
+                                                             self._dev(work, 17 * self.N + 64), _stream_ptr()))
+        return {f: getattr(r, f) for f, _ in r._fields_}
 
     # ------------------------------------------------------------ measurement
     @staticmethod

@@ -37,6 +37,8 @@ NETS = {
     "plain5": lambda: (G.make_network(8, 5, 6, 2, 1, rho=1e3), 8),
     "single30": lambda: (G.make_network(6, 30, 41, 6, 0, rho=1e3), 6),
     "pvpq200x8": lambda: (G.make_network(13, 200, 280, 36, 8, pvpq=True, rho=1e5), 13),
+    "agc9": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True), 99),
+    "agc118x8": lambda: (G.make_network(5, 118, 165, 21, 8, pvpq=True, rho=1e5, agc=True), 5),
 }
 
 
@@ -53,7 +55,7 @@ def setup(net, cfg, iteration=0):
     prob = I.Problem(pd=pd, lo=d["lo"], hi=d["hi"], y_n=d["y_n"], mu=0.1, rho=net.rho)
     st = I.State(d["z"], d["rt"], d["s"], d["zl"], d["zu"])
     gprob = dict(pd=dev(pd), lo=dev(d["lo"]), hi=dev(d["hi"]), y_n=dev(d["y_n"]), qd_ratio=prob.qd_ratio,
-                 qmax=prob.qmax, smax2=prob.smax2, eps=prob.eps, mu=prob.mu, rho=prob.rho)
+                 qmax=prob.qmax, pmax=prob.pmax, smax2=prob.smax2, eps=prob.eps, mu=prob.mu, rho=prob.rho)
     gst = {k: dev(d[k]) for k in ("z", "rt", "s", "zl", "zu")}
     return prob, st, gprob, gst
 
@@ -129,7 +131,8 @@ def test_sigma_rhs_recovery_match_oracle(which):
 
 
 @pytest.mark.parametrize("which,iteration", [("pvpq9", 0), ("pvpq9", 1), ("pvpq9", 2), ("plain5", 0),
-                                             ("single30", 0), ("pvpq200x8", 0), ("pvpq200x8", 1)])
+                                             ("single30", 0), ("pvpq200x8", 0), ("pvpq200x8", 1), ("agc9", 0),
+                                             ("agc118x8", 1)])
 def test_inertia_correction_matches_oracle(which, iteration):
     net, cfg = NETS[which]()
     prob, st, gprob, gst = setup(net, cfg, iteration)

@@ -36,6 +36,7 @@ NETS = {
     "pvpq": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5), 99),
     "plain": lambda: (G.make_network(8, 5, 6, 2, 1, rho=1e3), 8),
     "single": lambda: (G.make_network(7, 6, 8, 2, 0, rho=1e3), 7),
+    "agc": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True), 99),
 }
 
 
@@ -132,7 +133,7 @@ def test_reduced_step_equals_full_newton_step(which):
             assert err <= 1e-8, (name, err)
 
 
-@pytest.mark.parametrize("which", ["pvpq", "plain"])
+@pytest.mark.parametrize("which", ["pvpq", "plain", "agc"])
 def test_step_is_a_newton_direction(which):
     """d/da G(u + a du) at a = 0 is -G(u), by complex step in a (no matrix)."""
     net, cfg = NETS[which]()
@@ -214,3 +215,38 @@ def test_shift_sequence_restarts_from_the_last_shift():
     assert seq[0] == 0.0 and seq[1] == pytest.approx(1e-2) and seq[2] == pytest.approx(8e-2)
     seq = list(I.shift_sequence(0.0))
     assert seq[1] == 1e-4 and seq[-1] < 1e12 <= seq[-1] * 8
+
+
+def test_agc_rows_vanish_on_the_clipped_recourse():
+    """eq. (agc): p^k = min(max(p^0 + alpha Delta, pmin), pmax).  With pi+ and
+    pi- the parts of p^k - (p^0 + alpha Delta) above and below zero and the
+    slacks pmax - p^k, p^k - pmin, the five AGC rows of eq. (droopmpec)
+    vanish; pairing pi+ with the upper slack instead does not.  The point
+    puts generators on both bounds and inside."""
+    net, cfg = NETS["agc"]()
+    prob, st = setup(net, cfg)
+    pos = A.Positions(net)
+    z = st.z.copy()
+    ng = net.ng
+    z[pos.pg] = np.array([7.5, 0.2, 4.0])[:ng]
+    for k in range(1, net.nblk):
+        dk = [3.0, -2.0][k - 1]
+        z[pos.delta[k]] = dk
+        target = z[pos.pg] + net.gen_alpha * dk
+        pk = np.clip(target, 0.0, prob.pmax)
+        z[pos.pgk[k]] = pk
+        pip, pim, spu, spl = pos.acomp[k]
+        z[pip] = np.maximum(pk - target, 0.0)
+        z[pim] = np.maximum(target - pk, 0.0)
+        z[spu] = prob.pmax - pk
+        z[spl] = pk
+    c = I.constraints(net, z, prob)
+    rows = pos.rowA[1:].ravel()
+    assert np.abs(c[rows]).max() <= 1e-14
+    # the point has generators at pmax, at pmin and inside
+    pk = z[pos.pgk[1:].ravel()]
+    assert (pk == prob.pmax).any() and (pk == 0.0).any() and ((pk > 0) & (pk < prob.pmax)).any()
+    # the other pairing leaves a product nonzero
+    for k in range(1, net.nblk):
+        pip, pim, spu, spl = pos.acomp[k]
+        assert np.abs(z[pip] * z[spu]).max() + np.abs(z[pim] * z[spl]).max() > 0
