@@ -496,6 +496,8 @@ CONFIGS = {
     # the 500-bus x 256 grid with AGC droop rows added to the PV/PQ rows of
     # every contingency block (the same grid and outages: config 3's seed)
     7: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, agc=True, seed_cfg=3),
+    # screening of that grid's 256 contingencies with PV/PQ and AGC rows
+    8: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, agc=True, screen=True, seed_cfg=3),
 }
 
 

@@ -516,15 +516,20 @@ int ncl_kkt_dispatch_vjp(ncl_kkt *h, const ncl_nlp *p, const double *dz, const d
  *   d s  = mu/y - s - (s/y) dy                         (inequality rows)
  *   d zl = (mu - (w - lo) zl - zl dw)/(w - lo)         (finite lo)
  *   d zu = (mu - (hi - w) zu + zu dw)/(hi - w)         (finite hi).
- * Handles of one network only: NCL_SCREEN networks (no pg variable),
- * batches of several networks and pattern handles are rejected
- * (NCL_ERR_ARG), and so are qmax, pmax or smax2 <= 0. */
+ * An NCL_SCREEN network (eq. (screening)) takes pg0 and vm0 as data: its
+ * blocks are the contingencies' problems at that first stage, and phi
+ * keeps only the angle term.  Handles of one network only: batches of
+ * several networks and pattern handles are rejected (NCL_ERR_ARG), and so
+ * are qmax, pmax or smax2 <= 0 and a screening network without pg0 (or,
+ * with NCL_PVPQ, vm0). */
 typedef struct {
     const double *pd;        /* DEVICE [nbus] active loads */
     const double *lo, *hi;   /* DEVICE [N] bounds at primal positions (-inf/+inf: none; dual rows ignored) */
     const double *y_n;       /* DEVICE [N] multiplier estimates lam_n, nu0_n at dual rows */
     double qd_ratio, qmax, pmax, smax2, eps;
     double mu, rho;
+    const double *pg0;       /* DEVICE [ngen] fixed first-stage pg (NCL_SCREEN networks; NULL otherwise) */
+    const double *vm0;       /* DEVICE [ngen] fixed first-stage PV voltages (NCL_SCREEN with NCL_PVPQ) */
 } ncl_ipm_problem;
 
 /* A primal-dual point, DEVICE [N] each, layout order (entries outside the

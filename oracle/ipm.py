@@ -12,7 +12,11 @@ corrective SCOPF of Section II-B with the PV/PQ rows of eq. (pvpq):
          lo <= w <= hi                      (finite entries only)
 
 phi(w) = sum_g c2_g pg_g^2 + (eps/2) sum_k va_{k,0}^2 (the second term fixes
-each block's angle reference, as in the dispatch map).  Every dual row
+each block's angle reference, as in the dispatch map).  A screening network
+(eq. (screening)) fixes the first-stage pg0 and vm0, given as data: its
+blocks are the contingencies' feasibility problems (eq. (feaspb) once NCL
+drives r, t to zero or to their least violation), phi keeps only the angle
+term.  Every dual row
 carries one regularisation variable: r on the rows of c(w), t on the
 complementarity rows (both called rt here, one vector over the dual rows).
 The slack of an inequality row has the row multiplier as its own bound
@@ -84,6 +88,8 @@ class Problem:
     pmax: float = 8.0
     smax2: float = 100.0
     eps: float = 1.0
+    pg0: np.ndarray = None              # [ng] fixed first-stage pg (screening networks)
+    vm0: np.ndarray = None              # [ng] fixed first-stage PV voltages (screening with PV/PQ rows)
 
 
 @dataclass
@@ -113,8 +119,8 @@ class Masks:
 
 
 def masks(net, prob: Problem) -> Masks:
-    if getattr(net, "screen", False):
-        raise ValueError("the IPM step is defined for corrective networks (pg is a variable)")
+    if getattr(net, "screen", False) and (prob.pg0 is None or (net.pvpq and prob.vm0 is None)):
+        raise ValueError("a screening network needs the fixed first-stage values pg0 (and vm0)")
     pos = _asm.Positions(net)
     N = pos.N
     primal = pos.is_primal.copy()
@@ -159,7 +165,9 @@ def constraints(net, z, prob: Problem, m: Masks = None):
     gser, bser = _series(net)
     f, t = net.br_from.astype(np.int64), net.br_to.astype(np.int64)
     gb = net.gen_bus.astype(np.int64)
-    pg = z[pos.pg]
+    screen = pos.screen
+    pg = np.asarray(prob.pg0, np.float64) if screen else z[pos.pg]
+    vm0 = (np.asarray(prob.vm0, np.float64) if screen else z[pos.vm0]) if net.pvpq else None
     for k in range(net.nblk):
         st = _asm.branch_status(net, k)
         g, b = st * gser, st * bser
@@ -181,7 +189,7 @@ def constraints(net, z, prob: Problem, m: Masks = None):
         lin, dup, dlo, cup, clo = pos.rowC[k]
         if lin[0] >= 0:
             nup, num, sup, slo = (z[i] for i in pos.comp[k])
-            c[lin] = nup - num - v[gb] + z[pos.vm0]
+            c[lin] = nup - num - v[gb] + vm0
             c[dup] = sup - (prob.qmax - qg)
             c[dlo] = slo - (qg + prob.qmax)
             c[cup] = num * sup
@@ -200,9 +208,12 @@ def constraints(net, z, prob: Problem, m: Masks = None):
 def objective(net, z, prob: Problem, m: Masks = None):
     m = m or masks(net, prob)
     pos = m.pos
-    pg = z[pos.pg]
     va0 = z[m.vref]
-    return np.sum(net.gen_c2 * pg * pg) + 0.5 * prob.eps * np.sum(va0 * va0)
+    f = 0.5 * prob.eps * np.sum(va0 * va0)
+    if pos.screen:                       # pg fixed: the feasibility problem has no cost term
+        return f
+    pg = z[pos.pg]
+    return np.sum(net.gen_c2 * pg * pg) + f
 
 
 def grad_lagrangian(net, z, prob: Problem, m: Masks = None):
@@ -214,7 +225,9 @@ def grad_lagrangian(net, z, prob: Problem, m: Masks = None):
     gser, bser = _series(net)
     f, t = net.br_from.astype(np.int64), net.br_to.astype(np.int64)
     gb = net.gen_bus.astype(np.int64)
-    gL[pos.pg] += 2.0 * net.gen_c2 * z[pos.pg]
+    screen = pos.screen
+    if not screen:
+        gL[pos.pg] += 2.0 * net.gen_c2 * z[pos.pg]
     gL[m.vref] += prob.eps * z[m.vref]
     for k in range(net.nblk):
         st = _asm.branch_status(net, k)
@@ -230,7 +243,10 @@ def grad_lagrangian(net, z, prob: Problem, m: Masks = None):
             np.add.at(gL, var, yP[s_bus][:, None] * dP + yQ[s_bus][:, None] * dQ + yF[:, None] * dh)
         np.add.at(gL, pos.qg[k], -yQ[gb])
         agc = pos.pgk[k][0] >= 0
-        np.add.at(gL, pos.pgk[k] if agc else pos.pg, -yP[gb])
+        if agc:
+            np.add.at(gL, pos.pgk[k], -yP[gb])
+        elif not screen:
+            np.add.at(gL, pos.pg, -yP[gb])
         if agc:
             alin, adup, adlo, acup, aclo = pos.rowA[k]
             ipip, ipim, ispu, ispl = pos.acomp[k]
@@ -240,7 +256,8 @@ def grad_lagrangian(net, z, prob: Problem, m: Masks = None):
             np.add.at(gL, ispu, yu + ycu * z[ipim])
             np.add.at(gL, ispl, yd + ycl * z[ipip])
             np.add.at(gL, pos.pgk[k], -ya + yu - yd)
-            np.add.at(gL, pos.pg, ya)
+            if not screen:
+                np.add.at(gL, pos.pg, ya)
             gL[pos.delta[k]] += np.sum(net.gen_alpha * ya)
         lin, dup, dlo, cup, clo = pos.rowC[k]
         if lin[0] >= 0:
@@ -251,7 +268,8 @@ def grad_lagrangian(net, z, prob: Problem, m: Masks = None):
             np.add.at(gL, isup, yu + ycu * z[inum])
             np.add.at(gL, islo, yd + ycl * z[inup])
             np.add.at(gL, vm_p[gb], -yl)
-            np.add.at(gL, pos.vm0, yl)
+            if not screen:
+                np.add.at(gL, pos.vm0, yl)
             np.add.at(gL, pos.qg[k], yu - yd)
     gL[m.dual] = 0.0
     return gL

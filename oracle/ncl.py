@@ -147,8 +147,6 @@ def solve(net, prob: _ipm.Problem, st: _ipm.State, o: Opts = None):
     multiplier estimates, prob.rho the first penalty, prob.mu ignored: the
     first subproblem starts at o.mu0).  Returns (state, y_n, Report)."""
     o = o or Opts()
-    if getattr(net, "screen", False):
-        raise ValueError("the NCL solve is defined for corrective networks (pg is a variable)")
     rep = Report()
     factor = Factor.from_network(net)
     m = _ipm.masks(net, prob)

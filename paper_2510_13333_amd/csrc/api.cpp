@@ -1586,7 +1586,9 @@ static int ipm_check(const Handle &h, const ncl_ipm_problem *p, const ncl_ipm_st
     if (!(p->mu > 0) || !(p->rho > 0) || !(p->smax2 > 0) || !(p->qmax > 0) || !(p->pmax > 0) || !(p->eps >= 0) ||
         !std::isfinite(p->qd_ratio) || !std::isfinite(p->mu) || !std::isfinite(p->rho))
         return NCL_ERR_ARG;
-    if (!h.from_network || h.inst.size() != 1 || (h.inst[0].flags & NCL_SCREEN)) return NCL_ERR_ARG;
+    if (!h.from_network || h.inst.size() != 1) return NCL_ERR_ARG;
+    const uint32_t fl = h.inst[0].flags;
+    if ((fl & NCL_SCREEN) && (!p->pg0 || ((fl & NCL_PVPQ) && !p->vm0))) return NCL_ERR_ARG;
     if (!h.bound) return NCL_ERR_STATE;
     return NCL_OK;
 }
@@ -1602,6 +1604,8 @@ static ncl::IpmArgs ipm_args(const ncl_ipm_problem &p, const ncl_ipm_state &s) {
     q.s = s.s;
     q.zl = s.zl;
     q.zu = s.zu;
+    q.pg0 = p.pg0;
+    q.vm0 = p.vm0;
     q.qd_ratio = p.qd_ratio;
     q.qmax = p.qmax;
     q.pmax = p.pmax;

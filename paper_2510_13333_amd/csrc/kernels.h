@@ -105,6 +105,7 @@ hipError_t launch_disp_load_grad(const DevArgs &a, const double *adj, double qd,
 struct IpmArgs {
     const double *pd = nullptr, *lo = nullptr, *hi = nullptr, *yn = nullptr;
     const double *z = nullptr, *rt = nullptr, *s = nullptr, *zl = nullptr, *zu = nullptr;
+    const double *pg0 = nullptr, *vm0 = nullptr;   // fixed first stage (screening networks)
     double qd_ratio = 0.0, qmax = 0.0, pmax = 0.0, smax2 = 0.0, eps = 0.0, mu = 0.0, rho = 0.0;
 };
 enum IpmMode { IPM_SIGMA = 0, IPM_MASK, IPM_RHS, IPM_RECOVER, IPM_SHIFT, IPM_ERROR, IPM_YN };

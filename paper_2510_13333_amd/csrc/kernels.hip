@@ -2744,7 +2744,8 @@ __global__ __launch_bounds__(256) void k_ipm_cons(DevArgs a, IpmArgs q, double *
         double pgv = 0.0, qgv = 0.0;
         if (gat >= 0) {
             const int32_t *gi = T.gen_idx + size_t(gat) * GI_N;
-            pgv = z[zi(bstart, B, n, gi[GI_PG])];
+            // a screening block without AGC rows has no pg column: pg0 is data
+            pgv = gi[GI_PG] >= 0 ? z[zi(bstart, B, n, gi[GI_PG])] : q.pg0[gat];
             qgv = z[zi(bstart, B, n, gi[GI_QG])];
         }
         const double pd = q.pd[i];
@@ -2769,7 +2770,8 @@ __global__ __launch_bounds__(256) void k_ipm_cons(DevArgs a, IpmArgs q, double *
         const int64_t csup = zi(bstart, B, n, gi[GI_SUP]), cslo = zi(bstart, B, n, gi[GI_SLO]);
         const double nup = z[cnup], num = z[cnum], sup = z[csup], slo = z[cslo], qg = z[cq];
         const int32_t *bb = T.bus_idx + size_t(gi[GI_BUS]) * BI_N;
-        const double vi = z[zi(bstart, B, n, bb[BI_VM])], v0 = z[zi(bstart, B, n, gi[GI_VM0])];
+        const double vi = z[zi(bstart, B, n, bb[BI_VM])];
+        const double v0 = gi[GI_VM0] >= 0 ? z[zi(bstart, B, n, gi[GI_VM0])] : q.vm0[g];
         cg[cnup] = 0.0;
         cg[cnum] = 0.0;
         cg[csup] = 0.0;
@@ -2787,7 +2789,7 @@ __global__ __launch_bounds__(256) void k_ipm_cons(DevArgs a, IpmArgs q, double *
         const int64_t cspu = zi(bstart, B, n, gi[GI_SPU]), cspl = zi(bstart, B, n, gi[GI_SPL]);
         const int64_t cdel = zi(bstart, B, n, gi[GI_DELTA]);
         const double pk = z[cpk], pip = z[cpip], pim = z[cpim], spu = z[cspu], spl = z[cspl];
-        const double p0 = gi[GI_PG0] >= 0 ? z[zi(bstart, B, n, gi[GI_PG0])] : 0.0;
+        const double p0 = gi[GI_PG0] >= 0 ? z[zi(bstart, B, n, gi[GI_PG0])] : q.pg0[g];
         cg[cpk] = 0.0;
         cg[cpip] = 0.0;
         cg[cpim] = 0.0;

@@ -77,7 +77,8 @@ class NewtonOpts(ctypes.Structure):
 class _IpmProblem(ctypes.Structure):
     _fields_ = [("pd", ctypes.c_void_p), ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("y_n", ctypes.c_void_p),
                 ("qd_ratio", ctypes.c_double), ("qmax", ctypes.c_double), ("pmax", ctypes.c_double),
-                ("smax2", ctypes.c_double), ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double)]
+                ("smax2", ctypes.c_double), ("eps", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
+                ("pg0", ctypes.c_void_p), ("vm0", ctypes.c_void_p)]
 
 
 class _IpmState(ctypes.Structure):
@@ -514,12 +515,14 @@ class KKT:
     # ------------------------------------------------------------ IPM step
     def _ipm(self, prob, state):
         """Marshal the IPM problem (dict: pd, lo, hi, y_n device tensors and
-        the scalars qd_ratio, qmax, pmax (default 8), smax2, eps, mu, rho) and
-        state (dict: z, rt, s, zl, zu device tensors)."""
+        the scalars qd_ratio, qmax, pmax (default 8), smax2, eps, mu, rho, and
+        for screening networks pg0, vm0 device tensors) and state (dict: z,
+        rt, s, zl, zu device tensors)."""
         p = _IpmProblem(self._dev(prob["pd"]), self._dev(prob["lo"], self.N), self._dev(prob["hi"], self.N),
                         self._dev(prob["y_n"], self.N), float(prob["qd_ratio"]), float(prob["qmax"]),
                         float(prob.get("pmax", 8.0)), float(prob["smax2"]), float(prob["eps"]), float(prob["mu"]),
-                        float(prob["rho"]))
+                        float(prob["rho"]), None if prob.get("pg0") is None else self._dev(prob["pg0"]),
+                        None if prob.get("vm0") is None else self._dev(prob["vm0"]))
         st = _IpmState(*[self._dev(state[k], self.N) for k in ("z", "rt", "s", "zl", "zu")])
         return p, st
 

@@ -39,6 +39,8 @@ NETS = {
     "pvpq200x8": lambda: (G.make_network(13, 200, 280, 36, 8, pvpq=True, rho=1e5), 13),
     "agc9": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True), 99),
     "agc118x8": lambda: (G.make_network(5, 118, 165, 21, 8, pvpq=True, rho=1e5, agc=True), 5),
+    "screen60x6": lambda: (G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True), 43),
+    "screen_agc60x6": lambda: (G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True, agc=True), 43),
 }
 
 
@@ -56,6 +58,11 @@ def setup(net, cfg, iteration=0):
     st = I.State(d["z"], d["rt"], d["s"], d["zl"], d["zu"])
     gprob = dict(pd=dev(pd), lo=dev(d["lo"]), hi=dev(d["hi"]), y_n=dev(d["y_n"]), qd_ratio=prob.qd_ratio,
                  qmax=prob.qmax, pmax=prob.pmax, smax2=prob.smax2, eps=prob.eps, mu=prob.mu, rho=prob.rho)
+    if net.screen:
+        # the fixed first stage of a screening network (seeded)
+        g = np.random.default_rng(2510)
+        prob.pg0, prob.vm0 = g.uniform(1.0, 3.0, net.ng), g.uniform(0.95, 1.05, net.ng)
+        gprob["pg0"], gprob["vm0"] = dev(prob.pg0), dev(prob.vm0)
     gst = {k: dev(d[k]) for k in ("z", "rt", "s", "zl", "zu")}
     return prob, st, gprob, gst
 
@@ -207,7 +214,7 @@ def test_ipm_step_500bus_256_contingencies():
         assert np.abs(d[name] - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), name
 
 
-def test_ipm_rejects_screening_and_bad_arguments():
+def test_ipm_rejects_screening_without_first_stage_and_bad_arguments():
     net = G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True)
     k = KKT(net).bind(nrhs_max=1)
     N = k.N
@@ -215,6 +222,9 @@ def test_ipm_rejects_screening_and_bad_arguments():
     gprob = dict(pd=empty(net.nb), lo=z, hi=z, y_n=z, qd_ratio=0.3, qmax=3.0, smax2=100.0, eps=1.0, mu=0.1, rho=1e5)
     gst = dict(z=z, rt=z, s=z, zl=z, zu=z)
     from paper_2510_13333_amd.ncl import NclError
+    with pytest.raises(NclError):
+        k.ipm_sigma(gprob, gst, empty(N))
+    gprob["pg0"] = empty(net.ng).fill_(1.0)          # PV/PQ rows need vm0 too
     with pytest.raises(NclError):
         k.ipm_sigma(gprob, gst, empty(N))
     net2, cfg = NETS["pvpq9"]()

@@ -38,8 +38,11 @@ NETS = {
     "agc9": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True), 99, 0.1),
     "agc9_plain": lambda: (G.make_network(99, 9, 12, 3, 2, rho=1e3, agc=True), 99, 0.1),
     "agc30x3": lambda: (G.make_network(1, 30, 41, 6, 3, pvpq=True, rho=1e5, agc=True), 1, 0.2),
+    # contingency screening (eq. (screening)): six contingencies at a fixed
+    # first stage, their feasibility problems solved together
+    "screen_agc60x6": lambda: (G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True, agc=True), 43, 0.1),
 }
-EXACT_COUNTS = {"single7", "c1", "agc9", "agc30x3"}
+EXACT_COUNTS = {"single7", "c1", "agc9", "agc30x3", "screen_agc60x6"}
 
 
 def setup(net, cfg, scale):
@@ -50,6 +53,10 @@ def setup(net, cfg, scale):
     st = I.State(st0["z"], st0["rt"], st0["s"], st0["zl"], st0["zu"])
     gprob = dict(pd=dev(pd), lo=dev(st0["lo"]), hi=dev(st0["hi"]), qd_ratio=prob.qd_ratio, qmax=prob.qmax,
                  pmax=prob.pmax, smax2=prob.smax2, eps=prob.eps, rho=prob.rho)
+    if net.screen:
+        g = np.random.default_rng(2510)
+        prob.pg0, prob.vm0 = g.uniform(1.0, 3.0, net.ng), g.uniform(0.95, 1.05, net.ng)
+        gprob["pg0"], gprob["vm0"] = dev(prob.pg0), dev(prob.vm0)
     gst = {k: dev(st0[k]) for k in ("z", "rt", "s", "zl", "zu")}
     gst["y_n"] = dev(np.zeros(N))
     return prob, st, gprob, gst
@@ -82,7 +89,8 @@ def test_ncl_solve_matches_oracle(which):
         assert np.abs(z[~pm] - z_o[~pm]).max() <= 1e-4 * max(1.0, np.abs(z_o[~pm]).max())
     # the GPU's point is a solution by the oracle's own residual
     sg = I.State(z, host(gst["rt"]), host(gst["s"]), host(gst["zl"]), host(gst["zu"]))
-    pfin = I.Problem(pd=prob.pd, lo=prob.lo, hi=prob.hi, y_n=host(gst["y_n"]), mu=0.0, rho=rep["rho"])
+    pfin = I.Problem(pd=prob.pd, lo=prob.lo, hi=prob.hi, y_n=host(gst["y_n"]), mu=0.0, rho=rep["rho"],
+                     pg0=prob.pg0, vm0=prob.vm0)
     G0 = I.kkt_residual(net, sg, pfin, m)
     assert np.abs(G0).max() <= o.tol
 

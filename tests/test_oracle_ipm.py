@@ -25,9 +25,17 @@ from oracle import dispatch as D
 from oracle import ipm as I
 
 
+def first_stage(net):
+    """Fixed first-stage values of a screening network (seeded)."""
+    g = np.random.default_rng(2510)
+    return g.uniform(1.0, 3.0, net.ng), g.uniform(0.95, 1.05, net.ng)
+
+
 def setup(net, cfg, iteration=0, mu=0.1):
     d, pd = G.draw_ipm_point(net, cfg, iteration=iteration)
     prob = I.Problem(pd=pd, lo=d["lo"], hi=d["hi"], y_n=d["y_n"], mu=mu, rho=net.rho)
+    if net.screen:
+        prob.pg0, prob.vm0 = first_stage(net)
     st = I.State(d["z"], d["rt"], d["s"], d["zl"], d["zu"])
     return prob, st
 
@@ -37,6 +45,8 @@ NETS = {
     "plain": lambda: (G.make_network(8, 5, 6, 2, 1, rho=1e3), 8),
     "single": lambda: (G.make_network(7, 6, 8, 2, 0, rho=1e3), 7),
     "agc": lambda: (G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True), 99),
+    "screen": lambda: (G.make_network(41, 24, 33, 5, 3, pvpq=True, rho=1e5, screen=True), 41),
+    "screen_agc": lambda: (G.make_network(41, 24, 33, 5, 3, pvpq=True, rho=1e5, screen=True, agc=True), 41),
 }
 
 
@@ -250,3 +260,27 @@ def test_agc_rows_vanish_on_the_clipped_recourse():
     for k in range(1, net.nblk):
         pip, pim, spu, spl = pos.acomp[k]
         assert np.abs(z[pip] * z[spu]).max() + np.abs(z[pim] * z[spl]).max() > 0
+
+
+@pytest.mark.parametrize("agc", [False, True])
+def test_screening_blocks_are_the_corrective_contingency_blocks(agc):
+    """eq. (screening): with pg0 and vm0 fixed at a corrective state's first
+    stage, the screening network's constraint values and Lagrangian
+    gradient equal those of the corrective network's contingency blocks at
+    the same block states."""
+    full = G.make_network(41, 24, 33, 5, 3, pvpq=True, rho=1e5, agc=agc)
+    scr = G.make_network(41, 24, 33, 5, 3, pvpq=True, rho=1e5, agc=agc, screen=True)
+    prob_f, st_f = setup(full, 41)
+    pf, ps = A.Positions(full), A.Positions(scr)
+    a, b = pf.block_off[1], pf.block_off[-1]
+    prob_s = I.Problem(pd=prob_f.pd, lo=prob_f.lo[a:b], hi=prob_f.hi[a:b], y_n=prob_f.y_n[a:b], mu=prob_f.mu,
+                       rho=prob_f.rho, pg0=st_f.z[pf.pg], vm0=st_f.z[pf.vm0])
+    zs = st_f.z[a:b]
+    c_f = I.constraints(full, st_f.z, prob_f)
+    c_s = I.constraints(scr, zs, prob_s)
+    np.testing.assert_array_equal(c_s, c_f[a:b])
+    g_f = I.grad_lagrangian(full, st_f.z, prob_f)
+    g_s = I.grad_lagrangian(scr, zs, prob_s)
+    # the contingency blocks' own positions (the corrective gradient also
+    # collects the blocks' terms on the border pg and vm0, absent here)
+    np.testing.assert_allclose(g_s, g_f[a:b], rtol=1e-14, atol=1e-14)
