@@ -53,6 +53,8 @@ WORKLOADS = {
        "rows (N=1335036), rho=1e5, FP64",
     8: "contingency screening of the 500-bus grid's 256 branch-outage contingencies with PV/PQ and AGC droop "
        "rows, first-stage variables fixed: 256 independent blocks, no border (N=1331456), rho=1e5, FP64",
+    9: "2000-bus synthetic grid x 64 branch-outage contingencies with AGC droop complementarity rows "
+       "(N=1138224), rho=1e5, FP64",
 }
 COPY_DOUBLES = 64 * 2 ** 20          # the plain copy whose counters calibrate FETCH_SIZE / WRITE_SIZE
 PROFILE_STRIDE = 7                   # one launch in 7 of the dominant kernel is event-timed in the timed region

@@ -498,6 +498,9 @@ CONFIGS = {
     7: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, agc=True, seed_cfg=3),
     # screening of that grid's 256 contingencies with PV/PQ and AGC rows
     8: dict(nb=500, nl=700, ng=90, ncont=256, pvpq=True, rho=1e5, agc=True, screen=True, seed_cfg=3),
+    # the 2000-bus x 64 grid (config 5's) with AGC droop rows; no PV/PQ rows,
+    # which would double its 360-row border past the dense border's limit
+    9: dict(nb=2000, nl=2800, ng=360, ncont=64, pvpq=False, rho=1e5, agc=True, seed_cfg=5),
 }
 
 

@@ -615,8 +615,10 @@ int ncl_kkt_ipm_step(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *
  *     alpha_p, zl, zu and y at inequality rows by alpha_d.
  * p: the subproblem data as for ncl_kkt_ipm_step; p->rho is the first
  * penalty; p->y_n and p->mu are not read.  s: DEVICE [N] arrays, in: a
- * strictly interior start and the first y_n; out: the last iterate and
- * y_n.  dwork: DEVICE 17 N + 64 doubles.  Synchronises the stream several
+ * strictly interior start (w strictly within its finite bounds with
+ * positive zl, zu there; s and y positive at inequality rows; everything
+ * finite; else NCL_ERR_ARG before any iteration) and the first y_n; out:
+ * the last iterate and y_n.  dwork: DEVICE 17 N + 64 doubles.  Synchronises the stream several
  * times per inner iteration (it reads the inertia, the error norms and the
  * step lengths).  Returns NCL_OK with rep->status 0 (converged), 1 (outer
  * limit) or 2 (inner limit); numerical failures of a step as

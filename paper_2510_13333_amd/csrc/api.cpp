@@ -1778,6 +1778,12 @@ int ncl_kkt_ncl_solve(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_solve_stat
     R.sc = R.part + ncl::vec_reduce_partials(N);
     if (R.sc + 8 > dwork + 17 * N + 64) return NCL_ERR_ARG;
     if (hipMemsetAsync(R.zero, 0, sizeof(double) * size_t(N), st) != hipSuccess) return NCL_ERR_HIP;
+    // the start must be strictly interior (and finite)
+    if (ncl::launch_ipm_point(R.a, ipm_args(pr, cs), ncl::IPM_INTERIOR, nullptr, 0.0, R.e0, nullptr, nullptr, nullptr,
+                              st) != hipSuccess)
+        return NCL_ERR_HIP;
+    if ((rc = R.reduce_max(R.e0, 0)) || (rc = R.read(1))) return rc;
+    if (R.hs[0] != 0.0) return NCL_ERR_ARG;
     *rep = ncl_solve_report{};
     rep->status = 1;
     double eta = o->eta0, mu = o->mu0;

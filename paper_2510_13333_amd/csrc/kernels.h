@@ -108,7 +108,7 @@ struct IpmArgs {
     const double *pg0 = nullptr, *vm0 = nullptr;   // fixed first stage (screening networks)
     double qd_ratio = 0.0, qmax = 0.0, pmax = 0.0, smax2 = 0.0, eps = 0.0, mu = 0.0, rho = 0.0;
 };
-enum IpmMode { IPM_SIGMA = 0, IPM_MASK, IPM_RHS, IPM_RECOVER, IPM_SHIFT, IPM_ERROR, IPM_YN };
+enum IpmMode { IPM_SIGMA = 0, IPM_MASK, IPM_RHS, IPM_RECOVER, IPM_SHIFT, IPM_ERROR, IPM_YN, IPM_INTERIOR };
 hipError_t launch_ipm_point(const DevArgs &a, const IpmArgs &q, int mode, const double *in, double dw, double *o0,
                             double *o1, double *o2, double *o3, hipStream_t st);
 hipError_t launch_ipm_cons(const DevArgs &a, const IpmArgs &q, double *cg, hipStream_t st);

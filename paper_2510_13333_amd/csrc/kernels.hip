@@ -2594,6 +2594,19 @@ __global__ __launch_bounds__(256) void k_ipm_point(DevArgs a, IpmArgs q, int mod
     } else if (mode == IPM_YN) {
         // the first-order multiplier update: y_n takes y at the dual rows
         if (!primal) o0[col] = z;
+    } else if (mode == IPM_INTERIOR) {
+        // 1 where the point is not strictly interior (or not finite), else 0
+        bool ok = z == z && fabs(z) < INFINITY;
+        if (primal) {
+            const double lo = q.lo[col], hi = q.hi[col];
+            if (lo > -INFINITY) ok = ok && z > lo && q.zl[col] > 0.0;
+            if (hi < INFINITY) ok = ok && z < hi && q.zu[col] > 0.0;
+        } else {
+            const double rt = q.rt[col];
+            ok = ok && rt == rt && fabs(rt) < INFINITY;
+            if (comp || flow) ok = ok && z > 0.0 && q.s[col] > 0.0;
+        }
+        o0[col] = ok ? 0.0 : 1.0;
     } else if (mode == IPM_ERROR) {
         // the barrier KKT residual G at this position, at mu (o0) and at 0
         // (o1), as the largest magnitude of its components, and |rt| at dual

@@ -117,6 +117,19 @@ def test_ncl_solve_limits_and_bad_options():
         k.ncl_solve(gprob, gst, SolveOpts(kappa_mu=1.5))
     with pytest.raises(NclError):
         k.ncl_solve(gprob, gst, SolveOpts(rho_max=1.0))
+    # a start that is not strictly interior is refused before any iteration
+    net, cfg, scale = NETS["agc9"]()
+    _, st, gprob, gst = setup(net, cfg, scale)
+    m = I.masks(net, I.Problem(pd=np.zeros(net.nb), lo=G.ncl_bounds(net)[0], hi=G.ncl_bounds(net)[1],
+                               y_n=np.zeros(st.z.shape[0])))
+    for name, idx, val in (("z", int(np.flatnonzero(m.has_lo)[0]), -1.0), ("s", int(np.flatnonzero(m.ineq)[0]), 0.0),
+                           ("zu", int(np.flatnonzero(m.has_hi)[0]), 0.0), ("rt", int(np.flatnonzero(m.dual)[0]), np.nan)):
+        bad = {n: t.clone() for n, t in gst.items()}
+        bad[name][idx] = val
+        before = bad["z"].clone()
+        with pytest.raises(NclError):
+            k.ncl_solve(gprob, bad)
+        assert torch.equal(bad["z"], before)
 
 
 def test_ncl_solve_500bus_256_contingencies_agc():
