@@ -630,7 +630,14 @@ typedef struct {
     double eta0, eta_shrink;            /* 1e-2, 10 */
     double rho_grow, rho_max;           /* 10, 1e12 */
     int32_t max_inner, max_outer;       /* per subproblem 300, 30 */
+    /* optional iteration log (HOST, may be NULL): record t < trace_len of
+     * inner iteration t (counted over all subproblems) holds NCL_TRACE_W
+     * doubles: outer index, mu, E0 and max |G| at mu before the step, the
+     * accepted shift, the factorisations, alpha_p, alpha_d, rho. */
+    double *trace;
+    int32_t trace_len, pad;
 } ncl_solve_opts;
+#define NCL_TRACE_W 9
 typedef struct {
     int32_t status, outer, inner, factorizations;
     double rho, mu, r_inf, kkt_err;     /* at the last iterate (kkt_err = E0) */

@@ -1824,6 +1824,13 @@ int ncl_kkt_ncl_solve(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_solve_stat
                 return NCL_ERR_HIP;
             if ((rc = R.reduce_max(R.e0, 0)) || (rc = R.reduce_max(R.e1, 1)) || (rc = R.read(2))) return rc;
             const double ap = 1.0 / R.hs[0], ad = 1.0 / R.hs[1];
+            const int t = rep->inner + its;
+            if (o->trace && t < o->trace_len) {
+                double *rec = o->trace + size_t(t) * NCL_TRACE_W;
+                const double v[NCL_TRACE_W] = {double(outer), mu, e0, emu, dw_last, double(io.nfactor), ap, ad,
+                                               pr.rho};
+                std::memcpy(rec, v, sizeof(v));
+            }
             if (ncl::launch_ipm_line(R.a, q, mv, ncl::IPM_UPDATE, ap, ad, nullptr, nullptr, st) != hipSuccess)
                 return NCL_ERR_HIP;
             its++;

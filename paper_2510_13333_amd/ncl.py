@@ -19,6 +19,7 @@ _lib = None
 NCL_PVPQ = 1
 NCL_SCREEN = 2
 NCL_AGC = 4
+NCL_TRACE_W = 9
 
 # kernel kinds (NCL_K_* of ncl_kkt.h), in enum order
 KERNELS = ["assemble", "values", "fac_gather", "fac_diag", "fac_rows", "border_schur", "border_sum",
@@ -101,13 +102,23 @@ class SolveOpts(ctypes.Structure):
                 ("mu_warm", ctypes.c_double), ("kappa_eps", ctypes.c_double), ("kappa_mu", ctypes.c_double),
                 ("theta_mu", ctypes.c_double), ("tau_min", ctypes.c_double), ("eta0", ctypes.c_double),
                 ("eta_shrink", ctypes.c_double), ("rho_grow", ctypes.c_double), ("rho_max", ctypes.c_double),
-                ("max_inner", ctypes.c_int32), ("max_outer", ctypes.c_int32)]
+                ("max_inner", ctypes.c_int32), ("max_outer", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("trace_len", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
-    def __init__(self, **kw):
+    def __init__(self, trace=None, **kw):
+        """trace: an optional float64 numpy array (n, NCL_TRACE_W) that the
+        solve fills with its iteration log (kept alive by this object)."""
         d = dict(tol=1e-6, mu_min=1e-7, mu0=0.1, mu_warm=1e-5, kappa_eps=10.0, kappa_mu=0.2, theta_mu=1.5,
                  tau_min=0.99, eta0=1e-2, eta_shrink=10.0, rho_grow=10.0, rho_max=1e12, max_inner=300, max_outer=30)
         d.update(kw)
         super().__init__(**d)
+        self._trace = trace
+        if trace is not None:
+            if trace.dtype != np.float64 or trace.ndim != 2 or trace.shape[1] != NCL_TRACE_W or \
+                    not trace.flags["C_CONTIGUOUS"]:
+                raise ValueError("trace must be a contiguous float64 array of shape (n, NCL_TRACE_W)")
+            self.trace = trace.ctypes.data_as(ctypes.c_void_p)
+            self.trace_len = trace.shape[0]
 
 
 class _SolveReport(ctypes.Structure):

@@ -153,3 +153,31 @@ def test_ncl_solve_500bus_256_contingencies_agc():
     z = sg.z
     target = z[pos.pg][None, :] + net.gen_alpha[None, :] * z[pos.delta[1:]][:, None]
     assert np.abs(z[pos.pgk[1:]] - np.clip(target, 0.0, prob.pmax)).max() <= 1e-3
+
+
+def test_ncl_solve_iteration_log():
+    """The optional iteration log: one record per inner iteration, the outer
+    index of each matching the oracle's iterations per subproblem, the
+    barrier parameter non-increasing inside a subproblem, step lengths in
+    (0, 1], and the penalty of the record its subproblem's."""
+    from paper_2510_13333_amd.ncl import NCL_TRACE_W
+    net, cfg, scale = NETS["agc9"]()
+    prob, st, gprob, gst = setup(net, cfg, scale)
+    _, _, rep_o = NC.solve(net, prob, st)
+    k = KKT(net).bind(nrhs_max=1)
+    tr = np.full((200, NCL_TRACE_W), np.nan)
+    rep = k.ncl_solve(gprob, gst, SolveOpts(trace=tr))
+    n = rep["inner"]
+    assert np.isfinite(tr[:n]).all() and np.isnan(tr[n:]).all()
+    per_outer = np.bincount(tr[:n, 0].astype(int), minlength=rep["outer"])
+    assert list(per_outer) == [h[0] for h in rep_o.history]
+    for o in range(rep["outer"]):
+        mu = tr[:n][tr[:n, 0] == o, 1]
+        assert (np.diff(mu) <= 0).all()
+    assert ((tr[:n, 6] > 0) & (tr[:n, 6] <= 1) & (tr[:n, 7] > 0) & (tr[:n, 7] <= 1)).all()
+    assert (tr[:n, 8] == net.rho).all()
+    # a log shorter than the run keeps its first records only
+    _, _, gprob2, gst2 = setup(net, cfg, scale)
+    short = np.full((5, NCL_TRACE_W), np.nan)
+    k.ncl_solve(gprob2, gst2, SolveOpts(trace=short))
+    np.testing.assert_array_equal(short, tr[:5])
