@@ -357,7 +357,7 @@ def run_single(args):
 
     ncl = None
     if not args.no_ncl and args.gpus == 1:
-        ncl = ncl_solve_run(args.ncl_config)
+        ncl = ncl_solve_run(args.ncl_config, args.ncl_load_scale)
         print(f"[bench] NCL solve: {ncl['s']:.3f} s, status {ncl['status']}, {ncl['outer']} outer / {ncl['inner']} "
               f"inner iterations, {ncl['factorizations']} factorisations", file=sys.stderr, flush=True)
         sc = ncl.get("screening")
@@ -462,13 +462,13 @@ def ipm_steps(k, net, cfg, steps):
 NCL_LOAD_SCALE = 0.1     # the NCL workload's loads: this fraction of the seeded pd
 
 
-def ncl_solve_run(cfg):
+def ncl_solve_run(cfg, load_scale=NCL_LOAD_SCALE):
     """The NCL method end to end (ncl_kkt_ncl_solve) on config cfg's network
-    (the 500-bus x 256 grid with PV/PQ and AGC droop rows): from the fixed
-    interior start, loads NCL_LOAD_SCALE x the seeded pd, the network's rho
-    as the first penalty, tolerance 1e-6 and smallest barrier parameter 1e-7
-    (Section V); wall clock of the whole solve, the analysis before it
-    untimed.  One warm-up solve of the same problem first."""
+    (by default the 500-bus x 256 grid with PV/PQ and AGC droop rows): from
+    the fixed interior start, loads load_scale x the seeded pd, the
+    network's rho as the first penalty, tolerance 1e-6 and smallest barrier
+    parameter 1e-7 (Section V); wall clock of the whole solve, the analysis
+    before it untimed.  One warm-up solve of the same problem first."""
     import torch
     import gridgen as G
     from paper_2510_13333_amd import KKT
@@ -478,7 +478,7 @@ def ncl_solve_run(cfg):
     k = KKT(net).bind(nrhs_max=1)
     t_an = time.perf_counter() - t0
     st0 = G.ncl_start(net)
-    pd = NCL_LOAD_SCALE * G.draw_loads(net, cfg)
+    pd = load_scale * G.draw_loads(net, cfg)
     prob = dict(pd=dev(pd), lo=dev(st0["lo"]), hi=dev(st0["hi"]), qd_ratio=0.3, qmax=3.0, pmax=8.0, smax2=100.0,
                 eps=1.0, rho=net.rho)
     work = torch.empty(17 * k.N + 64, dtype=torch.float64, device="cuda")
@@ -496,7 +496,7 @@ def ncl_solve_run(cfg):
     rep, t, state = run()
     screen = ncl_screen_run(net, cfg, pd, state) if cfg == 7 else None
     return {"what": "the NCL method end to end (outer multiplier / penalty updates around the subproblem's "
-                    "primal-dual IPM, every step on the GPU) on " + WORKLOADS[cfg] + f", loads {NCL_LOAD_SCALE} x "
+                    "primal-dual IPM, every step on the GPU) on " + WORKLOADS[cfg] + f", loads {load_scale} x "
                     "the seeded pd, from the fixed interior start; tol 1e-6, smallest mu 1e-7",
             "N": k.N, "s": t, "status": rep["status"], "outer": rep["outer"], "inner": rep["inner"],
             "factorizations": rep["factorizations"], "ms_per_inner": 1e3 * t / max(1, rep["inner"]),
@@ -769,6 +769,8 @@ def main():
     ap.add_argument("--no-ipm", action="store_true", help="skip the IPM-step timing")
     ap.add_argument("--no-ncl", action="store_true", help="skip the NCL-solve timing")
     ap.add_argument("--ncl-config", type=int, default=7, help="network of the NCL-solve timing")
+    ap.add_argument("--ncl-load-scale", type=float, default=NCL_LOAD_SCALE,
+                    help="the NCL workload's loads as a fraction of the seeded pd")
     ap.add_argument("--ipm-steps", type=int, default=5, help="interior points of the IPM-step timing")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default=None)
