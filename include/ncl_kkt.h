@@ -622,7 +622,7 @@ int ncl_kkt_ipm_step(ncl_kkt *h, const ncl_ipm_problem *p, const ncl_ipm_state *
  * times per inner iteration (it reads the inertia, the error norms and the
  * step lengths).  Returns NCL_OK with rep->status 0 (converged), 1 (outer
  * limit) or 2 (inner limit); numerical failures of a step as
- * ncl_kkt_ipm_step (rep then holds the counts so far). */
+ * ncl_kkt_ipm_step, with rep->status 3 and the counts so far. */
 typedef struct {
     double tol, mu_min;                 /* 1e-6, 1e-7 */
     double mu0, mu_warm;                /* 0.1, 1e-5 */

@@ -1815,6 +1815,7 @@ int ncl_kkt_ncl_solve(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_solve_stat
             rep->factorizations += io.nfactor;
             if (rc) {
                 rep->inner += its;
+                rep->status = 3;
                 return rc;
             }
             dw_last = io.dw_last;
