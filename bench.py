@@ -504,6 +504,41 @@ def ncl_solve_run(cfg, load_scale=NCL_LOAD_SCALE):
             "screening": screen}
 
 
+def ncl_sweep(ks, load_scale=NCL_LOAD_SCALE):
+    """The NCL solve as the number of contingencies K grows (the shape of
+    Table II): the 500-bus grid with PV/PQ and AGC rows and K outages (the
+    grid and loads of config 3's seed; each K draws its own outage set),
+    from the fixed start, one warm-up and one timed solve each."""
+    import torch
+    import gridgen as G
+    from paper_2510_13333_amd import KKT
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).to("cuda")
+    rows = []
+    for K in ks:
+        net = G.make_network(3, 500, 700, 90, K, pvpq=True, rho=1e5, agc=True)
+        k = KKT(net).bind(nrhs_max=1)
+        st0 = G.ncl_start(net)
+        pd = load_scale * G.draw_loads(net, 3)
+        prob = dict(pd=dev(pd), lo=dev(st0["lo"]), hi=dev(st0["hi"]), qd_ratio=0.3, qmax=3.0, pmax=8.0,
+                    smax2=100.0, eps=1.0, rho=net.rho)
+        work = torch.empty(17 * k.N + 64, dtype=torch.float64, device="cuda")
+        for timed in (False, True):
+            st = {n: dev(st0[n]) for n in ("z", "rt", "s", "zl", "zu")}
+            st["y_n"] = torch.zeros(k.N, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rep = k.ncl_solve(prob, st, work=work)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+        row = {"K": K, "N": k.N, "s": t, "status": rep["status"], "outer": rep["outer"], "inner": rep["inner"],
+               "factorizations": rep["factorizations"], "ms_per_inner": 1e3 * t / max(1, rep["inner"])}
+        rows.append(row)
+        print(f"[bench] NCL sweep K={K}: N={k.N} {t:.3f} s, status {rep['status']}, {rep['outer']} outer / "
+              f"{rep['inner']} inner, {rep['factorizations']} factorisations", file=sys.stderr, flush=True)
+        del k, work
+    return rows
+
+
 def ncl_screen_run(net, cfg, pd, state):
     """Contingency screening (eq. (screening)) at the first stage of the NCL
     solution just computed: the same grid's 256 contingencies with the
@@ -769,6 +804,9 @@ def main():
     ap.add_argument("--no-ipm", action="store_true", help="skip the IPM-step timing")
     ap.add_argument("--no-ncl", action="store_true", help="skip the NCL-solve timing")
     ap.add_argument("--ncl-config", type=int, default=7, help="network of the NCL-solve timing")
+    ap.add_argument("--ncl-sweep", default=None,
+                    help="comma-separated contingency counts: time the NCL solve on the 500-bus grid with PV/PQ "
+                         "and AGC rows at each, and report only that")
     ap.add_argument("--ncl-load-scale", type=float, default=NCL_LOAD_SCALE,
                     help="the NCL workload's loads as a fraction of the seeded pd")
     ap.add_argument("--ipm-steps", type=int, default=5, help="interior points of the IPM-step timing")
@@ -782,7 +820,13 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is documented, "
               "not built", file=sys.stderr)
         sys.exit(2)
-    if args.config == 4:
+    if args.ncl_sweep:
+        ks = [int(x) for x in args.ncl_sweep.split(",")]
+        print(json.dumps({"what": "NCL solve against the number of contingencies (the shape of Table II): the "
+                                  "500-bus synthetic grid with PV/PQ and AGC rows, loads "
+                                  f"{args.ncl_load_scale} x the seeded pd, tol 1e-6",
+                          "rows": ncl_sweep(ks, args.ncl_load_scale)}))
+    elif args.config == 4:
         run_batched(args)
     else:
         run_single(args)
