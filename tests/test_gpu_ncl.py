@@ -41,8 +41,12 @@ NETS = {
     # contingency screening (eq. (screening)): six contingencies at a fixed
     # first stage, their feasibility problems solved together
     "screen_agc60x6": lambda: (G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True, agc=True), 43, 0.1),
+    # the smallest AGC networks: one generator and one contingency, and one
+    # generator with two contingencies (three outer iterations)
+    "agc4x1_g1": lambda: (G.make_network(61, 4, 5, 1, 1, rho=1e5, agc=True), 61, 0.1),
+    "agc6x2_g1": lambda: (G.make_network(62, 6, 8, 1, 2, rho=1e5, agc=True), 62, 0.1),
 }
-EXACT_COUNTS = {"single7", "c1", "agc9", "agc30x3", "screen_agc60x6"}
+EXACT_COUNTS = {"single7", "c1", "agc9", "agc30x3", "screen_agc60x6", "agc4x1_g1", "agc6x2_g1"}
 
 
 def setup(net, cfg, scale):

@@ -174,6 +174,13 @@ def test_agc_small(pvpq):
     run_case(net, 99, nrhs=2)
 
 
+@pytest.mark.parametrize("pvpq", [False, True])
+def test_agc_degenerate_sizes(pvpq):
+    """One generator (delta's column has one entry), one or two contingencies."""
+    for nb, nl, ng, K, seed in ((4, 5, 1, 1, 61), (6, 8, 1, 2, 62), (5, 7, 2, 1, 63)):
+        run_case(G.make_network(seed, nb, nl, ng, K, pvpq=pvpq, rho=1e5, agc=True), seed, nrhs=2)
+
+
 def test_agc_screening():
     """Screening with AGC rows: no pg0 column in ALIN, no border."""
     net = G.make_network(43, 60, 84, 9, 6, pvpq=True, rho=1e5, screen=True, agc=True)

@@ -306,3 +306,17 @@ def test_agc_network_checks():
     single.gen_alpha = np.full(6, 1.0 / 6)
     with pytest.raises(NclError):
         KKT(single)
+
+
+@pytest.mark.parametrize("pvpq", [False, True])
+def test_agc_degenerate_sizes_match_oracle(pvpq):
+    """AGC rows at their smallest: one generator (delta's column has one
+    entry) and one contingency; pattern and symbolic bit-exact."""
+    for nb, nl, ng, K, seed in ((4, 5, 1, 1, 61), (6, 8, 1, 2, 62), (5, 7, 2, 1, 63)):
+        net = G.make_network(seed, nb, nl, ng, K, pvpq=pvpq, rho=1e5, agc=True)
+        z, s = G.draw_point(net, seed)
+        cp, ri, _, pos = O.kkt(net, z, s)
+        k = KKT(net)
+        kcp, kri = k.pattern()
+        assert k.N == pos.N and np.array_equal(kcp, cp) and np.array_equal(kri, ri), (nb, ng, K)
+        _compare(k, O.Factor.from_network(net))
