@@ -1381,9 +1381,11 @@ namespace {
 // Assemble the exact K (no diagonal shift) at (z, sig) and factor it; ok:
 // the inertia (n, m) of the Newton matrix of a minimum, no zero or
 // non-finite pivot (single pivots may carry the other sign).
-int factor_exact(Handle &h, ncl_kkt *k, const double *z, const double *sig, double rho, bool &ok, hipStream_t st) {
+// assembled: K at (z, sig) without the shift is already in the handle
+int factor_exact(Handle &h, ncl_kkt *k, const double *z, const double *sig, double rho, bool &ok, hipStream_t st,
+                 bool assembled = false) {
     ncl_kkt_point pt{z, sig, rho, NCL_NO_SHIFT};
-    int rc = ncl_kkt_assemble(k, &pt, st);
+    int rc = assembled ? NCL_OK : ncl_kkt_assemble(k, &pt, st);
     if (!rc) rc = ncl_kkt_factor(k, st);
     ncl_kkt_report rep{};
     if (!rc) rc = ncl_kkt_info(k, &rep, st);
@@ -1397,11 +1399,11 @@ int factor_exact(Handle &h, ncl_kkt *k, const double *z, const double *sig, doub
 // then sig + dw on the primal positions with dw from a third of the last
 // accepted shift (or 1e-4), growing x8 below 1e12.  sgs: N doubles.
 int inertia_loop(Handle &h, ncl_kkt *k, const double *z, const double *sig, double rho, double &dw_last, int &nfac,
-                 double *sgs, hipStream_t st) {
+                 double *sgs, hipStream_t st, bool first_assembled = false) {
     const ncl::DevArgs a = dev_args(h);
     bool ok = false;
     nfac = 1;
-    int rc = factor_exact(h, k, z, sig, rho, ok, st);
+    int rc = factor_exact(h, k, z, sig, rho, ok, st, first_assembled);
     if (rc) return rc;
     if (ok) {
         dw_last = 0.0;
@@ -1708,7 +1710,7 @@ struct NclRun {
     hipStream_t st;
     ncl::DevArgs a;
     int64_t N;
-    double *cg, *e0, *e1, *e2, *zero, *part, *sc;
+    double *cg, *e0, *e1, *e2, *sg, *part, *sc;
     double hs[4] = {0, 0, 0, 0};
     int read(int n) {
         if (hipMemcpyAsync(hs, sc, sizeof(double) * size_t(n), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1719,12 +1721,17 @@ struct NclRun {
     int reduce_max(const double *x, int slot) {
         return hip_rc(ncl::launch_vec_reduce(N, x, x, 0.0, 1, part, sc + slot, st));
     }
-    // J'y at the point (K's Jacobian blocks at z), c(w) and grad phi
+    // at the point: sigma and K (no shift), which is also the first matrix
+    // of the step's inertia correction; J'y from K's Jacobian blocks (the
+    // primal rows of x - Kx for x = (0, y) do not depend on sigma), c(w) and
+    // grad phi, which the step's right-hand side reuses
     int prepare(const ncl_ipm_problem &p, const ncl_ipm_state &s, double rho) {
-        ncl_kkt_point pt{s.z, zero, rho, NCL_NO_SHIFT};
+        const ncl::IpmArgs q = ipm_args(p, s);
+        if (ncl::launch_ipm_point(a, q, ncl::IPM_SIGMA, nullptr, 0.0, sg, nullptr, nullptr, nullptr, st) != hipSuccess)
+            return NCL_ERR_HIP;
+        ncl_kkt_point pt{s.z, sg, rho, NCL_NO_SHIFT};
         int rc = ncl_kkt_assemble(k, &pt, st);
         if (rc) return rc;
-        const ncl::IpmArgs q = ipm_args(p, s);
         if (ncl::launch_ipm_point(a, q, ncl::IPM_MASK, nullptr, 0.0, e0, nullptr, nullptr, nullptr, st) != hipSuccess)
             return NCL_ERR_HIP;
         if ((rc = residual_column(h, a, e0, e0, nullptr, st))) return rc;
@@ -1741,6 +1748,25 @@ struct NclRun {
         return rc ? rc : read(all ? 3 : 1);
     }
 };
+
+// ncl_kkt_ipm_step after NclRun::prepare at the same point: sigma, K(z,
+// sigma) without the shift, J'y and c(w) are in place.  wk: 2 N doubles.
+int ipm_step_prepared(Handle &h, ncl_kkt *k, const ncl_ipm_problem &p, const ncl_ipm_state &s,
+                      const ncl_ipm_direction &d, ncl_inertia_opts &o, const double *sg, const double *cg, double *wk,
+                      hipStream_t st) {
+    const ncl::DevArgs a = dev_args(h);
+    const ncl::IpmArgs q = ipm_args(p, s);
+    const int64_t N = h.N;
+    int nfac = 0;
+    int rc = inertia_loop(h, k, s.z, sg, p.rho, o.dw_last, nfac, wk, st, true);
+    o.nfactor = nfac;
+    if (rc) return rc;
+    double *r = wk + N;
+    if (ncl::launch_ipm_point(a, q, ncl::IPM_RHS, cg, 0.0, r, nullptr, nullptr, nullptr, st) != hipSuccess)
+        return NCL_ERR_HIP;
+    if ((rc = ncl_kkt_solve(k, r, d.dz, 1, N, st))) return rc;
+    return hip_rc(ncl::launch_ipm_point(a, q, ncl::IPM_RECOVER, d.dz, 0.0, d.drt, d.ds, d.dzl, d.dzu, st));
+}
 
 int solve_opts_ok(const ncl_solve_opts *o, double rho) {
     return o->tol > 0 && o->mu_min > 0 && o->mu0 >= o->mu_min && o->mu_warm >= o->mu_min && o->kappa_eps > 0 &&
@@ -1766,18 +1792,17 @@ int ncl_kkt_ncl_solve(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_solve_stat
     const int64_t N = h.N;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     // dwork: the direction (5 N), ncl_kkt_ipm_step's work (3 N), c and grad
-    // phi, three error vectors, a zero sigma, reduction partials, scalars
+    // phi, three error vectors, sigma, reduction partials, scalars
     double *dz = dwork, *drt = dz + N, *ds = drt + N, *dzl = ds + N, *dzu = dzl + N, *wk = dzu + N;
     NclRun R{h, k, st, dev_args(h), N};
     R.cg = wk + 3 * N;
     R.e0 = R.cg + N;
     R.e1 = R.e0 + N;
     R.e2 = R.e1 + N;
-    R.zero = R.e2 + N;
-    R.part = R.zero + N;
+    R.sg = R.e2 + N;
+    R.part = R.sg + N;
     R.sc = R.part + ncl::vec_reduce_partials(N);
     if (R.sc + 8 > dwork + 17 * N + 64) return NCL_ERR_ARG;
-    if (hipMemsetAsync(R.zero, 0, sizeof(double) * size_t(N), st) != hipSuccess) return NCL_ERR_HIP;
     // the start must be strictly interior (and finite)
     if (ncl::launch_ipm_point(R.a, ipm_args(pr, cs), ncl::IPM_INTERIOR, nullptr, 0.0, R.e0, nullptr, nullptr, nullptr,
                               st) != hipSuccess)
@@ -1811,7 +1836,7 @@ int ncl_kkt_ncl_solve(ncl_kkt *k, const ncl_ipm_problem *p, const ncl_solve_stat
                 break;
             }
             ncl_inertia_opts io{dw_last, 0, 0};
-            rc = ncl_kkt_ipm_step(k, &pr, &cs, &dir, &io, wk, stream);
+            rc = ipm_step_prepared(h, k, pr, cs, dir, io, R.sg, R.cg, wk, st);
             rep->factorizations += io.nfactor;
             if (rc) {
                 rep->inner += its;
