@@ -360,6 +360,11 @@ def run_single(args):
         ncl = ncl_solve_run(args.ncl_config, args.ncl_load_scale)
         print(f"[bench] NCL solve: {ncl['s']:.3f} s, status {ncl['status']}, {ncl['outer']} outer / {ncl['inner']} "
               f"inner iterations, {ncl['factorizations']} factorisations", file=sys.stderr, flush=True)
+        if not args.no_cpu:
+            ncl["cpu_oracle"] = ncl_oracle_beside(args.ncl_load_scale)
+            co = ncl["cpu_oracle"]
+            print(f"[bench] NCL solve, 500-bus x 4: oracle {co['oracle_s']:.1f} s ({co['oracle_inner']} inner), "
+                  f"library {co['gpu_s']:.3f} s ({co['gpu_inner']} inner)", file=sys.stderr, flush=True)
         sc = ncl.get("screening")
         if sc:
             print(f"[bench] screening at that first stage: {sc['s']:.3f} s ({sc['ms_per_contingency']:.3f} ms per "
@@ -537,6 +542,43 @@ def ncl_sweep(ks, load_scale=NCL_LOAD_SCALE):
               f"{rep['inner']} inner, {rep['factorizations']} factorisations", file=sys.stderr, flush=True)
         del k, work
     return rows
+
+
+def ncl_oracle_beside(load_scale=NCL_LOAD_SCALE):
+    """The oracle's NCL solve (oracle/ncl.py, numpy with the C LDL^T on one
+    thread) timed beside the library's on one bounded instance: the 500-bus
+    grid with PV/PQ and AGC rows and 4 contingencies (N = 24384), the same
+    start, loads and options.  Both solves and their iteration counts."""
+    import torch
+    import gridgen as G
+    from oracle import ipm as OI
+    from oracle import ncl as ON
+    from paper_2510_13333_amd import KKT
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).to("cuda")
+    net = G.make_network(3, 500, 700, 90, 4, pvpq=True, rho=1e5, agc=True)
+    st0 = G.ncl_start(net)
+    pd = load_scale * G.draw_loads(net, 3)
+    N = st0["z"].shape[0]
+    prob = OI.Problem(pd=pd, lo=st0["lo"], hi=st0["hi"], y_n=np.zeros(N), mu=0.1, rho=net.rho)
+    t = time.perf_counter()
+    _, _, rep_o = ON.solve(net, prob, OI.State(st0["z"], st0["rt"], st0["s"], st0["zl"], st0["zu"]))
+    t_o = time.perf_counter() - t
+    k = KKT(net).bind(nrhs_max=1)
+    gprob = dict(pd=dev(pd), lo=dev(st0["lo"]), hi=dev(st0["hi"]), qd_ratio=0.3, qmax=3.0, pmax=8.0, smax2=100.0,
+                 eps=1.0, rho=net.rho)
+    work = torch.empty(17 * k.N + 64, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        st = {n: dev(st0[n]) for n in ("z", "rt", "s", "zl", "zu")}
+        st["y_n"] = torch.zeros(k.N, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rep = k.ncl_solve(gprob, st, work=work)
+        torch.cuda.synchronize()
+        t_g = time.perf_counter() - t
+    return {"what": "the oracle's NCL solve (numpy, C LDL^T on 1 thread) beside the library's on the 500-bus grid "
+                    "with PV/PQ and AGC rows and 4 contingencies, the same start, loads and options",
+            "N": N, "oracle_s": t_o, "oracle_outer": rep_o.outer, "oracle_inner": rep_o.inner, "gpu_s": t_g,
+            "gpu_outer": rep["outer"], "gpu_inner": rep["inner"], "cores": 1}
 
 
 def ncl_screen_run(net, cfg, pd, state):
