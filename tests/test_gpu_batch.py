@@ -23,13 +23,16 @@ def dev(a):
 
 
 def mixed_networks(rho=1e4):
-    """Uneven small instances: no border, plain border, PV/PQ border."""
+    """Uneven small instances: no border, plain border, PV/PQ border, and
+    AGC rows with and without PV/PQ rows."""
     return [
         G.make_network(41, 30, 41, 6, 0, rho=rho, instance=0),
         G.make_network(41, 60, 84, 11, 5, rho=rho, instance=1),
         G.make_network(41, 24, 33, 4, 3, pvpq=True, rho=rho, instance=2),
         G.make_network(41, 118, 165, 21, 9, rho=rho, instance=3),
         G.make_network(41, 45, 63, 8, 2, pvpq=True, rho=rho, instance=4),
+        G.make_network(41, 36, 50, 7, 4, pvpq=True, rho=rho, instance=5, agc=True),
+        G.make_network(41, 50, 70, 9, 3, rho=rho, instance=6, agc=True),
     ]
 
 

@@ -201,8 +201,9 @@ def test_batch_symbolic_is_per_instance_symbolic():
     network's own analysis (global indices offset by the instance's first
     column), also with per-instance amalgamation parameters."""
     nets = [G.make_network(41, 30, 41, 6, 0, instance=0), G.make_network(41, 60, 84, 11, 5, instance=1),
-            G.make_network(41, 24, 33, 4, 3, pvpq=True, instance=2)]
-    relax = [(8, 1, 4), (16, 1, 2), (4, 1, 4)]
+            G.make_network(41, 24, 33, 4, 3, pvpq=True, instance=2),
+            G.make_network(41, 36, 50, 7, 4, pvpq=True, instance=5, agc=True)]
+    relax = [(8, 1, 4), (16, 1, 2), (4, 1, 4), (16, 1, 4)]
     kb = KKT(nets=nets, relax=relax)
     sb = kb.symbolic()
     cpb, rib = kb.pattern()
