@@ -164,3 +164,27 @@ def test_outer_updates():
     _, y2, rep2 = NC.solve(net, prob, st, NC.Opts(max_outer=1, eta0=1e-9))
     assert rep2.history[0][3] is False and rep2.history[0][2] == 10 * prob.rho
     assert not y2[m.dual].any()
+
+
+def test_screening_at_the_corrective_solution_is_feasible():
+    """eq. (screening): at the first stage (pg0, vm0) of a converged
+    corrective NCL solution every contingency is feasible, so the screening
+    network's NCL solve over the same contingencies converges with r -> 0;
+    and its blocks' primal values satisfy the AGC rule of eq. (agc)."""
+    from oracle.assemble import Positions
+    net = G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True)
+    prob, st = problem(net, 99)
+    st1, _, rep = NC.solve(net, prob, st)
+    assert rep.status == 0
+    pos = Positions(net)
+    pg0, vm0 = st1.z[pos.pg], st1.z[pos.vm0]
+    scr = G.make_network(99, 9, 12, 3, 2, pvpq=True, rho=1e5, agc=True, screen=True)
+    st0 = G.ncl_start(scr)
+    N = st0["z"].shape[0]
+    prob_s = I.Problem(pd=prob.pd, lo=st0["lo"], hi=st0["hi"], y_n=np.zeros(N), mu=0.1, rho=scr.rho, pg0=pg0, vm0=vm0)
+    ss, _, rep_s = NC.solve(scr, prob_s, I.State(st0["z"], st0["rt"], st0["s"], st0["zl"], st0["zu"]))
+    assert rep_s.status == 0 and rep_s.r_inf <= 1e-6
+    ps = Positions(scr)
+    for k in range(scr.nblk):
+        target = pg0 + scr.gen_alpha * ss.z[ps.delta[k]]
+        assert np.abs(ss.z[ps.pgk[k]] - np.clip(target, 0.0, prob_s.pmax)).max() <= 1e-3
