@@ -1044,6 +1044,22 @@ static int factor_levels(Handle &h, const ncl::DevArgs &a, hipStream_t st) {
     return NCL_OK;
 }
 
+// One level of the blocks' factorisation (the combined call's pipeline).
+static int factor_level(Handle &h, const ncl::DevArgs &a, int l, hipStream_t st) {
+    const ncl::Schedule &S = h.sched;
+    const ncl::Work *W = h.d.work;
+    auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr) {
+        ncl::LaunchArgs la;
+        la.wl = W + off + ptr[l];
+        la.nw = ptr[l + 1] - ptr[l];
+        return run(h, kind, a, la, st);
+    };
+    if (list(NCL_K_FAC_GATHER, h.w_a, S.a_ptr) != hipSuccess || list(NCL_K_FAC_DIAG, h.w_b, S.b_ptr) != hipSuccess ||
+        list(NCL_K_FAC_ROWS, h.w_c, S.c_ptr) != hipSuccess)
+        return NCL_ERR_HIP;
+    return NCL_OK;
+}
+
 // The border: the Schur products (schur = true; beside other work when
 // shared), their sum and the dense border factor.
 static int border_launches(Handle &h, const ncl::DevArgs &a, bool schur, bool shared, hipStream_t st) {
@@ -1214,31 +1230,42 @@ static ncl::LaunchArgs solve_args(Handle &h, const double *b, double *x, int nrh
     return v;
 }
 
-static int solve_first_half(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, bool check, hipStream_t st) {
+// The first half of a solve: the right-hand side loaded into the
+// interleaved order (without the factor's status check in the combined
+// call, whose status comes later), the forward substitution level by level,
+// and the border rows' partial sums.
+static int solve_load(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, hipStream_t st, bool check = false) {
+    ncl::LaunchArgs la = v;
+    la.nocheck = !check;
+    return run(h, NCL_K_SOL_LOAD, a, la, st) != hipSuccess ? NCL_ERR_HIP : NCL_OK;
+}
+
+static int solve_forward_level(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, int l, hipStream_t st) {
     const ncl::Schedule &S = h.sched;
     const ncl::Work *W = h.d.work;
-    auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr, int l) {
+    auto list = [&](int kind, size_t off, const std::vector<int32_t> &ptr) {
         ncl::LaunchArgs la = v;
         la.wl = W + off + ptr[l];
         la.nw = ptr[l + 1] - ptr[l];
         return run(h, kind, a, la, st);
     };
-    {
-        ncl::LaunchArgs la = v;
-        la.nocheck = !check;
-        if (run(h, NCL_K_SOL_LOAD, a, la, st) != hipSuccess) return NCL_ERR_HIP;
-    }
-    for (int l = 0; l < S.nlev; l++) {
-        if (list(NCL_K_SOL_FWD_GATHER, h.w_f, S.f_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-        if (list(NCL_K_SOL_FWD_DIAG, h.w_d, S.d_ptr, l) != hipSuccess) return NCL_ERR_HIP;
-    }
-    if (h.nbd_tot) {
-        ncl::LaunchArgs la = v;
-        la.wl = W + h.w_bpart;
-        la.nw = int(S.bpart.size());
-        if (run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess) return NCL_ERR_HIP;
-    }
+    if (list(NCL_K_SOL_FWD_GATHER, h.w_f, S.f_ptr) != hipSuccess || list(NCL_K_SOL_FWD_DIAG, h.w_d, S.d_ptr) != hipSuccess)
+        return NCL_ERR_HIP;
     return NCL_OK;
+}
+
+static int solve_border_partials(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, hipStream_t st) {
+    if (!h.nbd_tot) return NCL_OK;
+    ncl::LaunchArgs la = v;
+    la.wl = h.d.work + h.w_bpart;
+    la.nw = int(h.sched.bpart.size());
+    return run(h, NCL_K_SOL_BPART, a, la, st) != hipSuccess ? NCL_ERR_HIP : NCL_OK;
+}
+
+static int solve_first_half(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, bool check, hipStream_t st) {
+    int rc = solve_load(h, a, v, st, check);
+    for (int l = 0; !rc && l < h.sched.nlev; l++) rc = solve_forward_level(h, a, v, l, st);
+    return rc ? rc : solve_border_partials(h, a, v, st);
 }
 
 static int solve_second_half(Handle &h, const ncl::DevArgs &a, const ncl::LaunchArgs &v, hipStream_t st) {
@@ -1287,6 +1314,16 @@ static int side_stream(Handle &h) {
     h.side = s;
     h.ev_fork = e0;
     h.ev_join = e1;
+    return NCL_OK;
+}
+
+// one event per factor level (created once per handle)
+static int level_events(Handle &h) {
+    while (int(h.ev_lev.size()) < h.sched.nlev) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return NCL_ERR_HIP;
+        h.ev_lev.push_back(e);
+    }
     return NCL_OK;
 }
 
@@ -1965,33 +2002,60 @@ int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs,
     h.blocks_done = false;
     h.factored = false;
     h.factor_failed = false;
-    int rc = factor_levels(h, a, st);
-    if (rc) return rc;
     // a border of fewer than kForkMinBorder rows is factored in line: its
-    // work is too short to hide behind the forward substitution, and the
-    // fork and join would cost more than they save
+    // work is too short to hide, and the fork and join would cost more than
+    // they save
     constexpr int kForkMinBorder = 128;
     const bool fork = h.max_nbd >= kForkMinBorder;
-    hipStream_t side = nullptr;
-    if (fork) {
-        if ((rc = side_stream(h))) return rc;
-        side = static_cast<hipStream_t>(h.side);
+    const ncl::LaunchArgs v = solve_args(h, db, dx, nrhs, ld, false);
+    const ncl::LaunchArgs none;
+    int rc = NCL_OK;
+    if (!fork) {
+        if ((rc = factor_levels(h, a, st))) return rc;
+        if (h.nbd_tot && (rc = border_launches(h, a, true, false, st))) return rc;
+        for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
+            if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
+        if ((rc = solve_first_half(h, a, v, false, st))) return rc;
+    } else if (big_border(h)) {
+        // a border over the register kernel's size is the long chain (the
+        // blocked factor): it runs on the side stream beside the whole
+        // forward substitution, which it outlasts
+        if ((rc = factor_levels(h, a, st)) || (rc = side_stream(h))) return rc;
+        hipStream_t side = static_cast<hipStream_t>(h.side);
         hipEvent_t ef = static_cast<hipEvent_t>(h.ev_fork);
         if (hipEventRecord(ef, st) != hipSuccess || hipStreamWaitEvent(side, ef, 0) != hipSuccess) return NCL_ERR_HIP;
-        // a border in registers is short work next to the forward
-        // substitution, which then keeps most compute units; the blocked
-        // path of a larger border is the longer chain and takes them all
-        if ((rc = border_launches(h, a, true, big_border(h) == 0, side))) return rc;
+        if ((rc = border_launches(h, a, true, false, side))) return rc;
+        for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
+            if (run(h, kind, a, none, side) != hipSuccess) return NCL_ERR_HIP;
+        if (hipEventRecord(static_cast<hipEvent_t>(h.ev_join), side) != hipSuccess) return NCL_ERR_HIP;
+        if ((rc = solve_first_half(h, a, v, false, st))) return rc;
+        if (hipStreamWaitEvent(st, static_cast<hipEvent_t>(h.ev_join), 0) != hipSuccess) return NCL_ERR_HIP;
+    } else {
+        // a border in registers: the forward substitution of level l needs
+        // the factor of levels <= l only, so it runs on the side stream a
+        // level behind the factor, in the compute units the factor's upper
+        // levels leave idle, and the border's Schur products, sum and dense
+        // factor then have the GPU to themselves after the last level
+        if ((rc = side_stream(h)) || (rc = level_events(h))) return rc;
+        hipStream_t side = static_cast<hipStream_t>(h.side);
+        hipEvent_t ef = static_cast<hipEvent_t>(h.ev_fork);
+        if (hipEventRecord(ef, st) != hipSuccess || hipStreamWaitEvent(side, ef, 0) != hipSuccess) return NCL_ERR_HIP;
+        if ((rc = solve_load(h, a, v, side))) return rc;
+        const ncl::Schedule &S = h.sched;
+        for (int l = 0; l < S.nlev; l++) {
+            if ((rc = factor_level(h, a, l, st))) return rc;
+            hipEvent_t el = static_cast<hipEvent_t>(h.ev_lev[l]);
+            if (hipEventRecord(el, st) != hipSuccess || hipStreamWaitEvent(side, el, 0) != hipSuccess)
+                return NCL_ERR_HIP;
+            if ((rc = solve_forward_level(h, a, v, l, side))) return rc;
+        }
+        if ((rc = solve_border_partials(h, a, v, side))) return rc;
+        if (hipEventRecord(static_cast<hipEvent_t>(h.ev_join), side) != hipSuccess) return NCL_ERR_HIP;
+        if ((rc = border_launches(h, a, true, false, st))) return rc;
+        for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
+            if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
+        if (hipStreamWaitEvent(st, static_cast<hipEvent_t>(h.ev_join), 0) != hipSuccess) return NCL_ERR_HIP;
     }
-    if (!fork && h.nbd_tot && (rc = border_launches(h, a, true, false, st))) return rc;
-    // the status needs only the pivots: it closes the side stream's work
-    const ncl::LaunchArgs none;
-    for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
-        if (run(h, kind, a, none, fork ? side : st) != hipSuccess) return NCL_ERR_HIP;
-    if (fork && hipEventRecord(static_cast<hipEvent_t>(h.ev_join), side) != hipSuccess) return NCL_ERR_HIP;
-    const ncl::LaunchArgs v = solve_args(h, db, dx, nrhs, ld, false);
-    if ((rc = solve_first_half(h, a, v, false, st))) return rc;
-    if (fork && hipStreamWaitEvent(st, static_cast<hipEvent_t>(h.ev_join), 0) != hipSuccess) return NCL_ERR_HIP;
     h.blocks_done = true;
     h.factored = true;
     return solve_second_half(h, a, v, st);
@@ -2070,6 +2134,7 @@ int ncl_kkt_refine(ncl_kkt *k, const double *db, double *dx, int32_t nrhs, int64
 
 ncl_kkt::~ncl_kkt() {
     for (void *e : h.ev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
+    for (void *e : h.ev_lev) (void)hipEventDestroy(static_cast<hipEvent_t>(e));
     if (h.ev_fork) (void)hipEventDestroy(static_cast<hipEvent_t>(h.ev_fork));
     if (h.ev_join) (void)hipEventDestroy(static_cast<hipEvent_t>(h.ev_join));
     if (h.side) (void)hipStreamDestroy(static_cast<hipStream_t>(h.side));

@@ -387,6 +387,7 @@ struct Handle {
     // the second stream of the combined factor and solve, and its fork and
     // join events (hipStream_t, hipEvent_t; created on first use)
     void *side = nullptr, *ev_fork = nullptr, *ev_join = nullptr;
+    std::vector<void *> ev_lev;          // one per factor level: the combined call's pipeline
 };
 
 // model.cpp
