@@ -1060,15 +1060,11 @@ static int factor_level(Handle &h, const ncl::DevArgs &a, int l, hipStream_t st)
     return NCL_OK;
 }
 
-// The border: the Schur products (schur = true; beside other work when
-// shared), their sum and the dense border factor.
-static int border_launches(Handle &h, const ncl::DevArgs &a, bool schur, bool shared, hipStream_t st) {
+// The border: the Schur products (schur = true), their sum and the dense
+// border factor.
+static int border_launches(Handle &h, const ncl::DevArgs &a, bool schur, hipStream_t st) {
     const ncl::LaunchArgs none;
-    if (schur) {
-        ncl::LaunchArgs l;
-        l.shared_gpu = shared;
-        if (run(h, NCL_K_BORDER_SCHUR, a, l, st) != hipSuccess) return NCL_ERR_HIP;
-    }
+    if (schur && run(h, NCL_K_BORDER_SCHUR, a, none, st) != hipSuccess) return NCL_ERR_HIP;
     if (run(h, NCL_K_BORDER_SUM, a, none, st) != hipSuccess) return NCL_ERR_HIP;
     // the register path for borders of up to kBorderRegMax rows, then one
     // launch per column block of the largest larger border
@@ -1111,7 +1107,7 @@ int ncl_kkt_factor_border(ncl_kkt *k, void *stream) {
     const ncl::DevArgs a = dev_args(h);
     const ncl::LaunchArgs none;
     if (h.nbd_tot) {
-        const int rc = border_launches(h, a, false, false, st);
+        const int rc = border_launches(h, a, false, st);
         if (rc) return rc;
     }
     for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
@@ -2012,7 +2008,7 @@ int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs,
     int rc = NCL_OK;
     if (!fork) {
         if ((rc = factor_levels(h, a, st))) return rc;
-        if (h.nbd_tot && (rc = border_launches(h, a, true, false, st))) return rc;
+        if (h.nbd_tot && (rc = border_launches(h, a, true, st))) return rc;
         for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
             if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
         if ((rc = solve_first_half(h, a, v, false, st))) return rc;
@@ -2024,7 +2020,7 @@ int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs,
         hipStream_t side = static_cast<hipStream_t>(h.side);
         hipEvent_t ef = static_cast<hipEvent_t>(h.ev_fork);
         if (hipEventRecord(ef, st) != hipSuccess || hipStreamWaitEvent(side, ef, 0) != hipSuccess) return NCL_ERR_HIP;
-        if ((rc = border_launches(h, a, true, false, side))) return rc;
+        if ((rc = border_launches(h, a, true, side))) return rc;
         for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
             if (run(h, kind, a, none, side) != hipSuccess) return NCL_ERR_HIP;
         if (hipEventRecord(static_cast<hipEvent_t>(h.ev_join), side) != hipSuccess) return NCL_ERR_HIP;
@@ -2051,7 +2047,7 @@ int ncl_kkt_factor_solve(ncl_kkt *k, const double *db, double *dx, int32_t nrhs,
         }
         if ((rc = solve_border_partials(h, a, v, side))) return rc;
         if (hipEventRecord(static_cast<hipEvent_t>(h.ev_join), side) != hipSuccess) return NCL_ERR_HIP;
-        if ((rc = border_launches(h, a, true, false, st))) return rc;
+        if ((rc = border_launches(h, a, true, st))) return rc;
         for (int kind : {NCL_K_STATUS_INIT, NCL_K_STATUS})
             if (run(h, kind, a, none, st) != hipSuccess) return NCL_ERR_HIP;
         if (hipStreamWaitEvent(st, static_cast<hipEvent_t>(h.ev_join), 0) != hipSuccess) return NCL_ERR_HIP;

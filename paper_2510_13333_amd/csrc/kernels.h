@@ -70,7 +70,7 @@ struct LaunchArgs {
     bool to_internal = false;
     bool accumulate = false;                     // solve store: x += solution
     bool nocheck = false;                        // solve load: do not consult the factorisation status
-    bool shared_gpu = false;                     // border Schur: other work runs beside it (a smaller grid)
+    bool shared_gpu = false;                     // border Schur: cap the grid, for running beside other work (the library's call paths run it alone)
     const double *b = nullptr;                   // solve: right-hand side, solution, work vectors
     double *x = nullptr, *y = nullptr, *cpart = nullptr;
     int nnar = 0;                                // solve levels: narrow items first in the list
