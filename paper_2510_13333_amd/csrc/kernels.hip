@@ -820,15 +820,21 @@ __global__ __launch_bounds__(kWG) void k_fac_rows(DevArgs a, const Work *__restr
         double u[W_];
 #pragma unroll
         for (int j = 0; j < W_; j++) u[j] = ld32(Lb, at(j < w ? j : wl1, p));
-        // u_k -= L(k,j) u_j for j < k, row by row in increasing j
+        // u_k -= L(k,j) u_j for j < k, row by row in increasing j.  Each row
+        // of the diagonal block is loaded whole before its products, and
+        // rows past the width (clamped loads) update values that are never
+        // stored, with no select on the loaded values: with a select per
+        // product the compiler kept one load in flight at a time in the
+        // widest classes (hundreds of L2 round trips in a row); this way
+        // about ten are.
 #pragma unroll
         for (int k = 1; k < W_; k++) {
             const int kc = k < w ? k : wl1;
+            double l[W_];
 #pragma unroll
-            for (int j = 0; j < k; j++) {
-                const double l = ld32(Lb, at(j < w ? j : wl1, kc));
-                u[k] -= (k < w ? l : 0.0) * u[j];
-            }
+            for (int j = 0; j < k; j++) l[j] = ld32(Lb, at(j < w ? j : wl1, kc));
+#pragma unroll
+            for (int j = 0; j < k; j++) u[k] -= l[j] * u[j];
         }
         if (W.on) {
             double *Ub = a.upan + T.lbase;
