@@ -297,7 +297,17 @@ Plan plan_ws(Handle &h, int64_t nrhs, std::vector<uint8_t> *stage) {
     p.idev = L.take(nullptr, sizeof(ncl::InstDev) * h.inst.size());
     p.work = L.vec(all_work(h));
     p.ioff.resize(h.inst.size());
-    std::vector<uint8_t> bprim;
+    // expected sign of every pivot in the order of the pivots (the blocks'
+    // interleaved by template, then each instance's border), for the pivot
+    // report's coalesced reads
+    std::vector<uint8_t> bprim(size_t(h.dint));
+    for (size_t ti = 0; ti < h.tmpl.size(); ti++) {
+        const Template &t = h.tmpl[ti];
+        const std::vector<uint8_t> cp = col_primal(t);
+        const int64_t nb = int64_t(t.blocks.size());
+        for (int j = 0; j < t.n; j++)
+            std::fill_n(bprim.begin() + (h.t_dbase[ti] + int64_t(j) * nb), nb, cp[j]);
+    }
     for (size_t i = 0; i < h.inst.size(); i++) {
         const ncl::Inst &I = h.inst[i];
         p.ioff[i] = {L.vec(I.kbb_pos), L.vec(I.border_pg), L.vec(I.gen_c2), L.vec(I.br_r), L.vec(I.br_x),
@@ -531,7 +541,7 @@ void kernel_model(Handle &h) {
     L[NCL_K_STATUS_INIT] = 1;
     B[NCL_K_STATUS_INIT] = D * 6;
     L[NCL_K_STATUS] = 1;
-    B[NCL_K_STATUS] = D * (h.dint + h.nbd_tot);
+    B[NCL_K_STATUS] = (D + 1) * (h.dint + h.nbd_tot);   // each pivot and its expected sign
     L[NCL_K_SOL_LOAD] = L[NCL_K_SOL_STORE] = 1;
     B[NCL_K_SOL_LOAD] = B[NCL_K_SOL_STORE] = D * 2 * h.dint;
     if (h.nbd_tot) {

@@ -27,7 +27,7 @@ struct DevArgs {
     double *upan;                  // U = L D on the off-diagonal panel rows (rows >= w), panel layout
     double *zint, *sint;        // interleaved copies of the state and Sigma (assembly input)
     int64_t *stat;              // npos, nneg, nzero, first bad key, min |d| bits, max |d| bits, non-finite
-    const uint8_t *bprim;       // [nbd_tot] expected sign of the border pivots
+    const uint8_t *bprim;       // [dint + nbd_tot] expected sign of every pivot (1: positive), in dval's order
     int64_t rows_waves;         // residual-row wavefronts of all templates
     int64_t nprimal;            // expected positive pivots
     int rows_wg;                // workgroups of the residual-row kernel

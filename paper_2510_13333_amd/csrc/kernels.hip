@@ -1082,6 +1082,7 @@ static_assert(4 * kBFRegMaxNt == kBorderRegMax && kBB == kBorderBlock, "border f
 template <int T>
 __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, double *piv, double *pan) {
     const int nbd = I.nbd, tid = threadIdx.x;
+    if (nbd == 0) return;
     const int mt = (nbd + 3) >> 2, npad = 4 * mt, ntl = mt * (mt + 1) / 2;
     const double *Sg = a.sbb + I.sbb0;
     double *Lo = a.lbb + I.sbb0;
@@ -1104,17 +1105,24 @@ __device__ inline void border_factor_reg(const DevArgs &a, const InstDev &I, dou
         }
         ti[j] = i0;
         tk[j] = K;
+        // every load is issued (entries outside the matrix read entry (0, 0)
+        // and are replaced after), so that the tiles' loads are in flight
+        // together rather than one guarded group at a time
 #pragma unroll
         for (int r = 0; r < 4; r++)
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 const int i = 4 * i0 + r, k = 4 * K + c;
-                double v = 0.0;
-                if (q < ntl) {
-                    if (i < nbd && k <= i) v = Sg[pk(i, k)];
-                    else if (i == k) v = 1.0;
-                }
-                A[j][4 * r + c] = v;
+                const bool in = q < ntl && i < nbd && k <= i;
+                A[j][4 * r + c] = Sg[in ? pk(i, k) : 0];
+            }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                const int i = 4 * i0 + r, k = 4 * K + c;
+                const bool in = q < ntl && i < nbd && k <= i;
+                if (!in) A[j][4 * r + c] = (q < ntl && i == k) ? 1.0 : 0.0;
             }
     }
     for (int p = 0; p < mt; p++) {
@@ -1354,9 +1362,8 @@ __device__ inline int pivot_code(double d, bool primal) {
 }
 
 // Inertia and pivot report.  Each wavefront takes kStatusChunk consecutive
-// pivots (coalesced reads of D); the template owning them is found once per
-// wavefront and advanced only where a chunk crosses into the next one; the
-// column of a pivot is formed only for a bad one.
+// pivots and their expected signs (coalesced reads, all in flight before
+// any is used); the column of a pivot is formed only for a bad one.
 constexpr int kStatusChunk = 1024;
 
 __global__ __launch_bounds__(256) void k_status(DevArgs a) {
@@ -1364,30 +1371,16 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
     const int64_t total = a.dint + a.nbd_tot;
     const int64_t c0 = (int64_t(blockIdx.x) * 4 + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6))) * kStatusChunk;
     const int lane = lane_id();
-    int ti = (c0 < a.dint) ? find_tmpl(a, c0, &TemplDev::dbase) : 0;
-    const int64_t tend0 = ti + 1 < a.ntmpl ? a.tmpls[ti + 1].dbase : a.dint;
-    // every pivot and sign flag of the chunk is loaded before any is used
-    // (indices past the end re-read the last pivot and are not counted)
+    // indices past the end re-read the last pivot and are not counted
     constexpr int kQ = kStatusChunk / 64;
     double dv[kQ];
     uint8_t pf[kQ];
-    int tq[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; k++) {
         const int64_t idx = c0 + k * 64 + lane;
         const int64_t ic = idx < total ? idx : total - 1;
-        const uint8_t *pp;
-        if (ic < a.dint) {
-            if (ic >= tend0)
-                while (ti + 1 < a.ntmpl && a.tmpls[ti + 1].dbase <= ic) ti++;
-            const TemplDev &T = a.tmpls[ti];
-            pp = T.col_primal + uint32_t(ic - T.dbase) / uint32_t(T.nblk);
-        } else {
-            pp = a.bprim + (ic - a.dint);
-        }
-        tq[k] = ti;
         dv[k] = a.dval[ic];
-        pf[k] = *pp;
+        pf[k] = a.bprim[ic];
     }
 #pragma unroll
     for (int k = 0; k < kQ; k++) {
@@ -1403,7 +1396,7 @@ __global__ __launch_bounds__(256) void k_status(DevArgs a) {
         if (code) {
             int64_t col;
             if (idx < a.dint) {
-                const TemplDev &T = a.tmpls[tq[k]];
+                const TemplDev &T = a.tmpls[find_tmpl(a, idx, &TemplDev::dbase)];
                 const uint32_t off = uint32_t(idx - T.dbase), nb = uint32_t(T.nblk), j = off / nb;
                 col = a.blks[T.blocks[off - j * nb]].col0 + j;
             } else {
